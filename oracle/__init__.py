@@ -1,0 +1,32 @@
+"""Plain FP64 CPU oracle for the all-at-once Stokes/Oseen optimal-control solver.
+
+TEST INFRASTRUCTURE ONLY.  This package exists so that the HIP path can be
+checked against a slow, obviously correct implementation written directly from
+the paper (Heinzelreiter & Pearson, "Diagonalization-Based Parallel-in-Time
+Preconditioners for Instationary Fluid Flow Control Problems").  Only the test
+suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
+may import it.  The product path (``paper_2405_18964_amd``) never imports,
+links or calls anything here, and this package imports nothing from the product
+path.  The only code both sides share is the seeded input generator in
+``workloads``, which holds none of the method's arithmetic.
+
+Modules
+-------
+fem        Q2-Q1 finite-element matrices on the uniform unit-square grid
+           (section 2.2), assembled element by element with 3x3 Gauss, plus an
+           independent Kronecker-product route used to pin the assembly.
+kkt        the all-at-once matrix of eq. (FinalA), its right-hand side, a sparse
+           direct solve and the sequential time-stepping (reduced-gradient)
+           check of the optimality system (section 2.1/2.2).
+circulant  the circulant perturbation P_C, its FFT diagonalisation and the
+           per-frequency blocks G_j (section 3.1, eq. SubBlockG).
+smoothers  multicolour symmetric SOR, Chebyshev semi-iteration (section 3.4).
+mg         geometric multigrid V-cycles (section 3.4).
+precond    the Stokes preconditioners of section 3.2-3.4 (Algorithms 1 and 2)
+           and the Oseen preconditioner of section 4 (Algorithm 3).
+krylov     right-preconditioned GMRES and flexible GMRES.
+
+Parity status: every function is pinned by a ``-m "not gpu"`` test except the
+multigrid V-cycle beyond the Galerkin-coarse-operator identity (its convergence
+factor has no closed form): "parity unpinned" for the V-cycle contraction rate.
+"""

@@ -1,0 +1,170 @@
+"""Geometric multigrid on the nested uniform grids N, N/2, ..., 2.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Section 3.4 applies "4 V-cycles" of a geometric multigrid method with SOR
+smoothing to W_j and K_p (Stokes) and to Q_j, Q_j^H and K_p (Oseen).  Readings
+used (the paper leaves these unstated):
+
+* V(1,1) cycle: one forward multicolour Gauss-Seidel sweep before the coarse
+  correction, one backward sweep after it (so the cycle is symmetric for
+  symmetric operators); coarsest grid N = 2 solved exactly by dense LU.
+* Coarse operators are rediscretised with the same coefficients on the coarse
+  grid; for nested conforming spaces with exact quadrature this equals the
+  Galerkin product P^T A P.  The coarse-grid wind is the fine nodal wind
+  injected at the coarse nodes.
+* Prolongation P is finite-element interpolation: Q2 one-dimensional weights
+  are 1 at coincident nodes and (3/8, 3/4, -1/8) / (-1/8, 3/4, 3/8) at the
+  quarter points of a coarse element; Q1 uses (1/2, 1/2) at midpoints.
+  Restriction is P^T.  Dirichlet (Q2) nodes are excluded on every level.
+* Pressure-space (Q1) operators act on the *unconstrained* node set with
+  natural boundary conditions.  The pressure Laplacian K_N is then singular
+  with the constants as kernel, and V-cycles are applied to consistent
+  right-hand sides only; the coarsest singular system is solved with node
+  (0,0) held at zero (any solution is acceptable, the caller removes the
+  constant).  This is how the pinned K_p^{-1} is applied, through the exact
+  identity  K_p^{-1} = R L K_N^+ L^T R^T,  L = I - 1 e_0^T, R = drop node 0,
+  which multigrid approximates far better than V-cycles on the pinned matrix
+  (the pin leaves a mode with an O(h^2) eigenvalue that coarse grids cannot
+  represent).
+* ``cycles`` V-cycles start from x = 0; each later cycle starts its
+  pre-smoothing from the current iterate.
+
+A scalar operator on a level is  alpha M + gamma K + eta N + eta_t N^T  with
+M, K, N the mass, stiffness and convection matrices of the family (Q2
+interior or pinned Q1) and complex-allowed scalar coefficients.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .fem import Operators
+from .smoothers import ColouredSOR, colours_q1, colours_q2
+
+
+def prolong_1d_q2(Nc: int) -> np.ndarray:
+    """(2Nf+1) x (2Nc+1) 1-D Q2 interpolation, Nf = 2 Nc."""
+    Nf = 2 * Nc
+    P = np.zeros((2 * Nf + 1, 2 * Nc + 1))
+    for i in range(2 * Nf + 1):
+        e, r = divmod(i, 4)
+        if r == 0:
+            P[i, 2 * e] = 1.0
+        elif r == 2:
+            P[i, 2 * e + 1] = 1.0
+        elif r == 1:
+            P[i, 2 * e: 2 * e + 3] = [3 / 8, 3 / 4, -1 / 8]
+        else:
+            P[i, 2 * e: 2 * e + 3] = [-1 / 8, 3 / 4, 3 / 8]
+    return P
+
+
+def prolong_1d_q1(Nc: int) -> np.ndarray:
+    Nf = 2 * Nc
+    P = np.zeros((Nf + 1, Nc + 1))
+    for i in range(Nf + 1):
+        if i % 2 == 0:
+            P[i, i // 2] = 1.0
+        else:
+            P[i, (i - 1) // 2] = 0.5
+            P[i, (i + 1) // 2] = 0.5
+    return P
+
+
+def inject_wind(wind, Nf: int):
+    """Fine Q2 nodal wind -> coarse (Nf/2) Q2 nodal wind by injection."""
+    if wind is None:
+        return None
+    nqf = 2 * Nf + 1
+    W = np.asarray(wind).reshape(2, nqf, nqf)
+    return W[:, ::2, ::2].reshape(2, -1)
+
+
+class Levels:
+    """Level matrices and transfer operators of one hierarchy (one wind)."""
+
+    def __init__(self, N: int, wind=None):
+        if N < 2 or (N & (N - 1)):
+            raise ValueError("N must be a power of two >= 2")
+        self.sizes = []
+        n = N
+        while n >= 2:
+            self.sizes.append(n)
+            n //= 2
+        self.ops = []
+        w = None if wind is None else np.asarray(wind)
+        for l, n in enumerate(self.sizes):
+            self.ops.append(Operators(n, 1.0, w))
+            if l + 1 < len(self.sizes):
+                w = inject_wind(w, n)
+        self.P2, self.P1 = [], []
+        for l in range(len(self.sizes) - 1):
+            f, c = self.ops[l].grid, self.ops[l + 1].grid
+            p = prolong_1d_q2(self.sizes[l + 1])
+            P = sp.csr_matrix(np.kron(p, p))
+            self.P2.append((f.Rv() @ P @ c.Rv().T).tocsr())
+            p = prolong_1d_q1(self.sizes[l + 1])
+            self.P1.append(sp.csr_matrix(np.kron(p, p)))      # unconstrained Q1
+
+    def family(self, fam: str, l: int):
+        o = self.ops[l]
+        if fam == "q2":
+            return o.Ms, o.Ks, o.Ns, colours_q2(o.grid)
+        if fam == "q1":
+            f = o.full
+            Nn = f["N1"] if "N1" in f else sp.csr_matrix(f["M1"].shape)
+            iy, ix = np.divmod(np.arange(o.grid.np2), o.grid.np1)
+            return f["M1"], f["K1"], Nn, 2 * (iy % 2) + (ix % 2)
+        raise ValueError(fam)
+
+    def prolong(self, fam: str, l: int):
+        return self.P2[l] if fam == "q2" else self.P1[l]
+
+
+class ScalarMG:
+    """V(1,1) multigrid for  alpha M + gamma K + eta N + eta_t N^T."""
+
+    def __init__(self, levels: Levels, fam: str, alpha, gamma, eta=0.0, eta_t=0.0):
+        self.lv, self.fam = levels, fam
+        self.A, self.sor = [], []
+        for l in range(len(levels.sizes)):
+            M, K, N, col = levels.family(fam, l)
+            A = alpha * M + gamma * K
+            if eta != 0:
+                A = A + eta * N
+            if eta_t != 0:
+                A = A + eta_t * N.T
+            A = sp.csr_matrix(A)
+            self.A.append(A)
+            self.sor.append(ColouredSOR(A, col))
+        Ac = self.A[-1].toarray()
+        self.pin_coarse = fam == "q1"
+        self.coarse = sla.lu_factor(Ac[1:, 1:] if self.pin_coarse else Ac)
+
+    def coarse_solve(self, b):
+        if not self.pin_coarse:
+            return sla.lu_solve(self.coarse, b)
+        x = np.zeros_like(b)
+        x[1:] = sla.lu_solve(self.coarse, b[1:])
+        return x
+
+    def vcycle(self, l: int, b: np.ndarray, x: np.ndarray) -> np.ndarray:
+        if l == len(self.A) - 1:
+            return self.coarse_solve(b)
+        x = self.sor[l].forward(b, x)
+        r = b - self.A[l] @ x
+        P = self.lv.prolong(self.fam, l)
+        rc = P.T @ r
+        ec = self.vcycle(l + 1, rc, np.zeros_like(rc))
+        x = x + P @ ec
+        return self.sor[l].backward(b, x)
+
+    def solve(self, b: np.ndarray, cycles: int = 4) -> np.ndarray:
+        dt = np.result_type(b, self.A[0].dtype)
+        x = np.zeros(b.shape, dtype=dt)
+        b = b.astype(dt)
+        for _ in range(cycles):
+            x = self.vcycle(0, b, x)
+        return x

@@ -1,0 +1,104 @@
+"""Stationary building blocks: multicolour SOR sweeps and Chebyshev semi-iteration.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Section 3.4 approximates mass-matrix inverses by the Chebyshev semi-iteration
+(10 steps) and smooths the multigrid levels with successive over-relaxation.
+The paper states neither the SOR ordering, the relaxation factor nor the
+Chebyshev spectrum bounds; the readings used here are:
+
+* SOR: relaxation factor 1 (Gauss-Seidel) in a multicolour ordering.  Q2 nodes
+  couple only with nodes at most 2 grid indices away in each direction, so the
+  9 classes (ix mod 3, iy mod 3) are independent sets; Q1 nodes couple within
+  1 index, so (ix mod 2, iy mod 2) gives 4.  Colour number = 3*(iy%3) + ix%3
+  (Q2) or 2*(iy%2) + ix%2 (Q1) with (ix, iy) the padded-grid node indices.
+  A forward sweep visits colours 0..C-1, a backward sweep C-1..0.
+* Chebyshev: Jacobi-preconditioned semi-iteration of Golub and Varga with the
+  element-wise spectrum bounds of diag(M)^{-1} M: the 1-D P2 element gives
+  [1/2, 5/4] and P1 gives [1/2, 3/2]; tensor products give [1/4, 25/16] for
+  Q2 and [1/4, 9/4] for Q1.  ``k`` steps from x_0 = 0 return x_k.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+Q2_MASS_BOUNDS = (0.25, 25.0 / 16.0)
+Q1_MASS_BOUNDS = (0.25, 9.0 / 4.0)
+
+
+def colours_q2(grid) -> np.ndarray:
+    """Colour of every interior Q2 node (compact order)."""
+    iy, ix = np.divmod(grid.v_interior, grid.nq)
+    return 3 * (iy % 3) + (ix % 3)
+
+
+def colours_q1(grid) -> np.ndarray:
+    """Colour of every kept (non-pinned) Q1 node (compact order)."""
+    iy, ix = np.divmod(grid.p_kept, grid.np1)
+    return 2 * (iy % 2) + (ix % 2)
+
+
+class ColouredSOR:
+    """Gauss-Seidel sweeps over independent colour classes of a sparse matrix."""
+
+    def __init__(self, A: sp.spmatrix, colours: np.ndarray, omega: float = 1.0):
+        A = sp.csr_matrix(A)
+        self.A = A
+        self.diag = A.diagonal()
+        self.omega = omega
+        self.ncol = int(colours.max()) + 1 if colours.size else 0
+        self.idx = [np.flatnonzero(colours == c) for c in range(self.ncol)]
+        self.rows = [A[i, :] for i in self.idx]
+        for c, R in enumerate(self.rows):        # independence of each class
+            sub = R[:, self.idx[c]].tocoo()
+            assert np.all(sub.row == sub.col), "colour class is not an independent set"
+
+    def _update(self, c, b, x):
+        i = self.idx[c]
+        d = self.diag[i] if x.ndim == 1 else self.diag[i][:, None]
+        x[i] += self.omega * (b[i] - self.rows[c] @ x) / d
+
+    def forward(self, b, x):
+        for c in range(self.ncol):
+            self._update(c, b, x)
+        return x
+
+    def backward(self, b, x):
+        for c in range(self.ncol - 1, -1, -1):
+            self._update(c, b, x)
+        return x
+
+
+def chebyshev(A: sp.spmatrix, b: np.ndarray, steps: int, bounds) -> np.ndarray:
+    """Jacobi-preconditioned Chebyshev semi-iteration, ``steps`` steps from 0.
+
+    With D = diag(A) and spectrum(D^{-1} A) in [lo, hi]:
+        gamma = 2 / (lo + hi),  sigma = (hi - lo) / (hi + lo)
+        x_1 = gamma D^{-1} b
+        x_{k+1} = omega_{k+1} (x_k - x_{k-1} + gamma D^{-1}(b - A x_k)) + x_{k-1}
+        omega_2 = 1 / (1 - sigma^2 / 2),  omega_{k+1} = 1 / (1 - sigma^2 omega_k / 4).
+    """
+    lo, hi = bounds
+    D = A.diagonal()
+    if b.ndim > 1:
+        D = D[:, None]
+    gamma = 2.0 / (lo + hi)
+    sigma = (hi - lo) / (hi + lo)
+    if steps <= 0:
+        return np.zeros_like(b)
+    x_prev = np.zeros_like(b)
+    x = gamma * b / D
+    omega = 1.0
+    for k in range(1, steps):
+        omega = 1.0 / (1.0 - 0.5 * sigma * sigma) if k == 1 else 1.0 / (1.0 - 0.25 * sigma * sigma * omega)
+        x_new = omega * (x - x_prev + gamma * (b - A @ x) / D) + x_prev
+        x_prev, x = x, x_new
+    return x
+
+
+def chebyshev_error_bound(steps: int, bounds) -> float:
+    """1 / T_k(1/sigma): the energy-norm error reduction guaranteed after k steps."""
+    lo, hi = bounds
+    sigma = (hi - lo) / (hi + lo)
+    return 1.0 / np.cosh(steps * np.arccosh(1.0 / sigma))

@@ -1,0 +1,357 @@
+"""Pins of the oracle's preconditioners (sections 2.3, 3.2-3.4, 4) and solvers."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import circulant as circ
+from oracle.fem import Operators
+from oracle.kkt import Problem
+from oracle.krylov import fgmres, gmres
+from oracle.mg import Levels, ScalarMG
+from oracle.precond import OseenPreconditioner, StokesPreconditioner, stokes_constants
+from oracle.smoothers import (Q1_MASS_BOUNDS, Q2_MASS_BOUNDS, ColouredSOR, chebyshev,
+                              chebyshev_error_bound, colours_q1, colours_q2)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden_bounds():
+    out = {}
+    for line in open(os.path.join(GOLD, "bounds.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, val = line.split()[:2]
+        out[name] = float(val)
+    return out
+
+
+@pytest.fixture(scope="module")
+def stokes4():
+    w = W.small(W.STOKES, 4, 8, beta=1e-2)
+    P = Problem.from_workload(w)
+    return w, P, StokesPreconditioner(P)
+
+
+def test_golden_bounds_closed_forms():
+    g = golden_bounds()
+    assert abs(g["phat_lower"] - 1 / np.sqrt(12)) < 1e-15
+    assert abs(g["phat_upper"] - (1 + np.sqrt(5)) / 2) < 1e-15
+    assert g["uzawa_mu"] == (g["pw_lower"] + g["pw_upper"]) / 2
+
+
+@pytest.mark.parametrize("j", [0, 1, 3, 4, 7])
+def test_gj_factorisation(stokes4, j):
+    """P9: G_j = T_l Z_j T_r (eq. GJTransformation) with c1 = d_r / sqrt(tau^2/beta
+    + d_c^2); T_l^H = T_r; the inverse transforms invert T_l and T_r."""
+    _, P, pc = stokes4
+    Tl, Z, Tr = pc.T_matrices(j)
+    G = circ.G_block(P, pc.d[j])
+    assert abs(Tl @ Z @ Tr - G).max() < 1e-14
+    assert abs(Tl.conj().T - Tr).max() < 1e-15
+    rng = np.random.default_rng(j)
+    n = Tl.shape[0]
+    r = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    cut = np.cumsum([P.nv, P.nv, P.nP])
+    s = np.concatenate(pc.t_left_inv(j, *np.split(r, cut)))
+    assert np.allclose(Tl @ s, r, atol=1e-13)
+    y = np.concatenate(pc.t_right_inv(j, *np.split(r, cut)))
+    assert np.allclose(Tr @ y, r, atol=1e-13)
+
+
+def test_printed_c1_does_not_factorise(stokes4):
+    """The constant c1 as printed (d_c not squared) breaks G_j = T_l Z_j T_r
+    for j with d_c != +-1, which is why the squared form is used."""
+    _, P, pc = stokes4
+    j = 1
+    dr, dc, c1, c2 = pc.constants(j)
+    c1_printed = dr / np.sqrt(P.tau ** 2 / P.beta + dc)
+    assert abs(c1 - dr * c2 / P.tau) < 1e-15
+    assert abs(c1_printed - c1) > 1e-3 * abs(c1)
+
+
+@pytest.mark.parametrize("j", [0, 2, 4])
+def test_phat_bounds(stokes4, j):
+    """P10, eq. (SchurComplementHatBounds): |eig(P^_j^{-1} Z_j)| in
+    [1/sqrt(12), (1+sqrt(5))/2] with W_j = (1+c1)M + c2 L and exact B W^{-1} B^T."""
+    g = golden_bounds()
+    _, P, pc = stokes4
+    o = P.ops
+    _, _, c1, c2 = pc.constants(j)
+    Wj = ((1 + c1) * o.M + c2 * o.L).toarray()
+    B = o.B.toarray()
+    S = B @ np.linalg.solve(Wj, B.T)
+    Ph = sla.block_diag(Wj, Wj, S, S)
+    ev = np.abs(np.linalg.eigvals(np.linalg.solve(Ph, pc.Z_matrix(j).toarray())))
+    assert ev.min() >= g["phat_lower"] - 1e-10
+    assert ev.max() <= g["phat_upper"] + 1e-10
+
+
+def test_stokes_schur_commutator_algebra(stokes4):
+    """P15: M_p ((1+c1) M_p + c2 nu K_p)^{-1} K_p = ((1+c1) K_p^{-1} + nu c2 M_p^{-1})^{-1}."""
+    _, P, pc = stokes4
+    o = P.ops
+    _, _, c1, c2 = pc.constants(3)
+    Mp, Kp = o.Mp.toarray(), o.Kp.toarray()
+    lhs = Mp @ np.linalg.solve((1 + c1) * Mp + c2 * P.nu * Kp, Kp)
+    rhs = np.linalg.inv((1 + c1) * np.linalg.inv(Kp) + P.nu * c2 * np.linalg.inv(Mp))
+    assert np.allclose(lhs, rhs, rtol=1e-10, atol=1e-12)
+
+
+def _pin_ops(N):
+    o = Operators(N, 1.0)
+    np2 = o.grid.np2
+    R = np.eye(np2)[1:]
+    Lmap = np.eye(np2) - np.outer(np.ones(np2), np.eye(np2)[0])     # y - y0 * 1
+    return o, R, Lmap
+
+
+def test_pinned_inverse_identity():
+    """For any S whose left and right kernels are the constant pressures,
+    (R S R^T)^{-1} = R L S^+ L^T R^T with L = I - 1 e0^T (the identity used to
+    carry the commutator Schur approximation onto the pinned space)."""
+    N = 4
+    o, R, Lmap = _pin_ops(N)
+    Bfull = np.hstack([o.full["Bx"].toarray() @ o.grid.Rv().T.toarray(),
+                       o.full["By"].toarray() @ o.grid.Rv().T.toarray()])
+    Wd = (1.3 * o.M + 0.2 * o.L).toarray()
+    S = Bfull @ np.linalg.solve(Wd, Bfull.T)
+    lhs = np.linalg.inv(R @ S @ R.T)
+    rhs = R @ Lmap @ np.linalg.pinv(S) @ Lmap.T @ R.T
+    assert np.allclose(lhs, rhs, rtol=1e-9, atol=1e-9 * np.abs(lhs).max())
+
+
+@pytest.mark.parametrize("N", [4, 8])
+def test_pinned_schur_spectrum_h_robust(N):
+    """With the mass term transported by the identity above, eig(S^^{-1} S)
+    stays in [0.2, 1] (no h-dependent outlier from the pressure pin)."""
+    w = W.small(W.STOKES, N, 8, beta=1e-2)
+    P = Problem.from_workload(w)
+    pc = StokesPreconditioner(P, freqs=[1])
+    o = P.ops
+    _, _, c1, c2 = pc.constants(1)
+    Wj = ((1 + c1) * o.M + c2 * o.L).toarray()
+    B = o.B.toarray()
+    S = B @ np.linalg.solve(Wj, B.T)
+    np2 = o.grid.np2
+    R = np.eye(np2)[1:]
+    Lmap = np.eye(np2) - np.outer(np.ones(np2), np.eye(np2)[0])
+    MNi = Lmap @ np.linalg.inv(o.full["M1"].toarray()) @ Lmap.T
+    Shinv = (1 + c1) * np.linalg.inv(o.Kp.toarray()) + P.nu * c2 * (R @ MNi @ R.T)
+    ev = np.linalg.eigvals(Shinv @ S).real
+    assert ev.min() > 0.2 and ev.max() < 1.0 + 1e-10
+
+
+@pytest.mark.parametrize("j", [0, 1, 3])
+def test_pearson_wathen_bounds_complex(j):
+    """P11, eq. (SchurComplementPearsonWathen): for G_j^(1,1) (Oseen, complex
+    d_j) eig(S^^{-1} S) in [1/2, 1] with S^ = tau^{-1} Q_j M^{-1} Q_j^H."""
+    g = golden_bounds()
+    N = 4
+    w = W.small(W.OSEEN, N, 8, beta=1e-2, nu=0.1)
+    P = Problem.from_workload(w, W.wind_nodal(N))
+    o, tau, beta = P.ops, P.tau, P.beta
+    d = circ.d_closed_form(P.nt)[j]
+    M, L = o.M.toarray(), o.L.toarray()
+    Psi = d * M + tau * L
+    S = (tau / beta) * M + Psi @ np.linalg.solve(tau * M, Psi.conj().T)
+    Q = Psi + tau / np.sqrt(beta) * M
+    Sh = Q @ np.linalg.solve(M, Q.conj().T) / tau
+    ev = np.linalg.eigvals(np.linalg.solve(Sh, S))
+    assert np.abs(ev.imag).max() < 1e-9
+    assert ev.real.min() >= g["pw_lower"] - 1e-9 and ev.real.max() <= g["pw_upper"] + 1e-9
+
+
+def test_uzawa_exact_components():
+    """P14: with exact M^ = M and S^ = S and mu = 1, Uzawa from zero gives the
+    exact x2 after one step and the exact x1 after two (eq. Uzawa11 signs)."""
+    N = 2
+    w = W.small(W.OSEEN, N, 4, beta=1e-2, nu=0.1)
+    wind = W.wind_nodal(N)
+    P = Problem.from_workload(w, wind)
+    pc = OseenPreconditioner(P, wind, freqs=[1])
+    o, tau, beta = P.ops, P.tau, P.beta
+    j = 1
+    d = pc.d[j]
+    M, L = o.M.toarray(), o.L.toarray()
+    Psi = d * M + tau * L
+    S = (tau / beta) * M + Psi @ np.linalg.solve(tau * M, Psi.conj().T)
+    G11 = np.block([[tau * M, Psi.conj().T], [Psi, -(tau / beta) * M]])
+    rng = np.random.default_rng(0)
+    b = rng.standard_normal(2 * P.nv) + 1j * rng.standard_normal(2 * P.nv)
+    x = np.linalg.solve(G11, b)
+    Minv = lambda v: np.linalg.solve(M, v)
+    Sinv = lambda v: np.linalg.solve(S, v)
+    x1, x2 = pc.uzawa(j, b[:P.nv], b[P.nv:], Minv, Sinv, mu=1.0, steps=1)
+    assert np.allclose(x2, x[P.nv:], atol=1e-10 * np.abs(x).max())
+    x1, x2 = pc.uzawa(j, b[:P.nv], b[P.nv:], Minv, Sinv, mu=1.0, steps=2)
+    assert np.allclose(x1, x[:P.nv], atol=1e-10 * np.abs(x).max())
+    # with the Pearson-Wathen S^ and mu = 3/4 the error contracts by <= 1/3 per step
+    Q = Psi + tau / np.sqrt(beta) * M
+    Sh = Q @ np.linalg.solve(M, Q.conj().T) / tau
+    Shinv = lambda v: np.linalg.solve(Sh, v)
+    errs = []
+    for k in (3, 4):
+        _, x2 = pc.uzawa(j, b[:P.nv], b[P.nv:], Minv, Shinv, mu=0.75, steps=k)
+        errs.append(np.linalg.norm(x2 - x[P.nv:]))
+    assert errs[1] <= errs[0] / 3 + 1e-12
+
+
+@pytest.mark.parametrize("fam,bounds", [("q2", Q2_MASS_BOUNDS), ("q1", Q1_MASS_BOUNDS)])
+def test_chebyshev_error_bound(fam, bounds):
+    """P12: after k steps the M-norm error is at most 1/T_k(1/sigma) (4.18e-4
+    for Q2, 1.95e-3 for Q1 at k = 10) of the initial error."""
+    o = Operators(6, 1.0)
+    A = o.Ms if fam == "q2" else o.Mp
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        b = rng.standard_normal(A.shape[0])
+        xe = spla.spsolve(A.tocsc(), b)
+        for k in (1, 2, 5, 10):
+            e = chebyshev(A, b, k, bounds) - xe
+            en = np.sqrt(e @ (A @ e)) / np.sqrt(xe @ (A @ xe))
+            assert en <= chebyshev_error_bound(k, bounds) * (1 + 1e-9)
+    assert abs(chebyshev_error_bound(10, Q2_MASS_BOUNDS) - 4.18e-4) < 1e-6
+    assert abs(chebyshev_error_bound(10, Q1_MASS_BOUNDS) - 1.95e-3) < 1e-5
+
+
+def test_colour_classes_independent():
+    """The multicolour SOR colour classes are independent sets (checked by the
+    constructor) and a symmetric sweep pair is a symmetric operator."""
+    for N in (2, 4):
+        o = Operators(N, 1.0, W.wind_nodal(N))
+        for A, col in ((o.Ms + o.Ks + o.Ns, colours_q2(o.grid)), (o.Kp + o.Mp, colours_q1(o.grid))):
+            sor = ColouredSOR(A, col)
+            assert sor.ncol == (9 if col.size == o.grid.nV else 4)
+        A = (o.Ms + 0.3 * o.Ks).tocsr()
+        sor = ColouredSOR(A, colours_q2(o.grid))
+        n = A.shape[0]
+        Sm = np.zeros((n, n))
+        for k in range(n):
+            e = np.zeros(n); e[k] = 1.0
+            Sm[:, k] = sor.backward(e, sor.forward(e, np.zeros(n)))
+        assert np.allclose(Sm, Sm.T, atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [4, 8])
+def test_galerkin_equals_rediscretised(N):
+    """P13: P^T A_fine P equals the coarse operator for M, K, N(w) (Q2 interior)
+    and the unconstrained Q1 matrices, since the spaces are nested and the
+    quadrature exact."""
+    wind = W.wind_nodal(N)
+    lv = Levels(N, wind)
+    P2, P1 = lv.P2[0], lv.P1[0]
+    f, c = lv.ops[0], lv.ops[1]
+    for Af, Ac in ((f.Ms, c.Ms), (f.Ks, c.Ks), (f.Ns, c.Ns)):
+        assert abs(P2.T @ Af @ P2 - Ac).max() < 1e-13
+    for key in ("K1", "M1", "N1"):
+        assert abs(P1.T @ f.full[key] @ P1 - c.full[key]).max() < 1e-13
+
+
+def test_prolongation_reproduces_polynomials():
+    """Q2 interpolation reproduces quadratics, Q1 reproduces bilinears."""
+    from oracle.mg import prolong_1d_q1, prolong_1d_q2
+    Nc = 4
+    xc = np.arange(2 * Nc + 1) / (2 * Nc)
+    xf = np.arange(4 * Nc + 1) / (4 * Nc)
+    q = lambda x: 1 - 3 * x + 2 * x * x
+    assert np.allclose(prolong_1d_q2(Nc) @ q(xc), q(xf), atol=1e-14)
+    xc1, xf1 = np.arange(Nc + 1) / Nc, np.arange(2 * Nc + 1) / (2 * Nc)
+    assert np.allclose(prolong_1d_q1(Nc) @ (2 - xc1), 2 - xf1, atol=1e-14)
+
+
+def test_multigrid_converges_and_is_symmetric():
+    """A V-cycle is a contraction on W_j and on the unconstrained K_N (modulo
+    constants; multigrid convergence rate itself: parity unpinned), exact on
+    the coarsest grid, and symmetric; the pinned K_p^{-1} comes out through
+    R L K_N^+ L^T R^T."""
+    N = 8
+    lv = Levels(N)
+    rng = np.random.default_rng(0)
+    mg = ScalarMG(lv, "q2", 1.1, 0.05)
+    A = mg.A[0]
+    b = rng.standard_normal(A.shape[0])
+    xe = spla.spsolve(A.tocsc(), b)
+    errs = [np.linalg.norm(mg.solve(b, c) - xe) for c in (1, 2, 4)]
+    assert errs[0] < 0.3 * np.linalg.norm(xe) and errs[2] < 0.05 * errs[0]
+    n = A.shape[0]
+    Mx = np.column_stack([mg.solve(np.eye(n)[k], 1) for k in range(n)])
+    assert np.allclose(Mx, Mx.T, atol=1e-12 * np.abs(Mx).max())
+    # pressure Laplacian through the unconstrained hierarchy
+    w = W.small(W.STOKES, N, 4)
+    pc = StokesPreconditioner(Problem.from_workload(w), freqs=[0])
+    Kp = pc.P.ops.Kp
+    bp = rng.standard_normal(Kp.shape[0])
+    xe = spla.spsolve(Kp.tocsc(), bp)
+    errs = []
+    for c in (1, 2, 4):
+        pc.s.n_vcycles = c
+        errs.append(np.linalg.norm(pc.stiff_p_inv(bp) - xe) / np.linalg.norm(xe))
+    assert errs[0] < 0.1 and errs[2] < 1e-3
+    coarse = ScalarMG(Levels(2), "q2", 1.0, 1.0)
+    b = rng.standard_normal(coarse.A[0].shape[0])
+    assert np.allclose(coarse.A[0] @ coarse.solve(b, 1), b, atol=1e-13)
+
+
+def test_linear_stokes_preconditioner_symmetric(stokes4):
+    """P16: Algorithm 1 with symmetric V-cycles is a symmetric operator."""
+    _, P, pc = stokes4
+    rng = np.random.default_rng(4)
+    x, y = rng.standard_normal(P.n_all), rng.standard_normal(P.n_all)
+    a, b = x @ pc.apply(y), y @ pc.apply(x)
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_conjugate_symmetry_of_frequency_outputs(stokes4):
+    """P18: for real r, y_hat_{nt-j} = conj(y_hat_j) (linear and nonlinear)."""
+    _, P, pc = stokes4
+    r = np.random.default_rng(6).standard_normal(P.n_all)
+    for nl in (False, True):
+        out = pc.freq_domain(r, nonlinear=nl)
+        for j in range(1, P.nt // 2):
+            for a, b in zip(out[j], out[P.nt - j]):
+                assert np.allclose(a, np.conj(b), atol=1e-12 * np.abs(a).max())
+
+
+@pytest.mark.slow
+def test_fgmres_stokes_nonlinear_matches_direct():
+    """Outer FGMRES(10) with Algorithm 2 reaches 1e-8 and agrees with the
+    direct solve; inner GMRES counts stay moderate (section 5.1.2 behaviour)."""
+    w = W.config(1)
+    P = Problem.from_workload(w)
+    b = P.rhs(W.desired_state(w))
+    A = P.kkt_matrix()
+    pc = StokesPreconditioner(P)
+    x, its, hist = fgmres(lambda v: A @ v, lambda v: pc.apply(v, True), b, 1e-8, restart=10, maxit=40)
+    assert hist[-1] <= 1e-8 and its <= 12
+    assert np.mean(list(pc.inner_its.values())) < 40
+    xs = P.solve_direct(b)
+    assert np.linalg.norm(x - xs) <= 1e-5 * np.linalg.norm(xs)
+
+
+def test_fgmres_oseen_nonlinear_small():
+    """Oseen: FGMRES with GMRES(G_j, P~_j^(UZ)) converges to 1e-8."""
+    N = 4
+    w = W.Workload(W.OSEEN, N, 8, 1.0, 0.1, 1e-4, 0, 1.0)
+    wind = W.wind_nodal(N)
+    P = Problem.from_workload(w, wind)
+    b = P.rhs(W.desired_state(w))
+    A = P.kkt_matrix()
+    pc = OseenPreconditioner(P, wind)
+    x, its, hist = fgmres(lambda v: A @ v, lambda v: pc.apply(v, True), b, 1e-8, restart=10, maxit=40)
+    assert hist[-1] <= 1e-8
+
+
+def test_gmres_matches_direct_solution():
+    rng = np.random.default_rng(0)
+    n = 40
+    A = np.eye(n) * 3 + rng.standard_normal((n, n)) * 0.3
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, its, _ = gmres(lambda v: A @ v, None, b, 1e-12, restart=n, maxit=n)
+    assert np.linalg.norm(A @ x - b) <= 1e-11 * np.linalg.norm(b)
+    x, its, _ = fgmres(lambda v: A @ v, lambda v: v / 3, b.real, 1e-12, restart=5, maxit=200)
+    assert np.linalg.norm(A @ x - b.real) <= 1e-11 * np.linalg.norm(b.real)
