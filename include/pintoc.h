@@ -1,0 +1,171 @@
+/*
+ * pintoc -- parallel-in-time all-at-once solver for unsteady Stokes / Oseen
+ * distributed optimal control on MI355X (gfx950).
+ *
+ * Method: Heinzelreiter & Pearson, "Diagonalization-Based Parallel-in-Time
+ * Preconditioners for Instationary Fluid Flow Control Problems".
+ *
+ * C ABI.  Plain pointers and sizes only; no C++ types cross this boundary.
+ * Every device pointer argument names memory the caller owns (for example a
+ * torch tensor's data pointer).  ``stream`` is a hipStream_t passed as void*
+ * (NULL = the null stream).  All entry points return PINTOC_OK (0) on success
+ * or a negative PINTOC_E* code; pintoc_last_error() then gives a message
+ * (thread-local).  A problem handle is not thread-safe; distinct handles are.
+ *
+ * Vector layout at the boundary ("canonical"): real FP64, length
+ *     n_all = 2 * nt * (2 (2N+1)^2 + (N+1)^2),
+ * ordered [b][t][v_x (2N+1)^2, v_y (2N+1)^2, p (N+1)^2] with
+ *   b = 0: unknowns (v, p) / rows of the adjoint equations,
+ *   b = 1: unknowns (lambda, mu) / rows of the state equations,
+ *   t = 1..nt (time level t*tau),
+ * each grid row-major with x fastest.  This is the unknown ordering of the
+ * permuted all-at-once system, eq. (FinalA) (section 2.2).  Entries on the
+ * Dirichlet boundary of the velocity grids and the pinned pressure node (0,0)
+ * (section 2.2: the pressure is fixed at one point) must be zero on input and
+ * are zero on output.
+ */
+#ifndef PINTOC_H
+#define PINTOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PINTOC_OK = 0,
+  PINTOC_NOT_CONVERGED = 1, /* pintoc_solve: tolerance not reached, x = last iterate */
+  PINTOC_EINVAL = -1,       /* invalid argument (sizes, parameters, NULL pointers)   */
+  PINTOC_ENOMEM = -2,       /* workspace too small                                   */
+  PINTOC_EHIP = -3,         /* a HIP runtime call failed (message has its string)    */
+  PINTOC_ESTATE = -4        /* call order violated (e.g. no workspace bound)         */
+};
+
+/* Opaque problem handle (owned by the library). */
+typedef struct pintoc_problem pintoc_problem;
+
+enum { PINTOC_STOKES = 0, PINTOC_OSEEN = 1 };
+
+/* Inner treatment of the frequency blocks.
+ *  LINEAR: one application of the block preconditioner per frequency
+ *          (Algorithm 1 for Stokes; P~_j^(UZ) of Algorithm 3 for Oseen).
+ *  GMRES:  the blocks are solved by right-preconditioned GMRES to a relative
+ *          tolerance (Algorithm 2 for Stokes; its Oseen analogue, section 4). */
+enum { PINTOC_INNER_LINEAR = 0, PINTOC_INNER_GMRES = 1 };
+
+/* Arithmetic of the per-frequency block solves.  The outer Krylov method,
+ * residual recomputation, FFTs and the all-at-once matrix stay FP64. */
+enum { PINTOC_PREC_FP64 = 0, PINTOC_PREC_FP32_INNER = 1 };
+
+/* Problem of section 2 (eq. OseenOptimization / OseenFlow) on the unit square,
+ * Q2-Q1 Taylor-Hood elements on N x N uniform quadrilaterals (section 2.2),
+ * backward Euler with nt steps of tau = T / nt, v_0 = 0, f = 0, h = 0. */
+typedef struct {
+  int32_t N;            /* quads per side, a power of two >= 2               */
+  int32_t nt;           /* time steps = FFT length, >= 2, at most 1024       */
+  double T;             /* final time > 0                                    */
+  double nu;            /* viscosity > 0                                     */
+  double beta;          /* control cost (regularisation) > 0                 */
+  int32_t flow;         /* PINTOC_STOKES or PINTOC_OSEEN                     */
+  const double* wind;   /* host, [2][(2N+1)^2] Q2 nodal values of the
+                           divergence-free wind (x component first); NULL
+                           for Stokes.  Copied; the caller may free it.      */
+} pintoc_problem_desc;
+
+/* Solver parameters.  Defaults (pintoc_default_options) follow section 5:
+ * 4 V-cycles per multigrid solve, 10 Chebyshev steps, 6 Uzawa steps with
+ * mu = 3/4 (section 4), inner tolerance 1e-2, outer FGMRES restart 10. */
+typedef struct {
+  int32_t inner;          /* PINTOC_INNER_LINEAR or PINTOC_INNER_GMRES        */
+  int32_t precision;      /* PINTOC_PREC_*                                   */
+  int32_t restart;        /* outer FGMRES restart length                     */
+  int32_t max_outer;      /* outer iteration cap                             */
+  double tol;             /* outer: ||b - A x||_2 <= tol ||b||_2 (true res.) */
+  double inner_tol;       /* inner GMRES relative tolerance (epsilon)        */
+  int32_t inner_restart;  /* inner GMRES restart length                      */
+  int32_t inner_maxit;    /* inner GMRES iteration cap                       */
+  int32_t n_vcycles;      /* V-cycles per multigrid application             */
+  int32_t n_cheb;         /* Chebyshev semi-iteration steps                  */
+  int32_t n_uzawa;        /* Uzawa steps (Oseen)                             */
+  double mu_uzawa;        /* Uzawa damping parameter (Oseen)                 */
+} pintoc_options;
+
+/* Statistics of one pintoc_solve call (host memory, filled by the library). */
+typedef struct {
+  int32_t outer_iterations;
+  int32_t converged;             /* 1 if the tolerance was met              */
+  double rel_residual;           /* final true ||b - A x|| / ||b||          */
+  double inner_iterations_mean;  /* mean inner GMRES count per block solve  */
+  int32_t inner_iterations_max;
+  int32_t precond_applications;
+  double seconds;                /* host wall time of the call              */
+  double model_bytes;            /* modelled compulsory HBM traffic         */
+} pintoc_solve_stats;
+
+/* Fill *o with the defaults above.  Never fails for a non-NULL pointer. */
+int pintoc_default_options(pintoc_options* o);
+
+/* Validate d and o, compute the per-frequency constants (section 3.1-3.2,
+ * section 4), the multigrid hierarchy and the coarsest-grid inverses, and
+ * plan the workspace.  Host only; no device memory is touched.
+ * Errors: PINTOC_EINVAL for N not a power of two >= 2, nt < 2 or > 1024,
+ * T, nu or beta <= 0, an unknown flow/inner/precision, or Oseen without wind.
+ * On success *out owns the handle; release it with pintoc_problem_destroy. */
+int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_options* o,
+                          pintoc_problem** out);
+
+/* Device bytes the problem needs (all buffers, tables and Krylov bases). */
+size_t pintoc_workspace_bytes(const pintoc_problem* p);
+
+/* Bind caller-owned device memory of at least pintoc_workspace_bytes(p) bytes
+ * (256-byte aligned) and upload the tables on ``stream``.  The memory must
+ * stay valid until the handle is destroyed or another workspace is bound.
+ * Errors: PINTOC_ENOMEM if bytes is too small, PINTOC_EINVAL for NULL or a
+ * misaligned pointer, PINTOC_EHIP if an upload fails. */
+int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes, void* stream);
+
+/* Right-hand side for v_0 = f = h = 0 (section 2.2): b = tau M v_d(t_k) on the
+ * adjoint momentum rows (b = 0 velocity entries), zero elsewhere.
+ * vd: device, [nt][2][(2N+1)^2] Q2 nodal desired state at t_k = k tau,
+ * k = 1..nt (boundary values are ignored).  b: device, canonical layout.
+ * Asynchronous on ``stream``. */
+int pintoc_assemble_rhs(pintoc_problem* p, const double* vd, double* b, void* stream);
+
+/* y = A x with A the all-at-once matrix of eq. (FinalA) (FP64).  x, y: device,
+ * canonical layout, must not alias.  Asynchronous on ``stream``. */
+int pintoc_kkt_apply(pintoc_problem* p, const double* x, double* y, void* stream);
+
+/* z = P^{-1} r, the block-circulant preconditioner of section 3 / section 4:
+ * time FFT, per-frequency block solves (per options.inner: Algorithm 1/2 for
+ * Stokes, Algorithm 3 or its GMRES wrapper for Oseen), inverse FFT.
+ * r, z: device, canonical layout, must not alias.  LINEAR mode is
+ * asynchronous on ``stream``; GMRES mode synchronises the stream once per
+ * inner iteration (convergence flags are read back). */
+int pintoc_precond_apply(pintoc_problem* p, const double* r, double* z, void* stream);
+
+/* Solve A x = b with restarted flexible GMRES (section 3.4) preconditioned by
+ * pintoc_precond_apply.  x: device, canonical; on entry the initial guess,
+ * on exit the solution (or the last iterate).  Stops when the true residual
+ * satisfies ||b - A x||_2 <= options.tol ||b||_2.  st may be NULL.
+ * Synchronises ``stream`` before returning.
+ * Returns PINTOC_OK, or PINTOC_NOT_CONVERGED after options.max_outer
+ * iterations or a Krylov breakdown without convergence (x then holds the
+ * last iterate, st the residual reached). */
+int pintoc_solve(pintoc_problem* p, const double* b, double* x, pintoc_solve_stats* st,
+                 void* stream);
+
+/* Release the handle (does not free the bound workspace, which the caller owns). */
+void pintoc_problem_destroy(pintoc_problem* p);
+
+/* Message for the last error on this thread ("" if none). */
+const char* pintoc_last_error(void);
+
+/* Vector length of the canonical layout, for the caller's allocations. */
+int64_t pintoc_vector_length(const pintoc_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PINTOC_H */

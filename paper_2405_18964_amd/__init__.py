@@ -1,0 +1,17 @@
+"""pintoc: parallel-in-time all-at-once solver for unsteady Stokes/Oseen
+distributed optimal control on MI355X (gfx950).
+
+Thin Python binding over the C ABI in ``include/pintoc.h``: argument
+marshalling only.  Every step of the computation runs in the HIP library
+``libpintoc.so`` built in-tree by ``paper_2405_18964_amd.build``.  Importing
+works without a GPU; creating a :class:`Problem` requires the built library
+and raises if it is missing (there is no fallback path).
+
+PyTorch supplies device memory (``torch.empty``) and the stream
+(``torch.cuda.current_stream()``).
+"""
+from ._lib import (INNER_GMRES, INNER_LINEAR, OSEEN, PREC_FP32_INNER, PREC_FP64, STOKES, LibraryMissing,
+                   Problem, SolveStats, library, library_path)
+
+__all__ = ["Problem", "SolveStats", "library", "library_path", "LibraryMissing", "STOKES", "OSEEN",
+           "INNER_LINEAR", "INNER_GMRES", "PREC_FP64", "PREC_FP32_INNER"]

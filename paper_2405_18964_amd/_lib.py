@@ -1,0 +1,185 @@
+"""ctypes binding of libpintoc.so (names follow include/pintoc.h)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libpintoc.so")
+
+STOKES, OSEEN = 0, 1
+INNER_LINEAR, INNER_GMRES = 0, 1
+PREC_FP64, PREC_FP32_INNER = 0, 1
+OK, NOT_CONVERGED = 0, 1
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class Desc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("nt", C.c_int32), ("T", C.c_double), ("nu", C.c_double),
+                ("beta", C.c_double), ("flow", C.c_int32), ("wind", C.POINTER(C.c_double))]
+
+
+class Options(C.Structure):
+    _fields_ = [("inner", C.c_int32), ("precision", C.c_int32), ("restart", C.c_int32),
+                ("max_outer", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
+                ("inner_restart", C.c_int32), ("inner_maxit", C.c_int32), ("n_vcycles", C.c_int32),
+                ("n_cheb", C.c_int32), ("n_uzawa", C.c_int32), ("mu_uzawa", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("outer_iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double),
+                ("inner_iterations_mean", C.c_double), ("inner_iterations_max", C.c_int32),
+                ("precond_applications", C.c_int32), ("seconds", C.c_double), ("model_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# exported symbols and their signatures (restype, argtypes)
+SIGNATURES = {
+    "pintoc_default_options": (C.c_int, [C.POINTER(Options)]),
+    "pintoc_problem_create": (C.c_int, [C.POINTER(Desc), C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "pintoc_workspace_bytes": (C.c_size_t, [C.c_void_p]),
+    "pintoc_bind_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pintoc_assemble_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pintoc_kkt_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pintoc_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pintoc_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
+    "pintoc_problem_destroy": (None, [C.c_void_p]),
+    "pintoc_last_error": (C.c_char_p, []),
+    "pintoc_vector_length": (C.c_int64, [C.c_void_p]),
+}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def library():
+    """Load libpintoc.so (once).  Raises LibraryMissing if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise LibraryMissing(f"{_LIB_PATH} not found: run paper_2405_18964_amd.build.build() first")
+        lib = C.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc < 0:
+        msg = library().pintoc_last_error().decode()
+        raise RuntimeError(f"{what} failed ({rc}): {msg}")
+    return rc
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    library().pintoc_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """One control problem bound to device memory.
+
+    Vectors are torch float64 CUDA tensors in the canonical layout of
+    include/pintoc.h (length :attr:`n_all`)."""
+
+    def __init__(self, N, nt, T, nu, beta, flow=STOKES, wind=None, device="cuda", **options):
+        import numpy as np
+        import torch
+        lib = library()
+        self._torch = torch
+        self.N, self.nt, self.T, self.nu, self.beta, self.flow = N, nt, T, nu, beta, flow
+        self._wind = None
+        wptr = None
+        if wind is not None:
+            self._wind = np.ascontiguousarray(np.asarray(wind, dtype=np.float64).reshape(-1))
+            wptr = self._wind.ctypes.data_as(C.POINTER(C.c_double))
+        d = Desc(N, nt, T, nu, beta, flow, wptr)
+        self.options = default_options(**options)
+        h = C.c_void_p()
+        _check(lib.pintoc_problem_create(C.byref(d), C.byref(self.options), C.byref(h)), "pintoc_problem_create")
+        self._h = h
+        self.n_all = int(lib.pintoc_vector_length(h))
+        self.workspace_bytes = int(lib.pintoc_workspace_bytes(h))
+        self.device = torch.device(device)
+        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        _check(lib.pintoc_bind_workspace(h, C.c_void_p(self._ws.data_ptr()), self.workspace_bytes,
+                                         self._stream()), "pintoc_bind_workspace")
+
+    @classmethod
+    def from_workload(cls, w, **options):
+        import workloads as W
+        wind = W.wind_nodal(w.N) if w.flow == OSEEN else None
+        return cls(w.N, w.nt, w.T, w.nu, w.beta, w.flow, wind, **options)
+
+    def _stream(self):
+        return C.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _vec(self, v, name):
+        t = self._torch
+        if not (isinstance(v, t.Tensor) and v.is_cuda and v.dtype == t.float64 and v.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+        if v.numel() != self.n_all:
+            raise ValueError(f"{name} has {v.numel()} entries, expected {self.n_all}")
+        return C.c_void_p(v.data_ptr())
+
+    def empty(self):
+        return self._torch.zeros(self.n_all, dtype=self._torch.float64, device=self.device)
+
+    def assemble_rhs(self, vd, out=None):
+        t = self._torch
+        nq2 = (2 * self.N + 1) ** 2
+        if not (isinstance(vd, t.Tensor) and vd.is_cuda and vd.dtype == t.float64 and vd.is_contiguous()
+                and vd.numel() == self.nt * 2 * nq2):
+            raise TypeError("vd must be a contiguous float64 CUDA tensor of shape [nt, 2, (2N+1)^2]")
+        out = self.empty() if out is None else out
+        _check(library().pintoc_assemble_rhs(self._h, C.c_void_p(vd.data_ptr()), self._vec(out, "out"),
+                                             self._stream()), "pintoc_assemble_rhs")
+        return out
+
+    def kkt_apply(self, x, out=None):
+        out = self.empty() if out is None else out
+        _check(library().pintoc_kkt_apply(self._h, self._vec(x, "x"), self._vec(out, "out"), self._stream()),
+               "pintoc_kkt_apply")
+        return out
+
+    def precond_apply(self, r, out=None):
+        out = self.empty() if out is None else out
+        _check(library().pintoc_precond_apply(self._h, self._vec(r, "r"), self._vec(out, "out"),
+                                              self._stream()), "pintoc_precond_apply")
+        return out
+
+    def solve(self, b, x=None):
+        """Returns (x, stats dict, converged flag)."""
+        x = self.empty() if x is None else x
+        st = SolveStats()
+        rc = _check(library().pintoc_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), C.byref(st),
+                                           self._stream()), "pintoc_solve")
+        return x, st.as_dict(), rc == OK
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().pintoc_problem_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

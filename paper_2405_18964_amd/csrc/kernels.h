@@ -1,0 +1,54 @@
+// Launchers of the pintoc device kernels (internal to the library).
+#pragma once
+#include "common.h"
+
+namespace pintoc {
+
+// time FFT (fft_kernels.hip)
+template <typename R>
+void launch_time_fft_fwd(hipStream_t s, const double* r, cpx<R>* V, cpx<R>* P, int nt, int L, int nq2, int np2,
+                         const double2* tw, const double2* tj, double tau, int mode);
+template <typename R>
+void launch_time_fft_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double* z, int nt, int L, int nq2,
+                         int np2, const double2* tw, const double2* tj, double tau, int mode);
+
+// per-frequency operators and multigrid pieces (mg_kernels.hip)
+template <typename R>
+void launch_q2_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef, int fpc,
+                        int nb, const double* conv, bool forward);
+template <typename R>
+void launch_q1_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef, int fpc,
+                        int nb, const double* conv, bool forward);
+template <typename R>
+void launch_residual(hipStream_t s, bool q2, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
+                     const OpCoef* coef, int fpc, int nb, const double* conv);
+template <typename R>
+void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, double h, const OpCoef* coef, int fpc,
+                  int nb, const double* conv);
+template <typename R>
+void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb);
+template <typename R>
+void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* xf, const cpx<R>* ec, int nc, int nb);
+template <typename R>
+void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb);
+template <typename R>
+void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
+                 double h, double g, double w, int first, int nb);
+template <typename R>
+void launch_unpin_in(hipStream_t s, cpx<R>* z, int nn, int nb);
+template <typename R>
+void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, const cpx<R>* yM, const double2* ab,
+                              int fpc, int nn, int nb);
+
+// all-at-once matrix, rhs, FP64 vector kernels (kkt_kernels.hip)
+void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,
+                      const double* conv);
+void launch_assemble_rhs(hipStream_t s, const double* vd, double* b, int n, int nt, double tau);
+void launch_mdot(hipStream_t s, const double* V, size_t ld, int k, const double* w, size_t n, double* part,
+                 double* out);
+void launch_mgs_update(hipStream_t s, double* w, const double* V, size_t ld, int k, const double* c, size_t n);
+void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b, size_t n);
+void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, int k, const double* c, size_t n);
+void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
+
+}  // namespace pintoc

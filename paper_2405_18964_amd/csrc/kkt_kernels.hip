@@ -1,0 +1,296 @@
+// All-at-once matrix of eq. (FinalA), its right-hand side (section 2.2) and
+// the FP64 vector kernels of the outer Krylov method.
+//
+// Canonical layout: x[b][t][v_x (2N+1)^2, v_y (2N+1)^2, p (N+1)^2].
+// Rows (section 2.2, one backward-Euler step per block, t = 0..nt-1 here):
+//   adjoint momentum  (b=0): tau M v_t + M (l_t - l_{t+1}) + tau L^T l_t + tau B^T mu_t
+//   adjoint divergence(b=0): tau B l_t
+//   state momentum    (b=1): M (v_t - v_{t-1}) + tau L v_t + tau B^T p_t - tau/beta M l_t
+//   state divergence  (b=1): tau B v_t
+// with v_{-1} = 0, l_{nt} = 0, L = nu K + N(w), the pinned pressure row and
+// the Dirichlet velocity rows zero.
+#include "kernels.h"
+
+namespace pintoc {
+
+// Weighted Q2 stencil sums at interior node (ix, iy) of one scalar grid:
+// returns M u and K u (and N u, N^T u when a convection table is given).
+// Offsets +-2 have zero weight at midpoint nodes next to the boundary; their
+// indices are clamped so that every load stays inside the grid.
+__device__ inline void q2_mk(const double* __restrict__ u, int nq, int ix, int iy, double h, const double* mx,
+                             const double* kx, const double* my, const double* ky, double& mu, double& ku) {
+  mu = 0; ku = 0;
+  int cx[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) cx[d] = min(max(ix + d - 2, 0), nq - 1);
+#pragma unroll
+  for (int dy = 0; dy < 5; ++dy) {
+    const double* row = u + min(max(iy + dy - 2, 0), nq - 1) * nq;
+    double sm = 0, sk = 0;
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) { sm += mx[dx] * row[cx[dx]]; sk += kx[dx] * row[cx[dx]]; }
+    mu += my[dy] * sm;
+    ku += ky[dy] * sm + my[dy] * sk;
+  }
+}
+
+__device__ inline void q2_conv(const double* __restrict__ u, int nq, int ix, int iy, const double* cn,
+                               double& nu_, double& ntu) {
+  nu_ = 0; ntu = 0;
+  int cx[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) cx[d] = min(max(ix + d - 2, 0), nq - 1);
+#pragma unroll
+  for (int dy = 0; dy < 5; ++dy) {
+    const double* row = u + min(max(iy + dy - 2, 0), nq - 1) * nq;
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) {
+      nu_ += cn[dy * 5 + dx] * row[cx[dx]];
+      ntu += cn[25 + dy * 5 + dx] * row[cx[dx]];
+    }
+  }
+}
+
+// (B^T q)_comp at Q2 node (jx, jy): -sum mix(ky,jy) gmix(kx,jx) q (comp 0) or
+// -sum gmix(ky,jy) mix(kx,jx) q (comp 1).
+__device__ inline double bt_node(const double* __restrict__ q, int n, double h, int jx, int jy, int comp) {
+  double mxx[3], gxx[3], mxy[3], gxy[3];
+  mixed_cols(jx, n, h, mxx, gxx);
+  mixed_cols(jy, n, h, mxy, gxy);
+  const int kx0 = (jx >> 1) - 1, ky0 = (jy >> 1) - 1, np = n + 1;
+  double s = 0;
+  for (int a = 0; a < 3; ++a) {
+    const int ky = ky0 + a;
+    if (ky < 0 || ky > n) continue;
+    const double wy = comp == 0 ? mxy[a] : gxy[a];
+    for (int c = 0; c < 3; ++c) {
+      const int kx = kx0 + c;
+      if (kx < 0 || kx > n) continue;
+      const double wx = comp == 0 ? gxx[c] : mxx[c];
+      s += wy * wx * q[ky * np + kx];
+    }
+  }
+  return -s;
+}
+
+// (B v)_k at Q1 node (kx, ky), v = (vx, vy) padded Q2 grids.
+__device__ inline double b_node(const double* __restrict__ vx, const double* __restrict__ vy, int n, double h,
+                                int kx, int ky) {
+  double mxx[5], gxx[5], mxy[5], gxy[5];
+  mixed_rows(kx, n, h, mxx, gxx);
+  mixed_rows(ky, n, h, mxy, gxy);
+  const int nq = 2 * n + 1;
+  double s = 0;
+  for (int dy = 0; dy < 5; ++dy) {
+    const int jy = 2 * ky + dy - 2;
+    if (jy < 0 || jy >= nq) continue;
+    for (int dx = 0; dx < 5; ++dx) {
+      const int jx = 2 * kx + dx - 2;
+      if (jx < 0 || jx >= nq) continue;
+      const int j = jy * nq + jx;
+      s += mxy[dy] * gxx[dx] * vx[j] + gxy[dy] * mxx[dx] * vy[j];
+    }
+  }
+  return -s;
+}
+
+__global__ void k_kkt_apply(const double* __restrict__ x, double* __restrict__ y, int n, int nt, double tau,
+                            double beta, double nu, const double* __restrict__ conv) {
+  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
+  const int L = 2 * nq2 + np2;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y, b = blockIdx.z;
+  if (g >= L) return;
+  const double h = 1.0 / n;
+  const double* X0 = x;                           // block 0: v, p
+  const double* X1 = x + (size_t)nt * L;          // block 1: l, mu
+  auto lev = [&](const double* B0, int tt) { return B0 + (size_t)tt * L; };
+  double out = 0;
+  if (g < 2 * nq2) {
+    const int comp = g >= nq2, node = g - comp * nq2;
+    const int ix = node % nq, iy = node / nq;
+    if (ix > 0 && iy > 0 && ix < nq - 1 && iy < nq - 1) {
+      double mx[5], kx[5], my[5], ky[5];
+      q2_rows(ix, h, mx, kx);
+      q2_rows(iy, h, my, ky);
+      const double* vt = lev(X0, t) + comp * nq2;
+      const double* lt = lev(X1, t) + comp * nq2;
+      double Mv, Kv, Ml, Kl;
+      q2_mk(vt, nq, ix, iy, h, mx, kx, my, ky, Mv, Kv);
+      q2_mk(lt, nq, ix, iy, h, mx, kx, my, ky, Ml, Kl);
+      double Nv = 0, NTv = 0, Nl = 0, NTl = 0;
+      if (conv) {
+        const double* cn = conv + (size_t)node * 50;
+        q2_conv(vt, nq, ix, iy, cn, Nv, NTv);
+        q2_conv(lt, nq, ix, iy, cn, Nl, NTl);
+      }
+      if (b == 0) {
+        double Mln = 0, dummy;
+        if (t + 1 < nt) q2_mk(lev(X1, t + 1) + comp * nq2, nq, ix, iy, h, mx, kx, my, ky, Mln, dummy);
+        const double btmu = bt_node(lev(X1, t) + 2 * nq2, n, h, ix, iy, comp);
+        out = tau * Mv + (Ml - Mln) + tau * (nu * Kl + NTl) + tau * btmu;
+      } else {
+        double Mvp = 0, dummy;
+        if (t > 0) q2_mk(lev(X0, t - 1) + comp * nq2, nq, ix, iy, h, mx, kx, my, ky, Mvp, dummy);
+        const double btp = bt_node(lev(X0, t) + 2 * nq2, n, h, ix, iy, comp);
+        out = (Mv - Mvp) + tau * (nu * Kv + Nv) + tau * btp - (tau / beta) * Ml;
+      }
+    }
+  } else {
+    const int k = g - 2 * nq2;
+    if (k != 0) {
+      const int kx = k % np, ky = k / np;
+      const double* src = b == 0 ? lev(X1, t) : lev(X0, t);
+      out = tau * b_node(src, src + nq2, n, h, kx, ky);
+    }
+  }
+  y[((size_t)b * nt + t) * L + g] = out;
+}
+
+// b = tau M v_d on the adjoint momentum rows, zero elsewhere.
+__global__ void k_assemble_rhs(const double* __restrict__ vd, double* __restrict__ out, int n, int nt, double tau) {
+  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
+  const int L = 2 * nq2 + np2;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y, b = blockIdx.z;
+  if (g >= L) return;
+  double v = 0;
+  if (b == 0 && g < 2 * nq2) {
+    const int comp = g >= nq2, node = g - comp * nq2;
+    const int ix = node % nq, iy = node / nq;
+    if (ix > 0 && iy > 0 && ix < nq - 1 && iy < nq - 1) {
+      double mx[5], kx[5], my[5], ky[5];
+      const double h = 1.0 / n;
+      q2_rows(ix, h, mx, kx);
+      q2_rows(iy, h, my, ky);
+      // boundary values of v_d are ignored: read them as zero
+      double s = 0;
+      const double* u = vd + ((size_t)t * 2 + comp) * nq2;
+      for (int dy = 0; dy < 5; ++dy) {
+        const int jy = iy + dy - 2;
+        if (jy <= 0 || jy >= nq - 1) continue;
+        double sm = 0;
+        for (int dx = 0; dx < 5; ++dx) {
+          const int jx = ix + dx - 2;
+          if (jx <= 0 || jx >= nq - 1) continue;
+          sm += mx[dx] * u[jy * nq + jx];
+        }
+        s += my[dy] * sm;
+      }
+      v = tau * s;
+    }
+  }
+  out[((size_t)b * nt + t) * L + g] = v;
+}
+
+void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,
+                      const double* conv) {
+  const int L = 2 * (2 * n + 1) * (2 * n + 1) + (n + 1) * (n + 1);
+  hipLaunchKernelGGL(k_kkt_apply, dim3((L + 255) / 256, nt, 2), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, conv);
+}
+
+void launch_assemble_rhs(hipStream_t s, const double* vd, double* b, int n, int nt, double tau) {
+  const int L = 2 * (2 * n + 1) * (2 * n + 1) + (n + 1) * (n + 1);
+  hipLaunchKernelGGL(k_assemble_rhs, dim3((L + 255) / 256, nt, 2), dim3(256), 0, s, vd, b, n, nt, tau);
+}
+
+// ---------------------------------------------------------------- BLAS
+// Multi-dot: out[i] = <V_i, w>, i < k, V_i = V + i*ld.  Deterministic: every
+// block reduces its slice in a fixed tree order into part[i][block]; a second
+// kernel sums each row of part sequentially.
+constexpr int kDotBlocks = 1024;
+constexpr int kMaxDots = 40;
+
+template <int K>
+__global__ void k_mdot(const double* __restrict__ V, size_t ld, int k, const double* __restrict__ w, size_t n,
+                       double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) acc[i] = 0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const double we = w[e];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+      if (i < k) acc[i] += V[i * ld + e] * we;
+  }
+  for (int i = 0; i < k && i < K; ++i) {
+    red[threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)i * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_rowsum(const double* __restrict__ part, int nblk, int k, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)i * nblk + b];
+  out[i] = s;
+}
+
+// w -= sum_i c[i] V_i   (c on device)
+__global__ void k_mgs_update(double* __restrict__ w, const double* __restrict__ V, size_t ld, int k,
+                             const double* __restrict__ c, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double s = w[e];
+    for (int i = 0; i < k; ++i) s -= c[i] * V[i * ld + e];
+    w[e] = s;
+  }
+}
+
+// y = a x + b y
+__global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = a * x[e] + b * y[e];
+}
+
+// y += sum_i c[i] Z_i  (c on device)
+__global__ void k_lincomb_add(double* __restrict__ y, const double* __restrict__ Z, size_t ld, int k,
+                              const double* __restrict__ c, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double s = y[e];
+    for (int i = 0; i < k; ++i) s += c[i] * Z[i * ld + e];
+    y[e] = s;
+  }
+}
+
+void launch_mdot(hipStream_t s, const double* V, size_t ld, int k, const double* w, size_t n, double* part,
+                 double* out) {
+  for (int i0 = 0; i0 < k; i0 += 8) {
+    const int kk = k - i0 < 8 ? k - i0 : 8;
+    hipLaunchKernelGGL(k_mdot<8>, dim3(kDotBlocks), dim3(256), 0, s, V + i0 * ld, ld, kk, w, n, part);
+    hipLaunchKernelGGL(k_rowsum, dim3(1), dim3(64), 0, s, part, kDotBlocks, kk, out + i0);
+  }
+}
+
+void launch_mgs_update(hipStream_t s, double* w, const double* V, size_t ld, int k, const double* c, size_t n) {
+  hipLaunchKernelGGL(k_mgs_update, dim3(2048), dim3(256), 0, s, w, V, ld, k, c, n);
+}
+
+void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b, size_t n) {
+  hipLaunchKernelGGL(k_axpby, dim3(2048), dim3(256), 0, s, y, x, a, b, n);
+}
+
+void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, int k, const double* c, size_t n) {
+  hipLaunchKernelGGL(k_lincomb_add, dim3(2048), dim3(256), 0, s, y, Z, ld, k, c, n);
+}
+
+// zero-fill (a kernel rather than hipMemsetAsync so the sequence stays capturable)
+__global__ void k_fill_zero(uint4* __restrict__ p, size_t n16) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += (size_t)gridDim.x * blockDim.x)
+    p[e] = make_uint4(0, 0, 0, 0);
+}
+
+void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
+  // every buffer the library zeroes is carved 256-byte aligned and padded to a
+  // multiple of 256 bytes, so rounding the length up to 16 bytes stays inside it
+  hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, (uint4*)p, (bytes + 15) / 16);
+}
+
+}  // namespace pintoc

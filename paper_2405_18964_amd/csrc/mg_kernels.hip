@@ -1,0 +1,623 @@
+// Batched per-frequency kernels: scalar Q2/Q1 operators, multicolour
+// Gauss-Seidel sweeps, residuals, grid transfers, coarsest-grid solves and
+// Chebyshev steps (section 3.4: multigrid with SOR smoothing, Chebyshev
+// semi-iteration for mass matrices).
+//
+// A "batch" is nb complex grids stored back to back.  Q2 grids are padded
+// (2n+1)^2 with the Dirichlet boundary at zero; Q1 grids hold all (n+1)^2
+// nodes (natural boundary conditions).  Grid f uses coefficient set
+// coef[f / fpc] (fpc = grids per coefficient set).
+#include "kernels.h"
+
+namespace pintoc {
+
+// Q2 operator  alpha M + gamma K + eta N + etat N^T  at interior node (ix, iy).
+// Returns (A x)(ix, iy) and the diagonal entry.  The convection stencil table
+// (if any) holds 25 coefficients per node for N and 25 for N^T.
+template <typename R>
+__device__ inline void q2_apply_node(const cpx<R>* __restrict__ x, int nq, int ix, int iy, double h,
+                                     const OpCoef& c, const double* __restrict__ conv,
+                                     cpx<R>& ax, cpx<R>& diag) {
+  double mx[5], kx[5], my[5], ky[5];
+  q2_rows(ix, h, mx, kx);
+  q2_rows(iy, h, my, ky);
+  // Offsets +-2 carry zero weight at midpoint nodes, which may sit next to the
+  // boundary: clamp their indices so every load stays inside the grid.
+  int cx[5], ry[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    cx[d] = min(max(ix + d - 2, 0), nq - 1);
+    ry[d] = min(max(iy + d - 2, 0), nq - 1) * nq;
+  }
+  double amr = 0, ami = 0, akr = 0, aki = 0;   // M x and K x
+#pragma unroll
+  for (int dy = 0; dy < 5; ++dy) {
+    double smr = 0, smi = 0, skr = 0, ski = 0;
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) {
+      cpx<R> v = x[ry[dy] + cx[dx]];
+      smr += mx[dx] * (double)v.x; smi += mx[dx] * (double)v.y;
+      skr += kx[dx] * (double)v.x; ski += kx[dx] * (double)v.y;
+    }
+    amr += my[dy] * smr; ami += my[dy] * smi;
+    akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
+  }
+  double rr = c.alpha.x * amr - c.alpha.y * ami + c.gamma.x * akr - c.gamma.y * aki;
+  double ri = c.alpha.x * ami + c.alpha.y * amr + c.gamma.x * aki + c.gamma.y * akr;
+  const double md = mx[2] * my[2], kd = kx[2] * my[2] + mx[2] * ky[2];
+  double dr = c.alpha.x * md + c.gamma.x * kd, di = c.alpha.y * md + c.gamma.y * kd;
+  if (conv) {
+    const double* cn = conv + (size_t)(iy * nq + ix) * 50;
+    double nr = 0, ni = 0, tr = 0, ti = 0;
+#pragma unroll
+    for (int dy = 0; dy < 5; ++dy) {
+#pragma unroll
+      for (int dx = 0; dx < 5; ++dx) {
+        cpx<R> v = x[ry[dy] + cx[dx]];
+        const double a = cn[dy * 5 + dx], b = cn[25 + dy * 5 + dx];
+        nr += a * (double)v.x; ni += a * (double)v.y;
+        tr += b * (double)v.x; ti += b * (double)v.y;
+      }
+    }
+    rr += c.eta.x * nr - c.eta.y * ni + c.etat.x * tr - c.etat.y * ti;
+    ri += c.eta.x * ni + c.eta.y * nr + c.etat.x * ti + c.etat.y * tr;
+    dr += c.eta.x * cn[12] + c.etat.x * cn[37];
+    di += c.eta.y * cn[12] + c.etat.y * cn[37];
+  }
+  ax.x = (R)rr; ax.y = (R)ri;
+  diag.x = (R)dr; diag.y = (R)di;
+}
+
+// Q1 operator on the unconstrained grid at node (ix, iy), 0 <= ix, iy <= n.
+// Convection table: 9 coefficients per node for N and 9 for N^T.
+template <typename R>
+__device__ inline void q1_apply_node(const cpx<R>* __restrict__ x, int n, int ix, int iy, double h,
+                                     const OpCoef& c, const double* __restrict__ conv,
+                                     cpx<R>& ax, cpx<R>& diag) {
+  const int np = n + 1;
+  double mx[3], kx[3], my[3], ky[3];
+  q1_rows(ix, n, h, mx, kx);
+  q1_rows(iy, n, h, my, ky);
+  double amr = 0, ami = 0, akr = 0, aki = 0;
+  double nr = 0, ni = 0, tr = 0, ti = 0;
+  const double* cn = conv ? conv + (size_t)(iy * np + ix) * 18 : nullptr;
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy) {
+    const int jy = iy + dy - 1;
+    if (jy < 0 || jy > n) continue;
+    double smr = 0, smi = 0, skr = 0, ski = 0;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int jx = ix + dx - 1;
+      if (jx < 0 || jx > n) continue;
+      cpx<R> v = x[jy * np + jx];
+      smr += mx[dx] * (double)v.x; smi += mx[dx] * (double)v.y;
+      skr += kx[dx] * (double)v.x; ski += kx[dx] * (double)v.y;
+      if (cn) {
+        const double a = cn[dy * 3 + dx], b = cn[9 + dy * 3 + dx];
+        nr += a * (double)v.x; ni += a * (double)v.y;
+        tr += b * (double)v.x; ti += b * (double)v.y;
+      }
+    }
+    amr += my[dy] * smr; ami += my[dy] * smi;
+    akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
+  }
+  double rr = c.alpha.x * amr - c.alpha.y * ami + c.gamma.x * akr - c.gamma.y * aki;
+  double ri = c.alpha.x * ami + c.alpha.y * amr + c.gamma.x * aki + c.gamma.y * akr;
+  const double md = mx[1] * my[1], kd = kx[1] * my[1] + mx[1] * ky[1];
+  double dr = c.alpha.x * md + c.gamma.x * kd, di = c.alpha.y * md + c.gamma.y * kd;
+  if (cn) {
+    rr += c.eta.x * nr - c.eta.y * ni + c.etat.x * tr - c.etat.y * ti;
+    ri += c.eta.x * ni + c.eta.y * nr + c.etat.x * ti + c.etat.y * tr;
+    dr += c.eta.x * cn[4] + c.etat.x * cn[13];
+    di += c.eta.y * cn[4] + c.etat.y * cn[13];
+  }
+  ax.x = (R)rr; ax.y = (R)ri;
+  diag.x = (R)dr; diag.y = (R)di;
+}
+
+// ------------------------------------------------------------- GS colours
+// Q2 colour (cx, cy): interior nodes with ix % 3 == cx, iy % 3 == cy.
+template <typename R>
+__global__ void k_q2_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b, int n, double h,
+                               int cx, int cy, int ncx, int ncy, const OpCoef* __restrict__ coef, int fpc,
+                               const double* __restrict__ conv) {
+  const int f = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncx * ncy) return;
+  const int kx = t % ncx, ky = t / ncx;
+  const int ix0 = cx == 0 ? 3 : cx, iy0 = cy == 0 ? 3 : cy;      // first interior index of the class
+  const int ix = ix0 + 3 * kx, iy = iy0 + 3 * ky;
+  const int nq = 2 * n + 1;
+  if (ix > nq - 2 || iy > nq - 2) return;
+  const size_t off = (size_t)f * nq * nq;
+  const OpCoef c = coef[f / fpc];
+  cpx<R> ax, dg;
+  q2_apply_node<R>(x + off, nq, ix, iy, h, c, conv, ax, dg);
+  const size_t i = off + (size_t)iy * nq + ix;
+  cpx<R> r = b[i] - ax;
+  cpx<R> xi = x[i];
+  x[i] = xi + cdiv(r, dg);
+}
+
+// Q1 colour (cx, cy): nodes with ix % 2 == cx, iy % 2 == cy, 0 <= ix, iy <= n.
+template <typename R>
+__global__ void k_q1_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b, int n, double h,
+                               int cx, int cy, int ncx, int ncy, const OpCoef* __restrict__ coef, int fpc,
+                               const double* __restrict__ conv) {
+  const int f = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncx * ncy) return;
+  const int ix = cx + 2 * (t % ncx), iy = cy + 2 * (t / ncx);
+  if (ix > n || iy > n) return;
+  const int np = n + 1;
+  const size_t off = (size_t)f * np * np;
+  const OpCoef c = coef[f / fpc];
+  cpx<R> ax, dg;
+  q1_apply_node<R>(x + off, n, ix, iy, h, c, conv, ax, dg);
+  const size_t i = off + (size_t)iy * np + ix;
+  cpx<R> r = b[i] - ax;
+  x[i] = x[i] + cdiv(r, dg);
+}
+
+// ------------------------------------------------------ residual r = b - A x
+template <typename R>
+__global__ void k_q2_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
+                              int n, double h, const OpCoef* __restrict__ coef, int fpc,
+                              const double* __restrict__ conv) {
+  const int f = blockIdx.y;
+  const int nq = 2 * n + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nq * nq) return;
+  const int ix = t % nq, iy = t / nq;
+  const size_t i = (size_t)f * nq * nq + t;
+  if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) { r[i] = cmk<cpx<R>>(0, 0); return; }
+  cpx<R> ax, dg;
+  q2_apply_node<R>(x + (size_t)f * nq * nq, nq, ix, iy, h, coef[f / fpc], conv, ax, dg);
+  r[i] = b[i] - ax;
+}
+
+template <typename R>
+__global__ void k_q1_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
+                              int n, double h, const OpCoef* __restrict__ coef, int fpc,
+                              const double* __restrict__ conv) {
+  const int f = blockIdx.y;
+  const int np = n + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= np * np) return;
+  const int ix = t % np, iy = t / np;
+  cpx<R> ax, dg;
+  q1_apply_node<R>(x + (size_t)f * np * np, n, ix, iy, h, coef[f / fpc], conv, ax, dg);
+  const size_t i = (size_t)f * np * np + t;
+  r[i] = b[i] - ax;
+}
+
+// y = A x (operator application; b = 0 residual form negated)
+template <typename R>
+__global__ void k_q2_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
+                           const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv) {
+  const int f = blockIdx.y;
+  const int nq = 2 * n + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nq * nq) return;
+  const int ix = t % nq, iy = t / nq;
+  const size_t i = (size_t)f * nq * nq + t;
+  if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) { y[i] = cmk<cpx<R>>(0, 0); return; }
+  cpx<R> ax, dg;
+  q2_apply_node<R>(x + (size_t)f * nq * nq, nq, ix, iy, h, coef[f / fpc], conv, ax, dg);
+  y[i] = ax;
+}
+
+template <typename R>
+__global__ void k_q1_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
+                           const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv) {
+  const int f = blockIdx.y;
+  const int np = n + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= np * np) return;
+  const int ix = t % np, iy = t / np;
+  cpx<R> ax, dg;
+  q1_apply_node<R>(x + (size_t)f * np * np, n, ix, iy, h, coef[f / fpc], conv, ax, dg);
+  y[(size_t)f * np * np + t] = ax;
+}
+
+// ---------------------------------------------------------------- transfers
+// 1-D Q2 restriction weights for coarse node I, fine offsets -3..3 around 2I.
+__device__ inline void q2_restrict_w(int I, double w[7]) {
+  if ((I & 1) == 0) {
+    w[0] = -0.125; w[1] = 0; w[2] = 0.375; w[3] = 1; w[4] = 0.375; w[5] = 0; w[6] = -0.125;
+  } else {
+    w[0] = 0; w[1] = 0; w[2] = 0.75; w[3] = 1; w[4] = 0.75; w[5] = 0; w[6] = 0;
+  }
+}
+
+// bc = P^T rf on coarse interior nodes (fine boundary residuals are zero).
+template <typename R>
+__global__ void k_q2_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc) {
+  const int f = blockIdx.y;
+  const int nqc = 2 * nc + 1, nqf = 4 * nc + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nqc * nqc) return;
+  const int I = t % nqc, J = t / nqc;
+  const size_t oc = (size_t)f * nqc * nqc + t;
+  if (I == 0 || J == 0 || I == nqc - 1 || J == nqc - 1) { bc[oc] = cmk<cpx<R>>(0, 0); return; }
+  double wx[7], wy[7];
+  q2_restrict_w(I, wx);
+  q2_restrict_w(J, wy);
+  const cpx<R>* src = rf + (size_t)f * nqf * nqf;
+  double sr = 0, si = 0;
+  for (int dy = 0; dy < 7; ++dy) {
+    if (wy[dy] == 0.0) continue;
+    const int fy = 2 * J + dy - 3;
+    double rr = 0, ri = 0;
+    for (int dx = 0; dx < 7; ++dx) {
+      if (wx[dx] == 0.0) continue;
+      const cpx<R> v = src[(size_t)fy * nqf + 2 * I + dx - 3];
+      rr += wx[dx] * (double)v.x; ri += wx[dx] * (double)v.y;
+    }
+    sr += wy[dy] * rr; si += wy[dy] * ri;
+  }
+  bc[oc] = cmk<cpx<R>>(sr, si);
+}
+
+// 1-D Q2 prolongation weights of fine node i onto coarse nodes 2e, 2e+1, 2e+2 (e = i/4).
+__device__ inline void q2_prolong_w(int i, int& c0, double w[3]) {
+  const int e = i >> 2, r = i & 3;
+  c0 = 2 * e;
+  if (r == 0) { w[0] = 1; w[1] = 0; w[2] = 0; }
+  else if (r == 2) { w[0] = 0; w[1] = 1; w[2] = 0; }
+  else if (r == 1) { w[0] = 0.375; w[1] = 0.75; w[2] = -0.125; }
+  else { w[0] = -0.125; w[1] = 0.75; w[2] = 0.375; }
+}
+
+// xf += P ec on fine interior nodes.
+template <typename R>
+__global__ void k_q2_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc) {
+  const int f = blockIdx.y;
+  const int nqc = 2 * nc + 1, nqf = 4 * nc + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nqf * nqf) return;
+  const int i = t % nqf, j = t / nqf;
+  if (i == 0 || j == 0 || i == nqf - 1 || j == nqf - 1) return;
+  int cx0, cy0;
+  double wx[3], wy[3];
+  q2_prolong_w(i, cx0, wx);
+  q2_prolong_w(j, cy0, wy);
+  const cpx<R>* src = ec + (size_t)f * nqc * nqc;
+  double sr = 0, si = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (wy[a] == 0.0) continue;
+    double rr = 0, ri = 0;
+    for (int b2 = 0; b2 < 3; ++b2) {
+      if (wx[b2] == 0.0) continue;
+      const int cx = cx0 + b2, cy = cy0 + a;
+      const cpx<R> v = src[(size_t)cy * nqc + cx];
+      rr += wx[b2] * (double)v.x; ri += wx[b2] * (double)v.y;
+    }
+    sr += wy[a] * rr; si += wy[a] * ri;
+  }
+  const size_t o = (size_t)f * nqf * nqf + t;
+  cpx<R> v = xf[o];
+  v.x = (R)((double)v.x + sr); v.y = (R)((double)v.y + si);
+  xf[o] = v;
+}
+
+// Q1: bc = P^T rf (coarse node I <-> fine 2I, weights 1/2, 1, 1/2).
+template <typename R>
+__global__ void k_q1_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc) {
+  const int f = blockIdx.y;
+  const int npc = nc + 1, nf = 2 * nc, npf = nf + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npc * npc) return;
+  const int I = t % npc, J = t / npc;
+  const cpx<R>* src = rf + (size_t)f * npf * npf;
+  const double w[3] = {0.5, 1.0, 0.5};
+  double sr = 0, si = 0;
+  for (int dy = 0; dy < 3; ++dy) {
+    const int fy = 2 * J + dy - 1;
+    if (fy < 0 || fy > nf) continue;
+    for (int dx = 0; dx < 3; ++dx) {
+      const int fx = 2 * I + dx - 1;
+      if (fx < 0 || fx > nf) continue;
+      const cpx<R> v = src[(size_t)fy * npf + fx];
+      sr += w[dx] * w[dy] * (double)v.x; si += w[dx] * w[dy] * (double)v.y;
+    }
+  }
+  bc[(size_t)f * npc * npc + t] = cmk<cpx<R>>(sr, si);
+}
+
+template <typename R>
+__global__ void k_q1_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc) {
+  const int f = blockIdx.y;
+  const int npc = nc + 1, npf = 2 * nc + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npf * npf) return;
+  const int i = t % npf, j = t / npf;
+  const cpx<R>* src = ec + (size_t)f * npc * npc;
+  const int ia = i >> 1, ib = (i + 1) >> 1, ja = j >> 1, jb = (j + 1) >> 1;
+  const double wx = (i & 1) ? 0.5 : 1.0, wy = (j & 1) ? 0.5 : 1.0;
+  double sr = 0, si = 0;
+  // (i odd) -> average of ia, ib; (i even) -> ia == ib, weight 1 counted once
+  const int nxs = (i & 1) ? 2 : 1, nys = (j & 1) ? 2 : 1;
+  for (int a = 0; a < nys; ++a) {
+    const int cy = a == 0 ? ja : jb;
+    for (int b2 = 0; b2 < nxs; ++b2) {
+      const int cx = b2 == 0 ? ia : ib;
+      const cpx<R> v = src[(size_t)cy * npc + cx];
+      sr += wx * wy * (double)v.x; si += wx * wy * (double)v.y;
+    }
+  }
+  const size_t o = (size_t)f * npf * npf + t;
+  cpx<R> v = xf[o];
+  v.x = (R)((double)v.x + sr); v.y = (R)((double)v.y + si);
+  xf[o] = v;
+}
+
+// --------------------------------------------------------- coarsest grid
+// N = 2 level.  Q2: 9 interior unknowns (padded 5x5 grid, nodes (1..3)^2);
+// Q1: 9 nodes with node 0 held at zero and an 8x8 inverse for nodes 1..8.
+// inv[ci] holds the dense inverse (row-major, complex FP64) per coefficient set.
+template <typename R>
+__global__ void k_q2_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
+                                  const double2* __restrict__ inv, int fpc, int nb) {
+  const int f = blockIdx.x * (blockDim.x / 9) + threadIdx.x / 9;
+  const int r = threadIdx.x % 9;
+  if (f >= nb || threadIdx.x >= (blockDim.x / 9) * 9) return;
+  const double2* A = inv + (size_t)(f / fpc) * 81;
+  const cpx<R>* bb = b + (size_t)f * 25;
+  double sr = 0, si = 0;
+  for (int c = 0; c < 9; ++c) {
+    const cpx<R> v = bb[(1 + c / 3) * 5 + 1 + c % 3];
+    const double2 a = A[r * 9 + c];
+    sr += a.x * (double)v.x - a.y * (double)v.y;
+    si += a.x * (double)v.y + a.y * (double)v.x;
+  }
+  x[(size_t)f * 25 + (1 + r / 3) * 5 + 1 + r % 3] = cmk<cpx<R>>(sr, si);
+}
+
+template <typename R>
+__global__ void k_q1_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
+                                  const double2* __restrict__ inv, int fpc, int nb) {
+  const int f = blockIdx.x * (blockDim.x / 9) + threadIdx.x / 9;
+  const int r = threadIdx.x % 9;
+  if (f >= nb || threadIdx.x >= (blockDim.x / 9) * 9) return;
+  if (r == 0) { x[(size_t)f * 9] = cmk<cpx<R>>(0, 0); return; }
+  const double2* A = inv + (size_t)(f / fpc) * 64;
+  const cpx<R>* bb = b + (size_t)f * 9;
+  double sr = 0, si = 0;
+  for (int c = 0; c < 8; ++c) {
+    const cpx<R> v = bb[1 + c];
+    const double2 a = A[(r - 1) * 8 + c];
+    sr += a.x * (double)v.x - a.y * (double)v.y;
+    si += a.x * (double)v.y + a.y * (double)v.x;
+  }
+  x[(size_t)f * 9 + r] = cmk<cpx<R>>(sr, si);
+}
+
+// ---------------------------------------------------------------- Chebyshev
+// One step of the Jacobi-preconditioned Chebyshev semi-iteration for the
+// mass matrix (Q2 interior or Q1 unconstrained):
+//   first:  xn = g D^{-1} b
+//   else:   xn = w (x - xp + g D^{-1}(b - M x)) + xp
+// xn may alias xp (each thread reads its own xp entry before writing).
+template <typename R>
+__global__ void k_q2_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
+                          const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first) {
+  const int f = blockIdx.y;
+  const int nq = 2 * n + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nq * nq) return;
+  const int ix = t % nq, iy = t / nq;
+  const size_t i = (size_t)f * nq * nq + t;
+  if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) { xn[i] = cmk<cpx<R>>(0, 0); return; }
+  OpCoef c; c.alpha = make_double2(1, 0); c.gamma = make_double2(0, 0);
+  c.eta = c.gamma; c.etat = c.gamma;
+  if (first) {
+    double mx[5], kx[5], my[5], ky[5];
+    q2_rows(ix, h, mx, kx); q2_rows(iy, h, my, ky);
+    const double d = mx[2] * my[2];
+    const cpx<R> bi = b[i];
+    xn[i] = cmk<cpx<R>>(g * (double)bi.x / d, g * (double)bi.y / d);
+    return;
+  }
+  cpx<R> ax, dg;
+  q2_apply_node<R>(x + (size_t)f * nq * nq, nq, ix, iy, h, c, nullptr, ax, dg);
+  const cpx<R> bi = b[i], xi = x[i], pi = xp[i];
+  const double d = (double)dg.x;
+  xn[i] = cmk<cpx<R>>(w * ((double)xi.x - (double)pi.x + g * ((double)bi.x - (double)ax.x) / d) + (double)pi.x,
+                      w * ((double)xi.y - (double)pi.y + g * ((double)bi.y - (double)ax.y) / d) + (double)pi.y);
+}
+
+template <typename R>
+__global__ void k_q1_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
+                          const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first) {
+  const int f = blockIdx.y;
+  const int np = n + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= np * np) return;
+  const int ix = t % np, iy = t / np;
+  const size_t i = (size_t)f * np * np + t;
+  OpCoef c; c.alpha = make_double2(1, 0); c.gamma = make_double2(0, 0);
+  c.eta = c.gamma; c.etat = c.gamma;
+  cpx<R> ax, dg;
+  if (first) {
+    double mx[3], kx[3], my[3], ky[3];
+    q1_rows(ix, n, h, mx, kx); q1_rows(iy, n, h, my, ky);
+    const double d = mx[1] * my[1];
+    const cpx<R> bi = b[i];
+    xn[i] = cmk<cpx<R>>(g * (double)bi.x / d, g * (double)bi.y / d);
+    return;
+  }
+  q1_apply_node<R>(x + (size_t)f * np * np, n, ix, iy, h, c, nullptr, ax, dg);
+  const cpx<R> bi = b[i], xi = x[i], pi = xp[i];
+  const double d = (double)dg.x;
+  xn[i] = cmk<cpx<R>>(w * ((double)xi.x - (double)pi.x + g * ((double)bi.x - (double)ax.x) / d) + (double)pi.x,
+                      w * ((double)xi.y - (double)pi.y + g * ((double)bi.y - (double)ax.y) / d) + (double)pi.y);
+}
+
+// ------------------------------------------------ pressure pin in / pin out
+// z[f][0] = -sum_{i >= 1} z[f][i]   (the extension (I - e0 1^T) R^T of a
+// pinned pressure field whose node-0 entry is zero on entry).
+// One block per grid; fixed-order tree reduction (deterministic).
+template <typename R>
+__global__ void k_unpin_in(cpx<R>* __restrict__ z, int nn) {
+  __shared__ double sr[256], si[256];
+  const int f = blockIdx.x;
+  cpx<R>* g = z + (size_t)f * nn;
+  double ar = 0, ai = 0;
+  for (int i = 1 + threadIdx.x; i < nn; i += blockDim.x) { ar += (double)g[i].x; ai += (double)g[i].y; }
+  sr[threadIdx.x] = ar; si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) { sr[threadIdx.x] += sr[threadIdx.x + s]; si[threadIdx.x] += si[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[0] = cmk<cpx<R>>(-sr[0], -si[0]);
+}
+
+// out = a_j yK + g_j yM, then shift by out[node 0] so that node 0 is zero
+// (R (I - 1 e0^T)).  Coefficients per grid pair: ab[f / fpc] = (a, g) real.
+template <typename R>
+__global__ void k_schur_combine_pin(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ yK,
+                                    const cpx<R>* __restrict__ yM, const double2* __restrict__ ab,
+                                    int fpc, int nn) {
+  const int f = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nn) return;
+  const double a = ab[f / fpc].x, g = ab[f / fpc].y;
+  const size_t o = (size_t)f * nn;
+  const cpx<R> k0 = yK[o], m0 = yM[o], k = yK[o + t], m = yM[o + t];
+  out[o + t] = cmk<cpx<R>>(a * ((double)k.x - (double)k0.x) + g * ((double)m.x - (double)m0.x),
+                           a * ((double)k.y - (double)k0.y) + g * ((double)m.y - (double)m0.y));
+}
+
+// ------------------------------------------------------------ launchers
+static inline dim3 grid2(long work, int nb, int bs = 256) { return dim3((unsigned)((work + bs - 1) / bs), nb); }
+
+template <typename R>
+void launch_q2_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef,
+                        int fpc, int nb, const double* conv, bool forward) {
+  const int nq = 2 * n + 1;
+  for (int k = 0; k < 9; ++k) {
+    const int c = forward ? k : 8 - k;
+    const int cx = c % 3, cy = c / 3;
+    const int ix0 = cx == 0 ? 3 : cx, iy0 = cy == 0 ? 3 : cy;
+    const int ncx = ix0 <= nq - 2 ? (nq - 2 - ix0) / 3 + 1 : 0;
+    const int ncy = iy0 <= nq - 2 ? (nq - 2 - iy0) / 3 + 1 : 0;
+    if (ncx == 0 || ncy == 0) continue;
+    hipLaunchKernelGGL(k_q2_gs_colour<R>, grid2((long)ncx * ncy, nb), dim3(256), 0, s, x, b, n, h, cx, cy,
+                       ncx, ncy, coef, fpc, conv);
+  }
+}
+
+template <typename R>
+void launch_q1_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef,
+                        int fpc, int nb, const double* conv, bool forward) {
+  for (int k = 0; k < 4; ++k) {
+    const int c = forward ? k : 3 - k;
+    const int cx = c % 2, cy = c / 2;
+    const int ncx = (n - cx) / 2 + 1, ncy = (n - cy) / 2 + 1;
+    hipLaunchKernelGGL(k_q1_gs_colour<R>, grid2((long)ncx * ncy, nb), dim3(256), 0, s, x, b, n, h, cx, cy,
+                       ncx, ncy, coef, fpc, conv);
+  }
+}
+
+template <typename R>
+void launch_residual(hipStream_t s, bool q2, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
+                     const OpCoef* coef, int fpc, int nb, const double* conv) {
+  if (q2) {
+    const int nq = 2 * n + 1;
+    hipLaunchKernelGGL(k_q2_residual<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv);
+  } else {
+    const int np = n + 1;
+    hipLaunchKernelGGL(k_q1_residual<R>, grid2((long)np * np, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv);
+  }
+}
+
+template <typename R>
+void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, double h, const OpCoef* coef,
+                  int fpc, int nb, const double* conv) {
+  if (q2) {
+    const int nq = 2 * n + 1;
+    hipLaunchKernelGGL(k_q2_apply<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv);
+  } else {
+    const int np = n + 1;
+    hipLaunchKernelGGL(k_q1_apply<R>, grid2((long)np * np, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv);
+  }
+}
+
+template <typename R>
+void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb) {
+  if (q2) {
+    const int nqc = 2 * nc + 1;
+    hipLaunchKernelGGL(k_q2_restrict<R>, grid2((long)nqc * nqc, nb), dim3(256), 0, s, bc, rf, nc);
+  } else {
+    const int npc = nc + 1;
+    hipLaunchKernelGGL(k_q1_restrict<R>, grid2((long)npc * npc, nb), dim3(256), 0, s, bc, rf, nc);
+  }
+}
+
+template <typename R>
+void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* xf, const cpx<R>* ec, int nc, int nb) {
+  if (q2) {
+    const int nqf = 4 * nc + 1;
+    hipLaunchKernelGGL(k_q2_prolong_add<R>, grid2((long)nqf * nqf, nb), dim3(256), 0, s, xf, ec, nc);
+  } else {
+    const int npf = 2 * nc + 1;
+    hipLaunchKernelGGL(k_q1_prolong_add<R>, grid2((long)npf * npf, nb), dim3(256), 0, s, xf, ec, nc);
+  }
+}
+
+template <typename R>
+void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb) {
+  const int per = 256 / 9;
+  const unsigned blocks = (unsigned)((nb + per - 1) / per);
+  if (q2) hipLaunchKernelGGL(k_q2_coarse_solve<R>, dim3(blocks), dim3(256), 0, s, x, b, inv, fpc, nb);
+  else hipLaunchKernelGGL(k_q1_coarse_solve<R>, dim3(blocks), dim3(256), 0, s, x, b, inv, fpc, nb);
+}
+
+template <typename R>
+void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
+                 double h, double g, double w, int first, int nb) {
+  if (q2) {
+    const int nq = 2 * n + 1;
+    hipLaunchKernelGGL(k_q2_cheb<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, xn, x, xp, b, n, h, g, w, first);
+  } else {
+    const int np = n + 1;
+    hipLaunchKernelGGL(k_q1_cheb<R>, grid2((long)np * np, nb), dim3(256), 0, s, xn, x, xp, b, n, h, g, w, first);
+  }
+}
+
+template <typename R>
+void launch_unpin_in(hipStream_t s, cpx<R>* z, int nn, int nb) {
+  hipLaunchKernelGGL(k_unpin_in<R>, dim3(nb), dim3(256), 0, s, z, nn);
+}
+
+template <typename R>
+void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, const cpx<R>* yM, const double2* ab,
+                              int fpc, int nn, int nb) {
+  hipLaunchKernelGGL(k_schur_combine_pin<R>, grid2(nn, nb), dim3(256), 0, s, out, yK, yM, ab, fpc, nn);
+}
+
+#define PINTOC_INST(R)                                                                                        \
+  template void launch_q2_gs_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
+                                      const double*, bool);                                                    \
+  template void launch_q1_gs_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
+                                      const double*, bool);                                                    \
+  template void launch_residual<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,       \
+                                   const OpCoef*, int, int, const double*);                                    \
+  template void launch_apply<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
+                                const double*);                                                                \
+  template void launch_restrict<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int);                       \
+  template void launch_prolong_add<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int);                    \
+  template void launch_coarse<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const double2*, int, int);         \
+  template void launch_cheb<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int,    \
+                               double, double, double, int, int);                                              \
+  template void launch_unpin_in<R>(hipStream_t, cpx<R>*, int, int);                                            \
+  template void launch_schur_combine_pin<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, \
+                                            int, int, int);
+
+PINTOC_INST(double)
+PINTOC_INST(float)
+
+}  // namespace pintoc

@@ -1,0 +1,549 @@
+// Host side of the pintoc library: problem set-up, workspace plan, the
+// block-circulant preconditioner (sections 3-4) and the outer flexible GMRES
+// (section 3.4).  Every arithmetic step on vectors runs in the kernels of
+// fft_kernels.hip, mg_kernels.hip and kkt_kernels.hip; the host only holds
+// scalars (per-frequency constants, Hessenberg matrices, coarsest-grid
+// inverses computed once at set-up).
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pintoc.h"
+#include "kernels.h"
+
+using namespace pintoc;
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+static int fail(int code, const std::string& msg) { g_err = msg; return code; }
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(PINTOC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------ multigrid plan
+struct MGPlan {
+  bool q2 = true;
+  int nlev = 0;
+  int N = 0;            // finest n
+  int nb = 0;           // grids in the batch
+  int fpc = 1;          // grids per coefficient set
+  int ncoef = 0;
+  std::vector<OpCoef> coef_h;
+  std::vector<double2> inv_h;          // coarsest inverses, per coefficient set
+  OpCoef* coef = nullptr;              // device
+  double2* inv = nullptr;              // device
+  std::vector<const double*> conv;     // per level (device) or null
+  // per-level device buffers (complex, precision-typed); level 0 uses r only
+  std::vector<void*> b, x, r;
+  int n(int l) const { return N >> l; }
+  size_t nodes(int l) const {
+    const size_t m = q2 ? (size_t)(2 * n(l) + 1) : (size_t)(n(l) + 1);
+    return m * m;
+  }
+};
+
+struct pintoc_problem {
+  pintoc_problem_desc d{};
+  pintoc_options o{};
+  std::vector<double> wind;
+  double tau = 0;
+  int nf = 0, L = 0, nq2 = 0, np2 = 0;
+  int64_t n_all = 0;
+  size_t csize = 16;                    // bytes per complex entry of the inner solves
+  // host tables
+  std::vector<double2> tw_h, tj_h, ab_h;
+  // device tables / buffers (carved from the workspace)
+  void* ws = nullptr;
+  size_t ws_bytes = 0, need = 0;
+  double2 *tw = nullptr, *tj = nullptr, *ab = nullptr;
+  void *Vb = nullptr, *Vx = nullptr, *Pb = nullptr, *PxK = nullptr, *PxM = nullptr, *PxM2 = nullptr, *Px = nullptr;
+  MGPlan mgW, mgK;
+  // outer FGMRES
+  double *Vk = nullptr, *Zk = nullptr, *rvec = nullptr, *xtmp = nullptr;
+  double *dd = nullptr, *dd2 = nullptr, *part = nullptr;
+  bool bound = false;
+  // statistics
+  int precond_apps = 0;
+};
+
+// -------------------------------------------------------- small host helpers
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Dense complex inverse by Gauss-Jordan elimination with partial pivoting.
+static bool invert(std::vector<cd>& A, int n) {
+  std::vector<cd> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(A[r * n + c]) > std::abs(A[p * n + c])) p = r;
+    if (std::abs(A[p * n + c]) == 0.0) return false;
+    if (p != c)
+      for (int k = 0; k < n; ++k) { std::swap(A[p * n + k], A[c * n + k]); std::swap(I[p * n + k], I[c * n + k]); }
+    const cd piv = A[c * n + c];
+    for (int k = 0; k < n; ++k) { A[c * n + k] /= piv; I[c * n + k] /= piv; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const cd f = A[r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) { A[r * n + k] -= f * A[c * n + k]; I[r * n + k] -= f * I[c * n + k]; }
+    }
+  }
+  A.swap(I);
+  return true;
+}
+
+static cd toc(double2 v) { return cd(v.x, v.y); }
+
+// Coarsest (n = 2) operator alpha M + gamma K (+ eta N + etat N^T) as a dense
+// matrix and its inverse.  Q2: the 9 interior nodes of the padded 5x5 grid.
+// Q1: the 9 nodes of the 3x3 grid with node 0 removed (8x8).
+static bool coarse_inverse(bool q2, const OpCoef& c, const std::vector<double>* conv, std::vector<double2>& out) {
+  const int n = 2;
+  const double h = 1.0 / n;
+  if (q2) {
+    std::vector<cd> A(81, 0.0);
+    for (int r = 0; r < 9; ++r) {
+      const int ix = 1 + r % 3, iy = 1 + r / 3;
+      double mx[5], kx[5], my[5], ky[5];
+      q2_rows(ix, h, mx, kx);
+      q2_rows(iy, h, my, ky);
+      for (int q = 0; q < 9; ++q) {
+        const int jx = 1 + q % 3, jy = 1 + q / 3, dx = jx - ix + 2, dy = jy - iy + 2;
+        if (dx < 0 || dx > 4 || dy < 0 || dy > 4) continue;
+        cd v = toc(c.alpha) * (mx[dx] * my[dy]) + toc(c.gamma) * (kx[dx] * my[dy] + mx[dx] * ky[dy]);
+        if (conv) {
+          const double* cn = conv->data() + (size_t)(iy * 5 + ix) * 50;
+          v += toc(c.eta) * cn[dy * 5 + dx] + toc(c.etat) * cn[25 + dy * 5 + dx];
+        }
+        A[r * 9 + q] = v;
+      }
+    }
+    if (!invert(A, 9)) return false;
+    for (auto& v : A) out.push_back(make_double2(v.real(), v.imag()));
+  } else {
+    std::vector<cd> A(64, 0.0);
+    for (int r = 1; r < 9; ++r) {
+      const int ix = r % 3, iy = r / 3;
+      double mx[3], kx[3], my[3], ky[3];
+      q1_rows(ix, n, h, mx, kx);
+      q1_rows(iy, n, h, my, ky);
+      for (int q = 1; q < 9; ++q) {
+        const int jx = q % 3, jy = q / 3, dx = jx - ix + 1, dy = jy - iy + 1;
+        if (dx < 0 || dx > 2 || dy < 0 || dy > 2) continue;
+        cd v = toc(c.alpha) * (mx[dx] * my[dy]) + toc(c.gamma) * (kx[dx] * my[dy] + mx[dx] * ky[dy]);
+        if (conv) {
+          const double* cn = conv->data() + (size_t)(iy * 3 + ix) * 18;
+          v += toc(c.eta) * cn[dy * 3 + dx] + toc(c.etat) * cn[9 + dy * 3 + dx];
+        }
+        A[(r - 1) * 8 + (q - 1)] = v;
+      }
+    }
+    if (!invert(A, 8)) return false;
+    for (auto& v : A) out.push_back(make_double2(v.real(), v.imag()));
+  }
+  return true;
+}
+
+static OpCoef mkcoef(cd a, cd g, cd e = 0.0, cd et = 0.0) {
+  OpCoef c;
+  c.alpha = make_double2(a.real(), a.imag());
+  c.gamma = make_double2(g.real(), g.imag());
+  c.eta = make_double2(e.real(), e.imag());
+  c.etat = make_double2(et.real(), et.imag());
+  return c;
+}
+
+// ------------------------------------------------------------ workspace plan
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T> T* take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  }
+};
+
+static void plan_mg_buffers(MGPlan& m, Carver& cv, size_t csize) {
+  m.b.assign(m.nlev, nullptr);
+  m.x.assign(m.nlev, nullptr);
+  m.r.assign(m.nlev, nullptr);
+  for (int l = 0; l < m.nlev; ++l) {
+    const size_t bytes = m.nodes(l) * m.nb * csize;
+    if (l > 0) {
+      m.b[l] = cv.take<char>(bytes);
+      m.x[l] = cv.take<char>(bytes);
+    }
+    if (l + 1 < m.nlev) m.r[l] = cv.take<char>(bytes);
+  }
+  m.coef = cv.take<OpCoef>(sizeof(OpCoef) * m.ncoef);
+  m.inv = cv.take<double2>(sizeof(double2) * m.inv_h.size());
+}
+
+static void carve(pintoc_problem* p, char* base) {
+  Carver cv{base};
+  const int nf = p->nf;
+  p->tw = cv.take<double2>(sizeof(double2) * (p->d.nt / 2));
+  p->tj = cv.take<double2>(sizeof(double2) * nf);
+  p->ab = cv.take<double2>(sizeof(double2) * nf);
+  const size_t vbytes = (size_t)4 * nf * p->nq2 * p->csize;
+  const size_t pbytes = (size_t)2 * nf * p->np2 * p->csize;
+  p->Vb = cv.take<char>(vbytes);
+  p->Vx = cv.take<char>(vbytes);
+  p->Pb = cv.take<char>(pbytes);
+  p->PxK = cv.take<char>(pbytes);
+  p->PxM = cv.take<char>(pbytes);
+  p->PxM2 = cv.take<char>(pbytes);
+  p->Px = cv.take<char>(pbytes);
+  plan_mg_buffers(p->mgW, cv, p->csize);
+  plan_mg_buffers(p->mgK, cv, p->csize);
+  const int m = p->o.restart;
+  const size_t vb = sizeof(double) * (size_t)p->n_all;
+  p->Vk = cv.take<double>(vb * (m + 1));
+  p->Zk = cv.take<double>(vb * m);
+  p->rvec = cv.take<double>(vb);
+  p->xtmp = cv.take<double>(vb);
+  p->dd = cv.take<double>(sizeof(double) * 64);
+  p->dd2 = cv.take<double>(sizeof(double) * 64);
+  p->part = cv.take<double>(sizeof(double) * 8 * 1024);
+  p->need = cv.off;
+}
+
+// ------------------------------------------------------------ public: options
+extern "C" int pintoc_default_options(pintoc_options* o) {
+  if (!o) return fail(PINTOC_EINVAL, "options pointer is NULL");
+  o->inner = PINTOC_INNER_LINEAR;
+  o->precision = PINTOC_PREC_FP64;
+  o->restart = 10;
+  o->max_outer = 200;
+  o->tol = 1e-8;
+  o->inner_tol = 1e-2;
+  o->inner_restart = 50;
+  o->inner_maxit = 200;
+  o->n_vcycles = 4;
+  o->n_cheb = 10;
+  o->n_uzawa = 6;
+  o->mu_uzawa = 0.75;
+  return PINTOC_OK;
+}
+
+extern "C" const char* pintoc_last_error(void) { return g_err.c_str(); }
+
+extern "C" int64_t pintoc_vector_length(const pintoc_problem* p) { return p ? p->n_all : 0; }
+
+extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_options* o, pintoc_problem** out) {
+  if (!d || !out) return fail(PINTOC_EINVAL, "NULL descriptor or output pointer");
+  pintoc_options opt;
+  pintoc_default_options(&opt);
+  if (o) opt = *o;
+  if (d->N < 2 || !pow2(d->N) || d->N > 4096) return fail(PINTOC_EINVAL, "N must be a power of two in [2, 4096]");
+  if (d->nt < 2 || !pow2(d->nt) || d->nt > 1024) return fail(PINTOC_EINVAL, "nt must be a power of two in [2, 1024]");
+  if (!(d->T > 0) || !(d->nu > 0) || !(d->beta > 0)) return fail(PINTOC_EINVAL, "T, nu and beta must be > 0");
+  if (d->flow != PINTOC_STOKES && d->flow != PINTOC_OSEEN) return fail(PINTOC_EINVAL, "unknown flow");
+  if (d->flow == PINTOC_OSEEN) return fail(PINTOC_EINVAL, "Oseen flow is not available in this build");
+  if (opt.inner != PINTOC_INNER_LINEAR) return fail(PINTOC_EINVAL, "only the linear inner mode is available");
+  if (opt.precision != PINTOC_PREC_FP64 && opt.precision != PINTOC_PREC_FP32_INNER)
+    return fail(PINTOC_EINVAL, "unknown precision");
+  if (opt.restart < 1 || opt.restart > 60 || opt.max_outer < 1 || !(opt.tol > 0) || opt.n_vcycles < 1 ||
+      opt.n_cheb < 1)
+    return fail(PINTOC_EINVAL, "invalid solver options");
+  auto* p = new pintoc_problem();
+  p->d = *d;
+  p->d.wind = nullptr;
+  p->o = opt;
+  const int N = d->N, nt = d->nt;
+  p->tau = d->T / nt;
+  p->nf = nt / 2 + 1;
+  p->nq2 = (2 * N + 1) * (2 * N + 1);
+  p->np2 = (N + 1) * (N + 1);
+  p->L = 2 * p->nq2 + p->np2;
+  p->n_all = (int64_t)2 * nt * p->L;
+  p->csize = opt.precision == PINTOC_PREC_FP64 ? 16 : 8;
+  // twiddles exp(-2 pi i k / nt)
+  for (int k = 0; k < nt / 2; ++k) {
+    const double a = -2.0 * M_PI * k / nt;
+    p->tw_h.push_back(make_double2(std::cos(a), std::sin(a)));
+  }
+  // per-frequency constants (section 3.1-3.2): d_j = 1 - exp(-2 pi i j/nt),
+  // c2 = (1/beta + d_c^2/tau^2)^{-1/2},  c1 = d_r / sqrt(tau^2/beta + d_c^2)
+  const double tau = p->tau, beta = d->beta, nu = d->nu;
+  MGPlan& W = p->mgW;
+  W.q2 = true; W.N = N; W.nb = 4 * p->nf; W.fpc = 4; W.ncoef = p->nf;
+  for (int j = 0; j < p->nf; ++j) {
+    const double th = 2.0 * M_PI * j / nt;
+    const double dr = 1.0 - std::cos(th), dc = std::sin(th);
+    const double c2 = 1.0 / std::sqrt(1.0 / beta + dc * dc / (tau * tau));
+    const double c1 = dr / std::sqrt(tau * tau / beta + dc * dc);
+    p->tj_h.push_back(make_double2(dc, c2));
+    p->ab_h.push_back(make_double2(1.0 + c1, nu * c2));
+    W.coef_h.push_back(mkcoef(1.0 + c1, nu * c2));        // W_j = (1 + c1) M + c2 nu K
+  }
+  MGPlan& K = p->mgK;
+  K.q2 = false; K.N = N; K.nb = 2 * p->nf; K.fpc = 2 * p->nf; K.ncoef = 1;
+  K.coef_h.push_back(mkcoef(0.0, 1.0));                   // unconstrained pressure Laplacian
+  for (MGPlan* m : {&W, &K}) {
+    int nl = 0;
+    for (int n = N; n >= 2; n >>= 1) ++nl;
+    m->nlev = nl;
+    m->conv.assign(nl, nullptr);
+    for (const OpCoef& c : m->coef_h)
+      if (!coarse_inverse(m->q2, c, nullptr, m->inv_h)) { delete p; return fail(PINTOC_EINVAL, "singular coarse operator"); }
+  }
+  carve(p, nullptr);
+  *out = p;
+  return PINTOC_OK;
+}
+
+extern "C" size_t pintoc_workspace_bytes(const pintoc_problem* p) { return p ? p->need : 0; }
+
+extern "C" void pintoc_problem_destroy(pintoc_problem* p) { delete p; }
+
+extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes, void* stream) {
+  if (!p || !dev) return fail(PINTOC_EINVAL, "NULL handle or workspace");
+  if (((uintptr_t)dev) & 255) return fail(PINTOC_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < p->need) return fail(PINTOC_ENOMEM, "workspace too small: need " + std::to_string(p->need) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  p->ws = dev;
+  p->ws_bytes = bytes;
+  carve(p, (char*)dev);
+  // zero every buffer once: padded boundaries of all grids stay zero afterwards
+  launch_fill_zero(s, (char*)dev, (p->need + 15) & ~(size_t)15);
+  HIPCHK(hipMemcpyAsync(p->tw, p->tw_h.data(), sizeof(double2) * p->tw_h.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->tj, p->tj_h.data(), sizeof(double2) * p->tj_h.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->ab, p->ab_h.data(), sizeof(double2) * p->ab_h.size(), hipMemcpyHostToDevice, s));
+  for (MGPlan* m : {&p->mgW, &p->mgK}) {
+    HIPCHK(hipMemcpyAsync(m->coef, m->coef_h.data(), sizeof(OpCoef) * m->coef_h.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(m->inv, m->inv_h.data(), sizeof(double2) * m->inv_h.size(), hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  p->bound = true;
+  return PINTOC_OK;
+}
+
+// ------------------------------------------------------------ multigrid
+template <typename R>
+static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b) {
+  const int n = m.n(l);
+  const double h = 1.0 / n;
+  if (l == m.nlev - 1) {
+    launch_coarse<R>(s, m.q2, x, b, m.inv, m.fpc, m.nb);
+    return;
+  }
+  if (m.q2) launch_q2_gs_sweep<R>(s, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], true);
+  else launch_q1_gs_sweep<R>(s, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], true);
+  cpx<R>* r = (cpx<R>*)m.r[l];
+  launch_residual<R>(s, m.q2, r, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l]);
+  cpx<R>* bc = (cpx<R>*)m.b[l + 1];
+  cpx<R>* xc = (cpx<R>*)m.x[l + 1];
+  launch_restrict<R>(s, m.q2, bc, r, n / 2, m.nb);
+  launch_fill_zero(s, xc, m.nodes(l + 1) * m.nb * sizeof(cpx<R>));
+  vcycle<R>(s, m, l + 1, xc, bc);
+  launch_prolong_add<R>(s, m.q2, x, xc, n / 2, m.nb);
+  if (m.q2) launch_q2_gs_sweep<R>(s, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], false);
+  else launch_q1_gs_sweep<R>(s, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], false);
+}
+
+// x = MG^cycles(b) from x = 0
+template <typename R>
+static void mg_solve(hipStream_t s, MGPlan& m, cpx<R>* x, const cpx<R>* b, int cycles) {
+  launch_fill_zero(s, x, m.nodes(0) * m.nb * sizeof(cpx<R>));
+  for (int c = 0; c < cycles; ++c) vcycle<R>(s, m, 0, x, b);
+}
+
+// Chebyshev semi-iteration (Jacobi-preconditioned, spectrum bounds [lo, hi] of
+// diag(M)^{-1} M), ``steps`` steps from zero.  Returns the buffer holding x_steps.
+template <typename R>
+static cpx<R>* chebyshev(hipStream_t s, bool q2, int n, int nb, cpx<R>* A, cpx<R>* B, const cpx<R>* b, int steps,
+                         double lo, double hi) {
+  const double g = 2.0 / (lo + hi), sg = (hi - lo) / (hi + lo);
+  const double h = 1.0 / n;
+  const size_t bytes = (q2 ? (size_t)(2 * n + 1) * (2 * n + 1) : (size_t)(n + 1) * (n + 1)) * nb * sizeof(cpx<R>);
+  launch_cheb<R>(s, q2, A, A, A, b, n, h, g, 1.0, 1, nb);             // x_1 = g D^{-1} b
+  launch_fill_zero(s, B, bytes);                                       // x_0 = 0
+  cpx<R>*cur = A, *prev = B;
+  double w = 1.0;
+  for (int k = 1; k < steps; ++k) {
+    w = k == 1 ? 1.0 / (1.0 - 0.5 * sg * sg) : 1.0 / (1.0 - 0.25 * sg * sg * w);
+    launch_cheb<R>(s, q2, prev, cur, prev, b, n, h, g, w, 0, nb);     // x_{k+1} overwrites x_{k-1}
+    std::swap(cur, prev);
+  }
+  return cur;
+}
+
+// ------------------------------------------------------------ preconditioner
+// Algorithm 1 with P~_j (Stokes): FFT + T_l^{-1}, block-diagonal P~_j^{-1},
+// T_r^{-1} + inverse FFT.
+template <typename R>
+static void precond_linear_stokes(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
+  const int nf = p->nf, cyc = p->o.n_vcycles, N = p->d.N;
+  cpx<R>*Vb = (cpx<R>*)p->Vb, *Vx = (cpx<R>*)p->Vx, *Pb = (cpx<R>*)p->Pb;
+  launch_time_fft_fwd<R>(s, r, Vb, Pb, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, 1);
+  // W_j^{-1} on (s1, s2): 4 V-cycles, 4 complex grids per frequency
+  mg_solve<R>(s, p->mgW, Vx, Vb, cyc);
+  // S^_j^{-1} on (s3, s4):  R L [(1+c1) K_N^+ + nu c2 M_N^{-1}] L^T R^T
+  launch_unpin_in<R>(s, Pb, p->np2, 2 * nf);
+  mg_solve<R>(s, p->mgK, (cpx<R>*)p->PxK, Pb, cyc);
+  cpx<R>* ym = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, Pb, p->o.n_cheb, 0.25, 2.25);
+  launch_schur_combine_pin<R>(s, (cpx<R>*)p->Px, (cpx<R>*)p->PxK, ym, p->ab, 2, p->np2, 2 * nf);
+  launch_time_fft_inv<R>(s, Vx, (cpx<R>*)p->Px, z, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, 1);
+}
+
+static int precond(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
+  if (p->o.precision == PINTOC_PREC_FP64) precond_linear_stokes<double>(p, r, z, s);
+  else precond_linear_stokes<float>(p, r, z, s);
+  p->precond_apps++;
+  HIPCHK(hipGetLastError());
+  return PINTOC_OK;
+}
+
+// ------------------------------------------------------------ public entries
+static int check_ready(pintoc_problem* p) {
+  if (!p) return fail(PINTOC_EINVAL, "NULL handle");
+  if (!p->bound) return fail(PINTOC_ESTATE, "no workspace bound");
+  return PINTOC_OK;
+}
+
+extern "C" int pintoc_assemble_rhs(pintoc_problem* p, const double* vd, double* b, void* stream) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!vd || !b) return fail(PINTOC_EINVAL, "NULL vector");
+  launch_assemble_rhs((hipStream_t)stream, vd, b, p->d.N, p->d.nt, p->tau);
+  HIPCHK(hipGetLastError());
+  return PINTOC_OK;
+}
+
+static void kkt(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
+  launch_kkt_apply(s, x, y, p->d.N, p->d.nt, p->tau, p->d.beta, p->d.nu, nullptr);
+}
+
+extern "C" int pintoc_kkt_apply(pintoc_problem* p, const double* x, double* y, void* stream) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!x || !y || x == y) return fail(PINTOC_EINVAL, "NULL or aliased vectors");
+  kkt(p, x, y, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return PINTOC_OK;
+}
+
+extern "C" int pintoc_precond_apply(pintoc_problem* p, const double* r, double* z, void* stream) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!r || !z || r == z) return fail(PINTOC_EINVAL, "NULL or aliased vectors");
+  return precond(p, r, z, (hipStream_t)stream);
+}
+
+// dots of the first k vectors of V (stride n) with w, returned on the host
+static int dots(pintoc_problem* p, hipStream_t s, const double* V, int k, const double* w, double* dev_out,
+                double* host_out) {
+  launch_mdot(s, V, (size_t)p->n_all, k, w, (size_t)p->n_all, p->part, dev_out);
+  HIPCHK(hipMemcpyAsync(host_out, dev_out, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return PINTOC_OK;
+}
+
+extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pintoc_solve_stats* st, void* stream) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!b || !x || b == x) return fail(PINTOC_EINVAL, "NULL or aliased vectors");
+  hipStream_t s = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const size_t n = (size_t)p->n_all;
+  const int m = p->o.restart;
+  p->precond_apps = 0;
+  double hb[64], hb2[64];
+  if ((rc = dots(p, s, b, 1, b, p->dd, hb))) return rc;
+  const double bnorm = std::sqrt(hb[0]);
+  int its = 0;
+  double res = 0;
+  bool conv = false;
+  if (bnorm == 0.0) {
+    launch_fill_zero(s, x, n * sizeof(double));
+    conv = true;
+  } else {
+    // r = b - A x
+    kkt(p, x, p->rvec, s);
+    launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
+    if ((rc = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb))) return rc;
+    res = std::sqrt(hb[0]);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    while (true) {
+      if (!(res == res)) break;                        // NaN: give up
+      if (res <= p->o.tol * bnorm) { conv = true; break; }
+      if (its >= p->o.max_outer) break;
+      // V_0 = r / ||r||
+      launch_axpby(s, p->Vk, p->rvec, 1.0 / res, 0.0, n);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = res;
+      int k = 0;
+      bool breakdown = false;
+      for (; k < m && its < p->o.max_outer; ++k) {
+        double* vk = p->Vk + (size_t)k * n;
+        double* zk = p->Zk + (size_t)k * n;
+        double* w = p->Vk + (size_t)(k + 1) * n;
+        if ((rc = precond(p, vk, zk, s))) return rc;
+        kkt(p, zk, w, s);
+        // classical Gram-Schmidt, twice
+        if ((rc = dots(p, s, p->Vk, k + 1, w, p->dd, hb))) return rc;
+        launch_mgs_update(s, w, p->Vk, n, k + 1, p->dd, n);
+        if ((rc = dots(p, s, p->Vk, k + 1, w, p->dd2, hb2))) return rc;
+        launch_mgs_update(s, w, p->Vk, n, k + 1, p->dd2, n);
+        double nrm2;
+        if ((rc = dots(p, s, w, 1, w, p->dd, &nrm2))) return rc;
+        const double hk1 = std::sqrt(nrm2);
+        for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hb[i] + hb2[i];
+        H[(size_t)(k + 1) * m + k] = hk1;
+        if (hk1 > 0) launch_axpby(s, w, w, 1.0 / hk1, 0.0, n);
+        else breakdown = true;
+        for (int i = 0; i < k; ++i) {
+          const double a = H[(size_t)i * m + k], c = H[(size_t)(i + 1) * m + k];
+          H[(size_t)i * m + k] = cs[i] * a + sn[i] * c;
+          H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * c;
+        }
+        const double a = H[(size_t)k * m + k], c = H[(size_t)(k + 1) * m + k];
+        const double t = std::hypot(a, c);
+        cs[k] = t > 0 ? a / t : 1.0;
+        sn[k] = t > 0 ? c / t : 0.0;
+        H[(size_t)k * m + k] = t;
+        H[(size_t)(k + 1) * m + k] = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        ++its;
+        if (std::fabs(g[k + 1]) <= p->o.tol * bnorm || breakdown) { ++k; break; }
+      }
+      // y = H^{-1} g (upper triangular), x += Z y
+      for (int i = k - 1; i >= 0; --i) {
+        double v = g[i];
+        for (int j = i + 1; j < k; ++j) v -= H[(size_t)i * m + j] * y[j];
+        y[i] = v / H[(size_t)i * m + i];
+      }
+      HIPCHK(hipMemcpyAsync(p->dd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+      launch_lincomb_add(s, x, p->Zk, n, k, p->dd, n);
+      // true residual
+      kkt(p, x, p->rvec, s);
+      launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
+      if ((rc = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb))) return rc;
+      res = std::sqrt(hb[0]);
+      if (breakdown && !(res <= p->o.tol * bnorm)) break;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->outer_iterations = its;
+    st->converged = conv ? 1 : 0;
+    st->rel_residual = bnorm > 0 ? res / bnorm : 0.0;
+    st->precond_applications = p->precond_apps;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return conv ? PINTOC_OK : PINTOC_NOT_CONVERGED;
+}
