@@ -165,6 +165,14 @@ const char* pintoc_last_error(void);
 /* Vector length of the canonical layout, for the caller's allocations. */
 int64_t pintoc_vector_length(const pintoc_problem* p);
 
+/* Inner GMRES iteration counts of the most recent preconditioner application
+ * in GMRES mode, one per kept frequency j = 0..nt/2 (Algorithm 2 reports these
+ * per block).  counts: host array of at least n entries; writes
+ * min(n, nt/2 + 1) entries and returns that number, or a negative error code
+ * (PINTOC_EINVAL for a NULL handle/array, PINTOC_ESTATE before any GMRES-mode
+ * application).  Entries are zero in LINEAR mode. */
+int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* counts, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,7 @@ SIGNATURES = {
     "pintoc_problem_destroy": (None, [C.c_void_p]),
     "pintoc_last_error": (C.c_char_p, []),
     "pintoc_vector_length": (C.c_int64, [C.c_void_p]),
+    "pintoc_last_inner_iterations": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
 }
 
 
@@ -171,6 +172,13 @@ class Problem:
         rc = _check(library().pintoc_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), C.byref(st),
                                            self._stream()), "pintoc_solve")
         return x, st.as_dict(), rc == OK
+
+    def last_inner_iterations(self):
+        """Inner GMRES counts per kept frequency of the last application."""
+        nf = self.nt // 2 + 1
+        arr = (C.c_int32 * nf)()
+        k = _check(library().pintoc_last_inner_iterations(self._h, arr, nf), "pintoc_last_inner_iterations")
+        return [int(arr[i]) for i in range(k)]
 
     def close(self):
         if getattr(self, "_h", None):

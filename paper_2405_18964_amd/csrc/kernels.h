@@ -52,3 +52,24 @@ void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, in
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
 
 }  // namespace pintoc
+
+namespace pintoc {
+// per-frequency inner solves (inner_kernels.hip)
+template <typename R>
+void launch_zmat_stokes(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
+                        const double2* cj);
+template <typename R>
+void launch_fdot(hipStream_t s, const cpx<R>* bV, const cpx<R>* bP, size_t ldV, size_t ldP, int k, const cpx<R>* wV,
+                 const cpx<R>* wP, int segV, int segP, int nf, double2* part, double2* out);
+size_t fdot_part_entries(int segV, int segP, int nf);
+template <typename R>
+void launch_fupdate(hipStream_t s, cpx<R>* wV, cpx<R>* wP, const cpx<R>* bV, const cpx<R>* bP, size_t ldV,
+                    size_t ldP, int k, const double2* c, int segV, int segP, int nf, double sign);
+template <typename R>
+void launch_fscale(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, const double2* a,
+                   int segV, int segP, int nf);
+template <typename R>
+void launch_unpin_copy(hipStream_t s, cpx<R>* dst, const cpx<R>* src, int nn, int nb);
+template <typename Rd, typename Rs>
+void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n);
+}  // namespace pintoc

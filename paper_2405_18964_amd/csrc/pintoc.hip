@@ -62,8 +62,19 @@ struct pintoc_problem {
   void* ws = nullptr;
   size_t ws_bytes = 0, need = 0;
   double2 *tw = nullptr, *tj = nullptr, *ab = nullptr;
-  void *Vb = nullptr, *Vx = nullptr, *Pb = nullptr, *PxK = nullptr, *PxM = nullptr, *PxM2 = nullptr, *Px = nullptr;
+  // frequency vectors (precision of the inner solves): S = transformed residual,
+  // X = block solution, Zt/U = GMRES temporaries, B = inner Krylov basis
+  void *Vb = nullptr, *Vx = nullptr, *Pb = nullptr, *Px = nullptr;
+  void *ZtV = nullptr, *ZtP = nullptr, *UV = nullptr, *UP = nullptr, *BV = nullptr, *BP = nullptr;
+  void *Ptmp = nullptr, *PxK = nullptr, *PxM = nullptr, *PxM2 = nullptr;
+  double2 *cj = nullptr, *hdev = nullptr, *h2dev = nullptr, *ydev = nullptr, *fpart = nullptr;
+  std::vector<double2> cj_h;
+  int segV = 0, segP = 0;
   MGPlan mgW, mgK;
+  // inner statistics
+  long inner_its_sum = 0, inner_blocks = 0;
+  int inner_its_max = 0;
+  std::vector<int> last_its;
   // outer FGMRES
   double *Vk = nullptr, *Zk = nullptr, *rvec = nullptr, *xtmp = nullptr;
   double *dd = nullptr, *dd2 = nullptr, *part = nullptr;
@@ -196,13 +207,28 @@ static void carve(pintoc_problem* p, char* base) {
   p->ab = cv.take<double2>(sizeof(double2) * nf);
   const size_t vbytes = (size_t)4 * nf * p->nq2 * p->csize;
   const size_t pbytes = (size_t)2 * nf * p->np2 * p->csize;
+  p->cj = cv.take<double2>(sizeof(double2) * nf);
   p->Vb = cv.take<char>(vbytes);
   p->Vx = cv.take<char>(vbytes);
   p->Pb = cv.take<char>(pbytes);
+  p->Px = cv.take<char>(pbytes);
+  p->Ptmp = cv.take<char>(pbytes);
   p->PxK = cv.take<char>(pbytes);
   p->PxM = cv.take<char>(pbytes);
   p->PxM2 = cv.take<char>(pbytes);
-  p->Px = cv.take<char>(pbytes);
+  if (p->o.inner == PINTOC_INNER_GMRES) {
+    const int mi = p->o.inner_restart;
+    p->ZtV = cv.take<char>(vbytes);
+    p->ZtP = cv.take<char>(pbytes);
+    p->UV = cv.take<char>(vbytes);
+    p->UP = cv.take<char>(pbytes);
+    p->BV = cv.take<char>(vbytes * (mi + 1));
+    p->BP = cv.take<char>(pbytes * (mi + 1));
+    p->hdev = cv.take<double2>(sizeof(double2) * (mi + 1) * nf);
+    p->h2dev = cv.take<double2>(sizeof(double2) * (mi + 1) * nf);
+    p->ydev = cv.take<double2>(sizeof(double2) * (mi + 1) * nf);
+    p->fpart = cv.take<double2>(sizeof(double2) * fdot_part_entries(p->segV, p->segP, nf));
+  }
   plan_mg_buffers(p->mgW, cv, p->csize);
   plan_mg_buffers(p->mgK, cv, p->csize);
   const int m = p->o.restart;
@@ -239,6 +265,19 @@ extern "C" const char* pintoc_last_error(void) { return g_err.c_str(); }
 
 extern "C" int64_t pintoc_vector_length(const pintoc_problem* p) { return p ? p->n_all : 0; }
 
+extern "C" int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* counts, int32_t n) {
+  if (!p || !counts) return fail(PINTOC_EINVAL, "NULL handle or array");
+  if (p->o.inner == PINTOC_INNER_LINEAR) {
+    const int k = std::min(n, p->nf);
+    for (int j = 0; j < k; ++j) counts[j] = 0;
+    return k;
+  }
+  if (p->last_its.empty()) return fail(PINTOC_ESTATE, "no GMRES-mode application yet");
+  const int k = std::min(n, (int32_t)p->last_its.size());
+  for (int j = 0; j < k; ++j) counts[j] = p->last_its[j];
+  return k;
+}
+
 extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_options* o, pintoc_problem** out) {
   if (!d || !out) return fail(PINTOC_EINVAL, "NULL descriptor or output pointer");
   pintoc_options opt;
@@ -249,7 +288,10 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   if (!(d->T > 0) || !(d->nu > 0) || !(d->beta > 0)) return fail(PINTOC_EINVAL, "T, nu and beta must be > 0");
   if (d->flow != PINTOC_STOKES && d->flow != PINTOC_OSEEN) return fail(PINTOC_EINVAL, "unknown flow");
   if (d->flow == PINTOC_OSEEN) return fail(PINTOC_EINVAL, "Oseen flow is not available in this build");
-  if (opt.inner != PINTOC_INNER_LINEAR) return fail(PINTOC_EINVAL, "only the linear inner mode is available");
+  if (opt.inner != PINTOC_INNER_LINEAR && opt.inner != PINTOC_INNER_GMRES) return fail(PINTOC_EINVAL, "unknown inner mode");
+  if (opt.inner == PINTOC_INNER_GMRES &&
+      (opt.inner_restart < 1 || opt.inner_restart > 100 || opt.inner_maxit < 1 || !(opt.inner_tol > 0)))
+    return fail(PINTOC_EINVAL, "invalid inner GMRES options");
   if (opt.precision != PINTOC_PREC_FP64 && opt.precision != PINTOC_PREC_FP32_INNER)
     return fail(PINTOC_EINVAL, "unknown precision");
   if (opt.restart < 1 || opt.restart > 60 || opt.max_outer < 1 || !(opt.tol > 0) || opt.n_vcycles < 1 ||
@@ -267,6 +309,8 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   p->L = 2 * p->nq2 + p->np2;
   p->n_all = (int64_t)2 * nt * p->L;
   p->csize = opt.precision == PINTOC_PREC_FP64 ? 16 : 8;
+  p->segV = 4 * p->nq2;
+  p->segP = 2 * p->np2;
   // twiddles exp(-2 pi i k / nt)
   for (int k = 0; k < nt / 2; ++k) {
     const double a = -2.0 * M_PI * k / nt;
@@ -284,6 +328,7 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     const double c1 = dr / std::sqrt(tau * tau / beta + dc * dc);
     p->tj_h.push_back(make_double2(dc, c2));
     p->ab_h.push_back(make_double2(1.0 + c1, nu * c2));
+    p->cj_h.push_back(make_double2(c1, c2 * nu));          // X = c1 M + c2 L, L = nu K
     W.coef_h.push_back(mkcoef(1.0 + c1, nu * c2));        // W_j = (1 + c1) M + c2 nu K
   }
   MGPlan& K = p->mgK;
@@ -319,6 +364,7 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
   HIPCHK(hipMemcpyAsync(p->tw, p->tw_h.data(), sizeof(double2) * p->tw_h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->tj, p->tj_h.data(), sizeof(double2) * p->tj_h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->ab, p->ab_h.data(), sizeof(double2) * p->ab_h.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->cj, p->cj_h.data(), sizeof(double2) * p->cj_h.size(), hipMemcpyHostToDevice, s));
   for (MGPlan* m : {&p->mgW, &p->mgK}) {
     HIPCHK(hipMemcpyAsync(m->coef, m->coef_h.data(), sizeof(OpCoef) * m->coef_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(m->inv, m->inv_h.data(), sizeof(double2) * m->inv_h.size(), hipMemcpyHostToDevice, s));
@@ -380,26 +426,201 @@ static cpx<R>* chebyshev(hipStream_t s, bool q2, int n, int nb, cpx<R>* A, cpx<R
 }
 
 // ------------------------------------------------------------ preconditioner
-// Algorithm 1 with P~_j (Stokes): FFT + T_l^{-1}, block-diagonal P~_j^{-1},
-// T_r^{-1} + inverse FFT.
+// P~_j^{-1} (section 3.2) on a frequency vector: W_j^{-1} by V-cycles on the
+// velocity fields, S^_j^{-1} = R L [(1+c1) K_N^+ + nu c2 M_N^{-1}] L^T R^T on
+// the pressure fields.  in and out must not alias.
 template <typename R>
-static void precond_linear_stokes(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
+static void ptilde(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP, cpx<R>* outV,
+                   cpx<R>* outP) {
   const int nf = p->nf, cyc = p->o.n_vcycles, N = p->d.N;
-  cpx<R>*Vb = (cpx<R>*)p->Vb, *Vx = (cpx<R>*)p->Vx, *Pb = (cpx<R>*)p->Pb;
+  mg_solve<R>(s, p->mgW, outV, inV, cyc);
+  cpx<R>* z = (cpx<R>*)p->Ptmp;
+  launch_unpin_copy<R>(s, z, inP, p->np2, 2 * nf);
+  mg_solve<R>(s, p->mgK, (cpx<R>*)p->PxK, z, cyc);
+  cpx<R>* ym = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25);
+  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, ym, p->ab, 2, p->np2, 2 * nf);
+}
+
+// complex Givens rotation (c real) with [c, s; -conj(s), c] [a; b] = [r; 0]
+static void givens(cd a, cd b, double& c, cd& sn) {
+  if (b == 0.0) { c = 1.0; sn = 0.0; return; }
+  if (a == 0.0) { c = 0.0; sn = std::conj(b) / std::abs(b); return; }
+  const double t = std::hypot(std::abs(a), std::abs(b));
+  c = std::abs(a) / t;
+  sn = (a / std::abs(a)) * std::conj(b) / t;
+}
+
+// Batched right-preconditioned GMRES, one system Z_j x_j = s_j per kept
+// frequency (Algorithm 2): x_0 = 0, restart m, stop for frequency j when the
+// Arnoldi residual estimate satisfies |g_{k+1}| <= eps ||s_j||.  All
+// frequencies advance in lockstep; a converged frequency's Hessenberg matrix
+// is frozen and its later basis vectors are ignored.  Orthogonalisation:
+// classical Gram-Schmidt applied twice.
+template <typename R>
+static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
+  const int nf = p->nf, m = p->o.inner_restart, segV = p->segV, segP = p->segP, N = p->d.N;
+  const size_t ldV = (size_t)segV * nf, ldP = (size_t)segP * nf;
+  cpx<R>*SV = (cpx<R>*)p->Vb, *SP = (cpx<R>*)p->Pb, *XV = (cpx<R>*)p->Vx, *XP = (cpx<R>*)p->Px;
+  cpx<R>*BV = (cpx<R>*)p->BV, *BP = (cpx<R>*)p->BP, *ZV = (cpx<R>*)p->ZtV, *ZP = (cpx<R>*)p->ZtP;
+  cpx<R>*UV = (cpx<R>*)p->UV, *UP = (cpx<R>*)p->UP;
+  auto BVk = [&](int k) { return BV + (size_t)k * ldV; };
+  auto BPk = [&](int k) { return BP + (size_t)k * ldP; };
+  std::vector<double2> hb((size_t)(m + 1) * nf), hb2((size_t)(m + 1) * nf), scl(nf), yv((size_t)(m + 1) * nf);
+  auto fetch = [&](double2* dev, std::vector<double2>& host, int k) -> int {
+    HIPCHK(hipMemcpyAsync(host.data(), dev, sizeof(double2) * k * nf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PINTOC_OK;
+  };
+  auto upload = [&](double2* dev, const std::vector<double2>& host, int k) -> int {
+    HIPCHK(hipMemcpyAsync(dev, host.data(), sizeof(double2) * k * nf, hipMemcpyHostToDevice, s));
+    return PINTOC_OK;
+  };
+  int rc;
+  // ||s_j||
+  launch_fdot<R>(s, SV, SP, 0, 0, 1, SV, SP, segV, segP, nf, p->fpart, p->hdev);
+  if ((rc = fetch(p->hdev, hb, 1))) return rc;
+  std::vector<double> bnorm(nf), rnorm(nf);
+  std::vector<int> done(nf, 0), its(nf, 0);
+  for (int j = 0; j < nf; ++j) {
+    bnorm[j] = std::sqrt(std::max(hb[j].x, 0.0));
+    rnorm[j] = bnorm[j];
+    if (!(bnorm[j] > 0)) done[j] = 1;
+  }
+  launch_fill_zero(s, XV, (size_t)segV * nf * sizeof(cpx<R>));
+  launch_fill_zero(s, XP, (size_t)segP * nf * sizeof(cpx<R>));
+  std::vector<cd> H((size_t)nf * (m + 1) * m), sn((size_t)nf * m), g((size_t)nf * (m + 1));
+  std::vector<double> cs((size_t)nf * m);
+  const cpx<R>*RV = SV, *RP = SP;          // residual of the current cycle
+  int total = 0;
+  while (true) {
+    bool any = false;
+    for (int j = 0; j < nf; ++j) any |= !done[j];
+    if (!any || total >= p->o.inner_maxit) break;
+    // v_0 = r / ||r|| (frequencies already done get a zero basis)
+    for (int j = 0; j < nf; ++j) scl[j] = make_double2(done[j] ? 0.0 : 1.0 / rnorm[j], 0.0);
+    if ((rc = upload(p->ydev, scl, 1))) return rc;
+    launch_fscale<R>(s, BVk(0), BPk(0), RV, RP, p->ydev, segV, segP, nf);
+    std::vector<int> kj(nf, 0), active(nf);
+    for (int j = 0; j < nf; ++j) {
+      active[j] = !done[j];
+      std::fill(g.begin() + (size_t)j * (m + 1), g.begin() + (size_t)(j + 1) * (m + 1), cd(0.0));
+      g[(size_t)j * (m + 1)] = rnorm[j];
+    }
+    int k = 0;
+    for (; k < m && total < p->o.inner_maxit; ++k) {
+      ptilde<R>(p, s, BVk(k), BPk(k), ZV, ZP);
+      launch_zmat_stokes<R>(s, BVk(k + 1), BPk(k + 1), ZV, ZP, N, nf, p->cj);
+      launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->hdev);
+      launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->hdev, segV, segP, nf, 1.0);
+      launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->h2dev);
+      launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->h2dev, segV, segP, nf, 1.0);
+      launch_fdot<R>(s, BVk(k + 1), BPk(k + 1), 0, 0, 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart,
+                     p->ydev);
+      if ((rc = fetch(p->hdev, hb, k + 1)) || (rc = fetch(p->h2dev, hb2, k + 1))) return rc;
+      std::vector<double2> nr(nf);
+      if ((rc = fetch(p->ydev, nr, 1))) return rc;
+      for (int j = 0; j < nf; ++j) {
+        const double hk1 = std::sqrt(std::max(nr[j].x, 0.0));
+        scl[j] = make_double2(active[j] && hk1 > 0 ? 1.0 / hk1 : 0.0, 0.0);
+        if (!active[j]) continue;
+        cd* Hj = H.data() + (size_t)j * (m + 1) * m;
+        for (int i = 0; i <= k; ++i)
+          Hj[(size_t)i * m + k] = cd(hb[(size_t)i * nf + j].x + hb2[(size_t)i * nf + j].x,
+                                     hb[(size_t)i * nf + j].y + hb2[(size_t)i * nf + j].y);
+        Hj[(size_t)(k + 1) * m + k] = hk1;
+        for (int i = 0; i < k; ++i) {
+          const cd a = Hj[(size_t)i * m + k], c = Hj[(size_t)(i + 1) * m + k];
+          const double ci = cs[(size_t)j * m + i];
+          const cd si = sn[(size_t)j * m + i];
+          Hj[(size_t)i * m + k] = ci * a + si * c;
+          Hj[(size_t)(i + 1) * m + k] = -std::conj(si) * a + ci * c;
+        }
+        double ck; cd sk;
+        givens(Hj[(size_t)k * m + k], Hj[(size_t)(k + 1) * m + k], ck, sk);
+        cs[(size_t)j * m + k] = ck;
+        sn[(size_t)j * m + k] = sk;
+        Hj[(size_t)k * m + k] = ck * Hj[(size_t)k * m + k] + sk * Hj[(size_t)(k + 1) * m + k];
+        Hj[(size_t)(k + 1) * m + k] = 0.0;
+        cd* gj = g.data() + (size_t)j * (m + 1);
+        gj[k + 1] = -std::conj(sk) * gj[k];
+        gj[k] = ck * gj[k];
+        kj[j] = k + 1;
+        its[j]++;
+        if (std::abs(gj[k + 1]) <= p->o.inner_tol * bnorm[j] || hk1 == 0.0) { active[j] = 0; done[j] = 1; }
+      }
+      if ((rc = upload(p->ydev, scl, 1))) return rc;
+      launch_fscale<R>(s, BVk(k + 1), BPk(k + 1), BVk(k + 1), BPk(k + 1), p->ydev, segV, segP, nf);
+      ++total;
+      bool any_active = false;
+      for (int j = 0; j < nf; ++j) any_active |= active[j] != 0;
+      if (!any_active) { ++k; break; }
+    }
+    // y_j = H_j^{-1} g_j (size kj), U = sum_i y_ij v_i, X += P~^{-1} U
+    std::fill(yv.begin(), yv.end(), make_double2(0, 0));
+    for (int j = 0; j < nf; ++j) {
+      const int kk = kj[j];
+      const cd* Hj = H.data() + (size_t)j * (m + 1) * m;
+      const cd* gj = g.data() + (size_t)j * (m + 1);
+      std::vector<cd> y(kk);
+      for (int i = kk - 1; i >= 0; --i) {
+        cd v = gj[i];
+        for (int q = i + 1; q < kk; ++q) v -= Hj[(size_t)i * m + q] * y[q];
+        y[i] = v / Hj[(size_t)i * m + i];
+      }
+      for (int i = 0; i < kk; ++i) yv[(size_t)i * nf + j] = make_double2(y[i].real(), y[i].imag());
+    }
+    if ((rc = upload(p->ydev, yv, k))) return rc;
+    launch_fill_zero(s, UV, (size_t)segV * nf * sizeof(cpx<R>));
+    launch_fill_zero(s, UP, (size_t)segP * nf * sizeof(cpx<R>));
+    launch_fupdate<R>(s, UV, UP, BV, BP, ldV, ldP, k, p->ydev, segV, segP, nf, -1.0);
+    ptilde<R>(p, s, UV, UP, ZV, ZP);
+    for (int j = 0; j < nf; ++j) scl[j] = make_double2(1.0, 0.0);
+    if ((rc = upload(p->hdev, scl, 1))) return rc;
+    launch_fupdate<R>(s, XV, XP, ZV, ZP, 0, 0, 1, p->hdev, segV, segP, nf, -1.0);      // X += P~^{-1} U
+    bool any_left = false;
+    for (int j = 0; j < nf; ++j) any_left |= !done[j];
+    if (!any_left || total >= p->o.inner_maxit) break;
+    // restart: r = s - Z x for the frequencies still running
+    launch_zmat_stokes<R>(s, UV, UP, XV, XP, N, nf, p->cj);
+    for (int j = 0; j < nf; ++j) scl[j] = make_double2(-1.0, 0.0);
+    if ((rc = upload(p->hdev, scl, 1))) return rc;
+    launch_fscale<R>(s, UV, UP, UV, UP, p->hdev, segV, segP, nf);
+    for (int j = 0; j < nf; ++j) scl[j] = make_double2(1.0, 0.0);
+    if ((rc = upload(p->h2dev, scl, 1))) return rc;
+    launch_fupdate<R>(s, UV, UP, SV, SP, 0, 0, 1, p->h2dev, segV, segP, nf, -1.0);     // U = s - Z x
+    launch_fdot<R>(s, UV, UP, 0, 0, 1, UV, UP, segV, segP, nf, p->fpart, p->hdev);
+    if ((rc = fetch(p->hdev, hb, 1))) return rc;
+    for (int j = 0; j < nf; ++j) rnorm[j] = std::sqrt(std::max(hb[j].x, 0.0));
+    RV = UV; RP = UP;
+  }
+  p->last_its = its;
+  for (int j = 0; j < nf; ++j) {
+    p->inner_its_sum += its[j];
+    p->inner_blocks += 1;
+    p->inner_its_max = std::max(p->inner_its_max, its[j]);
+  }
+  return PINTOC_OK;
+}
+
+// Algorithm 1 (linear) or Algorithm 2 (GMRES per frequency), Stokes:
+// FFT + T_l^{-1}, block solves, T_r^{-1} + inverse FFT.
+template <typename R>
+static int precond_stokes(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
+  cpx<R>*Vb = (cpx<R>*)p->Vb, *Vx = (cpx<R>*)p->Vx, *Pb = (cpx<R>*)p->Pb, *Px = (cpx<R>*)p->Px;
   launch_time_fft_fwd<R>(s, r, Vb, Pb, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, 1);
-  // W_j^{-1} on (s1, s2): 4 V-cycles, 4 complex grids per frequency
-  mg_solve<R>(s, p->mgW, Vx, Vb, cyc);
-  // S^_j^{-1} on (s3, s4):  R L [(1+c1) K_N^+ + nu c2 M_N^{-1}] L^T R^T
-  launch_unpin_in<R>(s, Pb, p->np2, 2 * nf);
-  mg_solve<R>(s, p->mgK, (cpx<R>*)p->PxK, Pb, cyc);
-  cpx<R>* ym = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, Pb, p->o.n_cheb, 0.25, 2.25);
-  launch_schur_combine_pin<R>(s, (cpx<R>*)p->Px, (cpx<R>*)p->PxK, ym, p->ab, 2, p->np2, 2 * nf);
-  launch_time_fft_inv<R>(s, Vx, (cpx<R>*)p->Px, z, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, 1);
+  if (p->o.inner == PINTOC_INNER_LINEAR) {
+    ptilde<R>(p, s, Vb, Pb, Vx, Px);
+  } else {
+    int rc = gmres_blocks<R>(p, s);
+    if (rc) return rc;
+  }
+  launch_time_fft_inv<R>(s, Vx, Px, z, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, 1);
+  return PINTOC_OK;
 }
 
 static int precond(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
-  if (p->o.precision == PINTOC_PREC_FP64) precond_linear_stokes<double>(p, r, z, s);
-  else precond_linear_stokes<float>(p, r, z, s);
+  int rc = p->o.precision == PINTOC_PREC_FP64 ? precond_stokes<double>(p, r, z, s) : precond_stokes<float>(p, r, z, s);
+  if (rc) return rc;
   p->precond_apps++;
   HIPCHK(hipGetLastError());
   return PINTOC_OK;
@@ -459,6 +680,9 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
   const size_t n = (size_t)p->n_all;
   const int m = p->o.restart;
   p->precond_apps = 0;
+  p->inner_its_sum = 0;
+  p->inner_blocks = 0;
+  p->inner_its_max = 0;
   double hb[64], hb2[64];
   if ((rc = dots(p, s, b, 1, b, p->dd, hb))) return rc;
   const double bnorm = std::sqrt(hb[0]);
@@ -543,6 +767,8 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
     st->converged = conv ? 1 : 0;
     st->rel_residual = bnorm > 0 ? res / bnorm : 0.0;
     st->precond_applications = p->precond_apps;
+    st->inner_iterations_mean = p->inner_blocks ? (double)p->inner_its_sum / p->inner_blocks : 0.0;
+    st->inner_iterations_max = p->inner_its_max;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return conv ? PINTOC_OK : PINTOC_NOT_CONVERGED;

@@ -134,3 +134,39 @@ def test_errors(lib):
     b = gp.empty()
     xs, st, ok = gp.solve(b)                        # zero rhs -> zero solution
     assert ok and float(xs.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("N,nt,beta,src", [(4, 8, 1e-2, "rhs"), (8, 16, 1e-2, "random"), (16, 32, 1e-4, "rhs")])
+def test_precond_gmres_parity(lib, N, nt, beta, src):
+    """Algorithm 2: per-frequency GMRES on Z_j with P~_j.  The inner counts must
+    equal the oracle's; with equal counts the outputs agree to 1e-10."""
+    from oracle.kkt import Problem as OP
+    from oracle.precond import StokesPreconditioner
+    print(f"precond gmres N={N} nt={nt} src={src}", flush=True)
+    w = W.small(W.STOKES, N, nt, beta=beta)
+    op = OP.from_workload(w)
+    gp = lib.Problem.from_workload(w, inner=lib.INNER_GMRES)
+    r = W.random_canonical(N, nt, seed=9) if src == "random" else op.to_canonical(op.rhs(W.desired_state(w)))
+    z = _host(gp.precond_apply(_dev(r)))
+    counts = gp.last_inner_iterations()
+    pc = StokesPreconditioner(op)
+    ref = op.to_canonical(pc.apply(op.to_compact(r), nonlinear=True))
+    oracle_counts = [pc.inner_its[j] for j in range(nt // 2 + 1)]
+    assert counts == oracle_counts
+    assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert np.all(z[~W.canonical_mask(N, nt)] == 0)
+
+
+def test_solve_config1_gmres(lib):
+    from oracle.kkt import Problem as OP
+    w = W.config(1)
+    print(f"solve gmres {w.name}", flush=True)
+    gp = lib.Problem.from_workload(w, inner=lib.INNER_GMRES)
+    b = gp.assemble_rhs(_dev(W.desired_state(w)))
+    x, st, ok = gp.solve(b)
+    assert ok and st["rel_residual"] <= 1e-8 and st["outer_iterations"] <= 12
+    assert 1 <= st["inner_iterations_mean"] <= 40
+    op = OP.from_workload(w)
+    xh, bh = _host(x), _host(b)
+    xs = op.to_canonical(op.solve_direct(op.to_compact(bh)))
+    assert np.linalg.norm(xh - xs) <= 1e-5 * np.linalg.norm(xs)
