@@ -6,9 +6,10 @@ Section 3.4 applies "4 V-cycles" of a geometric multigrid method with SOR
 smoothing to W_j and K_p (Stokes) and to Q_j, Q_j^H and K_p (Oseen).  Readings
 used (the paper leaves these unstated):
 
-* V(1,1) cycle: one forward multicolour Gauss-Seidel sweep before the coarse
-  correction, one backward sweep after it (so the cycle is symmetric for
-  symmetric operators); coarsest grid N = 2 solved exactly by dense LU.
+* V(1,1) cycle: one forward sweep of the tiled multicolour Gauss-Seidel
+  smoother (``smoothers.TiledSOR``) before the coarse correction, one backward
+  sweep after it (so the cycle is symmetric for symmetric operators); coarsest
+  grid N = 2 solved exactly by dense LU.
 * Coarse operators are rediscretised with the same coefficients on the coarse
   grid; for nested conforming spaces with exact quadrature this equals the
   Galerkin product P^T A P.  The coarse-grid wind is the fine nodal wind
@@ -41,7 +42,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .fem import Operators
-from .smoothers import ColouredSOR, colours_q1, colours_q2
+from .smoothers import TILE_Q1, TILE_Q2, TiledSOR, colours_q2, tiles_of
 
 
 def prolong_1d_q2(Nc: int) -> np.ndarray:
@@ -110,13 +111,15 @@ class Levels:
 
     def family(self, fam: str, l: int):
         o = self.ops[l]
+        g = o.grid
         if fam == "q2":
-            return o.Ms, o.Ks, o.Ns, colours_q2(o.grid)
+            iy, ix = np.divmod(g.v_interior, g.nq)
+            return o.Ms, o.Ks, o.Ns, colours_q2(g), tiles_of(ix, iy, g.nq, TILE_Q2)
         if fam == "q1":
             f = o.full
             Nn = f["N1"] if "N1" in f else sp.csr_matrix(f["M1"].shape)
-            iy, ix = np.divmod(np.arange(o.grid.np2), o.grid.np1)
-            return f["M1"], f["K1"], Nn, 2 * (iy % 2) + (ix % 2)
+            iy, ix = np.divmod(np.arange(g.np2), g.np1)
+            return f["M1"], f["K1"], Nn, 2 * (iy % 2) + (ix % 2), tiles_of(ix, iy, g.np1, TILE_Q1)
         raise ValueError(fam)
 
     def prolong(self, fam: str, l: int):
@@ -130,7 +133,7 @@ class ScalarMG:
         self.lv, self.fam = levels, fam
         self.A, self.sor = [], []
         for l in range(len(levels.sizes)):
-            M, K, N, col = levels.family(fam, l)
+            M, K, N, col, tiles = levels.family(fam, l)
             A = alpha * M + gamma * K
             if eta != 0:
                 A = A + eta * N
@@ -138,7 +141,7 @@ class ScalarMG:
                 A = A + eta_t * N.T
             A = sp.csr_matrix(A)
             self.A.append(A)
-            self.sor.append(ColouredSOR(A, col))
+            self.sor.append(TiledSOR(A, col, tiles))
         Ac = self.A[-1].toarray()
         self.pin_coarse = fam == "q1"
         self.coarse = sla.lu_factor(Ac[1:, 1:] if self.pin_coarse else Ac)

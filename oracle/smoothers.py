@@ -13,6 +13,13 @@ Chebyshev spectrum bounds; the readings used here are:
   1 index, so (ix mod 2, iy mod 2) gives 4.  Colour number = 3*(iy%3) + ix%3
   (Q2) or 2*(iy%2) + ix%2 (Q1) with (ix, iy) the padded-grid node indices.
   A forward sweep visits colours 0..C-1, a backward sweep C-1..0.
+* Subdomains: as in a distributed SOR (each process relaxes its own unknowns
+  and sees its neighbours' values from the start of the sweep), the grid is cut
+  into square tiles of TILE_Q2 = 48 (Q2) or TILE_Q1 = 32 (Q1) node indices,
+  tile (ix // T, iy // T); the colour sweep runs inside every tile while
+  couplings to other tiles use the values the sweep started from (block Jacobi
+  between tiles, Gauss-Seidel inside).  Grids of at most T nodes per side form a
+  single tile, i.e. plain multicolour Gauss-Seidel.
 * Chebyshev: Jacobi-preconditioned semi-iteration of Golub and Varga with the
   element-wise spectrum bounds of diag(M)^{-1} M: the 1-D P2 element gives
   [1/2, 5/4] and P1 gives [1/2, 3/2]; tensor products give [1/4, 25/16] for
@@ -25,6 +32,8 @@ import scipy.sparse as sp
 
 Q2_MASS_BOUNDS = (0.25, 25.0 / 16.0)
 Q1_MASS_BOUNDS = (0.25, 9.0 / 4.0)
+TILE_Q2 = 48
+TILE_Q1 = 32
 
 
 def colours_q2(grid) -> np.ndarray:
@@ -37,6 +46,12 @@ def colours_q1(grid) -> np.ndarray:
     """Colour of every kept (non-pinned) Q1 node (compact order)."""
     iy, ix = np.divmod(grid.p_kept, grid.np1)
     return 2 * (iy % 2) + (ix % 2)
+
+
+def tiles_of(ix, iy, nside, T) -> np.ndarray:
+    """Tile number of nodes (ix, iy) on a grid of nside nodes per side."""
+    ntx = (nside + T - 1) // T
+    return (iy // T) * ntx + ix // T
 
 
 class ColouredSOR:
@@ -68,6 +83,32 @@ class ColouredSOR:
         for c in range(self.ncol - 1, -1, -1):
             self._update(c, b, x)
         return x
+
+
+class TiledSOR:
+    """Multicolour Gauss-Seidel inside tiles, block Jacobi between tiles.
+
+    Split A = A_in + A_out with A_in the couplings between nodes of the same
+    tile.  A sweep from x computes b' = b - A_out x once (neighbour tiles seen
+    at the start of the sweep) and then runs the colour sweep of A_in on b'.
+    Forward and backward sweeps are transposes of each other for symmetric A."""
+
+    def __init__(self, A: sp.spmatrix, colours: np.ndarray, tiles: np.ndarray):
+        C = sp.csr_matrix(A).tocoo()
+        same = tiles[C.row] == tiles[C.col]
+        n = A.shape[0]
+        self.A = sp.csr_matrix(A)
+        A_in = sp.csr_matrix((C.data[same], (C.row[same], C.col[same])), shape=(n, n))
+        self.A_out = sp.csr_matrix((C.data[~same], (C.row[~same], C.col[~same])), shape=(n, n))
+        self.inner = ColouredSOR(A_in, colours)
+        self.ncol = self.inner.ncol
+        self.diag = self.inner.diag
+
+    def forward(self, b, x):
+        return self.inner.forward(b - self.A_out @ x, x)
+
+    def backward(self, b, x):
+        return self.inner.backward(b - self.A_out @ x, x)
 
 
 def chebyshev(A: sp.spmatrix, b: np.ndarray, steps: int, bounds) -> np.ndarray:

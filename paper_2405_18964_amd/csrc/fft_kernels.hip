@@ -42,7 +42,7 @@ __device__ inline void lds_fft(double2* buf, int TN, int nt, int logn, const dou
 // mode 0: plain transform (Oseen blocks);  mode 1: apply T_l^{-1} (Stokes).
 // tj[j] = (d_c, c2) per kept frequency.
 template <typename R>
-__global__ void k_time_fft_fwd(const double* __restrict__ r, cpx<R>* __restrict__ V, cpx<R>* __restrict__ P,
+__global__ __launch_bounds__(256) void k_time_fft_fwd(const double* __restrict__ r, cpx<R>* __restrict__ V, cpx<R>* __restrict__ P,
                                int nt, int logn, int L, int nq2, int np2, int nf, int TN,
                                const double2* __restrict__ tw, const double2* __restrict__ tj, double tau, int mode) {
   extern __shared__ double2 buf[];
@@ -99,7 +99,7 @@ __global__ void k_time_fft_fwd(const double* __restrict__ r, cpx<R>* __restrict_
 // from Y_{nt-j} = conj(Y_j), packed as Z_j = Y0_j + i Y1_j, transformed with
 // exp(+2 pi i j t / nt) and scaled by 1/nt:  z[b=0] = Re, z[b=1] = Im.
 template <typename R>
-__global__ void k_time_fft_inv(const cpx<R>* __restrict__ V, const cpx<R>* __restrict__ P, double* __restrict__ z,
+__global__ __launch_bounds__(256) void k_time_fft_inv(const cpx<R>* __restrict__ V, const cpx<R>* __restrict__ P, double* __restrict__ z,
                                int nt, int logn, int L, int nq2, int np2, int nf, int TN,
                                const double2* __restrict__ tw, const double2* __restrict__ tj, double tau, int mode) {
   extern __shared__ double2 buf[];

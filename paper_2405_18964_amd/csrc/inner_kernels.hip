@@ -16,7 +16,7 @@ namespace pintoc {
 // Z_j = [[M, X, 0, B^T], [X, -M, B^T, 0], [0, B, 0, 0], [B, 0, 0, 0]],
 // X = c1 M + c2 L, L = nu K.  cj[j] = (c1, c2 nu).
 template <typename R>
-__global__ void k_zmat_vel(cpx<R>* __restrict__ yV, const cpx<R>* __restrict__ xV, const cpx<R>* __restrict__ xP,
+__global__ __launch_bounds__(256) void k_zmat_vel(cpx<R>* __restrict__ yV, const cpx<R>* __restrict__ xV, const cpx<R>* __restrict__ xP,
                            int n, const double2* __restrict__ cj) {
   const int nq = 2 * n + 1, nq2 = nq * nq, np2 = (n + 1) * (n + 1);
   const int node = blockIdx.x * blockDim.x + threadIdx.x;
@@ -84,7 +84,7 @@ __global__ void k_zmat_vel(cpx<R>* __restrict__ yV, const cpx<R>* __restrict__ x
 }
 
 template <typename R>
-__global__ void k_zmat_pres(cpx<R>* __restrict__ yP, const cpx<R>* __restrict__ xV, int n) {
+__global__ __launch_bounds__(256) void k_zmat_pres(cpx<R>* __restrict__ yP, const cpx<R>* __restrict__ xV, int n) {
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int jb = blockIdx.y;                   // j * 2 + b
@@ -131,7 +131,7 @@ constexpr int kFChunk = 2048;   // entries per work-group and chunk
 constexpr int kFK = 16;         // basis vectors per dot pass
 
 template <typename R>
-__global__ void k_fdot(const cpx<R>* __restrict__ bV, const cpx<R>* __restrict__ bP, size_t ldV, size_t ldP, int k,
+__global__ __launch_bounds__(256) void k_fdot(const cpx<R>* __restrict__ bV, const cpx<R>* __restrict__ bP, size_t ldV, size_t ldP, int k,
                        const cpx<R>* __restrict__ wV, const cpx<R>* __restrict__ wP, int segV, int segP, int chV,
                        int nch, int nf, double2* __restrict__ part) {
   __shared__ double red[2][256];
@@ -175,7 +175,7 @@ __global__ void k_fdot(const cpx<R>* __restrict__ bV, const cpx<R>* __restrict__
   }
 }
 
-__global__ void k_fdot_reduce(const double2* __restrict__ part, int k, int nf, int nch, double2* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_fdot_reduce(const double2* __restrict__ part, int k, int nf, int nch, double2* __restrict__ out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= k * nf) return;
   double sr = 0, si = 0;
@@ -185,7 +185,7 @@ __global__ void k_fdot_reduce(const double2* __restrict__ part, int k, int nf, i
 
 // w^j -= sum_i c[i][j] v_i^j    (c: [k][nf] complex, on the device)
 template <typename R>
-__global__ void k_fupdate(cpx<R>* __restrict__ wV, cpx<R>* __restrict__ wP, const cpx<R>* __restrict__ bV,
+__global__ __launch_bounds__(256) void k_fupdate(cpx<R>* __restrict__ wV, cpx<R>* __restrict__ wP, const cpx<R>* __restrict__ bV,
                           const cpx<R>* __restrict__ bP, size_t ldV, size_t ldP, int k, const double2* __restrict__ c,
                           int segV, int segP, int nf, double sign) {
   const int j = blockIdx.y;
@@ -209,7 +209,7 @@ __global__ void k_fupdate(cpx<R>* __restrict__ wV, cpx<R>* __restrict__ wP, cons
 
 // y^j = a[j] x^j   (a complex per frequency; y may alias x)
 template <typename R>
-__global__ void k_fscale(cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, const double2* __restrict__ a,
+__global__ __launch_bounds__(256) void k_fscale(cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, const double2* __restrict__ a,
                          int segV, int segP) {
   const int j = blockIdx.y;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -224,7 +224,7 @@ __global__ void k_fscale(cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>*
 
 // unpinned copy of the pressure fields: dst = src with dst[f][0] = -sum_{i>=1} src[f][i]
 template <typename R>
-__global__ void k_unpin_copy(cpx<R>* __restrict__ dst, const cpx<R>* __restrict__ src, int nn) {
+__global__ __launch_bounds__(256) void k_unpin_copy(cpx<R>* __restrict__ dst, const cpx<R>* __restrict__ src, int nn) {
   __shared__ double sr[256], si[256];
   const int f = blockIdx.x;
   const cpx<R>* g = src + (size_t)f * nn;
@@ -246,7 +246,7 @@ __global__ void k_unpin_copy(cpx<R>* __restrict__ dst, const cpx<R>* __restrict_
 
 // (de)conversion between the FP64 FFT output and a precision-R frequency vector
 template <typename Rd, typename Rs>
-__global__ void k_convert(cpx<Rd>* __restrict__ d, const cpx<Rs>* __restrict__ s, size_t n) {
+__global__ __launch_bounds__(256) void k_convert(cpx<Rd>* __restrict__ d, const cpx<Rs>* __restrict__ s, size_t n) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     const cpx<Rs> v = s[e];
     d[e] = cmk<cpx<Rd>>((double)v.x, (double)v.y);

@@ -14,6 +14,9 @@ void launch_time_fft_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double
 
 // per-frequency operators and multigrid pieces (mg_kernels.hip)
 template <typename R>
+void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, int n, double h,
+                       const OpCoef* coef, int fpc, int nb, const double* conv, bool forward);
+template <typename R>
 void launch_q2_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef, int fpc,
                         int nb, const double* conv, bool forward);
 template <typename R>

@@ -94,7 +94,7 @@ __device__ inline double b_node(const double* __restrict__ vx, const double* __r
   return -s;
 }
 
-__global__ void k_kkt_apply(const double* __restrict__ x, double* __restrict__ y, int n, int nt, double tau,
+__global__ __launch_bounds__(256) void k_kkt_apply(const double* __restrict__ x, double* __restrict__ y, int n, int nt, double tau,
                             double beta, double nu, const double* __restrict__ conv) {
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int L = 2 * nq2 + np2;
@@ -148,7 +148,7 @@ __global__ void k_kkt_apply(const double* __restrict__ x, double* __restrict__ y
 }
 
 // b = tau M v_d on the adjoint momentum rows, zero elsewhere.
-__global__ void k_assemble_rhs(const double* __restrict__ vd, double* __restrict__ out, int n, int nt, double tau) {
+__global__ __launch_bounds__(256) void k_assemble_rhs(const double* __restrict__ vd, double* __restrict__ out, int n, int nt, double tau) {
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int L = 2 * nq2 + np2;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -202,7 +202,7 @@ constexpr int kDotBlocks = 1024;
 constexpr int kMaxDots = 40;
 
 template <int K>
-__global__ void k_mdot(const double* __restrict__ V, size_t ld, int k, const double* __restrict__ w, size_t n,
+__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, size_t ld, int k, const double* __restrict__ w, size_t n,
                        double* __restrict__ part) {
   __shared__ double red[256];
   double acc[K];
@@ -226,7 +226,7 @@ __global__ void k_mdot(const double* __restrict__ V, size_t ld, int k, const dou
   }
 }
 
-__global__ void k_rowsum(const double* __restrict__ part, int nblk, int k, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_rowsum(const double* __restrict__ part, int nblk, int k, double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
   double s = 0;
@@ -235,7 +235,7 @@ __global__ void k_rowsum(const double* __restrict__ part, int nblk, int k, doubl
 }
 
 // w -= sum_i c[i] V_i   (c on device)
-__global__ void k_mgs_update(double* __restrict__ w, const double* __restrict__ V, size_t ld, int k,
+__global__ __launch_bounds__(256) void k_mgs_update(double* __restrict__ w, const double* __restrict__ V, size_t ld, int k,
                              const double* __restrict__ c, size_t n) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     double s = w[e];
@@ -245,13 +245,13 @@ __global__ void k_mgs_update(double* __restrict__ w, const double* __restrict__ 
 }
 
 // y = a x + b y
-__global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b, size_t n) {
+__global__ __launch_bounds__(256) void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b, size_t n) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
     y[e] = a * x[e] + b * y[e];
 }
 
 // y += sum_i c[i] Z_i  (c on device)
-__global__ void k_lincomb_add(double* __restrict__ y, const double* __restrict__ Z, size_t ld, int k,
+__global__ __launch_bounds__(256) void k_lincomb_add(double* __restrict__ y, const double* __restrict__ Z, size_t ld, int k,
                               const double* __restrict__ c, size_t n) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     double s = y[e];
@@ -282,7 +282,7 @@ void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, in
 }
 
 // zero-fill (a kernel rather than hipMemsetAsync so the sequence stays capturable)
-__global__ void k_fill_zero(uint4* __restrict__ p, size_t n16) {
+__global__ __launch_bounds__(256) void k_fill_zero(uint4* __restrict__ p, size_t n16) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += (size_t)gridDim.x * blockDim.x)
     p[e] = make_uint4(0, 0, 0, 0);
 }

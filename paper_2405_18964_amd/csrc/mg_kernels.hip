@@ -119,7 +119,7 @@ __device__ inline void q1_apply_node(const cpx<R>* __restrict__ x, int n, int ix
 // ------------------------------------------------------------- GS colours
 // Q2 colour (cx, cy): interior nodes with ix % 3 == cx, iy % 3 == cy.
 template <typename R>
-__global__ void k_q2_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b, int n, double h,
+__global__ __launch_bounds__(256) void k_q2_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b, int n, double h,
                                int cx, int cy, int ncx, int ncy, const OpCoef* __restrict__ coef, int fpc,
                                const double* __restrict__ conv) {
   const int f = blockIdx.y;
@@ -142,7 +142,7 @@ __global__ void k_q2_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict_
 
 // Q1 colour (cx, cy): nodes with ix % 2 == cx, iy % 2 == cy, 0 <= ix, iy <= n.
 template <typename R>
-__global__ void k_q1_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b, int n, double h,
+__global__ __launch_bounds__(256) void k_q1_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b, int n, double h,
                                int cx, int cy, int ncx, int ncy, const OpCoef* __restrict__ coef, int fpc,
                                const double* __restrict__ conv) {
   const int f = blockIdx.y;
@@ -160,9 +160,159 @@ __global__ void k_q1_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict_
   x[i] = x[i] + cdiv(r, dg);
 }
 
+// ------------------------------------------------------ tiled GS sweeps
+// Symmetric multicolour Gauss-Seidel inside square tiles, block Jacobi between
+// tiles (a distributed SOR with one tile per subdomain).  A work-group owns
+// one tile of one grid: it loads the tile and a halo into LDS, runs every
+// colour in LDS (neighbour tiles keep the values the sweep started from), and
+// writes the tile to xo.  xi and xo must be different buffers.
+constexpr int kT2 = 48, kL2 = kT2 + 4;       // Q2 tile and LDS side (halo 2)
+constexpr int kT1 = 32, kL1 = kT1 + 2;       // Q1 tile and LDS side (halo 1)
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_q2_tile_sweep(cpx<R>* __restrict__ xo, const cpx<R>* __restrict__ xi,
+                                                       const cpx<R>* __restrict__ b, int n, double h,
+                                                       const OpCoef* __restrict__ coef, int fpc,
+                                                       const double* __restrict__ conv, int forward, int ntx) {
+  __shared__ cpx<R> sx[kL2 * kL2];
+  const int f = blockIdx.y;
+  const int X0 = (blockIdx.x % ntx) * kT2, Y0 = (blockIdx.x / ntx) * kT2;
+  const int nq = 2 * n + 1;
+  const size_t off = (size_t)f * nq * nq;
+  for (int e = threadIdx.x; e < kL2 * kL2; e += blockDim.x) {
+    const int gx = X0 - 2 + e % kL2, gy = Y0 - 2 + e / kL2;
+    sx[e] = (gx >= 0 && gx < nq && gy >= 0 && gy < nq) ? xi[off + (size_t)gy * nq + gx] : cmk<cpx<R>>(0, 0);
+  }
+  const OpCoef c = coef[f / fpc];
+  __syncthreads();
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  for (int k = 0; k < 9; ++k) {
+    const int col = forward ? k : 8 - k;
+    const int lx = col % 3 + 3 * tx, ly = col / 3 + 3 * ty;
+    const int gx = X0 + lx, gy = Y0 + ly;
+    if (gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2) {
+      double mx[5], kx[5], my[5], ky[5];
+      q2_rows(gx, h, mx, kx);
+      q2_rows(gy, h, my, ky);
+      double amr = 0, ami = 0, akr = 0, aki = 0;
+#pragma unroll
+      for (int dy = 0; dy < 5; ++dy) {
+        const cpx<R>* row = sx + (ly + dy) * kL2 + lx;
+        double smr = 0, smi = 0, skr = 0, ski = 0;
+#pragma unroll
+        for (int dx = 0; dx < 5; ++dx) {
+          const cpx<R> v = row[dx];
+          smr += mx[dx] * (double)v.x; smi += mx[dx] * (double)v.y;
+          skr += kx[dx] * (double)v.x; ski += kx[dx] * (double)v.y;
+        }
+        amr += my[dy] * smr; ami += my[dy] * smi;
+        akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
+      }
+      double rr = c.alpha.x * amr - c.alpha.y * ami + c.gamma.x * akr - c.gamma.y * aki;
+      double ri = c.alpha.x * ami + c.alpha.y * amr + c.gamma.x * aki + c.gamma.y * akr;
+      const double md = mx[2] * my[2], kd = kx[2] * my[2] + mx[2] * ky[2];
+      double dr = c.alpha.x * md + c.gamma.x * kd, di = c.alpha.y * md + c.gamma.y * kd;
+      if (conv) {
+        const double* cn = conv + (size_t)(gy * nq + gx) * 50;
+        double nr = 0, ni = 0, tr = 0, ti = 0;
+        for (int dy = 0; dy < 5; ++dy)
+          for (int dx = 0; dx < 5; ++dx) {
+            const cpx<R> v = sx[(ly + dy) * kL2 + lx + dx];
+            const double a = cn[dy * 5 + dx], bb = cn[25 + dy * 5 + dx];
+            nr += a * (double)v.x; ni += a * (double)v.y;
+            tr += bb * (double)v.x; ti += bb * (double)v.y;
+          }
+        rr += c.eta.x * nr - c.eta.y * ni + c.etat.x * tr - c.etat.y * ti;
+        ri += c.eta.x * ni + c.eta.y * nr + c.etat.x * ti + c.etat.y * tr;
+        dr += c.eta.x * cn[12] + c.etat.x * cn[37];
+        di += c.eta.y * cn[12] + c.etat.y * cn[37];
+      }
+      const cpx<R> bi = b[off + (size_t)gy * nq + gx];
+      const double er = (double)bi.x - rr, ei = (double)bi.y - ri;
+      const double den = dr * dr + di * di;
+      cpx<R>& xs = sx[(ly + 2) * kL2 + lx + 2];
+      xs = cmk<cpx<R>>((double)xs.x + (er * dr + ei * di) / den, (double)xs.y + (ei * dr - er * di) / den);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kT2 * kT2; e += blockDim.x) {
+    const int gx = X0 + e % kT2, gy = Y0 + e / kT2;
+    if (gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2)
+      xo[off + (size_t)gy * nq + gx] = sx[(e / kT2 + 2) * kL2 + e % kT2 + 2];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_q1_tile_sweep(cpx<R>* __restrict__ xo, const cpx<R>* __restrict__ xi,
+                                                       const cpx<R>* __restrict__ b, int n, double h,
+                                                       const OpCoef* __restrict__ coef, int fpc,
+                                                       const double* __restrict__ conv, int forward, int ntx) {
+  __shared__ cpx<R> sx[kL1 * kL1];
+  const int f = blockIdx.y;
+  const int X0 = (blockIdx.x % ntx) * kT1, Y0 = (blockIdx.x / ntx) * kT1;
+  const int np = n + 1;
+  const size_t off = (size_t)f * np * np;
+  for (int e = threadIdx.x; e < kL1 * kL1; e += blockDim.x) {
+    const int gx = X0 - 1 + e % kL1, gy = Y0 - 1 + e / kL1;
+    sx[e] = (gx >= 0 && gx <= n && gy >= 0 && gy <= n) ? xi[off + (size_t)gy * np + gx] : cmk<cpx<R>>(0, 0);
+  }
+  const OpCoef c = coef[f / fpc];
+  __syncthreads();
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  for (int k = 0; k < 4; ++k) {
+    const int col = forward ? k : 3 - k;
+    const int lx = col % 2 + 2 * tx, ly = col / 2 + 2 * ty;
+    const int gx = X0 + lx, gy = Y0 + ly;
+    if (gx <= n && gy <= n) {
+      double mx[3], kx[3], my[3], ky[3];
+      q1_rows(gx, n, h, mx, kx);
+      q1_rows(gy, n, h, my, ky);
+      double amr = 0, ami = 0, akr = 0, aki = 0, nr = 0, ni = 0, tr = 0, ti = 0;
+      const double* cn = conv ? conv + (size_t)(gy * np + gx) * 18 : nullptr;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        double smr = 0, smi = 0, skr = 0, ski = 0;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const cpx<R> v = sx[(ly + dy) * kL1 + lx + dx];
+          smr += mx[dx] * (double)v.x; smi += mx[dx] * (double)v.y;
+          skr += kx[dx] * (double)v.x; ski += kx[dx] * (double)v.y;
+          if (cn) {
+            const double a = cn[dy * 3 + dx], bb = cn[9 + dy * 3 + dx];
+            nr += a * (double)v.x; ni += a * (double)v.y;
+            tr += bb * (double)v.x; ti += bb * (double)v.y;
+          }
+        }
+        amr += my[dy] * smr; ami += my[dy] * smi;
+        akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
+      }
+      double rr = c.alpha.x * amr - c.alpha.y * ami + c.gamma.x * akr - c.gamma.y * aki;
+      double ri = c.alpha.x * ami + c.alpha.y * amr + c.gamma.x * aki + c.gamma.y * akr;
+      const double md = mx[1] * my[1], kd = kx[1] * my[1] + mx[1] * ky[1];
+      double dr = c.alpha.x * md + c.gamma.x * kd, di = c.alpha.y * md + c.gamma.y * kd;
+      if (cn) {
+        rr += c.eta.x * nr - c.eta.y * ni + c.etat.x * tr - c.etat.y * ti;
+        ri += c.eta.x * ni + c.eta.y * nr + c.etat.x * ti + c.etat.y * tr;
+        dr += c.eta.x * cn[4] + c.etat.x * cn[13];
+        di += c.eta.y * cn[4] + c.etat.y * cn[13];
+      }
+      const cpx<R> bi = b[off + (size_t)gy * np + gx];
+      const double er = (double)bi.x - rr, ei = (double)bi.y - ri;
+      const double den = dr * dr + di * di;
+      cpx<R>& xs = sx[(ly + 1) * kL1 + lx + 1];
+      xs = cmk<cpx<R>>((double)xs.x + (er * dr + ei * di) / den, (double)xs.y + (ei * dr - er * di) / den);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kT1 * kT1; e += blockDim.x) {
+    const int gx = X0 + e % kT1, gy = Y0 + e / kT1;
+    if (gx <= n && gy <= n) xo[off + (size_t)gy * np + gx] = sx[(e / kT1 + 1) * kL1 + e % kT1 + 1];
+  }
+}
+
 // ------------------------------------------------------ residual r = b - A x
 template <typename R>
-__global__ void k_q2_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
+__global__ __launch_bounds__(256) void k_q2_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
                               int n, double h, const OpCoef* __restrict__ coef, int fpc,
                               const double* __restrict__ conv) {
   const int f = blockIdx.y;
@@ -178,7 +328,7 @@ __global__ void k_q2_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__
 }
 
 template <typename R>
-__global__ void k_q1_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
+__global__ __launch_bounds__(256) void k_q1_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
                               int n, double h, const OpCoef* __restrict__ coef, int fpc,
                               const double* __restrict__ conv) {
   const int f = blockIdx.y;
@@ -194,7 +344,7 @@ __global__ void k_q1_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__
 
 // y = A x (operator application; b = 0 residual form negated)
 template <typename R>
-__global__ void k_q2_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
+__global__ __launch_bounds__(256) void k_q2_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
                            const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv) {
   const int f = blockIdx.y;
   const int nq = 2 * n + 1;
@@ -209,7 +359,7 @@ __global__ void k_q2_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x,
 }
 
 template <typename R>
-__global__ void k_q1_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
+__global__ __launch_bounds__(256) void k_q1_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
                            const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv) {
   const int f = blockIdx.y;
   const int np = n + 1;
@@ -233,7 +383,7 @@ __device__ inline void q2_restrict_w(int I, double w[7]) {
 
 // bc = P^T rf on coarse interior nodes (fine boundary residuals are zero).
 template <typename R>
-__global__ void k_q2_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc) {
+__global__ __launch_bounds__(256) void k_q2_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc) {
   const int f = blockIdx.y;
   const int nqc = 2 * nc + 1, nqf = 4 * nc + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -272,7 +422,7 @@ __device__ inline void q2_prolong_w(int i, int& c0, double w[3]) {
 
 // xf += P ec on fine interior nodes.
 template <typename R>
-__global__ void k_q2_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc) {
+__global__ __launch_bounds__(256) void k_q2_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc) {
   const int f = blockIdx.y;
   const int nqc = 2 * nc + 1, nqf = 4 * nc + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -304,7 +454,7 @@ __global__ void k_q2_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restri
 
 // Q1: bc = P^T rf (coarse node I <-> fine 2I, weights 1/2, 1, 1/2).
 template <typename R>
-__global__ void k_q1_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc) {
+__global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc) {
   const int f = blockIdx.y;
   const int npc = nc + 1, nf = 2 * nc, npf = nf + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,7 +477,7 @@ __global__ void k_q1_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict_
 }
 
 template <typename R>
-__global__ void k_q1_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc) {
+__global__ __launch_bounds__(256) void k_q1_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc) {
   const int f = blockIdx.y;
   const int npc = nc + 1, npf = 2 * nc + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,7 +508,7 @@ __global__ void k_q1_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restri
 // Q1: 9 nodes with node 0 held at zero and an 8x8 inverse for nodes 1..8.
 // inv[ci] holds the dense inverse (row-major, complex FP64) per coefficient set.
 template <typename R>
-__global__ void k_q2_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
+__global__ __launch_bounds__(256) void k_q2_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
                                   const double2* __restrict__ inv, int fpc, int nb) {
   const int f = blockIdx.x * (blockDim.x / 9) + threadIdx.x / 9;
   const int r = threadIdx.x % 9;
@@ -376,7 +526,7 @@ __global__ void k_q2_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restri
 }
 
 template <typename R>
-__global__ void k_q1_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
+__global__ __launch_bounds__(256) void k_q1_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
                                   const double2* __restrict__ inv, int fpc, int nb) {
   const int f = blockIdx.x * (blockDim.x / 9) + threadIdx.x / 9;
   const int r = threadIdx.x % 9;
@@ -401,7 +551,7 @@ __global__ void k_q1_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restri
 //   else:   xn = w (x - xp + g D^{-1}(b - M x)) + xp
 // xn may alias xp (each thread reads its own xp entry before writing).
 template <typename R>
-__global__ void k_q2_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
+__global__ __launch_bounds__(256) void k_q2_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
                           const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first) {
   const int f = blockIdx.y;
   const int nq = 2 * n + 1;
@@ -429,7 +579,7 @@ __global__ void k_q2_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>
 }
 
 template <typename R>
-__global__ void k_q1_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
+__global__ __launch_bounds__(256) void k_q1_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
                           const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first) {
   const int f = blockIdx.y;
   const int np = n + 1;
@@ -460,7 +610,7 @@ __global__ void k_q1_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>
 // pinned pressure field whose node-0 entry is zero on entry).
 // One block per grid; fixed-order tree reduction (deterministic).
 template <typename R>
-__global__ void k_unpin_in(cpx<R>* __restrict__ z, int nn) {
+__global__ __launch_bounds__(256) void k_unpin_in(cpx<R>* __restrict__ z, int nn) {
   __shared__ double sr[256], si[256];
   const int f = blockIdx.x;
   cpx<R>* g = z + (size_t)f * nn;
@@ -478,7 +628,7 @@ __global__ void k_unpin_in(cpx<R>* __restrict__ z, int nn) {
 // out = a_j yK + g_j yM, then shift by out[node 0] so that node 0 is zero
 // (R (I - 1 e0^T)).  Coefficients per grid pair: ab[f / fpc] = (a, g) real.
 template <typename R>
-__global__ void k_schur_combine_pin(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ yK,
+__global__ __launch_bounds__(256) void k_schur_combine_pin(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ yK,
                                     const cpx<R>* __restrict__ yM, const double2* __restrict__ ab,
                                     int fpc, int nn) {
   const int f = blockIdx.y;
@@ -493,6 +643,20 @@ __global__ void k_schur_combine_pin(cpx<R>* __restrict__ out, const cpx<R>* __re
 
 // ------------------------------------------------------------ launchers
 static inline dim3 grid2(long work, int nb, int bs = 256) { return dim3((unsigned)((work + bs - 1) / bs), nb); }
+
+template <typename R>
+void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, int n, double h,
+                       const OpCoef* coef, int fpc, int nb, const double* conv, bool forward) {
+  if (q2) {
+    const int nq = 2 * n + 1, ntx = (nq + kT2 - 1) / kT2;
+    hipLaunchKernelGGL(k_q2_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, n, h, coef, fpc, conv,
+                       forward ? 1 : 0, ntx);
+  } else {
+    const int np = n + 1, ntx = (np + kT1 - 1) / kT1;
+    hipLaunchKernelGGL(k_q1_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, n, h, coef, fpc, conv,
+                       forward ? 1 : 0, ntx);
+  }
+}
 
 template <typename R>
 void launch_q2_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef,
@@ -600,6 +764,8 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
 }
 
 #define PINTOC_INST(R)                                                                                        \
+  template void launch_tile_sweep<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,        \
+                                     const OpCoef*, int, int, const double*, bool);                            \
   template void launch_q2_gs_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
                                       const double*, bool);                                                    \
   template void launch_q1_gs_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \

@@ -39,8 +39,9 @@ struct MGPlan {
   OpCoef* coef = nullptr;              // device
   double2* inv = nullptr;              // device
   std::vector<const double*> conv;     // per level (device) or null
-  // per-level device buffers (complex, precision-typed); level 0 uses r only
-  std::vector<void*> b, x, r;
+  // per-level device buffers (complex, precision-typed): b, x (level >= 1),
+  // t (second iterate buffer of the out-of-place smoother), r (residual)
+  std::vector<void*> b, x, r, t;
   int n(int l) const { return N >> l; }
   size_t nodes(int l) const {
     const size_t m = q2 ? (size_t)(2 * n(l) + 1) : (size_t)(n(l) + 1);
@@ -187,13 +188,17 @@ static void plan_mg_buffers(MGPlan& m, Carver& cv, size_t csize) {
   m.b.assign(m.nlev, nullptr);
   m.x.assign(m.nlev, nullptr);
   m.r.assign(m.nlev, nullptr);
+  m.t.assign(m.nlev, nullptr);
   for (int l = 0; l < m.nlev; ++l) {
     const size_t bytes = m.nodes(l) * m.nb * csize;
     if (l > 0) {
       m.b[l] = cv.take<char>(bytes);
       m.x[l] = cv.take<char>(bytes);
     }
-    if (l + 1 < m.nlev) m.r[l] = cv.take<char>(bytes);
+    if (l + 1 < m.nlev) {
+      m.r[l] = cv.take<char>(bytes);
+      m.t[l] = cv.take<char>(bytes);
+    }
   }
   m.coef = cv.take<OpCoef>(sizeof(OpCoef) * m.ncoef);
   m.inv = cv.take<double2>(sizeof(double2) * m.inv_h.size());
@@ -384,18 +389,18 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b) 
     launch_coarse<R>(s, m.q2, x, b, m.inv, m.fpc, m.nb);
     return;
   }
-  if (m.q2) launch_q2_gs_sweep<R>(s, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], true);
-  else launch_q1_gs_sweep<R>(s, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], true);
+  // pre-smoothing x -> t, coarse correction on t, post-smoothing t -> x
+  cpx<R>* t = (cpx<R>*)m.t[l];
+  launch_tile_sweep<R>(s, m.q2, t, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], true);
   cpx<R>* r = (cpx<R>*)m.r[l];
-  launch_residual<R>(s, m.q2, r, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l]);
+  launch_residual<R>(s, m.q2, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l]);
   cpx<R>* bc = (cpx<R>*)m.b[l + 1];
   cpx<R>* xc = (cpx<R>*)m.x[l + 1];
   launch_restrict<R>(s, m.q2, bc, r, n / 2, m.nb);
   launch_fill_zero(s, xc, m.nodes(l + 1) * m.nb * sizeof(cpx<R>));
   vcycle<R>(s, m, l + 1, xc, bc);
-  launch_prolong_add<R>(s, m.q2, x, xc, n / 2, m.nb);
-  if (m.q2) launch_q2_gs_sweep<R>(s, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], false);
-  else launch_q1_gs_sweep<R>(s, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], false);
+  launch_prolong_add<R>(s, m.q2, t, xc, n / 2, m.nb);
+  launch_tile_sweep<R>(s, m.q2, x, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], false);
 }
 
 // x = MG^cycles(b) from x = 0

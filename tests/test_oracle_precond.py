@@ -14,8 +14,8 @@ from oracle.kkt import Problem
 from oracle.krylov import fgmres, gmres
 from oracle.mg import Levels, ScalarMG
 from oracle.precond import OseenPreconditioner, StokesPreconditioner, stokes_constants
-from oracle.smoothers import (Q1_MASS_BOUNDS, Q2_MASS_BOUNDS, ColouredSOR, chebyshev,
-                              chebyshev_error_bound, colours_q1, colours_q2)
+from oracle.smoothers import (Q1_MASS_BOUNDS, Q2_MASS_BOUNDS, ColouredSOR, TiledSOR, chebyshev,
+                              chebyshev_error_bound, colours_q1, colours_q2, tiles_of)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -355,3 +355,62 @@ def test_gmres_matches_direct_solution():
     assert np.linalg.norm(A @ x - b) <= 1e-11 * np.linalg.norm(b)
     x, its, _ = fgmres(lambda v: A @ v, lambda v: v / 3, b.real, 1e-12, restart=5, maxit=200)
     assert np.linalg.norm(A @ x - b.real) <= 1e-11 * np.linalg.norm(b.real)
+
+
+def _brute_tiled_sweep(A, b, x, colours, tiles, order):
+    """Node-by-node definition: inside a tile, colours in ``order``; a node
+    sees the current values of its own tile and the sweep-start values of
+    other tiles."""
+    A = A.toarray()
+    x0 = x.copy()
+    x = x.copy()
+    for t in np.unique(tiles):
+        for c in order:
+            for i in np.flatnonzero((tiles == t) & (colours == c)):
+                y = np.where(tiles == t, x, x0)
+                x[i] = x[i] + (b[i] - A[i] @ y) / A[i, i]
+    return x
+
+
+@pytest.mark.parametrize("T", [2, 4, 48])
+def test_tiled_sor_matches_definition(T):
+    """The tiled sweep equals the node-by-node definition (several tiles for
+    small T) and, with a single tile, plain multicolour Gauss-Seidel."""
+    N = 4
+    o = Operators(N, 1.0, W.wind_nodal(N))
+    g = o.grid
+    iy, ix = np.divmod(g.v_interior, g.nq)
+    tiles = tiles_of(ix, iy, g.nq, T)
+    col = colours_q2(g)
+    A = (1.3 * o.Ms + 0.2 * o.Ks + 0.1 * o.Ns).tocsr()
+    rng = np.random.default_rng(T)
+    b, x = rng.standard_normal(g.nV), rng.standard_normal(g.nV)
+    sor = TiledSOR(A, col, tiles)
+    assert np.allclose(sor.forward(b, x.copy()), _brute_tiled_sweep(A, b, x, col, tiles, range(9)), atol=1e-13)
+    assert np.allclose(sor.backward(b, x.copy()), _brute_tiled_sweep(A, b, x, col, tiles, range(8, -1, -1)),
+                       atol=1e-13)
+    if T >= g.nq:
+        assert np.allclose(sor.forward(b, x.copy()), ColouredSOR(A, col).forward(b, x.copy()), atol=1e-14)
+    # Q1 unconstrained grid, 4 colours
+    iy1, ix1 = np.divmod(np.arange(g.np2), g.np1)
+    t1 = tiles_of(ix1, iy1, g.np1, max(T // 2, 2))
+    c1 = 2 * (iy1 % 2) + ix1 % 2
+    A1 = (o.full["K1"] + 0.5 * o.full["M1"]).tocsr()
+    b1, x1 = rng.standard_normal(g.np2), rng.standard_normal(g.np2)
+    assert np.allclose(TiledSOR(A1, c1, t1).forward(b1, x1.copy()),
+                       _brute_tiled_sweep(A1, b1, x1, c1, t1, range(4)), atol=1e-13)
+
+
+def test_tiled_sor_symmetric_pair():
+    N = 8
+    o = Operators(N, 1.0)
+    g = o.grid
+    iy, ix = np.divmod(g.v_interior, g.nq)
+    A = (o.Ms + 0.3 * o.Ks).tocsr()
+    sor = TiledSOR(A, colours_q2(g), tiles_of(ix, iy, g.nq, 4))
+    n = g.nV
+    Sm = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n); e[k] = 1.0
+        Sm[:, k] = sor.backward(e, sor.forward(e, np.zeros(n)))
+    assert np.allclose(Sm, Sm.T, atol=1e-13)
