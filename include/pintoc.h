@@ -173,6 +173,27 @@ int64_t pintoc_vector_length(const pintoc_problem* p);
  * application).  Entries are zero in LINEAR mode. */
 int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* counts, int32_t n);
 
+/* Live timing of the dominant kernel, for roofline reports: the fine-grid
+ * smoothing sweep of the velocity multigrid (the tiled Gauss-Seidel sweep of
+ * section 3.4 applied to W_j on all kept frequencies at once).  While enabled,
+ * each such launch is bracketed by HIP events recorded on the stream it runs
+ * on; the most recent 4096 launches are kept.  Enabling allocates the events
+ * (host-side HIP objects, no device memory from the workspace). */
+typedef struct {
+  double avg_ms;             /* mean duration of the timed launches           */
+  int64_t launches;          /* number of launches averaged (<= 4096)         */
+  double algorithmic_bytes;  /* compulsory bytes of one launch: read x, read b,
+                                write x over all grids of the batch           */
+} pintoc_kernel_timing;
+
+/* enable != 0 starts a new recording (clears previous samples); 0 stops.
+ * Errors: PINTOC_EINVAL (NULL), PINTOC_EHIP (event creation failed). */
+int pintoc_profile_enable(pintoc_problem* p, int32_t enable);
+
+/* Waits for the recorded launches to finish and fills *out.
+ * Errors: PINTOC_EINVAL (NULL), PINTOC_ESTATE (nothing recorded), PINTOC_EHIP. */
+int pintoc_profile_read(pintoc_problem* p, pintoc_kernel_timing* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,10 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelTiming(C.Structure):
+    _fields_ = [("avg_ms", C.c_double), ("launches", C.c_int64), ("algorithmic_bytes", C.c_double)]
+
+
 _lib = None
 
 # exported symbols and their signatures (restype, argtypes)
@@ -54,6 +58,8 @@ SIGNATURES = {
     "pintoc_last_error": (C.c_char_p, []),
     "pintoc_vector_length": (C.c_int64, [C.c_void_p]),
     "pintoc_last_inner_iterations": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
+    "pintoc_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pintoc_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelTiming)]),
 }
 
 
@@ -179,6 +185,15 @@ class Problem:
         arr = (C.c_int32 * nf)()
         k = _check(library().pintoc_last_inner_iterations(self._h, arr, nf), "pintoc_last_inner_iterations")
         return [int(arr[i]) for i in range(k)]
+
+    def profile_enable(self, on=True):
+        """Start (or stop) timing the finest-level velocity smoother launches."""
+        _check(library().pintoc_profile_enable(self._h, 1 if on else 0), "pintoc_profile_enable")
+
+    def profile_read(self):
+        kt = KernelTiming()
+        _check(library().pintoc_profile_read(self._h, C.byref(kt)), "pintoc_profile_read")
+        return {"avg_ms": kt.avg_ms, "launches": kt.launches, "algorithmic_bytes": kt.algorithmic_bytes}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -26,6 +26,27 @@ static int fail(int code, const std::string& msg) { g_err = msg; return code; }
     if (e_ != hipSuccess) return fail(PINTOC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// ------------------------------------------------------------ timing probe
+// Ring of HIP event pairs around launches of the dominant kernel.
+struct Probe {
+  static constexpr int kCap = 4096;
+  std::vector<hipEvent_t> e0, e1;
+  long count = 0;
+  bool on = false;
+  int create() {
+    if (!e0.empty()) return PINTOC_OK;
+    e0.resize(kCap); e1.resize(kCap);
+    for (int i = 0; i < kCap; ++i) {
+      if (hipEventCreate(&e0[i]) != hipSuccess || hipEventCreate(&e1[i]) != hipSuccess) return PINTOC_EHIP;
+    }
+    return PINTOC_OK;
+  }
+  ~Probe() {
+    for (auto e : e0) hipEventDestroy(e);
+    for (auto e : e1) hipEventDestroy(e);
+  }
+};
+
 // ------------------------------------------------------------ multigrid plan
 struct MGPlan {
   bool q2 = true;
@@ -42,6 +63,7 @@ struct MGPlan {
   // per-level device buffers (complex, precision-typed): b, x (level >= 1),
   // t (second iterate buffer of the out-of-place smoother), r (residual)
   std::vector<void*> b, x, r, t;
+  Probe* probe = nullptr;              // times the finest-level sweeps when on
   int n(int l) const { return N >> l; }
   size_t nodes(int l) const {
     const size_t m = q2 ? (size_t)(2 * n(l) + 1) : (size_t)(n(l) + 1);
@@ -72,6 +94,7 @@ struct pintoc_problem {
   std::vector<double2> cj_h;
   int segV = 0, segP = 0;
   MGPlan mgW, mgK;
+  Probe probe;
   // inner statistics
   long inner_its_sum = 0, inner_blocks = 0;
   int inner_its_max = 0;
@@ -270,6 +293,36 @@ extern "C" const char* pintoc_last_error(void) { return g_err.c_str(); }
 
 extern "C" int64_t pintoc_vector_length(const pintoc_problem* p) { return p ? p->n_all : 0; }
 
+extern "C" int pintoc_profile_enable(pintoc_problem* p, int32_t enable) {
+  if (!p) return fail(PINTOC_EINVAL, "NULL handle");
+  if (enable) {
+    if (p->probe.create() != PINTOC_OK) return fail(PINTOC_EHIP, "hipEventCreate failed");
+    p->probe.count = 0;
+    p->probe.on = true;
+    p->mgW.probe = &p->probe;
+  } else {
+    p->probe.on = false;
+  }
+  return PINTOC_OK;
+}
+
+extern "C" int pintoc_profile_read(pintoc_problem* p, pintoc_kernel_timing* out) {
+  if (!p || !out) return fail(PINTOC_EINVAL, "NULL handle or output");
+  const long n = std::min<long>(p->probe.count, Probe::kCap);
+  if (n == 0) return fail(PINTOC_ESTATE, "no timed launches recorded");
+  double sum = 0;
+  for (long i = 0; i < n; ++i) {
+    HIPCHK(hipEventSynchronize(p->probe.e1[i]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p->probe.e0[i], p->probe.e1[i]));
+    sum += ms;
+  }
+  out->avg_ms = sum / n;
+  out->launches = n;
+  out->algorithmic_bytes = 3.0 * (double)p->mgW.nodes(0) * p->mgW.nb * (double)p->csize;
+  return PINTOC_OK;
+}
+
 extern "C" int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* counts, int32_t n) {
   if (!p || !counts) return fail(PINTOC_EINVAL, "NULL handle or array");
   if (p->o.inner == PINTOC_INNER_LINEAR) {
@@ -391,7 +444,14 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b) 
   }
   // pre-smoothing x -> t, coarse correction on t, post-smoothing t -> x
   cpx<R>* t = (cpx<R>*)m.t[l];
-  launch_tile_sweep<R>(s, m.q2, t, x, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], true);
+  Probe* pr = (l == 0 && m.probe && m.probe->on) ? m.probe : nullptr;
+  auto timed_sweep = [&](cpx<R>* xo, const cpx<R>* xi, bool fwd) {
+    const int slot = pr ? (int)(pr->count % Probe::kCap) : 0;
+    if (pr) hipEventRecord(pr->e0[slot], s);
+    launch_tile_sweep<R>(s, m.q2, xo, xi, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], fwd);
+    if (pr) { hipEventRecord(pr->e1[slot], s); pr->count++; }
+  };
+  timed_sweep(t, x, true);
   cpx<R>* r = (cpx<R>*)m.r[l];
   launch_residual<R>(s, m.q2, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l]);
   cpx<R>* bc = (cpx<R>*)m.b[l + 1];
@@ -400,7 +460,7 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b) 
   launch_fill_zero(s, xc, m.nodes(l + 1) * m.nb * sizeof(cpx<R>));
   vcycle<R>(s, m, l + 1, xc, bc);
   launch_prolong_add<R>(s, m.q2, t, xc, n / 2, m.nb);
-  launch_tile_sweep<R>(s, m.q2, x, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], false);
+  timed_sweep(x, t, false);
 }
 
 // x = MG^cycles(b) from x = 0
