@@ -120,6 +120,13 @@ struct OpCoef {
   double2 alpha, gamma, eta, etat;
 };
 
+// Coefficients of one frequency block in the (v, lambda, p, mu) pattern shared
+// by the Stokes Z_j and the Oseen G_j (see oseen_kernels.hip).
+struct BlockCoef {
+  double2 a11, a12, b12, e12, a21, b21, e21, a22;
+  double s, pad;
+};
+
 inline __host__ __device__ int q2n(int n) { return 2 * n + 1; }
 inline __host__ __device__ int q1n(int n) { return n + 1; }
 

@@ -76,3 +76,21 @@ void launch_unpin_copy(hipStream_t s, cpx<R>* dst, const cpx<R>* src, int nn, in
 template <typename Rd, typename Rs>
 void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n);
 }  // namespace pintoc
+
+namespace pintoc {
+// frequency blocks and the Oseen preconditioner pieces (oseen_kernels.hip)
+template <typename R>
+void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
+                      const BlockCoef* bc, const double* conv, double sp);
+template <typename R>
+void launch_schur_rhs(hipStream_t s, cpx<R>* out, const cpx<R>* in, const cpx<R>* y1, const cpx<R>* y2, int n,
+                      int nf, double tau);
+template <typename R>
+void launch_oseen_hp(hipStream_t s, cpx<R>* U, const cpx<R>* zz, int n, int nf, const double2* dj, double tau,
+                     double beta, double nu, const double* conv);
+template <typename R>
+void launch_block_copy(hipStream_t s, cpx<R>* V, cpx<R>* X, int n, int nf, int b, int dir);
+template <typename R>
+void launch_combine3(hipStream_t s, cpx<R>* out, const cpx<R>* A, const cpx<R>* B, const cpx<R>* C, double c0,
+                     double c1, double c2, size_t n);
+}  // namespace pintoc

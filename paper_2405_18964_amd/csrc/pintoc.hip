@@ -94,6 +94,25 @@ struct pintoc_problem {
   std::vector<double2> cj_h;
   int segV = 0, segP = 0;
   MGPlan mgW, mgK;
+  // block coefficients of Z_j (Stokes) or G_j (Oseen), per kept frequency
+  std::vector<BlockCoef> bc_h;
+  BlockCoef* bc = nullptr;
+  double block_scale = 1.0;            // s of the pressure rows (1 Stokes, tau Oseen)
+  // Oseen: convection tables (host copies and device), Q_j / Q_j^H multigrid,
+  // operator tables of the Uzawa steps and the Schur step
+  std::vector<std::vector<double>> conv2_h;   // per level, 50 per Q2 node
+  std::vector<double> conv1_h;                // finest Q1 grid, 18 per node
+  std::vector<double*> conv2;
+  double* conv1 = nullptr;
+  MGPlan mgQ, mgQH;
+  std::vector<OpCoef> cpsi_h, cpsih_h;
+  OpCoef *cpsi = nullptr, *cpsih = nullptr, *cscal = nullptr;   // cscal: [tau M, tau/beta M, M]
+  std::vector<double2> dj_h;
+  double2 *dj = nullptr, *abO = nullptr;
+  OpCoef cscal_h[3];
+  double2 abO_h;
+  void *B1 = nullptr, *B2 = nullptr, *X1 = nullptr, *X2 = nullptr, *T1 = nullptr, *T2 = nullptr, *Rb = nullptr;
+  void *C1 = nullptr, *C2 = nullptr, *Pt = nullptr, *Ub = nullptr;
   Probe probe;
   // inner statistics
   long inner_its_sum = 0, inner_blocks = 0;
@@ -257,7 +276,26 @@ static void carve(pintoc_problem* p, char* base) {
     p->ydev = cv.take<double2>(sizeof(double2) * (mi + 1) * nf);
     p->fpart = cv.take<double2>(sizeof(double2) * fdot_part_entries(p->segV, p->segP, nf));
   }
-  plan_mg_buffers(p->mgW, cv, p->csize);
+  p->bc = cv.take<BlockCoef>(sizeof(BlockCoef) * nf);
+  if (p->d.flow == PINTOC_OSEEN) {
+    p->conv2.assign(p->conv2_h.size(), nullptr);
+    for (size_t l = 0; l < p->conv2_h.size(); ++l) p->conv2[l] = cv.take<double>(sizeof(double) * p->conv2_h[l].size());
+    p->conv1 = cv.take<double>(sizeof(double) * p->conv1_h.size());
+    p->cpsi = cv.take<OpCoef>(sizeof(OpCoef) * nf);
+    p->cpsih = cv.take<OpCoef>(sizeof(OpCoef) * nf);
+    p->cscal = cv.take<OpCoef>(sizeof(OpCoef) * 3);
+    p->dj = cv.take<double2>(sizeof(double2) * nf);
+    p->abO = cv.take<double2>(sizeof(double2));
+    const size_t hb = (size_t)2 * nf * p->nq2 * p->csize;    // one velocity block: [j][comp]
+    for (void** q : {&p->B1, &p->B2, &p->X1, &p->X2, &p->T1, &p->T2, &p->Rb, &p->C1, &p->C2}) *q = cv.take<char>(hb);
+    p->Pt = cv.take<char>(pbytes);
+    p->Ub = cv.take<char>(pbytes);
+    for (size_t l = 0; l < p->conv2.size(); ++l) { p->mgQ.conv[l] = p->conv2[l]; p->mgQH.conv[l] = p->conv2[l]; }
+    plan_mg_buffers(p->mgQ, cv, p->csize);
+    plan_mg_buffers(p->mgQH, cv, p->csize);
+  } else {
+    plan_mg_buffers(p->mgW, cv, p->csize);
+  }
   plan_mg_buffers(p->mgK, cv, p->csize);
   const int m = p->o.restart;
   const size_t vb = sizeof(double) * (size_t)p->n_all;
@@ -269,6 +307,78 @@ static void carve(pintoc_problem* p, char* base) {
   p->dd2 = cv.take<double>(sizeof(double) * 64);
   p->part = cv.take<double>(sizeof(double) * 8 * 1024);
   p->need = cv.off;
+}
+
+// ------------------------------------------------------------ convection
+// Element-by-element assembly (3x3 Gauss per element) of the convection
+// matrices N[i][j] = int (w . grad phi_j) phi_i (Q2) and the same with the Q1
+// basis, w the Q2 nodal interpolant of the wind, stored as node-centred
+// stencil tables: Q2 50 values per node (25 offsets of N, 25 of N^T), Q1 18.
+static void p2_1d(double s, double v[3], double d[3]) {
+  v[0] = (1 - s) * (1 - 2 * s); v[1] = 4 * s * (1 - s); v[2] = s * (2 * s - 1);
+  d[0] = 4 * s - 3; d[1] = 4 - 8 * s; d[2] = 4 * s - 1;
+}
+
+static void conv_tables(int n, const double* wx, const double* wy, std::vector<double>& t2, std::vector<double>* t1) {
+  const int nq = 2 * n + 1, np = n + 1;
+  const double h = 1.0 / n;
+  const double g[3] = {0.5 - std::sqrt(15.0) / 10.0, 0.5, 0.5 + std::sqrt(15.0) / 10.0};
+  const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  t2.assign((size_t)nq * nq * 50, 0.0);
+  if (t1) t1->assign((size_t)np * np * 18, 0.0);
+  for (int ey = 0; ey < n; ++ey)
+    for (int ex = 0; ex < n; ++ex) {
+      double Ne[9][9] = {}, Np[4][4] = {};
+      for (int qy = 0; qy < 3; ++qy)
+        for (int qx = 0; qx < 3; ++qx) {
+          double vx[3], dx[3], vy[3], dy[3];
+          p2_1d(g[qx], vx, dx);
+          p2_1d(g[qy], vy, dy);
+          const double lx[2] = {1 - g[qx], g[qx]}, ly[2] = {1 - g[qy], g[qy]};
+          double phi[9], phx[9], phy[9];
+          double wxq = 0, wyq = 0;
+          for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+              const int l = 3 * b + a;
+              phi[l] = vx[a] * vy[b];
+              phx[l] = dx[a] / h * vy[b];
+              phy[l] = vx[a] * dy[b] / h;
+              const int node = (2 * ey + b) * nq + 2 * ex + a;
+              wxq += wx[node] * phi[l];
+              wyq += wy[node] * phi[l];
+            }
+          const double wt = gw[qx] * gw[qy] * h * h;
+          for (int a = 0; a < 9; ++a)
+            for (int b = 0; b < 9; ++b) Ne[a][b] += wt * phi[a] * (wxq * phx[b] + wyq * phy[b]);
+          if (t1) {
+            double psi[4], psx[4], psy[4];
+            for (int b = 0; b < 2; ++b)
+              for (int a = 0; a < 2; ++a) {
+                const int l = 2 * b + a;
+                psi[l] = lx[a] * ly[b];
+                psx[l] = (a ? 1.0 : -1.0) / h * ly[b];
+                psy[l] = lx[a] * (b ? 1.0 : -1.0) / h;
+              }
+            for (int a = 0; a < 4; ++a)
+              for (int b = 0; b < 4; ++b) Np[a][b] += wt * psi[a] * (wxq * psx[b] + wyq * psy[b]);
+          }
+        }
+      for (int a = 0; a < 9; ++a)
+        for (int b = 0; b < 9; ++b) {
+          const int ix = 2 * ex + a % 3, iy = 2 * ey + a / 3, jx = 2 * ex + b % 3, jy = 2 * ey + b / 3;
+          const int ox = jx - ix, oy = jy - iy;
+          t2[(size_t)(iy * nq + ix) * 50 + (oy + 2) * 5 + ox + 2] += Ne[a][b];
+          t2[(size_t)(jy * nq + jx) * 50 + 25 + (-oy + 2) * 5 + (-ox + 2)] += Ne[a][b];
+        }
+      if (t1)
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b) {
+            const int ix = ex + a % 2, iy = ey + a / 2, jx = ex + b % 2, jy = ey + b / 2;
+            const int ox = jx - ix, oy = jy - iy;
+            (*t1)[(size_t)(iy * np + ix) * 18 + (oy + 1) * 3 + ox + 1] += Np[a][b];
+            (*t1)[(size_t)(jy * np + jx) * 18 + 9 + (-oy + 1) * 3 + (-ox + 1)] += Np[a][b];
+          }
+    }
 }
 
 // ------------------------------------------------------------ public: options
@@ -299,7 +409,7 @@ extern "C" int pintoc_profile_enable(pintoc_problem* p, int32_t enable) {
     if (p->probe.create() != PINTOC_OK) return fail(PINTOC_EHIP, "hipEventCreate failed");
     p->probe.count = 0;
     p->probe.on = true;
-    p->mgW.probe = &p->probe;
+    (p->d.flow == PINTOC_OSEEN ? p->mgQ : p->mgW).probe = &p->probe;
   } else {
     p->probe.on = false;
   }
@@ -319,7 +429,8 @@ extern "C" int pintoc_profile_read(pintoc_problem* p, pintoc_kernel_timing* out)
   }
   out->avg_ms = sum / n;
   out->launches = n;
-  out->algorithmic_bytes = 3.0 * (double)p->mgW.nodes(0) * p->mgW.nb * (double)p->csize;
+  const MGPlan& m = p->d.flow == PINTOC_OSEEN ? p->mgQ : p->mgW;
+  out->algorithmic_bytes = 3.0 * (double)m.nodes(0) * m.nb * (double)p->csize;
   return PINTOC_OK;
 }
 
@@ -345,7 +456,7 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   if (d->nt < 2 || !pow2(d->nt) || d->nt > 1024) return fail(PINTOC_EINVAL, "nt must be a power of two in [2, 1024]");
   if (!(d->T > 0) || !(d->nu > 0) || !(d->beta > 0)) return fail(PINTOC_EINVAL, "T, nu and beta must be > 0");
   if (d->flow != PINTOC_STOKES && d->flow != PINTOC_OSEEN) return fail(PINTOC_EINVAL, "unknown flow");
-  if (d->flow == PINTOC_OSEEN) return fail(PINTOC_EINVAL, "Oseen flow is not available in this build");
+  if (d->flow == PINTOC_OSEEN && !d->wind) return fail(PINTOC_EINVAL, "Oseen flow needs a wind");
   if (opt.inner != PINTOC_INNER_LINEAR && opt.inner != PINTOC_INNER_GMRES) return fail(PINTOC_EINVAL, "unknown inner mode");
   if (opt.inner == PINTOC_INNER_GMRES &&
       (opt.inner_restart < 1 || opt.inner_restart > 100 || opt.inner_maxit < 1 || !(opt.inner_tol > 0)))
@@ -377,28 +488,72 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   // per-frequency constants (section 3.1-3.2): d_j = 1 - exp(-2 pi i j/nt),
   // c2 = (1/beta + d_c^2/tau^2)^{-1/2},  c1 = d_r / sqrt(tau^2/beta + d_c^2)
   const double tau = p->tau, beta = d->beta, nu = d->nu;
+  const bool oseen = d->flow == PINTOC_OSEEN;
+  int nl = 0;
+  for (int n = N; n >= 2; n >>= 1) ++nl;
+  if (oseen) {
+    // wind on every level by injection of the finest nodal values
+    const int nq = 2 * N + 1;
+    std::vector<double> wx(d->wind, d->wind + (size_t)nq * nq), wy(d->wind + (size_t)nq * nq, d->wind + 2 * (size_t)nq * nq);
+    p->conv2_h.resize(nl);
+    for (int l = 0; l < nl; ++l) {
+      const int n = N >> l, nql = 2 * n + 1, st = 1 << l;
+      std::vector<double> lx((size_t)nql * nql), ly((size_t)nql * nql);
+      for (int iy = 0; iy < nql; ++iy)
+        for (int ix = 0; ix < nql; ++ix) {
+          lx[(size_t)iy * nql + ix] = wx[(size_t)(iy * st) * nq + ix * st];
+          ly[(size_t)iy * nql + ix] = wy[(size_t)(iy * st) * nq + ix * st];
+        }
+      conv_tables(n, lx.data(), ly.data(), p->conv2_h[l], l == 0 ? &p->conv1_h : nullptr);
+    }
+  }
   MGPlan& W = p->mgW;
   W.q2 = true; W.N = N; W.nb = 4 * p->nf; W.fpc = 4; W.ncoef = p->nf;
+  const double sb = std::sqrt(beta);
   for (int j = 0; j < p->nf; ++j) {
     const double th = 2.0 * M_PI * j / nt;
     const double dr = 1.0 - std::cos(th), dc = std::sin(th);
+    const cd dj(dr, dc), djc(dr, -dc);
     const double c2 = 1.0 / std::sqrt(1.0 / beta + dc * dc / (tau * tau));
     const double c1 = dr / std::sqrt(tau * tau / beta + dc * dc);
     p->tj_h.push_back(make_double2(dc, c2));
     p->ab_h.push_back(make_double2(1.0 + c1, nu * c2));
     p->cj_h.push_back(make_double2(c1, c2 * nu));          // X = c1 M + c2 L, L = nu K
     W.coef_h.push_back(mkcoef(1.0 + c1, nu * c2));        // W_j = (1 + c1) M + c2 nu K
+    BlockCoef bc{};
+    auto c2d = [](cd v) { return make_double2(v.real(), v.imag()); };
+    if (!oseen) {          // Z_j = [[M, X, 0, B^T], [X, -M, B^T, 0], [0, B, 0, 0], [B, 0, 0, 0]]
+      bc.a11 = c2d(1.0); bc.a12 = c2d(c1); bc.b12 = c2d(c2 * nu); bc.e12 = c2d(0.0);
+      bc.a21 = c2d(c1); bc.b21 = c2d(c2 * nu); bc.e21 = c2d(0.0); bc.a22 = c2d(-1.0); bc.s = 1.0;
+    } else {               // G_j of eq. (SubBlockG)
+      bc.a11 = c2d(tau); bc.a12 = c2d(djc); bc.b12 = c2d(tau * nu); bc.e12 = c2d(tau);
+      bc.a21 = c2d(dj); bc.b21 = c2d(tau * nu); bc.e21 = c2d(tau); bc.a22 = c2d(-tau / beta); bc.s = tau;
+      // Psi = d M + tau L, Psi^H = conj(d) M + tau L^T (L = nu K + N);
+      // Q_j = Psi + tau/sqrt(beta) M, Q_j^H = Psi^H + tau/sqrt(beta) M
+      p->cpsi_h.push_back(mkcoef(dj, tau * nu, tau, 0.0));
+      p->cpsih_h.push_back(mkcoef(djc, tau * nu, 0.0, tau));
+      p->mgQ.coef_h.push_back(mkcoef(dj + tau / sb, tau * nu, tau, 0.0));
+      p->mgQH.coef_h.push_back(mkcoef(djc + tau / sb, tau * nu, 0.0, tau));
+      p->dj_h.push_back(make_double2(dr, dc));
+    }
+    p->bc_h.push_back(bc);
   }
+  p->block_scale = oseen ? tau : 1.0;
   MGPlan& K = p->mgK;
   K.q2 = false; K.N = N; K.nb = 2 * p->nf; K.fpc = 2 * p->nf; K.ncoef = 1;
   K.coef_h.push_back(mkcoef(0.0, 1.0));                   // unconstrained pressure Laplacian
-  for (MGPlan* m : {&W, &K}) {
-    int nl = 0;
-    for (int n = N; n >= 2; n >>= 1) ++nl;
+  for (MGPlan* m : {&p->mgQ, &p->mgQH}) {
+    m->q2 = true; m->N = N; m->nb = 2 * p->nf; m->fpc = 2; m->ncoef = p->nf;
+  }
+  std::vector<MGPlan*> plans = {&K};
+  if (oseen) { plans.push_back(&p->mgQ); plans.push_back(&p->mgQH); }
+  else plans.push_back(&W);
+  for (MGPlan* m : plans) {
     m->nlev = nl;
     m->conv.assign(nl, nullptr);
+    const std::vector<double>* cc = (oseen && m->q2) ? &p->conv2_h[nl - 1] : nullptr;
     for (const OpCoef& c : m->coef_h)
-      if (!coarse_inverse(m->q2, c, nullptr, m->inv_h)) { delete p; return fail(PINTOC_EINVAL, "singular coarse operator"); }
+      if (!coarse_inverse(m->q2, c, cc, m->inv_h)) { delete p; return fail(PINTOC_EINVAL, "singular coarse operator"); }
   }
   carve(p, nullptr);
   *out = p;
@@ -423,9 +578,27 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
   HIPCHK(hipMemcpyAsync(p->tj, p->tj_h.data(), sizeof(double2) * p->tj_h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->ab, p->ab_h.data(), sizeof(double2) * p->ab_h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->cj, p->cj_h.data(), sizeof(double2) * p->cj_h.size(), hipMemcpyHostToDevice, s));
-  for (MGPlan* m : {&p->mgW, &p->mgK}) {
+  HIPCHK(hipMemcpyAsync(p->bc, p->bc_h.data(), sizeof(BlockCoef) * p->bc_h.size(), hipMemcpyHostToDevice, s));
+  for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) {
+    if (m->nlev == 0 || !m->coef) continue;
     HIPCHK(hipMemcpyAsync(m->coef, m->coef_h.data(), sizeof(OpCoef) * m->coef_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(m->inv, m->inv_h.data(), sizeof(double2) * m->inv_h.size(), hipMemcpyHostToDevice, s));
+  }
+  if (p->d.flow == PINTOC_OSEEN) {
+    for (size_t l = 0; l < p->conv2.size(); ++l)
+      HIPCHK(hipMemcpyAsync(p->conv2[l], p->conv2_h[l].data(), sizeof(double) * p->conv2_h[l].size(),
+                            hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->conv1, p->conv1_h.data(), sizeof(double) * p->conv1_h.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->cpsi, p->cpsi_h.data(), sizeof(OpCoef) * p->cpsi_h.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->cpsih, p->cpsih_h.data(), sizeof(OpCoef) * p->cpsih_h.size(), hipMemcpyHostToDevice, s));
+    const double tau = p->tau;
+    p->cscal_h[0] = mkcoef(tau, 0.0);
+    p->cscal_h[1] = mkcoef(tau / p->d.beta, 0.0);
+    p->cscal_h[2] = mkcoef(1.0, 0.0);
+    HIPCHK(hipMemcpyAsync(p->cscal, p->cscal_h, sizeof(p->cscal_h), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->dj, p->dj_h.data(), sizeof(double2) * p->dj_h.size(), hipMemcpyHostToDevice, s));
+    p->abO_h = make_double2(-1.0 / (tau * tau), 0.0);
+    HIPCHK(hipMemcpyAsync(p->abO, &p->abO_h, sizeof(double2), hipMemcpyHostToDevice, s));
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -506,6 +679,69 @@ static void ptilde(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cp
   launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, ym, p->ab, 2, p->np2, 2 * nf);
 }
 
+// P~_j^(UZ)^{-1} of Algorithm 3 (Oseen) on a frequency vector, all kept
+// frequencies at once.  (y1, y2) = k steps of eq. (Uzawa11) from zero on
+// G_j^(1,1) with M^^{-1} = Chebyshev(M) and S^^{-1} = tau Q_j^{-H} M Q_j^{-1};
+// (y3, y4) = -S^_j^{-1}((r3, r4) - tau (B y2, B y1)) with the commutator
+// approximation carried onto the pinned pressure space.  in and out must not alias.
+template <typename R>
+static void puz(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP, cpx<R>* outV,
+                cpx<R>* outP) {
+  const int nf = p->nf, N = p->d.N, cyc = p->o.n_vcycles;
+  const double tau = p->tau, h = 1.0 / N;
+  const size_t nh = (size_t)2 * nf * p->nq2;                  // complex entries of one velocity block
+  cpx<R>*B1 = (cpx<R>*)p->B1, *B2 = (cpx<R>*)p->B2, *X1 = (cpx<R>*)p->X1, *X2 = (cpx<R>*)p->X2;
+  cpx<R>*T1 = (cpx<R>*)p->T1, *T2 = (cpx<R>*)p->T2, *Rb = (cpx<R>*)p->Rb;
+  launch_block_copy<R>(s, (cpx<R>*)inV, B1, N, nf, 0, 0);
+  launch_block_copy<R>(s, (cpx<R>*)inV, B2, N, nf, 1, 0);
+  launch_fill_zero(s, X1, nh * sizeof(cpx<R>));
+  launch_fill_zero(s, X2, nh * sizeof(cpx<R>));
+  const double* cv = p->conv2[0];
+  for (int k = 0; k < p->o.n_uzawa; ++k) {
+    // x1 += tau^{-1} M^^{-1} (b1 - tau M x1 - Psi^H x2)
+    launch_apply<R>(s, true, T1, X1, N, h, p->cscal + 0, 2 * nf, 2 * nf, nullptr);
+    launch_apply<R>(s, true, T2, X2, N, h, p->cpsih, 2, 2 * nf, cv);
+    launch_combine3<R>(s, Rb, B1, T1, T2, 1.0, -1.0, -1.0, nh);
+    cpx<R>* c = chebyshev<R>(s, true, N, 2 * nf, (cpx<R>*)p->C1, (cpx<R>*)p->C2, Rb, p->o.n_cheb, 0.25, 25.0 / 16.0);
+    launch_combine3<R>(s, X1, X1, c, nullptr, 1.0, 1.0 / tau, 0.0, nh);
+    // x2 -= mu^{-1} S^^{-1} (b2 - Psi x1 + tau/beta M x2)
+    launch_apply<R>(s, true, T1, X1, N, h, p->cpsi, 2, 2 * nf, cv);
+    launch_apply<R>(s, true, T2, X2, N, h, p->cscal + 1, 2 * nf, 2 * nf, nullptr);
+    launch_combine3<R>(s, Rb, B2, T1, T2, 1.0, -1.0, 1.0, nh);
+    mg_solve<R>(s, p->mgQ, T1, Rb, cyc);                                   // Q_j^{-1}
+    launch_apply<R>(s, true, T2, T1, N, h, p->cscal + 2, 2 * nf, 2 * nf, nullptr);   // M
+    mg_solve<R>(s, p->mgQH, T1, T2, cyc);                                  // Q_j^{-H}
+    launch_combine3<R>(s, X2, X2, T1, nullptr, 1.0, -tau / p->o.mu_uzawa, 0.0, nh);
+  }
+  launch_block_copy<R>(s, outV, X1, N, nf, 0, 1);
+  launch_block_copy<R>(s, outV, X2, N, nf, 1, 1);
+  // Schur step on the pressure fields
+  cpx<R>*Pt = (cpx<R>*)p->Pt, *Ub = (cpx<R>*)p->Ub, *z = (cpx<R>*)p->Ptmp;
+  launch_schur_rhs<R>(s, Pt, inP, X1, X2, N, nf, tau);            // (r3 - tau B y2, r4 - tau B y1)
+  launch_unpin_copy<R>(s, z, Pt, p->np2, 2 * nf);
+  cpx<R>* zz = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25);
+  launch_oseen_hp<R>(s, Ub, zz, N, nf, p->dj, tau, p->d.beta, p->d.nu, p->conv1);
+  launch_unpin_copy<R>(s, z, Ub, p->np2, 2 * nf);
+  mg_solve<R>(s, p->mgK, (cpx<R>*)p->PxK, z, cyc);
+  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, (cpx<R>*)p->PxK, p->abO, 2 * nf, p->np2, 2 * nf);
+}
+
+// block preconditioner of the flow: P~_j (Stokes) or P~_j^(UZ) (Oseen)
+template <typename R>
+static void block_precond(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP, cpx<R>* outV,
+                          cpx<R>* outP) {
+  if (p->d.flow == PINTOC_OSEEN) puz<R>(p, s, inV, inP, outV, outP);
+  else ptilde<R>(p, s, inV, inP, outV, outP);
+}
+
+// block matrix of the flow: Z_j (Stokes) or G_j (Oseen)
+template <typename R>
+static void block_matvec(pintoc_problem* p, hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV,
+                         const cpx<R>* xP) {
+  launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, p->d.flow == PINTOC_OSEEN ? p->conv2[0] : nullptr,
+                      p->block_scale);
+}
+
 // complex Givens rotation (c real) with [c, s; -conj(s), c] [a; b] = [r; 0]
 static void givens(cd a, cd b, double& c, cd& sn) {
   if (b == 0.0) { c = 1.0; sn = 0.0; return; }
@@ -573,8 +809,8 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     }
     int k = 0;
     for (; k < m && total < p->o.inner_maxit; ++k) {
-      ptilde<R>(p, s, BVk(k), BPk(k), ZV, ZP);
-      launch_zmat_stokes<R>(s, BVk(k + 1), BPk(k + 1), ZV, ZP, N, nf, p->cj);
+      block_precond<R>(p, s, BVk(k), BPk(k), ZV, ZP);
+      block_matvec<R>(p, s, BVk(k + 1), BPk(k + 1), ZV, ZP);
       launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->hdev);
       launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->hdev, segV, segP, nf, 1.0);
       launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->h2dev);
@@ -638,7 +874,7 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     launch_fill_zero(s, UV, (size_t)segV * nf * sizeof(cpx<R>));
     launch_fill_zero(s, UP, (size_t)segP * nf * sizeof(cpx<R>));
     launch_fupdate<R>(s, UV, UP, BV, BP, ldV, ldP, k, p->ydev, segV, segP, nf, -1.0);
-    ptilde<R>(p, s, UV, UP, ZV, ZP);
+    block_precond<R>(p, s, UV, UP, ZV, ZP);
     for (int j = 0; j < nf; ++j) scl[j] = make_double2(1.0, 0.0);
     if ((rc = upload(p->hdev, scl, 1))) return rc;
     launch_fupdate<R>(s, XV, XP, ZV, ZP, 0, 0, 1, p->hdev, segV, segP, nf, -1.0);      // X += P~^{-1} U
@@ -646,7 +882,7 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     for (int j = 0; j < nf; ++j) any_left |= !done[j];
     if (!any_left || total >= p->o.inner_maxit) break;
     // restart: r = s - Z x for the frequencies still running
-    launch_zmat_stokes<R>(s, UV, UP, XV, XP, N, nf, p->cj);
+    block_matvec<R>(p, s, UV, UP, XV, XP);
     for (int j = 0; j < nf; ++j) scl[j] = make_double2(-1.0, 0.0);
     if ((rc = upload(p->hdev, scl, 1))) return rc;
     launch_fscale<R>(s, UV, UP, UV, UP, p->hdev, segV, segP, nf);
@@ -667,24 +903,27 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
   return PINTOC_OK;
 }
 
-// Algorithm 1 (linear) or Algorithm 2 (GMRES per frequency), Stokes:
-// FFT + T_l^{-1}, block solves, T_r^{-1} + inverse FFT.
+// The block-circulant preconditioner: FFT in time (+ T_l^{-1} for Stokes),
+// per-frequency block solves (one application of P~_j / P~_j^(UZ), or GMRES
+// to the inner tolerance), (T_r^{-1} +) inverse FFT.  Stokes: Algorithms 1
+// and 2; Oseen: Algorithm 3 and its GMRES wrapper (section 4).
 template <typename R>
-static int precond_stokes(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
+static int precond_apply_t(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
   cpx<R>*Vb = (cpx<R>*)p->Vb, *Vx = (cpx<R>*)p->Vx, *Pb = (cpx<R>*)p->Pb, *Px = (cpx<R>*)p->Px;
-  launch_time_fft_fwd<R>(s, r, Vb, Pb, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, 1);
+  const int mode = p->d.flow == PINTOC_STOKES ? 1 : 0;
+  launch_time_fft_fwd<R>(s, r, Vb, Pb, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, mode);
   if (p->o.inner == PINTOC_INNER_LINEAR) {
-    ptilde<R>(p, s, Vb, Pb, Vx, Px);
+    block_precond<R>(p, s, Vb, Pb, Vx, Px);
   } else {
     int rc = gmres_blocks<R>(p, s);
     if (rc) return rc;
   }
-  launch_time_fft_inv<R>(s, Vx, Px, z, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, 1);
+  launch_time_fft_inv<R>(s, Vx, Px, z, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, mode);
   return PINTOC_OK;
 }
 
 static int precond(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
-  int rc = p->o.precision == PINTOC_PREC_FP64 ? precond_stokes<double>(p, r, z, s) : precond_stokes<float>(p, r, z, s);
+  int rc = p->o.precision == PINTOC_PREC_FP64 ? precond_apply_t<double>(p, r, z, s) : precond_apply_t<float>(p, r, z, s);
   if (rc) return rc;
   p->precond_apps++;
   HIPCHK(hipGetLastError());
@@ -708,7 +947,8 @@ extern "C" int pintoc_assemble_rhs(pintoc_problem* p, const double* vd, double* 
 }
 
 static void kkt(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
-  launch_kkt_apply(s, x, y, p->d.N, p->d.nt, p->tau, p->d.beta, p->d.nu, nullptr);
+  launch_kkt_apply(s, x, y, p->d.N, p->d.nt, p->tau, p->d.beta, p->d.nu,
+                   p->d.flow == PINTOC_OSEEN ? p->conv2[0] : nullptr);
 }
 
 extern "C" int pintoc_kkt_apply(pintoc_problem* p, const double* x, double* y, void* stream) {
