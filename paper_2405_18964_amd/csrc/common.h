@@ -127,6 +127,15 @@ struct BlockCoef {
   double s, pad;
 };
 
+// Per-frequency activity mask of a batched launch: grid f of the batch belongs
+// to frequency f / fpj; a frequency whose entry is 0 is skipped (its blocks
+// return at once).  m == nullptr: every grid is active.
+struct Mask {
+  const int* m;
+  int fpj;
+  __device__ bool off(int f) const { return m != nullptr && m[f / fpj] == 0; }
+};
+
 inline __host__ __device__ int q2n(int n) { return 2 * n + 1; }
 inline __host__ __device__ int q1n(int n) { return n + 1; }
 

@@ -12,118 +12,6 @@
 
 namespace pintoc {
 
-// ------------------------------------------------------------ Z_j x (Stokes)
-// Z_j = [[M, X, 0, B^T], [X, -M, B^T, 0], [0, B, 0, 0], [B, 0, 0, 0]],
-// X = c1 M + c2 L, L = nu K.  cj[j] = (c1, c2 nu).
-template <typename R>
-__global__ __launch_bounds__(256) void k_zmat_vel(cpx<R>* __restrict__ yV, const cpx<R>* __restrict__ xV, const cpx<R>* __restrict__ xP,
-                           int n, const double2* __restrict__ cj) {
-  const int nq = 2 * n + 1, nq2 = nq * nq, np2 = (n + 1) * (n + 1);
-  const int node = blockIdx.x * blockDim.x + threadIdx.x;
-  const int jbc = blockIdx.y;                  // (j * 2 + b) * 2 + comp
-  if (node >= nq2) return;
-  const int comp = jbc & 1, b = (jbc >> 1) & 1, j = jbc >> 2;
-  const size_t o = (size_t)jbc * nq2 + node;
-  const int ix = node % nq, iy = node / nq;
-  if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) { yV[o] = cmk<cpx<R>>(0, 0); return; }
-  const double h = 1.0 / n;
-  double mx[5], kx[5], my[5], ky[5];
-  q2_rows(ix, h, mx, kx);
-  q2_rows(iy, h, my, ky);
-  int cx[5], ry[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    cx[d] = min(max(ix + d - 2, 0), nq - 1);
-    ry[d] = min(max(iy + d - 2, 0), nq - 1) * nq;
-  }
-  const cpx<R>* v = xV + ((size_t)(j * 2 + 0) * 2 + comp) * nq2;
-  const cpx<R>* l = xV + ((size_t)(j * 2 + 1) * 2 + comp) * nq2;
-  double Mv[2] = {0, 0}, Kv[2] = {0, 0}, Ml[2] = {0, 0}, Kl[2] = {0, 0};
-#pragma unroll
-  for (int dy = 0; dy < 5; ++dy) {
-    double smv[2] = {0, 0}, skv[2] = {0, 0}, sml[2] = {0, 0}, skl[2] = {0, 0};
-#pragma unroll
-    for (int dx = 0; dx < 5; ++dx) {
-      const cpx<R> a = v[ry[dy] + cx[dx]], c = l[ry[dy] + cx[dx]];
-      smv[0] += mx[dx] * (double)a.x; smv[1] += mx[dx] * (double)a.y;
-      skv[0] += kx[dx] * (double)a.x; skv[1] += kx[dx] * (double)a.y;
-      sml[0] += mx[dx] * (double)c.x; sml[1] += mx[dx] * (double)c.y;
-      skl[0] += kx[dx] * (double)c.x; skl[1] += kx[dx] * (double)c.y;
-    }
-    for (int q = 0; q < 2; ++q) {
-      Mv[q] += my[dy] * smv[q]; Kv[q] += ky[dy] * smv[q] + my[dy] * skv[q];
-      Ml[q] += my[dy] * sml[q]; Kl[q] += ky[dy] * sml[q] + my[dy] * skl[q];
-    }
-  }
-  // B^T of the pressure field of the other block: row 1 uses mu, row 2 uses p
-  const cpx<R>* q = xP + (size_t)(j * 2 + (b == 0 ? 1 : 0)) * np2;
-  double mxx[3], gxx[3], mxy[3], gxy[3];
-  mixed_cols(ix, n, h, mxx, gxx);
-  mixed_cols(iy, n, h, mxy, gxy);
-  const int kx0 = (ix >> 1) - 1, ky0 = (iy >> 1) - 1, np = n + 1;
-  double bt[2] = {0, 0};
-  for (int a = 0; a < 3; ++a) {
-    const int kyy = ky0 + a;
-    if (kyy < 0 || kyy > n) continue;
-    const double wy = comp == 0 ? mxy[a] : gxy[a];
-    for (int c = 0; c < 3; ++c) {
-      const int kxx = kx0 + c;
-      if (kxx < 0 || kxx > n) continue;
-      const double wgt = wy * (comp == 0 ? gxx[c] : mxx[c]);
-      const cpx<R> pv = q[kyy * np + kxx];
-      bt[0] -= wgt * (double)pv.x; bt[1] -= wgt * (double)pv.y;
-    }
-  }
-  const double c1 = cj[j].x, c2n = cj[j].y;
-  double out[2];
-  for (int qq = 0; qq < 2; ++qq) {
-    const double Xv = c1 * Mv[qq] + c2n * Kv[qq], Xl = c1 * Ml[qq] + c2n * Kl[qq];
-    out[qq] = (b == 0 ? Mv[qq] + Xl : Xv - Ml[qq]) + bt[qq];
-  }
-  yV[o] = cmk<cpx<R>>(out[0], out[1]);
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_zmat_pres(cpx<R>* __restrict__ yP, const cpx<R>* __restrict__ xV, int n) {
-  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int jb = blockIdx.y;                   // j * 2 + b
-  if (k >= np2) return;
-  const int b = jb & 1, j = jb >> 1;
-  const size_t o = (size_t)jb * np2 + k;
-  if (k == 0) { yP[o] = cmk<cpx<R>>(0, 0); return; }
-  // row 3 (b = 0): B lambda;  row 4 (b = 1): B v
-  const cpx<R>* ux = xV + ((size_t)(j * 2 + (b == 0 ? 1 : 0)) * 2 + 0) * nq2;
-  const cpx<R>* uy = ux + nq2;
-  const double h = 1.0 / n;
-  const int kx = k % np, ky = k / np;
-  double mxx[5], gxx[5], mxy[5], gxy[5];
-  mixed_rows(kx, n, h, mxx, gxx);
-  mixed_rows(ky, n, h, mxy, gxy);
-  double sr = 0, si = 0;
-  for (int dy = 0; dy < 5; ++dy) {
-    const int jy = 2 * ky + dy - 2;
-    if (jy < 0 || jy >= nq) continue;
-    for (int dx = 0; dx < 5; ++dx) {
-      const int jx = 2 * kx + dx - 2;
-      if (jx < 0 || jx >= nq) continue;
-      const double wa = mxy[dy] * gxx[dx], wb = gxy[dy] * mxx[dx];
-      const cpx<R> a = ux[jy * nq + jx], c = uy[jy * nq + jx];
-      sr += wa * (double)a.x + wb * (double)c.x;
-      si += wa * (double)a.y + wb * (double)c.y;
-    }
-  }
-  yP[o] = cmk<cpx<R>>(-sr, -si);
-}
-
-template <typename R>
-void launch_zmat_stokes(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                        const double2* cj) {
-  const int nq2 = (2 * n + 1) * (2 * n + 1), np2 = (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_zmat_vel<R>, dim3((nq2 + 255) / 256, 4 * nf), dim3(256), 0, s, yV, xV, xP, n, cj);
-  hipLaunchKernelGGL(k_zmat_pres<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, yP, xV, n);
-}
-
 // ------------------------------------------------------ per-frequency BLAS
 // Geometry of a frequency vector: per frequency segV complex entries in the V
 // part and segP in the P part; basis vector i starts at i*ldV / i*ldP.
@@ -133,9 +21,10 @@ constexpr int kFK = 16;         // basis vectors per dot pass
 template <typename R>
 __global__ __launch_bounds__(256) void k_fdot(const cpx<R>* __restrict__ bV, const cpx<R>* __restrict__ bP, size_t ldV, size_t ldP, int k,
                        const cpx<R>* __restrict__ wV, const cpx<R>* __restrict__ wP, int segV, int segP, int chV,
-                       int nch, int nf, double2* __restrict__ part) {
+                       int nch, int nf, double2* __restrict__ part, Mask mk) {
   __shared__ double red[2][256];
   const int j = blockIdx.y, c = blockIdx.x;
+  if (mk.off(j)) return;
   const bool inV = c < chV;
   const int seg = inV ? segV : segP;
   const int cc = inV ? c : c - chV;
@@ -187,8 +76,9 @@ __global__ __launch_bounds__(256) void k_fdot_reduce(const double2* __restrict__
 template <typename R>
 __global__ __launch_bounds__(256) void k_fupdate(cpx<R>* __restrict__ wV, cpx<R>* __restrict__ wP, const cpx<R>* __restrict__ bV,
                           const cpx<R>* __restrict__ bP, size_t ldV, size_t ldP, int k, const double2* __restrict__ c,
-                          int segV, int segP, int nf, double sign) {
+                          int segV, int segP, int nf, double sign, Mask mk) {
   const int j = blockIdx.y;
+  if (mk.off(j)) return;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool inV = e < (size_t)segV;
   if (!inV && e >= (size_t)segV + segP) return;
@@ -210,8 +100,9 @@ __global__ __launch_bounds__(256) void k_fupdate(cpx<R>* __restrict__ wV, cpx<R>
 // y^j = a[j] x^j   (a complex per frequency; y may alias x)
 template <typename R>
 __global__ __launch_bounds__(256) void k_fscale(cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, const double2* __restrict__ a,
-                         int segV, int segP) {
+                         int segV, int segP, Mask mk) {
   const int j = blockIdx.y;
+  if (mk.off(j)) return;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool inV = e < (size_t)segV;
   if (!inV && e >= (size_t)segV + segP) return;
@@ -224,9 +115,10 @@ __global__ __launch_bounds__(256) void k_fscale(cpx<R>* yV, cpx<R>* yP, const cp
 
 // unpinned copy of the pressure fields: dst = src with dst[f][0] = -sum_{i>=1} src[f][i]
 template <typename R>
-__global__ __launch_bounds__(256) void k_unpin_copy(cpx<R>* __restrict__ dst, const cpx<R>* __restrict__ src, int nn) {
+__global__ __launch_bounds__(256) void k_unpin_copy(cpx<R>* __restrict__ dst, const cpx<R>* __restrict__ src, int nn, Mask mk) {
   __shared__ double sr[256], si[256];
   const int f = blockIdx.x;
+  if (mk.off(f)) return;
   const cpx<R>* g = src + (size_t)f * nn;
   cpx<R>* d = dst + (size_t)f * nn;
   double ar = 0, ai = 0;
@@ -255,12 +147,12 @@ __global__ __launch_bounds__(256) void k_convert(cpx<Rd>* __restrict__ d, const 
 
 template <typename R>
 void launch_fdot(hipStream_t s, const cpx<R>* bV, const cpx<R>* bP, size_t ldV, size_t ldP, int k, const cpx<R>* wV,
-                 const cpx<R>* wP, int segV, int segP, int nf, double2* part, double2* out) {
+                 const cpx<R>* wP, int segV, int segP, int nf, double2* part, double2* out, Mask mk) {
   const int chV = (segV + kFChunk - 1) / kFChunk, chP = (segP + kFChunk - 1) / kFChunk, nch = chV + chP;
   for (int i0 = 0; i0 < k; i0 += kFK) {
     const int kk = k - i0 < kFK ? k - i0 : kFK;
     hipLaunchKernelGGL(k_fdot<R>, dim3(nch, nf), dim3(256), 0, s, bV + i0 * ldV, bP + i0 * ldP, ldV, ldP, kk, wV, wP,
-                       segV, segP, chV, nch, nf, part);
+                       segV, segP, chV, nch, nf, part, mk);
     hipLaunchKernelGGL(k_fdot_reduce, dim3((kk * nf + 255) / 256), dim3(256), 0, s, part, kk, nf, nch,
                        out + (size_t)i0 * nf);
   }
@@ -273,23 +165,23 @@ size_t fdot_part_entries(int segV, int segP, int nf) {
 
 template <typename R>
 void launch_fupdate(hipStream_t s, cpx<R>* wV, cpx<R>* wP, const cpx<R>* bV, const cpx<R>* bP, size_t ldV,
-                    size_t ldP, int k, const double2* c, int segV, int segP, int nf, double sign) {
+                    size_t ldP, int k, const double2* c, int segV, int segP, int nf, double sign, Mask mk) {
   const size_t tot = (size_t)segV + segP;
   hipLaunchKernelGGL(k_fupdate<R>, dim3((unsigned)((tot + 255) / 256), nf), dim3(256), 0, s, wV, wP, bV, bP, ldV,
-                     ldP, k, c, segV, segP, nf, sign);
+                     ldP, k, c, segV, segP, nf, sign, mk);
 }
 
 template <typename R>
 void launch_fscale(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, const double2* a,
-                   int segV, int segP, int nf) {
+                   int segV, int segP, int nf, Mask mk) {
   const size_t tot = (size_t)segV + segP;
   hipLaunchKernelGGL(k_fscale<R>, dim3((unsigned)((tot + 255) / 256), nf), dim3(256), 0, s, yV, yP, xV, xP, a, segV,
-                     segP);
+                     segP, mk);
 }
 
 template <typename R>
-void launch_unpin_copy(hipStream_t s, cpx<R>* dst, const cpx<R>* src, int nn, int nb) {
-  hipLaunchKernelGGL(k_unpin_copy<R>, dim3(nb), dim3(256), 0, s, dst, src, nn);
+void launch_unpin_copy(hipStream_t s, cpx<R>* dst, const cpx<R>* src, int nn, int nb, Mask mk) {
+  hipLaunchKernelGGL(k_unpin_copy<R>, dim3(nb), dim3(256), 0, s, dst, src, nn, mk);
 }
 
 template <typename Rd, typename Rs>
@@ -298,15 +190,13 @@ void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n) {
 }
 
 #define PINTOC_INNER_INST(R)                                                                                       \
-  template void launch_zmat_stokes<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,       \
-                                      const double2*);                                                             \
   template void launch_fdot<R>(hipStream_t, const cpx<R>*, const cpx<R>*, size_t, size_t, int, const cpx<R>*,      \
-                               const cpx<R>*, int, int, int, double2*, double2*);                                  \
+                               const cpx<R>*, int, int, int, double2*, double2*, Mask);                                  \
   template void launch_fupdate<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, size_t, size_t, int, \
-                                  const double2*, int, int, int, double);                                          \
+                                  const double2*, int, int, int, double, Mask);                                          \
   template void launch_fscale<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, int, \
-                                 int, int);                                                                        \
-  template void launch_unpin_copy<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int);
+                                 int, int, Mask);                                                                        \
+  template void launch_unpin_copy<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, Mask);
 
 PINTOC_INNER_INST(double)
 PINTOC_INNER_INST(float)

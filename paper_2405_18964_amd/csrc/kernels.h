@@ -1,8 +1,12 @@
 // Launchers of the pintoc device kernels (internal to the library).
+// Every batched per-frequency launcher takes a Mask: grids of frequencies
+// whose mask entry is 0 are skipped (kAll: every grid active).
 #pragma once
 #include "common.h"
 
 namespace pintoc {
+
+constexpr Mask kAll{nullptr, 1};
 
 // time FFT (fft_kernels.hip)
 template <typename R>
@@ -15,33 +19,25 @@ void launch_time_fft_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double
 // per-frequency operators and multigrid pieces (mg_kernels.hip)
 template <typename R>
 void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, int n, double h,
-                       const OpCoef* coef, int fpc, int nb, const double* conv, bool forward);
-template <typename R>
-void launch_q2_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef, int fpc,
-                        int nb, const double* conv, bool forward);
-template <typename R>
-void launch_q1_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef, int fpc,
-                        int nb, const double* conv, bool forward);
+                       const OpCoef* coef, int fpc, int nb, const double* conv, bool forward, Mask mk);
 template <typename R>
 void launch_residual(hipStream_t s, bool q2, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
-                     const OpCoef* coef, int fpc, int nb, const double* conv);
+                     const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk);
 template <typename R>
 void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, double h, const OpCoef* coef, int fpc,
-                  int nb, const double* conv);
+                  int nb, const double* conv, Mask mk);
 template <typename R>
-void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb);
+void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk);
 template <typename R>
-void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* xf, const cpx<R>* ec, int nc, int nb);
+void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* xf, const cpx<R>* ec, int nc, int nb, Mask mk);
 template <typename R>
-void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb);
+void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb, Mask mk);
 template <typename R>
 void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
-                 double h, double g, double w, int first, int nb);
-template <typename R>
-void launch_unpin_in(hipStream_t s, cpx<R>* z, int nn, int nb);
+                 double h, double g, double w, int first, int nb, Mask mk);
 template <typename R>
 void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, const cpx<R>* yM, const double2* ab,
-                              int fpc, int nn, int nb);
+                              int fpc, int nn, int nb, Mask mk);
 
 // all-at-once matrix, rhs, FP64 vector kernels (kkt_kernels.hip)
 void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,
@@ -54,43 +50,36 @@ void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b,
 void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, int k, const double* c, size_t n);
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
 
-}  // namespace pintoc
-
-namespace pintoc {
-// per-frequency inner solves (inner_kernels.hip)
-template <typename R>
-void launch_zmat_stokes(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                        const double2* cj);
+// per-frequency GMRES vector operations (inner_kernels.hip)
 template <typename R>
 void launch_fdot(hipStream_t s, const cpx<R>* bV, const cpx<R>* bP, size_t ldV, size_t ldP, int k, const cpx<R>* wV,
-                 const cpx<R>* wP, int segV, int segP, int nf, double2* part, double2* out);
+                 const cpx<R>* wP, int segV, int segP, int nf, double2* part, double2* out, Mask mk);
 size_t fdot_part_entries(int segV, int segP, int nf);
 template <typename R>
 void launch_fupdate(hipStream_t s, cpx<R>* wV, cpx<R>* wP, const cpx<R>* bV, const cpx<R>* bP, size_t ldV,
-                    size_t ldP, int k, const double2* c, int segV, int segP, int nf, double sign);
+                    size_t ldP, int k, const double2* c, int segV, int segP, int nf, double sign, Mask mk);
 template <typename R>
 void launch_fscale(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, const double2* a,
-                   int segV, int segP, int nf);
+                   int segV, int segP, int nf, Mask mk);
 template <typename R>
-void launch_unpin_copy(hipStream_t s, cpx<R>* dst, const cpx<R>* src, int nn, int nb);
+void launch_unpin_copy(hipStream_t s, cpx<R>* dst, const cpx<R>* src, int nn, int nb, Mask mk);
 template <typename Rd, typename Rs>
 void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n);
-}  // namespace pintoc
 
-namespace pintoc {
 // frequency blocks and the Oseen preconditioner pieces (oseen_kernels.hip)
 template <typename R>
 void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                      const BlockCoef* bc, const double* conv, double sp);
+                      const BlockCoef* bc, const double* conv, double sp, Mask mk);
 template <typename R>
 void launch_schur_rhs(hipStream_t s, cpx<R>* out, const cpx<R>* in, const cpx<R>* y1, const cpx<R>* y2, int n,
-                      int nf, double tau);
+                      int nf, double tau, Mask mk);
 template <typename R>
 void launch_oseen_hp(hipStream_t s, cpx<R>* U, const cpx<R>* zz, int n, int nf, const double2* dj, double tau,
-                     double beta, double nu, const double* conv);
+                     double beta, double nu, const double* conv, Mask mk);
 template <typename R>
-void launch_block_copy(hipStream_t s, cpx<R>* V, cpx<R>* X, int n, int nf, int b, int dir);
+void launch_block_copy(hipStream_t s, cpx<R>* V, cpx<R>* X, int n, int nf, int b, int dir, Mask mk);
 template <typename R>
 void launch_combine3(hipStream_t s, cpx<R>* out, const cpx<R>* A, const cpx<R>* B, const cpx<R>* C, double c0,
-                     double c1, double c2, size_t n);
+                     double c1, double c2, size_t n, int seg, Mask mk);
+
 }  // namespace pintoc

@@ -116,50 +116,6 @@ __device__ inline void q1_apply_node(const cpx<R>* __restrict__ x, int n, int ix
   diag.x = (R)dr; diag.y = (R)di;
 }
 
-// ------------------------------------------------------------- GS colours
-// Q2 colour (cx, cy): interior nodes with ix % 3 == cx, iy % 3 == cy.
-template <typename R>
-__global__ __launch_bounds__(256) void k_q2_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b, int n, double h,
-                               int cx, int cy, int ncx, int ncy, const OpCoef* __restrict__ coef, int fpc,
-                               const double* __restrict__ conv) {
-  const int f = blockIdx.y;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ncx * ncy) return;
-  const int kx = t % ncx, ky = t / ncx;
-  const int ix0 = cx == 0 ? 3 : cx, iy0 = cy == 0 ? 3 : cy;      // first interior index of the class
-  const int ix = ix0 + 3 * kx, iy = iy0 + 3 * ky;
-  const int nq = 2 * n + 1;
-  if (ix > nq - 2 || iy > nq - 2) return;
-  const size_t off = (size_t)f * nq * nq;
-  const OpCoef c = coef[f / fpc];
-  cpx<R> ax, dg;
-  q2_apply_node<R>(x + off, nq, ix, iy, h, c, conv, ax, dg);
-  const size_t i = off + (size_t)iy * nq + ix;
-  cpx<R> r = b[i] - ax;
-  cpx<R> xi = x[i];
-  x[i] = xi + cdiv(r, dg);
-}
-
-// Q1 colour (cx, cy): nodes with ix % 2 == cx, iy % 2 == cy, 0 <= ix, iy <= n.
-template <typename R>
-__global__ __launch_bounds__(256) void k_q1_gs_colour(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b, int n, double h,
-                               int cx, int cy, int ncx, int ncy, const OpCoef* __restrict__ coef, int fpc,
-                               const double* __restrict__ conv) {
-  const int f = blockIdx.y;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ncx * ncy) return;
-  const int ix = cx + 2 * (t % ncx), iy = cy + 2 * (t / ncx);
-  if (ix > n || iy > n) return;
-  const int np = n + 1;
-  const size_t off = (size_t)f * np * np;
-  const OpCoef c = coef[f / fpc];
-  cpx<R> ax, dg;
-  q1_apply_node<R>(x + off, n, ix, iy, h, c, conv, ax, dg);
-  const size_t i = off + (size_t)iy * np + ix;
-  cpx<R> r = b[i] - ax;
-  x[i] = x[i] + cdiv(r, dg);
-}
-
 // ------------------------------------------------------ tiled GS sweeps
 // Symmetric multicolour Gauss-Seidel inside square tiles, block Jacobi between
 // tiles (a distributed SOR with one tile per subdomain).  A work-group owns
@@ -173,9 +129,10 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_q2_tile_sweep(cpx<R>* __restrict__ xo, const cpx<R>* __restrict__ xi,
                                                        const cpx<R>* __restrict__ b, int n, double h,
                                                        const OpCoef* __restrict__ coef, int fpc,
-                                                       const double* __restrict__ conv, int forward, int ntx) {
+                                                       const double* __restrict__ conv, int forward, int ntx, Mask mk) {
   __shared__ cpx<R> sx[kL2 * kL2];
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int X0 = (blockIdx.x % ntx) * kT2, Y0 = (blockIdx.x / ntx) * kT2;
   const int nq = 2 * n + 1;
   const size_t off = (size_t)f * nq * nq;
@@ -246,9 +203,10 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_q1_tile_sweep(cpx<R>* __restrict__ xo, const cpx<R>* __restrict__ xi,
                                                        const cpx<R>* __restrict__ b, int n, double h,
                                                        const OpCoef* __restrict__ coef, int fpc,
-                                                       const double* __restrict__ conv, int forward, int ntx) {
+                                                       const double* __restrict__ conv, int forward, int ntx, Mask mk) {
   __shared__ cpx<R> sx[kL1 * kL1];
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int X0 = (blockIdx.x % ntx) * kT1, Y0 = (blockIdx.x / ntx) * kT1;
   const int np = n + 1;
   const size_t off = (size_t)f * np * np;
@@ -314,8 +272,9 @@ __global__ __launch_bounds__(256) void k_q1_tile_sweep(cpx<R>* __restrict__ xo, 
 template <typename R>
 __global__ __launch_bounds__(256) void k_q2_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
                               int n, double h, const OpCoef* __restrict__ coef, int fpc,
-                              const double* __restrict__ conv) {
+                              const double* __restrict__ conv, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int nq = 2 * n + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nq * nq) return;
@@ -330,8 +289,9 @@ __global__ __launch_bounds__(256) void k_q2_residual(cpx<R>* __restrict__ r, con
 template <typename R>
 __global__ __launch_bounds__(256) void k_q1_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
                               int n, double h, const OpCoef* __restrict__ coef, int fpc,
-                              const double* __restrict__ conv) {
+                              const double* __restrict__ conv, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int np = n + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= np * np) return;
@@ -345,8 +305,9 @@ __global__ __launch_bounds__(256) void k_q1_residual(cpx<R>* __restrict__ r, con
 // y = A x (operator application; b = 0 residual form negated)
 template <typename R>
 __global__ __launch_bounds__(256) void k_q2_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
-                           const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv) {
+                           const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int nq = 2 * n + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nq * nq) return;
@@ -360,8 +321,9 @@ __global__ __launch_bounds__(256) void k_q2_apply(cpx<R>* __restrict__ y, const 
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_q1_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
-                           const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv) {
+                           const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int np = n + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= np * np) return;
@@ -383,8 +345,9 @@ __device__ inline void q2_restrict_w(int I, double w[7]) {
 
 // bc = P^T rf on coarse interior nodes (fine boundary residuals are zero).
 template <typename R>
-__global__ __launch_bounds__(256) void k_q2_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc) {
+__global__ __launch_bounds__(256) void k_q2_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int nqc = 2 * nc + 1, nqf = 4 * nc + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nqc * nqc) return;
@@ -422,8 +385,9 @@ __device__ inline void q2_prolong_w(int i, int& c0, double w[3]) {
 
 // xf += P ec on fine interior nodes.
 template <typename R>
-__global__ __launch_bounds__(256) void k_q2_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc) {
+__global__ __launch_bounds__(256) void k_q2_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int nqc = 2 * nc + 1, nqf = 4 * nc + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nqf * nqf) return;
@@ -454,8 +418,9 @@ __global__ __launch_bounds__(256) void k_q2_prolong_add(cpx<R>* __restrict__ xf,
 
 // Q1: bc = P^T rf (coarse node I <-> fine 2I, weights 1/2, 1, 1/2).
 template <typename R>
-__global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc) {
+__global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int npc = nc + 1, nf = 2 * nc, npf = nf + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= npc * npc) return;
@@ -477,8 +442,9 @@ __global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, co
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_q1_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc) {
+__global__ __launch_bounds__(256) void k_q1_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int npc = nc + 1, npf = 2 * nc + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= npf * npf) return;
@@ -509,10 +475,10 @@ __global__ __launch_bounds__(256) void k_q1_prolong_add(cpx<R>* __restrict__ xf,
 // inv[ci] holds the dense inverse (row-major, complex FP64) per coefficient set.
 template <typename R>
 __global__ __launch_bounds__(256) void k_q2_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
-                                  const double2* __restrict__ inv, int fpc, int nb) {
+                                  const double2* __restrict__ inv, int fpc, int nb, Mask mk) {
   const int f = blockIdx.x * (blockDim.x / 9) + threadIdx.x / 9;
   const int r = threadIdx.x % 9;
-  if (f >= nb || threadIdx.x >= (blockDim.x / 9) * 9) return;
+  if (f >= nb || threadIdx.x >= (blockDim.x / 9) * 9 || mk.off(f)) return;
   const double2* A = inv + (size_t)(f / fpc) * 81;
   const cpx<R>* bb = b + (size_t)f * 25;
   double sr = 0, si = 0;
@@ -527,10 +493,10 @@ __global__ __launch_bounds__(256) void k_q2_coarse_solve(cpx<R>* __restrict__ x,
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_q1_coarse_solve(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
-                                  const double2* __restrict__ inv, int fpc, int nb) {
+                                  const double2* __restrict__ inv, int fpc, int nb, Mask mk) {
   const int f = blockIdx.x * (blockDim.x / 9) + threadIdx.x / 9;
   const int r = threadIdx.x % 9;
-  if (f >= nb || threadIdx.x >= (blockDim.x / 9) * 9) return;
+  if (f >= nb || threadIdx.x >= (blockDim.x / 9) * 9 || mk.off(f)) return;
   if (r == 0) { x[(size_t)f * 9] = cmk<cpx<R>>(0, 0); return; }
   const double2* A = inv + (size_t)(f / fpc) * 64;
   const cpx<R>* bb = b + (size_t)f * 9;
@@ -552,8 +518,9 @@ __global__ __launch_bounds__(256) void k_q1_coarse_solve(cpx<R>* __restrict__ x,
 // xn may alias xp (each thread reads its own xp entry before writing).
 template <typename R>
 __global__ __launch_bounds__(256) void k_q2_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
-                          const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first) {
+                          const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int nq = 2 * n + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nq * nq) return;
@@ -580,8 +547,9 @@ __global__ __launch_bounds__(256) void k_q2_cheb(cpx<R>* xn, const cpx<R>* __res
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_q1_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
-                          const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first) {
+                          const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int np = n + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= np * np) return;
@@ -606,32 +574,14 @@ __global__ __launch_bounds__(256) void k_q1_cheb(cpx<R>* xn, const cpx<R>* __res
 }
 
 // ------------------------------------------------ pressure pin in / pin out
-// z[f][0] = -sum_{i >= 1} z[f][i]   (the extension (I - e0 1^T) R^T of a
-// pinned pressure field whose node-0 entry is zero on entry).
-// One block per grid; fixed-order tree reduction (deterministic).
-template <typename R>
-__global__ __launch_bounds__(256) void k_unpin_in(cpx<R>* __restrict__ z, int nn) {
-  __shared__ double sr[256], si[256];
-  const int f = blockIdx.x;
-  cpx<R>* g = z + (size_t)f * nn;
-  double ar = 0, ai = 0;
-  for (int i = 1 + threadIdx.x; i < nn; i += blockDim.x) { ar += (double)g[i].x; ai += (double)g[i].y; }
-  sr[threadIdx.x] = ar; si[threadIdx.x] = ai;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) { sr[threadIdx.x] += sr[threadIdx.x + s]; si[threadIdx.x] += si[threadIdx.x + s]; }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) g[0] = cmk<cpx<R>>(-sr[0], -si[0]);
-}
-
 // out = a_j yK + g_j yM, then shift by out[node 0] so that node 0 is zero
 // (R (I - 1 e0^T)).  Coefficients per grid pair: ab[f / fpc] = (a, g) real.
 template <typename R>
 __global__ __launch_bounds__(256) void k_schur_combine_pin(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ yK,
                                     const cpx<R>* __restrict__ yM, const double2* __restrict__ ab,
-                                    int fpc, int nn) {
+                                    int fpc, int nn, Mask mk) {
   const int f = blockIdx.y;
+  if (mk.off(f)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nn) return;
   const double a = ab[f / fpc].x, g = ab[f / fpc].y;
@@ -646,142 +596,104 @@ static inline dim3 grid2(long work, int nb, int bs = 256) { return dim3((unsigne
 
 template <typename R>
 void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, int n, double h,
-                       const OpCoef* coef, int fpc, int nb, const double* conv, bool forward) {
+                       const OpCoef* coef, int fpc, int nb, const double* conv, bool forward, Mask mk) {
   if (q2) {
     const int nq = 2 * n + 1, ntx = (nq + kT2 - 1) / kT2;
     hipLaunchKernelGGL(k_q2_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, n, h, coef, fpc, conv,
-                       forward ? 1 : 0, ntx);
+                       forward ? 1 : 0, ntx, mk);
   } else {
     const int np = n + 1, ntx = (np + kT1 - 1) / kT1;
     hipLaunchKernelGGL(k_q1_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, n, h, coef, fpc, conv,
-                       forward ? 1 : 0, ntx);
-  }
-}
-
-template <typename R>
-void launch_q2_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef,
-                        int fpc, int nb, const double* conv, bool forward) {
-  const int nq = 2 * n + 1;
-  for (int k = 0; k < 9; ++k) {
-    const int c = forward ? k : 8 - k;
-    const int cx = c % 3, cy = c / 3;
-    const int ix0 = cx == 0 ? 3 : cx, iy0 = cy == 0 ? 3 : cy;
-    const int ncx = ix0 <= nq - 2 ? (nq - 2 - ix0) / 3 + 1 : 0;
-    const int ncy = iy0 <= nq - 2 ? (nq - 2 - iy0) / 3 + 1 : 0;
-    if (ncx == 0 || ncy == 0) continue;
-    hipLaunchKernelGGL(k_q2_gs_colour<R>, grid2((long)ncx * ncy, nb), dim3(256), 0, s, x, b, n, h, cx, cy,
-                       ncx, ncy, coef, fpc, conv);
-  }
-}
-
-template <typename R>
-void launch_q1_gs_sweep(hipStream_t s, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef,
-                        int fpc, int nb, const double* conv, bool forward) {
-  for (int k = 0; k < 4; ++k) {
-    const int c = forward ? k : 3 - k;
-    const int cx = c % 2, cy = c / 2;
-    const int ncx = (n - cx) / 2 + 1, ncy = (n - cy) / 2 + 1;
-    hipLaunchKernelGGL(k_q1_gs_colour<R>, grid2((long)ncx * ncy, nb), dim3(256), 0, s, x, b, n, h, cx, cy,
-                       ncx, ncy, coef, fpc, conv);
+                       forward ? 1 : 0, ntx, mk);
   }
 }
 
 template <typename R>
 void launch_residual(hipStream_t s, bool q2, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
-                     const OpCoef* coef, int fpc, int nb, const double* conv) {
+                     const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk) {
   if (q2) {
     const int nq = 2 * n + 1;
-    hipLaunchKernelGGL(k_q2_residual<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv);
+    hipLaunchKernelGGL(k_q2_residual<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv, mk);
   } else {
     const int np = n + 1;
-    hipLaunchKernelGGL(k_q1_residual<R>, grid2((long)np * np, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv);
+    hipLaunchKernelGGL(k_q1_residual<R>, grid2((long)np * np, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv, mk);
   }
 }
 
 template <typename R>
 void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, double h, const OpCoef* coef,
-                  int fpc, int nb, const double* conv) {
+                  int fpc, int nb, const double* conv, Mask mk) {
   if (q2) {
     const int nq = 2 * n + 1;
-    hipLaunchKernelGGL(k_q2_apply<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv);
+    hipLaunchKernelGGL(k_q2_apply<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv, mk);
   } else {
     const int np = n + 1;
-    hipLaunchKernelGGL(k_q1_apply<R>, grid2((long)np * np, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv);
+    hipLaunchKernelGGL(k_q1_apply<R>, grid2((long)np * np, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv, mk);
   }
 }
 
 template <typename R>
-void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb) {
+void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk) {
   if (q2) {
     const int nqc = 2 * nc + 1;
-    hipLaunchKernelGGL(k_q2_restrict<R>, grid2((long)nqc * nqc, nb), dim3(256), 0, s, bc, rf, nc);
+    hipLaunchKernelGGL(k_q2_restrict<R>, grid2((long)nqc * nqc, nb), dim3(256), 0, s, bc, rf, nc, mk);
   } else {
     const int npc = nc + 1;
-    hipLaunchKernelGGL(k_q1_restrict<R>, grid2((long)npc * npc, nb), dim3(256), 0, s, bc, rf, nc);
+    hipLaunchKernelGGL(k_q1_restrict<R>, grid2((long)npc * npc, nb), dim3(256), 0, s, bc, rf, nc, mk);
   }
 }
 
 template <typename R>
-void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* xf, const cpx<R>* ec, int nc, int nb) {
+void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* xf, const cpx<R>* ec, int nc, int nb, Mask mk) {
   if (q2) {
     const int nqf = 4 * nc + 1;
-    hipLaunchKernelGGL(k_q2_prolong_add<R>, grid2((long)nqf * nqf, nb), dim3(256), 0, s, xf, ec, nc);
+    hipLaunchKernelGGL(k_q2_prolong_add<R>, grid2((long)nqf * nqf, nb), dim3(256), 0, s, xf, ec, nc, mk);
   } else {
     const int npf = 2 * nc + 1;
-    hipLaunchKernelGGL(k_q1_prolong_add<R>, grid2((long)npf * npf, nb), dim3(256), 0, s, xf, ec, nc);
+    hipLaunchKernelGGL(k_q1_prolong_add<R>, grid2((long)npf * npf, nb), dim3(256), 0, s, xf, ec, nc, mk);
   }
 }
 
 template <typename R>
-void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb) {
+void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb, Mask mk) {
   const int per = 256 / 9;
   const unsigned blocks = (unsigned)((nb + per - 1) / per);
-  if (q2) hipLaunchKernelGGL(k_q2_coarse_solve<R>, dim3(blocks), dim3(256), 0, s, x, b, inv, fpc, nb);
-  else hipLaunchKernelGGL(k_q1_coarse_solve<R>, dim3(blocks), dim3(256), 0, s, x, b, inv, fpc, nb);
+  if (q2) hipLaunchKernelGGL(k_q2_coarse_solve<R>, dim3(blocks), dim3(256), 0, s, x, b, inv, fpc, nb, mk);
+  else hipLaunchKernelGGL(k_q1_coarse_solve<R>, dim3(blocks), dim3(256), 0, s, x, b, inv, fpc, nb, mk);
 }
 
 template <typename R>
 void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
-                 double h, double g, double w, int first, int nb) {
+                 double h, double g, double w, int first, int nb, Mask mk) {
   if (q2) {
     const int nq = 2 * n + 1;
-    hipLaunchKernelGGL(k_q2_cheb<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, xn, x, xp, b, n, h, g, w, first);
+    hipLaunchKernelGGL(k_q2_cheb<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, xn, x, xp, b, n, h, g, w, first, mk);
   } else {
     const int np = n + 1;
-    hipLaunchKernelGGL(k_q1_cheb<R>, grid2((long)np * np, nb), dim3(256), 0, s, xn, x, xp, b, n, h, g, w, first);
+    hipLaunchKernelGGL(k_q1_cheb<R>, grid2((long)np * np, nb), dim3(256), 0, s, xn, x, xp, b, n, h, g, w, first, mk);
   }
 }
 
 template <typename R>
-void launch_unpin_in(hipStream_t s, cpx<R>* z, int nn, int nb) {
-  hipLaunchKernelGGL(k_unpin_in<R>, dim3(nb), dim3(256), 0, s, z, nn);
-}
-
-template <typename R>
 void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, const cpx<R>* yM, const double2* ab,
-                              int fpc, int nn, int nb) {
-  hipLaunchKernelGGL(k_schur_combine_pin<R>, grid2(nn, nb), dim3(256), 0, s, out, yK, yM, ab, fpc, nn);
+                              int fpc, int nn, int nb, Mask mk) {
+  hipLaunchKernelGGL(k_schur_combine_pin<R>, grid2(nn, nb), dim3(256), 0, s, out, yK, yM, ab, fpc, nn, mk);
 }
 
 #define PINTOC_INST(R)                                                                                        \
   template void launch_tile_sweep<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,        \
-                                     const OpCoef*, int, int, const double*, bool);                            \
-  template void launch_q2_gs_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
-                                      const double*, bool);                                                    \
-  template void launch_q1_gs_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
-                                      const double*, bool);                                                    \
+                                     const OpCoef*, int, int, const double*, bool, Mask);                            \
   template void launch_residual<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,       \
-                                   const OpCoef*, int, int, const double*);                                    \
+                                   const OpCoef*, int, int, const double*, Mask);                                    \
   template void launch_apply<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
-                                const double*);                                                                \
-  template void launch_restrict<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int);                       \
-  template void launch_prolong_add<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int);                    \
-  template void launch_coarse<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const double2*, int, int);         \
+                                const double*, Mask);                                                                \
+  template void launch_restrict<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int, Mask);                       \
+  template void launch_prolong_add<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int, Mask);                    \
+  template void launch_coarse<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const double2*, int, int, Mask);         \
   template void launch_cheb<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int,    \
-                               double, double, double, int, int);                                              \
-  template void launch_unpin_in<R>(hipStream_t, cpx<R>*, int, int);                                            \
+                               double, double, double, int, int, Mask);                                              \
   template void launch_schur_combine_pin<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, \
-                                            int, int, int);
+                                            int, int, int, Mask);
 
 PINTOC_INST(double)
 PINTOC_INST(float)

@@ -19,11 +19,11 @@ namespace pintoc {
 template <typename R>
 __global__ __launch_bounds__(256) void k_block_vel(cpx<R>* __restrict__ yV, const cpx<R>* __restrict__ xV,
                                                    const cpx<R>* __restrict__ xP, int n,
-                                                   const BlockCoef* __restrict__ bc, const double* __restrict__ conv) {
+                                                   const BlockCoef* __restrict__ bc, const double* __restrict__ conv, Mask mk) {
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int node = blockIdx.x * blockDim.x + threadIdx.x;
   const int jc = blockIdx.y;                    // j * 2 + comp
-  if (node >= nq2) return;
+  if (node >= nq2 || mk.off(jc)) return;
   const int comp = jc & 1, j = jc >> 1;
   const size_t o0 = ((size_t)(j * 2 + 0) * 2 + comp) * nq2 + node;
   const size_t o1 = ((size_t)(j * 2 + 1) * 2 + comp) * nq2 + node;
@@ -138,11 +138,11 @@ __device__ inline void b_apply_node(const cpx<R>* __restrict__ ux, const cpx<R>*
 // rows 3 and 4: yP[j][0] = s B lambda, yP[j][1] = s B v  (node 0 pinned: 0)
 template <typename R>
 __global__ __launch_bounds__(256) void k_block_pres(cpx<R>* __restrict__ yP, const cpx<R>* __restrict__ xV, int n,
-                                                    double s) {
+                                                    double s, Mask mk) {
   const int nq2 = (2 * n + 1) * (2 * n + 1), np2 = (n + 1) * (n + 1);
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int jb = blockIdx.y;
-  if (k >= np2) return;
+  if (k >= np2 || mk.off(jb)) return;
   const int b = jb & 1, j = jb >> 1;
   const size_t o = (size_t)jb * np2 + k;
   if (k == 0) { yP[o] = cmk<cpx<R>>(0, 0); return; }
@@ -158,11 +158,11 @@ __global__ __launch_bounds__(256) void k_block_pres(cpx<R>* __restrict__ yP, con
 template <typename R>
 __global__ __launch_bounds__(256) void k_schur_rhs(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ in,
                                                    const cpx<R>* __restrict__ y1, const cpx<R>* __restrict__ y2,
-                                                   int n, double tau) {
+                                                   int n, double tau, Mask mk) {
   const int nq2 = (2 * n + 1) * (2 * n + 1), np2 = (n + 1) * (n + 1);
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int jb = blockIdx.y;
-  if (k >= np2) return;
+  if (k >= np2 || mk.off(jb)) return;
   const int b = jb & 1, j = jb >> 1;
   const size_t o = (size_t)jb * np2 + k;
   if (k == 0) { out[o] = cmk<cpx<R>>(0, 0); return; }
@@ -180,11 +180,11 @@ __global__ __launch_bounds__(256) void k_schur_rhs(cpx<R>* __restrict__ out, con
 template <typename R>
 __global__ __launch_bounds__(256) void k_oseen_hp(cpx<R>* __restrict__ U, const cpx<R>* __restrict__ zz, int n,
                                                   const double2* __restrict__ dj, double tau, double beta,
-                                                  double nu, const double* __restrict__ conv) {
+                                                  double nu, const double* __restrict__ conv, Mask mk) {
   const int np = n + 1, np2 = np * np;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
-  if (k >= np2) return;
+  if (k >= np2 || mk.off(j)) return;
   const int ix = k % np, iy = k / np;
   const double h = 1.0 / n;
   double mx[3], kx[3], my[3], ky[3];
@@ -226,10 +226,10 @@ __global__ __launch_bounds__(256) void k_oseen_hp(cpx<R>* __restrict__ U, const 
 // contiguous per-block batch X[j][comp] (dir 0: V -> X, dir 1: X -> V).
 template <typename R>
 __global__ __launch_bounds__(256) void k_block_copy(cpx<R>* __restrict__ V, cpx<R>* __restrict__ X, int nq2, int b,
-                                                    int dir) {
+                                                    int dir, Mask mk) {
   const int node = blockIdx.x * blockDim.x + threadIdx.x;
   const int jc = blockIdx.y;                    // j * 2 + comp
-  if (node >= nq2) return;
+  if (node >= nq2 || mk.off(jc)) return;
   const int comp = jc & 1, j = jc >> 1;
   const size_t ov = ((size_t)(j * 2 + b) * 2 + comp) * nq2 + node;
   const size_t ox = (size_t)jc * nq2 + node;
@@ -240,8 +240,9 @@ __global__ __launch_bounds__(256) void k_block_copy(cpx<R>* __restrict__ V, cpx<
 // out = c0 A + c1 B + c2 C (real coefficients; B or C may be null); out may alias A.
 template <typename R>
 __global__ __launch_bounds__(256) void k_combine3(cpx<R>* out, const cpx<R>* A, const cpx<R>* B, const cpx<R>* C,
-                                                  double c0, double c1, double c2, size_t n) {
+                                                  double c0, double c1, double c2, size_t n, int seg, Mask mk) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    if (mk.off((int)(e / seg))) continue;
     const cpx<R> a = A[e];
     double r = c0 * (double)a.x, i = c0 * (double)a.y;
     if (B) { const cpx<R> v = B[e]; r += c1 * (double)v.x; i += c1 * (double)v.y; }
@@ -252,48 +253,48 @@ __global__ __launch_bounds__(256) void k_combine3(cpx<R>* out, const cpx<R>* A, 
 
 template <typename R>
 void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                      const BlockCoef* bc, const double* conv, double sp) {
+                      const BlockCoef* bc, const double* conv, double sp, Mask mk) {
   const int nq2 = (2 * n + 1) * (2 * n + 1), np2 = (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_block_vel<R>, dim3((nq2 + 255) / 256, 2 * nf), dim3(256), 0, s, yV, xV, xP, n, bc, conv);
-  hipLaunchKernelGGL(k_block_pres<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, yP, xV, n, sp);
+  hipLaunchKernelGGL(k_block_vel<R>, dim3((nq2 + 255) / 256, 2 * nf), dim3(256), 0, s, yV, xV, xP, n, bc, conv, mk);
+  hipLaunchKernelGGL(k_block_pres<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, yP, xV, n, sp, mk);
 }
 
 template <typename R>
 void launch_schur_rhs(hipStream_t s, cpx<R>* out, const cpx<R>* in, const cpx<R>* y1, const cpx<R>* y2, int n,
-                      int nf, double tau) {
+                      int nf, double tau, Mask mk) {
   const int np2 = (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_schur_rhs<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, out, in, y1, y2, n, tau);
+  hipLaunchKernelGGL(k_schur_rhs<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, out, in, y1, y2, n, tau, mk);
 }
 
 template <typename R>
 void launch_oseen_hp(hipStream_t s, cpx<R>* U, const cpx<R>* zz, int n, int nf, const double2* dj, double tau,
-                     double beta, double nu, const double* conv) {
+                     double beta, double nu, const double* conv, Mask mk) {
   const int np2 = (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_oseen_hp<R>, dim3((np2 + 255) / 256, nf), dim3(256), 0, s, U, zz, n, dj, tau, beta, nu, conv);
+  hipLaunchKernelGGL(k_oseen_hp<R>, dim3((np2 + 255) / 256, nf), dim3(256), 0, s, U, zz, n, dj, tau, beta, nu, conv, mk);
 }
 
 template <typename R>
-void launch_block_copy(hipStream_t s, cpx<R>* V, cpx<R>* X, int n, int nf, int b, int dir) {
+void launch_block_copy(hipStream_t s, cpx<R>* V, cpx<R>* X, int n, int nf, int b, int dir, Mask mk) {
   const int nq2 = (2 * n + 1) * (2 * n + 1);
-  hipLaunchKernelGGL(k_block_copy<R>, dim3((nq2 + 255) / 256, 2 * nf), dim3(256), 0, s, V, X, nq2, b, dir);
+  hipLaunchKernelGGL(k_block_copy<R>, dim3((nq2 + 255) / 256, 2 * nf), dim3(256), 0, s, V, X, nq2, b, dir, mk);
 }
 
 template <typename R>
 void launch_combine3(hipStream_t s, cpx<R>* out, const cpx<R>* A, const cpx<R>* B, const cpx<R>* C, double c0,
-                     double c1, double c2, size_t n) {
-  hipLaunchKernelGGL(k_combine3<R>, dim3(2048), dim3(256), 0, s, out, A, B, C, c0, c1, c2, n);
+                     double c1, double c2, size_t n, int seg, Mask mk) {
+  hipLaunchKernelGGL(k_combine3<R>, dim3(2048), dim3(256), 0, s, out, A, B, C, c0, c1, c2, n, seg, mk);
 }
 
 #define PINTOC_OSEEN_INST(R)                                                                                       \
   template void launch_block_mat<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,         \
-                                    const BlockCoef*, const double*, double);                                      \
+                                    const BlockCoef*, const double*, double, Mask);                                      \
   template void launch_schur_rhs<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,   \
-                                    double);                                                                       \
+                                    double, Mask);                                                                       \
   template void launch_oseen_hp<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, const double2*, double, double,  \
-                                   double, const double*);                                                         \
-  template void launch_block_copy<R>(hipStream_t, cpx<R>*, cpx<R>*, int, int, int, int);                           \
+                                   double, const double*, Mask);                                                         \
+  template void launch_block_copy<R>(hipStream_t, cpx<R>*, cpx<R>*, int, int, int, int, Mask);                           \
   template void launch_combine3<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, double,      \
-                                   double, double, size_t);
+                                   double, double, size_t, int, Mask);
 
 PINTOC_OSEEN_INST(double)
 PINTOC_OSEEN_INST(float)

@@ -64,6 +64,9 @@ struct MGPlan {
   // t (second iterate buffer of the out-of-place smoother), r (residual)
   std::vector<void*> b, x, r, t;
   Probe* probe = nullptr;              // times the finest-level sweeps when on
+  int fpj = 1;                         // grids per frequency in the batch
+  const int* mask = nullptr;           // per-frequency activity (inner GMRES), or null
+  Mask mk() const { return Mask{mask, fpj}; }
   int n(int l) const { return N >> l; }
   size_t nodes(int l) const {
     const size_t m = q2 ? (size_t)(2 * n(l) + 1) : (size_t)(n(l) + 1);
@@ -105,6 +108,10 @@ struct pintoc_problem {
   std::vector<double*> conv2;
   double* conv1 = nullptr;
   MGPlan mgQ, mgQH;
+  int* maskd = nullptr;                 // device mask of the batched inner GMRES
+  std::vector<int> mask_h;
+  const int* cur_mask = nullptr;       // mask in force for the current block operations
+  Mask mk(int fpj) const { return Mask{cur_mask, fpj}; }
   std::vector<OpCoef> cpsi_h, cpsih_h;
   OpCoef *cpsi = nullptr, *cpsih = nullptr, *cscal = nullptr;   // cscal: [tau M, tau/beta M, M]
   std::vector<double2> dj_h;
@@ -277,6 +284,7 @@ static void carve(pintoc_problem* p, char* base) {
     p->fpart = cv.take<double2>(sizeof(double2) * fdot_part_entries(p->segV, p->segP, nf));
   }
   p->bc = cv.take<BlockCoef>(sizeof(BlockCoef) * nf);
+  p->maskd = cv.take<int>(sizeof(int) * nf);
   if (p->d.flow == PINTOC_OSEEN) {
     p->conv2.assign(p->conv2_h.size(), nullptr);
     for (size_t l = 0; l < p->conv2_h.size(); ++l) p->conv2[l] = cv.take<double>(sizeof(double) * p->conv2_h[l].size());
@@ -508,7 +516,7 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     }
   }
   MGPlan& W = p->mgW;
-  W.q2 = true; W.N = N; W.nb = 4 * p->nf; W.fpc = 4; W.ncoef = p->nf;
+  W.q2 = true; W.N = N; W.nb = 4 * p->nf; W.fpc = 4; W.ncoef = p->nf; W.fpj = 4;
   const double sb = std::sqrt(beta);
   for (int j = 0; j < p->nf; ++j) {
     const double th = 2.0 * M_PI * j / nt;
@@ -540,10 +548,10 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   }
   p->block_scale = oseen ? tau : 1.0;
   MGPlan& K = p->mgK;
-  K.q2 = false; K.N = N; K.nb = 2 * p->nf; K.fpc = 2 * p->nf; K.ncoef = 1;
+  K.q2 = false; K.N = N; K.nb = 2 * p->nf; K.fpc = 2 * p->nf; K.ncoef = 1; K.fpj = 2;
   K.coef_h.push_back(mkcoef(0.0, 1.0));                   // unconstrained pressure Laplacian
   for (MGPlan* m : {&p->mgQ, &p->mgQH}) {
-    m->q2 = true; m->N = N; m->nb = 2 * p->nf; m->fpc = 2; m->ncoef = p->nf;
+    m->q2 = true; m->N = N; m->nb = 2 * p->nf; m->fpc = 2; m->ncoef = p->nf; m->fpj = 2;
   }
   std::vector<MGPlan*> plans = {&K};
   if (oseen) { plans.push_back(&p->mgQ); plans.push_back(&p->mgQH); }
@@ -612,7 +620,7 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b) 
   const int n = m.n(l);
   const double h = 1.0 / n;
   if (l == m.nlev - 1) {
-    launch_coarse<R>(s, m.q2, x, b, m.inv, m.fpc, m.nb);
+    launch_coarse<R>(s, m.q2, x, b, m.inv, m.fpc, m.nb, m.mk());
     return;
   }
   // pre-smoothing x -> t, coarse correction on t, post-smoothing t -> x
@@ -621,18 +629,18 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b) 
   auto timed_sweep = [&](cpx<R>* xo, const cpx<R>* xi, bool fwd) {
     const int slot = pr ? (int)(pr->count % Probe::kCap) : 0;
     if (pr) hipEventRecord(pr->e0[slot], s);
-    launch_tile_sweep<R>(s, m.q2, xo, xi, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], fwd);
+    launch_tile_sweep<R>(s, m.q2, xo, xi, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], fwd, m.mk());
     if (pr) { hipEventRecord(pr->e1[slot], s); pr->count++; }
   };
   timed_sweep(t, x, true);
   cpx<R>* r = (cpx<R>*)m.r[l];
-  launch_residual<R>(s, m.q2, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l]);
+  launch_residual<R>(s, m.q2, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
   cpx<R>* bc = (cpx<R>*)m.b[l + 1];
   cpx<R>* xc = (cpx<R>*)m.x[l + 1];
-  launch_restrict<R>(s, m.q2, bc, r, n / 2, m.nb);
+  launch_restrict<R>(s, m.q2, bc, r, n / 2, m.nb, m.mk());
   launch_fill_zero(s, xc, m.nodes(l + 1) * m.nb * sizeof(cpx<R>));
   vcycle<R>(s, m, l + 1, xc, bc);
-  launch_prolong_add<R>(s, m.q2, t, xc, n / 2, m.nb);
+  launch_prolong_add<R>(s, m.q2, t, xc, n / 2, m.nb, m.mk());
   timed_sweep(x, t, false);
 }
 
@@ -647,17 +655,17 @@ static void mg_solve(hipStream_t s, MGPlan& m, cpx<R>* x, const cpx<R>* b, int c
 // diag(M)^{-1} M), ``steps`` steps from zero.  Returns the buffer holding x_steps.
 template <typename R>
 static cpx<R>* chebyshev(hipStream_t s, bool q2, int n, int nb, cpx<R>* A, cpx<R>* B, const cpx<R>* b, int steps,
-                         double lo, double hi) {
+                         double lo, double hi, Mask mk) {
   const double g = 2.0 / (lo + hi), sg = (hi - lo) / (hi + lo);
   const double h = 1.0 / n;
   const size_t bytes = (q2 ? (size_t)(2 * n + 1) * (2 * n + 1) : (size_t)(n + 1) * (n + 1)) * nb * sizeof(cpx<R>);
-  launch_cheb<R>(s, q2, A, A, A, b, n, h, g, 1.0, 1, nb);             // x_1 = g D^{-1} b
+  launch_cheb<R>(s, q2, A, A, A, b, n, h, g, 1.0, 1, nb, mk);         // x_1 = g D^{-1} b
   launch_fill_zero(s, B, bytes);                                       // x_0 = 0
   cpx<R>*cur = A, *prev = B;
   double w = 1.0;
   for (int k = 1; k < steps; ++k) {
     w = k == 1 ? 1.0 / (1.0 - 0.5 * sg * sg) : 1.0 / (1.0 - 0.25 * sg * sg * w);
-    launch_cheb<R>(s, q2, prev, cur, prev, b, n, h, g, w, 0, nb);     // x_{k+1} overwrites x_{k-1}
+    launch_cheb<R>(s, q2, prev, cur, prev, b, n, h, g, w, 0, nb, mk); // x_{k+1} overwrites x_{k-1}
     std::swap(cur, prev);
   }
   return cur;
@@ -673,10 +681,11 @@ static void ptilde(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cp
   const int nf = p->nf, cyc = p->o.n_vcycles, N = p->d.N;
   mg_solve<R>(s, p->mgW, outV, inV, cyc);
   cpx<R>* z = (cpx<R>*)p->Ptmp;
-  launch_unpin_copy<R>(s, z, inP, p->np2, 2 * nf);
+  launch_unpin_copy<R>(s, z, inP, p->np2, 2 * nf, p->mk(2));
   mg_solve<R>(s, p->mgK, (cpx<R>*)p->PxK, z, cyc);
-  cpx<R>* ym = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25);
-  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, ym, p->ab, 2, p->np2, 2 * nf);
+  cpx<R>* ym = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25,
+                            p->mk(2));
+  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, ym, p->ab, 2, p->np2, 2 * nf, p->mk(2));
 }
 
 // P~_j^(UZ)^{-1} of Algorithm 3 (Oseen) on a frequency vector, all kept
@@ -692,38 +701,41 @@ static void puz(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R
   const size_t nh = (size_t)2 * nf * p->nq2;                  // complex entries of one velocity block
   cpx<R>*B1 = (cpx<R>*)p->B1, *B2 = (cpx<R>*)p->B2, *X1 = (cpx<R>*)p->X1, *X2 = (cpx<R>*)p->X2;
   cpx<R>*T1 = (cpx<R>*)p->T1, *T2 = (cpx<R>*)p->T2, *Rb = (cpx<R>*)p->Rb;
-  launch_block_copy<R>(s, (cpx<R>*)inV, B1, N, nf, 0, 0);
-  launch_block_copy<R>(s, (cpx<R>*)inV, B2, N, nf, 1, 0);
+  const Mask m2 = p->mk(2);
+  const int nq2 = p->nq2;
+  launch_block_copy<R>(s, (cpx<R>*)inV, B1, N, nf, 0, 0, m2);
+  launch_block_copy<R>(s, (cpx<R>*)inV, B2, N, nf, 1, 0, m2);
   launch_fill_zero(s, X1, nh * sizeof(cpx<R>));
   launch_fill_zero(s, X2, nh * sizeof(cpx<R>));
   const double* cv = p->conv2[0];
   for (int k = 0; k < p->o.n_uzawa; ++k) {
     // x1 += tau^{-1} M^^{-1} (b1 - tau M x1 - Psi^H x2)
-    launch_apply<R>(s, true, T1, X1, N, h, p->cscal + 0, 2 * nf, 2 * nf, nullptr);
-    launch_apply<R>(s, true, T2, X2, N, h, p->cpsih, 2, 2 * nf, cv);
-    launch_combine3<R>(s, Rb, B1, T1, T2, 1.0, -1.0, -1.0, nh);
-    cpx<R>* c = chebyshev<R>(s, true, N, 2 * nf, (cpx<R>*)p->C1, (cpx<R>*)p->C2, Rb, p->o.n_cheb, 0.25, 25.0 / 16.0);
-    launch_combine3<R>(s, X1, X1, c, nullptr, 1.0, 1.0 / tau, 0.0, nh);
+    launch_apply<R>(s, true, T1, X1, N, h, p->cscal + 0, 2 * nf, 2 * nf, nullptr, m2);
+    launch_apply<R>(s, true, T2, X2, N, h, p->cpsih, 2, 2 * nf, cv, m2);
+    launch_combine3<R>(s, Rb, B1, T1, T2, 1.0, -1.0, -1.0, nh, nq2, m2);
+    cpx<R>* c = chebyshev<R>(s, true, N, 2 * nf, (cpx<R>*)p->C1, (cpx<R>*)p->C2, Rb, p->o.n_cheb, 0.25, 25.0 / 16.0,
+                             m2);
+    launch_combine3<R>(s, X1, X1, c, nullptr, 1.0, 1.0 / tau, 0.0, nh, nq2, m2);
     // x2 -= mu^{-1} S^^{-1} (b2 - Psi x1 + tau/beta M x2)
-    launch_apply<R>(s, true, T1, X1, N, h, p->cpsi, 2, 2 * nf, cv);
-    launch_apply<R>(s, true, T2, X2, N, h, p->cscal + 1, 2 * nf, 2 * nf, nullptr);
-    launch_combine3<R>(s, Rb, B2, T1, T2, 1.0, -1.0, 1.0, nh);
+    launch_apply<R>(s, true, T1, X1, N, h, p->cpsi, 2, 2 * nf, cv, m2);
+    launch_apply<R>(s, true, T2, X2, N, h, p->cscal + 1, 2 * nf, 2 * nf, nullptr, m2);
+    launch_combine3<R>(s, Rb, B2, T1, T2, 1.0, -1.0, 1.0, nh, nq2, m2);
     mg_solve<R>(s, p->mgQ, T1, Rb, cyc);                                   // Q_j^{-1}
-    launch_apply<R>(s, true, T2, T1, N, h, p->cscal + 2, 2 * nf, 2 * nf, nullptr);   // M
+    launch_apply<R>(s, true, T2, T1, N, h, p->cscal + 2, 2 * nf, 2 * nf, nullptr, m2);   // M
     mg_solve<R>(s, p->mgQH, T1, T2, cyc);                                  // Q_j^{-H}
-    launch_combine3<R>(s, X2, X2, T1, nullptr, 1.0, -tau / p->o.mu_uzawa, 0.0, nh);
+    launch_combine3<R>(s, X2, X2, T1, nullptr, 1.0, -tau / p->o.mu_uzawa, 0.0, nh, nq2, m2);
   }
-  launch_block_copy<R>(s, outV, X1, N, nf, 0, 1);
-  launch_block_copy<R>(s, outV, X2, N, nf, 1, 1);
+  launch_block_copy<R>(s, outV, X1, N, nf, 0, 1, m2);
+  launch_block_copy<R>(s, outV, X2, N, nf, 1, 1, m2);
   // Schur step on the pressure fields
   cpx<R>*Pt = (cpx<R>*)p->Pt, *Ub = (cpx<R>*)p->Ub, *z = (cpx<R>*)p->Ptmp;
-  launch_schur_rhs<R>(s, Pt, inP, X1, X2, N, nf, tau);            // (r3 - tau B y2, r4 - tau B y1)
-  launch_unpin_copy<R>(s, z, Pt, p->np2, 2 * nf);
-  cpx<R>* zz = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25);
-  launch_oseen_hp<R>(s, Ub, zz, N, nf, p->dj, tau, p->d.beta, p->d.nu, p->conv1);
-  launch_unpin_copy<R>(s, z, Ub, p->np2, 2 * nf);
+  launch_schur_rhs<R>(s, Pt, inP, X1, X2, N, nf, tau, m2);       // (r3 - tau B y2, r4 - tau B y1)
+  launch_unpin_copy<R>(s, z, Pt, p->np2, 2 * nf, m2);
+  cpx<R>* zz = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25, m2);
+  launch_oseen_hp<R>(s, Ub, zz, N, nf, p->dj, tau, p->d.beta, p->d.nu, p->conv1, p->mk(1));
+  launch_unpin_copy<R>(s, z, Ub, p->np2, 2 * nf, m2);
   mg_solve<R>(s, p->mgK, (cpx<R>*)p->PxK, z, cyc);
-  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, (cpx<R>*)p->PxK, p->abO, 2 * nf, p->np2, 2 * nf);
+  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, (cpx<R>*)p->PxK, p->abO, 2 * nf, p->np2, 2 * nf, m2);
 }
 
 // block preconditioner of the flow: P~_j (Stokes) or P~_j^(UZ) (Oseen)
@@ -739,7 +751,7 @@ template <typename R>
 static void block_matvec(pintoc_problem* p, hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV,
                          const cpx<R>* xP) {
   launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, p->d.flow == PINTOC_OSEEN ? p->conv2[0] : nullptr,
-                      p->block_scale);
+                      p->block_scale, p->mk(2));
 }
 
 // complex Givens rotation (c real) with [c, s; -conj(s), c] [a; b] = [r; 0]
@@ -777,8 +789,22 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     return PINTOC_OK;
   };
   int rc;
+  // the mask in force for the block operations: frequencies still iterating
+  auto set_mask = [&](const std::vector<int>& on) -> int {
+    p->mask_h = on;
+    HIPCHK(hipMemcpyAsync(p->maskd, p->mask_h.data(), sizeof(int) * nf, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    p->cur_mask = p->maskd;
+    for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) m->mask = p->maskd;
+    return PINTOC_OK;
+  };
+  auto clear_mask = [&]() {
+    p->cur_mask = nullptr;
+    for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) m->mask = nullptr;
+  };
+  clear_mask();
   // ||s_j||
-  launch_fdot<R>(s, SV, SP, 0, 0, 1, SV, SP, segV, segP, nf, p->fpart, p->hdev);
+  launch_fdot<R>(s, SV, SP, 0, 0, 1, SV, SP, segV, segP, nf, p->fpart, p->hdev, kAll);
   if ((rc = fetch(p->hdev, hb, 1))) return rc;
   std::vector<double> bnorm(nf), rnorm(nf);
   std::vector<int> done(nf, 0), its(nf, 0);
@@ -797,10 +823,13 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     bool any = false;
     for (int j = 0; j < nf; ++j) any |= !done[j];
     if (!any || total >= p->o.inner_maxit) break;
-    // v_0 = r / ||r|| (frequencies already done get a zero basis)
+    // v_0 = r / ||r|| for the frequencies still running
+    std::vector<int> running(nf);
+    for (int j = 0; j < nf; ++j) running[j] = !done[j];
+    if ((rc = set_mask(running))) return rc;
     for (int j = 0; j < nf; ++j) scl[j] = make_double2(done[j] ? 0.0 : 1.0 / rnorm[j], 0.0);
     if ((rc = upload(p->ydev, scl, 1))) return rc;
-    launch_fscale<R>(s, BVk(0), BPk(0), RV, RP, p->ydev, segV, segP, nf);
+    launch_fscale<R>(s, BVk(0), BPk(0), RV, RP, p->ydev, segV, segP, nf, p->mk(1));
     std::vector<int> kj(nf, 0), active(nf);
     for (int j = 0; j < nf; ++j) {
       active[j] = !done[j];
@@ -811,12 +840,13 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     for (; k < m && total < p->o.inner_maxit; ++k) {
       block_precond<R>(p, s, BVk(k), BPk(k), ZV, ZP);
       block_matvec<R>(p, s, BVk(k + 1), BPk(k + 1), ZV, ZP);
-      launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->hdev);
-      launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->hdev, segV, segP, nf, 1.0);
-      launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->h2dev);
-      launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->h2dev, segV, segP, nf, 1.0);
+      const Mask m1 = p->mk(1);
+      launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->hdev, m1);
+      launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->hdev, segV, segP, nf, 1.0, m1);
+      launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->h2dev, m1);
+      launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->h2dev, segV, segP, nf, 1.0, m1);
       launch_fdot<R>(s, BVk(k + 1), BPk(k + 1), 0, 0, 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart,
-                     p->ydev);
+                     p->ydev, m1);
       if ((rc = fetch(p->hdev, hb, k + 1)) || (rc = fetch(p->h2dev, hb2, k + 1))) return rc;
       std::vector<double2> nr(nf);
       if ((rc = fetch(p->ydev, nr, 1))) return rc;
@@ -850,11 +880,12 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
         if (std::abs(gj[k + 1]) <= p->o.inner_tol * bnorm[j] || hk1 == 0.0) { active[j] = 0; done[j] = 1; }
       }
       if ((rc = upload(p->ydev, scl, 1))) return rc;
-      launch_fscale<R>(s, BVk(k + 1), BPk(k + 1), BVk(k + 1), BPk(k + 1), p->ydev, segV, segP, nf);
+      launch_fscale<R>(s, BVk(k + 1), BPk(k + 1), BVk(k + 1), BPk(k + 1), p->ydev, segV, segP, nf, m1);
       ++total;
       bool any_active = false;
       for (int j = 0; j < nf; ++j) any_active |= active[j] != 0;
       if (!any_active) { ++k; break; }
+      if (active != p->mask_h && (rc = set_mask(active))) return rc;     // drop converged frequencies
     }
     // y_j = H_j^{-1} g_j (size kj), U = sum_i y_ij v_i, X += P~^{-1} U
     std::fill(yv.begin(), yv.end(), make_double2(0, 0));
@@ -871,29 +902,33 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
       for (int i = 0; i < kk; ++i) yv[(size_t)i * nf + j] = make_double2(y[i].real(), y[i].imag());
     }
     if ((rc = upload(p->ydev, yv, k))) return rc;
+    if ((rc = set_mask(running))) return rc;                 // every frequency that ran in this cycle
     launch_fill_zero(s, UV, (size_t)segV * nf * sizeof(cpx<R>));
     launch_fill_zero(s, UP, (size_t)segP * nf * sizeof(cpx<R>));
-    launch_fupdate<R>(s, UV, UP, BV, BP, ldV, ldP, k, p->ydev, segV, segP, nf, -1.0);
+    launch_fupdate<R>(s, UV, UP, BV, BP, ldV, ldP, k, p->ydev, segV, segP, nf, -1.0, p->mk(1));
     block_precond<R>(p, s, UV, UP, ZV, ZP);
     for (int j = 0; j < nf; ++j) scl[j] = make_double2(1.0, 0.0);
     if ((rc = upload(p->hdev, scl, 1))) return rc;
-    launch_fupdate<R>(s, XV, XP, ZV, ZP, 0, 0, 1, p->hdev, segV, segP, nf, -1.0);      // X += P~^{-1} U
+    launch_fupdate<R>(s, XV, XP, ZV, ZP, 0, 0, 1, p->hdev, segV, segP, nf, -1.0, p->mk(1));   // X += P~^{-1} U
     bool any_left = false;
     for (int j = 0; j < nf; ++j) any_left |= !done[j];
     if (!any_left || total >= p->o.inner_maxit) break;
     // restart: r = s - Z x for the frequencies still running
+    for (int j = 0; j < nf; ++j) running[j] = !done[j];
+    if ((rc = set_mask(running))) return rc;
     block_matvec<R>(p, s, UV, UP, XV, XP);
     for (int j = 0; j < nf; ++j) scl[j] = make_double2(-1.0, 0.0);
     if ((rc = upload(p->hdev, scl, 1))) return rc;
-    launch_fscale<R>(s, UV, UP, UV, UP, p->hdev, segV, segP, nf);
+    launch_fscale<R>(s, UV, UP, UV, UP, p->hdev, segV, segP, nf, p->mk(1));
     for (int j = 0; j < nf; ++j) scl[j] = make_double2(1.0, 0.0);
     if ((rc = upload(p->h2dev, scl, 1))) return rc;
-    launch_fupdate<R>(s, UV, UP, SV, SP, 0, 0, 1, p->h2dev, segV, segP, nf, -1.0);     // U = s - Z x
-    launch_fdot<R>(s, UV, UP, 0, 0, 1, UV, UP, segV, segP, nf, p->fpart, p->hdev);
+    launch_fupdate<R>(s, UV, UP, SV, SP, 0, 0, 1, p->h2dev, segV, segP, nf, -1.0, p->mk(1));   // U = s - Z x
+    launch_fdot<R>(s, UV, UP, 0, 0, 1, UV, UP, segV, segP, nf, p->fpart, p->hdev, p->mk(1));
     if ((rc = fetch(p->hdev, hb, 1))) return rc;
     for (int j = 0; j < nf; ++j) rnorm[j] = std::sqrt(std::max(hb[j].x, 0.0));
     RV = UV; RP = UP;
   }
+  clear_mask();
   p->last_its = its;
   for (int j = 0; j < nf; ++j) {
     p->inner_its_sum += its[j];
