@@ -174,16 +174,20 @@ int64_t pintoc_vector_length(const pintoc_problem* p);
 int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* counts, int32_t n);
 
 /* Live timing of the dominant kernel, for roofline reports: the fine-grid
- * smoothing sweep of the velocity multigrid (the tiled Gauss-Seidel sweep of
- * section 3.4 applied to W_j on all kept frequencies at once).  While enabled,
- * each such launch is bracketed by HIP events recorded on the stream it runs
- * on; the most recent 4096 launches are kept.  Enabling allocates the events
- * (host-side HIP objects, no device memory from the workspace). */
+ * pre-smoothing sweep of the velocity multigrid (the tiled Gauss-Seidel sweep
+ * of section 3.4 applied to W_j (Stokes) or Q_j (Oseen) on all kept
+ * frequencies at once).  While enabled, each such launch is bracketed by HIP
+ * events recorded on the stream it runs on; the most recent 4096 launches are
+ * kept.  Enabling allocates the events (host-side HIP objects, no device
+ * memory from the workspace). */
 typedef struct {
   double avg_ms;             /* mean duration of the timed launches           */
   int64_t launches;          /* number of launches averaged (<= 4096)         */
-  double algorithmic_bytes;  /* compulsory bytes of one launch: read x, read b,
-                                write x over all grids of the batch           */
+  double algorithmic_bytes;  /* mean compulsory bytes of one launch over the
+                                grids it updates (frequencies skipped by the
+                                inner GMRES excluded): read b, read x (not on
+                                the first V-cycle, which starts from x = 0),
+                                write x                                       */
 } pintoc_kernel_timing;
 
 /* enable != 0 starts a new recording (clears previous samples); 0 stops.

@@ -16,10 +16,14 @@ template <typename R>
 void launch_time_fft_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double* z, int nt, int L, int nq2,
                          int np2, const double2* tw, const double2* tj, double tau, int mode);
 
-// per-frequency operators and multigrid pieces (mg_kernels.hip)
+// per-frequency operators and multigrid pieces (mg_kernels.hip).  For Q2
+// grids ``conv`` is a convection table in the tile layout of
+// q2_tile_conv_table (one operator half, scaled by coef.eta); for Q1 grids it
+// is the per-node table of 9 + 9 values (coef.eta, coef.etat).
 template <typename R>
-void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, int n, double h,
-                       const OpCoef* coef, int fpc, int nb, const double* conv, bool forward, Mask mk);
+void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, const cpx<R>* ec,
+                       int n, double h, const OpCoef* coef, int fpc, int nb, const double* conv, bool forward,
+                       Mask mk);
 template <typename R>
 void launch_residual(hipStream_t s, bool q2, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
                      const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk);
@@ -29,8 +33,6 @@ void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, dou
 template <typename R>
 void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk);
 template <typename R>
-void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* xf, const cpx<R>* ec, int nc, int nb, Mask mk);
-template <typename R>
 void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb, Mask mk);
 template <typename R>
 void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
@@ -38,6 +40,16 @@ void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<
 template <typename R>
 void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, const cpx<R>* yM, const double2* ab,
                               int fpc, int nn, int nb, Mask mk);
+
+// Q2 tile kernels (q2_tiles.hip)
+template <typename R>
+void launch_q2_sweep(hipStream_t s, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, const cpx<R>* ec, int n, double h,
+                     const OpCoef* coef, int fpc, int nb, const double* tconv, bool forward, Mask mk);
+template <typename R>
+void launch_q2_apply(hipStream_t s, cpx<R>* out, const cpx<R>* x, const cpx<R>* b, int n, double h,
+                     const OpCoef* coef, int fpc, int nb, const double* tconv, Mask mk);
+size_t q2_tile_conv_entries(int n);
+void q2_tile_conv_table(int n, const double* t50, int half, double* out);
 
 // all-at-once matrix, rhs, FP64 vector kernels (kkt_kernels.hip)
 void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,

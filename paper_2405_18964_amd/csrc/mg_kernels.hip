@@ -116,92 +116,40 @@ __device__ inline void q1_apply_node(const cpx<R>* __restrict__ x, int n, int ix
   diag.x = (R)dr; diag.y = (R)di;
 }
 
+// (P e)(i, j) of the Q1 prolongation from the coarse grid (npc nodes per side):
+// fine node i takes coarse i/2 (i even) or the mean of (i-1)/2 and (i+1)/2.
+template <typename R>
+__device__ inline double2 q1_prolong_at(const cpx<R>* __restrict__ ec, int npc, int i, int j) {
+  const int ia = i >> 1, ib = (i + 1) >> 1, ja = j >> 1, jb = (j + 1) >> 1;
+  const double wx = (i & 1) ? 0.5 : 1.0, wy = (j & 1) ? 0.5 : 1.0;
+  const int nxs = (i & 1) ? 2 : 1, nys = (j & 1) ? 2 : 1;
+  double sr = 0, si = 0;
+  for (int a = 0; a < nys; ++a) {
+    const int cy = a == 0 ? ja : jb;
+    for (int q = 0; q < nxs; ++q) {
+      const int cx = q == 0 ? ia : ib;
+      const cpx<R> v = ec[(size_t)cy * npc + cx];
+      sr += wx * wy * (double)v.x;
+      si += wx * wy * (double)v.y;
+    }
+  }
+  return make_double2(sr, si);
+}
+
 // ------------------------------------------------------ tiled GS sweeps
 // Symmetric multicolour Gauss-Seidel inside square tiles, block Jacobi between
 // tiles (a distributed SOR with one tile per subdomain).  A work-group owns
 // one tile of one grid: it loads the tile and a halo into LDS, runs every
 // colour in LDS (neighbour tiles keep the values the sweep started from), and
-// writes the tile to xo.  xi and xo must be different buffers.
-constexpr int kT2 = 48, kL2 = kT2 + 4;       // Q2 tile and LDS side (halo 2)
+// writes the tile to xo.  xi and xo must be different buffers; xi == nullptr
+// starts from x = 0, ec != nullptr adds the prolonged coarse correction P ec
+// on load.  The Q2 sweep (and Q2 operator application) live in q2_tiles.hip.
 constexpr int kT1 = 32, kL1 = kT1 + 2;       // Q1 tile and LDS side (halo 1)
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_q2_tile_sweep(cpx<R>* __restrict__ xo, const cpx<R>* __restrict__ xi,
-                                                       const cpx<R>* __restrict__ b, int n, double h,
-                                                       const OpCoef* __restrict__ coef, int fpc,
-                                                       const double* __restrict__ conv, int forward, int ntx, Mask mk) {
-  __shared__ cpx<R> sx[kL2 * kL2];
-  const int f = blockIdx.y;
-  if (mk.off(f)) return;
-  const int X0 = (blockIdx.x % ntx) * kT2, Y0 = (blockIdx.x / ntx) * kT2;
-  const int nq = 2 * n + 1;
-  const size_t off = (size_t)f * nq * nq;
-  for (int e = threadIdx.x; e < kL2 * kL2; e += blockDim.x) {
-    const int gx = X0 - 2 + e % kL2, gy = Y0 - 2 + e / kL2;
-    sx[e] = (gx >= 0 && gx < nq && gy >= 0 && gy < nq) ? xi[off + (size_t)gy * nq + gx] : cmk<cpx<R>>(0, 0);
-  }
-  const OpCoef c = coef[f / fpc];
-  __syncthreads();
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  for (int k = 0; k < 9; ++k) {
-    const int col = forward ? k : 8 - k;
-    const int lx = col % 3 + 3 * tx, ly = col / 3 + 3 * ty;
-    const int gx = X0 + lx, gy = Y0 + ly;
-    if (gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2) {
-      double mx[5], kx[5], my[5], ky[5];
-      q2_rows(gx, h, mx, kx);
-      q2_rows(gy, h, my, ky);
-      double amr = 0, ami = 0, akr = 0, aki = 0;
-#pragma unroll
-      for (int dy = 0; dy < 5; ++dy) {
-        const cpx<R>* row = sx + (ly + dy) * kL2 + lx;
-        double smr = 0, smi = 0, skr = 0, ski = 0;
-#pragma unroll
-        for (int dx = 0; dx < 5; ++dx) {
-          const cpx<R> v = row[dx];
-          smr += mx[dx] * (double)v.x; smi += mx[dx] * (double)v.y;
-          skr += kx[dx] * (double)v.x; ski += kx[dx] * (double)v.y;
-        }
-        amr += my[dy] * smr; ami += my[dy] * smi;
-        akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
-      }
-      double rr = c.alpha.x * amr - c.alpha.y * ami + c.gamma.x * akr - c.gamma.y * aki;
-      double ri = c.alpha.x * ami + c.alpha.y * amr + c.gamma.x * aki + c.gamma.y * akr;
-      const double md = mx[2] * my[2], kd = kx[2] * my[2] + mx[2] * ky[2];
-      double dr = c.alpha.x * md + c.gamma.x * kd, di = c.alpha.y * md + c.gamma.y * kd;
-      if (conv) {
-        const double* cn = conv + (size_t)(gy * nq + gx) * 50;
-        double nr = 0, ni = 0, tr = 0, ti = 0;
-        for (int dy = 0; dy < 5; ++dy)
-          for (int dx = 0; dx < 5; ++dx) {
-            const cpx<R> v = sx[(ly + dy) * kL2 + lx + dx];
-            const double a = cn[dy * 5 + dx], bb = cn[25 + dy * 5 + dx];
-            nr += a * (double)v.x; ni += a * (double)v.y;
-            tr += bb * (double)v.x; ti += bb * (double)v.y;
-          }
-        rr += c.eta.x * nr - c.eta.y * ni + c.etat.x * tr - c.etat.y * ti;
-        ri += c.eta.x * ni + c.eta.y * nr + c.etat.x * ti + c.etat.y * tr;
-        dr += c.eta.x * cn[12] + c.etat.x * cn[37];
-        di += c.eta.y * cn[12] + c.etat.y * cn[37];
-      }
-      const cpx<R> bi = b[off + (size_t)gy * nq + gx];
-      const double er = (double)bi.x - rr, ei = (double)bi.y - ri;
-      const double den = dr * dr + di * di;
-      cpx<R>& xs = sx[(ly + 2) * kL2 + lx + 2];
-      xs = cmk<cpx<R>>((double)xs.x + (er * dr + ei * di) / den, (double)xs.y + (ei * dr - er * di) / den);
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < kT2 * kT2; e += blockDim.x) {
-    const int gx = X0 + e % kT2, gy = Y0 + e / kT2;
-    if (gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2)
-      xo[off + (size_t)gy * nq + gx] = sx[(e / kT2 + 2) * kL2 + e % kT2 + 2];
-  }
-}
-
-template <typename R>
 __global__ __launch_bounds__(256) void k_q1_tile_sweep(cpx<R>* __restrict__ xo, const cpx<R>* __restrict__ xi,
-                                                       const cpx<R>* __restrict__ b, int n, double h,
+                                                       const cpx<R>* __restrict__ b, const cpx<R>* __restrict__ ec,
+                                                       int n, double h,
                                                        const OpCoef* __restrict__ coef, int fpc,
                                                        const double* __restrict__ conv, int forward, int ntx, Mask mk) {
   __shared__ cpx<R> sx[kL1 * kL1];
@@ -210,9 +158,19 @@ __global__ __launch_bounds__(256) void k_q1_tile_sweep(cpx<R>* __restrict__ xo, 
   const int X0 = (blockIdx.x % ntx) * kT1, Y0 = (blockIdx.x / ntx) * kT1;
   const int np = n + 1;
   const size_t off = (size_t)f * np * np;
+  const int npc = n / 2 + 1;
+  const cpx<R>* ecf = ec ? ec + (size_t)f * npc * npc : nullptr;
   for (int e = threadIdx.x; e < kL1 * kL1; e += blockDim.x) {
     const int gx = X0 - 1 + e % kL1, gy = Y0 - 1 + e / kL1;
-    sx[e] = (gx >= 0 && gx <= n && gy >= 0 && gy <= n) ? xi[off + (size_t)gy * np + gx] : cmk<cpx<R>>(0, 0);
+    cpx<R> v = cmk<cpx<R>>(0, 0);
+    if (gx >= 0 && gx <= n && gy >= 0 && gy <= n) {
+      if (xi) v = xi[off + (size_t)gy * np + gx];
+      if (ecf) {
+        const double2 p = q1_prolong_at<R>(ecf, npc, gx, gy);
+        v = cmk<cpx<R>>((double)v.x + p.x, (double)v.y + p.y);
+      }
+    }
+    sx[e] = v;
   }
   const OpCoef c = coef[f / fpc];
   __syncthreads();
@@ -270,23 +228,6 @@ __global__ __launch_bounds__(256) void k_q1_tile_sweep(cpx<R>* __restrict__ xo, 
 
 // ------------------------------------------------------ residual r = b - A x
 template <typename R>
-__global__ __launch_bounds__(256) void k_q2_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
-                              int n, double h, const OpCoef* __restrict__ coef, int fpc,
-                              const double* __restrict__ conv, Mask mk) {
-  const int f = blockIdx.y;
-  if (mk.off(f)) return;
-  const int nq = 2 * n + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nq * nq) return;
-  const int ix = t % nq, iy = t / nq;
-  const size_t i = (size_t)f * nq * nq + t;
-  if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) { r[i] = cmk<cpx<R>>(0, 0); return; }
-  cpx<R> ax, dg;
-  q2_apply_node<R>(x + (size_t)f * nq * nq, nq, ix, iy, h, coef[f / fpc], conv, ax, dg);
-  r[i] = b[i] - ax;
-}
-
-template <typename R>
 __global__ __launch_bounds__(256) void k_q1_residual(cpx<R>* __restrict__ r, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ b,
                               int n, double h, const OpCoef* __restrict__ coef, int fpc,
                               const double* __restrict__ conv, Mask mk) {
@@ -303,22 +244,6 @@ __global__ __launch_bounds__(256) void k_q1_residual(cpx<R>* __restrict__ r, con
 }
 
 // y = A x (operator application; b = 0 residual form negated)
-template <typename R>
-__global__ __launch_bounds__(256) void k_q2_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
-                           const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv, Mask mk) {
-  const int f = blockIdx.y;
-  if (mk.off(f)) return;
-  const int nq = 2 * n + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nq * nq) return;
-  const int ix = t % nq, iy = t / nq;
-  const size_t i = (size_t)f * nq * nq + t;
-  if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) { y[i] = cmk<cpx<R>>(0, 0); return; }
-  cpx<R> ax, dg;
-  q2_apply_node<R>(x + (size_t)f * nq * nq, nq, ix, iy, h, coef[f / fpc], conv, ax, dg);
-  y[i] = ax;
-}
-
 template <typename R>
 __global__ __launch_bounds__(256) void k_q1_apply(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, int n, double h,
                            const OpCoef* __restrict__ coef, int fpc, const double* __restrict__ conv, Mask mk) {
@@ -373,49 +298,6 @@ __global__ __launch_bounds__(256) void k_q2_restrict(cpx<R>* __restrict__ bc, co
   bc[oc] = cmk<cpx<R>>(sr, si);
 }
 
-// 1-D Q2 prolongation weights of fine node i onto coarse nodes 2e, 2e+1, 2e+2 (e = i/4).
-__device__ inline void q2_prolong_w(int i, int& c0, double w[3]) {
-  const int e = i >> 2, r = i & 3;
-  c0 = 2 * e;
-  if (r == 0) { w[0] = 1; w[1] = 0; w[2] = 0; }
-  else if (r == 2) { w[0] = 0; w[1] = 1; w[2] = 0; }
-  else if (r == 1) { w[0] = 0.375; w[1] = 0.75; w[2] = -0.125; }
-  else { w[0] = -0.125; w[1] = 0.75; w[2] = 0.375; }
-}
-
-// xf += P ec on fine interior nodes.
-template <typename R>
-__global__ __launch_bounds__(256) void k_q2_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc, Mask mk) {
-  const int f = blockIdx.y;
-  if (mk.off(f)) return;
-  const int nqc = 2 * nc + 1, nqf = 4 * nc + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nqf * nqf) return;
-  const int i = t % nqf, j = t / nqf;
-  if (i == 0 || j == 0 || i == nqf - 1 || j == nqf - 1) return;
-  int cx0, cy0;
-  double wx[3], wy[3];
-  q2_prolong_w(i, cx0, wx);
-  q2_prolong_w(j, cy0, wy);
-  const cpx<R>* src = ec + (size_t)f * nqc * nqc;
-  double sr = 0, si = 0;
-  for (int a = 0; a < 3; ++a) {
-    if (wy[a] == 0.0) continue;
-    double rr = 0, ri = 0;
-    for (int b2 = 0; b2 < 3; ++b2) {
-      if (wx[b2] == 0.0) continue;
-      const int cx = cx0 + b2, cy = cy0 + a;
-      const cpx<R> v = src[(size_t)cy * nqc + cx];
-      rr += wx[b2] * (double)v.x; ri += wx[b2] * (double)v.y;
-    }
-    sr += wy[a] * rr; si += wy[a] * ri;
-  }
-  const size_t o = (size_t)f * nqf * nqf + t;
-  cpx<R> v = xf[o];
-  v.x = (R)((double)v.x + sr); v.y = (R)((double)v.y + si);
-  xf[o] = v;
-}
-
 // Q1: bc = P^T rf (coarse node I <-> fine 2I, weights 1/2, 1, 1/2).
 template <typename R>
 __global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc, Mask mk) {
@@ -439,34 +321,6 @@ __global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, co
     }
   }
   bc[(size_t)f * npc * npc + t] = cmk<cpx<R>>(sr, si);
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_q1_prolong_add(cpx<R>* __restrict__ xf, const cpx<R>* __restrict__ ec, int nc, Mask mk) {
-  const int f = blockIdx.y;
-  if (mk.off(f)) return;
-  const int npc = nc + 1, npf = 2 * nc + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= npf * npf) return;
-  const int i = t % npf, j = t / npf;
-  const cpx<R>* src = ec + (size_t)f * npc * npc;
-  const int ia = i >> 1, ib = (i + 1) >> 1, ja = j >> 1, jb = (j + 1) >> 1;
-  const double wx = (i & 1) ? 0.5 : 1.0, wy = (j & 1) ? 0.5 : 1.0;
-  double sr = 0, si = 0;
-  // (i odd) -> average of ia, ib; (i even) -> ia == ib, weight 1 counted once
-  const int nxs = (i & 1) ? 2 : 1, nys = (j & 1) ? 2 : 1;
-  for (int a = 0; a < nys; ++a) {
-    const int cy = a == 0 ? ja : jb;
-    for (int b2 = 0; b2 < nxs; ++b2) {
-      const int cx = b2 == 0 ? ia : ib;
-      const cpx<R> v = src[(size_t)cy * npc + cx];
-      sr += wx * wy * (double)v.x; si += wx * wy * (double)v.y;
-    }
-  }
-  const size_t o = (size_t)f * npf * npf + t;
-  cpx<R> v = xf[o];
-  v.x = (R)((double)v.x + sr); v.y = (R)((double)v.y + si);
-  xf[o] = v;
 }
 
 // --------------------------------------------------------- coarsest grid
@@ -595,16 +449,15 @@ __global__ __launch_bounds__(256) void k_schur_combine_pin(cpx<R>* __restrict__ 
 static inline dim3 grid2(long work, int nb, int bs = 256) { return dim3((unsigned)((work + bs - 1) / bs), nb); }
 
 template <typename R>
-void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, int n, double h,
-                       const OpCoef* coef, int fpc, int nb, const double* conv, bool forward, Mask mk) {
+void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, const cpx<R>* ec,
+                       int n, double h, const OpCoef* coef, int fpc, int nb, const double* conv, bool forward,
+                       Mask mk) {
   if (q2) {
-    const int nq = 2 * n + 1, ntx = (nq + kT2 - 1) / kT2;
-    hipLaunchKernelGGL(k_q2_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, n, h, coef, fpc, conv,
-                       forward ? 1 : 0, ntx, mk);
+    launch_q2_sweep<R>(s, xo, xi, b, ec, n, h, coef, fpc, nb, conv, forward, mk);
   } else {
     const int np = n + 1, ntx = (np + kT1 - 1) / kT1;
-    hipLaunchKernelGGL(k_q1_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, n, h, coef, fpc, conv,
-                       forward ? 1 : 0, ntx, mk);
+    hipLaunchKernelGGL(k_q1_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, ec, n, h, coef, fpc,
+                       conv, forward ? 1 : 0, ntx, mk);
   }
 }
 
@@ -612,8 +465,7 @@ template <typename R>
 void launch_residual(hipStream_t s, bool q2, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
                      const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk) {
   if (q2) {
-    const int nq = 2 * n + 1;
-    hipLaunchKernelGGL(k_q2_residual<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv, mk);
+    launch_q2_apply<R>(s, r, x, b, n, h, coef, fpc, nb, conv, mk);
   } else {
     const int np = n + 1;
     hipLaunchKernelGGL(k_q1_residual<R>, grid2((long)np * np, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv, mk);
@@ -624,8 +476,7 @@ template <typename R>
 void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, double h, const OpCoef* coef,
                   int fpc, int nb, const double* conv, Mask mk) {
   if (q2) {
-    const int nq = 2 * n + 1;
-    hipLaunchKernelGGL(k_q2_apply<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv, mk);
+    launch_q2_apply<R>(s, y, x, nullptr, n, h, coef, fpc, nb, conv, mk);
   } else {
     const int np = n + 1;
     hipLaunchKernelGGL(k_q1_apply<R>, grid2((long)np * np, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv, mk);
@@ -640,17 +491,6 @@ void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int n
   } else {
     const int npc = nc + 1;
     hipLaunchKernelGGL(k_q1_restrict<R>, grid2((long)npc * npc, nb), dim3(256), 0, s, bc, rf, nc, mk);
-  }
-}
-
-template <typename R>
-void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* xf, const cpx<R>* ec, int nc, int nb, Mask mk) {
-  if (q2) {
-    const int nqf = 4 * nc + 1;
-    hipLaunchKernelGGL(k_q2_prolong_add<R>, grid2((long)nqf * nqf, nb), dim3(256), 0, s, xf, ec, nc, mk);
-  } else {
-    const int npf = 2 * nc + 1;
-    hipLaunchKernelGGL(k_q1_prolong_add<R>, grid2((long)npf * npf, nb), dim3(256), 0, s, xf, ec, nc, mk);
   }
 }
 
@@ -681,14 +521,13 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
 }
 
 #define PINTOC_INST(R)                                                                                        \
-  template void launch_tile_sweep<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,        \
-                                     const OpCoef*, int, int, const double*, bool, Mask);                            \
+  template void launch_tile_sweep<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, \
+                                     double, const OpCoef*, int, int, const double*, bool, Mask);                    \
   template void launch_residual<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,       \
                                    const OpCoef*, int, int, const double*, Mask);                                    \
   template void launch_apply<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
                                 const double*, Mask);                                                                \
   template void launch_restrict<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int, Mask);                       \
-  template void launch_prolong_add<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int, Mask);                    \
   template void launch_coarse<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const double2*, int, int, Mask);         \
   template void launch_cheb<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int,    \
                                double, double, double, int, int, Mask);                                              \

@@ -28,14 +28,16 @@ static int fail(int code, const std::string& msg) { g_err = msg; return code; }
 
 // ------------------------------------------------------------ timing probe
 // Ring of HIP event pairs around launches of the dominant kernel.
+// Algorithmic bytes of each timed launch are kept beside its events.
 struct Probe {
   static constexpr int kCap = 4096;
   std::vector<hipEvent_t> e0, e1;
+  std::vector<double> bytes;
   long count = 0;
   bool on = false;
   int create() {
     if (!e0.empty()) return PINTOC_OK;
-    e0.resize(kCap); e1.resize(kCap);
+    e0.resize(kCap); e1.resize(kCap); bytes.assign(kCap, 0.0);
     for (int i = 0; i < kCap; ++i) {
       if (hipEventCreate(&e0[i]) != hipSuccess || hipEventCreate(&e1[i]) != hipSuccess) return PINTOC_EHIP;
     }
@@ -55,17 +57,19 @@ struct MGPlan {
   int nb = 0;           // grids in the batch
   int fpc = 1;          // grids per coefficient set
   int ncoef = 0;
-  std::vector<OpCoef> coef_h;
+  std::vector<OpCoef> coef_h;          // eta scales N, etat scales N^T (coarsest inverses)
+  std::vector<OpCoef> coef_dev_h;      // as uploaded: Q2 tile kernels apply eta to the plan's one table
   std::vector<double2> inv_h;          // coarsest inverses, per coefficient set
   OpCoef* coef = nullptr;              // device
   double2* inv = nullptr;              // device
-  std::vector<const double*> conv;     // per level (device) or null
+  std::vector<const double*> conv;     // per level (device, tile layout for Q2) or null
   // per-level device buffers (complex, precision-typed): b, x (level >= 1),
   // t (second iterate buffer of the out-of-place smoother), r (residual)
   std::vector<void*> b, x, r, t;
   Probe* probe = nullptr;              // times the finest-level sweeps when on
   int fpj = 1;                         // grids per frequency in the batch
   const int* mask = nullptr;           // per-frequency activity (inner GMRES), or null
+  int active = 0;                      // grids of the batch that the mask leaves active
   Mask mk() const { return Mask{mask, fpj}; }
   int n(int l) const { return N >> l; }
   size_t nodes(int l) const {
@@ -105,7 +109,9 @@ struct pintoc_problem {
   // operator tables of the Uzawa steps and the Schur step
   std::vector<std::vector<double>> conv2_h;   // per level, 50 per Q2 node
   std::vector<double> conv1_h;                // finest Q1 grid, 18 per node
-  std::vector<double*> conv2;
+  std::vector<std::vector<double>> tconv_h[2];  // per level below the coarsest: N, N^T in tile layout
+  std::vector<double*> tconv[2];
+  double* conv50 = nullptr;                   // finest level, 50 per node (block and all-at-once matrices)
   double* conv1 = nullptr;
   MGPlan mgQ, mgQH;
   int* maskd = nullptr;                 // device mask of the batched inner GMRES
@@ -286,8 +292,12 @@ static void carve(pintoc_problem* p, char* base) {
   p->bc = cv.take<BlockCoef>(sizeof(BlockCoef) * nf);
   p->maskd = cv.take<int>(sizeof(int) * nf);
   if (p->d.flow == PINTOC_OSEEN) {
-    p->conv2.assign(p->conv2_h.size(), nullptr);
-    for (size_t l = 0; l < p->conv2_h.size(); ++l) p->conv2[l] = cv.take<double>(sizeof(double) * p->conv2_h[l].size());
+    p->conv50 = cv.take<double>(sizeof(double) * p->conv2_h[0].size());
+    for (int hf = 0; hf < 2; ++hf) {
+      p->tconv[hf].assign(p->tconv_h[hf].size(), nullptr);
+      for (size_t l = 0; l < p->tconv_h[hf].size(); ++l)
+        p->tconv[hf][l] = cv.take<double>(sizeof(double) * p->tconv_h[hf][l].size());
+    }
     p->conv1 = cv.take<double>(sizeof(double) * p->conv1_h.size());
     p->cpsi = cv.take<OpCoef>(sizeof(OpCoef) * nf);
     p->cpsih = cv.take<OpCoef>(sizeof(OpCoef) * nf);
@@ -298,7 +308,7 @@ static void carve(pintoc_problem* p, char* base) {
     for (void** q : {&p->B1, &p->B2, &p->X1, &p->X2, &p->T1, &p->T2, &p->Rb, &p->C1, &p->C2}) *q = cv.take<char>(hb);
     p->Pt = cv.take<char>(pbytes);
     p->Ub = cv.take<char>(pbytes);
-    for (size_t l = 0; l < p->conv2.size(); ++l) { p->mgQ.conv[l] = p->conv2[l]; p->mgQH.conv[l] = p->conv2[l]; }
+    for (size_t l = 0; l < p->tconv[0].size(); ++l) { p->mgQ.conv[l] = p->tconv[0][l]; p->mgQH.conv[l] = p->tconv[1][l]; }
     plan_mg_buffers(p->mgQ, cv, p->csize);
     plan_mg_buffers(p->mgQH, cv, p->csize);
   } else {
@@ -428,17 +438,17 @@ extern "C" int pintoc_profile_read(pintoc_problem* p, pintoc_kernel_timing* out)
   if (!p || !out) return fail(PINTOC_EINVAL, "NULL handle or output");
   const long n = std::min<long>(p->probe.count, Probe::kCap);
   if (n == 0) return fail(PINTOC_ESTATE, "no timed launches recorded");
-  double sum = 0;
+  double sum = 0, bytes = 0;
   for (long i = 0; i < n; ++i) {
     HIPCHK(hipEventSynchronize(p->probe.e1[i]));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, p->probe.e0[i], p->probe.e1[i]));
     sum += ms;
+    bytes += p->probe.bytes[i];
   }
   out->avg_ms = sum / n;
   out->launches = n;
-  const MGPlan& m = p->d.flow == PINTOC_OSEEN ? p->mgQ : p->mgW;
-  out->algorithmic_bytes = 3.0 * (double)m.nodes(0) * m.nb * (double)p->csize;
+  out->algorithmic_bytes = bytes / n;
   return PINTOC_OK;
 }
 
@@ -513,6 +523,11 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
           ly[(size_t)iy * nql + ix] = wy[(size_t)(iy * st) * nq + ix * st];
         }
       conv_tables(n, lx.data(), ly.data(), p->conv2_h[l], l == 0 ? &p->conv1_h : nullptr);
+      if (l + 1 < nl)
+        for (int hf = 0; hf < 2; ++hf) {
+          p->tconv_h[hf].emplace_back(q2_tile_conv_entries(n));
+          q2_tile_conv_table(n, p->conv2_h[l].data(), hf, p->tconv_h[hf].back().data());
+        }
     }
   }
   MGPlan& W = p->mgW;
@@ -539,7 +554,7 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
       // Psi = d M + tau L, Psi^H = conj(d) M + tau L^T (L = nu K + N);
       // Q_j = Psi + tau/sqrt(beta) M, Q_j^H = Psi^H + tau/sqrt(beta) M
       p->cpsi_h.push_back(mkcoef(dj, tau * nu, tau, 0.0));
-      p->cpsih_h.push_back(mkcoef(djc, tau * nu, 0.0, tau));
+      p->cpsih_h.push_back(mkcoef(djc, tau * nu, tau, 0.0));     // eta: applied to the N^T table
       p->mgQ.coef_h.push_back(mkcoef(dj + tau / sb, tau * nu, tau, 0.0));
       p->mgQH.coef_h.push_back(mkcoef(djc + tau / sb, tau * nu, 0.0, tau));
       p->dj_h.push_back(make_double2(dr, dc));
@@ -559,6 +574,15 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   for (MGPlan* m : plans) {
     m->nlev = nl;
     m->conv.assign(nl, nullptr);
+    m->active = m->nb;
+    for (OpCoef c : m->coef_h) {          // the Q2 tile kernels take the one nonzero half as eta
+      if (m->q2 && (c.etat.x != 0.0 || c.etat.y != 0.0)) {
+        if (c.eta.x != 0.0 || c.eta.y != 0.0) { delete p; return fail(PINTOC_EINVAL, "operator with N and N^T"); }
+        c.eta = c.etat;
+        c.etat = make_double2(0, 0);
+      }
+      m->coef_dev_h.push_back(c);
+    }
     const std::vector<double>* cc = (oseen && m->q2) ? &p->conv2_h[nl - 1] : nullptr;
     for (const OpCoef& c : m->coef_h)
       if (!coarse_inverse(m->q2, c, cc, m->inv_h)) { delete p; return fail(PINTOC_EINVAL, "singular coarse operator"); }
@@ -589,13 +613,16 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
   HIPCHK(hipMemcpyAsync(p->bc, p->bc_h.data(), sizeof(BlockCoef) * p->bc_h.size(), hipMemcpyHostToDevice, s));
   for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) {
     if (m->nlev == 0 || !m->coef) continue;
-    HIPCHK(hipMemcpyAsync(m->coef, m->coef_h.data(), sizeof(OpCoef) * m->coef_h.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(m->coef, m->coef_dev_h.data(), sizeof(OpCoef) * m->coef_dev_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(m->inv, m->inv_h.data(), sizeof(double2) * m->inv_h.size(), hipMemcpyHostToDevice, s));
   }
   if (p->d.flow == PINTOC_OSEEN) {
-    for (size_t l = 0; l < p->conv2.size(); ++l)
-      HIPCHK(hipMemcpyAsync(p->conv2[l], p->conv2_h[l].data(), sizeof(double) * p->conv2_h[l].size(),
-                            hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->conv50, p->conv2_h[0].data(), sizeof(double) * p->conv2_h[0].size(),
+                          hipMemcpyHostToDevice, s));
+    for (int hf = 0; hf < 2; ++hf)
+      for (size_t l = 0; l < p->tconv[hf].size(); ++l)
+        HIPCHK(hipMemcpyAsync(p->tconv[hf][l], p->tconv_h[hf][l].data(), sizeof(double) * p->tconv_h[hf][l].size(),
+                              hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->conv1, p->conv1_h.data(), sizeof(double) * p->conv1_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsi, p->cpsi_h.data(), sizeof(OpCoef) * p->cpsi_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsih, p->cpsih_h.data(), sizeof(OpCoef) * p->cpsih_h.size(), hipMemcpyHostToDevice, s));
@@ -615,40 +642,43 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
 }
 
 // ------------------------------------------------------------ multigrid
+// One V(1,1)-cycle on level l: pre-smoothing x -> t (from x = 0 when x_zero,
+// without reading x), residual, restriction, coarse cycle from zero, and the
+// post-smoothing sweep of t + P e_c -> x (the prolongation is applied while
+// the sweep loads its tile).
 template <typename R>
-static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b) {
+static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, bool x_zero) {
   const int n = m.n(l);
   const double h = 1.0 / n;
   if (l == m.nlev - 1) {
     launch_coarse<R>(s, m.q2, x, b, m.inv, m.fpc, m.nb, m.mk());
     return;
   }
-  // pre-smoothing x -> t, coarse correction on t, post-smoothing t -> x
   cpx<R>* t = (cpx<R>*)m.t[l];
-  Probe* pr = (l == 0 && m.probe && m.probe->on) ? m.probe : nullptr;
-  auto timed_sweep = [&](cpx<R>* xo, const cpx<R>* xi, bool fwd) {
-    const int slot = pr ? (int)(pr->count % Probe::kCap) : 0;
-    if (pr) hipEventRecord(pr->e0[slot], s);
-    launch_tile_sweep<R>(s, m.q2, xo, xi, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], fwd, m.mk());
-    if (pr) { hipEventRecord(pr->e1[slot], s); pr->count++; }
-  };
-  timed_sweep(t, x, true);
-  cpx<R>* r = (cpx<R>*)m.r[l];
-  launch_residual<R>(s, m.q2, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
   cpx<R>* bc = (cpx<R>*)m.b[l + 1];
   cpx<R>* xc = (cpx<R>*)m.x[l + 1];
+  // the probe times the finest pre-smoothing sweeps (reads b and, unless x = 0, x; writes t)
+  Probe* pr = (l == 0 && m.probe && m.probe->on) ? m.probe : nullptr;
+  const int slot = pr ? (int)(pr->count % Probe::kCap) : 0;
+  if (pr) (void)hipEventRecord(pr->e0[slot], s);
+  launch_tile_sweep<R>(s, m.q2, t, x_zero ? nullptr : x, b, nullptr, n, h, m.coef, m.fpc, m.nb, m.conv[l], true,
+                       m.mk());
+  if (pr) {
+    (void)hipEventRecord(pr->e1[slot], s);
+    pr->bytes[slot] = (x_zero ? 2.0 : 3.0) * (double)m.nodes(0) * m.active * sizeof(cpx<R>);
+    pr->count++;
+  }
+  cpx<R>* r = (cpx<R>*)m.r[l];
+  launch_residual<R>(s, m.q2, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
   launch_restrict<R>(s, m.q2, bc, r, n / 2, m.nb, m.mk());
-  launch_fill_zero(s, xc, m.nodes(l + 1) * m.nb * sizeof(cpx<R>));
-  vcycle<R>(s, m, l + 1, xc, bc);
-  launch_prolong_add<R>(s, m.q2, t, xc, n / 2, m.nb, m.mk());
-  timed_sweep(x, t, false);
+  vcycle<R>(s, m, l + 1, xc, bc, true);
+  launch_tile_sweep<R>(s, m.q2, x, t, b, xc, n, h, m.coef, m.fpc, m.nb, m.conv[l], false, m.mk());
 }
 
 // x = MG^cycles(b) from x = 0
 template <typename R>
 static void mg_solve(hipStream_t s, MGPlan& m, cpx<R>* x, const cpx<R>* b, int cycles) {
-  launch_fill_zero(s, x, m.nodes(0) * m.nb * sizeof(cpx<R>));
-  for (int c = 0; c < cycles; ++c) vcycle<R>(s, m, 0, x, b);
+  for (int c = 0; c < cycles; ++c) vcycle<R>(s, m, 0, x, b, c == 0);
 }
 
 // Chebyshev semi-iteration (Jacobi-preconditioned, spectrum bounds [lo, hi] of
@@ -707,17 +737,17 @@ static void puz(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R
   launch_block_copy<R>(s, (cpx<R>*)inV, B2, N, nf, 1, 0, m2);
   launch_fill_zero(s, X1, nh * sizeof(cpx<R>));
   launch_fill_zero(s, X2, nh * sizeof(cpx<R>));
-  const double* cv = p->conv2[0];
+  const double *cvN = p->tconv[0][0], *cvNT = p->tconv[1][0];
   for (int k = 0; k < p->o.n_uzawa; ++k) {
     // x1 += tau^{-1} M^^{-1} (b1 - tau M x1 - Psi^H x2)
     launch_apply<R>(s, true, T1, X1, N, h, p->cscal + 0, 2 * nf, 2 * nf, nullptr, m2);
-    launch_apply<R>(s, true, T2, X2, N, h, p->cpsih, 2, 2 * nf, cv, m2);
+    launch_apply<R>(s, true, T2, X2, N, h, p->cpsih, 2, 2 * nf, cvNT, m2);
     launch_combine3<R>(s, Rb, B1, T1, T2, 1.0, -1.0, -1.0, nh, nq2, m2);
     cpx<R>* c = chebyshev<R>(s, true, N, 2 * nf, (cpx<R>*)p->C1, (cpx<R>*)p->C2, Rb, p->o.n_cheb, 0.25, 25.0 / 16.0,
                              m2);
     launch_combine3<R>(s, X1, X1, c, nullptr, 1.0, 1.0 / tau, 0.0, nh, nq2, m2);
     // x2 -= mu^{-1} S^^{-1} (b2 - Psi x1 + tau/beta M x2)
-    launch_apply<R>(s, true, T1, X1, N, h, p->cpsi, 2, 2 * nf, cv, m2);
+    launch_apply<R>(s, true, T1, X1, N, h, p->cpsi, 2, 2 * nf, cvN, m2);
     launch_apply<R>(s, true, T2, X2, N, h, p->cscal + 1, 2 * nf, 2 * nf, nullptr, m2);
     launch_combine3<R>(s, Rb, B2, T1, T2, 1.0, -1.0, 1.0, nh, nq2, m2);
     mg_solve<R>(s, p->mgQ, T1, Rb, cyc);                                   // Q_j^{-1}
@@ -750,7 +780,7 @@ static void block_precond(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, c
 template <typename R>
 static void block_matvec(pintoc_problem* p, hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV,
                          const cpx<R>* xP) {
-  launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, p->d.flow == PINTOC_OSEEN ? p->conv2[0] : nullptr,
+  launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr,
                       p->block_scale, p->mk(2));
 }
 
@@ -795,12 +825,14 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(p->maskd, p->mask_h.data(), sizeof(int) * nf, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     p->cur_mask = p->maskd;
-    for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) m->mask = p->maskd;
+    int on_count = 0;
+    for (int v : on) on_count += v != 0;
+    for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) { m->mask = p->maskd; m->active = on_count * m->fpj; }
     return PINTOC_OK;
   };
   auto clear_mask = [&]() {
     p->cur_mask = nullptr;
-    for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) m->mask = nullptr;
+    for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) { m->mask = nullptr; m->active = m->nb; }
   };
   clear_mask();
   // ||s_j||
@@ -983,7 +1015,7 @@ extern "C" int pintoc_assemble_rhs(pintoc_problem* p, const double* vd, double* 
 
 static void kkt(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
   launch_kkt_apply(s, x, y, p->d.N, p->d.nt, p->tau, p->d.beta, p->d.nu,
-                   p->d.flow == PINTOC_OSEEN ? p->conv2[0] : nullptr);
+                   p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr);
 }
 
 extern "C" int pintoc_kkt_apply(pintoc_problem* p, const double* x, double* y, void* stream) {
