@@ -11,10 +11,9 @@
 //   vertex    m = h/30 (-1, 2, 8, 2, -1),   k = 1/(3h) (1, -8, 14, -8, 1)
 //   midpoint  m = h/30 (2, 16, 2),          k = 1/(3h) (-8, 16, -8)
 // so M = h^2/900 (m' x m') and K = 1/90 (k' x m' + m' x k') in integer weights
-// m', k' that the compiler folds into the code.  Each wave serves one class:
-// wave (PX, PY) takes the nodes with gx % 2 == PX, gy % 2 == PY of the current
-// colour, 8 x 8 of them per tile (one per 6 x 6 block); inside a sub-grid they
-// sit 3 entries apart, so the 64 lanes' LDS reads fall on distinct banks.
+// m', k' that the compiler folds into the code.  Each wave serves one class at
+// a time: the nodes with gx % 2 == PX, gy % 2 == PY of the current colour, 8 x 8
+// of them per tile (one per 6 x 6 block), 3 entries apart inside a sub-grid.
 //
 // Colours and tiles are those of the tiled SOR: colour 3 (gy % 3) + gx % 3,
 // tiles of 48 node indices aligned at node 0, Gauss-Seidel inside a tile and
@@ -22,6 +21,16 @@
 //
 // Convection tables are reordered on the host per (tile, colour, class,
 // stencil entry, lane), so the lanes of a wave read 64 consecutive doubles.
+//
+// Lanes.  A class wave reads the nodes (la, lb) of the class's 8 x 8 nodes of
+// the colour at sub-grid entries u = 3 la + 78 lb + const.  A 128-bit LDS read
+// is served 16 lanes at a time; it runs without bank conflicts when every
+// 16-lane group covers the 16 residues u mod 16 once and lane j of every group
+// has the same residue (measured on gfx950).  Each residue occurs at exactly
+// four nodes, so group g takes the g-th of them and lane 16 g + j the node of
+// residue j.  Waves take the four classes in an order rotated per colour and
+// per work-group, which spreads the heavy vertex-vertex class (25 points) over
+// the SIMDs.
 //
 // Work-group order is XCD-aware: ids are dealt round-robin to the 8 XCDs, so
 // id g is remapped to v = (g % 8) (G / 8) + g / 8 and every XCD gets a
@@ -34,10 +43,12 @@ namespace pintoc {
 
 namespace {
 
-constexpr int kT = 48;            // tile side (node indices)
-constexpr int kE = kT + 4;        // tile with halo
-constexpr int kH = kE / 2;        // parity sub-grid side
-constexpr int kSub = kH * kH;     // entries per sub-grid
+constexpr int kT = 48;                 // tile side (node indices)
+constexpr int kE = kT + 4;             // tile with halo
+constexpr int kH = kE / 2;             // parity sub-grid side
+constexpr int kSub = kH * kH + 4;      // sub-grid stride (entries; = 8 mod 16 for the row-order phases)
+constexpr int kSP = kT + 1;            // row pitch of the staged results of the operator tiles
+static_assert(kT * kSP <= 4 * kSub, "staged results fit the tile");
 
 __host__ __device__ constexpr int wlen(int P) { return P ? 3 : 5; }
 __host__ __device__ constexpr int wlo(int P) { return P ? -1 : -2; }
@@ -69,13 +80,30 @@ template <> struct Comb<1> {
   }
 };
 
-// Tile-local coordinates of a lane's node of colour col in class (PX, PY).
-template <int PX, int PY>
-__device__ __forceinline__ void node_of(int col, int la, int lb, int& lx, int& ly) {
-  const int cx = col % 3, cy = col / 3;
-  lx = cx + 3 * (2 * la + ((PX - cx) & 1));
-  ly = cy + 3 * (2 * lb + ((PY - cy) & 1));
+// Lane (la, lb) of a class wave; see the comment at the top of the file.
+__host__ __device__ __forceinline__ void lane_ab(int lane, int& la, int& lb) {
+  const int g = lane >> 4, j = lane & 15;
+  int cnt = 0;
+  la = 0;
+  lb = 0;
+  for (int b = 0; b < 8; ++b) {
+    const int a = (11 * (j - 14 * b + 256)) & 15;      // 3 a + 14 b = j (mod 16); 11 = 3^-1 mod 16
+    if (a < 8) {
+      if (cnt == g) { la = a; lb = b; }
+      ++cnt;
+    }
+  }
 }
+
+// Tile-local coordinates of a lane's node of colour col in class (px, py).
+__host__ __device__ __forceinline__ void node_of(int px, int py, int col, int la, int lb, int& lx, int& ly) {
+  const int cx = col % 3, cy = col / 3;
+  lx = cx + 3 * (2 * la + ((px - cx) & 1));
+  ly = cy + 3 * (2 * lb + ((py - cy) & 1));
+}
+
+// class served by wave w at colour step k (0: (0,0), 1: (1,0), 2: (0,1), 3: (1,1))
+__device__ __forceinline__ int class_of(int w, int k, int rot) { return (w + k + rot) & 3; }
 
 // Uniform coefficients of a work-group: a = alpha h^2/900, g = gamma/90, e = eta.
 struct TCoef {
@@ -145,119 +173,173 @@ __device__ __forceinline__ bool tile_of_block(int ntiles, int nb, bool grid_fast
   return true;
 }
 
-// (P e)(i, j) of the Q2 prolongation from the coarse padded grid (side nqc).
+__device__ __forceinline__ int sub_index(int ex, int ey) {
+  return ((ey & 1) * 2 + (ex & 1)) * kSub + (ey >> 1) * kH + (ex >> 1);
+}
+
+// Load the tile and halo of x (zero when xi is null) into the parity
+// sub-grids; boundary and outside nodes are zero.  Thread t < 4 kE owns column
+// ex = t % kE and rows ey = t / kE + 4 k, so addresses advance by constant
+// strides (coalesced along each row).
+constexpr int kLR = kE / 4;            // rows per loading thread
+static_assert(kE % 4 == 0 && 4 * kE <= 256, "tile loading layout");
+
 template <typename R>
-__device__ __forceinline__ double2 q2_prolong_at(const cpx<R>* __restrict__ ec, int nqc, int i, int j) {
-  auto w1 = [](int i, int& c0, double w[3]) {
-    const int e = i >> 2, r = i & 3;
-    c0 = 2 * e;
-    if (r == 0) { w[0] = 1; w[1] = 0; w[2] = 0; }
-    else if (r == 2) { w[0] = 0; w[1] = 1; w[2] = 0; }
-    else if (r == 1) { w[0] = 0.375; w[1] = 0.75; w[2] = -0.125; }
-    else { w[0] = -0.125; w[1] = 0.75; w[2] = 0.375; }
-  };
-  int cx0, cy0;
-  double wx[3], wy[3];
-  w1(i, cx0, wx);
-  w1(j, cy0, wy);
-  double sr = 0, si = 0;
-  for (int a = 0; a < 3; ++a) {
-    if (wy[a] == 0.0) continue;
-    double rr = 0, ri = 0;
+__device__ __forceinline__ void load_tile(cpx<R>* sx, const cpx<R>* __restrict__ xi, int nq, int X0, int Y0) {
+  if (threadIdx.x >= 4 * kE) return;
+  const int ex = (int)threadIdx.x % kE, ey0 = (int)threadIdx.x / kE;
+  const int gx = X0 - 2 + ex, gy0 = Y0 - 2 + ey0;
+  const bool xin = xi && gx >= 1 && gx <= nq - 2;
+  const cpx<R>* src = xin ? xi + ((ptrdiff_t)gy0 * nq + gx) : xi;    // dereferenced only for nodes inside
+  cpx<R> v[kLR];
+#pragma unroll
+  for (int k = 0; k < kLR; ++k) {
+    const int gy = gy0 + 4 * k;
+    v[k] = (xin && gy >= 1 && gy <= nq - 2) ? src[(ptrdiff_t)4 * k * nq] : cmk<cpx<R>>(0, 0);
+  }
+  cpx<R>* dst = sx + ((ey0 & 1) * 2 + (ex & 1)) * kSub + (ey0 >> 1) * kH + (ex >> 1);
+#pragma unroll
+  for (int k = 0; k < kLR; ++k) dst[2 * k * kH] = v[k];
+}
+
+// 1-D Q2 prolongation: fine node 4e + r from coarse nodes 2e, 2e + 1, 2e + 2.
+__device__ __forceinline__ void prolong_row(const double c[3], double f[4]) {
+  f[0] = c[0];
+  f[1] = 0.375 * c[0] + 0.75 * c[1] - 0.125 * c[2];
+  f[2] = c[1];
+  f[3] = -0.125 * c[0] + 0.75 * c[1] + 0.375 * c[2];
+}
+
+// Load t + P ec (t: fine iterate, ec: coarse correction on the padded grid of
+// side (nq + 1) / 2) for the tile and halo.  A thread builds one 4 x 4 block of
+// fine nodes aligned with a coarse cell (fine 4e .. 4e + 3 per direction,
+// coarse 2e .. 2e + 2) from 3 x 3 coarse values; 14 x 14 blocks cover
+// [X0 - 4, X0 + 52).
+constexpr int kPB = kE / 4 + 1;
+
+template <typename R>
+__device__ __forceinline__ void load_tile_prolong(cpx<R>* sx, const cpx<R>* __restrict__ xi,
+                                                  const cpx<R>* __restrict__ ec, int nq, int X0, int Y0) {
+  if (threadIdx.x >= kPB * kPB) return;
+  const int nqc = (nq + 1) / 2;
+  const int ex0 = X0 / 4 - 1 + (int)threadIdx.x % kPB, ey0 = Y0 / 4 - 1 + (int)threadIdx.x / kPB;
+  cpx<R> c[9], tv[16];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int q = 0; q < 3; ++q) {
-      if (wx[q] == 0.0) continue;
-      const cpx<R> v = ec[(size_t)(cy0 + a) * nqc + cx0 + q];
-      rr += wx[q] * (double)v.x;
-      ri += wx[q] * (double)v.y;
+      const int cx = 2 * ex0 + q, cy = 2 * ey0 + a;
+      c[3 * a + q] = (cx >= 0 && cx < nqc && cy >= 0 && cy < nqc) ? ec[(size_t)cy * nqc + cx] : cmk<cpx<R>>(0, 0);
     }
-    sr += wy[a] * rr;
-    si += wy[a] * ri;
-  }
-  return make_double2(sr, si);
-}
-
-constexpr int kLoads = (kE * kE + 255) / 256;
-
-// Load the tile and halo of x (zero when xi is null), plus P ec when ec is
-// given, into the parity sub-grids.  Boundary and outside nodes are zero.
-template <typename R>
-__device__ __forceinline__ void load_tile(cpx<R>* sx, const cpx<R>* __restrict__ xi, const cpx<R>* __restrict__ ec,
-                                          int nq, int X0, int Y0) {
-  cpx<R> v[kLoads];
 #pragma unroll
-  for (int i = 0; i < kLoads; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    const int ey = e / kE, ex = e - ey * kE;
-    const int gx = X0 - 2 + ex, gy = Y0 - 2 + ey;
-    v[i] = cmk<cpx<R>>(0, 0);
-    if (e < kE * kE && gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2) {
-      if (xi) v[i] = xi[(size_t)gy * nq + gx];
-      if (ec) {
-        const double2 p = q2_prolong_at<R>(ec, (nq + 1) / 2, gx, gy);
-        v[i] = cmk<cpx<R>>((double)v[i].x + p.x, (double)v[i].y + p.y);
-      }
+  for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gx = 4 * ex0 + r, gy = 4 * ey0 + s2;
+      const int ex = gx - X0 + 2, ey = gy - Y0 + 2;
+      const bool load = xi && ex >= 0 && ex < kE && ey >= 0 && ey < kE && gx >= 1 && gx <= nq - 2 && gy >= 1 &&
+                        gy <= nq - 2;
+      tv[4 * s2 + r] = load ? xi[(size_t)gy * nq + gx] : cmk<cpx<R>>(0, 0);
     }
+  double pr[3][4], pi[3][4];          // prolonged along x, per coarse row
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double cr[3] = {(double)c[3 * a].x, (double)c[3 * a + 1].x, (double)c[3 * a + 2].x};
+    const double ci[3] = {(double)c[3 * a].y, (double)c[3 * a + 1].y, (double)c[3 * a + 2].y};
+    prolong_row(cr, pr[a]);
+    prolong_row(ci, pi[a]);
   }
 #pragma unroll
-  for (int i = 0; i < kLoads; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    if (e < kE * kE) {
-      const int ey = e / kE, ex = e - ey * kE;
-      sx[((ey & 1) * 2 + (ex & 1)) * kSub + (ey >> 1) * kH + (ex >> 1)] = v[i];
+  for (int r = 0; r < 4; ++r) {
+    const double colr[3] = {pr[0][r], pr[1][r], pr[2][r]}, coli[3] = {pi[0][r], pi[1][r], pi[2][r]};
+    double fr[4], fi[4];
+    prolong_row(colr, fr);
+    prolong_row(coli, fi);
+    const int gx = 4 * ex0 + r, ex = gx - X0 + 2;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int gy = 4 * ey0 + s2, ey = gy - Y0 + 2;
+      if (ex < 0 || ex >= kE || ey < 0 || ey >= kE) continue;
+      const bool in = gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2;
+      const cpx<R> t = tv[4 * s2 + r];
+      sx[sub_index(ex, ey)] = in ? cmk<cpx<R>>((double)t.x + fr[s2], (double)t.y + fi[s2]) : cmk<cpx<R>>(0, 0);
     }
   }
 }
 
-// One colour of the sweep for a lane of class (PX, PY).
+// b at the lane's node of every colour step k (class and colour of that step).
+template <typename R, bool FWD>
+__device__ __forceinline__ void prefetch_b(cpx<R>* bb, const cpx<R>* __restrict__ bf, int w, int rot, int la, int lb,
+                                           int X0, int Y0, int nq) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int col = FWD ? k : 8 - k, c = class_of(w, k, rot);
+    int lx, ly;
+    node_of(c & 1, c >> 1, col, la, lb, lx, ly);
+    const int gx = X0 + lx, gy = Y0 + ly;
+    bb[k] = (gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2) ? bf[(size_t)gy * nq + gx] : cmk<cpx<R>>(0, 0);
+  }
+}
+
+// One colour of the sweep for a lane of class (PX, PY).  dinv: inverse of the
+// class diagonal (used without convection, where it is uniform).
 template <int PX, int PY, bool CV, typename R>
 __device__ __forceinline__ void sweep_node(cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0, int nq,
-                                           cpx<R> bv, const TCoef& t, const double* __restrict__ ctile) {
+                                           cpx<R> bv, const TCoef& t, double2 dinv, const double* __restrict__ ctile) {
   int lx, ly;
-  node_of<PX, PY>(col, la, lb, lx, ly);
+  node_of(PX, PY, col, la, lb, lx, ly);
   const int gx = X0 + lx, gy = Y0 + ly;
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return;
   cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
   const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
   double cd = 0;
   const double2 ax = stencil<PX, PY, CV, R>(base, cn, t, cd);
-  double2 d = diag0<PX, PY>(t);
-  if (CV) { d.x += t.er * cd; d.y += t.ei * cd; }
-  const double er = (double)bv.x - ax.x, ei = (double)bv.y - ax.y;
-  const double inv = 1.0 / (d.x * d.x + d.y * d.y);
-  cpx<R>& xs = base[loff<PX, PY>(0, 0)];
-  xs = cmk<cpx<R>>((double)xs.x + (er * d.x + ei * d.y) * inv, (double)xs.y + (ei * d.x - er * d.y) * inv);
-}
-
-template <int PX, int PY, typename R>
-__device__ __forceinline__ void prefetch_b(cpx<R>* bb, const cpx<R>* __restrict__ bf, int la, int lb, int X0, int Y0,
-                                           int nq) {
-#pragma unroll
-  for (int col = 0; col < 9; ++col) {
-    int lx, ly;
-    node_of<PX, PY>(col, la, lb, lx, ly);
-    const int gx = X0 + lx, gy = Y0 + ly;
-    bb[col] = (gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2) ? bf[(size_t)gy * nq + gx] : cmk<cpx<R>>(0, 0);
+  if (CV) {
+    double2 d = diag0<PX, PY>(t);
+    d.x += t.er * cd;
+    d.y += t.ei * cd;
+    const double inv = 1.0 / (d.x * d.x + d.y * d.y);
+    dinv = make_double2(d.x * inv, -d.y * inv);
   }
+  const double er = (double)bv.x - ax.x, ei = (double)bv.y - ax.y;
+  cpx<R>& xs = base[loff<PX, PY>(0, 0)];
+  xs = cmk<cpx<R>>((double)xs.x + er * dinv.x - ei * dinv.y, (double)xs.y + er * dinv.y + ei * dinv.x);
 }
 
-// Write the tile interior from LDS (or zero on boundary nodes) to xo.
+template <int PX, int PY>
+__device__ __forceinline__ double2 inv_diag0(const TCoef& t) {
+  const double2 d = diag0<PX, PY>(t);
+  const double inv = 1.0 / (d.x * d.x + d.y * d.y);
+  return make_double2(d.x * inv, -d.y * inv);
+}
+
+// Write the tile interior from LDS (or zero on boundary nodes) to xo.  Thread
+// t < 5 kT owns column lx = t % kT and rows ly = t / kT + 5 k.
+constexpr int kSR = (kT + 4) / 5;      // rows per storing thread (the last may fall outside)
+static_assert(5 * kT <= 256, "tile storing layout");
+
 template <typename R>
 __device__ __forceinline__ void store_tile(cpx<R>* __restrict__ xo, const cpx<R>* sx, int nq, int X0, int Y0) {
-  for (int e = threadIdx.x; e < kT * kT; e += 256) {
-    const int ly = e / kT, lx = e - ly * kT;
-    const int gx = X0 + lx, gy = Y0 + ly;
-    if (gx >= nq || gy >= nq) continue;
-    const bool in = gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2;
-    xo[(size_t)gy * nq + gx] =
-        in ? sx[((ly & 1) * 2 + (lx & 1)) * kSub + ((ly + 2) >> 1) * kH + ((lx + 2) >> 1)] : cmk<cpx<R>>(0, 0);
+  if (threadIdx.x >= 5 * kT) return;
+  const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT;
+  const int gx = X0 + lx;
+  if (gx >= nq) return;
+  const bool xin = gx >= 1 && gx <= nq - 2;
+  cpx<R>* dst = xo + (ptrdiff_t)(Y0 + ly0) * nq + gx;
+#pragma unroll
+  for (int k = 0; k < kSR; ++k) {
+    const int ly = ly0 + 5 * k, gy = Y0 + ly;
+    if (ly >= kT || gy >= nq) break;
+    const bool in = xin && gy >= 1 && gy <= nq - 2;
+    dst[(ptrdiff_t)5 * k * nq] = in ? sx[sub_index(lx + 2, ly + 2)] : cmk<cpx<R>>(0, 0);
   }
 }
 
 }  // namespace
 
-// Sweep x -> xo.  xi == nullptr: start from x = 0.  ec != nullptr: start from
-// x + P ec (coarse-grid correction of the V-cycle applied on load).
-template <typename R, bool CV, bool FWD>
+// Sweep x -> xo.  xi == nullptr: start from x = 0.  PRO: start from xi + P ec
+// (the coarse-grid correction of the V-cycle, applied while loading).
+template <typename R, bool CV, bool FWD, bool PRO>
 __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const cpx<R>* __restrict__ xi,
                                                   const cpx<R>* __restrict__ b, const cpx<R>* __restrict__ ec, int n,
                                                   double h, const OpCoef* __restrict__ coef, int fpc,
@@ -269,26 +351,31 @@ __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const
   const int X0 = (tile % ntx) * kT, Y0 = (tile / ntx) * kT;
   const int nq = 2 * n + 1, nqc = n + 1;
   const size_t off = (size_t)f * nq * nq;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, la = lane & 7, lb = lane >> 3;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
+  int la, lb;
+  lane_ab(lane, la, lb);
   cpx<R> bb[9];
-  switch (w) {
-    case 0: prefetch_b<0, 0, R>(bb, b + off, la, lb, X0, Y0, nq); break;
-    case 1: prefetch_b<1, 0, R>(bb, b + off, la, lb, X0, Y0, nq); break;
-    case 2: prefetch_b<0, 1, R>(bb, b + off, la, lb, X0, Y0, nq); break;
-    default: prefetch_b<1, 1, R>(bb, b + off, la, lb, X0, Y0, nq); break;
-  }
-  load_tile<R>(sx, xi ? xi + off : nullptr, ec ? ec + (size_t)f * nqc * nqc : nullptr, nq, X0, Y0);
+  prefetch_b<R, FWD>(bb, b + off, w, rot, la, lb, X0, Y0, nq);
+  if (PRO) load_tile_prolong<R>(sx, xi ? xi + off : nullptr, ec + (size_t)f * nqc * nqc, nq, X0, Y0);
+  else load_tile<R>(sx, xi ? xi + off : nullptr, nq, X0, Y0);
   const TCoef t = tcoef(coef[f / fpc], h);
+  double2 dv0 = make_double2(0, 0), dv1 = dv0, dv2 = dv0, dv3 = dv0;
+  if (!CV) {
+    dv0 = inv_diag0<0, 0>(t);
+    dv1 = inv_diag0<1, 0>(t);
+    dv2 = inv_diag0<0, 1>(t);
+    dv3 = inv_diag0<1, 1>(t);
+  }
   const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const int col = FWD ? k : 8 - k;
-    switch (w) {
-      case 0: sweep_node<0, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[col], t, ctile); break;
-      case 1: sweep_node<1, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[col], t, ctile); break;
-      case 2: sweep_node<0, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[col], t, ctile); break;
-      default: sweep_node<1, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[col], t, ctile); break;
+    switch (class_of(w, k, rot)) {
+      case 0: sweep_node<0, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv0, ctile); break;
+      case 1: sweep_node<1, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv1, ctile); break;
+      case 2: sweep_node<0, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv2, ctile); break;
+      default: sweep_node<1, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv3, ctile); break;
     }
     __syncthreads();
   }
@@ -298,22 +385,16 @@ __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const
 namespace {
 template <int PX, int PY, bool CV, typename R>
 __device__ __forceinline__ double2 apply_node(const cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0,
-                                              int nq, const TCoef& t, const double* __restrict__ ctile) {
+                                              int nq, const TCoef& t, const double* __restrict__ ctile, int& si) {
   int lx, ly;
-  node_of<PX, PY>(col, la, lb, lx, ly);
+  node_of(PX, PY, col, la, lb, lx, ly);
+  si = ly * kSP + lx;
   const int gx = X0 + lx, gy = Y0 + ly;
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return make_double2(0, 0);
   const cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
   const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
   double cd = 0;
   return stencil<PX, PY, CV, R>(base, cn, t, cd);
-}
-
-template <int PX, int PY>
-__device__ __forceinline__ int stage_index(int col, int la, int lb) {
-  int lx, ly;
-  node_of<PX, PY>(col, la, lb, lx, ly);
-  return ly * kT + lx;
 }
 }  // namespace
 
@@ -331,44 +412,46 @@ __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out,
   const int X0 = (tile % ntx) * kT, Y0 = (tile / ntx) * kT;
   const int nq = 2 * n + 1;
   const size_t off = (size_t)f * nq * nq;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, la = lane & 7, lb = lane >> 3;
-  load_tile<R>(sx, x + off, nullptr, nq, X0, Y0);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
+  int la, lb;
+  lane_ab(lane, la, lb);
+  load_tile<R>(sx, x + off, nq, X0, Y0);
   const TCoef t = tcoef(coef[f / fpc], h);
   const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
   __syncthreads();
   double2 acc[9];
+  int si[9];
 #pragma unroll
-  for (int col = 0; col < 9; ++col) {
-    switch (w) {
-      case 0: acc[col] = apply_node<0, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, t, ctile); break;
-      case 1: acc[col] = apply_node<1, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, t, ctile); break;
-      case 2: acc[col] = apply_node<0, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, t, ctile); break;
-      default: acc[col] = apply_node<1, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, t, ctile); break;
+  for (int k = 0; k < 9; ++k) {
+    switch (class_of(w, k, rot)) {
+      case 0: acc[k] = apply_node<0, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
+      case 1: acc[k] = apply_node<1, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
+      case 2: acc[k] = apply_node<0, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
+      default: acc[k] = apply_node<1, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
     }
   }
   __syncthreads();
-  // stage A x row-major (kT x kT) in the LDS tile for a coalesced store
+  // stage A x row-major (pitch kSP) in the LDS tile for a coalesced store
 #pragma unroll
-  for (int col = 0; col < 9; ++col) {
-    int i;
-    switch (w) {
-      case 0: i = stage_index<0, 0>(col, la, lb); break;
-      case 1: i = stage_index<1, 0>(col, la, lb); break;
-      case 2: i = stage_index<0, 1>(col, la, lb); break;
-      default: i = stage_index<1, 1>(col, la, lb); break;
-    }
-    sx[i] = cmk<cpx<R>>(acc[col].x, acc[col].y);
-  }
+  for (int k = 0; k < 9; ++k) sx[si[k]] = cmk<cpx<R>>(acc[k].x, acc[k].y);
   __syncthreads();
-  for (int e = threadIdx.x; e < kT * kT; e += 256) {
-    const int ly = e / kT, lx = e - ly * kT;
-    const int gx = X0 + lx, gy = Y0 + ly;
-    if (gx >= nq || gy >= nq) continue;
-    const size_t g = off + (size_t)gy * nq + gx;
-    const bool in = gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2;
-    cpx<R> v = in ? sx[e] : cmk<cpx<R>>(0, 0);
-    if (b) v = in ? b[g] - v : cmk<cpx<R>>(0, 0);
-    out[g] = v;
+  if (threadIdx.x < 5 * kT) {
+    const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT;
+    const int gx = X0 + lx;
+    if (gx < nq) {
+      const bool xin = gx >= 1 && gx <= nq - 2;
+      const ptrdiff_t g0 = (ptrdiff_t)off + (ptrdiff_t)(Y0 + ly0) * nq + gx;
+#pragma unroll
+      for (int k = 0; k < kSR; ++k) {
+        const int ly = ly0 + 5 * k, gy = Y0 + ly;
+        if (ly >= kT || gy >= nq) break;
+        const ptrdiff_t g = g0 + (ptrdiff_t)5 * k * nq;
+        const bool in = xin && gy >= 1 && gy <= nq - 2;
+        cpx<R> v = in ? sx[ly * kSP + lx] : cmk<cpx<R>>(0, 0);
+        if (b) v = in ? b[g] - v : cmk<cpx<R>>(0, 0);
+        out[g] = v;
+      }
+    }
   }
 }
 
@@ -388,13 +471,22 @@ void launch_q2_sweep(hipStream_t s, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* 
                      const OpCoef* coef, int fpc, int nb, const double* tconv, bool forward, Mask mk) {
   const int ntx = (2 * n + 1 + kT - 1) / kT;
   const dim3 g(tile_blocks(ntx, nb)), blk(256);
-  if (tconv) {
-    if (forward) hipLaunchKernelGGL((k_q2_sweep<R, true, true>), g, blk, 0, s, xo, xi, b, ec, n, h, coef, fpc, tconv, ntx, nb, mk);
-    else hipLaunchKernelGGL((k_q2_sweep<R, true, false>), g, blk, 0, s, xo, xi, b, ec, n, h, coef, fpc, tconv, ntx, nb, mk);
-  } else {
-    if (forward) hipLaunchKernelGGL((k_q2_sweep<R, false, true>), g, blk, 0, s, xo, xi, b, ec, n, h, coef, fpc, tconv, ntx, nb, mk);
-    else hipLaunchKernelGGL((k_q2_sweep<R, false, false>), g, blk, 0, s, xo, xi, b, ec, n, h, coef, fpc, tconv, ntx, nb, mk);
+  const bool cv = tconv != nullptr, pro = ec != nullptr;
+#define PINTOC_SWEEP(CV, FWD, PRO)                                                                                 \
+  if (cv == CV && forward == FWD && pro == PRO) {                                                                   \
+    hipLaunchKernelGGL((k_q2_sweep<R, CV, FWD, PRO>), g, blk, 0, s, xo, xi, b, ec, n, h, coef, fpc, tconv, ntx, nb, \
+                       mk);                                                                                         \
+    return;                                                                                                         \
   }
+  PINTOC_SWEEP(false, true, false)
+  PINTOC_SWEEP(false, false, true)
+  PINTOC_SWEEP(true, true, false)
+  PINTOC_SWEEP(true, false, true)
+  PINTOC_SWEEP(false, false, false)
+  PINTOC_SWEEP(false, true, true)
+  PINTOC_SWEEP(true, false, false)
+  PINTOC_SWEEP(true, true, true)
+#undef PINTOC_SWEEP
 }
 
 template <typename R>
@@ -416,12 +508,12 @@ void q2_tile_conv_table(int n, const double* t50, int half, double* out) {
   for (int tile = 0; tile < ntx * ntx; ++tile) {
     const int X0 = (tile % ntx) * kT, Y0 = (tile / ntx) * kT;
     for (int col = 0; col < 9; ++col) {
-      const int cx = col % 3, cy = col / 3;
       for (int cls = 0; cls < 4; ++cls) {
         const int PX = cls & 1, PY = cls >> 1;
         for (int lane = 0; lane < 64; ++lane) {
-          const int la = lane & 7, lb = lane >> 3;
-          const int lx = cx + 3 * (2 * la + ((PX - cx) & 1)), ly = cy + 3 * (2 * lb + ((PY - cy) & 1));
+          int la, lb, lx, ly;
+          lane_ab(lane, la, lb);
+          node_of(PX, PY, col, la, lb, lx, ly);
           const int gx = X0 + lx, gy = Y0 + ly;
           if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) continue;
           int k = 0;
