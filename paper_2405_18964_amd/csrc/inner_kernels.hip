@@ -72,6 +72,139 @@ __global__ __launch_bounds__(256) void k_fdot_reduce(const double2* __restrict__
   out[t] = make_double2(sr, si);
 }
 
+// ---------------------------------------------- lagged reorthogonalisation
+// Arnoldi with classical Gram-Schmidt applied twice, where the second pass of
+// one column is carried out together with the first pass of the next (the
+// matrix acts on the once-projected vector u_k; the host corrects the
+// Hessenberg column through the Arnoldi relation).  Per iteration the basis is
+// read twice: one fused dot pass and one fused update pass.
+//
+// Dot pass, per frequency: s_i = q_i^H u, t_i = q_i^H w (i < k), nu = u^H u,
+// mu = u^H w, with q_i = basis vector i, u = basis vector k, w = basis vector
+// k + 1 (w == nullptr: s and nu only).  One launch covers i in [i0, i1) (nu
+// and mu with i0 = 0); wave q of a work-group handles i = i0 + q, i0 + q + 4,
+// ...; partial sums per chunk go to
+// part[(slot * nf + j) * nch + chunk], slots s_0..s_{k-1}, t_0..t_{k-1}, nu, mu.
+constexpr int kLW = 13;                  // basis vectors per wave: k <= 52
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fdot_lag(const cpx<R>* __restrict__ bV, const cpx<R>* __restrict__ bP,
+                                                  size_t ldV, size_t ldP, int k, int i0, int i1,
+                                                  const cpx<R>* __restrict__ uV,
+                                                  const cpx<R>* __restrict__ uP, const cpx<R>* __restrict__ wV,
+                                                  const cpx<R>* __restrict__ wP, int segV, int segP, int chV, int nch,
+                                                  int nf, double2* __restrict__ part, Mask mk) {
+  const int j = blockIdx.y, c = blockIdx.x;
+  if (mk.off(j)) return;
+  const bool inV = c < chV;
+  const int seg = inV ? segV : segP;
+  const int cc = inV ? c : c - chV;
+  const size_t base = (size_t)j * seg;
+  const cpx<R>* B = inV ? bV : bP;
+  const cpx<R>* U = inV ? uV : uP;
+  const cpx<R>* W = inV ? wV : wP;
+  const size_t ld = inV ? ldV : ldP;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double sr[kLW], si[kLW], tr[kLW], ti[kLW];
+#pragma unroll
+  for (int q = 0; q < kLW; ++q) { sr[q] = 0; si[q] = 0; tr[q] = 0; ti[q] = 0; }
+  double nu = 0, mur = 0, mui = 0;
+  const int lo = cc * kFChunk, hi = min(lo + kFChunk, seg);
+  for (int e = lo + lane; e < hi; e += 64) {
+    const cpx<R> u = U[base + e];
+    const double ur = (double)u.x, ui = (double)u.y;
+    double wr = 0, wi = 0;
+    if (W) { const cpx<R> w = W[base + e]; wr = (double)w.x; wi = (double)w.y; }
+    if (wv == 0 && i0 == 0) {
+      nu += ur * ur + ui * ui;
+      mur += ur * wr + ui * wi;                // conj(u) w
+      mui += ur * wi - ui * wr;
+    }
+#pragma unroll
+    for (int q = 0; q < kLW; ++q) {
+      const int i = i0 + wv + 4 * q;
+      if (i < i1) {
+        const cpx<R> v = B[(size_t)i * ld + base + e];
+        const double vr = (double)v.x, vi = (double)v.y;
+        sr[q] += vr * ur + vi * ui;  si[q] += vr * ui - vi * ur;      // conj(v) u
+        tr[q] += vr * wr + vi * wi;  ti[q] += vr * wi - vi * wr;      // conj(v) w
+      }
+    }
+  }
+  auto put = [&](int slot, double re, double im) {
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) part[((size_t)slot * nf + j) * nch + c] = make_double2(re, im);
+  };
+#pragma unroll
+  for (int q = 0; q < kLW; ++q) {
+    const int i = i0 + wv + 4 * q;
+    if (i < i1) {
+      put(i, sr[q], si[q]);
+      if (W) put(k + i, tr[q], ti[q]);
+    }
+  }
+  if (wv == 0 && i0 == 0) {
+    put(2 * k, nu, 0.0);
+    if (W) put(2 * k + 1, mur, mui);
+  }
+}
+
+// Update pass, per frequency j with alpha = ag[j].x, gamma = ag[nf + j]:
+//   q_k     = (u - sum_i s_i q_i) / alpha                  (written over u)
+//   u_{k+1} = (w - gamma u - sum_i c_i q_i) / alpha        (written over w)
+// with s_i = cs[i * nf + j], c_i = cc[i * nf + j], and ||u_{k+1}||^2 partial
+// sums per chunk in part[j * nch + chunk].  k = 0: q_0 = u is kept.
+template <typename R>
+__global__ __launch_bounds__(256) void k_fupdate_lag(cpx<R>* __restrict__ bV, cpx<R>* __restrict__ bP, size_t ldV,
+                                                     size_t ldP, int k, const double2* __restrict__ cs,
+                                                     const double2* __restrict__ cc, const double2* __restrict__ ag,
+                                                     int segV, int segP, int chV, int nch, int nf,
+                                                     double2* __restrict__ part, Mask mk) {
+  __shared__ double red[4];
+  const int j = blockIdx.y, c = blockIdx.x;
+  if (mk.off(j)) return;
+  const bool inV = c < chV;
+  const int seg = inV ? segV : segP;
+  const int ch = inV ? c : c - chV;
+  const size_t base = (size_t)j * seg;
+  cpx<R>* B = inV ? bV : bP;
+  const size_t ld = inV ? ldV : ldP;
+  const double alpha = ag[j].x, ia = 1.0 / alpha;
+  const double2 gam = ag[nf + j];
+  cpx<R>* U = B + (size_t)k * ld + base;
+  cpx<R>* W = B + (size_t)(k + 1) * ld + base;
+  double nrm = 0;
+  const int lo = ch * kFChunk, hi = min(lo + kFChunk, seg);
+  for (int e = lo + (int)threadIdx.x; e < hi; e += 256) {
+    const cpx<R> u = U[e], w = W[e];
+    const double ur = (double)u.x, ui = (double)u.y;
+    double asr = 0, asi = 0, acr = 0, aci = 0;
+    for (int i = 0; i < k; ++i) {
+      const double2 si = cs[(size_t)i * nf + j], ci = cc[(size_t)i * nf + j];
+      const cpx<R> v = B[(size_t)i * ld + base + e];
+      const double vr = (double)v.x, vi = (double)v.y;
+      asr += si.x * vr - si.y * vi;  asi += si.x * vi + si.y * vr;
+      acr += ci.x * vr - ci.y * vi;  aci += ci.x * vi + ci.y * vr;
+    }
+    if (k > 0) U[e] = cmk<cpx<R>>((ur - asr) * ia, (ui - asi) * ia);
+    const cpx<R> un = cmk<cpx<R>>(((double)w.x - (gam.x * ur - gam.y * ui) - acr) * ia,
+                                  ((double)w.y - (gam.x * ui + gam.y * ur) - aci) * ia);
+    W[e] = un;
+    nrm += (double)un.x * (double)un.x + (double)un.y * (double)un.y;
+  }
+  nrm = wave_sum(nrm);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)j * nch + c] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+
 // w^j -= sum_i c[i][j] v_i^j    (c: [k][nf] complex, on the device)
 template <typename R>
 __global__ __launch_bounds__(256) void k_fupdate(cpx<R>* __restrict__ wV, cpx<R>* __restrict__ wP, const cpx<R>* __restrict__ bV,
@@ -164,6 +297,35 @@ size_t fdot_part_entries(int segV, int segP, int nf) {
 }
 
 template <typename R>
+void launch_fdot_lag(hipStream_t s, const cpx<R>* bV, const cpx<R>* bP, size_t ldV, size_t ldP, int k,
+                     const cpx<R>* uV, const cpx<R>* uP, const cpx<R>* wV, const cpx<R>* wP, int segV, int segP,
+                     int nf, double2* part, double2* out, Mask mk) {
+  const int chV = (segV + kFChunk - 1) / kFChunk, chP = (segP + kFChunk - 1) / kFChunk, nch = chV + chP;
+  for (int i0 = 0; i0 < (k > 0 ? k : 1); i0 += 4 * kLW) {
+    const int i1 = i0 + 4 * kLW < k ? i0 + 4 * kLW : k;
+    hipLaunchKernelGGL(k_fdot_lag<R>, dim3(nch, nf), dim3(256), 0, s, bV, bP, ldV, ldP, k, i0, i1, uV, uP, wV, wP,
+                       segV, segP, chV, nch, nf, part, mk);
+  }
+  const int slots = 2 * k + 2;
+  hipLaunchKernelGGL(k_fdot_reduce, dim3((slots * nf + 255) / 256), dim3(256), 0, s, part, slots, nf, nch, out);
+}
+
+template <typename R>
+void launch_fupdate_lag(hipStream_t s, cpx<R>* bV, cpx<R>* bP, size_t ldV, size_t ldP, int k, const double2* cs,
+                        const double2* cc, const double2* ag, int segV, int segP, int nf, double2* part,
+                        double2* out, Mask mk) {
+  const int chV = (segV + kFChunk - 1) / kFChunk, chP = (segP + kFChunk - 1) / kFChunk, nch = chV + chP;
+  hipLaunchKernelGGL(k_fupdate_lag<R>, dim3(nch, nf), dim3(256), 0, s, bV, bP, ldV, ldP, k, cs, cc, ag, segV, segP,
+                     chV, nch, nf, part, mk);
+  hipLaunchKernelGGL(k_fdot_reduce, dim3((nf + 255) / 256), dim3(256), 0, s, part, 1, nf, nch, out);
+}
+
+size_t lag_part_entries(int segV, int segP, int nf, int m) {
+  const int nch = (segV + kFChunk - 1) / kFChunk + (segP + kFChunk - 1) / kFChunk;
+  return (size_t)(2 * m + 2) * nf * nch;
+}
+
+template <typename R>
 void launch_fupdate(hipStream_t s, cpx<R>* wV, cpx<R>* wP, const cpx<R>* bV, const cpx<R>* bP, size_t ldV,
                     size_t ldP, int k, const double2* c, int segV, int segP, int nf, double sign, Mask mk) {
   const size_t tot = (size_t)segV + segP;
@@ -196,7 +358,11 @@ void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n) {
                                   const double2*, int, int, int, double, Mask);                                          \
   template void launch_fscale<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, int, \
                                  int, int, Mask);                                                                        \
-  template void launch_unpin_copy<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, Mask);
+  template void launch_unpin_copy<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, Mask);                         \
+  template void launch_fdot_lag<R>(hipStream_t, const cpx<R>*, const cpx<R>*, size_t, size_t, int, const cpx<R>*,  \
+                                   const cpx<R>*, const cpx<R>*, const cpx<R>*, int, int, int, double2*, double2*, Mask); \
+  template void launch_fupdate_lag<R>(hipStream_t, cpx<R>*, cpx<R>*, size_t, size_t, int, const double2*,           \
+                                      const double2*, const double2*, int, int, int, double2*, double2*, Mask);
 
 PINTOC_INNER_INST(double)
 PINTOC_INNER_INST(float)

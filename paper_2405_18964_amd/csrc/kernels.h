@@ -71,6 +71,15 @@ template <typename R>
 void launch_fupdate(hipStream_t s, cpx<R>* wV, cpx<R>* wP, const cpx<R>* bV, const cpx<R>* bP, size_t ldV,
                     size_t ldP, int k, const double2* c, int segV, int segP, int nf, double sign, Mask mk);
 template <typename R>
+void launch_fdot_lag(hipStream_t s, const cpx<R>* bV, const cpx<R>* bP, size_t ldV, size_t ldP, int k,
+                     const cpx<R>* uV, const cpx<R>* uP, const cpx<R>* wV, const cpx<R>* wP, int segV, int segP,
+                     int nf, double2* part, double2* out, Mask mk);
+template <typename R>
+void launch_fupdate_lag(hipStream_t s, cpx<R>* bV, cpx<R>* bP, size_t ldV, size_t ldP, int k, const double2* cs,
+                        const double2* cc, const double2* ag, int segV, int segP, int nf, double2* part,
+                        double2* out, Mask mk);
+size_t lag_part_entries(int segV, int segP, int nf, int m);
+template <typename R>
 void launch_fscale(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, const double2* a,
                    int segV, int segP, int nf, Mask mk);
 template <typename R>

@@ -4,6 +4,7 @@
 // fft_kernels.hip, mg_kernels.hip and kkt_kernels.hip; the host only holds
 // scalars (per-frequency constants, Hessenberg matrices, coarsest-grid
 // inverses computed once at set-up).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -98,6 +99,9 @@ struct pintoc_problem {
   void *ZtV = nullptr, *ZtP = nullptr, *UV = nullptr, *UP = nullptr, *BV = nullptr, *BP = nullptr;
   void *Ptmp = nullptr, *PxK = nullptr, *PxM = nullptr, *PxM2 = nullptr;
   double2 *cj = nullptr, *hdev = nullptr, *h2dev = nullptr, *ydev = nullptr, *fpart = nullptr;
+  // lagged Gram-Schmidt: dot sweep results, update coefficients (s_i, c_i per
+  // frequency; alpha and gamma), norms of the once-projected vectors
+  double2 *lagOut = nullptr, *lagCS = nullptr, *lagCC = nullptr, *lagAG = nullptr, *lagRho = nullptr;
   std::vector<double2> cj_h;
   int segV = 0, segP = 0;
   MGPlan mgW, mgK;
@@ -287,7 +291,13 @@ static void carve(pintoc_problem* p, char* base) {
     p->hdev = cv.take<double2>(sizeof(double2) * (mi + 1) * nf);
     p->h2dev = cv.take<double2>(sizeof(double2) * (mi + 1) * nf);
     p->ydev = cv.take<double2>(sizeof(double2) * (mi + 1) * nf);
-    p->fpart = cv.take<double2>(sizeof(double2) * fdot_part_entries(p->segV, p->segP, nf));
+    p->fpart = cv.take<double2>(sizeof(double2) * std::max(fdot_part_entries(p->segV, p->segP, nf),
+                                                           lag_part_entries(p->segV, p->segP, nf, mi)));
+    p->lagOut = cv.take<double2>(sizeof(double2) * (2 * mi + 2) * nf);
+    p->lagCS = cv.take<double2>(sizeof(double2) * mi * nf);
+    p->lagCC = cv.take<double2>(sizeof(double2) * mi * nf);
+    p->lagAG = cv.take<double2>(sizeof(double2) * 2 * nf);
+    p->lagRho = cv.take<double2>(sizeof(double2) * nf);
   }
   p->bc = cv.take<BlockCoef>(sizeof(BlockCoef) * nf);
   p->maskd = cv.take<int>(sizeof(int) * nf);
@@ -796,19 +806,36 @@ static void givens(cd a, cd b, double& c, cd& sn) {
 // Batched right-preconditioned GMRES, one system Z_j x_j = s_j per kept
 // frequency (Algorithm 2): x_0 = 0, restart m, stop for frequency j when the
 // Arnoldi residual estimate satisfies |g_{k+1}| <= eps ||s_j||.  All
-// frequencies advance in lockstep; a converged frequency's Hessenberg matrix
-// is frozen and its later basis vectors are ignored.  Orthogonalisation:
-// classical Gram-Schmidt applied twice.
+// frequencies advance in lockstep under a per-frequency mask.
+//
+// Orthogonalisation: classical Gram-Schmidt applied twice, with the second
+// pass of column k - 1 carried out in the same sweep over the basis as the
+// first pass of column k.  Iteration k holds final orthonormal q_0..q_{k-1}
+// and the once-projected u_k (u_0 = q_0):
+//   w^ = Z P~^{-1} u_k;  s = Q^H u_k, t = Q^H w^, nu = u_k^H u_k, mu = u_k^H w^
+//   column k-1 += s,  H[k][k-1] = alpha = sqrt(nu - |s|^2),  q_k = (u_k - Q s)/alpha
+//   since Z P~^{-1} q_k = (w^ - sum_i s_i Z P~^{-1} q_i)/alpha and
+//   Z P~^{-1} q_i = sum_r H[r][i] q_r, with e = H[0:k+1, 0:k] s and
+//   beta = (mu - s^H t)/alpha:
+//     H[i][k] = (t_i - e_i)/alpha (i < k),  H[k][k] = (beta - e_k)/alpha,
+//     u_{k+1} = (w^ - gamma u_k - Q (t - gamma s))/alpha,  gamma = beta/alpha.
+// Column k is final once the next sweep adds Q_k^H u_{k+1}.  The stopping test
+// is taken on final columns only: when the test on the tentative column k
+// (subdiagonal ||u_{k+1}||) passes, a dot sweep finishes column k before the
+// decision; a frequency whose final column k - 1 passes only at iteration k
+// stops there (its last operator application is discarded).  Decisions and
+// results equal those of Gram-Schmidt applied twice column by column.
 template <typename R>
 static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
-  const int nf = p->nf, m = p->o.inner_restart, segV = p->segV, segP = p->segP, N = p->d.N;
+  const int nf = p->nf, m = p->o.inner_restart, segV = p->segV, segP = p->segP;
   const size_t ldV = (size_t)segV * nf, ldP = (size_t)segP * nf;
   cpx<R>*SV = (cpx<R>*)p->Vb, *SP = (cpx<R>*)p->Pb, *XV = (cpx<R>*)p->Vx, *XP = (cpx<R>*)p->Px;
   cpx<R>*BV = (cpx<R>*)p->BV, *BP = (cpx<R>*)p->BP, *ZV = (cpx<R>*)p->ZtV, *ZP = (cpx<R>*)p->ZtP;
   cpx<R>*UV = (cpx<R>*)p->UV, *UP = (cpx<R>*)p->UP;
   auto BVk = [&](int k) { return BV + (size_t)k * ldV; };
   auto BPk = [&](int k) { return BP + (size_t)k * ldP; };
-  std::vector<double2> hb((size_t)(m + 1) * nf), hb2((size_t)(m + 1) * nf), scl(nf), yv((size_t)(m + 1) * nf);
+  std::vector<double2> hb((size_t)(2 * m + 2) * nf), scl(nf), yv((size_t)(m + 1) * nf), rho(nf);
+  std::vector<double2> csh((size_t)m * nf), cch((size_t)m * nf), agh((size_t)2 * nf);
   auto fetch = [&](double2* dev, std::vector<double2>& host, int k) -> int {
     HIPCHK(hipMemcpyAsync(host.data(), dev, sizeof(double2) * k * nf, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -847,97 +874,182 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
   }
   launch_fill_zero(s, XV, (size_t)segV * nf * sizeof(cpx<R>));
   launch_fill_zero(s, XP, (size_t)segP * nf * sizeof(cpx<R>));
+  // per-frequency Hessenberg columns (unrotated), committed Givens rotations, g
   std::vector<cd> H((size_t)nf * (m + 1) * m), sn((size_t)nf * m), g((size_t)nf * (m + 1));
   std::vector<double> cs((size_t)nf * m);
+  std::vector<char> fin((size_t)nf * m);
+  auto Hj = [&](int j, int r, int c) -> cd& { return H[((size_t)j * (m + 1) + r) * m + c]; };
+  std::vector<cd> col(m + 2);
+  auto rotated = [&](int j, int k) {          // column k with rotations 0..k-1 applied
+    for (int r = 0; r <= k + 1; ++r) col[r] = Hj(j, r, k);
+    for (int i = 0; i < k; ++i) {
+      const cd a = col[i], c = col[i + 1];
+      const double ci = cs[(size_t)j * m + i];
+      const cd si = sn[(size_t)j * m + i];
+      col[i] = ci * a + si * c;
+      col[i + 1] = -std::conj(si) * a + ci * c;
+    }
+  };
+  auto commit = [&](int j, int k) -> double {  // rotation k of a final column; |g[k+1]|
+    rotated(j, k);
+    double ck; cd sk;
+    givens(col[k], col[k + 1], ck, sk);
+    cs[(size_t)j * m + k] = ck;
+    sn[(size_t)j * m + k] = sk;
+    cd* gj = g.data() + (size_t)j * (m + 1);
+    gj[k + 1] = -std::conj(sk) * gj[k];
+    gj[k] = ck * gj[k];
+    return std::abs(gj[k + 1]);
+  };
+  auto tentative = [&](int j, int k) -> double {
+    rotated(j, k);
+    double ck; cd sk;
+    givens(col[k], col[k + 1], ck, sk);
+    return std::abs(std::conj(sk) * g[(size_t)j * (m + 1) + k]);
+  };
   const cpx<R>*RV = SV, *RP = SP;          // residual of the current cycle
   int total = 0;
   while (true) {
     bool any = false;
     for (int j = 0; j < nf; ++j) any |= !done[j];
     if (!any || total >= p->o.inner_maxit) break;
-    // v_0 = r / ||r|| for the frequencies still running
+    // q_0 = r / ||r|| for the frequencies still running
     std::vector<int> running(nf);
     for (int j = 0; j < nf; ++j) running[j] = !done[j];
     if ((rc = set_mask(running))) return rc;
     for (int j = 0; j < nf; ++j) scl[j] = make_double2(done[j] ? 0.0 : 1.0 / rnorm[j], 0.0);
     if ((rc = upload(p->ydev, scl, 1))) return rc;
     launch_fscale<R>(s, BVk(0), BPk(0), RV, RP, p->ydev, segV, segP, nf, p->mk(1));
-    std::vector<int> kj(nf, 0), active(nf);
-    for (int j = 0; j < nf; ++j) {
-      active[j] = !done[j];
-      std::fill(g.begin() + (size_t)j * (m + 1), g.begin() + (size_t)(j + 1) * (m + 1), cd(0.0));
-      g[(size_t)j * (m + 1)] = rnorm[j];
-    }
+    std::vector<int> kj(nf, 0), active = running;
+    std::fill(H.begin(), H.end(), cd(0.0));
+    std::fill(g.begin(), g.end(), cd(0.0));
+    std::fill(fin.begin(), fin.end(), 0);
+    for (int j = 0; j < nf; ++j) g[(size_t)j * (m + 1)] = rnorm[j];
+    auto any_of = [&](const std::vector<int>& v) {
+      for (int x : v) if (x) return true;
+      return false;
+    };
     int k = 0;
-    for (; k < m && total < p->o.inner_maxit; ++k) {
+    for (; k < m; ++k) {
+      if (active != p->mask_h && (rc = set_mask(active))) return rc;
+      // operator on the once-projected u_k, then the fused dot sweep
       block_precond<R>(p, s, BVk(k), BPk(k), ZV, ZP);
       block_matvec<R>(p, s, BVk(k + 1), BPk(k + 1), ZV, ZP);
-      const Mask m1 = p->mk(1);
-      launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->hdev, m1);
-      launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->hdev, segV, segP, nf, 1.0, m1);
-      launch_fdot<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart, p->h2dev, m1);
-      launch_fupdate<R>(s, BVk(k + 1), BPk(k + 1), BV, BP, ldV, ldP, k + 1, p->h2dev, segV, segP, nf, 1.0, m1);
-      launch_fdot<R>(s, BVk(k + 1), BPk(k + 1), 0, 0, 1, BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart,
-                     p->ydev, m1);
-      if ((rc = fetch(p->hdev, hb, k + 1)) || (rc = fetch(p->h2dev, hb2, k + 1))) return rc;
-      std::vector<double2> nr(nf);
-      if ((rc = fetch(p->ydev, nr, 1))) return rc;
+      launch_fdot_lag<R>(s, BV, BP, ldV, ldP, k, BVk(k), BPk(k), BVk(k + 1), BPk(k + 1), segV, segP, nf, p->fpart,
+                         p->lagOut, p->mk(1));
+      if ((rc = fetch(p->lagOut, hb, 2 * k + 2))) return rc;
+      std::vector<int> upd = active;
       for (int j = 0; j < nf; ++j) {
-        const double hk1 = std::sqrt(std::max(nr[j].x, 0.0));
-        scl[j] = make_double2(active[j] && hk1 > 0 ? 1.0 / hk1 : 0.0, 0.0);
         if (!active[j]) continue;
-        cd* Hj = H.data() + (size_t)j * (m + 1) * m;
-        for (int i = 0; i <= k; ++i)
-          Hj[(size_t)i * m + k] = cd(hb[(size_t)i * nf + j].x + hb2[(size_t)i * nf + j].x,
-                                     hb[(size_t)i * nf + j].y + hb2[(size_t)i * nf + j].y);
-        Hj[(size_t)(k + 1) * m + k] = hk1;
-        for (int i = 0; i < k; ++i) {
-          const cd a = Hj[(size_t)i * m + k], c = Hj[(size_t)(i + 1) * m + k];
-          const double ci = cs[(size_t)j * m + i];
-          const cd si = sn[(size_t)j * m + i];
-          Hj[(size_t)i * m + k] = ci * a + si * c;
-          Hj[(size_t)(i + 1) * m + k] = -std::conj(si) * a + ci * c;
+        auto sv = [&](int i) { const double2 v = hb[(size_t)i * nf + j]; return cd(v.x, v.y); };
+        auto tv = [&](int i) { const double2 v = hb[(size_t)(k + i) * nf + j]; return cd(v.x, v.y); };
+        const double nu = hb[(size_t)(2 * k) * nf + j].x;
+        const cd mu(hb[(size_t)(2 * k + 1) * nf + j].x, hb[(size_t)(2 * k + 1) * nf + j].y);
+        double alpha = 1.0;
+        if (k > 0) {
+          if (!fin[(size_t)j * m + k - 1]) {           // finish column k - 1
+            double ss = 0;
+            for (int i = 0; i < k; ++i) { Hj(j, i, k - 1) += sv(i); ss += std::norm(sv(i)); }
+            Hj(j, k, k - 1) = std::sqrt(std::max(nu - ss, 0.0));
+            fin[(size_t)j * m + k - 1] = 1;
+            if (commit(j, k - 1) <= p->o.inner_tol * bnorm[j] || Hj(j, k, k - 1) == 0.0) {
+              done[j] = 1; kj[j] = k; upd[j] = 0;
+              continue;
+            }
+          }
+          alpha = Hj(j, k, k - 1).real();
         }
-        double ck; cd sk;
-        givens(Hj[(size_t)k * m + k], Hj[(size_t)(k + 1) * m + k], ck, sk);
-        cs[(size_t)j * m + k] = ck;
-        sn[(size_t)j * m + k] = sk;
-        Hj[(size_t)k * m + k] = ck * Hj[(size_t)k * m + k] + sk * Hj[(size_t)(k + 1) * m + k];
-        Hj[(size_t)(k + 1) * m + k] = 0.0;
-        cd* gj = g.data() + (size_t)j * (m + 1);
-        gj[k + 1] = -std::conj(sk) * gj[k];
-        gj[k] = ck * gj[k];
-        kj[j] = k + 1;
-        its[j]++;
-        if (std::abs(gj[k + 1]) <= p->o.inner_tol * bnorm[j] || hk1 == 0.0) { active[j] = 0; done[j] = 1; }
+        // first pass of column k from the sweep's dot products
+        cd stt = 0.0;
+        for (int i = 0; i < k; ++i) stt += std::conj(sv(i)) * tv(i);
+        const cd bk = (mu - stt) / alpha, gam = bk / alpha;
+        for (int r = 0; r <= k; ++r) {
+          cd e = 0.0;
+          for (int l = std::max(r - 1, 0); l < k; ++l) e += Hj(j, r, l) * sv(l);
+          Hj(j, r, k) = (r < k ? tv(r) - e : bk - e) / alpha;
+        }
+        for (int i = 0; i < k; ++i) {
+          const cd si = sv(i), ci = tv(i) - gam * si;
+          csh[(size_t)i * nf + j] = make_double2(si.real(), si.imag());
+          cch[(size_t)i * nf + j] = make_double2(ci.real(), ci.imag());
+        }
+        agh[j] = make_double2(alpha, 0.0);
+        agh[nf + j] = make_double2(gam.real(), gam.imag());
       }
-      if ((rc = upload(p->ydev, scl, 1))) return rc;
-      launch_fscale<R>(s, BVk(k + 1), BPk(k + 1), BVk(k + 1), BPk(k + 1), p->ydev, segV, segP, nf, m1);
+      active = upd;
+      if (!any_of(active)) break;
+      // fused update sweep: q_k, u_{k+1} and ||u_{k+1}||^2
+      if (active != p->mask_h && (rc = set_mask(active))) return rc;
+      if (k > 0 && ((rc = upload(p->lagCS, csh, k)) || (rc = upload(p->lagCC, cch, k)))) return rc;
+      if ((rc = upload(p->lagAG, agh, 2))) return rc;
+      launch_fupdate_lag<R>(s, BV, BP, ldV, ldP, k, p->lagCS, p->lagCC, p->lagAG, segV, segP, nf, p->fpart, p->lagRho,
+                            p->mk(1));
+      if ((rc = fetch(p->lagRho, rho, 1))) return rc;
       ++total;
-      bool any_active = false;
-      for (int j = 0; j < nf; ++j) any_active |= active[j] != 0;
-      if (!any_active) { ++k; break; }
-      if (active != p->mask_h && (rc = set_mask(active))) return rc;     // drop converged frequencies
+      // tentative test on column k; finish it at once where it passes or the cycle ends
+      std::vector<int> fnl(nf, 0);
+      bool anyf = false;
+      const bool last = k + 1 == m || total >= p->o.inner_maxit;
+      for (int j = 0; j < nf; ++j) {
+        if (!active[j]) continue;
+        its[j]++;
+        const double r2 = std::max(rho[j].x, 0.0);
+        Hj(j, k + 1, k) = std::sqrt(r2);
+        if (last || r2 == 0.0 || tentative(j, k) <= p->o.inner_tol * bnorm[j]) { fnl[j] = 1; anyf = true; }
+      }
+      if (anyf) {
+        if ((rc = set_mask(fnl))) return rc;
+        launch_fdot_lag<R>(s, BV, BP, ldV, ldP, k + 1, BVk(k + 1), BPk(k + 1), (const cpx<R>*)nullptr,
+                           (const cpx<R>*)nullptr, segV, segP, nf, p->fpart, p->lagOut, p->mk(1));
+        if ((rc = fetch(p->lagOut, hb, 2 * k + 4))) return rc;
+        for (int j = 0; j < nf; ++j) {
+          if (!fnl[j]) continue;
+          double ss = 0;
+          for (int i = 0; i <= k; ++i) {
+            const cd si(hb[(size_t)i * nf + j].x, hb[(size_t)i * nf + j].y);
+            Hj(j, i, k) += si;
+            ss += std::norm(si);
+          }
+          Hj(j, k + 1, k) = std::sqrt(std::max(hb[(size_t)(2 * k + 2) * nf + j].x - ss, 0.0));
+          fin[(size_t)j * m + k] = 1;
+          const double res = commit(j, k);
+          if (res <= p->o.inner_tol * bnorm[j] || Hj(j, k + 1, k) == 0.0) {
+            done[j] = 1; kj[j] = k + 1; active[j] = 0;
+          } else if (last) {
+            kj[j] = k + 1; active[j] = 0;
+          }
+        }
+      }
+      if (!any_of(active)) { ++k; break; }
     }
-    // y_j = H_j^{-1} g_j (size kj), U = sum_i y_ij v_i, X += P~^{-1} U
+    // y_j = R_j^{-1} g_j (size kj), U = sum_i y_ij q_i, X += P~^{-1} U
     std::fill(yv.begin(), yv.end(), make_double2(0, 0));
+    int kmax = 0;
     for (int j = 0; j < nf; ++j) {
+      if (!running[j]) continue;
       const int kk = kj[j];
-      const cd* Hj = H.data() + (size_t)j * (m + 1) * m;
+      kmax = std::max(kmax, kk);
+      std::vector<cd> Rm((size_t)kk * kk), y(kk);
+      for (int c = 0; c < kk; ++c) {
+        rotated(j, c);
+        const double ck = cs[(size_t)j * m + c];
+        const cd sk = sn[(size_t)j * m + c];
+        col[c] = ck * col[c] + sk * col[c + 1];
+        for (int r = 0; r <= c; ++r) Rm[(size_t)r * kk + c] = col[r];
+      }
       const cd* gj = g.data() + (size_t)j * (m + 1);
-      std::vector<cd> y(kk);
       for (int i = kk - 1; i >= 0; --i) {
         cd v = gj[i];
-        for (int q = i + 1; q < kk; ++q) v -= Hj[(size_t)i * m + q] * y[q];
-        y[i] = v / Hj[(size_t)i * m + i];
+        for (int q = i + 1; q < kk; ++q) v -= Rm[(size_t)i * kk + q] * y[q];
+        y[i] = v / Rm[(size_t)i * kk + i];
       }
       for (int i = 0; i < kk; ++i) yv[(size_t)i * nf + j] = make_double2(y[i].real(), y[i].imag());
     }
-    if ((rc = upload(p->ydev, yv, k))) return rc;
+    if ((rc = upload(p->ydev, yv, kmax))) return rc;
     if ((rc = set_mask(running))) return rc;                 // every frequency that ran in this cycle
     launch_fill_zero(s, UV, (size_t)segV * nf * sizeof(cpx<R>));
     launch_fill_zero(s, UP, (size_t)segP * nf * sizeof(cpx<R>));
-    launch_fupdate<R>(s, UV, UP, BV, BP, ldV, ldP, k, p->ydev, segV, segP, nf, -1.0, p->mk(1));
+    launch_fupdate<R>(s, UV, UP, BV, BP, ldV, ldP, kmax, p->ydev, segV, segP, nf, -1.0, p->mk(1));
     block_precond<R>(p, s, UV, UP, ZV, ZP);
     for (int j = 0; j < nf; ++j) scl[j] = make_double2(1.0, 0.0);
     if ((rc = upload(p->hdev, scl, 1))) return rc;
