@@ -23,6 +23,25 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel (finest-grid pre-smoothing sweep) from two
+# rocprofv3 --pmc passes over one solve of this workload (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch at the finest grid), each scaled by what the
+# same counter reads for a 1 GiB device copy in the same process (FETCH_SIZE
+# 524315.7 KiB, WRITE_SIZE 1048576 KiB).  Valid only for the kernel source they
+# were taken on: reported as null once that file changes.
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2405_18964_amd", "csrc", "q2_tiles.hip")
+SWEEP_PMC = {"source_sha256": "816a618418dafb3d7df0621ab3db53f1cf41eb8ff7f9f7123785d94c82ea1924",
+             "fetch_kib": 363429.2, "fetch_scale": 1048576.0 / 524315.7,
+             "write_kib": 419683.5, "write_scale": 1.0}
+
+
+def sweep_traffic_bytes():
+    import hashlib
+    with open(SWEEP_SOURCE, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != SWEEP_PMC["source_sha256"]:
+            return None
+    return 1024.0 * (SWEEP_PMC["fetch_kib"] * SWEEP_PMC["fetch_scale"] + SWEEP_PMC["write_kib"] * SWEEP_PMC["write_scale"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -34,6 +53,9 @@ def parse():
     ap.add_argument("--inner", choices=["gmres", "linear"], default="gmres")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond-reps", type=int, default=5)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the extra FP32-inner solve")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one device copy of 1 GiB first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -43,14 +65,13 @@ def precond_model_bytes(N: int, nt: int, n_vcycles: int, n_cheb: int, csize: int
 
     Field sizes per kept frequency (nf = nt/2 + 1): 4 complex Q2 grids (velocity
     of both blocks) and 2 complex Q1 grids (pressure).  Per multigrid level
-    (sizes shrink by 4): a smoothing sweep reads x, b and writes x (3 passes),
-    residual reads x, b and writes r (3), restriction reads r and writes the
-    coarse rhs (1 + 1/4), prolongation reads the coarse correction and
-    reads/writes x (2 + 1/4); a V-cycle therefore moves about
-    (3 + 3 + 1.25 + 2.25 + 3) = 12.5 fine-field passes per level, times 4/3
-    over the hierarchy.  A Chebyshev step reads x_k, x_{k-1}, b, writes x_{k+1}.
-    The FFT pair reads and writes the canonical vector and the frequency
-    vector once each."""
+    (sizes shrink by 4): the pre-smoothing sweep reads x, b and writes x (3
+    passes), the residual reads x, b and writes r (3), the restriction reads r
+    and writes the coarse rhs (1 + 1/4), the post-smoothing sweep reads x, the
+    coarse correction and b and writes x (3 + 1/4): 10.5 fine-field passes per
+    level, times 4/3 over the hierarchy = 14 per V-cycle.  A Chebyshev step
+    reads x_k, x_{k-1}, b, writes x_{k+1}.  The FFT pair reads and writes the
+    canonical vector and the frequency vector once each."""
     nf = nt // 2 + 1
     nq2, np2 = (2 * N + 1) ** 2, (N + 1) ** 2
     FV = 4 * nf * nq2 * csize          # velocity frequency fields
@@ -58,7 +79,7 @@ def precond_model_bytes(N: int, nt: int, n_vcycles: int, n_cheb: int, csize: int
     L = 2 * nq2 + np2
     canon = 2 * nt * L * 8
     freq = FV + FP
-    vcycle = 12.5 * 4.0 / 3.0
+    vcycle = 10.5 * 4.0 / 3.0
     mg_w = n_vcycles * vcycle * FV
     mg_k = n_vcycles * vcycle * FP
     cheb = (1 + 4 * (n_cheb - 1)) * FP
@@ -125,6 +146,12 @@ def main():
     inner = P.INNER_GMRES if args.inner == "gmres" else P.INNER_LINEAR
     gp = P.Problem.from_workload(w, inner=inner, precision=prec, max_outer=60 if args.inner == "gmres" else 400,
                                  restart=10 if args.inner == "gmres" else 30)
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     vd = torch.from_numpy(W.desired_state(w)).cuda()
     b = gp.assemble_rhs(vd)
     x = gp.empty()
@@ -208,10 +235,30 @@ def main():
     }
     achieved = kt["algorithmic_bytes"] / (kt["avg_ms"] * 1e-3) / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                       "kernel": "k_q2_tile_sweep (finest-grid velocity smoothing sweep, all kept frequencies)",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic_bytes(),
+                       "kernel": "k_q2_sweep<double,false,true,false> (finest-grid pre-smoothing sweep of the "
+                                 "velocity multigrid, all kept frequencies)",
                        "avg_launch_ms": kt["avg_ms"], "launches_timed": kt["launches"],
                        "algorithmic_bytes_per_launch": kt["algorithmic_bytes"]}
+    if not args.no_fp32 and args.precision == "fp64":
+        del gp
+        torch.cuda.empty_cache()
+        g32 = P.Problem.from_workload(w, inner=inner, precision=P.PREC_FP32_INNER, max_outer=60, restart=10)
+        x.zero_()
+        g32.solve(b, x)                                  # warm-up
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st32, ok32 = g32.solve(b, x)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t1
+        r32 = float(torch.linalg.norm(b - g32.kkt_apply(x)) / torch.linalg.norm(b))
+        out["fp32_inner"] = {"solves_per_s": 1.0 / t32, "seconds": t32, "converged": bool(ok32),
+                             "final_rel_residual": r32, "outer": st32["outer_iterations"],
+                             "inner_mean": st32["inner_iterations_mean"],
+                             "note": "multigrid, Chebyshev, Uzawa and inner GMRES in FP32; outer FGMRES, "
+                                     "residuals and the coarsest-grid inverses in FP64"}
+        del g32
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, outer, inner_mean)
     print(json.dumps(out), flush=True)
