@@ -8,6 +8,8 @@
 //   P part [j][b][(N+1)^2]          b = 0: p,  b = 1: mu   (node 0 pinned, zero)
 // Dot products are per frequency with the Hermitian inner product, reduced in
 // a fixed order (chunk partial sums, then a sequential sum over chunks).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace pintoc {
@@ -82,10 +84,11 @@ __global__ __launch_bounds__(256) void k_fdot_reduce(const double2* __restrict__
 // Dot pass, per frequency: s_i = q_i^H u, t_i = q_i^H w (i < k), nu = u^H u,
 // mu = u^H w, with q_i = basis vector i, u = basis vector k, w = basis vector
 // k + 1 (w == nullptr: s and nu only).  One launch covers i in [i0, i1) (nu
-// and mu with i0 = 0); wave q of a work-group handles i = i0 + q, i0 + q + 4,
+// and mu with i0 = 0); wave q of a work-group handles i = i0 + q, i0 + q + 8,
 // ...; partial sums per chunk go to
 // part[(slot * nf + j) * nch + chunk], slots s_0..s_{k-1}, t_0..t_{k-1}, nu, mu.
-constexpr int kLW = 13;                  // basis vectors per wave: k <= 52
+constexpr int kLW = 7;                   // basis vectors per wave
+constexpr int kLWaves = 6;               // waves per work-group: k <= 42 per launch
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -93,13 +96,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// kU consecutive complex entries at p (16-byte loads: one FP64 or two FP32 entries)
+template <typename R, int kU> struct Pack;
+template <> struct Pack<double, 1> {
+  double2 v[1];
+  __device__ __forceinline__ void load(const double2* p) { v[0] = *p; }
+  __device__ __forceinline__ void zero() { v[0] = make_double2(0, 0); }
+};
+template <> struct Pack<float, 2> {
+  float2 v[2];
+  __device__ __forceinline__ void load(const float2* p) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = make_float2(q.x, q.y);
+    v[1] = make_float2(q.z, q.w);
+  }
+  __device__ __forceinline__ void zero() { v[0] = make_float2(0, 0); v[1] = v[0]; }
+};
+
+// Work-groups of 64 W threads (W = blockDim.x / 64 waves); wave q takes the
+// basis vectors i = i0 + q + W r.  Every lane reads 16 bytes per vector and
+// step (one FP64 or two FP32 entries); segments and chunk bounds are even.
 template <typename R>
-__global__ __launch_bounds__(256) void k_fdot_lag(const cpx<R>* __restrict__ bV, const cpx<R>* __restrict__ bP,
+__global__ __launch_bounds__(64 * kLWaves) void k_fdot_lag(const cpx<R>* __restrict__ bV, const cpx<R>* __restrict__ bP,
                                                   size_t ldV, size_t ldP, int k, int i0, int i1,
                                                   const cpx<R>* __restrict__ uV,
                                                   const cpx<R>* __restrict__ uP, const cpx<R>* __restrict__ wV,
                                                   const cpx<R>* __restrict__ wP, int segV, int segP, int chV, int nch,
                                                   int nf, double2* __restrict__ part, Mask mk) {
+  constexpr int kU = sizeof(R) == 4 ? 2 : 1;
   const int j = blockIdx.y, c = blockIdx.x;
   if (mk.off(j)) return;
   const bool inV = c < chV;
@@ -110,28 +134,39 @@ __global__ __launch_bounds__(256) void k_fdot_lag(const cpx<R>* __restrict__ bV,
   const cpx<R>* U = inV ? uV : uP;
   const cpx<R>* W = inV ? wV : wP;
   const size_t ld = inV ? ldV : ldP;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool mine = wv == 0 && i0 == 0;          // this wave also forms nu and mu
+  bool any = mine;
+#pragma unroll
+  for (int q = 0; q < kLW; ++q) any |= i0 + wv + nw * q < i1;
   double sr[kLW], si[kLW], tr[kLW], ti[kLW];
 #pragma unroll
   for (int q = 0; q < kLW; ++q) { sr[q] = 0; si[q] = 0; tr[q] = 0; ti[q] = 0; }
   double nu = 0, mur = 0, mui = 0;
   const int lo = cc * kFChunk, hi = min(lo + kFChunk, seg);
-  for (int e = lo + lane; e < hi; e += 64) {
-    const cpx<R> u = U[base + e];
-    const double ur = (double)u.x, ui = (double)u.y;
-    double wr = 0, wi = 0;
-    if (W) { const cpx<R> w = W[base + e]; wr = (double)w.x; wi = (double)w.y; }
-    if (wv == 0 && i0 == 0) {
-      nu += ur * ur + ui * ui;
-      mur += ur * wr + ui * wi;                // conj(u) w
-      mui += ur * wi - ui * wr;
-    }
+  for (int e = lo + kU * lane; any && e < hi; e += 64 * kU) {
+    Pack<R, kU> u, w;
+    u.load(U + base + e);
+    if (W) w.load(W + base + e);
+    else w.zero();
+    Pack<R, kU> vv[kLW];
 #pragma unroll
     for (int q = 0; q < kLW; ++q) {
-      const int i = i0 + wv + 4 * q;
-      if (i < i1) {
-        const cpx<R> v = B[(size_t)i * ld + base + e];
-        const double vr = (double)v.x, vi = (double)v.y;
+      const int i = i0 + wv + nw * q;
+      if (i < i1) vv[q].load(B + (size_t)i * ld + base + e);
+      else vv[q].zero();
+    }
+#pragma unroll
+    for (int h = 0; h < kU; ++h) {
+      const double ur = (double)u.v[h].x, ui = (double)u.v[h].y, wr = (double)w.v[h].x, wi = (double)w.v[h].y;
+      if (mine) {
+        nu += ur * ur + ui * ui;
+        mur += ur * wr + ui * wi;              // conj(u) w
+        mui += ur * wi - ui * wr;
+      }
+#pragma unroll
+      for (int q = 0; q < kLW; ++q) {
+        const double vr = (double)vv[q].v[h].x, vi = (double)vv[q].v[h].y;
         sr[q] += vr * ur + vi * ui;  si[q] += vr * ui - vi * ur;      // conj(v) u
         tr[q] += vr * wr + vi * wi;  ti[q] += vr * wi - vi * wr;      // conj(v) w
       }
@@ -144,13 +179,13 @@ __global__ __launch_bounds__(256) void k_fdot_lag(const cpx<R>* __restrict__ bV,
   };
 #pragma unroll
   for (int q = 0; q < kLW; ++q) {
-    const int i = i0 + wv + 4 * q;
+    const int i = i0 + wv + nw * q;
     if (i < i1) {
       put(i, sr[q], si[q]);
       if (W) put(k + i, tr[q], ti[q]);
     }
   }
-  if (wv == 0 && i0 == 0) {
+  if (mine) {
     put(2 * k, nu, 0.0);
     if (W) put(2 * k + 1, mur, mui);
   }
@@ -182,22 +217,35 @@ __global__ __launch_bounds__(256) void k_fupdate_lag(cpx<R>* __restrict__ bV, cp
   cpx<R>* W = B + (size_t)(k + 1) * ld + base;
   double nrm = 0;
   const int lo = ch * kFChunk, hi = min(lo + kFChunk, seg);
-  for (int e = lo + (int)threadIdx.x; e < hi; e += 256) {
-    const cpx<R> u = U[e], w = W[e];
-    const double ur = (double)u.x, ui = (double)u.y;
-    double asr = 0, asi = 0, acr = 0, aci = 0;
+  for (int e0 = lo + (int)threadIdx.x; e0 < hi; e0 += 512) {
+    const int e1 = e0 + 256;
+    const bool ok1 = e1 < hi;
+    const cpx<R> u0 = U[e0], w0 = W[e0];
+    const cpx<R> u1 = ok1 ? U[e1] : cmk<cpx<R>>(0, 0), w1 = ok1 ? W[e1] : cmk<cpx<R>>(0, 0);
+    double as[2][2] = {{0, 0}, {0, 0}}, ac[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll 4
     for (int i = 0; i < k; ++i) {
       const double2 si = cs[(size_t)i * nf + j], ci = cc[(size_t)i * nf + j];
-      const cpx<R> v = B[(size_t)i * ld + base + e];
-      const double vr = (double)v.x, vi = (double)v.y;
-      asr += si.x * vr - si.y * vi;  asi += si.x * vi + si.y * vr;
-      acr += ci.x * vr - ci.y * vi;  aci += ci.x * vi + ci.y * vr;
+      const cpx<R>* qi = B + (size_t)i * ld + base;
+      const cpx<R> v0 = qi[e0], v1 = ok1 ? qi[e1] : cmk<cpx<R>>(0, 0);
+      const double v0r = (double)v0.x, v0i = (double)v0.y, v1r = (double)v1.x, v1i = (double)v1.y;
+      as[0][0] += si.x * v0r - si.y * v0i;  as[0][1] += si.x * v0i + si.y * v0r;
+      ac[0][0] += ci.x * v0r - ci.y * v0i;  ac[0][1] += ci.x * v0i + ci.y * v0r;
+      as[1][0] += si.x * v1r - si.y * v1i;  as[1][1] += si.x * v1i + si.y * v1r;
+      ac[1][0] += ci.x * v1r - ci.y * v1i;  ac[1][1] += ci.x * v1i + ci.y * v1r;
     }
-    if (k > 0) U[e] = cmk<cpx<R>>((ur - asr) * ia, (ui - asi) * ia);
-    const cpx<R> un = cmk<cpx<R>>(((double)w.x - (gam.x * ur - gam.y * ui) - acr) * ia,
-                                  ((double)w.y - (gam.x * ui + gam.y * ur) - aci) * ia);
-    W[e] = un;
-    nrm += (double)un.x * (double)un.x + (double)un.y * (double)un.y;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !ok1) break;
+      const int e = h ? e1 : e0;
+      const cpx<R> u = h ? u1 : u0, w = h ? w1 : w0;
+      const double ur = (double)u.x, ui = (double)u.y;
+      if (k > 0) U[e] = cmk<cpx<R>>((ur - as[h][0]) * ia, (ui - as[h][1]) * ia);
+      const cpx<R> un = cmk<cpx<R>>(((double)w.x - (gam.x * ur - gam.y * ui) - ac[h][0]) * ia,
+                                    ((double)w.y - (gam.x * ui + gam.y * ur) - ac[h][1]) * ia);
+      W[e] = un;
+      nrm += (double)un.x * (double)un.x + (double)un.y * (double)un.y;
+    }
   }
   nrm = wave_sum(nrm);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
@@ -301,9 +349,10 @@ void launch_fdot_lag(hipStream_t s, const cpx<R>* bV, const cpx<R>* bP, size_t l
                      const cpx<R>* uV, const cpx<R>* uP, const cpx<R>* wV, const cpx<R>* wP, int segV, int segP,
                      int nf, double2* part, double2* out, Mask mk) {
   const int chV = (segV + kFChunk - 1) / kFChunk, chP = (segP + kFChunk - 1) / kFChunk, nch = chV + chP;
-  for (int i0 = 0; i0 < (k > 0 ? k : 1); i0 += 4 * kLW) {
-    const int i1 = i0 + 4 * kLW < k ? i0 + 4 * kLW : k;
-    hipLaunchKernelGGL(k_fdot_lag<R>, dim3(nch, nf), dim3(256), 0, s, bV, bP, ldV, ldP, k, i0, i1, uV, uP, wV, wP,
+  for (int i0 = 0; i0 < (k > 0 ? k : 1); i0 += kLWaves * kLW) {
+    const int i1 = i0 + kLWaves * kLW < k ? i0 + kLWaves * kLW : k;
+    const int waves = std::max(1, std::min(kLWaves, (i1 - i0 + kLW - 1) / kLW));
+    hipLaunchKernelGGL(k_fdot_lag<R>, dim3(nch, nf), dim3(64 * waves), 0, s, bV, bP, ldV, ldP, k, i0, i1, uV, uP, wV, wP,
                        segV, segP, chV, nch, nf, part, mk);
   }
   const int slots = 2 * k + 2;
