@@ -48,6 +48,9 @@ void launch_q2_sweep(hipStream_t s, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* 
 template <typename R>
 void launch_q2_apply(hipStream_t s, cpx<R>* out, const cpx<R>* x, const cpx<R>* b, int n, double h,
                      const OpCoef* coef, int fpc, int nb, const double* tconv, Mask mk);
+template <typename R>
+void launch_q2_block_vel(hipStream_t s, cpx<R>* yV, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
+                         const BlockCoef* bc, const double* tcN, const double* tcNT, Mask mk);
 size_t q2_tile_conv_entries(int n);
 void q2_tile_conv_table(int n, const double* t50, int half, double* out);
 
@@ -90,7 +93,7 @@ void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n);
 // frequency blocks and the Oseen preconditioner pieces (oseen_kernels.hip)
 template <typename R>
 void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                      const BlockCoef* bc, const double* conv, double sp, Mask mk);
+                      const BlockCoef* bc, const double* tcN, const double* tcNT, double sp, Mask mk);
 template <typename R>
 void launch_schur_rhs(hipStream_t s, cpx<R>* out, const cpx<R>* in, const cpx<R>* y1, const cpx<R>* y2, int n,
                       int nf, double tau, Mask mk);

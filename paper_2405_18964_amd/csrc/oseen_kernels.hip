@@ -16,99 +16,7 @@
 
 namespace pintoc {
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_block_vel(cpx<R>* __restrict__ yV, const cpx<R>* __restrict__ xV,
-                                                   const cpx<R>* __restrict__ xP, int n,
-                                                   const BlockCoef* __restrict__ bc, const double* __restrict__ conv, Mask mk) {
-  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
-  const int node = blockIdx.x * blockDim.x + threadIdx.x;
-  const int jc = blockIdx.y;                    // j * 2 + comp
-  if (node >= nq2 || mk.off(jc)) return;
-  const int comp = jc & 1, j = jc >> 1;
-  const size_t o0 = ((size_t)(j * 2 + 0) * 2 + comp) * nq2 + node;
-  const size_t o1 = ((size_t)(j * 2 + 1) * 2 + comp) * nq2 + node;
-  const int ix = node % nq, iy = node / nq;
-  if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) {
-    yV[o0] = cmk<cpx<R>>(0, 0);
-    yV[o1] = cmk<cpx<R>>(0, 0);
-    return;
-  }
-  const double h = 1.0 / n;
-  double mx[5], kx[5], my[5], ky[5];
-  q2_rows(ix, h, mx, kx);
-  q2_rows(iy, h, my, ky);
-  int cx[5], ry[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    cx[d] = min(max(ix + d - 2, 0), nq - 1);
-    ry[d] = min(max(iy + d - 2, 0), nq - 1) * nq;
-  }
-  const cpx<R>* v = xV + ((size_t)(j * 2 + 0) * 2 + comp) * nq2;
-  const cpx<R>* l = xV + ((size_t)(j * 2 + 1) * 2 + comp) * nq2;
-  double Mv[2] = {0, 0}, Kv[2] = {0, 0}, Ml[2] = {0, 0}, Kl[2] = {0, 0}, Nv[2] = {0, 0}, NTl[2] = {0, 0};
-  const double* cn = conv ? conv + (size_t)node * 50 : nullptr;
-#pragma unroll
-  for (int dy = 0; dy < 5; ++dy) {
-    double smv[2] = {0, 0}, skv[2] = {0, 0}, sml[2] = {0, 0}, skl[2] = {0, 0};
-#pragma unroll
-    for (int dx = 0; dx < 5; ++dx) {
-      const cpx<R> a = v[ry[dy] + cx[dx]], c = l[ry[dy] + cx[dx]];
-      smv[0] += mx[dx] * (double)a.x; smv[1] += mx[dx] * (double)a.y;
-      skv[0] += kx[dx] * (double)a.x; skv[1] += kx[dx] * (double)a.y;
-      sml[0] += mx[dx] * (double)c.x; sml[1] += mx[dx] * (double)c.y;
-      skl[0] += kx[dx] * (double)c.x; skl[1] += kx[dx] * (double)c.y;
-      if (cn) {
-        const double wn = cn[dy * 5 + dx], wt = cn[25 + dy * 5 + dx];
-        Nv[0] += wn * (double)a.x; Nv[1] += wn * (double)a.y;
-        NTl[0] += wt * (double)c.x; NTl[1] += wt * (double)c.y;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      Mv[q] += my[dy] * smv[q]; Kv[q] += ky[dy] * smv[q] + my[dy] * skv[q];
-      Ml[q] += my[dy] * sml[q]; Kl[q] += ky[dy] * sml[q] + my[dy] * skl[q];
-    }
-  }
-  // B^T mu (row 1) and B^T p (row 2) for this component
-  double mxx[3], gxx[3], mxy[3], gxy[3];
-  mixed_cols(ix, n, h, mxx, gxx);
-  mixed_cols(iy, n, h, mxy, gxy);
-  const int kx0 = (ix >> 1) - 1, ky0 = (iy >> 1) - 1;
-  const cpx<R>* pp = xP + (size_t)(j * 2 + 0) * np2;
-  const cpx<R>* pm = xP + (size_t)(j * 2 + 1) * np2;
-  double btp[2] = {0, 0}, btm[2] = {0, 0};
-  for (int a = 0; a < 3; ++a) {
-    const int kyy = ky0 + a;
-    if (kyy < 0 || kyy > n) continue;
-    const double wy = comp == 0 ? mxy[a] : gxy[a];
-    for (int c = 0; c < 3; ++c) {
-      const int kxx = kx0 + c;
-      if (kxx < 0 || kxx > n) continue;
-      const double wgt = wy * (comp == 0 ? gxx[c] : mxx[c]);
-      const cpx<R> p = pp[kyy * np + kxx], m = pm[kyy * np + kxx];
-      btp[0] -= wgt * (double)p.x; btp[1] -= wgt * (double)p.y;
-      btm[0] -= wgt * (double)m.x; btm[1] -= wgt * (double)m.y;
-    }
-  }
-  const BlockCoef k = bc[j];
-  auto cm = [](double2 c, const double* z, double& re, double& im) {   // (re, im) += c * z
-    re += c.x * z[0] - c.y * z[1];
-    im += c.x * z[1] + c.y * z[0];
-  };
-  double r1[2] = {0, 0}, r2[2] = {0, 0};
-  cm(k.a11, Mv, r1[0], r1[1]);
-  cm(k.a12, Ml, r1[0], r1[1]);
-  cm(k.b12, Kl, r1[0], r1[1]);
-  cm(k.e12, NTl, r1[0], r1[1]);
-  r1[0] += k.s * btm[0]; r1[1] += k.s * btm[1];
-  cm(k.a21, Mv, r2[0], r2[1]);
-  cm(k.b21, Kv, r2[0], r2[1]);
-  cm(k.e21, Nv, r2[0], r2[1]);
-  cm(k.a22, Ml, r2[0], r2[1]);
-  r2[0] += k.s * btp[0]; r2[1] += k.s * btp[1];
-  yV[o0] = cmk<cpx<R>>(r1[0], r1[1]);
-  yV[o1] = cmk<cpx<R>>(r2[0], r2[1]);
-}
+// Velocity rows 1 and 2: Q2 tile kernel k_q2_block_vel (q2_tiles.hip).
 
 // (B u)_k at Q1 node k for a velocity pair (ux, uy) on padded Q2 grids.
 template <typename R>
@@ -253,9 +161,9 @@ __global__ __launch_bounds__(256) void k_combine3(cpx<R>* out, const cpx<R>* A, 
 
 template <typename R>
 void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                      const BlockCoef* bc, const double* conv, double sp, Mask mk) {
-  const int nq2 = (2 * n + 1) * (2 * n + 1), np2 = (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_block_vel<R>, dim3((nq2 + 255) / 256, 2 * nf), dim3(256), 0, s, yV, xV, xP, n, bc, conv, mk);
+                      const BlockCoef* bc, const double* tcN, const double* tcNT, double sp, Mask mk) {
+  const int np2 = (n + 1) * (n + 1);
+  launch_q2_block_vel<R>(s, yV, xV, xP, n, nf, bc, tcN, tcNT, mk);
   hipLaunchKernelGGL(k_block_pres<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, yP, xV, n, sp, mk);
 }
 
@@ -287,7 +195,7 @@ void launch_combine3(hipStream_t s, cpx<R>* out, const cpx<R>* A, const cpx<R>* 
 
 #define PINTOC_OSEEN_INST(R)                                                                                       \
   template void launch_block_mat<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,         \
-                                    const BlockCoef*, const double*, double, Mask);                                      \
+                                    const BlockCoef*, const double*, const double*, double, Mask);                       \
   template void launch_schur_rhs<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,   \
                                     double, Mask);                                                                       \
   template void launch_oseen_hp<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, const double2*, double, double,  \

@@ -790,8 +790,9 @@ static void block_precond(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, c
 template <typename R>
 static void block_matvec(pintoc_problem* p, hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV,
                          const cpx<R>* xP) {
-  launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr,
-                      p->block_scale, p->mk(2));
+  const bool oseen = p->d.flow == PINTOC_OSEEN;
+  launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, oseen ? p->tconv[0][0] : nullptr,
+                      oseen ? p->tconv[1][0] : nullptr, p->block_scale, p->mk(2));
 }
 
 // complex Givens rotation (c real) with [c, s; -conj(s), c] [a; b] = [r; 0]

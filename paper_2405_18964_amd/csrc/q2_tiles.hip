@@ -455,6 +455,203 @@ __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out,
   }
 }
 
+namespace {
+// Raw stencil sums at a class-(PX, PY) node: pm = m'.m' x, pk = (k'.m' + m'.k') x
+// (so M x = h^2/900 pm, K x = pk/90) and the convection sum pc.
+template <int PX, int PY, bool CV, typename R>
+__device__ __forceinline__ void stencil_raw(const cpx<R>* base, const double* __restrict__ cn, double2& pm, double2& pk,
+                                            double2& pc) {
+  constexpr int nx = wlen(PX), ny = wlen(PY), lx0 = wlo(PX), ly0 = wlo(PY);
+  double smr[ny], smi[ny], skr[ny], ski[ny];
+  double cr = 0, ci = 0;
+#pragma unroll
+  for (int iy = 0; iy < ny; ++iy) {
+    double vr[nx], vi[nx];
+#pragma unroll
+    for (int ix = 0; ix < nx; ++ix) {
+      const cpx<R> v = base[loff<PX, PY>(lx0 + ix, ly0 + iy)];
+      vr[ix] = (double)v.x;
+      vi[ix] = (double)v.y;
+      if (CV) {
+        const double c = cn[(iy * nx + ix) * 64];
+        cr = fma(c, vr[ix], cr);
+        ci = fma(c, vi[ix], ci);
+      }
+    }
+    Comb<PX>::run(vr, smr[iy], skr[iy]);
+    Comb<PX>::run(vi, smi[iy], ski[iy]);
+  }
+  double pmr, pmi, kmr, kmi, mkr, mki, unr, uni;
+  Comb<PY>::run(smr, pmr, kmr);
+  Comb<PY>::run(smi, pmi, kmi);
+  Comb<PY>::run(skr, mkr, unr);
+  Comb<PY>::run(ski, mki, uni);
+  pm = make_double2(pmr, pmi);
+  pk = make_double2(mkr + kmr, mki + kmi);
+  pc = make_double2(cr, ci);
+}
+
+__device__ __forceinline__ double2 cmad(double2 acc, double2 c, double2 z) {     // acc + c z
+  return make_double2(acc.x + c.x * z.x - c.y * z.y, acc.y + c.x * z.y + c.y * z.x);
+}
+
+constexpr int kPP = kT / 2 + 2;       // side of the Q1 patch of a tile (26)
+
+// Velocity rows of one frequency block (see oseen_kernels.hip for the block
+// pattern) at a lane's node of colour col, phase 0 (v) or 1 (lambda):
+//   phase 0: r1 = a11 M v + s B^T mu,  r2 = a21 M v + b21 K v + e21 N v + s B^T p
+//   phase 1: r1 += a12 M l + b12 K l + e12 N^T l,  r2 += a22 M l
+template <int PX, int PY, bool CV, int PH, typename R>
+__device__ __forceinline__ void block_node(const cpx<R>* sx, const cpx<R>* sp, const cpx<R>* sm, int col, int la,
+                                           int lb, int lane, int X0, int Y0, int n, int comp, double h,
+                                           const BlockCoef& k, const double* __restrict__ ctile, double2& r1,
+                                           double2& r2) {
+  const int nq = 2 * n + 1;
+  int lx, ly;
+  node_of(PX, PY, col, la, lb, lx, ly);
+  const int gx = X0 + lx, gy = Y0 + ly;
+  if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return;
+  const cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
+  const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
+  double2 pm, pk, pc;
+  stencil_raw<PX, PY, CV, R>(base, cn, pm, pk, pc);
+  const double sM = h * h / 900.0, sK = 1.0 / 90.0;
+  const double2 Mz = make_double2(sM * pm.x, sM * pm.y), Kz = make_double2(sK * pk.x, sK * pk.y);
+  if (PH == 0) {
+    r1 = cmad(r1, k.a11, Mz);
+    r2 = cmad(cmad(r2, k.a21, Mz), k.b21, Kz);
+    if (CV) r2 = cmad(r2, k.e21, pc);
+    // B^T p (row 2) and B^T mu (row 1) for this velocity component
+    double mxx[3], gxx[3], mxy[3], gxy[3];
+    mixed_cols(gx, n, h, mxx, gxx);
+    mixed_cols(gy, n, h, mxy, gxy);
+    const int kx0 = (gx >> 1) - 1, ky0 = (gy >> 1) - 1;
+    double bpr = 0, bpi = 0, bmr = 0, bmi = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int kyy = ky0 + a;
+      if (kyy < 0 || kyy > n) continue;
+      const double wy = comp == 0 ? mxy[a] : gxy[a];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int kxx = kx0 + c;
+        if (kxx < 0 || kxx > n) continue;
+        const double wgt = wy * (comp == 0 ? gxx[c] : mxx[c]);
+        const int pi = (kyy - (Y0 / 2 - 1)) * kPP + (kxx - (X0 / 2 - 1));
+        const cpx<R> pv = sp[pi], mv = sm[pi];
+        bpr -= wgt * (double)pv.x; bpi -= wgt * (double)pv.y;
+        bmr -= wgt * (double)mv.x; bmi -= wgt * (double)mv.y;
+      }
+    }
+    r1.x += k.s * bmr; r1.y += k.s * bmi;
+    r2.x += k.s * bpr; r2.y += k.s * bpi;
+  } else {
+    r1 = cmad(cmad(r1, k.a12, Mz), k.b12, Kz);
+    if (CV) r1 = cmad(r1, k.e12, pc);
+    r2 = cmad(r2, k.a22, Mz);
+  }
+}
+
+template <bool CV, int PH, typename R>
+__device__ __forceinline__ void block_phase(const cpx<R>* sx, const cpx<R>* sp, const cpx<R>* sm, int w, int rot,
+                                            int la, int lb, int lane, int X0, int Y0, int n, int comp, double h,
+                                            const BlockCoef& k, const double* __restrict__ ctile, double2* r1,
+                                            double2* r2) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    switch (class_of(w, c, rot)) {
+      case 0: block_node<0, 0, CV, PH, R>(sx, sp, sm, c, la, lb, lane, X0, Y0, n, comp, h, k, ctile, r1[c], r2[c]); break;
+      case 1: block_node<1, 0, CV, PH, R>(sx, sp, sm, c, la, lb, lane, X0, Y0, n, comp, h, k, ctile, r1[c], r2[c]); break;
+      case 2: block_node<0, 1, CV, PH, R>(sx, sp, sm, c, la, lb, lane, X0, Y0, n, comp, h, k, ctile, r1[c], r2[c]); break;
+      default: block_node<1, 1, CV, PH, R>(sx, sp, sm, c, la, lb, lane, X0, Y0, n, comp, h, k, ctile, r1[c], r2[c]); break;
+    }
+  }
+}
+
+// staging index (pitch kSP) of a lane's node at colour step c
+__device__ __forceinline__ int stage_at(int w, int c, int rot, int la, int lb) {
+  const int cl = class_of(w, c, rot);
+  int lx, ly;
+  node_of(cl & 1, cl >> 1, c, la, lb, lx, ly);
+  return ly * kSP + lx;
+}
+
+// store a staged (pitch kSP) result tile to dst; zero on boundary nodes
+template <typename R>
+__device__ __forceinline__ void store_staged(cpx<R>* __restrict__ dst, const cpx<R>* st, int nq, int X0, int Y0) {
+  if (threadIdx.x >= 5 * kT) return;
+  const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT;
+  const int gx = X0 + lx;
+  if (gx >= nq) return;
+  const bool xin = gx >= 1 && gx <= nq - 2;
+  cpx<R>* d = dst + (ptrdiff_t)(Y0 + ly0) * nq + gx;
+#pragma unroll
+  for (int k = 0; k < kSR; ++k) {
+    const int ly = ly0 + 5 * k, gy = Y0 + ly;
+    if (ly >= kT || gy >= nq) break;
+    const bool in = xin && gy >= 1 && gy <= nq - 2;
+    d[(ptrdiff_t)5 * k * nq] = in ? st[ly * kSP + lx] : cmk<cpx<R>>(0, 0);
+  }
+}
+}  // namespace
+
+// Velocity rows of the frequency blocks Z_j (Stokes) or G_j (Oseen): grid
+// f = 2 j + comp of the batch, inputs xV [j][b][comp][(2n+1)^2] and xP
+// [j][b][(n+1)^2], outputs yV (rows 1 and 2 in blocks b = 0 and 1).  tcN /
+// tcNT: tile-layout tables of N and N^T (Oseen) or null.
+template <typename R, bool CV>
+__global__ __launch_bounds__(256, 2) void k_q2_block_vel(cpx<R>* __restrict__ yV, const cpx<R>* __restrict__ xV,
+                                                      const cpx<R>* __restrict__ xP, int n,
+                                                      const BlockCoef* __restrict__ bc,
+                                                      const double* __restrict__ tcN, const double* __restrict__ tcNT,
+                                                      int ntx, int nb, Mask mk) {
+  __shared__ cpx<R> sx[4 * kSub];
+  __shared__ cpx<R> sp[kPP * kPP], sm[kPP * kPP];
+  int tile, f;
+  if (!tile_of_block(ntx * ntx, nb, CV, tile, f)) return;
+  if (mk.off(f)) return;
+  const int j = f >> 1, comp = f & 1;
+  const int X0 = (tile % ntx) * kT, Y0 = (tile / ntx) * kT;
+  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
+  const double h = 1.0 / n;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
+  int la, lb;
+  lane_ab(lane, la, lb);
+  const cpx<R>* v = xV + ((size_t)(j * 2 + 0) * 2 + comp) * nq2;
+  const cpx<R>* l = xV + ((size_t)(j * 2 + 1) * 2 + comp) * nq2;
+  const cpx<R>* pp = xP + (size_t)(j * 2 + 0) * np2;
+  const cpx<R>* pmu = xP + (size_t)(j * 2 + 1) * np2;
+  // pressure patches (Q1 nodes X0/2 - 1 .. X0/2 + 24 per direction)
+  for (int e = threadIdx.x; e < kPP * kPP; e += 256) {
+    const int ky = Y0 / 2 - 1 + e / kPP, kx = X0 / 2 - 1 + e % kPP;
+    const bool in = kx >= 0 && kx <= n && ky >= 0 && ky <= n;
+    sp[e] = in ? pp[(size_t)ky * np + kx] : cmk<cpx<R>>(0, 0);
+    sm[e] = in ? pmu[(size_t)ky * np + kx] : cmk<cpx<R>>(0, 0);
+  }
+  load_tile<R>(sx, v, nq, X0, Y0);
+  const BlockCoef k = bc[j];
+  const size_t toff = (size_t)tile * 9 * 64 * 64;
+  double2 r1[9], r2[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) { r1[c] = make_double2(0, 0); r2[c] = r1[c]; }
+  __syncthreads();
+  block_phase<CV, 0, R>(sx, sp, sm, w, rot, la, lb, lane, X0, Y0, n, comp, h, k, CV ? tcN + toff : nullptr, r1, r2);
+  __syncthreads();
+  load_tile<R>(sx, l, nq, X0, Y0);
+  __syncthreads();
+  block_phase<CV, 1, R>(sx, sp, sm, w, rot, la, lb, lane, X0, Y0, n, comp, h, k, CV ? tcNT + toff : nullptr, r1, r2);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 9; ++c) sx[stage_at(w, c, rot, la, lb)] = cmk<cpx<R>>(r1[c].x, r1[c].y);
+  __syncthreads();
+  store_staged<R>(yV + ((size_t)(j * 2 + 0) * 2 + comp) * nq2, sx, nq, X0, Y0);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 9; ++c) sx[stage_at(w, c, rot, la, lb)] = cmk<cpx<R>>(r2[c].x, r2[c].y);
+  __syncthreads();
+  store_staged<R>(yV + ((size_t)(j * 2 + 1) * 2 + comp) * nq2, sx, nq, X0, Y0);
+}
+
 // ------------------------------------------------------------ launchers
 static inline unsigned tile_blocks(int ntx, int nb) {
   const unsigned total = (unsigned)(ntx * ntx) * (unsigned)nb;
@@ -498,6 +695,15 @@ void launch_q2_apply(hipStream_t s, cpx<R>* out, const cpx<R>* x, const cpx<R>* 
   else hipLaunchKernelGGL((k_q2_tile_apply<R, false>), g, blk, 0, s, out, x, b, n, h, coef, fpc, tconv, ntx, nb, mk);
 }
 
+template <typename R>
+void launch_q2_block_vel(hipStream_t s, cpx<R>* yV, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
+                         const BlockCoef* bc, const double* tcN, const double* tcNT, Mask mk) {
+  const int ntx = (2 * n + 1 + kT - 1) / kT;
+  const dim3 g(tile_blocks(ntx, 2 * nf)), blk(256);
+  if (tcN) hipLaunchKernelGGL((k_q2_block_vel<R, true>), g, blk, 0, s, yV, xV, xP, n, bc, tcN, tcNT, ntx, 2 * nf, mk);
+  else hipLaunchKernelGGL((k_q2_block_vel<R, false>), g, blk, 0, s, yV, xV, xP, n, bc, tcN, tcNT, ntx, 2 * nf, mk);
+}
+
 // Reorder one half (0: N, 1: N^T) of a per-node convection table (50 values
 // per padded Q2 node: 25 offsets of N, then 25 of N^T) into the layout of the
 // tile kernels.
@@ -535,7 +741,9 @@ size_t q2_tile_conv_entries(int n) { return (size_t)q2_tile_count(n) * 9 * 64 * 
   template void launch_q2_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, double, \
                                    const OpCoef*, int, int, const double*, bool, Mask);                             \
   template void launch_q2_apply<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double, const OpCoef*,  \
-                                   int, int, const double*, Mask);
+                                   int, int, const double*, Mask);                                                    \
+  template void launch_q2_block_vel<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,                 \
+                                       const BlockCoef*, const double*, const double*, Mask);
 
 PINTOC_Q2T_INST(double)
 PINTOC_Q2T_INST(float)
