@@ -8,8 +8,11 @@
 // separated by Hermitian symmetry:
 //   R0_j = (Z_j + conj(Z_{nt-j})) / 2,   R1_j = (Z_j - conj(Z_{nt-j})) / (2i)
 // and only j = 0..nt/2 are kept (real data, so R_{nt-j} = conj(R_j)).
-// A work-group loads a tile [t = 0..nt-1] x [TN consecutive n] (coalesced along
-// n), transforms in LDS and writes [j][TN consecutive n] (coalesced along n).
+// A work-group takes a tile [t = 0..nt-1] x [16 consecutive n] (coalesced along
+// n) and writes [j][16 consecutive n] (coalesced along n).  For nt <= 256 the
+// transform is the four-step split nt = N1 N2 with both factor transforms in
+// registers and two LDS exchanges; longer sequences use radix-2 stages in LDS
+// over 4096/nt level indices per work-group.
 //
 // Frequency-domain layout:  V[j][b][comp][(2N+1)^2], P[j][b][(N+1)^2] (complex).
 #include "kernels.h"
@@ -155,6 +158,226 @@ __global__ __launch_bounds__(256) void k_time_fft_inv(const cpx<R>* __restrict__
   }
 }
 
+// ---- four-step transform, nt = N1 N2 <= 256 ------------------------------
+// With t = N2 t1 + t2 and k = k1 + N1 k2 the length-nt DFT factors as
+//   X[k1 + N1 k2] = sum_t2 W_N2^(t2 k2) W_nt^(t2 k1) sum_t1 x[N2 t1 + t2] W_N1^(t1 k1),
+// W_m = exp(-+2 pi i / m).  A work-group of 16 N1 threads holds 16 level
+// indices; thread (n, c), n = threadIdx.x mod 16, c = threadIdx.x / 16, runs
+// the length-N1 transform of column t2 = c (if c < N2) and then the length-N2
+// transform of row k1 = c.  LDS keeps element p of level index n at
+// p * 16 + n, so lane j of every 16-lane group sits on 16-byte residue j in
+// all accesses (conflict-free 128-bit LDS reads and writes).
+constexpr int kFN = 16;
+
+// v * exp(-+2 pi i q / 16), q in [0, 8): cos and sin of multiples of pi / 8.
+__device__ __forceinline__ double2 rot16(double2 v, int q, bool inv) {
+  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, h = 0.70710678118654752440;
+  double c, sn;
+  switch (q) {
+    case 0: return v;
+    case 4: return inv ? make_double2(-v.y, v.x) : make_double2(v.y, -v.x);
+    case 1: c = c1; sn = s1; break;
+    case 2: c = h; sn = h; break;
+    case 3: c = s1; sn = c1; break;
+    case 5: c = -s1; sn = c1; break;
+    case 6: c = -h; sn = h; break;
+    default: c = -c1; sn = s1; break;
+  }
+  if (!inv) sn = -sn;
+  return make_double2(v.x * c - v.y * sn, v.x * sn + v.y * c);
+}
+
+template <int M> __host__ __device__ constexpr int brev_c(int i) {
+  int r = 0;
+  for (int b = 1; b < M; b <<= 1) { r = (r << 1) | (i & 1); i >>= 1; }
+  return r;
+}
+
+// In-register length-M DFT (M in {1, 2, 4, 8, 16}), natural order in and out:
+// bit-reversal permutation, then radix-2 decimation-in-time stages.
+template <int M, bool INV>
+__device__ __forceinline__ void reg_fft(double2 (&x)[M]) {
+  double2 y[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) y[brev_c<M>(i)] = x[i];
+#pragma unroll
+  for (int m = 1; m < M; m <<= 1) {
+#pragma unroll
+    for (int i0 = 0; i0 < M; i0 += 2 * m) {
+#pragma unroll
+      for (int q = 0; q < m; ++q) {
+        const double2 a = y[i0 + q], b = rot16(y[i0 + q + m], q * (16 / (2 * m)), INV);
+        y[i0 + q] = a + b;
+        y[i0 + q + m] = a - b;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) x[i] = y[i];
+}
+
+// exp(-+2 pi i e / nt) for 0 <= e < nt from the half table tw[k] = exp(-2 pi i k / nt).
+__device__ __forceinline__ double2 tw_at(const double2* __restrict__ tw, int e, int nt, bool inv) {
+  const int h = nt >> 1;
+  double2 w = tw[e & (h - 1)];
+  if (e & h) { w.x = -w.x; w.y = -w.y; }
+  if (inv) w.y = -w.y;
+  return w;
+}
+
+template <typename R, int N1, int N2>
+__global__ __launch_bounds__(kFN * N1) void k_fft4_fwd(const double* __restrict__ r, cpx<R>* __restrict__ V,
+                                                       cpx<R>* __restrict__ P, int L, int nq2, int np2,
+                                                       const double2* __restrict__ tw, const double2* __restrict__ tj,
+                                                       double tau, int mode) {
+  constexpr int NT = N1 * N2, NF = NT / 2 + 1;
+  __shared__ double2 buf[NT * kFN];
+  const int n = threadIdx.x & (kFN - 1), c = threadIdx.x / kFN;
+  const int n0 = blockIdx.x * kFN, g = n0 + n;
+  const bool live = g < L;
+  if (c < N2) {                                   // pass 1: column t2 = c
+    double2 x[N1];
+#pragma unroll
+    for (int t1 = 0; t1 < N1; ++t1) {
+      const size_t t = (size_t)(N2 * t1 + c);
+      x[t1] = live ? make_double2(r[t * L + g], r[(NT + t) * L + g]) : make_double2(0.0, 0.0);
+    }
+    reg_fft<N1, false>(x);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1)
+      buf[(N2 * k1 + c) * kFN + n] = k1 == 0 ? x[0] : cmul(x[k1], tw_at(tw, c * k1, NT, false));
+  }
+  __syncthreads();
+  {                                               // pass 2: row k1 = c; X[c + N1 k2] kept at N2 c + k2
+    double2 x[N2];
+#pragma unroll
+    for (int t2 = 0; t2 < N2; ++t2) x[t2] = buf[(N2 * c + t2) * kFN + n];
+    reg_fft<N2, false>(x);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) buf[(N2 * c + k2) * kFN + n] = x[k2];
+  }
+  __syncthreads();
+  if (!live) return;
+  const double st = sqrt(tau);
+  for (int j = c; j < NF; j += N1) {
+    const int jm = (NT - j) & (NT - 1);
+    const double2 Zj = buf[(N2 * (j % N1) + j / N1) * kFN + n];
+    const double2 Zm = buf[(N2 * (jm % N1) + jm / N1) * kFN + n];
+    double2 X0 = make_double2(0.5 * (Zj.x + Zm.x), 0.5 * (Zj.y - Zm.y));
+    double2 X1 = make_double2(0.5 * (Zj.y + Zm.y), -0.5 * (Zj.x - Zm.x));
+    const bool vel = g < 2 * nq2;
+    if (mode == 1) {
+      const double dc = tj[j].x, c2 = tj[j].y;
+      const double2 idr = make_double2(dc * X0.y / tau, -dc * X0.x / tau);   // -i dc X0 / tau
+      if (vel) {
+        const double2 s2 = (c2 / st) * (X1 + idr);
+        X0 = (1.0 / st) * X0;
+        X1 = s2;
+      } else {
+        const double2 s4 = (1.0 / st) * (X1 + idr);
+        X0 = (1.0 / (st * c2)) * X0;
+        X1 = s4;
+      }
+    }
+    if (vel) {
+      const int comp = g >= nq2, node = g - comp * nq2;
+      V[((size_t)(j * 2 + 0) * 2 + comp) * nq2 + node] = cmk<cpx<R>>(X0.x, X0.y);
+      V[((size_t)(j * 2 + 1) * 2 + comp) * nq2 + node] = cmk<cpx<R>>(X1.x, X1.y);
+    } else {
+      const int node = g - 2 * nq2;
+      P[(size_t)(j * 2 + 0) * np2 + node] = cmk<cpx<R>>(X0.x, X0.y);
+      P[(size_t)(j * 2 + 1) * np2 + node] = cmk<cpx<R>>(X1.x, X1.y);
+    }
+  }
+}
+
+template <typename R, int N1, int N2>
+__global__ __launch_bounds__(kFN * N1) void k_fft4_inv(const cpx<R>* __restrict__ V, const cpx<R>* __restrict__ P,
+                                                       double* __restrict__ z, int L, int nq2, int np2,
+                                                       const double2* __restrict__ tw, const double2* __restrict__ tj,
+                                                       double tau, int mode) {
+  constexpr int NT = N1 * N2, NF = NT / 2 + 1;
+  __shared__ double2 buf[NT * kFN];
+  const int n = threadIdx.x & (kFN - 1), c = threadIdx.x / kFN;
+  const int g = blockIdx.x * kFN + n;
+  const bool live = g < L;
+  const double st = sqrt(tau);
+  // Spectrum of z = y0 + i y1 at j and nt - j from the kept j = 0..nt/2.
+#pragma unroll
+  for (int i = 0; i < (NF + N1 - 1) / N1; ++i) {
+    const int jj = c + i * N1;
+    if (jj >= NF) break;
+    double2 Zv = make_double2(0.0, 0.0), Zc = Zv;
+    if (live) {
+      const bool vel = g < 2 * nq2;
+      cpx<R> a, b;
+      if (vel) {
+        const int comp = g >= nq2, node = g - comp * nq2;
+        a = V[((size_t)(jj * 2 + 0) * 2 + comp) * nq2 + node];
+        b = V[((size_t)(jj * 2 + 1) * 2 + comp) * nq2 + node];
+      } else {
+        const int node = g - 2 * nq2;
+        a = P[(size_t)(jj * 2 + 0) * np2 + node];
+        b = P[(size_t)(jj * 2 + 1) * np2 + node];
+      }
+      double2 Y0 = make_double2((double)a.x, (double)a.y), Y1 = make_double2((double)b.x, (double)b.y);
+      if (mode == 1) {
+        const double dc = tj[jj].x, c2 = tj[jj].y;
+        if (vel) {
+          const double2 y2 = (c2 / st) * Y1;
+          const double2 y1 = (1.0 / st) * (Y0 + make_double2(-dc * y2.y / st, dc * y2.x / st));
+          Y0 = y1; Y1 = y2;
+        } else {
+          const double2 y4 = (1.0 / st) * Y1;
+          const double2 y3 = (1.0 / (st * c2)) * (Y0 + make_double2(-dc * c2 * y4.y / st, dc * c2 * y4.x / st));
+          Y0 = y3; Y1 = y4;
+        }
+      }
+      Zv = make_double2(Y0.x - Y1.y, Y0.y + Y1.x);          // Y0 + i Y1
+      Zc = make_double2(Y0.x + Y1.y, Y1.x - Y0.y);          // conj(Y0) + i conj(Y1)
+    }
+    buf[jj * kFN + n] = Zv;
+    if (jj > 0 && jj < NT / 2) buf[(NT - jj) * kFN + n] = Zc;
+  }
+  __syncthreads();
+  if (c < N2) {                                   // pass 1: column t2 = c, in place
+    double2 x[N1];
+#pragma unroll
+    for (int t1 = 0; t1 < N1; ++t1) x[t1] = buf[(N2 * t1 + c) * kFN + n];
+    reg_fft<N1, true>(x);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1)
+      buf[(N2 * k1 + c) * kFN + n] = k1 == 0 ? x[0] : cmul(x[k1], tw_at(tw, c * k1, NT, true));
+  }
+  __syncthreads();
+  if (!live) return;
+  double2 x[N2];                                  // pass 2: row k1 = c -> t = c + N1 k2
+#pragma unroll
+  for (int t2 = 0; t2 < N2; ++t2) x[t2] = buf[(N2 * c + t2) * kFN + n];
+  reg_fft<N2, true>(x);
+  const double sc = 1.0 / NT;
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) {
+    const size_t t = (size_t)(c + N1 * k2);
+    z[t * L + g] = sc * x[k2].x;
+    z[(NT + t) * L + g] = sc * x[k2].y;
+  }
+}
+
+template <typename R, int N1, int N2>
+static void fft4_fwd(hipStream_t s, const double* r, cpx<R>* V, cpx<R>* P, int L, int nq2, int np2,
+                     const double2* tw, const double2* tj, double tau, int mode) {
+  hipLaunchKernelGGL((k_fft4_fwd<R, N1, N2>), dim3((unsigned)((L + kFN - 1) / kFN)), dim3(kFN * N1), 0, s, r, V, P, L,
+                     nq2, np2, tw, tj, tau, mode);
+}
+
+template <typename R, int N1, int N2>
+static void fft4_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double* z, int L, int nq2, int np2,
+                     const double2* tw, const double2* tj, double tau, int mode) {
+  hipLaunchKernelGGL((k_fft4_inv<R, N1, N2>), dim3((unsigned)((L + kFN - 1) / kFN)), dim3(kFN * N1), 0, s, V, P, z, L,
+                     nq2, np2, tw, tj, tau, mode);
+}
+
 static int fft_tile(int nt) {
   int tn = 4096 / nt;            // 64 KiB of LDS per work-group
   return tn < 1 ? 1 : (tn > 32 ? 32 : tn);
@@ -163,6 +386,17 @@ static int fft_tile(int nt) {
 template <typename R>
 void launch_time_fft_fwd(hipStream_t s, const double* r, cpx<R>* V, cpx<R>* P, int nt, int L, int nq2, int np2,
                          const double2* tw, const double2* tj, double tau, int mode) {
+  switch (nt) {
+    case 2: return fft4_fwd<R, 2, 1>(s, r, V, P, L, nq2, np2, tw, tj, tau, mode);
+    case 4: return fft4_fwd<R, 2, 2>(s, r, V, P, L, nq2, np2, tw, tj, tau, mode);
+    case 8: return fft4_fwd<R, 4, 2>(s, r, V, P, L, nq2, np2, tw, tj, tau, mode);
+    case 16: return fft4_fwd<R, 4, 4>(s, r, V, P, L, nq2, np2, tw, tj, tau, mode);
+    case 32: return fft4_fwd<R, 8, 4>(s, r, V, P, L, nq2, np2, tw, tj, tau, mode);
+    case 64: return fft4_fwd<R, 8, 8>(s, r, V, P, L, nq2, np2, tw, tj, tau, mode);
+    case 128: return fft4_fwd<R, 16, 8>(s, r, V, P, L, nq2, np2, tw, tj, tau, mode);
+    case 256: return fft4_fwd<R, 16, 16>(s, r, V, P, L, nq2, np2, tw, tj, tau, mode);
+    default: break;
+  }
   int logn = 0;
   while ((1 << logn) < nt) ++logn;
   const int TN = fft_tile(nt), nf = nt / 2 + 1;
@@ -174,6 +408,17 @@ void launch_time_fft_fwd(hipStream_t s, const double* r, cpx<R>* V, cpx<R>* P, i
 template <typename R>
 void launch_time_fft_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double* z, int nt, int L, int nq2,
                          int np2, const double2* tw, const double2* tj, double tau, int mode) {
+  switch (nt) {
+    case 2: return fft4_inv<R, 2, 1>(s, V, P, z, L, nq2, np2, tw, tj, tau, mode);
+    case 4: return fft4_inv<R, 2, 2>(s, V, P, z, L, nq2, np2, tw, tj, tau, mode);
+    case 8: return fft4_inv<R, 4, 2>(s, V, P, z, L, nq2, np2, tw, tj, tau, mode);
+    case 16: return fft4_inv<R, 4, 4>(s, V, P, z, L, nq2, np2, tw, tj, tau, mode);
+    case 32: return fft4_inv<R, 8, 4>(s, V, P, z, L, nq2, np2, tw, tj, tau, mode);
+    case 64: return fft4_inv<R, 8, 8>(s, V, P, z, L, nq2, np2, tw, tj, tau, mode);
+    case 128: return fft4_inv<R, 16, 8>(s, V, P, z, L, nq2, np2, tw, tj, tau, mode);
+    case 256: return fft4_inv<R, 16, 16>(s, V, P, z, L, nq2, np2, tw, tj, tau, mode);
+    default: break;
+  }
   int logn = 0;
   while ((1 << logn) < nt) ++logn;
   const int TN = fft_tile(nt), nf = nt / 2 + 1;

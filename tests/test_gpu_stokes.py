@@ -86,6 +86,14 @@ def test_precond_linear_parity(lib, N, nt, beta):
     assert np.all(z[~W.canonical_mask(N, nt)] == 0)
 
 
+@pytest.mark.parametrize("nt", [2, 64, 128, 512])
+def test_precond_linear_parity_time_lengths(lib, nt):
+    """Every time-transform route on a small grid: the in-register four-step
+    split for nt <= 256 (here 2 = 2x1, 64 = 8x8, 128 = 16x8) and the LDS
+    radix-2 stages for longer sequences (512)."""
+    test_precond_linear_parity(lib, 2, nt, 1e-2)
+
+
 def test_precond_single_frequency_full_size(lib):
     """Full-size check at the N=128, nt=256 Stokes workload: a residual with
     one Fourier mode j in time excites only blocks j and nt-j, so the oracle
