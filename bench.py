@@ -65,13 +65,15 @@ def precond_model_bytes(N: int, nt: int, n_vcycles: int, n_cheb: int, csize: int
 
     Field sizes per kept frequency (nf = nt/2 + 1): 4 complex Q2 grids (velocity
     of both blocks) and 2 complex Q1 grids (pressure).  Per multigrid level
-    (sizes shrink by 4): the pre-smoothing sweep reads x, b and writes x (3
-    passes), the residual reads x, b and writes r (3), the restriction reads r
-    and writes the coarse rhs (1 + 1/4), the post-smoothing sweep reads x, the
-    coarse correction and b and writes x (3 + 1/4): 10.5 fine-field passes per
-    level, times 4/3 over the hierarchy = 14 per V-cycle.  A Chebyshev step
-    reads x_k, x_{k-1}, b, writes x_{k+1}.  The FFT pair reads and writes the
-    canonical vector and the frequency vector once each."""
+    (sizes shrink by 4, so a cycle costs 4/3 of its finest level): the
+    pre-smoothing sweep reads x, b and writes x (3 passes; 2 in the first cycle,
+    which starts from x = 0), the post-smoothing sweep reads x, the coarse
+    correction and b and writes x (3 + 1/4).  Between them the Q2 levels run
+    one fused residual/restriction pass (reads x, b, writes the coarse rhs:
+    2 + 1/4), the Q1 levels a residual (3) and a restriction (1 + 1/4): 8.5
+    (Q2) and 10.5 (Q1) passes per level.  A Chebyshev step reads x_k, x_{k-1},
+    b, writes x_{k+1}.  The FFT pair reads and writes the canonical vector and
+    the frequency vector once each."""
     nf = nt // 2 + 1
     nq2, np2 = (2 * N + 1) ** 2, (N + 1) ** 2
     FV = 4 * nf * nq2 * csize          # velocity frequency fields
@@ -79,9 +81,8 @@ def precond_model_bytes(N: int, nt: int, n_vcycles: int, n_cheb: int, csize: int
     L = 2 * nq2 + np2
     canon = 2 * nt * L * 8
     freq = FV + FP
-    vcycle = 10.5 * 4.0 / 3.0
-    mg_w = n_vcycles * vcycle * FV
-    mg_k = n_vcycles * vcycle * FP
+    mg_w = (8.5 * n_vcycles - 1.0) * 4.0 / 3.0 * FV
+    mg_k = (10.5 * n_vcycles - 1.0) * 4.0 / 3.0 * FP
     cheb = (1 + 4 * (n_cheb - 1)) * FP
     schur = 2 * FP + 3 * FP            # unpin copy, combine
     fft = 2 * (canon + freq)

@@ -51,6 +51,12 @@ void launch_q2_apply(hipStream_t s, cpx<R>* out, const cpx<R>* x, const cpx<R>* 
 template <typename R>
 void launch_q2_block_vel(hipStream_t s, cpx<R>* yV, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
                          const BlockCoef* bc, const double* tcN, const double* tcNT, Mask mk);
+// bc = P^T (b - A x) on the coarse grid of side n + 1 without storing the fine
+// residual; side: q2_restrict_side_entries(n) * nb complex entries of scratch
+template <typename R>
+void launch_q2_residual_restrict(hipStream_t s, cpx<R>* bc, cpx<R>* side, const cpx<R>* x, const cpx<R>* b, int n,
+                                 double h, const OpCoef* coef, int fpc, int nb, const double* tconv, Mask mk);
+size_t q2_restrict_side_entries(int n);
 size_t q2_tile_conv_entries(int n);
 void q2_tile_conv_table(int n, const double* t50, int half, double* out);
 

@@ -255,7 +255,8 @@ static void plan_mg_buffers(MGPlan& m, Carver& cv, size_t csize) {
       m.x[l] = cv.take<char>(bytes);
     }
     if (l + 1 < m.nlev) {
-      m.r[l] = cv.take<char>(bytes);
+      // Q2 levels restrict without storing the residual: r holds the shared partial sums only
+      m.r[l] = cv.take<char>(m.q2 ? q2_restrict_side_entries(m.n(l)) * m.nb * csize : bytes);
       m.t[l] = cv.take<char>(bytes);
     }
   }
@@ -653,7 +654,8 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
 
 // ------------------------------------------------------------ multigrid
 // One V(1,1)-cycle on level l: pre-smoothing x -> t (from x = 0 when x_zero,
-// without reading x), residual, restriction, coarse cycle from zero, and the
+// without reading x), residual and restriction (one fused pass on Q2 levels),
+// coarse cycle from zero, and the
 // post-smoothing sweep of t + P e_c -> x (the prolongation is applied while
 // the sweep loads its tile).
 template <typename R>
@@ -679,8 +681,12 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
     pr->count++;
   }
   cpx<R>* r = (cpx<R>*)m.r[l];
-  launch_residual<R>(s, m.q2, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
-  launch_restrict<R>(s, m.q2, bc, r, n / 2, m.nb, m.mk());
+  if (m.q2) {
+    launch_q2_residual_restrict<R>(s, bc, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
+  } else {
+    launch_residual<R>(s, false, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
+    launch_restrict<R>(s, false, bc, r, n / 2, m.nb, m.mk());
+  }
   vcycle<R>(s, m, l + 1, xc, bc, true);
   launch_tile_sweep<R>(s, m.q2, x, t, b, xc, n, h, m.coef, m.fpc, m.nb, m.conv[l], false, m.mk());
 }

@@ -396,6 +396,33 @@ __device__ __forceinline__ double2 apply_node(const cpx<R>* sx, int col, int la,
   double cd = 0;
   return stencil<PX, PY, CV, R>(base, cn, t, cd);
 }
+
+// Load x into the tile and leave A x of every tile node staged row-major
+// (pitch kSP) in the LDS tile (zero on boundary and outside nodes).
+template <typename R, bool CV>
+__device__ __forceinline__ void apply_stage(cpx<R>* sx, const cpx<R>* __restrict__ x, int nq, int X0, int Y0,
+                                            const TCoef& t, const double* __restrict__ ctile, int w, int lane,
+                                            int rot) {
+  int la, lb;
+  lane_ab(lane, la, lb);
+  load_tile<R>(sx, x, nq, X0, Y0);
+  __syncthreads();
+  double2 acc[9];
+  int si[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    switch (class_of(w, k, rot)) {
+      case 0: acc[k] = apply_node<0, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
+      case 1: acc[k] = apply_node<1, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
+      case 2: acc[k] = apply_node<0, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
+      default: acc[k] = apply_node<1, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 9; ++k) sx[si[k]] = cmk<cpx<R>>(acc[k].x, acc[k].y);
+  __syncthreads();
+}
 }  // namespace
 
 // out = b - A x (b != nullptr) or out = A x, on every node of the grids
@@ -413,28 +440,9 @@ __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out,
   const int nq = 2 * n + 1;
   const size_t off = (size_t)f * nq * nq;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
-  int la, lb;
-  lane_ab(lane, la, lb);
-  load_tile<R>(sx, x + off, nq, X0, Y0);
   const TCoef t = tcoef(coef[f / fpc], h);
   const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
-  __syncthreads();
-  double2 acc[9];
-  int si[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    switch (class_of(w, k, rot)) {
-      case 0: acc[k] = apply_node<0, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
-      case 1: acc[k] = apply_node<1, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
-      case 2: acc[k] = apply_node<0, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
-      default: acc[k] = apply_node<1, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
-    }
-  }
-  __syncthreads();
-  // stage A x row-major (pitch kSP) in the LDS tile for a coalesced store
-#pragma unroll
-  for (int k = 0; k < 9; ++k) sx[si[k]] = cmk<cpx<R>>(acc[k].x, acc[k].y);
-  __syncthreads();
+  apply_stage<R, CV>(sx, x + off, nq, X0, Y0, t, ctile, w, lane, rot);     // A x staged for a coalesced store
   if (threadIdx.x < 5 * kT) {
     const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT;
     const int gx = X0 + lx;
@@ -453,6 +461,161 @@ __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out,
       }
     }
   }
+}
+
+// Residual and restriction in one pass: bc = P^T (b - A x) on the coarse grid
+// (side n + 1, zero on its boundary).  The fine tile of tile (tx, ty) reaches
+// the coarse nodes 24 tx .. 24 tx + 24 per direction (1-D weights of an even
+// coarse node at fine offsets -3, -1, 0, 1, 3: -1/8, 3/8, 1, 3/8, -1/8; of an
+// odd one at -1, 0, 1: 3/4, 1, 3/4).  The work-group writes its own coarse
+// nodes (local index < 24 in both directions) to bc and the partial sums of the
+// shared column (local x index 24, 25 values) and row (local y index 24, 24
+// values) to side[(f * ntiles + tile) * 49 + ...]; k_q2_restrict_fix adds those
+// to the neighbours' nodes.  The fine residual never goes to memory.
+namespace {
+constexpr int kCT = kT / 2;            // coarse nodes owned per tile and direction
+constexpr int kSide = 2 * kCT + 1;     // shared partial sums per tile: column (25) then row (24)
+
+// 1-D restriction weight of fine offset index i (offsets -3, -1, 0, 1, 3) for coarse parity P
+template <int P> __device__ __forceinline__ constexpr double rw(int i) {
+  return P ? (i == 1 || i == 3 ? 0.75 : (i == 2 ? 1.0 : 0.0))
+           : (i == 0 || i == 4 ? -0.125 : (i == 1 || i == 3 ? 0.375 : 1.0));
+}
+__device__ __forceinline__ constexpr int roff(int i) { return i == 0 ? -3 : (i == 4 ? 3 : i - 2); }
+
+// Coarse nodes of parity class (PI, PJ) of the tile: local (2 a + PI, 2 b + PJ).
+template <int PI, int PJ, typename R>
+__device__ __forceinline__ void restrict_class(cpx<R>* __restrict__ bcf, cpx<R>* __restrict__ sd, const cpx<R>* sr,
+                                               int I0, int J0, int nqc) {
+  constexpr int na = PI ? kCT / 2 : kCT / 2 + 1, nbj = PJ ? kCT / 2 : kCT / 2 + 1;
+  for (int e = threadIdx.x; e < na * nbj; e += blockDim.x) {
+    const int ci = 2 * (e % na) + PI, cj = 2 * (e / na) + PJ;
+    const int I = I0 + ci, J = J0 + cj;
+    if (I >= nqc || J >= nqc) continue;
+    double vr = 0, vi = 0;
+#pragma unroll
+    for (int iy = 0; iy < 5; ++iy) {
+      if (rw<PJ>(iy) == 0.0) continue;
+      const int fy = 2 * cj + roff(iy);
+      if (fy < 0 || fy >= kT) continue;
+      double rr = 0, ri = 0;
+#pragma unroll
+      for (int ix = 0; ix < 5; ++ix) {
+        if (rw<PI>(ix) == 0.0) continue;
+        const int fx = 2 * ci + roff(ix);
+        if (fx < 0 || fx >= kT) continue;
+        const cpx<R> v = sr[fy * kSP + fx];
+        rr = fma(rw<PI>(ix), (double)v.x, rr);
+        ri = fma(rw<PI>(ix), (double)v.y, ri);
+      }
+      vr = fma(rw<PJ>(iy), rr, vr);
+      vi = fma(rw<PJ>(iy), ri, vi);
+    }
+    const bool bnd = I == 0 || J == 0 || I == nqc - 1 || J == nqc - 1;
+    const cpx<R> v = bnd ? cmk<cpx<R>>(0, 0) : cmk<cpx<R>>(vr, vi);
+    if (ci < kCT && cj < kCT) bcf[(size_t)J * nqc + I] = v;
+    else if (ci == kCT) sd[cj] = v;
+    else sd[kCT + 1 + ci] = v;
+  }
+}
+}  // namespace
+
+template <typename R, bool CV>
+__global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict__ bc, cpx<R>* __restrict__ side,
+                                                              const cpx<R>* __restrict__ x,
+                                                              const cpx<R>* __restrict__ b, int n, double h,
+                                                              const OpCoef* __restrict__ coef, int fpc,
+                                                              const double* __restrict__ conv, int ntx, int nb,
+                                                              Mask mk) {
+  __shared__ cpx<R> sx[4 * kSub];
+  int tile, f;
+  if (!tile_of_block(ntx * ntx, nb, CV, tile, f)) return;
+  if (mk.off(f)) return;
+  const int X0 = (tile % ntx) * kT, Y0 = (tile / ntx) * kT;
+  const int nq = 2 * n + 1, nqc = n + 1;
+  const size_t off = (size_t)f * nq * nq;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
+  const TCoef t = tcoef(coef[f / fpc], h);
+  const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
+  // b of this thread's column rows (thread t < 5 kT: column t % kT, rows t / kT + 5 k);
+  // in FP64 it is loaded before the stencil phase so its latency overlaps it (in
+  // FP32 the registers would cost a wave of occupancy)
+  constexpr bool kPre = sizeof(R) == 8;
+  const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT;
+  const int gx = X0 + lx;
+  const bool xin = threadIdx.x < 5 * kT && gx >= 1 && gx <= nq - 2;
+  const cpx<R>* bp = b + off + (ptrdiff_t)(Y0 + ly0) * nq + gx;
+  auto bload = [&](int k) -> cpx<R> {
+    const int gy = Y0 + ly0 + 5 * k;
+    return (xin && ly0 + 5 * k < kT && gy >= 1 && gy <= nq - 2) ? bp[(ptrdiff_t)5 * k * nq] : cmk<cpx<R>>(0, 0);
+  };
+  cpx<R> bv[kSR];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int k = 0; k < kSR; ++k) bv[k] = bload(k);
+  }
+  apply_stage<R, CV>(sx, x + off, nq, X0, Y0, t, ctile, w, lane, rot);
+  // r = b - A x in place over the staged A x (A x and b are zero on boundary and outside nodes)
+  if (threadIdx.x < 5 * kT) {
+#pragma unroll
+    for (int k = 0; k < kSR; ++k) {
+      const int ly = ly0 + 5 * k;
+      if (ly >= kT) break;
+      if constexpr (!kPre) bv[k] = bload(k);
+      const cpx<R> a = sx[ly * kSP + lx];
+      sx[ly * kSP + lx] = cmk<cpx<R>>((double)bv[k].x - (double)a.x, (double)bv[k].y - (double)a.y);
+    }
+  }
+  __syncthreads();
+  cpx<R>* bcf = bc + (size_t)f * nqc * nqc;
+  cpx<R>* sd = side + ((size_t)f * ntx * ntx + tile) * kSide;
+  const int I0 = X0 / 2, J0 = Y0 / 2;
+  restrict_class<0, 0, R>(bcf, sd, sx, I0, J0, nqc);
+  restrict_class<1, 0, R>(bcf, sd, sx, I0, J0, nqc);
+  restrict_class<0, 1, R>(bcf, sd, sx, I0, J0, nqc);
+  restrict_class<1, 1, R>(bcf, sd, sx, I0, J0, nqc);
+}
+
+// Shared coarse nodes of k_q2_residual_restrict: I or J a positive multiple of
+// 24 (interior nodes only).  Such a node adds the column partial of the tile
+// to its left, the row partial of the tile below, and, when both I and J are
+// multiples of 24, the corner partial of the tile below-left.  One thread per
+// node, fixed summation order.
+template <typename R>
+__global__ __launch_bounds__(256) void k_q2_restrict_fix(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ side,
+                                                         int n, int ntx, Mask mk) {
+  const int f = blockIdx.y;
+  if (mk.off(f)) return;
+  const int nqc = n + 1, len = nqc - 2, A = len / kCT;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * A * len) return;
+  const int line = e / len, pos = 1 + e % len;
+  int I, J;
+  if (line < A) {
+    I = kCT * (line + 1);
+    J = pos;
+  } else {
+    J = kCT * (line - A + 1);
+    I = pos;
+    if (I % kCT == 0) return;          // on a column line as well: done there
+  }
+  const int tx = I / kCT, ty = J / kCT, ci = I % kCT, cj = J % kCT;
+  const cpx<R>* sd = side + (size_t)f * ntx * ntx * kSide;
+  double vr = 0, vi = 0;
+  if (ci == 0) {
+    const cpx<R> v = sd[(size_t)(ty * ntx + tx - 1) * kSide + cj];
+    vr += (double)v.x; vi += (double)v.y;
+  }
+  if (cj == 0) {
+    const cpx<R> v = sd[(size_t)((ty - 1) * ntx + tx) * kSide + kCT + 1 + ci];
+    vr += (double)v.x; vi += (double)v.y;
+  }
+  if (ci == 0 && cj == 0) {
+    const cpx<R> v = sd[(size_t)((ty - 1) * ntx + tx - 1) * kSide + kCT];
+    vr += (double)v.x; vi += (double)v.y;
+  }
+  cpx<R>& d = bc[(size_t)f * nqc * nqc + (size_t)J * nqc + I];
+  d = cmk<cpx<R>>((double)d.x + vr, (double)d.y + vi);
 }
 
 namespace {
@@ -696,6 +859,27 @@ void launch_q2_apply(hipStream_t s, cpx<R>* out, const cpx<R>* x, const cpx<R>* 
 }
 
 template <typename R>
+void launch_q2_residual_restrict(hipStream_t s, cpx<R>* bc, cpx<R>* side, const cpx<R>* x, const cpx<R>* b, int n,
+                                 double h, const OpCoef* coef, int fpc, int nb, const double* tconv, Mask mk) {
+  const int ntx = (2 * n + 1 + kT - 1) / kT;
+  const dim3 g(tile_blocks(ntx, nb)), blk(256);
+  if (tconv)
+    hipLaunchKernelGGL((k_q2_residual_restrict<R, true>), g, blk, 0, s, bc, side, x, b, n, h, coef, fpc, tconv, ntx,
+                       nb, mk);
+  else
+    hipLaunchKernelGGL((k_q2_residual_restrict<R, false>), g, blk, 0, s, bc, side, x, b, n, h, coef, fpc, tconv, ntx,
+                       nb, mk);
+  const int len = n - 1, A = len / kCT;
+  if (A > 0) {
+    const unsigned items = (unsigned)(2 * A * len);
+    hipLaunchKernelGGL((k_q2_restrict_fix<R>), dim3((items + 255) / 256, (unsigned)nb), blk, 0, s, bc, side, n, ntx,
+                       mk);
+  }
+}
+
+size_t q2_restrict_side_entries(int n) { return (size_t)q2_tile_count(n) * kSide; }
+
+template <typename R>
 void launch_q2_block_vel(hipStream_t s, cpx<R>* yV, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
                          const BlockCoef* bc, const double* tcN, const double* tcNT, Mask mk) {
   const int ntx = (2 * n + 1 + kT - 1) / kT;
@@ -743,7 +927,9 @@ size_t q2_tile_conv_entries(int n) { return (size_t)q2_tile_count(n) * 9 * 64 * 
   template void launch_q2_apply<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double, const OpCoef*,  \
                                    int, int, const double*, Mask);                                                    \
   template void launch_q2_block_vel<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,                 \
-                                       const BlockCoef*, const double*, const double*, Mask);
+                                       const BlockCoef*, const double*, const double*, Mask);                         \
+  template void launch_q2_residual_restrict<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, int,      \
+                                               double, const OpCoef*, int, int, const double*, Mask);
 
 PINTOC_Q2T_INST(double)
 PINTOC_Q2T_INST(float)
