@@ -25,13 +25,13 @@ void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, con
                        int n, double h, const OpCoef* coef, int fpc, int nb, const double* conv, bool forward,
                        Mask mk);
 template <typename R>
-void launch_residual(hipStream_t s, bool q2, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
-                     const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk);
+void launch_q1_residual(hipStream_t s, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
+                        const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk);
 template <typename R>
 void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, double h, const OpCoef* coef, int fpc,
                   int nb, const double* conv, Mask mk);
 template <typename R>
-void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk);
+void launch_q1_restrict(hipStream_t s, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk);
 template <typename R>
 void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb, Mask mk);
 template <typename R>

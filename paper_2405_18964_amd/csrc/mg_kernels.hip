@@ -259,45 +259,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(cpx<R>* __restrict__ y, const 
 }
 
 // ---------------------------------------------------------------- transfers
-// 1-D Q2 restriction weights for coarse node I, fine offsets -3..3 around 2I.
-__device__ inline void q2_restrict_w(int I, double w[7]) {
-  if ((I & 1) == 0) {
-    w[0] = -0.125; w[1] = 0; w[2] = 0.375; w[3] = 1; w[4] = 0.375; w[5] = 0; w[6] = -0.125;
-  } else {
-    w[0] = 0; w[1] = 0; w[2] = 0.75; w[3] = 1; w[4] = 0.75; w[5] = 0; w[6] = 0;
-  }
-}
-
-// bc = P^T rf on coarse interior nodes (fine boundary residuals are zero).
-template <typename R>
-__global__ __launch_bounds__(256) void k_q2_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc, Mask mk) {
-  const int f = blockIdx.y;
-  if (mk.off(f)) return;
-  const int nqc = 2 * nc + 1, nqf = 4 * nc + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nqc * nqc) return;
-  const int I = t % nqc, J = t / nqc;
-  const size_t oc = (size_t)f * nqc * nqc + t;
-  if (I == 0 || J == 0 || I == nqc - 1 || J == nqc - 1) { bc[oc] = cmk<cpx<R>>(0, 0); return; }
-  double wx[7], wy[7];
-  q2_restrict_w(I, wx);
-  q2_restrict_w(J, wy);
-  const cpx<R>* src = rf + (size_t)f * nqf * nqf;
-  double sr = 0, si = 0;
-  for (int dy = 0; dy < 7; ++dy) {
-    if (wy[dy] == 0.0) continue;
-    const int fy = 2 * J + dy - 3;
-    double rr = 0, ri = 0;
-    for (int dx = 0; dx < 7; ++dx) {
-      if (wx[dx] == 0.0) continue;
-      const cpx<R> v = src[(size_t)fy * nqf + 2 * I + dx - 3];
-      rr += wx[dx] * (double)v.x; ri += wx[dx] * (double)v.y;
-    }
-    sr += wy[dy] * rr; si += wy[dy] * ri;
-  }
-  bc[oc] = cmk<cpx<R>>(sr, si);
-}
-
+// (Q2 levels restrict inside k_q2_residual_restrict, q2_tiles.hip.)
 // Q1: bc = P^T rf (coarse node I <-> fine 2I, weights 1/2, 1, 1/2).
 template <typename R>
 __global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, const cpx<R>* __restrict__ rf, int nc, Mask mk) {
@@ -462,14 +424,10 @@ void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, con
 }
 
 template <typename R>
-void launch_residual(hipStream_t s, bool q2, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
-                     const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk) {
-  if (q2) {
-    launch_q2_apply<R>(s, r, x, b, n, h, coef, fpc, nb, conv, mk);
-  } else {
-    const int np = n + 1;
-    hipLaunchKernelGGL(k_q1_residual<R>, grid2((long)np * np, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv, mk);
-  }
+void launch_q1_residual(hipStream_t s, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
+                        const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk) {
+  const int np = n + 1;
+  hipLaunchKernelGGL(k_q1_residual<R>, grid2((long)np * np, nb), dim3(256), 0, s, r, x, b, n, h, coef, fpc, conv, mk);
 }
 
 template <typename R>
@@ -484,14 +442,9 @@ void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, dou
 }
 
 template <typename R>
-void launch_restrict(hipStream_t s, bool q2, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk) {
-  if (q2) {
-    const int nqc = 2 * nc + 1;
-    hipLaunchKernelGGL(k_q2_restrict<R>, grid2((long)nqc * nqc, nb), dim3(256), 0, s, bc, rf, nc, mk);
-  } else {
-    const int npc = nc + 1;
-    hipLaunchKernelGGL(k_q1_restrict<R>, grid2((long)npc * npc, nb), dim3(256), 0, s, bc, rf, nc, mk);
-  }
+void launch_q1_restrict(hipStream_t s, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk) {
+  const int npc = nc + 1;
+  hipLaunchKernelGGL(k_q1_restrict<R>, grid2((long)npc * npc, nb), dim3(256), 0, s, bc, rf, nc, mk);
 }
 
 template <typename R>
@@ -523,11 +476,11 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
 #define PINTOC_INST(R)                                                                                        \
   template void launch_tile_sweep<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, \
                                      double, const OpCoef*, int, int, const double*, bool, Mask);                    \
-  template void launch_residual<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,       \
-                                   const OpCoef*, int, int, const double*, Mask);                                    \
+  template void launch_q1_residual<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,          \
+                                      const OpCoef*, int, int, const double*, Mask);                                 \
   template void launch_apply<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
                                 const double*, Mask);                                                                \
-  template void launch_restrict<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, int, Mask);                       \
+  template void launch_q1_restrict<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, Mask);                          \
   template void launch_coarse<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const double2*, int, int, Mask);         \
   template void launch_cheb<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int,    \
                                double, double, double, int, int, Mask);                                              \

@@ -684,8 +684,8 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
   if (m.q2) {
     launch_q2_residual_restrict<R>(s, bc, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
   } else {
-    launch_residual<R>(s, false, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
-    launch_restrict<R>(s, false, bc, r, n / 2, m.nb, m.mk());
+    launch_q1_residual<R>(s, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
+    launch_q1_restrict<R>(s, bc, r, n / 2, m.nb, m.mk());
   }
   vcycle<R>(s, m, l + 1, xc, bc, true);
   launch_tile_sweep<R>(s, m.q2, x, t, b, xc, n, h, m.coef, m.fpc, m.nb, m.conv[l], false, m.mk());

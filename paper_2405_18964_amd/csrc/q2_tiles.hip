@@ -32,6 +32,11 @@
 // per work-group, which spreads the heavy vertex-vertex class (25 points) over
 // the SIMDs.
 //
+// Arithmetic runs in the storage precision R of the grids (FP64, or FP32 for
+// the inner solves of the mixed-precision mode), so an FP32 sweep neither
+// converts its operands nor holds FP64 registers.  (The frequency-block matvec
+// k_q2_block_vel accumulates in FP64 in both modes.)
+//
 // Work-group order is XCD-aware: ids are dealt round-robin to the 8 XCDs, so
 // id g is remapped to v = (g % 8) (G / 8) + g / 8 and every XCD gets a
 // contiguous range of v.  With a convection table v runs over grids fastest
@@ -66,17 +71,19 @@ __device__ __forceinline__ constexpr int loff(int dx, int dy) {
 // (m' . v, k' . v) along one direction for class P
 template <int P> struct Comb;
 template <> struct Comb<0> {
-  static __device__ __forceinline__ void run(const double* v, double& m, double& k) {
-    const double s04 = v[0] + v[4], s13 = v[1] + v[3];
-    m = fma(8.0, v[2], fma(2.0, s13, -s04));
-    k = fma(14.0, v[2], fma(-8.0, s13, s04));
+  template <typename T>
+  static __device__ __forceinline__ void run(const T* v, T& m, T& k) {
+    const T s04 = v[0] + v[4], s13 = v[1] + v[3];
+    m = fma(T(8), v[2], fma(T(2), s13, -s04));
+    k = fma(T(14), v[2], fma(T(-8), s13, s04));
   }
 };
 template <> struct Comb<1> {
-  static __device__ __forceinline__ void run(const double* v, double& m, double& k) {
-    const double s02 = v[0] + v[2];
-    m = fma(16.0, v[1], 2.0 * s02);
-    k = fma(16.0, v[1], -8.0 * s02);
+  template <typename T>
+  static __device__ __forceinline__ void run(const T* v, T& m, T& k) {
+    const T s02 = v[0] + v[2];
+    m = fma(T(16), v[1], T(2) * s02);
+    k = fma(T(16), v[1], T(-8) * s02);
   }
 };
 
@@ -105,42 +112,49 @@ __host__ __device__ __forceinline__ void node_of(int px, int py, int col, int la
 // class served by wave w at colour step k (0: (0,0), 1: (1,0), 2: (0,1), 3: (1,1))
 __device__ __forceinline__ int class_of(int w, int k, int rot) { return (w + k + rot) & 3; }
 
-// Uniform coefficients of a work-group: a = alpha h^2/900, g = gamma/90, e = eta.
+// Uniform coefficients of a work-group in precision T: a = alpha h^2/900,
+// g = gamma/90, e = eta.
+template <typename T>
 struct TCoef {
-  double ar, ai, gr, gi, er, ei;
+  T ar, ai, gr, gi, er, ei;
 };
 
-__device__ __forceinline__ TCoef tcoef(const OpCoef& c, double h) {
+template <typename T>
+__device__ __forceinline__ TCoef<T> tcoef(const OpCoef& c, double h) {
   const double s = h * h / 900.0;
-  return TCoef{c.alpha.x * s, c.alpha.y * s, c.gamma.x / 90.0, c.gamma.y / 90.0, c.eta.x, c.eta.y};
+  return TCoef<T>{(T)(c.alpha.x * s), (T)(c.alpha.y * s), (T)(c.gamma.x / 90.0), (T)(c.gamma.y / 90.0), (T)c.eta.x,
+                  (T)c.eta.y};
 }
 
 // a Md + g Kd: diagonal without convection for class (PX, PY)
-template <int PX, int PY>
-__device__ __forceinline__ double2 diag0(const TCoef& t) {
-  constexpr double md = cm0(PX) * cm0(PY), kd = ck0(PX) * cm0(PY) + cm0(PX) * ck0(PY);
-  return make_double2(t.ar * md + t.gr * kd, t.ai * md + t.gi * kd);
+template <int PX, int PY, typename T>
+__device__ __forceinline__ cpx<T> diag0(const TCoef<T>& t) {
+  constexpr T md = cm0(PX) * cm0(PY), kd = ck0(PX) * cm0(PY) + cm0(PX) * ck0(PY);
+  cpx<T> d;
+  d.x = t.ar * md + t.gr * kd;
+  d.y = t.ai * md + t.gi * kd;
+  return d;
 }
 
 // A x at a class-(PX, PY) node: base points at the node's sub-grid origin, cn
 // at its lane's first convection entry (stride 64).  Returns A x and the
 // diagonal convection entry.
 template <int PX, int PY, bool CV, typename R>
-__device__ __forceinline__ double2 stencil(const cpx<R>* base, const double* __restrict__ cn, const TCoef& t,
-                                          double& cdiag) {
+__device__ __forceinline__ cpx<R> stencil(const cpx<R>* base, const double* __restrict__ cn, const TCoef<R>& t,
+                                          R& cdiag) {
   constexpr int nx = wlen(PX), ny = wlen(PY), lx0 = wlo(PX), ly0 = wlo(PY);
-  double smr[ny], smi[ny], skr[ny], ski[ny];
-  double cr = 0, ci = 0;
+  R smr[ny], smi[ny], skr[ny], ski[ny];
+  R cr = 0, ci = 0;
 #pragma unroll
   for (int iy = 0; iy < ny; ++iy) {
-    double vr[nx], vi[nx];
+    R vr[nx], vi[nx];
 #pragma unroll
     for (int ix = 0; ix < nx; ++ix) {
       const cpx<R> v = base[loff<PX, PY>(lx0 + ix, ly0 + iy)];
-      vr[ix] = (double)v.x;
-      vi[ix] = (double)v.y;
+      vr[ix] = v.x;
+      vi[ix] = v.y;
       if (CV) {
-        const double c = cn[(iy * nx + ix) * 64];
+        const R c = (R)cn[(iy * nx + ix) * 64];
         cr = fma(c, vr[ix], cr);
         ci = fma(c, vi[ix], ci);
       }
@@ -148,20 +162,21 @@ __device__ __forceinline__ double2 stencil(const cpx<R>* base, const double* __r
     Comb<PX>::run(vr, smr[iy], skr[iy]);
     Comb<PX>::run(vi, smi[iy], ski[iy]);
   }
-  double pmr, pmi, kmr, kmi, mkr, mki, unr, uni;
+  R pmr, pmi, kmr, kmi, mkr, mki, unr, uni;
   Comb<PY>::run(smr, pmr, kmr);        // m'_y . (m'_x v),  k'_y . (m'_x v)
   Comb<PY>::run(smi, pmi, kmi);
   Comb<PY>::run(skr, mkr, unr);        // m'_y . (k'_x v)
   Comb<PY>::run(ski, mki, uni);
-  const double pkr = mkr + kmr, pki = mki + kmi;
-  double axr = t.ar * pmr - t.ai * pmi + t.gr * pkr - t.gi * pki;
-  double axi = t.ar * pmi + t.ai * pmr + t.gr * pki + t.gi * pkr;
+  const R pkr = mkr + kmr, pki = mki + kmi;
+  cpx<R> ax;
+  ax.x = t.ar * pmr - t.ai * pmi + t.gr * pkr - t.gi * pki;
+  ax.y = t.ar * pmi + t.ai * pmr + t.gr * pki + t.gi * pkr;
   if (CV) {
-    axr += t.er * cr - t.ei * ci;
-    axi += t.er * ci + t.ei * cr;
-    cdiag = cn[((wlen(PY) / 2) * nx + nx / 2) * 64];
+    ax.x += t.er * cr - t.ei * ci;
+    ax.y += t.er * ci + t.ei * cr;
+    cdiag = (R)cn[((wlen(PY) / 2) * nx + nx / 2) * 64];
   }
-  return make_double2(axr, axi);
+  return ax;
 }
 
 __device__ __forceinline__ bool tile_of_block(int ntiles, int nb, bool grid_fast, int& tile, int& f) {
@@ -203,11 +218,12 @@ __device__ __forceinline__ void load_tile(cpx<R>* sx, const cpx<R>* __restrict__
 }
 
 // 1-D Q2 prolongation: fine node 4e + r from coarse nodes 2e, 2e + 1, 2e + 2.
-__device__ __forceinline__ void prolong_row(const double c[3], double f[4]) {
+template <typename T>
+__device__ __forceinline__ void prolong_row(const T c[3], T f[4]) {
   f[0] = c[0];
-  f[1] = 0.375 * c[0] + 0.75 * c[1] - 0.125 * c[2];
+  f[1] = T(0.375) * c[0] + T(0.75) * c[1] - T(0.125) * c[2];
   f[2] = c[1];
-  f[3] = -0.125 * c[0] + 0.75 * c[1] + 0.375 * c[2];
+  f[3] = T(-0.125) * c[0] + T(0.75) * c[1] + T(0.375) * c[2];
 }
 
 // Load t + P ec (t: fine iterate, ec: coarse correction on the padded grid of
@@ -241,20 +257,20 @@ __device__ __forceinline__ void load_tile_prolong(cpx<R>* sx, const cpx<R>* __re
                         gy <= nq - 2;
       tv[4 * s2 + r] = load ? xi[(size_t)gy * nq + gx] : cmk<cpx<R>>(0, 0);
     }
-  double pr[3][4], pi[3][4];          // prolonged along x, per coarse row
+  R pr[3][4], pi[3][4];                // prolonged along x, per coarse row
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double cr[3] = {(double)c[3 * a].x, (double)c[3 * a + 1].x, (double)c[3 * a + 2].x};
-    const double ci[3] = {(double)c[3 * a].y, (double)c[3 * a + 1].y, (double)c[3 * a + 2].y};
-    prolong_row(cr, pr[a]);
-    prolong_row(ci, pi[a]);
+    const R cr[3] = {c[3 * a].x, c[3 * a + 1].x, c[3 * a + 2].x};
+    const R ci[3] = {c[3 * a].y, c[3 * a + 1].y, c[3 * a + 2].y};
+    prolong_row<R>(cr, pr[a]);
+    prolong_row<R>(ci, pi[a]);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const double colr[3] = {pr[0][r], pr[1][r], pr[2][r]}, coli[3] = {pi[0][r], pi[1][r], pi[2][r]};
-    double fr[4], fi[4];
-    prolong_row(colr, fr);
-    prolong_row(coli, fi);
+    const R colr[3] = {pr[0][r], pr[1][r], pr[2][r]}, coli[3] = {pi[0][r], pi[1][r], pi[2][r]};
+    R fr[4], fi[4];
+    prolong_row<R>(colr, fr);
+    prolong_row<R>(coli, fi);
     const int gx = 4 * ex0 + r, ex = gx - X0 + 2;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
@@ -262,7 +278,10 @@ __device__ __forceinline__ void load_tile_prolong(cpx<R>* sx, const cpx<R>* __re
       if (ex < 0 || ex >= kE || ey < 0 || ey >= kE) continue;
       const bool in = gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2;
       const cpx<R> t = tv[4 * s2 + r];
-      sx[sub_index(ex, ey)] = in ? cmk<cpx<R>>((double)t.x + fr[s2], (double)t.y + fi[s2]) : cmk<cpx<R>>(0, 0);
+      cpx<R> v;
+      v.x = in ? t.x + fr[s2] : R(0);
+      v.y = in ? t.y + fi[s2] : R(0);
+      sx[sub_index(ex, ey)] = v;
     }
   }
 }
@@ -285,32 +304,40 @@ __device__ __forceinline__ void prefetch_b(cpx<R>* bb, const cpx<R>* __restrict_
 // class diagonal (used without convection, where it is uniform).
 template <int PX, int PY, bool CV, typename R>
 __device__ __forceinline__ void sweep_node(cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0, int nq,
-                                           cpx<R> bv, const TCoef& t, double2 dinv, const double* __restrict__ ctile) {
+                                           cpx<R> bv, const TCoef<R>& t, cpx<R> dinv,
+                                           const double* __restrict__ ctile) {
   int lx, ly;
   node_of(PX, PY, col, la, lb, lx, ly);
   const int gx = X0 + lx, gy = Y0 + ly;
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return;
   cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
   const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
-  double cd = 0;
-  const double2 ax = stencil<PX, PY, CV, R>(base, cn, t, cd);
+  R cd = 0;
+  const cpx<R> ax = stencil<PX, PY, CV, R>(base, cn, t, cd);
   if (CV) {
-    double2 d = diag0<PX, PY>(t);
+    cpx<R> d = diag0<PX, PY, R>(t);
     d.x += t.er * cd;
     d.y += t.ei * cd;
-    const double inv = 1.0 / (d.x * d.x + d.y * d.y);
-    dinv = make_double2(d.x * inv, -d.y * inv);
+    const R inv = R(1) / (d.x * d.x + d.y * d.y);
+    dinv.x = d.x * inv;
+    dinv.y = -d.y * inv;
   }
-  const double er = (double)bv.x - ax.x, ei = (double)bv.y - ax.y;
+  const R er = bv.x - ax.x, ei = bv.y - ax.y;
   cpx<R>& xs = base[loff<PX, PY>(0, 0)];
-  xs = cmk<cpx<R>>((double)xs.x + er * dinv.x - ei * dinv.y, (double)xs.y + er * dinv.y + ei * dinv.x);
+  cpx<R> nx;
+  nx.x = xs.x + er * dinv.x - ei * dinv.y;
+  nx.y = xs.y + er * dinv.y + ei * dinv.x;
+  xs = nx;
 }
 
-template <int PX, int PY>
-__device__ __forceinline__ double2 inv_diag0(const TCoef& t) {
-  const double2 d = diag0<PX, PY>(t);
-  const double inv = 1.0 / (d.x * d.x + d.y * d.y);
-  return make_double2(d.x * inv, -d.y * inv);
+template <int PX, int PY, typename R>
+__device__ __forceinline__ cpx<R> inv_diag0(const TCoef<R>& t) {
+  const cpx<R> d = diag0<PX, PY, R>(t);
+  const R inv = R(1) / (d.x * d.x + d.y * d.y);
+  cpx<R> v;
+  v.x = d.x * inv;
+  v.y = -d.y * inv;
+  return v;
 }
 
 // Write the tile interior from LDS (or zero on boundary nodes) to xo.  Thread
@@ -358,13 +385,13 @@ __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const
   prefetch_b<R, FWD>(bb, b + off, w, rot, la, lb, X0, Y0, nq);
   if (PRO) load_tile_prolong<R>(sx, xi ? xi + off : nullptr, ec + (size_t)f * nqc * nqc, nq, X0, Y0);
   else load_tile<R>(sx, xi ? xi + off : nullptr, nq, X0, Y0);
-  const TCoef t = tcoef(coef[f / fpc], h);
-  double2 dv0 = make_double2(0, 0), dv1 = dv0, dv2 = dv0, dv3 = dv0;
+  const TCoef<R> t = tcoef<R>(coef[f / fpc], h);
+  cpx<R> dv0 = cmk<cpx<R>>(0, 0), dv1 = dv0, dv2 = dv0, dv3 = dv0;
   if (!CV) {
-    dv0 = inv_diag0<0, 0>(t);
-    dv1 = inv_diag0<1, 0>(t);
-    dv2 = inv_diag0<0, 1>(t);
-    dv3 = inv_diag0<1, 1>(t);
+    dv0 = inv_diag0<0, 0, R>(t);
+    dv1 = inv_diag0<1, 0, R>(t);
+    dv2 = inv_diag0<0, 1, R>(t);
+    dv3 = inv_diag0<1, 1, R>(t);
   }
   const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
   __syncthreads();
@@ -384,16 +411,16 @@ __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const
 
 namespace {
 template <int PX, int PY, bool CV, typename R>
-__device__ __forceinline__ double2 apply_node(const cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0,
-                                              int nq, const TCoef& t, const double* __restrict__ ctile, int& si) {
+__device__ __forceinline__ cpx<R> apply_node(const cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0,
+                                             int nq, const TCoef<R>& t, const double* __restrict__ ctile, int& si) {
   int lx, ly;
   node_of(PX, PY, col, la, lb, lx, ly);
   si = ly * kSP + lx;
   const int gx = X0 + lx, gy = Y0 + ly;
-  if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return make_double2(0, 0);
+  if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return cmk<cpx<R>>(0, 0);
   const cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
   const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
-  double cd = 0;
+  R cd = 0;
   return stencil<PX, PY, CV, R>(base, cn, t, cd);
 }
 
@@ -401,13 +428,13 @@ __device__ __forceinline__ double2 apply_node(const cpx<R>* sx, int col, int la,
 // (pitch kSP) in the LDS tile (zero on boundary and outside nodes).
 template <typename R, bool CV>
 __device__ __forceinline__ void apply_stage(cpx<R>* sx, const cpx<R>* __restrict__ x, int nq, int X0, int Y0,
-                                            const TCoef& t, const double* __restrict__ ctile, int w, int lane,
+                                            const TCoef<R>& t, const double* __restrict__ ctile, int w, int lane,
                                             int rot) {
   int la, lb;
   lane_ab(lane, la, lb);
   load_tile<R>(sx, x, nq, X0, Y0);
   __syncthreads();
-  double2 acc[9];
+  cpx<R> acc[9];
   int si[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
@@ -420,7 +447,7 @@ __device__ __forceinline__ void apply_stage(cpx<R>* sx, const cpx<R>* __restrict
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 9; ++k) sx[si[k]] = cmk<cpx<R>>(acc[k].x, acc[k].y);
+  for (int k = 0; k < 9; ++k) sx[si[k]] = acc[k];
   __syncthreads();
 }
 }  // namespace
@@ -440,7 +467,7 @@ __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out,
   const int nq = 2 * n + 1;
   const size_t off = (size_t)f * nq * nq;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
-  const TCoef t = tcoef(coef[f / fpc], h);
+  const TCoef<R> t = tcoef<R>(coef[f / fpc], h);
   const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
   apply_stage<R, CV>(sx, x + off, nq, X0, Y0, t, ctile, w, lane, rot);     // A x staged for a coalesced store
   if (threadIdx.x < 5 * kT) {
@@ -492,27 +519,29 @@ __device__ __forceinline__ void restrict_class(cpx<R>* __restrict__ bcf, cpx<R>*
     const int ci = 2 * (e % na) + PI, cj = 2 * (e / na) + PJ;
     const int I = I0 + ci, J = J0 + cj;
     if (I >= nqc || J >= nqc) continue;
-    double vr = 0, vi = 0;
+    R vr = 0, vi = 0;
 #pragma unroll
     for (int iy = 0; iy < 5; ++iy) {
       if (rw<PJ>(iy) == 0.0) continue;
       const int fy = 2 * cj + roff(iy);
       if (fy < 0 || fy >= kT) continue;
-      double rr = 0, ri = 0;
+      R rr = 0, ri = 0;
 #pragma unroll
       for (int ix = 0; ix < 5; ++ix) {
         if (rw<PI>(ix) == 0.0) continue;
         const int fx = 2 * ci + roff(ix);
         if (fx < 0 || fx >= kT) continue;
         const cpx<R> v = sr[fy * kSP + fx];
-        rr = fma(rw<PI>(ix), (double)v.x, rr);
-        ri = fma(rw<PI>(ix), (double)v.y, ri);
+        rr = fma((R)rw<PI>(ix), v.x, rr);
+        ri = fma((R)rw<PI>(ix), v.y, ri);
       }
-      vr = fma(rw<PJ>(iy), rr, vr);
-      vi = fma(rw<PJ>(iy), ri, vi);
+      vr = fma((R)rw<PJ>(iy), rr, vr);
+      vi = fma((R)rw<PJ>(iy), ri, vi);
     }
     const bool bnd = I == 0 || J == 0 || I == nqc - 1 || J == nqc - 1;
-    const cpx<R> v = bnd ? cmk<cpx<R>>(0, 0) : cmk<cpx<R>>(vr, vi);
+    cpx<R> v;
+    v.x = bnd ? R(0) : vr;
+    v.y = bnd ? R(0) : vi;
     if (ci < kCT && cj < kCT) bcf[(size_t)J * nqc + I] = v;
     else if (ci == kCT) sd[cj] = v;
     else sd[kCT + 1 + ci] = v;
@@ -535,7 +564,7 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
   const int nq = 2 * n + 1, nqc = n + 1;
   const size_t off = (size_t)f * nq * nq;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
-  const TCoef t = tcoef(coef[f / fpc], h);
+  const TCoef<R> t = tcoef<R>(coef[f / fpc], h);
   const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
   // b of this thread's column rows (thread t < 5 kT: column t % kT, rows t / kT + 5 k);
   // in FP64 it is loaded before the stencil phase so its latency overlaps it (in
@@ -563,7 +592,10 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
       if (ly >= kT) break;
       if constexpr (!kPre) bv[k] = bload(k);
       const cpx<R> a = sx[ly * kSP + lx];
-      sx[ly * kSP + lx] = cmk<cpx<R>>((double)bv[k].x - (double)a.x, (double)bv[k].y - (double)a.y);
+      cpx<R> r;
+      r.x = bv[k].x - a.x;
+      r.y = bv[k].y - a.y;
+      sx[ly * kSP + lx] = r;
     }
   }
   __syncthreads();
