@@ -3,6 +3,9 @@
 // Chebyshev steps (section 3.4: multigrid with SOR smoothing, Chebyshev
 // semi-iteration for mass matrices).
 //
+// Arithmetic runs in the grids' precision R (stencil rows are formed in FP64
+// and rounded once); the coarsest-grid solves accumulate in FP64.
+//
 // A "batch" is nb complex grids stored back to back.  Q2 grids are padded
 // (2n+1)^2 with the Dirichlet boundary at zero; Q1 grids hold all (n+1)^2
 // nodes (natural boundary conditions).  Grid f uses coefficient set
@@ -11,6 +14,31 @@
 
 namespace pintoc {
 
+// 1-D stencil rows in precision R
+template <typename R>
+__device__ __forceinline__ void q2_rows_r(int i, double h, R m[5], R k[5]) {
+  double md[5], kd[5];
+  q2_rows(i, h, md, kd);
+#pragma unroll
+  for (int d = 0; d < 5; ++d) { m[d] = (R)md[d]; k[d] = (R)kd[d]; }
+}
+template <typename R>
+__device__ __forceinline__ void q1_rows_r(int i, int n, double h, R m[3], R k[3]) {
+  double md[3], kd[3];
+  q1_rows(i, n, h, md, kd);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) { m[d] = (R)md[d]; k[d] = (R)kd[d]; }
+}
+
+// Operator coefficients in precision R
+template <typename R>
+struct OpR {
+  R ar, ai, gr, gi, er, ei, tr, ti;
+  __device__ __forceinline__ explicit OpR(const OpCoef& c)
+      : ar((R)c.alpha.x), ai((R)c.alpha.y), gr((R)c.gamma.x), gi((R)c.gamma.y), er((R)c.eta.x), ei((R)c.eta.y),
+        tr((R)c.etat.x), ti((R)c.etat.y) {}
+};
+
 // Q2 operator  alpha M + gamma K + eta N + etat N^T  at interior node (ix, iy).
 // Returns (A x)(ix, iy) and the diagonal entry.  The convection stencil table
 // (if any) holds 25 coefficients per node for N and 25 for N^T.
@@ -18,9 +46,10 @@ template <typename R>
 __device__ inline void q2_apply_node(const cpx<R>* __restrict__ x, int nq, int ix, int iy, double h,
                                      const OpCoef& c, const double* __restrict__ conv,
                                      cpx<R>& ax, cpx<R>& diag) {
-  double mx[5], kx[5], my[5], ky[5];
-  q2_rows(ix, h, mx, kx);
-  q2_rows(iy, h, my, ky);
+  R mx[5], kx[5], my[5], ky[5];
+  q2_rows_r<R>(ix, h, mx, kx);
+  q2_rows_r<R>(iy, h, my, ky);
+  const OpR<R> o(c);
   // Offsets +-2 carry zero weight at midpoint nodes, which may sit next to the
   // boundary: clamp their indices so every load stays inside the grid.
   int cx[5], ry[5];
@@ -29,43 +58,43 @@ __device__ inline void q2_apply_node(const cpx<R>* __restrict__ x, int nq, int i
     cx[d] = min(max(ix + d - 2, 0), nq - 1);
     ry[d] = min(max(iy + d - 2, 0), nq - 1) * nq;
   }
-  double amr = 0, ami = 0, akr = 0, aki = 0;   // M x and K x
+  R amr = 0, ami = 0, akr = 0, aki = 0;        // M x and K x
 #pragma unroll
   for (int dy = 0; dy < 5; ++dy) {
-    double smr = 0, smi = 0, skr = 0, ski = 0;
+    R smr = 0, smi = 0, skr = 0, ski = 0;
 #pragma unroll
     for (int dx = 0; dx < 5; ++dx) {
       cpx<R> v = x[ry[dy] + cx[dx]];
-      smr += mx[dx] * (double)v.x; smi += mx[dx] * (double)v.y;
-      skr += kx[dx] * (double)v.x; ski += kx[dx] * (double)v.y;
+      smr += mx[dx] * v.x; smi += mx[dx] * v.y;
+      skr += kx[dx] * v.x; ski += kx[dx] * v.y;
     }
     amr += my[dy] * smr; ami += my[dy] * smi;
     akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
   }
-  double rr = c.alpha.x * amr - c.alpha.y * ami + c.gamma.x * akr - c.gamma.y * aki;
-  double ri = c.alpha.x * ami + c.alpha.y * amr + c.gamma.x * aki + c.gamma.y * akr;
-  const double md = mx[2] * my[2], kd = kx[2] * my[2] + mx[2] * ky[2];
-  double dr = c.alpha.x * md + c.gamma.x * kd, di = c.alpha.y * md + c.gamma.y * kd;
+  R rr = o.ar * amr - o.ai * ami + o.gr * akr - o.gi * aki;
+  R ri = o.ar * ami + o.ai * amr + o.gr * aki + o.gi * akr;
+  const R md = mx[2] * my[2], kd = kx[2] * my[2] + mx[2] * ky[2];
+  R dr = o.ar * md + o.gr * kd, di = o.ai * md + o.gi * kd;
   if (conv) {
     const double* cn = conv + (size_t)(iy * nq + ix) * 50;
-    double nr = 0, ni = 0, tr = 0, ti = 0;
+    R nr = 0, ni = 0, tr = 0, ti = 0;
 #pragma unroll
     for (int dy = 0; dy < 5; ++dy) {
 #pragma unroll
       for (int dx = 0; dx < 5; ++dx) {
         cpx<R> v = x[ry[dy] + cx[dx]];
-        const double a = cn[dy * 5 + dx], b = cn[25 + dy * 5 + dx];
-        nr += a * (double)v.x; ni += a * (double)v.y;
-        tr += b * (double)v.x; ti += b * (double)v.y;
+        const R a = (R)cn[dy * 5 + dx], b = (R)cn[25 + dy * 5 + dx];
+        nr += a * v.x; ni += a * v.y;
+        tr += b * v.x; ti += b * v.y;
       }
     }
-    rr += c.eta.x * nr - c.eta.y * ni + c.etat.x * tr - c.etat.y * ti;
-    ri += c.eta.x * ni + c.eta.y * nr + c.etat.x * ti + c.etat.y * tr;
-    dr += c.eta.x * cn[12] + c.etat.x * cn[37];
-    di += c.eta.y * cn[12] + c.etat.y * cn[37];
+    rr += o.er * nr - o.ei * ni + o.tr * tr - o.ti * ti;
+    ri += o.er * ni + o.ei * nr + o.tr * ti + o.ti * tr;
+    dr += o.er * (R)cn[12] + o.tr * (R)cn[37];
+    di += o.ei * (R)cn[12] + o.ti * (R)cn[37];
   }
-  ax.x = (R)rr; ax.y = (R)ri;
-  diag.x = (R)dr; diag.y = (R)di;
+  ax.x = rr; ax.y = ri;
+  diag.x = dr; diag.y = di;
 }
 
 // Q1 operator on the unconstrained grid at node (ix, iy), 0 <= ix, iy <= n.
@@ -75,65 +104,66 @@ __device__ inline void q1_apply_node(const cpx<R>* __restrict__ x, int n, int ix
                                      const OpCoef& c, const double* __restrict__ conv,
                                      cpx<R>& ax, cpx<R>& diag) {
   const int np = n + 1;
-  double mx[3], kx[3], my[3], ky[3];
-  q1_rows(ix, n, h, mx, kx);
-  q1_rows(iy, n, h, my, ky);
-  double amr = 0, ami = 0, akr = 0, aki = 0;
-  double nr = 0, ni = 0, tr = 0, ti = 0;
+  R mx[3], kx[3], my[3], ky[3];
+  q1_rows_r<R>(ix, n, h, mx, kx);
+  q1_rows_r<R>(iy, n, h, my, ky);
+  const OpR<R> o(c);
+  R amr = 0, ami = 0, akr = 0, aki = 0;
+  R nr = 0, ni = 0, tr = 0, ti = 0;
   const double* cn = conv ? conv + (size_t)(iy * np + ix) * 18 : nullptr;
 #pragma unroll
   for (int dy = 0; dy < 3; ++dy) {
     const int jy = iy + dy - 1;
     if (jy < 0 || jy > n) continue;
-    double smr = 0, smi = 0, skr = 0, ski = 0;
+    R smr = 0, smi = 0, skr = 0, ski = 0;
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       const int jx = ix + dx - 1;
       if (jx < 0 || jx > n) continue;
       cpx<R> v = x[jy * np + jx];
-      smr += mx[dx] * (double)v.x; smi += mx[dx] * (double)v.y;
-      skr += kx[dx] * (double)v.x; ski += kx[dx] * (double)v.y;
+      smr += mx[dx] * v.x; smi += mx[dx] * v.y;
+      skr += kx[dx] * v.x; ski += kx[dx] * v.y;
       if (cn) {
-        const double a = cn[dy * 3 + dx], b = cn[9 + dy * 3 + dx];
-        nr += a * (double)v.x; ni += a * (double)v.y;
-        tr += b * (double)v.x; ti += b * (double)v.y;
+        const R a = (R)cn[dy * 3 + dx], b = (R)cn[9 + dy * 3 + dx];
+        nr += a * v.x; ni += a * v.y;
+        tr += b * v.x; ti += b * v.y;
       }
     }
     amr += my[dy] * smr; ami += my[dy] * smi;
     akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
   }
-  double rr = c.alpha.x * amr - c.alpha.y * ami + c.gamma.x * akr - c.gamma.y * aki;
-  double ri = c.alpha.x * ami + c.alpha.y * amr + c.gamma.x * aki + c.gamma.y * akr;
-  const double md = mx[1] * my[1], kd = kx[1] * my[1] + mx[1] * ky[1];
-  double dr = c.alpha.x * md + c.gamma.x * kd, di = c.alpha.y * md + c.gamma.y * kd;
+  R rr = o.ar * amr - o.ai * ami + o.gr * akr - o.gi * aki;
+  R ri = o.ar * ami + o.ai * amr + o.gr * aki + o.gi * akr;
+  const R md = mx[1] * my[1], kd = kx[1] * my[1] + mx[1] * ky[1];
+  R dr = o.ar * md + o.gr * kd, di = o.ai * md + o.gi * kd;
   if (cn) {
-    rr += c.eta.x * nr - c.eta.y * ni + c.etat.x * tr - c.etat.y * ti;
-    ri += c.eta.x * ni + c.eta.y * nr + c.etat.x * ti + c.etat.y * tr;
-    dr += c.eta.x * cn[4] + c.etat.x * cn[13];
-    di += c.eta.y * cn[4] + c.etat.y * cn[13];
+    rr += o.er * nr - o.ei * ni + o.tr * tr - o.ti * ti;
+    ri += o.er * ni + o.ei * nr + o.tr * ti + o.ti * tr;
+    dr += o.er * (R)cn[4] + o.tr * (R)cn[13];
+    di += o.ei * (R)cn[4] + o.ti * (R)cn[13];
   }
-  ax.x = (R)rr; ax.y = (R)ri;
-  diag.x = (R)dr; diag.y = (R)di;
+  ax.x = rr; ax.y = ri;
+  diag.x = dr; diag.y = di;
 }
 
 // (P e)(i, j) of the Q1 prolongation from the coarse grid (npc nodes per side):
 // fine node i takes coarse i/2 (i even) or the mean of (i-1)/2 and (i+1)/2.
 template <typename R>
-__device__ inline double2 q1_prolong_at(const cpx<R>* __restrict__ ec, int npc, int i, int j) {
+__device__ inline cpx<R> q1_prolong_at(const cpx<R>* __restrict__ ec, int npc, int i, int j) {
   const int ia = i >> 1, ib = (i + 1) >> 1, ja = j >> 1, jb = (j + 1) >> 1;
-  const double wx = (i & 1) ? 0.5 : 1.0, wy = (j & 1) ? 0.5 : 1.0;
+  const R wx = (i & 1) ? R(0.5) : R(1), wy = (j & 1) ? R(0.5) : R(1);
   const int nxs = (i & 1) ? 2 : 1, nys = (j & 1) ? 2 : 1;
-  double sr = 0, si = 0;
+  cpx<R> s = cmk<cpx<R>>(0, 0);
   for (int a = 0; a < nys; ++a) {
     const int cy = a == 0 ? ja : jb;
     for (int q = 0; q < nxs; ++q) {
       const int cx = q == 0 ? ia : ib;
       const cpx<R> v = ec[(size_t)cy * npc + cx];
-      sr += wx * wy * (double)v.x;
-      si += wx * wy * (double)v.y;
+      s.x += wx * wy * v.x;
+      s.y += wx * wy * v.y;
     }
   }
-  return make_double2(sr, si);
+  return s;
 }
 
 // ------------------------------------------------------ tiled GS sweeps
@@ -166,13 +196,14 @@ __global__ __launch_bounds__(256) void k_q1_tile_sweep(cpx<R>* __restrict__ xo, 
     if (gx >= 0 && gx <= n && gy >= 0 && gy <= n) {
       if (xi) v = xi[off + (size_t)gy * np + gx];
       if (ecf) {
-        const double2 p = q1_prolong_at<R>(ecf, npc, gx, gy);
-        v = cmk<cpx<R>>((double)v.x + p.x, (double)v.y + p.y);
+        const cpx<R> p = q1_prolong_at<R>(ecf, npc, gx, gy);
+        v.x += p.x;
+        v.y += p.y;
       }
     }
     sx[e] = v;
   }
-  const OpCoef c = coef[f / fpc];
+  const OpR<R> o(coef[f / fpc]);
   __syncthreads();
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   for (int k = 0; k < 4; ++k) {
@@ -180,43 +211,46 @@ __global__ __launch_bounds__(256) void k_q1_tile_sweep(cpx<R>* __restrict__ xo, 
     const int lx = col % 2 + 2 * tx, ly = col / 2 + 2 * ty;
     const int gx = X0 + lx, gy = Y0 + ly;
     if (gx <= n && gy <= n) {
-      double mx[3], kx[3], my[3], ky[3];
-      q1_rows(gx, n, h, mx, kx);
-      q1_rows(gy, n, h, my, ky);
-      double amr = 0, ami = 0, akr = 0, aki = 0, nr = 0, ni = 0, tr = 0, ti = 0;
+      R mx[3], kx[3], my[3], ky[3];
+      q1_rows_r<R>(gx, n, h, mx, kx);
+      q1_rows_r<R>(gy, n, h, my, ky);
+      R amr = 0, ami = 0, akr = 0, aki = 0, nr = 0, ni = 0, tr = 0, ti = 0;
       const double* cn = conv ? conv + (size_t)(gy * np + gx) * 18 : nullptr;
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
-        double smr = 0, smi = 0, skr = 0, ski = 0;
+        R smr = 0, smi = 0, skr = 0, ski = 0;
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
           const cpx<R> v = sx[(ly + dy) * kL1 + lx + dx];
-          smr += mx[dx] * (double)v.x; smi += mx[dx] * (double)v.y;
-          skr += kx[dx] * (double)v.x; ski += kx[dx] * (double)v.y;
+          smr += mx[dx] * v.x; smi += mx[dx] * v.y;
+          skr += kx[dx] * v.x; ski += kx[dx] * v.y;
           if (cn) {
-            const double a = cn[dy * 3 + dx], bb = cn[9 + dy * 3 + dx];
-            nr += a * (double)v.x; ni += a * (double)v.y;
-            tr += bb * (double)v.x; ti += bb * (double)v.y;
+            const R a = (R)cn[dy * 3 + dx], bb = (R)cn[9 + dy * 3 + dx];
+            nr += a * v.x; ni += a * v.y;
+            tr += bb * v.x; ti += bb * v.y;
           }
         }
         amr += my[dy] * smr; ami += my[dy] * smi;
         akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
       }
-      double rr = c.alpha.x * amr - c.alpha.y * ami + c.gamma.x * akr - c.gamma.y * aki;
-      double ri = c.alpha.x * ami + c.alpha.y * amr + c.gamma.x * aki + c.gamma.y * akr;
-      const double md = mx[1] * my[1], kd = kx[1] * my[1] + mx[1] * ky[1];
-      double dr = c.alpha.x * md + c.gamma.x * kd, di = c.alpha.y * md + c.gamma.y * kd;
+      R rr = o.ar * amr - o.ai * ami + o.gr * akr - o.gi * aki;
+      R ri = o.ar * ami + o.ai * amr + o.gr * aki + o.gi * akr;
+      const R md = mx[1] * my[1], kd = kx[1] * my[1] + mx[1] * ky[1];
+      R dr = o.ar * md + o.gr * kd, di = o.ai * md + o.gi * kd;
       if (cn) {
-        rr += c.eta.x * nr - c.eta.y * ni + c.etat.x * tr - c.etat.y * ti;
-        ri += c.eta.x * ni + c.eta.y * nr + c.etat.x * ti + c.etat.y * tr;
-        dr += c.eta.x * cn[4] + c.etat.x * cn[13];
-        di += c.eta.y * cn[4] + c.etat.y * cn[13];
+        rr += o.er * nr - o.ei * ni + o.tr * tr - o.ti * ti;
+        ri += o.er * ni + o.ei * nr + o.tr * ti + o.ti * tr;
+        dr += o.er * (R)cn[4] + o.tr * (R)cn[13];
+        di += o.ei * (R)cn[4] + o.ti * (R)cn[13];
       }
       const cpx<R> bi = b[off + (size_t)gy * np + gx];
-      const double er = (double)bi.x - rr, ei = (double)bi.y - ri;
-      const double den = dr * dr + di * di;
+      const R er = bi.x - rr, ei = bi.y - ri;
+      const R den = dr * dr + di * di;
       cpx<R>& xs = sx[(ly + 1) * kL1 + lx + 1];
-      xs = cmk<cpx<R>>((double)xs.x + (er * dr + ei * di) / den, (double)xs.y + (ei * dr - er * di) / den);
+      cpx<R> nxv;
+      nxv.x = xs.x + (er * dr + ei * di) / den;
+      nxv.y = xs.y + (ei * dr - er * di) / den;
+      xs = nxv;
     }
     __syncthreads();
   }
@@ -270,8 +304,8 @@ __global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, co
   if (t >= npc * npc) return;
   const int I = t % npc, J = t / npc;
   const cpx<R>* src = rf + (size_t)f * npf * npf;
-  const double w[3] = {0.5, 1.0, 0.5};
-  double sr = 0, si = 0;
+  const R w[3] = {R(0.5), R(1), R(0.5)};
+  cpx<R> sv = cmk<cpx<R>>(0, 0);
   for (int dy = 0; dy < 3; ++dy) {
     const int fy = 2 * J + dy - 1;
     if (fy < 0 || fy > nf) continue;
@@ -279,10 +313,10 @@ __global__ __launch_bounds__(256) void k_q1_restrict(cpx<R>* __restrict__ bc, co
       const int fx = 2 * I + dx - 1;
       if (fx < 0 || fx > nf) continue;
       const cpx<R> v = src[(size_t)fy * npf + fx];
-      sr += w[dx] * w[dy] * (double)v.x; si += w[dx] * w[dy] * (double)v.y;
+      sv.x += w[dx] * w[dy] * v.x; sv.y += w[dx] * w[dy] * v.y;
     }
   }
-  bc[(size_t)f * npc * npc + t] = cmk<cpx<R>>(sr, si);
+  bc[(size_t)f * npc * npc + t] = sv;
 }
 
 // --------------------------------------------------------- coarsest grid
@@ -345,20 +379,26 @@ __global__ __launch_bounds__(256) void k_q2_cheb(cpx<R>* xn, const cpx<R>* __res
   if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) { xn[i] = cmk<cpx<R>>(0, 0); return; }
   OpCoef c; c.alpha = make_double2(1, 0); c.gamma = make_double2(0, 0);
   c.eta = c.gamma; c.etat = c.gamma;
+  const R gr = (R)g, wr = (R)w;
   if (first) {
-    double mx[5], kx[5], my[5], ky[5];
-    q2_rows(ix, h, mx, kx); q2_rows(iy, h, my, ky);
-    const double d = mx[2] * my[2];
+    R mx[5], kx[5], my[5], ky[5];
+    q2_rows_r<R>(ix, h, mx, kx); q2_rows_r<R>(iy, h, my, ky);
+    const R d = mx[2] * my[2];
     const cpx<R> bi = b[i];
-    xn[i] = cmk<cpx<R>>(g * (double)bi.x / d, g * (double)bi.y / d);
+    cpx<R> v;
+    v.x = gr * bi.x / d;
+    v.y = gr * bi.y / d;
+    xn[i] = v;
     return;
   }
   cpx<R> ax, dg;
   q2_apply_node<R>(x + (size_t)f * nq * nq, nq, ix, iy, h, c, nullptr, ax, dg);
   const cpx<R> bi = b[i], xi = x[i], pi = xp[i];
-  const double d = (double)dg.x;
-  xn[i] = cmk<cpx<R>>(w * ((double)xi.x - (double)pi.x + g * ((double)bi.x - (double)ax.x) / d) + (double)pi.x,
-                      w * ((double)xi.y - (double)pi.y + g * ((double)bi.y - (double)ax.y) / d) + (double)pi.y);
+  const R d = dg.x;
+  cpx<R> v;
+  v.x = wr * (xi.x - pi.x + gr * (bi.x - ax.x) / d) + pi.x;
+  v.y = wr * (xi.y - pi.y + gr * (bi.y - ax.y) / d) + pi.y;
+  xn[i] = v;
 }
 
 template <typename R>
@@ -374,19 +414,25 @@ __global__ __launch_bounds__(256) void k_q1_cheb(cpx<R>* xn, const cpx<R>* __res
   OpCoef c; c.alpha = make_double2(1, 0); c.gamma = make_double2(0, 0);
   c.eta = c.gamma; c.etat = c.gamma;
   cpx<R> ax, dg;
+  const R gr = (R)g, wr = (R)w;
   if (first) {
-    double mx[3], kx[3], my[3], ky[3];
-    q1_rows(ix, n, h, mx, kx); q1_rows(iy, n, h, my, ky);
-    const double d = mx[1] * my[1];
+    R mx[3], kx[3], my[3], ky[3];
+    q1_rows_r<R>(ix, n, h, mx, kx); q1_rows_r<R>(iy, n, h, my, ky);
+    const R d = mx[1] * my[1];
     const cpx<R> bi = b[i];
-    xn[i] = cmk<cpx<R>>(g * (double)bi.x / d, g * (double)bi.y / d);
+    cpx<R> v;
+    v.x = gr * bi.x / d;
+    v.y = gr * bi.y / d;
+    xn[i] = v;
     return;
   }
   q1_apply_node<R>(x + (size_t)f * np * np, n, ix, iy, h, c, nullptr, ax, dg);
   const cpx<R> bi = b[i], xi = x[i], pi = xp[i];
-  const double d = (double)dg.x;
-  xn[i] = cmk<cpx<R>>(w * ((double)xi.x - (double)pi.x + g * ((double)bi.x - (double)ax.x) / d) + (double)pi.x,
-                      w * ((double)xi.y - (double)pi.y + g * ((double)bi.y - (double)ax.y) / d) + (double)pi.y);
+  const R d = dg.x;
+  cpx<R> v;
+  v.x = wr * (xi.x - pi.x + gr * (bi.x - ax.x) / d) + pi.x;
+  v.y = wr * (xi.y - pi.y + gr * (bi.y - ax.y) / d) + pi.y;
+  xn[i] = v;
 }
 
 // ------------------------------------------------ pressure pin in / pin out

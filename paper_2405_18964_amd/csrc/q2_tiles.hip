@@ -34,8 +34,7 @@
 //
 // Arithmetic runs in the storage precision R of the grids (FP64, or FP32 for
 // the inner solves of the mixed-precision mode), so an FP32 sweep neither
-// converts its operands nor holds FP64 registers.  (The frequency-block matvec
-// k_q2_block_vel accumulates in FP64 in both modes.)
+// converts its operands nor holds FP64 registers.
 //
 // Work-group order is XCD-aware: ids are dealt round-robin to the 8 XCDs, so
 // id g is remapped to v = (g % 8) (G / 8) + g / 8 and every XCD gets a
@@ -654,21 +653,21 @@ namespace {
 // Raw stencil sums at a class-(PX, PY) node: pm = m'.m' x, pk = (k'.m' + m'.k') x
 // (so M x = h^2/900 pm, K x = pk/90) and the convection sum pc.
 template <int PX, int PY, bool CV, typename R>
-__device__ __forceinline__ void stencil_raw(const cpx<R>* base, const double* __restrict__ cn, double2& pm, double2& pk,
-                                            double2& pc) {
+__device__ __forceinline__ void stencil_raw(const cpx<R>* base, const double* __restrict__ cn, cpx<R>& pm, cpx<R>& pk,
+                                            cpx<R>& pc) {
   constexpr int nx = wlen(PX), ny = wlen(PY), lx0 = wlo(PX), ly0 = wlo(PY);
-  double smr[ny], smi[ny], skr[ny], ski[ny];
-  double cr = 0, ci = 0;
+  R smr[ny], smi[ny], skr[ny], ski[ny];
+  R cr = 0, ci = 0;
 #pragma unroll
   for (int iy = 0; iy < ny; ++iy) {
-    double vr[nx], vi[nx];
+    R vr[nx], vi[nx];
 #pragma unroll
     for (int ix = 0; ix < nx; ++ix) {
       const cpx<R> v = base[loff<PX, PY>(lx0 + ix, ly0 + iy)];
-      vr[ix] = (double)v.x;
-      vi[ix] = (double)v.y;
+      vr[ix] = v.x;
+      vi[ix] = v.y;
       if (CV) {
-        const double c = cn[(iy * nx + ix) * 64];
+        const R c = (R)cn[(iy * nx + ix) * 64];
         cr = fma(c, vr[ix], cr);
         ci = fma(c, vi[ix], ci);
       }
@@ -676,18 +675,23 @@ __device__ __forceinline__ void stencil_raw(const cpx<R>* base, const double* __
     Comb<PX>::run(vr, smr[iy], skr[iy]);
     Comb<PX>::run(vi, smi[iy], ski[iy]);
   }
-  double pmr, pmi, kmr, kmi, mkr, mki, unr, uni;
+  R pmr, pmi, kmr, kmi, mkr, mki, unr, uni;
   Comb<PY>::run(smr, pmr, kmr);
   Comb<PY>::run(smi, pmi, kmi);
   Comb<PY>::run(skr, mkr, unr);
   Comb<PY>::run(ski, mki, uni);
-  pm = make_double2(pmr, pmi);
-  pk = make_double2(mkr + kmr, mki + kmi);
-  pc = make_double2(cr, ci);
+  pm.x = pmr; pm.y = pmi;
+  pk.x = mkr + kmr; pk.y = mki + kmi;
+  pc.x = cr; pc.y = ci;
 }
 
-__device__ __forceinline__ double2 cmad(double2 acc, double2 c, double2 z) {     // acc + c z
-  return make_double2(acc.x + c.x * z.x - c.y * z.y, acc.y + c.x * z.y + c.y * z.x);
+template <typename R>
+__device__ __forceinline__ cpx<R> cmad(cpx<R> acc, double2 cd, cpx<R> z) {     // acc + c z
+  const R cx = (R)cd.x, cy = (R)cd.y;
+  cpx<R> r;
+  r.x = acc.x + cx * z.x - cy * z.y;
+  r.y = acc.y + cx * z.y + cy * z.x;
+  return r;
 }
 
 constexpr int kPP = kT / 2 + 2;       // side of the Q1 patch of a tile (26)
@@ -699,8 +703,8 @@ constexpr int kPP = kT / 2 + 2;       // side of the Q1 patch of a tile (26)
 template <int PX, int PY, bool CV, int PH, typename R>
 __device__ __forceinline__ void block_node(const cpx<R>* sx, const cpx<R>* sp, const cpx<R>* sm, int col, int la,
                                            int lb, int lane, int X0, int Y0, int n, int comp, double h,
-                                           const BlockCoef& k, const double* __restrict__ ctile, double2& r1,
-                                           double2& r2) {
+                                           const BlockCoef& k, const double* __restrict__ ctile, cpx<R>& r1,
+                                           cpx<R>& r2) {
   const int nq = 2 * n + 1;
   int lx, ly;
   node_of(PX, PY, col, la, lb, lx, ly);
@@ -708,20 +712,22 @@ __device__ __forceinline__ void block_node(const cpx<R>* sx, const cpx<R>* sp, c
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return;
   const cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
   const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
-  double2 pm, pk, pc;
+  cpx<R> pm, pk, pc;
   stencil_raw<PX, PY, CV, R>(base, cn, pm, pk, pc);
-  const double sM = h * h / 900.0, sK = 1.0 / 90.0;
-  const double2 Mz = make_double2(sM * pm.x, sM * pm.y), Kz = make_double2(sK * pk.x, sK * pk.y);
+  const R sM = (R)(h * h / 900.0), sK = (R)(1.0 / 90.0);
+  cpx<R> Mz, Kz;
+  Mz.x = sM * pm.x; Mz.y = sM * pm.y;
+  Kz.x = sK * pk.x; Kz.y = sK * pk.y;
   if (PH == 0) {
-    r1 = cmad(r1, k.a11, Mz);
-    r2 = cmad(cmad(r2, k.a21, Mz), k.b21, Kz);
-    if (CV) r2 = cmad(r2, k.e21, pc);
+    r1 = cmad<R>(r1, k.a11, Mz);
+    r2 = cmad<R>(cmad<R>(r2, k.a21, Mz), k.b21, Kz);
+    if (CV) r2 = cmad<R>(r2, k.e21, pc);
     // B^T p (row 2) and B^T mu (row 1) for this velocity component
     double mxx[3], gxx[3], mxy[3], gxy[3];
     mixed_cols(gx, n, h, mxx, gxx);
     mixed_cols(gy, n, h, mxy, gxy);
     const int kx0 = (gx >> 1) - 1, ky0 = (gy >> 1) - 1;
-    double bpr = 0, bpi = 0, bmr = 0, bmi = 0;
+    R bpr = 0, bpi = 0, bmr = 0, bmi = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int kyy = ky0 + a;
@@ -731,27 +737,28 @@ __device__ __forceinline__ void block_node(const cpx<R>* sx, const cpx<R>* sp, c
       for (int c = 0; c < 3; ++c) {
         const int kxx = kx0 + c;
         if (kxx < 0 || kxx > n) continue;
-        const double wgt = wy * (comp == 0 ? gxx[c] : mxx[c]);
+        const R wgt = (R)(wy * (comp == 0 ? gxx[c] : mxx[c]));
         const int pi = (kyy - (Y0 / 2 - 1)) * kPP + (kxx - (X0 / 2 - 1));
         const cpx<R> pv = sp[pi], mv = sm[pi];
-        bpr -= wgt * (double)pv.x; bpi -= wgt * (double)pv.y;
-        bmr -= wgt * (double)mv.x; bmi -= wgt * (double)mv.y;
+        bpr -= wgt * pv.x; bpi -= wgt * pv.y;
+        bmr -= wgt * mv.x; bmi -= wgt * mv.y;
       }
     }
-    r1.x += k.s * bmr; r1.y += k.s * bmi;
-    r2.x += k.s * bpr; r2.y += k.s * bpi;
+    const R ks = (R)k.s;
+    r1.x += ks * bmr; r1.y += ks * bmi;
+    r2.x += ks * bpr; r2.y += ks * bpi;
   } else {
-    r1 = cmad(cmad(r1, k.a12, Mz), k.b12, Kz);
-    if (CV) r1 = cmad(r1, k.e12, pc);
-    r2 = cmad(r2, k.a22, Mz);
+    r1 = cmad<R>(cmad<R>(r1, k.a12, Mz), k.b12, Kz);
+    if (CV) r1 = cmad<R>(r1, k.e12, pc);
+    r2 = cmad<R>(r2, k.a22, Mz);
   }
 }
 
 template <bool CV, int PH, typename R>
 __device__ __forceinline__ void block_phase(const cpx<R>* sx, const cpx<R>* sp, const cpx<R>* sm, int w, int rot,
                                             int la, int lb, int lane, int X0, int Y0, int n, int comp, double h,
-                                            const BlockCoef& k, const double* __restrict__ ctile, double2* r1,
-                                            double2* r2) {
+                                            const BlockCoef& k, const double* __restrict__ ctile, cpx<R>* r1,
+                                            cpx<R>* r2) {
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
     switch (class_of(w, c, rot)) {
@@ -826,9 +833,9 @@ __global__ __launch_bounds__(256, 2) void k_q2_block_vel(cpx<R>* __restrict__ yV
   load_tile<R>(sx, v, nq, X0, Y0);
   const BlockCoef k = bc[j];
   const size_t toff = (size_t)tile * 9 * 64 * 64;
-  double2 r1[9], r2[9];
+  cpx<R> r1[9], r2[9];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) { r1[c] = make_double2(0, 0); r2[c] = r1[c]; }
+  for (int c = 0; c < 9; ++c) { r1[c] = cmk<cpx<R>>(0, 0); r2[c] = r1[c]; }
   __syncthreads();
   block_phase<CV, 0, R>(sx, sp, sm, w, rot, la, lb, lane, X0, Y0, n, comp, h, k, CV ? tcN + toff : nullptr, r1, r2);
   __syncthreads();
@@ -837,12 +844,12 @@ __global__ __launch_bounds__(256, 2) void k_q2_block_vel(cpx<R>* __restrict__ yV
   block_phase<CV, 1, R>(sx, sp, sm, w, rot, la, lb, lane, X0, Y0, n, comp, h, k, CV ? tcNT + toff : nullptr, r1, r2);
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 9; ++c) sx[stage_at(w, c, rot, la, lb)] = cmk<cpx<R>>(r1[c].x, r1[c].y);
+  for (int c = 0; c < 9; ++c) sx[stage_at(w, c, rot, la, lb)] = r1[c];
   __syncthreads();
   store_staged<R>(yV + ((size_t)(j * 2 + 0) * 2 + comp) * nq2, sx, nq, X0, Y0);
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 9; ++c) sx[stage_at(w, c, rot, la, lb)] = cmk<cpx<R>>(r2[c].x, r2[c].y);
+  for (int c = 0; c < 9; ++c) sx[stage_at(w, c, rot, la, lb)] = r2[c];
   __syncthreads();
   store_staged<R>(yV + ((size_t)(j * 2 + 1) * 2 + comp) * nq2, sx, nq, X0, Y0);
 }
