@@ -566,9 +566,10 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
   const TCoef<R> t = tcoef<R>(coef[f / fpc], h);
   const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
   // b of this thread's column rows (thread t < 5 kT: column t % kT, rows t / kT + 5 k);
-  // in FP64 it is loaded before the stencil phase so its latency overlaps it (in
-  // FP32 the registers would cost a wave of occupancy)
-  constexpr bool kPre = sizeof(R) == 8;
+  // in FP64 without convection it is loaded before the stencil phase so its
+  // latency overlaps it (in FP32, or beside the convection table reads, the
+  // registers cost more than the overlap gains)
+  constexpr bool kPre = sizeof(R) == 8 && !CV;
   const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT;
   const int gx = X0 + lx;
   const bool xin = threadIdx.x < 5 * kT && gx >= 1 && gx <= nq - 2;
