@@ -26,7 +26,9 @@ precond    the Stokes preconditioners of section 3.2-3.4 (Algorithms 1 and 2)
            and the Oseen preconditioner of section 4 (Algorithm 3).
 krylov     right-preconditioned GMRES and flexible GMRES.
 
-Parity status: every function is pinned by a ``-m "not gpu"`` test except the
-multigrid V-cycle beyond the Galerkin-coarse-operator identity (its convergence
-factor has no closed form): "parity unpinned" for the V-cycle contraction rate.
+Parity status: every function is pinned by a ``-m "not gpu"`` test.  The
+multigrid V-cycle is pinned to the textbook two-/three-grid error propagation
+operator assembled from dense smoother, transfer and coarse matrices; its
+contraction rate is a property of that operator (no closed form) and is only
+checked for being a contraction.
 """

@@ -266,8 +266,9 @@ def test_prolongation_reproduces_polynomials():
 
 def test_multigrid_converges_and_is_symmetric():
     """A V-cycle is a contraction on W_j and on the unconstrained K_N (modulo
-    constants; multigrid convergence rate itself: parity unpinned), exact on
-    the coarsest grid, and symmetric; the pinned K_p^{-1} comes out through
+    constants; the rate has no closed form, the cycle operator itself is pinned
+    by test_vcycle_equals_error_propagation_formula), exact on the coarsest
+    grid, and symmetric; the pinned K_p^{-1} comes out through
     R L K_N^+ L^T R^T."""
     N = 8
     lv = Levels(N)
@@ -295,6 +296,60 @@ def test_multigrid_converges_and_is_symmetric():
     coarse = ScalarMG(Levels(2), "q2", 1.0, 1.0)
     b = rng.standard_normal(coarse.A[0].shape[0])
     assert np.allclose(coarse.A[0] @ coarse.solve(b, 1), b, atol=1e-13)
+
+
+def _vcycle_error_operator(mg, l):
+    """Textbook error propagation of one V(1,1) cycle from level l, built from
+    dense matrices: E_l = S_b (I - P (I - E_{l+1}) C_{l+1} P^T A_l) S_f, where
+    S_f / S_b are the error operators of the forward / backward sweeps (their
+    columns are sweeps of unit vectors with b = 0), C the coarse solution
+    operator (dense inverse; Q1: node 0 held at zero) and E = 0 on the
+    coarsest level."""
+    A = mg.A[l].toarray()
+    n = A.shape[0]
+    Id = np.eye(n)
+    Sf = np.column_stack([mg.sor[l].forward(np.zeros(n, complex), Id[:, k].astype(complex)) for k in range(n)])
+    Sb = np.column_stack([mg.sor[l].backward(np.zeros(n, complex), Id[:, k].astype(complex)) for k in range(n)])
+    P = mg.lv.prolong(mg.fam, l).toarray()
+    Ac = mg.A[l + 1].toarray()
+    nc = Ac.shape[0]
+    if l + 1 == len(mg.A) - 1:
+        C = np.zeros((nc, nc), complex)
+        if mg.pin_coarse:
+            C[1:, 1:] = np.linalg.inv(Ac[1:, 1:])
+        else:
+            C = np.linalg.inv(Ac)
+        coarse = C
+    else:
+        Ec = _vcycle_error_operator(mg, l + 1)
+        coarse = (np.eye(nc) - Ec) @ np.linalg.inv(Ac)
+    return Sb @ (Id - P @ coarse @ P.T @ A) @ Sf
+
+
+@pytest.mark.parametrize("N,fam,conv", [(4, "q2", False), (4, "q2", True), (8, "q2", True), (4, "q1", False),
+                                        (8, "q1", True)])
+def test_vcycle_equals_error_propagation_formula(N, fam, conv):
+    """V-cycle operator pinned to the two-/three-grid error propagation formula:
+    one cycle from x = 0 gives (I - E) A^{-1} b and two cycles (I - E^2) A^{-1} b,
+    with E composed from dense smoother, transfer and coarse operators.  A
+    dropped coarse correction, a restriction by P instead of P^T, a sign error
+    in the residual or swapped sweep directions each break the identity."""
+    wind = W.wind_nodal(N) if conv else None
+    lv = Levels(N, wind)
+    mg = ScalarMG(lv, fam, 0.9 + 0.4j, 0.07 - 0.02j, eta=(0.3 + 0.1j) if conv else 0.0,
+                  eta_t=(0.05 - 0.2j) if conv else 0.0)
+    A = mg.A[0].toarray()
+    n = A.shape[0]
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    if fam == "q1":
+        b -= b.mean()                                       # consistent for the singular-free shifted operator too
+    E = _vcycle_error_operator(mg, 0)
+    xe = np.linalg.solve(A, b)
+    for cycles, Ek in ((1, E), (2, E @ E)):
+        x = mg.solve(b, cycles)
+        ref = xe - Ek @ xe
+        assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(xe)
 
 
 def test_linear_stokes_preconditioner_symmetric(stokes4):
