@@ -8,6 +8,19 @@ unknowns, inputs resident in HBM before timing starts).
 
 Prints one JSON line (see the keys below).  ``--gpus`` above 1 is refused:
 this build runs on one GPU.
+
+``--config 4`` measures the batched form instead: the 64-problem mix of
+``workloads.batch_mix`` (N in {32, 64, 128}, nt in {32, ..., 256}, log-uniform
+beta, nu in {1, 1/50, 1/100}, Stokes and Oseen) solved with FP32 inner /
+FP64 outer solves by the concurrent runner of ``paper_2405_18964_amd.batch``;
+one step = one pass over the whole mix, value = aggregate solves/s.
+
+``--config 5`` measures the served form: the Poisson request stream of
+``workloads.serve_stream`` (``--requests`` requests, N capped by
+``--serve-max-n``).  A closed-loop pass (all requests at once) measures the
+capacity C; the timed open-loop pass releases request k at its arrival time
+scaled to the rate rho * C (``--rho``) and reports p50/p99 arrival-to-
+completion latency beside solves/s.
 """
 from __future__ import annotations
 
@@ -48,7 +61,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, help="single-problem workload index (1, 2)")
+    ap.add_argument("--config", type=int, default=2,
+                    help="workload: 1, 2 (single Stokes problem) or 4 (batched 64-problem mix)")
+    ap.add_argument("--batch-count", type=int, default=64, help="problems of the batched mix (--config 4)")
+    ap.add_argument("--workers", type=int, default=4, help="concurrent problems on the device (--config 4)")
+    ap.add_argument("--requests", type=int, default=32, help="requests of the served stream (--config 5)")
+    ap.add_argument("--rho", type=float, default=0.8, help="arrival rate / measured capacity (--config 5)")
+    ap.add_argument("--serve-max-n", type=int, default=128, help="largest grid of the served stream (--config 5)")
+    ap.add_argument("--compare", action="store_true",
+                    help="--config 4: also solve the mix one problem at a time (FP32-inner and FP64)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--inner", choices=["gmres", "linear"], default="gmres")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,6 +163,10 @@ def main():
     import paper_2405_18964_amd as P
     import workloads as W
 
+    if args.config == 4:
+        return bench_batch(args)
+    if args.config == 5:
+        return bench_serve(args)
     w = W.config(args.config)
     prec = P.PREC_FP64 if args.precision == "fp64" else P.PREC_FP32_INNER
     inner = P.INNER_GMRES if args.inner == "gmres" else P.INNER_LINEAR
@@ -263,6 +288,124 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, outer, inner_mean)
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Batched form: the 64-problem mix through the concurrent runner."""
+    import torch
+
+    import paper_2405_18964_amd as P
+    import workloads as W
+    from paper_2405_18964_amd.batch import job_bytes, run
+
+    mix = W.batch_mix(args.batch_count)
+    jobs = [{"N": w.N, "nt": w.nt, "T": w.T, "nu": w.nu, "beta": w.beta, "flow": w.flow,
+             "wind": W.wind_nodal(w.N) if w.flow == W.OSEEN else None, "vd": W.desired_state(w)} for w in mix]
+    opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60)
+    print(f"[bench] batched mix of {len(jobs)} problems, {sum(w.n_all for w in mix) / 1e9:.2f}e9 unknowns, "
+          f"{sum(job_bytes(j, **opts) for j in jobs) / 1e9:.0f} GB of job memory", file=sys.stderr, flush=True)
+    small = sorted(range(len(jobs)), key=lambda k: job_bytes(jobs[k], **opts))[:args.workers]
+    for i in range(args.warmup):                           # module loading, allocator warm-up
+        run([jobs[k] for k in small], workers=args.workers, **opts)
+    walls, outs = [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = run(jobs, workers=args.workers, checksum=True, **opts)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        outs.append(out)
+        print(f"[bench] step {i}: {walls[-1]:.2f} s, converged {sum(r['converged'] for r in out)}/{len(out)}",
+              file=sys.stderr, flush=True)
+    out = outs[-1]
+    wall = sum(walls)
+    lat = sorted(r["end"] - r["start"] for r in out)
+    res = {
+        "metric": "KKT solves/sec to 1e-8 residual (batched mix, aggregate); p50/p99 per-solve latency",
+        "value": len(jobs) * args.steps / wall,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer",
+        "data": "synthetic",
+        "config": {"workload": f"{len(jobs)} independent Stokes/Oseen control problems (N in {{32,64,128}}, "
+                               "nt in {32,...,256}, log-uniform beta in [1e-6,1e-2], nu in {1,1/50,1/100}), "
+                               f"{args.workers} concurrent on one GPU",
+                   "solver": "FGMRES(10) + block-circulant preconditioner with inner GMRES per frequency"},
+        "converged": int(sum(r["converged"] for r in out)),
+        "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]},
+    }
+    if args.compare:
+        for name, prec in (("sequential_fp32_inner", P.PREC_FP32_INNER), ("sequential_fp64", P.PREC_FP64)):
+            o = dict(opts, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            seq = run(jobs, workers=1, checksum=True, **o)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            res[name] = {"solves_per_s": len(jobs) / t, "seconds": t,
+                         "converged": int(sum(r["converged"] for r in seq))}
+            if prec == P.PREC_FP32_INNER:
+                res["identical_to_sequential"] = int(sum(a["digest"] == b["digest"] for a, b in zip(seq, out)))
+            print(f"[bench] {name}: {t:.2f} s", file=sys.stderr, flush=True)
+    print(json.dumps(res), flush=True)
+
+
+def bench_serve(args):
+    """Served form: Poisson arrivals at rho times the measured capacity."""
+    import torch
+
+    import paper_2405_18964_amd as P
+    import workloads as W
+    from paper_2405_18964_amd.batch import run
+
+    stream = W.serve_stream(args.requests, max_N=args.serve_max_n)
+
+    def jobs_at(rate):
+        return [{"N": w.N, "nt": w.nt, "T": w.T, "nu": w.nu, "beta": w.beta, "flow": w.flow,
+                 "wind": W.wind_nodal(w.N) if w.flow == W.OSEEN else None, "vd": W.desired_state(w),
+                 "arrival": (a / rate if rate else 0.0)} for w, a in stream]
+    opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    closed = run(jobs_at(None), workers=args.workers, checksum=True, **opts)
+    cap = len(stream) / (time.perf_counter() - t0)
+    rate = args.rho * cap
+    print(f"[bench] closed loop: capacity {cap:.3f} solves/s; open loop at {rate:.3f} requests/s",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    out = run(jobs_at(rate), workers=args.workers, checksum=True, **opts)
+    wall = time.perf_counter() - t0
+    lat = sorted(r["end"] - r["arrival"] for r in out)
+    same = int(sum(a["digest"] == b["digest"] for a, b in zip(closed, out)))
+    res = {
+        "metric": "served KKT solves/sec to 1e-8 residual; p50/p99 arrival-to-completion latency",
+        "value": len(stream) / wall,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": 1e3 * wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer",
+        "data": "synthetic",
+        "config": {"workload": f"{len(stream)} Poisson-arrival Stokes/Oseen control requests (N in 32..."
+                               f"{args.serve_max_n}, nt in 32...256), rate {args.rho} x measured capacity, "
+                               f"{args.workers} concurrent on one GPU"},
+        "capacity_solves_per_s": cap,
+        "arrival_rate_per_s": rate,
+        "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]},
+        "converged": int(sum(r["converged"] for r in out)),
+        "identical_to_closed_loop": same,
+    }
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

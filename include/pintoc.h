@@ -156,6 +156,24 @@ int pintoc_precond_apply(pintoc_problem* p, const double* r, double* z, void* st
 int pintoc_solve(pintoc_problem* p, const double* b, double* x, pintoc_solve_stats* st,
                  void* stream);
 
+/* Solve n independent problems concurrently (batched solve of several control
+ * problems, the paper's per-problem solve of section 5 applied to a set of
+ * problems at once).  Problem k runs pintoc_solve(p[k], b[k], x[k], &st[k],
+ * streams[k]) on its own host thread, so the kernels of different problems
+ * overlap on the device.
+ *   p, b, x, streams: host arrays of n entries; the handles must be distinct
+ *     and bound, the streams distinct and non-NULL (streams of the same device);
+ *     b[k], x[k] are device vectors of problem k as for pintoc_solve.
+ *   st: host array of n stats records, or NULL.
+ * Every kernel and reduction of a solve is deterministic and depends only on
+ * its own problem, so each x[k] equals the result of a separate pintoc_solve
+ * call bit for bit.  Returns PINTOC_OK when all converged, PINTOC_NOT_CONVERGED
+ * when some did not (see st), or the first negative code in problem order
+ * (its message names the problem); n = 0 is a no-op.  Invalid arguments are
+ * rejected before any work starts.  Synchronises every stream before return. */
+int pintoc_solve_batch(pintoc_problem* const* p, const double* const* b, double* const* x,
+                       pintoc_solve_stats* st, void* const* streams, int32_t n);
+
 /* Release the handle (does not free the bound workspace, which the caller owns). */
 void pintoc_problem_destroy(pintoc_problem* p);
 

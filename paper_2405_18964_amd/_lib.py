@@ -54,6 +54,8 @@ SIGNATURES = {
     "pintoc_kkt_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pintoc_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pintoc_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
+    "pintoc_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                      C.POINTER(SolveStats), C.POINTER(C.c_void_p), C.c_int32]),
     "pintoc_problem_destroy": (None, [C.c_void_p]),
     "pintoc_last_error": (C.c_char_p, []),
     "pintoc_vector_length": (C.c_int64, [C.c_void_p]),
@@ -206,3 +208,35 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch(problems, bs, xs=None):
+    """Solve several bound problems concurrently (``pintoc_solve_batch``):
+    problem k on its own HIP stream, driven by its own host thread inside the
+    library.  ``bs``/``xs`` are the problems' canonical vectors (``xs[k]`` is
+    the initial guess and receives the solution; zeros when None).  Returns a
+    list of (x, stats dict, converged flag).  Each result equals that of a
+    separate :meth:`Problem.solve` call."""
+    n = len(problems)
+    if len(bs) != n or (xs is not None and len(xs) != n):
+        raise ValueError("one right-hand side (and initial guess) per problem")
+    if n == 0:
+        return []
+    torch = problems[0]._torch
+    xs = [p.empty() for p in problems] if xs is None else list(xs)
+    cur = torch.cuda.current_stream(problems[0].device)
+    streams = [torch.cuda.Stream(device=p.device) for p in problems]    # default priority
+    for s in streams:
+        s.wait_stream(cur)                      # inputs were produced on the current stream
+    for k in range(n):
+        if bs[k].data_ptr() == xs[k].data_ptr():
+            raise ValueError("b and x alias")
+    P = (C.c_void_p * n)(*[p._h.value for p in problems])
+    B = (C.c_void_p * n)(*[p._vec(b, "b").value for p, b in zip(problems, bs)])
+    X = (C.c_void_p * n)(*[p._vec(x, "x").value for p, x in zip(problems, xs)])
+    S = (C.c_void_p * n)(*[s.cuda_stream for s in streams])
+    st = (SolveStats * n)()
+    _check(library().pintoc_solve_batch(P, B, X, st, S, n), "pintoc_solve_batch")
+    for s in streams:
+        cur.wait_stream(s)
+    return [(xs[k], st[k].as_dict(), st[k].converged == 1) for k in range(n)]

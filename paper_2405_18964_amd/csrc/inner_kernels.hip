@@ -139,10 +139,12 @@ __global__ __launch_bounds__(64 * kLWaves) void k_fdot_lag(const cpx<R>* __restr
   bool any = mine;
 #pragma unroll
   for (int q = 0; q < kLW; ++q) any |= i0 + wv + nw * q < i1;
-  double sr[kLW], si[kLW], tr[kLW], ti[kLW];
+  // per-lane partial sums in the storage precision (a lane adds at most
+  // kFChunk / 64 products), the wave and chunk reductions in FP64
+  R sr[kLW], si[kLW], tr[kLW], ti[kLW];
 #pragma unroll
   for (int q = 0; q < kLW; ++q) { sr[q] = 0; si[q] = 0; tr[q] = 0; ti[q] = 0; }
-  double nu = 0, mur = 0, mui = 0;
+  R nu = 0, mur = 0, mui = 0;
   const int lo = cc * kFChunk, hi = min(lo + kFChunk, seg);
   for (int e = lo + kU * lane; any && e < hi; e += 64 * kU) {
     Pack<R, kU> u, w;
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(64 * kLWaves) void k_fdot_lag(const cpx<R>* __restr
     }
 #pragma unroll
     for (int h = 0; h < kU; ++h) {
-      const double ur = (double)u.v[h].x, ui = (double)u.v[h].y, wr = (double)w.v[h].x, wi = (double)w.v[h].y;
+      const R ur = u.v[h].x, ui = u.v[h].y, wr = w.v[h].x, wi = w.v[h].y;
       if (mine) {
         nu += ur * ur + ui * ui;
         mur += ur * wr + ui * wi;              // conj(u) w
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(64 * kLWaves) void k_fdot_lag(const cpx<R>* __restr
       }
 #pragma unroll
       for (int q = 0; q < kLW; ++q) {
-        const double vr = (double)vv[q].v[h].x, vi = (double)vv[q].v[h].y;
+        const R vr = vv[q].v[h].x, vi = vv[q].v[h].y;
         sr[q] += vr * ur + vi * ui;  si[q] += vr * ui - vi * ur;      // conj(v) u
         tr[q] += vr * wr + vi * wi;  ti[q] += vr * wi - vi * wr;      // conj(v) w
       }

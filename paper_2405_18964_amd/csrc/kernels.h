@@ -34,6 +34,12 @@ template <typename R>
 void launch_q1_restrict(hipStream_t s, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk);
 template <typename R>
 void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb, Mask mk);
+// the rest of a Q2 V-cycle (no convection) from level n0 <= kQ2SmallN down to
+// N = 2 in one launch, one work-group per grid; x0: initial iterate or null (zero)
+constexpr int kQ2SmallN = 16;
+template <typename R>
+void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
+                            int fpc, const double2* inv, int nb, Mask mk);
 template <typename R>
 void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
                  double h, double g, double w, int first, int nb, Mask mk);

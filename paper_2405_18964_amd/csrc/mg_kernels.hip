@@ -360,6 +360,233 @@ __global__ __launch_bounds__(256) void k_q1_coarse_solve(cpx<R>* __restrict__ x,
   x[(size_t)f * 9 + r] = cmk<cpx<R>>(sr, si);
 }
 
+// ------------------------------------------------ small-grid V-cycles
+// The rest of a Q2 V(1,1) cycle from level n0 <= kSmallN down to the N = 2
+// grid, for operators without convection, in one work-group per grid with
+// every level in LDS.  A 48-node tile covers these grids, so the tiled
+// smoother is plain multicolour Gauss-Seidel (colour 3 (gy % 3) + gx % 3,
+// forward before and backward after the coarse correction); residual,
+// restriction P^T, exact coarsest solve (FP64 accumulation, as in
+// k_q2_coarse_solve) and prolongation P follow the per-level kernels.
+// x0 == nullptr: the cycle starts from zero on level n0; x0 may equal xg
+// (every grid is read into LDS before it is written back).
+constexpr int kSmallN = kQ2SmallN;
+
+namespace {
+constexpr int sq(int v) { return v * v; }
+constexpr int kSmallEntries = sq(2 * kSmallN + 1) + sq(kSmallN + 1) + sq(kSmallN / 2 + 1) + sq(kSmallN / 4 + 1);
+
+// m' . v and k' . v along one direction for node parity P (offsets -2..2 or -1..1)
+template <typename R>
+__device__ __forceinline__ void small_comb(int P, const R* v, R& m, R& k) {
+  if (P == 0) {
+    const R s04 = v[0] + v[4], s13 = v[1] + v[3];
+    m = R(8) * v[2] + R(2) * s13 - s04;
+    k = R(14) * v[2] - R(8) * s13 + s04;
+  } else {
+    const R s02 = v[1] + v[3];
+    m = R(16) * v[2] + R(2) * s02;
+    k = R(16) * v[2] - R(8) * s02;
+  }
+}
+
+// (A x)(gx, gy) and the diagonal for alpha M + gamma K on a padded grid in LDS
+template <typename R>
+__device__ __forceinline__ void small_apply(const cpx<R>* x, int nq, int gx, int gy, R ar, R ai, R gr, R gi,
+                                            cpx<R>& ax, cpx<R>& dg) {
+  const int px = gx & 1, py = gy & 1;
+  R smr[5], smi[5], skr[5], ski[5];
+#pragma unroll
+  for (int dy = 0; dy < 5; ++dy) {
+    const bool use = py == 0 || (dy >= 1 && dy <= 3);
+    R vr[5], vi[5];
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) {
+      const bool u = use && (px == 0 || (dx >= 1 && dx <= 3));
+      const cpx<R> v = u ? x[(gy + dy - 2) * nq + gx + dx - 2] : cmk<cpx<R>>(0, 0);
+      vr[dx] = v.x;
+      vi[dx] = v.y;
+    }
+    small_comb<R>(px, vr, smr[dy], skr[dy]);
+    small_comb<R>(px, vi, smi[dy], ski[dy]);
+  }
+  R pmr, pmi, kmr, kmi, mkr, mki, unr, uni;
+  small_comb<R>(py, smr, pmr, kmr);
+  small_comb<R>(py, smi, pmi, kmi);
+  small_comb<R>(py, skr, mkr, unr);
+  small_comb<R>(py, ski, mki, uni);
+  const R pkr = mkr + kmr, pki = mki + kmi;
+  ax.x = ar * pmr - ai * pmi + gr * pkr - gi * pki;
+  ax.y = ar * pmi + ai * pmr + gr * pki + gi * pkr;
+  const R md = (px ? R(16) : R(8)) * (py ? R(16) : R(8));
+  const R kd = (px ? R(16) : R(14)) * (py ? R(16) : R(8)) + (px ? R(16) : R(8)) * (py ? R(16) : R(14));
+  dg.x = ar * md + gr * kd;
+  dg.y = ai * md + gi * kd;
+}
+
+// one Gauss-Seidel sweep (forward or backward colour order) of level grid x
+template <typename R>
+__device__ __forceinline__ void small_sweep(cpx<R>* x, const cpx<R>* b, int n, const OpCoef& c, bool forward) {
+  const int nq = 2 * n + 1;
+  const double h = 1.0 / n, sm = h * h / 900.0;
+  const R ar = (R)(c.alpha.x * sm), ai = (R)(c.alpha.y * sm), gr = (R)(c.gamma.x / 90.0), gi = (R)(c.gamma.y / 90.0);
+  const int per = (nq + 2) / 3;                       // nodes per colour and direction (upper bound)
+  for (int k = 0; k < 9; ++k) {
+    const int col = forward ? k : 8 - k, cx = col % 3, cy = col / 3;
+    for (int e = threadIdx.x; e < per * per; e += blockDim.x) {
+      const int gx = cx + 3 * (e % per), gy = cy + 3 * (e / per);
+      if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) continue;
+      cpx<R> ax, dg;
+      small_apply<R>(x, nq, gx, gy, ar, ai, gr, gi, ax, dg);
+      const cpx<R> bv = b[gy * nq + gx];
+      const R er = bv.x - ax.x, ei = bv.y - ax.y, inv = R(1) / (dg.x * dg.x + dg.y * dg.y);
+      cpx<R>& xs = x[gy * nq + gx];
+      cpx<R> nv;
+      nv.x = xs.x + (er * dg.x + ei * dg.y) * inv;
+      nv.y = xs.y + (ei * dg.x - er * dg.y) * inv;
+      xs = nv;
+    }
+    __syncthreads();
+  }
+}
+
+// 1-D weight of fine offset d (-3..3) in the restriction to a coarse node of parity P
+template <typename R>
+__device__ __forceinline__ R small_rw(int P, int d) {
+  if (P) return d == 0 ? R(1) : ((d == 1 || d == -1) ? R(0.75) : R(0));
+  return d == 0 ? R(1) : ((d == 1 || d == -1) ? R(0.375) : ((d == 3 || d == -3) ? R(-0.125) : R(0)));
+}
+
+// 1-D prolongation weight of coarse node 2e + q for fine node 4e + r
+template <typename R>
+__device__ __forceinline__ R small_pw(int r, int q) {
+  if (r == 0) return q == 0 ? R(1) : R(0);
+  if (r == 2) return q == 1 ? R(1) : R(0);
+  if (r == 1) return q == 0 ? R(0.375) : (q == 1 ? R(0.75) : R(-0.125));
+  return q == 0 ? R(-0.125) : (q == 1 ? R(0.75) : R(0.375));
+}
+}  // namespace
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_q2_small_vcycle(cpx<R>* xg, const cpx<R>* x0,
+                                                         const cpx<R>* __restrict__ bg, int n0,
+                                                         const OpCoef* __restrict__ coef, int fpc,
+                                                         const double2* __restrict__ inv, int nb, Mask mk) {
+  // x of every level and b of the coarser levels in LDS (the top level's b is
+  // read from memory: 47.5 KB in FP64, three work-groups per CU)
+  constexpr int kB = kSmallEntries - sq(2 * kSmallN + 1);
+  __shared__ cpx<R> xs[kSmallEntries], bsc[kB], rs[sq(2 * kSmallN + 1)];
+  const int f = blockIdx.x;
+  if (f >= nb || mk.off(f)) return;
+  const OpCoef c = coef[f / fpc];
+  int lev = 0, off[8], nn[8];
+  for (int n = n0, o = 0; n >= 2; n >>= 1, ++lev) { off[lev] = o; nn[lev] = n; o += sq(2 * n + 1); }
+  const int nq0 = 2 * n0 + 1;
+  const size_t g0 = (size_t)f * nq0 * nq0;
+  const cpx<R>* b0 = bg + g0;
+  // b of level l: level 0 in memory, level l >= 1 in LDS at off[l] - off[1]
+  auto blev = [&](int l) -> const cpx<R>* { return l == 0 ? b0 : bsc + (off[l] - off[1]); };
+  for (int e = threadIdx.x; e < nq0 * nq0; e += blockDim.x) xs[e] = x0 ? x0[g0 + e] : cmk<cpx<R>>(0, 0);
+  for (int e = nq0 * nq0 + threadIdx.x; e < off[lev - 1] + 25; e += blockDim.x) xs[e] = cmk<cpx<R>>(0, 0);
+  __syncthreads();
+  // down: pre-smoothing, residual, restriction
+  for (int l = 0; l + 1 < lev; ++l) {
+    const int n = nn[l], nq = 2 * n + 1, nqc = n + 1;
+    cpx<R>* x = xs + off[l];
+    const cpx<R>* b = blev(l);
+    small_sweep<R>(x, b, n, c, true);
+    const double h = 1.0 / n, sm = h * h / 900.0;
+    const R ar = (R)(c.alpha.x * sm), ai = (R)(c.alpha.y * sm), gr = (R)(c.gamma.x / 90.0), gi = (R)(c.gamma.y / 90.0);
+    for (int e = threadIdx.x; e < nq * nq; e += blockDim.x) {
+      const int gx = e % nq, gy = e / nq;
+      cpx<R> r = cmk<cpx<R>>(0, 0);
+      if (gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2) {
+        cpx<R> ax, dg;
+        small_apply<R>(x, nq, gx, gy, ar, ai, gr, gi, ax, dg);
+        r.x = b[e].x - ax.x;
+        r.y = b[e].y - ax.y;
+      }
+      rs[e] = r;
+    }
+    __syncthreads();
+    cpx<R>* bc = bsc + (off[l + 1] - off[1]);
+    for (int e = threadIdx.x; e < nqc * nqc; e += blockDim.x) {
+      const int I = e % nqc, J = e / nqc;
+      cpx<R> v = cmk<cpx<R>>(0, 0);
+      if (I >= 1 && I <= nqc - 2 && J >= 1 && J <= nqc - 2) {
+        for (int dy = -3; dy <= 3; ++dy) {
+          const R wy = small_rw<R>(J & 1, dy);
+          if (wy == R(0)) continue;
+          R rr = 0, ri = 0;
+          for (int dx = -3; dx <= 3; ++dx) {
+            const R wx = small_rw<R>(I & 1, dx);
+            if (wx == R(0)) continue;
+            const cpx<R> rv = rs[(2 * J + dy) * nq + 2 * I + dx];
+            rr += wx * rv.x;
+            ri += wx * rv.y;
+          }
+          v.x += wy * rr;
+          v.y += wy * ri;
+        }
+      }
+      bc[e] = v;
+    }
+    __syncthreads();
+  }
+  // coarsest grid (N = 2): 9 interior unknowns of the padded 5 x 5 grid
+  {
+    const cpx<R>* b = blev(lev - 1);
+    cpx<R>* x = xs + off[lev - 1];
+    const double2* A = inv + (size_t)(f / fpc) * 81;
+    if (threadIdx.x < 9) {
+      const int r = threadIdx.x;
+      double sr = 0, si = 0;
+      for (int q = 0; q < 9; ++q) {
+        const cpx<R> v = b[(1 + q / 3) * 5 + 1 + q % 3];
+        const double2 a = A[r * 9 + q];
+        sr += a.x * (double)v.x - a.y * (double)v.y;
+        si += a.x * (double)v.y + a.y * (double)v.x;
+      }
+      x[(1 + r / 3) * 5 + 1 + r % 3] = cmk<cpx<R>>(sr, si);
+    }
+    __syncthreads();
+  }
+  // up: prolongation of the coarse correction, post-smoothing
+  for (int l = lev - 2; l >= 0; --l) {
+    const int n = nn[l], nq = 2 * n + 1, nqc = n + 1;
+    cpx<R>* x = xs + off[l];
+    const cpx<R>* ec = xs + off[l + 1];
+    for (int e = threadIdx.x; e < nq * nq; e += blockDim.x) {
+      const int gx = e % nq, gy = e / nq;
+      if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) continue;
+      const int ex = gx >> 2, rx = gx & 3, ey = gy >> 2, ry = gy & 3;
+      R pr = 0, pi = 0;
+      for (int qy = 0; qy < 3; ++qy) {
+        const R wy = small_pw<R>(ry, qy);
+        if (wy == R(0)) continue;
+        for (int qx = 0; qx < 3; ++qx) {
+          const R wx = small_pw<R>(rx, qx);
+          if (wx == R(0)) continue;
+          const cpx<R> v = ec[(2 * ey + qy) * nqc + 2 * ex + qx];
+          pr += wy * (wx * v.x);
+          pi += wy * (wx * v.y);
+        }
+      }
+      x[e].x += pr;
+      x[e].y += pi;
+    }
+    __syncthreads();
+    small_sweep<R>(x, blev(l), n, c, false);
+  }
+  for (int e = threadIdx.x; e < nq0 * nq0; e += blockDim.x) xg[g0 + e] = xs[e];
+}
+
+template <typename R>
+void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
+                            int fpc, const double2* inv, int nb, Mask mk) {
+  hipLaunchKernelGGL(k_q2_small_vcycle<R>, dim3((unsigned)nb), dim3(256), 0, s, x, x0, b, n0, coef, fpc, inv, nb, mk);
+}
+
 // ---------------------------------------------------------------- Chebyshev
 // One step of the Jacobi-preconditioned Chebyshev semi-iteration for the
 // mass matrix (Q2 interior or Q1 unconstrained):
@@ -531,7 +758,9 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
   template void launch_cheb<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int,    \
                                double, double, double, int, int, Mask);                                              \
   template void launch_schur_combine_pin<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, \
-                                            int, int, int, Mask);
+                                            int, int, int, Mask);                                                   \
+  template void launch_q2_small_vcycle<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, const OpCoef*,  \
+                                          int, const double2*, int, Mask);
 
 PINTOC_INST(double)
 PINTOC_INST(float)

@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pintoc.h"
@@ -666,6 +667,10 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
     launch_coarse<R>(s, m.q2, x, b, m.inv, m.fpc, m.nb, m.mk());
     return;
   }
+  if (m.q2 && !m.conv[l] && n <= kQ2SmallN) {     // every remaining level in one work-group per grid
+    launch_q2_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv, m.nb, m.mk());
+    return;
+  }
   cpx<R>* t = (cpx<R>*)m.t[l];
   cpx<R>* bc = (cpx<R>*)m.b[l + 1];
   cpx<R>* xc = (cpx<R>*)m.x[l + 1];
@@ -1263,4 +1268,46 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return conv ? PINTOC_OK : PINTOC_NOT_CONVERGED;
+}
+
+// Several problems at once: one host thread per problem, each driving its
+// problem's solve on that problem's stream.
+extern "C" int pintoc_solve_batch(pintoc_problem* const* p, const double* const* b, double* const* x,
+                                  pintoc_solve_stats* st, void* const* streams, int32_t n) {
+  if (n < 0) return fail(PINTOC_EINVAL, "negative problem count");
+  if (n == 0) return PINTOC_OK;
+  if (!p || !b || !x || !streams) return fail(PINTOC_EINVAL, "NULL argument array");
+  for (int k = 0; k < n; ++k) {
+    if (!p[k] || !b[k] || !x[k] || !streams[k])
+      return fail(PINTOC_EINVAL, "problem " + std::to_string(k) + ": NULL handle, vector or stream");
+    if (!p[k]->bound) return fail(PINTOC_ESTATE, "problem " + std::to_string(k) + ": no workspace bound");
+    for (int q = 0; q < k; ++q)
+      if (p[q] == p[k] || streams[q] == streams[k])
+        return fail(PINTOC_EINVAL, "problems " + std::to_string(q) + " and " + std::to_string(k) +
+                                       " share a handle or a stream");
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::vector<int> rc(n, PINTOC_OK);
+  std::vector<std::string> msg(n);
+  std::vector<std::thread> th;
+  th.reserve(n);
+  for (int k = 0; k < n; ++k) {
+    th.emplace_back([&, k]() {
+      if (hipSetDevice(dev) != hipSuccess) {
+        rc[k] = PINTOC_EHIP;
+        msg[k] = "hipSetDevice failed in the worker thread";
+        return;
+      }
+      rc[k] = pintoc_solve(p[k], b[k], x[k], st ? st + k : nullptr, streams[k]);
+      if (rc[k] < 0) msg[k] = g_err;
+    });
+  }
+  for (auto& t : th) t.join();
+  int out = PINTOC_OK;
+  for (int k = 0; k < n; ++k) {
+    if (rc[k] < 0) return fail(rc[k], "problem " + std::to_string(k) + ": " + msg[k]);
+    if (rc[k] == PINTOC_NOT_CONVERGED) out = PINTOC_NOT_CONVERGED;
+  }
+  return out;
 }

@@ -20,7 +20,9 @@
 // the values of the sweep's start for couplings to other tiles.
 //
 // Convection tables are reordered on the host per (tile, colour, class,
-// stencil entry, lane), so the lanes of a wave read 64 consecutive doubles.
+// stencil entry, lane), so the lanes of a wave read 64 consecutive doubles;
+// every class slot holds 25 entries, so a sweep can load the next colour's
+// entries of its lane (whatever its class) while the current colour computes.
 //
 // Lanes.  A class wave reads the nodes (la, lb) of the class's 8 x 8 nodes of
 // the colour at sub-grid entries u = 3 la + 78 lb + const.  A 128-bit LDS read
@@ -58,8 +60,15 @@ __host__ __device__ constexpr int wlen(int P) { return P ? 3 : 5; }
 __host__ __device__ constexpr int wlo(int P) { return P ? -1 : -2; }
 __host__ __device__ constexpr int cm0(int P) { return P ? 16 : 8; }    // centre of m'
 __host__ __device__ constexpr int ck0(int P) { return P ? 16 : 14; }   // centre of k'
-// offset of a class's entries in the per-(tile, colour) convection block
-__host__ __device__ constexpr int coff(int PX, int PY) { return PY ? (PX ? 55 : 40) : (PX ? 25 : 0); }
+// Convection table block per (tile, colour): four class slots of kCE entries
+// (a class uses wlen(PX) wlen(PY) of them), each entry 64 lanes wide.
+constexpr int kCE = 25, kCC = 4 * kCE;
+__host__ __device__ constexpr int coff(int PX, int PY) { return (PX + 2 * PY) * kCE; }
+constexpr size_t kTileTab = (size_t)9 * kCC * 64;     // doubles per tile
+// FP64 kernels load the next colour's entries into registers while the current
+// colour computes; in FP32 those registers cost more occupancy than the
+// overlap gains, so the entries are read where used.
+template <typename R> constexpr bool kTabPrefetch = sizeof(R) == 8;
 
 // LDS offset of neighbour (dx, dy) from the base of a class-(PX, PY) node
 template <int PX, int PY>
@@ -135,12 +144,22 @@ __device__ __forceinline__ cpx<T> diag0(const TCoef<T>& t) {
   return d;
 }
 
-// A x at a class-(PX, PY) node: base points at the node's sub-grid origin, cn
-// at its lane's first convection entry (stride 64).  Returns A x and the
-// diagonal convection entry.
-template <int PX, int PY, bool CV, typename R>
-__device__ __forceinline__ cpx<R> stencil(const cpx<R>* base, const double* __restrict__ cn, const TCoef<R>& t,
-                                          R& cdiag) {
+// Convection entries of a lane's node: held in registers (RegTab) or read
+// where used from the tile table (GlobTab, stride 64 between entries).
+template <typename R> struct RegTab {
+  const R* t;
+  __device__ __forceinline__ R operator()(int e) const { return t[e]; }
+};
+template <typename R> struct GlobTab {
+  const double* p;
+  __device__ __forceinline__ R operator()(int e) const { return (R)p[e * 64]; }
+};
+
+// A x at a class-(PX, PY) node: base points at the node's sub-grid origin,
+// tab gives its lane's convection entries.  Returns A x and the diagonal
+// convection entry.
+template <int PX, int PY, bool CV, typename R, typename Tab>
+__device__ __forceinline__ cpx<R> stencil(const cpx<R>* base, const Tab& tab, const TCoef<R>& t, R& cdiag) {
   constexpr int nx = wlen(PX), ny = wlen(PY), lx0 = wlo(PX), ly0 = wlo(PY);
   R smr[ny], smi[ny], skr[ny], ski[ny];
   R cr = 0, ci = 0;
@@ -153,7 +172,7 @@ __device__ __forceinline__ cpx<R> stencil(const cpx<R>* base, const double* __re
       vr[ix] = v.x;
       vi[ix] = v.y;
       if (CV) {
-        const R c = (R)cn[(iy * nx + ix) * 64];
+        const R c = tab(iy * nx + ix);
         cr = fma(c, vr[ix], cr);
         ci = fma(c, vi[ix], ci);
       }
@@ -173,9 +192,20 @@ __device__ __forceinline__ cpx<R> stencil(const cpx<R>* base, const double* __re
   if (CV) {
     ax.x += t.er * cr - t.ei * ci;
     ax.y += t.er * ci + t.ei * cr;
-    cdiag = (R)cn[((wlen(PY) / 2) * nx + nx / 2) * 64];
+    cdiag = tab((wlen(PY) / 2) * nx + nx / 2);
   }
   return ax;
+}
+
+// Load the convection entries of a lane's node at colour col into registers:
+// class cls (wave-uniform) of the tile's table ctile.  All kCE slot entries
+// are read (a class's unused ones are zero), which keeps the register array
+// statically indexed.
+template <typename R>
+__device__ __forceinline__ void load_tab(R* tab, const double* __restrict__ ctile, int col, int cls, int lane) {
+  const double* src = ctile + ((size_t)col * kCC + cls * kCE) * 64 + lane;
+#pragma unroll
+  for (int e = 0; e < kCE; ++e) tab[e] = (R)src[e * 64];
 }
 
 __device__ __forceinline__ bool tile_of_block(int ntiles, int nb, bool grid_fast, int& tile, int& f) {
@@ -303,16 +333,20 @@ __device__ __forceinline__ void prefetch_b(cpx<R>* bb, const cpx<R>* __restrict_
 // class diagonal (used without convection, where it is uniform).
 template <int PX, int PY, bool CV, typename R>
 __device__ __forceinline__ void sweep_node(cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0, int nq,
-                                           cpx<R> bv, const TCoef<R>& t, cpx<R> dinv,
+                                           cpx<R> bv, const TCoef<R>& t, cpx<R> dinv, const R* tab,
                                            const double* __restrict__ ctile) {
   int lx, ly;
   node_of(PX, PY, col, la, lb, lx, ly);
   const int gx = X0 + lx, gy = Y0 + ly;
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return;
   cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
-  const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
   R cd = 0;
-  const cpx<R> ax = stencil<PX, PY, CV, R>(base, cn, t, cd);
+  cpx<R> ax;
+  if (kTabPrefetch<R>)
+    ax = stencil<PX, PY, CV, R>(base, RegTab<R>{tab}, t, cd);
+  else
+    ax = stencil<PX, PY, CV, R>(base, GlobTab<R>{CV ? ctile + ((size_t)col * kCC + coff(PX, PY)) * 64 + lane : nullptr},
+                                t, cd);
   if (CV) {
     cpx<R> d = diag0<PX, PY, R>(t);
     d.x += t.er * cd;
@@ -392,18 +426,28 @@ __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const
     dv2 = inv_diag0<0, 1, R>(t);
     dv3 = inv_diag0<1, 1, R>(t);
   }
-  const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
+  // Convection entries: those of colour step k + 1 are loaded while step k
+  // computes, so their latency overlaps the step.
+  const double* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
+  constexpr bool PF = CV && kTabPrefetch<R>;
+  R tcur[PF ? kCE : 1], tnxt[PF ? kCE : 1];
+  if (PF) load_tab<R>(tcur, ctile, FWD ? 0 : 8, class_of(w, 0, rot), lane);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const int col = FWD ? k : 8 - k;
+    if (PF && k < 8) load_tab<R>(tnxt, ctile, FWD ? k + 1 : 7 - k, class_of(w, k + 1, rot), lane);
     switch (class_of(w, k, rot)) {
-      case 0: sweep_node<0, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv0, ctile); break;
-      case 1: sweep_node<1, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv1, ctile); break;
-      case 2: sweep_node<0, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv2, ctile); break;
-      default: sweep_node<1, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv3, ctile); break;
+      case 0: sweep_node<0, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv0, tcur, ctile); break;
+      case 1: sweep_node<1, 0, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv1, tcur, ctile); break;
+      case 2: sweep_node<0, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv2, tcur, ctile); break;
+      default: sweep_node<1, 1, CV, R>(sx, col, la, lb, lane, X0, Y0, nq, bb[k], t, dv3, tcur, ctile); break;
     }
     __syncthreads();
+    if (PF) {
+#pragma unroll
+      for (int e = 0; e < kCE; ++e) tcur[e] = tnxt[e];
+    }
   }
   store_tile<R>(xo + off, sx, nq, X0, Y0);
 }
@@ -411,16 +455,18 @@ __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const
 namespace {
 template <int PX, int PY, bool CV, typename R>
 __device__ __forceinline__ cpx<R> apply_node(const cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0,
-                                             int nq, const TCoef<R>& t, const double* __restrict__ ctile, int& si) {
+                                             int nq, const TCoef<R>& t, const R* tab,
+                                             const double* __restrict__ ctile, int& si) {
   int lx, ly;
   node_of(PX, PY, col, la, lb, lx, ly);
   si = ly * kSP + lx;
   const int gx = X0 + lx, gy = Y0 + ly;
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return cmk<cpx<R>>(0, 0);
   const cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
-  const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
   R cd = 0;
-  return stencil<PX, PY, CV, R>(base, cn, t, cd);
+  if (kTabPrefetch<R>) return stencil<PX, PY, CV, R>(base, RegTab<R>{tab}, t, cd);
+  return stencil<PX, PY, CV, R>(base, GlobTab<R>{CV ? ctile + ((size_t)col * kCC + coff(PX, PY)) * 64 + lane : nullptr},
+                                t, cd);
 }
 
 // Load x into the tile and leave A x of every tile node staged row-major
@@ -431,17 +477,25 @@ __device__ __forceinline__ void apply_stage(cpx<R>* sx, const cpx<R>* __restrict
                                             int rot) {
   int la, lb;
   lane_ab(lane, la, lb);
+  constexpr bool PF = CV && kTabPrefetch<R>;
+  R tcur[PF ? kCE : 1], tnxt[PF ? kCE : 1];
+  if (PF) load_tab<R>(tcur, ctile, 0, class_of(w, 0, rot), lane);
   load_tile<R>(sx, x, nq, X0, Y0);
   __syncthreads();
   cpx<R> acc[9];
   int si[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
+    if (PF && k < 8) load_tab<R>(tnxt, ctile, k + 1, class_of(w, k + 1, rot), lane);
     switch (class_of(w, k, rot)) {
-      case 0: acc[k] = apply_node<0, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
-      case 1: acc[k] = apply_node<1, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
-      case 2: acc[k] = apply_node<0, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
-      default: acc[k] = apply_node<1, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, ctile, si[k]); break;
+      case 0: acc[k] = apply_node<0, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, tcur, ctile, si[k]); break;
+      case 1: acc[k] = apply_node<1, 0, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, tcur, ctile, si[k]); break;
+      case 2: acc[k] = apply_node<0, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, tcur, ctile, si[k]); break;
+      default: acc[k] = apply_node<1, 1, CV, R>(sx, k, la, lb, lane, X0, Y0, nq, t, tcur, ctile, si[k]); break;
+    }
+    if (PF) {
+#pragma unroll
+      for (int e = 0; e < kCE; ++e) tcur[e] = tnxt[e];
     }
   }
   __syncthreads();
@@ -467,7 +521,7 @@ __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out,
   const size_t off = (size_t)f * nq * nq;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
   const TCoef<R> t = tcoef<R>(coef[f / fpc], h);
-  const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
+  const double* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
   apply_stage<R, CV>(sx, x + off, nq, X0, Y0, t, ctile, w, lane, rot);     // A x staged for a coalesced store
   if (threadIdx.x < 5 * kT) {
     const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT;
@@ -564,7 +618,7 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
   const size_t off = (size_t)f * nq * nq;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
   const TCoef<R> t = tcoef<R>(coef[f / fpc], h);
-  const double* ctile = CV ? conv + (size_t)tile * 9 * 64 * 64 : nullptr;
+  const double* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
   // b of this thread's column rows (thread t < 5 kT: column t % kT, rows t / kT + 5 k);
   // in FP64 without convection it is loaded before the stencil phase so its
   // latency overlaps it (in FP32, or beside the convection table reads, the
@@ -712,7 +766,7 @@ __device__ __forceinline__ void block_node(const cpx<R>* sx, const cpx<R>* sp, c
   const int gx = X0 + lx, gy = Y0 + ly;
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return;
   const cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
-  const double* cn = CV ? ctile + ((size_t)col * 64 + coff(PX, PY)) * 64 + lane : nullptr;
+  const double* cn = CV ? ctile + ((size_t)col * kCC + coff(PX, PY)) * 64 + lane : nullptr;
   cpx<R> pm, pk, pc;
   stencil_raw<PX, PY, CV, R>(base, cn, pm, pk, pc);
   const R sM = (R)(h * h / 900.0), sK = (R)(1.0 / 90.0);
@@ -833,7 +887,7 @@ __global__ __launch_bounds__(256, 2) void k_q2_block_vel(cpx<R>* __restrict__ yV
   }
   load_tile<R>(sx, v, nq, X0, Y0);
   const BlockCoef k = bc[j];
-  const size_t toff = (size_t)tile * 9 * 64 * 64;
+  const size_t toff = (size_t)tile * kTileTab;
   cpx<R> r1[9], r2[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) { r1[c] = cmk<cpx<R>>(0, 0); r2[c] = r1[c]; }
@@ -933,7 +987,7 @@ void launch_q2_block_vel(hipStream_t s, cpx<R>* yV, const cpx<R>* xV, const cpx<
 // tile kernels.
 void q2_tile_conv_table(int n, const double* t50, int half, double* out) {
   const int nq = 2 * n + 1, ntx = (nq + kT - 1) / kT;
-  const size_t total = (size_t)ntx * ntx * 9 * 64 * 64;
+  const size_t total = (size_t)ntx * ntx * kTileTab;
   for (size_t i = 0; i < total; ++i) out[i] = 0.0;
   for (int tile = 0; tile < ntx * ntx; ++tile) {
     const int X0 = (tile % ntx) * kT, Y0 = (tile / ntx) * kT;
@@ -950,7 +1004,7 @@ void q2_tile_conv_table(int n, const double* t50, int half, double* out) {
           for (int iy = 0; iy < wlen(PY); ++iy)
             for (int ix = 0; ix < wlen(PX); ++ix, ++k) {
               const int dx = wlo(PX) + ix, dy = wlo(PY) + iy;
-              out[(((size_t)tile * 9 + col) * 64 + coff(PX, PY) + k) * 64 + lane] =
+              out[(((size_t)tile * 9 + col) * kCC + coff(PX, PY) + k) * 64 + lane] =
                   t50[((size_t)gy * nq + gx) * 50 + half * 25 + (dy + 2) * 5 + (dx + 2)];
             }
         }
@@ -959,7 +1013,7 @@ void q2_tile_conv_table(int n, const double* t50, int half, double* out) {
   }
 }
 
-size_t q2_tile_conv_entries(int n) { return (size_t)q2_tile_count(n) * 9 * 64 * 64; }
+size_t q2_tile_conv_entries(int n) { return (size_t)q2_tile_count(n) * kTileTab; }
 
 #define PINTOC_Q2T_INST(R)                                                                                       \
   template void launch_q2_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, double, \

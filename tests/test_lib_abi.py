@@ -54,3 +54,50 @@ def test_host_validation(lib):
     assert lib.pintoc_bind_workspace(h, None, 0, None) == -1
     assert lib.pintoc_kkt_apply(h, None, None, None) < 0          # unbound: refused before any GPU call
     lib.pintoc_problem_destroy(h)
+
+
+def test_solve_batch_validation(lib):
+    """pintoc_solve_batch rejects bad arguments before any GPU work."""
+    from paper_2405_18964_amd._lib import Desc, SolveStats, default_options
+    V = ctypes.c_void_p
+    assert lib.pintoc_solve_batch(None, None, None, None, None, 0) == 0
+    assert lib.pintoc_solve_batch(None, None, None, None, None, -1) == -1
+    assert lib.pintoc_solve_batch(None, None, None, None, None, 1) == -1
+    o = default_options()
+    h = ctypes.c_void_p()
+    d = Desc(8, 16, 1.0, 1.0, 1e-2, 0, None)
+    assert lib.pintoc_problem_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)) == 0
+    P = (V * 1)(h.value)
+    vecs = (V * 1)(16)                     # never dereferenced: refused first
+    st = (SolveStats * 1)()
+    assert lib.pintoc_solve_batch(P, vecs, (V * 1)(32), st, (V * 1)(None), 1) == -1    # NULL stream
+    assert lib.pintoc_solve_batch(P, vecs, (V * 1)(32), st, (V * 1)(64), 1) == -4      # no workspace bound
+    assert b"problem 0" in lib.pintoc_last_error()
+    lib.pintoc_problem_destroy(h)
+
+
+def test_batch_job_bytes_and_mix():
+    """Memory accounting of the batch runner and the batched workload draw."""
+    import workloads as W
+    from paper_2405_18964_amd.batch import job_bytes
+    mix = W.batch_mix()
+    assert len(mix) == 64 and mix == W.batch_mix()
+    assert {w.N for w in mix} <= {32, 64, 128} and {w.nt for w in mix} <= {32, 64, 128, 256}
+    assert all(1e-6 <= w.beta <= 1e-2 for w in mix)
+    small = {"N": 8, "nt": 16, "nu": 1.0, "beta": 1e-2, "flow": 0}
+    big = dict(small, nt=32)
+    assert 0 < job_bytes(small) < job_bytes(big)
+    assert job_bytes(small, precision=1) < job_bytes(small, precision=0)
+
+
+def test_serve_stream_draw():
+    """Served workload: seeded Poisson arrivals (increasing, mean gap 1 at unit
+    rate) and request parameters drawn like the batched mix."""
+    import numpy as np
+    import workloads as W
+    s = W.serve_stream(256)
+    assert len(s) == 256 and [a for _, a in s] == [a for _, a in W.serve_stream(256)]
+    arr = np.array([a for _, a in s])
+    assert np.all(np.diff(arr) > 0) and 0.8 < arr[-1] / 256 < 1.2
+    assert {w.N for w, _ in s} <= {32, 64, 128, 256} and 256 in {w.N for w, _ in s}
+    assert max(w.N for w, _ in W.serve_stream(64, max_N=128)) <= 128

@@ -73,6 +73,44 @@ def config(idx: int, seed: int | None = None) -> Workload:
     raise ValueError(f"unknown config {idx}")
 
 
+def batch_mix(count: int = 64, seed: int = 4) -> list:
+    """The batched workload: ``count`` independent control problems.
+
+    N ~ U{32, 64, 128}, nt ~ U{32, 64, 128, 256}, log10(beta) ~ U[-6, -2],
+    nu ~ U{1, 1/50, 1/100}, Stokes or Oseen with probability 1/2 each (Oseen
+    with the wind of ``wind_nodal``), T = 1, amplitude ~ U[0.5, 2].  Draw order
+    from ``default_rng(seed)``: every problem parameter array, then the
+    amplitudes; problem k's noise comes from its own stream (its Workload seed
+    is 1000 * seed + k)."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.choice([32, 64, 128], size=count)
+    nts = rng.choice([32, 64, 128, 256], size=count)
+    lbeta = rng.uniform(-6.0, -2.0, size=count)
+    nus = rng.choice([1.0, 1.0 / 50.0, 1.0 / 100.0], size=count)
+    flows = rng.integers(0, 2, size=count)
+    amps = rng.uniform(0.5, 2.0, size=count)
+    return [Workload(int(flows[k]), int(Ns[k]), int(nts[k]), 1.0, float(nus[k]), float(10.0 ** lbeta[k]),
+                     1000 * seed + k, float(amps[k])) for k in range(count)]
+
+
+def serve_stream(count: int = 256, seed: int = 5, max_N: int = 256) -> list:
+    """The served workload: ``count`` requests with parameters drawn as in
+    ``batch_mix`` except N ~ U{32, 64, 128, 256} (capped at ``max_N``).
+    Returns (workload, unit-rate arrival time) pairs: the arrivals of a Poisson
+    process of rate 1 (cumulative sums of Exp(1) gaps from
+    ``default_rng((seed, 2))``); divide by a rate lambda for that rate."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.choice([n for n in (32, 64, 128, 256) if n <= max_N], size=count)
+    nts = rng.choice([32, 64, 128, 256], size=count)
+    lbeta = rng.uniform(-6.0, -2.0, size=count)
+    nus = rng.choice([1.0, 1.0 / 50.0, 1.0 / 100.0], size=count)
+    flows = rng.integers(0, 2, size=count)
+    amps = rng.uniform(0.5, 2.0, size=count)
+    arrivals = np.cumsum(np.random.default_rng((seed, 2)).exponential(1.0, size=count))
+    return [(Workload(int(flows[k]), int(Ns[k]), int(nts[k]), 1.0, float(nus[k]), float(10.0 ** lbeta[k]),
+                      1000 * seed + k, float(amps[k])), float(arrivals[k])) for k in range(count)]
+
+
 def small(flow: int, N: int, nt: int, beta: float = 1e-2, nu: float = 1.0,
           T: float = 1.0, seed: int = 0, amplitude: float = 1.0) -> Workload:
     """A small workload of the same family, for parity tests."""
