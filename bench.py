@@ -59,7 +59,7 @@ def sweep_traffic_bytes():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3; 1 for --config 4 and 5)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2,
                     help="workload: 1, 2 (single Stokes problem) or 4 (batched 64-problem mix)")
@@ -154,6 +154,8 @@ def cpu_baseline(w, outer_its: int, inner_mean: float, budget_s: float = 15.0) -
 
 def main():
     args = parse()
+    if args.steps is None:
+        args.steps = 1 if args.config in (4, 5) else 3
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
@@ -307,11 +309,17 @@ def bench_batch(args):
     small = sorted(range(len(jobs)), key=lambda k: job_bytes(jobs[k], **opts))[:args.workers]
     for i in range(args.warmup):                           # module loading, allocator warm-up
         run([jobs[k] for k in small], workers=args.workers, **opts)
+    def progress(tag):
+        def cb(k, r):
+            print(f"[bench] {tag}: job {k} ({mix[k].name}, nt={mix[k].nt}) {r['end'] - r['start']:.2f} s"
+                  f"{'' if r['converged'] else ' NOT CONVERGED'}", file=sys.stderr, flush=True)
+        return cb
+
     walls, outs = [], []
     for i in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = run(jobs, workers=args.workers, checksum=True, **opts)
+        out = run(jobs, workers=args.workers, checksum=True, on_done=progress(f"step {i}"), **opts)
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t0)
         outs.append(out)
@@ -345,7 +353,7 @@ def bench_batch(args):
             o = dict(opts, precision=prec)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            seq = run(jobs, workers=1, checksum=True, **o)
+            seq = run(jobs, workers=1, checksum=True, on_done=progress(name), **o)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
             res[name] = {"solves_per_s": len(jobs) / t, "seconds": t,
@@ -373,13 +381,20 @@ def bench_serve(args):
     opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    closed = run(jobs_at(None), workers=args.workers, checksum=True, **opts)
+    def progress(tag):
+        def cb(k, r):
+            w = stream[k][0]
+            print(f"[bench] {tag}: request {k} ({w.name}, nt={w.nt}) {r['end'] - r['start']:.2f} s",
+                  file=sys.stderr, flush=True)
+        return cb
+
+    closed = run(jobs_at(None), workers=args.workers, checksum=True, on_done=progress("closed loop"), **opts)
     cap = len(stream) / (time.perf_counter() - t0)
     rate = args.rho * cap
     print(f"[bench] closed loop: capacity {cap:.3f} solves/s; open loop at {rate:.3f} requests/s",
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    out = run(jobs_at(rate), workers=args.workers, checksum=True, **opts)
+    out = run(jobs_at(rate), workers=args.workers, checksum=True, on_done=progress("open loop"), **opts)
     wall = time.perf_counter() - t0
     lat = sorted(r["end"] - r["arrival"] for r in out)
     same = int(sum(a["digest"] == b["digest"] for a, b in zip(closed, out)))

@@ -90,6 +90,14 @@ typedef struct {
   int32_t n_cheb;         /* Chebyshev semi-iteration steps                  */
   int32_t n_uzawa;        /* Uzawa steps (Oseen)                             */
   double mu_uzawa;        /* Uzawa damping parameter (Oseen)                 */
+  int32_t stall_guard;    /* 1 (default): give up early where the iteration
+                             stagnates -- an inner GMRES frequency whose
+                             residual estimate is still above half its start
+                             after a restart cycle, and the outer solve when
+                             its residual estimate is above half the initial
+                             residual after 10 iterations (NOT_CONVERGED).  A
+                             safeguard outside the paper's method for blocks
+                             whose multigrid diverges; 0 turns it off.       */
 } pintoc_options;
 
 /* Statistics of one pintoc_solve call (host memory, filled by the library). */

@@ -26,7 +26,8 @@ class Options(C.Structure):
     _fields_ = [("inner", C.c_int32), ("precision", C.c_int32), ("restart", C.c_int32),
                 ("max_outer", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("inner_restart", C.c_int32), ("inner_maxit", C.c_int32), ("n_vcycles", C.c_int32),
-                ("n_cheb", C.c_int32), ("n_uzawa", C.c_int32), ("mu_uzawa", C.c_double)]
+                ("n_cheb", C.c_int32), ("n_uzawa", C.c_int32), ("mu_uzawa", C.c_double),
+                ("stall_guard", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -48,18 +48,23 @@ def job_bytes(job, **options) -> int:
 
 
 def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions: bool = False,
-        checksum: bool = False, device="cuda", **options):
+        checksum: bool = False, on_done=None, device="cuda", **options):
     """Solve every job; returns one record per job (in job order) with the
     stats of its solve, its arrival, start and end times (seconds after the
     start of the run), the device bytes it held, with ``keep_solutions`` its
     solution copied to host memory (numpy) and with ``checksum`` a BLAKE2b
-    digest of the solution's bytes (to compare runs without keeping them)."""
+    digest of the solution's bytes (to compare runs without keeping them).
+    ``on_done(k, record)`` is called (from the worker thread) as job k ends."""
     import hashlib
     import numpy as np
     import torch
 
     n = len(jobs)
     need = [job_bytes(j, **options) for j in jobs]
+    # blocks the caching allocator keeps for streams of earlier runs are of no
+    # use to this run's streams: return them before measuring the free memory
+    torch.cuda.synchronize(device)
+    torch.cuda.empty_cache()
     if budget_bytes is None:
         free, _ = torch.cuda.mem_get_info(device)
         budget_bytes = int(0.85 * free)
@@ -112,12 +117,16 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
             with lock:
                 state["free"] += need[k]
                 lock.notify_all()
+            if on_done is not None:
+                on_done(k, out[k])
 
     threads = [threading.Thread(target=worker, daemon=True) for _ in range(max(1, workers))]
     for t in threads:
         t.start()
     for t in threads:
         t.join()
+    torch.cuda.synchronize(device)
+    torch.cuda.empty_cache()
     if state["error"] is not None:
         raise state["error"]
     return out

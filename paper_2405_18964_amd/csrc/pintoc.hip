@@ -426,6 +426,7 @@ extern "C" int pintoc_default_options(pintoc_options* o) {
   o->n_cheb = 10;
   o->n_uzawa = 6;
   o->mu_uzawa = 0.75;
+  o->stall_guard = 1;
   return PINTOC_OK;
 }
 
@@ -494,7 +495,7 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   if (opt.precision != PINTOC_PREC_FP64 && opt.precision != PINTOC_PREC_FP32_INNER)
     return fail(PINTOC_EINVAL, "unknown precision");
   if (opt.restart < 1 || opt.restart > 60 || opt.max_outer < 1 || !(opt.tol > 0) || opt.n_vcycles < 1 ||
-      opt.n_cheb < 1)
+      opt.n_cheb < 1 || (opt.stall_guard != 0 && opt.stall_guard != 1))
     return fail(PINTOC_EINVAL, "invalid solver options");
   auto* p = new pintoc_problem();
   p->d = *d;
@@ -878,7 +879,7 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
   launch_fdot<R>(s, SV, SP, 0, 0, 1, SV, SP, segV, segP, nf, p->fpart, p->hdev, kAll);
   if ((rc = fetch(p->hdev, hb, 1))) return rc;
   std::vector<double> bnorm(nf), rnorm(nf);
-  std::vector<int> done(nf, 0), its(nf, 0);
+  std::vector<int> done(nf, 0), its(nf, 0), stalled(nf, 0);
   for (int j = 0; j < nf; ++j) {
     bnorm[j] = std::sqrt(std::max(hb[j].x, 0.0));
     rnorm[j] = bnorm[j];
@@ -1029,6 +1030,8 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
             done[j] = 1; kj[j] = k + 1; active[j] = 0;
           } else if (last) {
             kj[j] = k + 1; active[j] = 0;
+            // stagnation guard: a whole restart cycle without halving the residual
+            if (p->o.stall_guard && res > 0.5 * bnorm[j]) stalled[j] = 1;
           }
         }
       }
@@ -1067,7 +1070,10 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     if ((rc = upload(p->hdev, scl, 1))) return rc;
     launch_fupdate<R>(s, XV, XP, ZV, ZP, 0, 0, 1, p->hdev, segV, segP, nf, -1.0, p->mk(1));   // X += P~^{-1} U
     bool any_left = false;
-    for (int j = 0; j < nf; ++j) any_left |= !done[j];
+    for (int j = 0; j < nf; ++j) {
+      if (stalled[j]) done[j] = 1;                         // given up: keeps its approximate solution
+      any_left |= !done[j];
+    }
     if (!any_left || total >= p->o.inner_maxit) break;
     // restart: r = s - Z x for the frequencies still running
     for (int j = 0; j < nf; ++j) running[j] = !done[j];
@@ -1194,9 +1200,11 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
     launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
     if ((rc = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb))) return rc;
     res = std::sqrt(hb[0]);
+    const double res0 = res;
+    bool stalled = false;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     while (true) {
-      if (!(res == res)) break;                        // NaN: give up
+      if (!std::isfinite(res)) break;                  // NaN or overflow: give up
       if (res <= p->o.tol * bnorm) { conv = true; break; }
       if (its >= p->o.max_outer) break;
       // V_0 = r / ||r||
@@ -1237,7 +1245,9 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
         g[k + 1] = -sn[k] * g[k];
         g[k] = cs[k] * g[k];
         ++its;
-        if (std::fabs(g[k + 1]) <= p->o.tol * bnorm || breakdown) { ++k; break; }
+        // stagnation guard: ten iterations without halving the initial residual
+        stalled = p->o.stall_guard && its >= 10 && std::fabs(g[k + 1]) > 0.5 * res0;
+        if (std::fabs(g[k + 1]) <= p->o.tol * bnorm || breakdown || stalled) { ++k; break; }
       }
       // y = H^{-1} g (upper triangular), x += Z y
       for (int i = k - 1; i >= 0; --i) {
@@ -1252,7 +1262,7 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
       launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
       if ((rc = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb))) return rc;
       res = std::sqrt(hb[0]);
-      if (breakdown && !(res <= p->o.tol * bnorm)) break;
+      if ((breakdown || stalled) && !(res <= p->o.tol * bnorm)) break;
     }
   }
   HIPCHK(hipGetLastError());
