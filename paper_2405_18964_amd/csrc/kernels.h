@@ -40,6 +40,11 @@ constexpr int kQ2SmallN = 16;
 template <typename R>
 void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
                             int fpc, const double2* inv, int nb, Mask mk);
+// the same for the unconstrained Q1 hierarchies (n0 <= kQ1SmallN)
+constexpr int kQ1SmallN = 16;
+template <typename R>
+void launch_q1_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
+                            int fpc, const double2* inv, int nb, Mask mk);
 template <typename R>
 void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
                  double h, double g, double w, int first, int nb, Mask mk);

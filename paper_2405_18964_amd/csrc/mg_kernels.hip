@@ -587,6 +587,165 @@ void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cp
   hipLaunchKernelGGL(k_q2_small_vcycle<R>, dim3((unsigned)nb), dim3(256), 0, s, x, x0, b, n0, coef, fpc, inv, nb, mk);
 }
 
+// The Q1 counterpart for the pressure hierarchies (no convection): levels
+// n0 <= kQ1SmallN .. 2 of the unconstrained grids in one work-group per grid.
+// A 32-node tile covers them, so the tiled smoother is plain four-colour
+// Gauss-Seidel (colour 2 (gy % 2) + gx % 2); residual, restriction (1/2, 1,
+// 1/2), the coarsest solve with node 0 held at zero (FP64 accumulation, as in
+// k_q1_coarse_solve) and prolongation follow the per-level kernels.
+namespace {
+constexpr int kQ1SmallEntries = sq(kQ1SmallN + 1) + sq(kQ1SmallN / 2 + 1) + sq(kQ1SmallN / 4 + 1) + sq(kQ1SmallN / 8 + 1);
+
+// (A x)(gx, gy) and the diagonal of alpha M + gamma K on the unconstrained grid
+template <typename R>
+__device__ __forceinline__ void q1_small_apply(const cpx<R>* x, int n, int gx, int gy, double h, const OpR<R>& o,
+                                               cpx<R>& ax, cpx<R>& dg) {
+  const int np = n + 1;
+  R mx[3], kx[3], my[3], ky[3];
+  q1_rows_r<R>(gx, n, h, mx, kx);
+  q1_rows_r<R>(gy, n, h, my, ky);
+  R amr = 0, ami = 0, akr = 0, aki = 0;
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy) {
+    const int jy = gy + dy - 1;
+    if (jy < 0 || jy > n) continue;
+    R smr = 0, smi = 0, skr = 0, ski = 0;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int jx = gx + dx - 1;
+      if (jx < 0 || jx > n) continue;
+      const cpx<R> v = x[jy * np + jx];
+      smr += mx[dx] * v.x; smi += mx[dx] * v.y;
+      skr += kx[dx] * v.x; ski += kx[dx] * v.y;
+    }
+    amr += my[dy] * smr; ami += my[dy] * smi;
+    akr += ky[dy] * smr + my[dy] * skr; aki += ky[dy] * smi + my[dy] * ski;
+  }
+  ax.x = o.ar * amr - o.ai * ami + o.gr * akr - o.gi * aki;
+  ax.y = o.ar * ami + o.ai * amr + o.gr * aki + o.gi * akr;
+  const R md = mx[1] * my[1], kd = kx[1] * my[1] + mx[1] * ky[1];
+  dg.x = o.ar * md + o.gr * kd;
+  dg.y = o.ai * md + o.gi * kd;
+}
+
+template <typename R>
+__device__ __forceinline__ void q1_small_sweep(cpx<R>* x, const cpx<R>* b, int n, const OpR<R>& o, bool forward) {
+  const int np = n + 1, half = (np + 1) / 2;
+  const double h = 1.0 / n;
+  for (int k = 0; k < 4; ++k) {
+    const int col = forward ? k : 3 - k;
+    for (int e = threadIdx.x; e < half * half; e += blockDim.x) {
+      const int gx = col % 2 + 2 * (e % half), gy = col / 2 + 2 * (e / half);
+      if (gx > n || gy > n) continue;
+      cpx<R> ax, dg;
+      q1_small_apply<R>(x, n, gx, gy, h, o, ax, dg);
+      const cpx<R> bv = b[gy * np + gx];
+      const R er = bv.x - ax.x, ei = bv.y - ax.y;
+      const R den = dg.x * dg.x + dg.y * dg.y;
+      cpx<R>& xs = x[gy * np + gx];
+      cpx<R> nv;
+      nv.x = xs.x + (er * dg.x + ei * dg.y) / den;
+      nv.y = xs.y + (ei * dg.x - er * dg.y) / den;
+      xs = nv;
+    }
+    __syncthreads();
+  }
+}
+}  // namespace
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_q1_small_vcycle(cpx<R>* xg, const cpx<R>* x0, const cpx<R>* __restrict__ bg,
+                                                         int n0, const OpCoef* __restrict__ coef, int fpc,
+                                                         const double2* __restrict__ inv, int nb, Mask mk) {
+  __shared__ cpx<R> xs[kQ1SmallEntries], bs[kQ1SmallEntries], rs[sq(kQ1SmallN + 1)];
+  const int f = blockIdx.x;
+  if (f >= nb || mk.off(f)) return;
+  const OpR<R> o(coef[f / fpc]);
+  int lev = 0, off[8], nn[8];
+  for (int n = n0, q = 0; n >= 2; n >>= 1, ++lev) { off[lev] = q; nn[lev] = n; q += sq(n + 1); }
+  const int np0 = n0 + 1;
+  const size_t g0 = (size_t)f * np0 * np0;
+  for (int e = threadIdx.x; e < np0 * np0; e += blockDim.x) {
+    bs[e] = bg[g0 + e];
+    xs[e] = x0 ? x0[g0 + e] : cmk<cpx<R>>(0, 0);
+  }
+  for (int e = np0 * np0 + threadIdx.x; e < off[lev - 1] + 9; e += blockDim.x) xs[e] = cmk<cpx<R>>(0, 0);
+  __syncthreads();
+  for (int l = 0; l + 1 < lev; ++l) {
+    const int n = nn[l], np = n + 1, nc = n / 2, npc = nc + 1;
+    cpx<R>* x = xs + off[l];
+    const cpx<R>* b = bs + off[l];
+    q1_small_sweep<R>(x, b, n, o, true);
+    const double h = 1.0 / n;
+    for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+      cpx<R> ax, dg;
+      q1_small_apply<R>(x, n, e % np, e / np, h, o, ax, dg);
+      cpx<R> r;
+      r.x = b[e].x - ax.x;
+      r.y = b[e].y - ax.y;
+      rs[e] = r;
+    }
+    __syncthreads();
+    cpx<R>* bc = bs + off[l + 1];
+    const R w[3] = {R(0.5), R(1), R(0.5)};
+    for (int e = threadIdx.x; e < npc * npc; e += blockDim.x) {
+      const int I = e % npc, J = e / npc;
+      cpx<R> v = cmk<cpx<R>>(0, 0);
+      for (int dy = 0; dy < 3; ++dy) {
+        const int fy = 2 * J + dy - 1;
+        if (fy < 0 || fy > n) continue;
+        for (int dx = 0; dx < 3; ++dx) {
+          const int fx = 2 * I + dx - 1;
+          if (fx < 0 || fx > n) continue;
+          const cpx<R> rv = rs[fy * np + fx];
+          v.x += w[dx] * w[dy] * rv.x;
+          v.y += w[dx] * w[dy] * rv.y;
+        }
+      }
+      bc[e] = v;
+    }
+    __syncthreads();
+  }
+  {   // coarsest grid (N = 2): node 0 held at zero, 8 x 8 inverse for nodes 1..8
+    const cpx<R>* b = bs + off[lev - 1];
+    cpx<R>* x = xs + off[lev - 1];
+    const double2* A = inv + (size_t)(f / fpc) * 64;
+    if (threadIdx.x < 9) {
+      const int r = threadIdx.x;
+      double sr = 0, si = 0;
+      if (r > 0) {
+        for (int q = 0; q < 8; ++q) {
+          const cpx<R> v = b[1 + q];
+          const double2 a = A[(r - 1) * 8 + q];
+          sr += a.x * (double)v.x - a.y * (double)v.y;
+          si += a.x * (double)v.y + a.y * (double)v.x;
+        }
+      }
+      x[r] = cmk<cpx<R>>(sr, si);
+    }
+    __syncthreads();
+  }
+  for (int l = lev - 2; l >= 0; --l) {
+    const int n = nn[l], np = n + 1, npc = n / 2 + 1;
+    cpx<R>* x = xs + off[l];
+    const cpx<R>* ec = xs + off[l + 1];
+    for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+      const cpx<R> p = q1_prolong_at<R>(ec, npc, e % np, e / np);
+      x[e].x += p.x;
+      x[e].y += p.y;
+    }
+    __syncthreads();
+    q1_small_sweep<R>(x, bs + off[l], n, o, false);
+  }
+  for (int e = threadIdx.x; e < np0 * np0; e += blockDim.x) xg[g0 + e] = xs[e];
+}
+
+template <typename R>
+void launch_q1_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
+                            int fpc, const double2* inv, int nb, Mask mk) {
+  hipLaunchKernelGGL(k_q1_small_vcycle<R>, dim3((unsigned)nb), dim3(256), 0, s, x, x0, b, n0, coef, fpc, inv, nb, mk);
+}
+
 // ---------------------------------------------------------------- Chebyshev
 // One step of the Jacobi-preconditioned Chebyshev semi-iteration for the
 // mass matrix (Q2 interior or Q1 unconstrained):
@@ -760,6 +919,8 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
   template void launch_schur_combine_pin<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, \
                                             int, int, int, Mask);                                                   \
   template void launch_q2_small_vcycle<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, const OpCoef*,  \
+                                          int, const double2*, int, Mask);                                           \
+  template void launch_q1_small_vcycle<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, const OpCoef*,  \
                                           int, const double2*, int, Mask);
 
 PINTOC_INST(double)

@@ -668,8 +668,9 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
     launch_coarse<R>(s, m.q2, x, b, m.inv, m.fpc, m.nb, m.mk());
     return;
   }
-  if (m.q2 && !m.conv[l] && n <= kQ2SmallN) {     // every remaining level in one work-group per grid
-    launch_q2_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv, m.nb, m.mk());
+  if (!m.conv[l] && n <= (m.q2 ? kQ2SmallN : kQ1SmallN)) {   // every remaining level in one work-group per grid
+    if (m.q2) launch_q2_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv, m.nb, m.mk());
+    else launch_q1_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv, m.nb, m.mk());
     return;
   }
   cpx<R>* t = (cpx<R>*)m.t[l];
