@@ -40,12 +40,12 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc passes over one solve of this workload (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch at the finest grid), each scaled by what the
 # same counter reads for a 1 GiB device copy in the same process (FETCH_SIZE
-# 524314.8 KiB, WRITE_SIZE 1048576 KiB).  Valid only for the kernel source they
+# 524314.6 KiB, WRITE_SIZE 1048576 KiB).  Valid only for the kernel source they
 # were taken on: reported as null once that file changes.
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2405_18964_amd", "csrc", "q2_tiles.hip")
-SWEEP_PMC = {"source_sha256": "8eef8397e1606007ce24610de8e53820ea7242ecf2a09228f87e6535284d001c",
-             "fetch_kib": 363439.5, "fetch_scale": 1048576.0 / 524314.8,
-             "write_kib": 420189.3, "write_scale": 1.0}
+SWEEP_PMC = {"source_sha256": "bb46283c2680e0092e869a23b8ef3d4324fe2f99f0d00fbe00e73eeacdd189e8",
+             "fetch_kib": 363448.1, "fetch_scale": 1048576.0 / 524314.6,
+             "write_kib": 420478.7, "write_scale": 1.0}
 
 
 def sweep_traffic_bytes():
