@@ -18,18 +18,19 @@ void launch_time_fft_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double
 
 // per-frequency operators and multigrid pieces (mg_kernels.hip).  For Q2
 // grids ``conv`` is a convection table in the tile layout of
-// q2_tile_conv_table (one operator half, scaled by coef.eta); for Q1 grids it
-// is the per-node table of 9 + 9 values (coef.eta, coef.etat).
+// q2_tile_conv_table (one operator half, scaled by coef.eta) stored in the
+// grids' precision R; for Q1 grids it is the per-node FP64 table of 9 + 9
+// values (coef.eta, coef.etat).
 template <typename R>
 void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, const cpx<R>* ec,
-                       int n, double h, const OpCoef* coef, int fpc, int nb, const double* conv, bool forward,
+                       int n, double h, const OpCoef* coef, int fpc, int nb, const void* conv, bool forward,
                        Mask mk);
 template <typename R>
 void launch_q1_residual(hipStream_t s, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
                         const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk);
 template <typename R>
 void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, double h, const OpCoef* coef, int fpc,
-                  int nb, const double* conv, Mask mk);
+                  int nb, const void* conv, Mask mk);
 template <typename R>
 void launch_q1_restrict(hipStream_t s, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk);
 template <typename R>
@@ -55,18 +56,18 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
 // Q2 tile kernels (q2_tiles.hip)
 template <typename R>
 void launch_q2_sweep(hipStream_t s, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, const cpx<R>* ec, int n, double h,
-                     const OpCoef* coef, int fpc, int nb, const double* tconv, bool forward, Mask mk);
+                     const OpCoef* coef, int fpc, int nb, const R* tconv, bool forward, Mask mk);
 template <typename R>
 void launch_q2_apply(hipStream_t s, cpx<R>* out, const cpx<R>* x, const cpx<R>* b, int n, double h,
-                     const OpCoef* coef, int fpc, int nb, const double* tconv, Mask mk);
+                     const OpCoef* coef, int fpc, int nb, const R* tconv, Mask mk);
 template <typename R>
 void launch_q2_block_vel(hipStream_t s, cpx<R>* yV, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                         const BlockCoef* bc, const double* tcN, const double* tcNT, Mask mk);
+                         const BlockCoef* bc, const R* tcN, const R* tcNT, Mask mk);
 // bc = P^T (b - A x) on the coarse grid of side n + 1 without storing the fine
 // residual; side: q2_restrict_side_entries(n) * nb complex entries of scratch
 template <typename R>
 void launch_q2_residual_restrict(hipStream_t s, cpx<R>* bc, cpx<R>* side, const cpx<R>* x, const cpx<R>* b, int n,
-                                 double h, const OpCoef* coef, int fpc, int nb, const double* tconv, Mask mk);
+                                 double h, const OpCoef* coef, int fpc, int nb, const R* tconv, Mask mk);
 size_t q2_restrict_side_entries(int n);
 size_t q2_tile_conv_entries(int n);
 void q2_tile_conv_table(int n, const double* t50, int half, double* out);
@@ -110,7 +111,7 @@ void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n);
 // frequency blocks and the Oseen preconditioner pieces (oseen_kernels.hip)
 template <typename R>
 void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                      const BlockCoef* bc, const double* tcN, const double* tcNT, double sp, Mask mk);
+                      const BlockCoef* bc, const R* tcN, const R* tcNT, double sp, Mask mk);
 template <typename R>
 void launch_schur_rhs(hipStream_t s, cpx<R>* out, const cpx<R>* in, const cpx<R>* y1, const cpx<R>* y2, int n,
                       int nf, double tau, Mask mk);

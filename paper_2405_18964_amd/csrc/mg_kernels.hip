@@ -844,14 +844,14 @@ static inline dim3 grid2(long work, int nb, int bs = 256) { return dim3((unsigne
 
 template <typename R>
 void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, const cpx<R>* ec,
-                       int n, double h, const OpCoef* coef, int fpc, int nb, const double* conv, bool forward,
+                       int n, double h, const OpCoef* coef, int fpc, int nb, const void* conv, bool forward,
                        Mask mk) {
   if (q2) {
-    launch_q2_sweep<R>(s, xo, xi, b, ec, n, h, coef, fpc, nb, conv, forward, mk);
+    launch_q2_sweep<R>(s, xo, xi, b, ec, n, h, coef, fpc, nb, (const R*)conv, forward, mk);
   } else {
     const int np = n + 1, ntx = (np + kT1 - 1) / kT1;
     hipLaunchKernelGGL(k_q1_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, ec, n, h, coef, fpc,
-                       conv, forward ? 1 : 0, ntx, mk);
+                       (const double*)conv, forward ? 1 : 0, ntx, mk);
   }
 }
 
@@ -864,12 +864,13 @@ void launch_q1_residual(hipStream_t s, cpx<R>* r, const cpx<R>* x, const cpx<R>*
 
 template <typename R>
 void launch_apply(hipStream_t s, bool q2, cpx<R>* y, const cpx<R>* x, int n, double h, const OpCoef* coef,
-                  int fpc, int nb, const double* conv, Mask mk) {
+                  int fpc, int nb, const void* conv, Mask mk) {
   if (q2) {
-    launch_q2_apply<R>(s, y, x, nullptr, n, h, coef, fpc, nb, conv, mk);
+    launch_q2_apply<R>(s, y, x, nullptr, n, h, coef, fpc, nb, (const R*)conv, mk);
   } else {
     const int np = n + 1;
-    hipLaunchKernelGGL(k_q1_apply<R>, grid2((long)np * np, nb), dim3(256), 0, s, y, x, n, h, coef, fpc, conv, mk);
+    hipLaunchKernelGGL(k_q1_apply<R>, grid2((long)np * np, nb), dim3(256), 0, s, y, x, n, h, coef, fpc,
+                       (const double*)conv, mk);
   }
 }
 
@@ -907,11 +908,11 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
 
 #define PINTOC_INST(R)                                                                                        \
   template void launch_tile_sweep<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, \
-                                     double, const OpCoef*, int, int, const double*, bool, Mask);                    \
+                                     double, const OpCoef*, int, int, const void*, bool, Mask);                    \
   template void launch_q1_residual<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,          \
                                       const OpCoef*, int, int, const double*, Mask);                                 \
   template void launch_apply<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int, int, \
-                                const double*, Mask);                                                                \
+                                const void*, Mask);                                                                \
   template void launch_q1_restrict<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, Mask);                          \
   template void launch_coarse<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const double2*, int, int, Mask);         \
   template void launch_cheb<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int,    \

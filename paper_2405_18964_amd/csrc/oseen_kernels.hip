@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_combine3(cpx<R>* out, const cpx<R>* A, 
 
 template <typename R>
 void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                      const BlockCoef* bc, const double* tcN, const double* tcNT, double sp, Mask mk) {
+                      const BlockCoef* bc, const R* tcN, const R* tcNT, double sp, Mask mk) {
   const int np2 = (n + 1) * (n + 1);
   launch_q2_block_vel<R>(s, yV, xV, xP, n, nf, bc, tcN, tcNT, mk);
   hipLaunchKernelGGL(k_block_pres<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, yP, xV, n, sp, mk);
@@ -195,7 +195,7 @@ void launch_combine3(hipStream_t s, cpx<R>* out, const cpx<R>* A, const cpx<R>* 
 
 #define PINTOC_OSEEN_INST(R)                                                                                       \
   template void launch_block_mat<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,         \
-                                    const BlockCoef*, const double*, const double*, double, Mask);                       \
+                                    const BlockCoef*, const R*, const R*, double, Mask);                       \
   template void launch_schur_rhs<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,   \
                                     double, Mask);                                                                       \
   template void launch_oseen_hp<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, const double2*, double, double,  \

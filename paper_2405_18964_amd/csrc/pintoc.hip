@@ -64,7 +64,7 @@ struct MGPlan {
   std::vector<double2> inv_h;          // coarsest inverses, per coefficient set
   OpCoef* coef = nullptr;              // device
   double2* inv = nullptr;              // device
-  std::vector<const double*> conv;     // per level (device, tile layout for Q2) or null
+  std::vector<const void*> conv;       // per level (device; Q2: tile layout in the grids' precision) or null
   // per-level device buffers (complex, precision-typed): b, x (level >= 1),
   // t (second iterate buffer of the out-of-place smoother), r (residual)
   std::vector<void*> b, x, r, t;
@@ -115,7 +115,7 @@ struct pintoc_problem {
   std::vector<std::vector<double>> conv2_h;   // per level, 50 per Q2 node
   std::vector<double> conv1_h;                // finest Q1 grid, 18 per node
   std::vector<std::vector<double>> tconv_h[2];  // per level below the coarsest: N, N^T in tile layout
-  std::vector<double*> tconv[2];
+  std::vector<void*> tconv[2];                 // device, in the inner precision (double or float entries)
   double* conv50 = nullptr;                   // finest level, 50 per node (block and all-at-once matrices)
   double* conv1 = nullptr;
   MGPlan mgQ, mgQH;
@@ -308,7 +308,7 @@ static void carve(pintoc_problem* p, char* base) {
     for (int hf = 0; hf < 2; ++hf) {
       p->tconv[hf].assign(p->tconv_h[hf].size(), nullptr);
       for (size_t l = 0; l < p->tconv_h[hf].size(); ++l)
-        p->tconv[hf][l] = cv.take<double>(sizeof(double) * p->tconv_h[hf][l].size());
+        p->tconv[hf][l] = cv.take<char>(p->csize / 2 * p->tconv_h[hf][l].size());
     }
     p->conv1 = cv.take<double>(sizeof(double) * p->conv1_h.size());
     p->cpsi = cv.take<OpCoef>(sizeof(OpCoef) * nf);
@@ -633,9 +633,16 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
     HIPCHK(hipMemcpyAsync(p->conv50, p->conv2_h[0].data(), sizeof(double) * p->conv2_h[0].size(),
                           hipMemcpyHostToDevice, s));
     for (int hf = 0; hf < 2; ++hf)
-      for (size_t l = 0; l < p->tconv[hf].size(); ++l)
-        HIPCHK(hipMemcpyAsync(p->tconv[hf][l], p->tconv_h[hf][l].data(), sizeof(double) * p->tconv_h[hf][l].size(),
-                              hipMemcpyHostToDevice, s));
+      for (size_t l = 0; l < p->tconv[hf].size(); ++l) {
+        const std::vector<double>& t = p->tconv_h[hf][l];
+        if (p->csize == 16) {
+          HIPCHK(hipMemcpyAsync(p->tconv[hf][l], t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, s));
+        } else {                          // FP32 inner solves read FP32 tables
+          const std::vector<float> f(t.begin(), t.end());
+          HIPCHK(hipMemcpyAsync(p->tconv[hf][l], f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, s));
+          HIPCHK(hipStreamSynchronize(s));   // f is a temporary
+        }
+      }
     HIPCHK(hipMemcpyAsync(p->conv1, p->conv1_h.data(), sizeof(double) * p->conv1_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsi, p->cpsi_h.data(), sizeof(OpCoef) * p->cpsi_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsih, p->cpsih_h.data(), sizeof(OpCoef) * p->cpsih_h.size(), hipMemcpyHostToDevice, s));
@@ -689,9 +696,9 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
   }
   cpx<R>* r = (cpx<R>*)m.r[l];
   if (m.q2) {
-    launch_q2_residual_restrict<R>(s, bc, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
+    launch_q2_residual_restrict<R>(s, bc, r, t, b, n, h, m.coef, m.fpc, m.nb, (const R*)m.conv[l], m.mk());
   } else {
-    launch_q1_residual<R>(s, r, t, b, n, h, m.coef, m.fpc, m.nb, m.conv[l], m.mk());
+    launch_q1_residual<R>(s, r, t, b, n, h, m.coef, m.fpc, m.nb, (const double*)m.conv[l], m.mk());
     launch_q1_restrict<R>(s, bc, r, n / 2, m.nb, m.mk());
   }
   vcycle<R>(s, m, l + 1, xc, bc, true);
@@ -760,7 +767,7 @@ static void puz(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R
   launch_block_copy<R>(s, (cpx<R>*)inV, B2, N, nf, 1, 0, m2);
   launch_fill_zero(s, X1, nh * sizeof(cpx<R>));
   launch_fill_zero(s, X2, nh * sizeof(cpx<R>));
-  const double *cvN = p->tconv[0][0], *cvNT = p->tconv[1][0];
+  const R *cvN = (const R*)p->tconv[0][0], *cvNT = (const R*)p->tconv[1][0];
   for (int k = 0; k < p->o.n_uzawa; ++k) {
     // x1 += tau^{-1} M^^{-1} (b1 - tau M x1 - Psi^H x2)
     launch_apply<R>(s, true, T1, X1, N, h, p->cscal + 0, 2 * nf, 2 * nf, nullptr, m2);
@@ -804,8 +811,8 @@ template <typename R>
 static void block_matvec(pintoc_problem* p, hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV,
                          const cpx<R>* xP) {
   const bool oseen = p->d.flow == PINTOC_OSEEN;
-  launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, oseen ? p->tconv[0][0] : nullptr,
-                      oseen ? p->tconv[1][0] : nullptr, p->block_scale, p->mk(2));
+  launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, oseen ? (const R*)p->tconv[0][0] : nullptr,
+                      oseen ? (const R*)p->tconv[1][0] : nullptr, p->block_scale, p->mk(2));
 }
 
 // complex Givens rotation (c real) with [c, s; -conj(s), c] [a; b] = [r; 0]

@@ -65,9 +65,10 @@ __host__ __device__ constexpr int ck0(int P) { return P ? 16 : 14; }   // centre
 constexpr int kCE = 25, kCC = 4 * kCE;
 __host__ __device__ constexpr int coff(int PX, int PY) { return (PX + 2 * PY) * kCE; }
 constexpr size_t kTileTab = (size_t)9 * kCC * 64;     // doubles per tile
-// FP64 kernels load the next colour's entries into registers while the current
-// colour computes; in FP32 those registers cost more occupancy than the
-// overlap gains, so the entries are read where used.
+// Tables are stored in the grids' precision R.  FP64 kernels load the next
+// colour's entries into registers while the current colour computes; in FP32
+// those registers cost more occupancy than the overlap gains, so the entries
+// are read where used.
 template <typename R> constexpr bool kTabPrefetch = sizeof(R) == 8;
 
 // LDS offset of neighbour (dx, dy) from the base of a class-(PX, PY) node
@@ -151,8 +152,8 @@ template <typename R> struct RegTab {
   __device__ __forceinline__ R operator()(int e) const { return t[e]; }
 };
 template <typename R> struct GlobTab {
-  const double* p;
-  __device__ __forceinline__ R operator()(int e) const { return (R)p[e * 64]; }
+  const R* p;
+  __device__ __forceinline__ R operator()(int e) const { return p[e * 64]; }
 };
 
 // A x at a class-(PX, PY) node: base points at the node's sub-grid origin,
@@ -198,14 +199,16 @@ __device__ __forceinline__ cpx<R> stencil(const cpx<R>* base, const Tab& tab, co
 }
 
 // Load the convection entries of a lane's node at colour col into registers:
-// class cls (wave-uniform) of the tile's table ctile.  All kCE slot entries
-// are read (a class's unused ones are zero), which keeps the register array
-// statically indexed.
+// class cls (wave-uniform) of the tile's table ctile.  Entry e is loaded only
+// when the class uses it (a wave-uniform predicate), so the array stays
+// statically indexed without reading a slot's unused entries.
 template <typename R>
-__device__ __forceinline__ void load_tab(R* tab, const double* __restrict__ ctile, int col, int cls, int lane) {
-  const double* src = ctile + ((size_t)col * kCC + cls * kCE) * 64 + lane;
+__device__ __forceinline__ void load_tab(R* tab, const R* __restrict__ ctile, int col, int cls, int lane) {
+  const R* src = ctile + ((size_t)col * kCC + cls * kCE) * 64 + lane;
+  const int ne = wlen(cls & 1) * wlen(cls >> 1);
 #pragma unroll
-  for (int e = 0; e < kCE; ++e) tab[e] = (R)src[e * 64];
+  for (int e = 0; e < kCE; ++e)
+    if (e < ne) tab[e] = src[e * 64];
 }
 
 __device__ __forceinline__ bool tile_of_block(int ntiles, int nb, bool grid_fast, int& tile, int& f) {
@@ -334,7 +337,7 @@ __device__ __forceinline__ void prefetch_b(cpx<R>* bb, const cpx<R>* __restrict_
 template <int PX, int PY, bool CV, typename R>
 __device__ __forceinline__ void sweep_node(cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0, int nq,
                                            cpx<R> bv, const TCoef<R>& t, cpx<R> dinv, const R* tab,
-                                           const double* __restrict__ ctile) {
+                                           const R* __restrict__ ctile) {
   int lx, ly;
   node_of(PX, PY, col, la, lb, lx, ly);
   const int gx = X0 + lx, gy = Y0 + ly;
@@ -403,7 +406,7 @@ template <typename R, bool CV, bool FWD, bool PRO>
 __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const cpx<R>* __restrict__ xi,
                                                   const cpx<R>* __restrict__ b, const cpx<R>* __restrict__ ec, int n,
                                                   double h, const OpCoef* __restrict__ coef, int fpc,
-                                                  const double* __restrict__ conv, int ntx, int nb, Mask mk) {
+                                                  const R* __restrict__ conv, int ntx, int nb, Mask mk) {
   __shared__ cpx<R> sx[4 * kSub];
   int tile, f;
   if (!tile_of_block(ntx * ntx, nb, CV, tile, f)) return;
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(256) void k_q2_sweep(cpx<R>* __restrict__ xo, const
   }
   // Convection entries: those of colour step k + 1 are loaded while step k
   // computes, so their latency overlaps the step.
-  const double* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
+  const R* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
   constexpr bool PF = CV && kTabPrefetch<R>;
   R tcur[PF ? kCE : 1], tnxt[PF ? kCE : 1];
   if (PF) load_tab<R>(tcur, ctile, FWD ? 0 : 8, class_of(w, 0, rot), lane);
@@ -456,7 +459,7 @@ namespace {
 template <int PX, int PY, bool CV, typename R>
 __device__ __forceinline__ cpx<R> apply_node(const cpx<R>* sx, int col, int la, int lb, int lane, int X0, int Y0,
                                              int nq, const TCoef<R>& t, const R* tab,
-                                             const double* __restrict__ ctile, int& si) {
+                                             const R* __restrict__ ctile, int& si) {
   int lx, ly;
   node_of(PX, PY, col, la, lb, lx, ly);
   si = ly * kSP + lx;
@@ -473,7 +476,7 @@ __device__ __forceinline__ cpx<R> apply_node(const cpx<R>* sx, int col, int la, 
 // (pitch kSP) in the LDS tile (zero on boundary and outside nodes).
 template <typename R, bool CV>
 __device__ __forceinline__ void apply_stage(cpx<R>* sx, const cpx<R>* __restrict__ x, int nq, int X0, int Y0,
-                                            const TCoef<R>& t, const double* __restrict__ ctile, int w, int lane,
+                                            const TCoef<R>& t, const R* __restrict__ ctile, int w, int lane,
                                             int rot) {
   int la, lb;
   lane_ab(lane, la, lb);
@@ -511,7 +514,7 @@ template <typename R, bool CV>
 __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ x,
                                                        const cpx<R>* __restrict__ b, int n, double h,
                                                        const OpCoef* __restrict__ coef, int fpc,
-                                                       const double* __restrict__ conv, int ntx, int nb, Mask mk) {
+                                                       const R* __restrict__ conv, int ntx, int nb, Mask mk) {
   __shared__ cpx<R> sx[4 * kSub];
   int tile, f;
   if (!tile_of_block(ntx * ntx, nb, CV, tile, f)) return;
@@ -521,7 +524,7 @@ __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out,
   const size_t off = (size_t)f * nq * nq;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
   const TCoef<R> t = tcoef<R>(coef[f / fpc], h);
-  const double* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
+  const R* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
   apply_stage<R, CV>(sx, x + off, nq, X0, Y0, t, ctile, w, lane, rot);     // A x staged for a coalesced store
   if (threadIdx.x < 5 * kT) {
     const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT;
@@ -607,7 +610,7 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
                                                               const cpx<R>* __restrict__ x,
                                                               const cpx<R>* __restrict__ b, int n, double h,
                                                               const OpCoef* __restrict__ coef, int fpc,
-                                                              const double* __restrict__ conv, int ntx, int nb,
+                                                              const R* __restrict__ conv, int ntx, int nb,
                                                               Mask mk) {
   __shared__ cpx<R> sx[4 * kSub];
   int tile, f;
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
   const size_t off = (size_t)f * nq * nq;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
   const TCoef<R> t = tcoef<R>(coef[f / fpc], h);
-  const double* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
+  const R* ctile = CV ? conv + (size_t)tile * kTileTab : nullptr;
   // b of this thread's column rows (thread t < 5 kT: column t % kT, rows t / kT + 5 k);
   // in FP64 without convection it is loaded before the stencil phase so its
   // latency overlaps it (in FP32, or beside the convection table reads, the
@@ -708,7 +711,7 @@ namespace {
 // Raw stencil sums at a class-(PX, PY) node: pm = m'.m' x, pk = (k'.m' + m'.k') x
 // (so M x = h^2/900 pm, K x = pk/90) and the convection sum pc.
 template <int PX, int PY, bool CV, typename R>
-__device__ __forceinline__ void stencil_raw(const cpx<R>* base, const double* __restrict__ cn, cpx<R>& pm, cpx<R>& pk,
+__device__ __forceinline__ void stencil_raw(const cpx<R>* base, const R* __restrict__ cn, cpx<R>& pm, cpx<R>& pk,
                                             cpx<R>& pc) {
   constexpr int nx = wlen(PX), ny = wlen(PY), lx0 = wlo(PX), ly0 = wlo(PY);
   R smr[ny], smi[ny], skr[ny], ski[ny];
@@ -722,7 +725,7 @@ __device__ __forceinline__ void stencil_raw(const cpx<R>* base, const double* __
       vr[ix] = v.x;
       vi[ix] = v.y;
       if (CV) {
-        const R c = (R)cn[(iy * nx + ix) * 64];
+        const R c = cn[(iy * nx + ix) * 64];
         cr = fma(c, vr[ix], cr);
         ci = fma(c, vi[ix], ci);
       }
@@ -758,7 +761,7 @@ constexpr int kPP = kT / 2 + 2;       // side of the Q1 patch of a tile (26)
 template <int PX, int PY, bool CV, int PH, typename R>
 __device__ __forceinline__ void block_node(const cpx<R>* sx, const cpx<R>* sp, const cpx<R>* sm, int col, int la,
                                            int lb, int lane, int X0, int Y0, int n, int comp, double h,
-                                           const BlockCoef& k, const double* __restrict__ ctile, cpx<R>& r1,
+                                           const BlockCoef& k, const R* __restrict__ ctile, cpx<R>& r1,
                                            cpx<R>& r2) {
   const int nq = 2 * n + 1;
   int lx, ly;
@@ -766,7 +769,7 @@ __device__ __forceinline__ void block_node(const cpx<R>* sx, const cpx<R>* sp, c
   const int gx = X0 + lx, gy = Y0 + ly;
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return;
   const cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
-  const double* cn = CV ? ctile + ((size_t)col * kCC + coff(PX, PY)) * 64 + lane : nullptr;
+  const R* cn = CV ? ctile + ((size_t)col * kCC + coff(PX, PY)) * 64 + lane : nullptr;
   cpx<R> pm, pk, pc;
   stencil_raw<PX, PY, CV, R>(base, cn, pm, pk, pc);
   const R sM = (R)(h * h / 900.0), sK = (R)(1.0 / 90.0);
@@ -812,7 +815,7 @@ __device__ __forceinline__ void block_node(const cpx<R>* sx, const cpx<R>* sp, c
 template <bool CV, int PH, typename R>
 __device__ __forceinline__ void block_phase(const cpx<R>* sx, const cpx<R>* sp, const cpx<R>* sm, int w, int rot,
                                             int la, int lb, int lane, int X0, int Y0, int n, int comp, double h,
-                                            const BlockCoef& k, const double* __restrict__ ctile, cpx<R>* r1,
+                                            const BlockCoef& k, const R* __restrict__ ctile, cpx<R>* r1,
                                             cpx<R>* r2) {
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
@@ -860,7 +863,7 @@ template <typename R, bool CV>
 __global__ __launch_bounds__(256, 2) void k_q2_block_vel(cpx<R>* __restrict__ yV, const cpx<R>* __restrict__ xV,
                                                       const cpx<R>* __restrict__ xP, int n,
                                                       const BlockCoef* __restrict__ bc,
-                                                      const double* __restrict__ tcN, const double* __restrict__ tcNT,
+                                                      const R* __restrict__ tcN, const R* __restrict__ tcNT,
                                                       int ntx, int nb, Mask mk) {
   __shared__ cpx<R> sx[4 * kSub];
   __shared__ cpx<R> sp[kPP * kPP], sm[kPP * kPP];
@@ -922,7 +925,7 @@ int q2_tile_count(int n) {
 
 template <typename R>
 void launch_q2_sweep(hipStream_t s, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, const cpx<R>* ec, int n, double h,
-                     const OpCoef* coef, int fpc, int nb, const double* tconv, bool forward, Mask mk) {
+                     const OpCoef* coef, int fpc, int nb, const R* tconv, bool forward, Mask mk) {
   const int ntx = (2 * n + 1 + kT - 1) / kT;
   const dim3 g(tile_blocks(ntx, nb)), blk(256);
   const bool cv = tconv != nullptr, pro = ec != nullptr;
@@ -945,7 +948,7 @@ void launch_q2_sweep(hipStream_t s, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* 
 
 template <typename R>
 void launch_q2_apply(hipStream_t s, cpx<R>* out, const cpx<R>* x, const cpx<R>* b, int n, double h,
-                     const OpCoef* coef, int fpc, int nb, const double* tconv, Mask mk) {
+                     const OpCoef* coef, int fpc, int nb, const R* tconv, Mask mk) {
   const int ntx = (2 * n + 1 + kT - 1) / kT;
   const dim3 g(tile_blocks(ntx, nb)), blk(256);
   if (tconv) hipLaunchKernelGGL((k_q2_tile_apply<R, true>), g, blk, 0, s, out, x, b, n, h, coef, fpc, tconv, ntx, nb, mk);
@@ -954,7 +957,7 @@ void launch_q2_apply(hipStream_t s, cpx<R>* out, const cpx<R>* x, const cpx<R>* 
 
 template <typename R>
 void launch_q2_residual_restrict(hipStream_t s, cpx<R>* bc, cpx<R>* side, const cpx<R>* x, const cpx<R>* b, int n,
-                                 double h, const OpCoef* coef, int fpc, int nb, const double* tconv, Mask mk) {
+                                 double h, const OpCoef* coef, int fpc, int nb, const R* tconv, Mask mk) {
   const int ntx = (2 * n + 1 + kT - 1) / kT;
   const dim3 g(tile_blocks(ntx, nb)), blk(256);
   if (tconv)
@@ -975,7 +978,7 @@ size_t q2_restrict_side_entries(int n) { return (size_t)q2_tile_count(n) * kSide
 
 template <typename R>
 void launch_q2_block_vel(hipStream_t s, cpx<R>* yV, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                         const BlockCoef* bc, const double* tcN, const double* tcNT, Mask mk) {
+                         const BlockCoef* bc, const R* tcN, const R* tcNT, Mask mk) {
   const int ntx = (2 * n + 1 + kT - 1) / kT;
   const dim3 g(tile_blocks(ntx, 2 * nf)), blk(256);
   if (tcN) hipLaunchKernelGGL((k_q2_block_vel<R, true>), g, blk, 0, s, yV, xV, xP, n, bc, tcN, tcNT, ntx, 2 * nf, mk);
@@ -1017,13 +1020,13 @@ size_t q2_tile_conv_entries(int n) { return (size_t)q2_tile_count(n) * kTileTab;
 
 #define PINTOC_Q2T_INST(R)                                                                                       \
   template void launch_q2_sweep<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, double, \
-                                   const OpCoef*, int, int, const double*, bool, Mask);                             \
+                                   const OpCoef*, int, int, const R*, bool, Mask);                                  \
   template void launch_q2_apply<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double, const OpCoef*,  \
-                                   int, int, const double*, Mask);                                                    \
+                                   int, int, const R*, Mask);                                                         \
   template void launch_q2_block_vel<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,                 \
-                                       const BlockCoef*, const double*, const double*, Mask);                         \
+                                       const BlockCoef*, const R*, const R*, Mask);                                   \
   template void launch_q2_residual_restrict<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, int,      \
-                                               double, const OpCoef*, int, int, const double*, Mask);
+                                               double, const OpCoef*, int, int, const R*, Mask);
 
 PINTOC_Q2T_INST(double)
 PINTOC_Q2T_INST(float)
