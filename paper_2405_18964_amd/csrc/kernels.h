@@ -69,6 +69,10 @@ template <typename R>
 void launch_q2_residual_restrict(hipStream_t s, cpx<R>* bc, cpx<R>* side, const cpx<R>* x, const cpx<R>* b, int n,
                                  double h, const OpCoef* coef, int fpc, int nb, const R* tconv, Mask mk);
 size_t q2_restrict_side_entries(int n);
+// Chebyshev step (not the first) for the Q2 mass matrix on LDS tiles
+template <typename R>
+void launch_q2_tile_cheb(hipStream_t s, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
+                         double h, double g, double w, int nb, Mask mk);
 size_t q2_tile_conv_entries(int n);
 void q2_tile_conv_table(int n, const double* t50, int half, double* out);
 

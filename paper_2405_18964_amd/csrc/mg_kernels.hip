@@ -892,6 +892,7 @@ template <typename R>
 void launch_cheb(hipStream_t s, bool q2, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
                  double h, double g, double w, int first, int nb, Mask mk) {
   if (q2) {
+    if (!first) return launch_q2_tile_cheb<R>(s, xn, x, xp, b, n, h, g, w, nb, mk);
     const int nq = 2 * n + 1;
     hipLaunchKernelGGL(k_q2_cheb<R>, grid2((long)nq * nq, nb), dim3(256), 0, s, xn, x, xp, b, n, h, g, w, first, mk);
   } else {

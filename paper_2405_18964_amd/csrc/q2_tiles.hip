@@ -665,6 +665,46 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
   restrict_class<1, 1, R>(bcf, sd, sx, I0, J0, nqc);
 }
 
+// One Chebyshev step for the Q2 mass matrix (not the first):
+//   xn = w (x - xp + g D^{-1} (b - M x)) + xp      (D = diag(M), zero boundary)
+// with M x formed on the LDS tile.  xn may alias xp (each node's xp is read
+// by the thread that writes it).
+template <typename R>
+__global__ __launch_bounds__(256) void k_q2_tile_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
+                                                      const cpx<R>* __restrict__ b, int n, double h, double g,
+                                                      double w, int ntx, int nb, Mask mk) {
+  __shared__ cpx<R> sx[4 * kSub];
+  int tile, f;
+  if (!tile_of_block(ntx * ntx, nb, false, tile, f)) return;
+  if (mk.off(f)) return;
+  const int X0 = (tile % ntx) * kT, Y0 = (tile / ntx) * kT;
+  const int nq = 2 * n + 1;
+  const size_t off = (size_t)f * nq * nq;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, rot = (int)(blockIdx.x >> 3) & 3;
+  const TCoef<R> t{(R)(h * h / 900.0), R(0), R(0), R(0), R(0), R(0)};
+  apply_stage<R, false>(sx, x + off, nq, X0, Y0, t, nullptr, wv, lane, rot);      // M x staged row-major
+  if (threadIdx.x >= 5 * kT) return;
+  const int lx = (int)threadIdx.x % kT, ly0 = (int)threadIdx.x / kT, gx = X0 + lx;
+  if (gx >= nq) return;
+  const R gr = (R)g, wr = (R)w;
+#pragma unroll
+  for (int k = 0; k < kSR; ++k) {
+    const int ly = ly0 + 5 * k, gy = Y0 + ly;
+    if (ly >= kT || gy >= nq) break;
+    const size_t i = off + (size_t)gy * nq + gx;
+    if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) {
+      xn[i] = cmk<cpx<R>>(0, 0);
+      continue;
+    }
+    const R d = (R)(cm0(gx & 1) * cm0(gy & 1)) * t.ar;
+    const cpx<R> mx = sx[ly * kSP + lx], xi = x[i], pi = xp[i], bi = b[i];
+    cpx<R> v;
+    v.x = wr * (xi.x - pi.x + gr * (bi.x - mx.x) / d) + pi.x;
+    v.y = wr * (xi.y - pi.y + gr * (bi.y - mx.y) / d) + pi.y;
+    xn[i] = v;
+  }
+}
+
 // Shared coarse nodes of k_q2_residual_restrict: I or J a positive multiple of
 // 24 (interior nodes only).  Such a node adds the column partial of the tile
 // to its left, the row partial of the tile below, and, when both I and J are
@@ -977,6 +1017,14 @@ void launch_q2_residual_restrict(hipStream_t s, cpx<R>* bc, cpx<R>* side, const 
 size_t q2_restrict_side_entries(int n) { return (size_t)q2_tile_count(n) * kSide; }
 
 template <typename R>
+void launch_q2_tile_cheb(hipStream_t s, cpx<R>* xn, const cpx<R>* x, const cpx<R>* xp, const cpx<R>* b, int n,
+                         double h, double g, double w, int nb, Mask mk) {
+  const int ntx = (2 * n + 1 + kT - 1) / kT;
+  hipLaunchKernelGGL((k_q2_tile_cheb<R>), dim3(tile_blocks(ntx, nb)), dim3(256), 0, s, xn, x, xp, b, n, h, g, w, ntx,
+                     nb, mk);
+}
+
+template <typename R>
 void launch_q2_block_vel(hipStream_t s, cpx<R>* yV, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
                          const BlockCoef* bc, const R* tcN, const R* tcNT, Mask mk) {
   const int ntx = (2 * n + 1 + kT - 1) / kT;
@@ -1026,7 +1074,9 @@ size_t q2_tile_conv_entries(int n) { return (size_t)q2_tile_count(n) * kTileTab;
   template void launch_q2_block_vel<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,                 \
                                        const BlockCoef*, const R*, const R*, Mask);                                   \
   template void launch_q2_residual_restrict<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, int,      \
-                                               double, const OpCoef*, int, int, const R*, Mask);
+                                               double, const OpCoef*, int, int, const R*, Mask);                      \
+  template void launch_q2_tile_cheb<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int,        \
+                                       double, double, double, int, Mask);
 
 PINTOC_Q2T_INST(double)
 PINTOC_Q2T_INST(float)
