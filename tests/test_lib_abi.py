@@ -48,6 +48,9 @@ def test_host_validation(lib):
         assert lib.pintoc_problem_create(ctypes.byref(bad), ctypes.byref(o), ctypes.byref(h)) == -1
         assert lib.pintoc_last_error()
     good = Desc(8, 16, 1.0, 1.0, 1e-2, 0, None)
+    assert o.stall_guard == 1
+    bad_opt = default_options(stall_guard=2)
+    assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(bad_opt), ctypes.byref(h)) == -1
     assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(o), ctypes.byref(h)) == 0
     assert lib.pintoc_vector_length(h) == 2 * 16 * (2 * 17 ** 2 + 9 ** 2)
     assert lib.pintoc_workspace_bytes(h) > 0
