@@ -2,6 +2,8 @@
 // Every batched per-frequency launcher takes a Mask: grids of frequencies
 // whose mask entry is 0 are skipped (kAll: every grid active).
 #pragma once
+#include <vector>
+
 #include "common.h"
 
 namespace pintoc {
@@ -35,12 +37,16 @@ template <typename R>
 void launch_q1_restrict(hipStream_t s, cpx<R>* bc, const cpx<R>* rf, int nc, int nb, Mask mk);
 template <typename R>
 void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const double2* inv, int fpc, int nb, Mask mk);
-// the rest of a Q2 V-cycle (no convection) from level n0 <= kQ2SmallN down to
-// N = 2 in one launch, one work-group per grid; x0: initial iterate or null (zero)
+// the rest of a Q2 V-cycle from level n0 <= kQ2SmallN down to N = 2 in one
+// launch, one work-group per grid; x0: initial iterate or null (zero); tconv:
+// the convection table of q2_small_conv_table (scaled by coef.eta) in the
+// grids' precision, or null
 constexpr int kQ2SmallN = 16;
 template <typename R>
 void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
-                            int fpc, const double2* inv, int nb, Mask mk);
+                            int fpc, const double2* inv, const R* tconv, int nb, Mask mk);
+size_t q2_small_conv_entries(int n0);
+void q2_small_conv_table(int n0, const std::vector<const double*>& tabs, int half, double* out);
 // the same for the unconstrained Q1 hierarchies (n0 <= kQ1SmallN)
 constexpr int kQ1SmallN = 16;
 template <typename R>

@@ -362,10 +362,13 @@ __global__ __launch_bounds__(256) void k_q1_coarse_solve(cpx<R>* __restrict__ x,
 
 // ------------------------------------------------ small-grid V-cycles
 // The rest of a Q2 V(1,1) cycle from level n0 <= kSmallN down to the N = 2
-// grid, for operators without convection, in one work-group per grid with
-// every level in LDS.  A 48-node tile covers these grids, so the tiled
-// smoother is plain multicolour Gauss-Seidel (colour 3 (gy % 3) + gx % 3,
-// forward before and backward after the coarse correction); residual,
+// grid in one work-group per grid with every level in LDS.  With convection
+// the operator gains eta C, C read from a per-node table of the levels
+// n0 .. 4 (q2_small_conv_table; the coarsest inverse already holds it).  A
+// 48-node tile covers these grids, so the tiled smoother is plain
+// multicolour Gauss-Seidel (colour 3 (gy % 3) + gx % 3, forward before and
+// backward after the coarse correction; L lanes share a node's stencil rows
+// and add their parts before the update); residual,
 // restriction P^T, exact coarsest solve (FP64 accumulation, as in
 // k_q2_coarse_solve) and prolongation P follow the per-level kernels.
 // x0 == nullptr: the cycle starts from zero on level n0; x0 may equal xg
@@ -375,6 +378,10 @@ constexpr int kSmallN = kQ2SmallN;
 namespace {
 constexpr int sq(int v) { return v * v; }
 constexpr int kSmallEntries = sq(2 * kSmallN + 1) + sq(kSmallN + 1) + sq(kSmallN / 2 + 1) + sq(kSmallN / 4 + 1);
+// waves per work-group for L lanes per colour slot
+template <int L> constexpr int kSmallWaves = L == 4 ? 8 : 4;
+static_assert(4 * sq((2 * kSmallN + 3) / 3) <= 512, "four lanes per colour slot in a 512-thread work-group");
+static_assert(sq((2 * kSmallN + 3) / 3) <= 256, "one lane per colour slot in a 256-thread work-group");
 
 // m' . v and k' . v along one direction for node parity P (offsets -2..2 or -1..1)
 template <typename R>
@@ -390,61 +397,170 @@ __device__ __forceinline__ void small_comb(int P, const R* v, R& m, R& k) {
   }
 }
 
-// (A x)(gx, gy) and the diagonal for alpha M + gamma K on a padded grid in LDS
+// Level operator coefficients: integer-weight scales of M and K, eta of the
+// convection table tl (level table of q2_small_conv_table, or null)
 template <typename R>
-__device__ __forceinline__ void small_apply(const cpx<R>* x, int nq, int gx, int gy, R ar, R ai, R gr, R gi,
-                                            cpx<R>& ax, cpx<R>& dg) {
-  const int px = gx & 1, py = gy & 1;
-  R smr[5], smi[5], skr[5], ski[5];
+struct SmallOp {
+  R ar, ai, gr, gi, er, ei;
+  const R* tl;
+  int per;                                            // nodes per colour and direction
+};
+
+template <typename R>
+__device__ __forceinline__ SmallOp<R> small_op(const OpCoef& c, int n, const R* tl) {
+  const double h = 1.0 / n, sm = h * h / 900.0;
+  return SmallOp<R>{(R)(c.alpha.x * sm), (R)(c.alpha.y * sm), (R)(c.gamma.x / 90.0), (R)(c.gamma.y / 90.0),
+                    (R)c.eta.x, (R)c.eta.y, tl, (2 * n + 3) / 3};
+}
+
+// 1-D weights m'(d), k'(d) (offset d - 2) of a node of parity P: the rows
+// that small_comb applies
+template <typename R>
+__device__ __forceinline__ R small_mw(int P, int d) {
+  if (d == 2) return P ? R(16) : R(8);
+  if (d == 1 || d == 3) return R(2);
+  return P ? R(0) : R(-1);
+}
+template <typename R>
+__device__ __forceinline__ R small_kw(int P, int d) {
+  if (d == 2) return P ? R(16) : R(14);
+  if (d == 1 || d == 3) return R(-8);
+  return P ? R(0) : R(1);
+}
+
+// Rows of the 5 x 5 stencil window handled by lane q of the L lanes that
+// share a node: dy = q, q + L, .. (at most kRows(L) of them).
+template <int L> constexpr int kRows = (5 + L - 1) / L;
+
+// the convection coefficients of lane q's rows at slot e of colour col (zero
+// outside the grid): tv[5 r + dx] for row dy = q + r L
+template <typename R, int L>
+__device__ __forceinline__ void small_tab(const SmallOp<R>& o, int col, int e, int q, R* tv) {
+  const int pp = o.per * o.per;
+  const R* t = o.tl + (size_t)col * 25 * pp + e;
 #pragma unroll
-  for (int dy = 0; dy < 5; ++dy) {
-    const bool use = py == 0 || (dy >= 1 && dy <= 3);
+  for (int r = 0; r < kRows<L>; ++r) {
+    const int dy = q + r * L;
+    if (dy < 5) {
+#pragma unroll
+      for (int dx = 0; dx < 5; ++dx) tv[5 * r + dx] = t[(5 * dy + dx) * pp];
+    }
+  }
+}
+
+// Lane q's share of (A x)(gx, gy) for alpha M + gamma K (+ eta C, with the
+// lane's coefficients tv) on a padded grid in LDS: the rows dy = q + r L of
+// the window, weighted by their 1-D y-weights, and (CV) the lane's part of
+// the diagonal convection entry.  Summed over the L lanes this is A x.
+// Offsets +-2 of a midpoint node carry no weight in M, K or C.
+template <typename R, bool CV, int L>
+__device__ __forceinline__ void small_apply(const cpx<R>* x, int nq, int gx, int gy, int q, const SmallOp<R>& o,
+                                            const R* tv, R& axr, R& axi, R& cdg) {
+  const int px = gx & 1, py = gy & 1;
+  R pmr = 0, pmi = 0, pkr = 0, pki = 0, cr = 0, ci = 0;
+  cdg = 0;
+#pragma unroll
+  for (int r = 0; r < kRows<L>; ++r) {
+    const int dy = q + r * L;
+    if (dy >= 5 || (py && (dy == 0 || dy == 4))) continue;
     R vr[5], vi[5];
 #pragma unroll
     for (int dx = 0; dx < 5; ++dx) {
-      const bool u = use && (px == 0 || (dx >= 1 && dx <= 3));
+      const bool u = px == 0 || (dx >= 1 && dx <= 3);
       const cpx<R> v = u ? x[(gy + dy - 2) * nq + gx + dx - 2] : cmk<cpx<R>>(0, 0);
       vr[dx] = v.x;
       vi[dx] = v.y;
+      if (CV) {
+        cr += tv[5 * r + dx] * v.x;
+        ci += tv[5 * r + dx] * v.y;
+      }
     }
-    small_comb<R>(px, vr, smr[dy], skr[dy]);
-    small_comb<R>(px, vi, smi[dy], ski[dy]);
+    R smr, skr, smi, ski;
+    small_comb<R>(px, vr, smr, skr);
+    small_comb<R>(px, vi, smi, ski);
+    const R wm = small_mw<R>(py, dy), wk = small_kw<R>(py, dy);
+    pmr += wm * smr;                       // m'_y m'_x
+    pmi += wm * smi;
+    pkr += wk * smr + wm * skr;            // k'_y m'_x + m'_y k'_x
+    pki += wk * smi + wm * ski;
+    if (CV && dy == 2) cdg = tv[5 * r + 2];
   }
-  R pmr, pmi, kmr, kmi, mkr, mki, unr, uni;
-  small_comb<R>(py, smr, pmr, kmr);
-  small_comb<R>(py, smi, pmi, kmi);
-  small_comb<R>(py, skr, mkr, unr);
-  small_comb<R>(py, ski, mki, uni);
-  const R pkr = mkr + kmr, pki = mki + kmi;
-  ax.x = ar * pmr - ai * pmi + gr * pkr - gi * pki;
-  ax.y = ar * pmi + ai * pmr + gr * pki + gi * pkr;
-  const R md = (px ? R(16) : R(8)) * (py ? R(16) : R(8));
-  const R kd = (px ? R(16) : R(14)) * (py ? R(16) : R(8)) + (px ? R(16) : R(8)) * (py ? R(16) : R(14));
-  dg.x = ar * md + gr * kd;
-  dg.y = ai * md + gi * kd;
+  axr = o.ar * pmr - o.ai * pmi + o.gr * pkr - o.gi * pki;
+  axi = o.ar * pmi + o.ai * pmr + o.gr * pki + o.gi * pkr;
+  if (CV) {
+    axr += o.er * cr - o.ei * ci;
+    axi += o.er * ci + o.ei * cr;
+  }
 }
 
-// one Gauss-Seidel sweep (forward or backward colour order) of level grid x
-template <typename R>
-__device__ __forceinline__ void small_sweep(cpx<R>* x, const cpx<R>* b, int n, const OpCoef& c, bool forward) {
-  const int nq = 2 * n + 1;
-  const double h = 1.0 / n, sm = h * h / 900.0;
-  const R ar = (R)(c.alpha.x * sm), ai = (R)(c.alpha.y * sm), gr = (R)(c.gamma.x / 90.0), gi = (R)(c.gamma.y / 90.0);
-  const int per = (nq + 2) / 3;                       // nodes per colour and direction (upper bound)
+// the diagonal of alpha M + gamma K + eta C at a node of parity (px, py)
+// with diagonal convection entry cdg
+template <typename R, bool CV>
+__device__ __forceinline__ cpx<R> small_diag(const SmallOp<R>& o, int px, int py, R cdg) {
+  const R md = (px ? R(16) : R(8)) * (py ? R(16) : R(8));
+  const R kd = (px ? R(16) : R(14)) * (py ? R(16) : R(8)) + (px ? R(16) : R(8)) * (py ? R(16) : R(14));
+  cpx<R> dg;
+  dg.x = o.ar * md + o.gr * kd + (CV ? o.er * cdg : R(0));
+  dg.y = o.ai * md + o.gi * kd + (CV ? o.ei * cdg : R(0));
+  return dg;
+}
+
+// Sum over the 4 lanes of a quad (lanes 4i .. 4i + 3) by DPP quad
+// permutations; every lane of the quad must be active.
+template <int C>
+__device__ __forceinline__ int dpp_i(int v) { return __builtin_amdgcn_update_dpp(0, v, C, 0xF, 0xF, true); }
+template <int C>
+__device__ __forceinline__ float dpp_r(float v) { return __int_as_float(dpp_i<C>(__float_as_int(v))); }
+template <int C>
+__device__ __forceinline__ double dpp_r(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<C>((int)(unsigned)(b & 0xffffffffll)), hi = dpp_i<C>((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <typename R, int L>
+__device__ __forceinline__ R lane_sum(R v) {
+  static_assert(L == 1 || L == 4, "lanes per node");
+  if (L == 4) {
+    v += dpp_r<0xB1>(v);                   // quad_perm [1, 0, 3, 2]
+    v += dpp_r<0x4E>(v);                   // quad_perm [2, 3, 0, 1]
+  }
+  return v;
+}
+
+// one Gauss-Seidel sweep (forward or backward colour order) of level grid x.
+// Lanes L s .. L s + L - 1 own slot s of every colour (per^2 L <= blockDim.x
+// for n <= 16); their convection coefficients for the next colour are loaded
+// while the current colour is updated.  Every thread reaches the lane sums.
+template <typename R, bool CV, int L>
+__device__ __forceinline__ void small_sweep(cpx<R>* x, const cpx<R>* b, int n, const SmallOp<R>& o, bool forward) {
+  const int nq = 2 * n + 1, per = o.per, e = threadIdx.x / L, q = threadIdx.x % L;
+  const bool mine = e < per * per;
+  constexpr int kTv = 5 * kRows<L>;
+  R cur[kTv], nxt[kTv];
+  if (CV && mine) small_tab<R, L>(o, forward ? 0 : 8, e, q, cur);
   for (int k = 0; k < 9; ++k) {
     const int col = forward ? k : 8 - k, cx = col % 3, cy = col / 3;
-    for (int e = threadIdx.x; e < per * per; e += blockDim.x) {
-      const int gx = cx + 3 * (e % per), gy = cy + 3 * (e / per);
-      if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) continue;
-      cpx<R> ax, dg;
-      small_apply<R>(x, nq, gx, gy, ar, ai, gr, gi, ax, dg);
+    if (CV && mine && k < 8) small_tab<R, L>(o, forward ? col + 1 : col - 1, e, q, nxt);
+    const int gx = cx + 3 * (e % per), gy = cy + 3 * (e / per);
+    const bool act = mine && gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2;
+    R axr = 0, axi = 0, cdg = 0;
+    if (act) small_apply<R, CV, L>(x, nq, gx, gy, q, o, cur, axr, axi, cdg);
+    axr = lane_sum<R, L>(axr);
+    axi = lane_sum<R, L>(axi);
+    if (CV) cdg = lane_sum<R, L>(cdg);
+    if (act && q == 0) {
+      const cpx<R> dg = small_diag<R, CV>(o, gx & 1, gy & 1, cdg);
       const cpx<R> bv = b[gy * nq + gx];
-      const R er = bv.x - ax.x, ei = bv.y - ax.y, inv = R(1) / (dg.x * dg.x + dg.y * dg.y);
+      const R er = bv.x - axr, ei = bv.y - axi, inv = R(1) / (dg.x * dg.x + dg.y * dg.y);
       cpx<R>& xs = x[gy * nq + gx];
       cpx<R> nv;
       nv.x = xs.x + (er * dg.x + ei * dg.y) * inv;
       nv.y = xs.y + (ei * dg.x - er * dg.y) * inv;
       xs = nv;
+    }
+    if (CV) {
+#pragma unroll
+      for (int i = 0; i < kTv; ++i) cur[i] = nxt[i];
     }
     __syncthreads();
   }
@@ -467,11 +583,12 @@ __device__ __forceinline__ R small_pw(int r, int q) {
 }
 }  // namespace
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_q2_small_vcycle(cpx<R>* xg, const cpx<R>* x0,
+template <typename R, bool CV, int L>
+__global__ __launch_bounds__(64 * kSmallWaves<L>) void k_q2_small_vcycle(cpx<R>* xg, const cpx<R>* x0,
                                                          const cpx<R>* __restrict__ bg, int n0,
                                                          const OpCoef* __restrict__ coef, int fpc,
-                                                         const double2* __restrict__ inv, int nb, Mask mk) {
+                                                         const double2* __restrict__ inv,
+                                                         const R* __restrict__ tconv, int nb, Mask mk) {
   // x of every level and b of the coarser levels in LDS (the top level's b is
   // read from memory: 47.5 KB in FP64, three work-groups per CU)
   constexpr int kB = kSmallEntries - sq(2 * kSmallN + 1);
@@ -479,8 +596,13 @@ __global__ __launch_bounds__(256) void k_q2_small_vcycle(cpx<R>* xg, const cpx<R
   const int f = blockIdx.x;
   if (f >= nb || mk.off(f)) return;
   const OpCoef c = coef[f / fpc];
-  int lev = 0, off[8], nn[8];
-  for (int n = n0, o = 0; n >= 2; n >>= 1, ++lev) { off[lev] = o; nn[lev] = n; o += sq(2 * n + 1); }
+  int lev = 0, off[8], nn[8], toff[8];
+  for (int n = n0, o = 0, t = 0; n >= 2; n >>= 1, ++lev) {
+    off[lev] = o; nn[lev] = n; toff[lev] = t;
+    o += sq(2 * n + 1);
+    t += 225 * sq((2 * n + 3) / 3);
+  }
+  auto op = [&](int l) { return small_op<R>(c, nn[l], CV ? tconv + toff[l] : nullptr); };
   const int nq0 = 2 * n0 + 1;
   const size_t g0 = (size_t)f * nq0 * nq0;
   const cpx<R>* b0 = bg + g0;
@@ -494,19 +616,24 @@ __global__ __launch_bounds__(256) void k_q2_small_vcycle(cpx<R>* xg, const cpx<R
     const int n = nn[l], nq = 2 * n + 1, nqc = n + 1;
     cpx<R>* x = xs + off[l];
     const cpx<R>* b = blev(l);
-    small_sweep<R>(x, b, n, c, true);
-    const double h = 1.0 / n, sm = h * h / 900.0;
-    const R ar = (R)(c.alpha.x * sm), ai = (R)(c.alpha.y * sm), gr = (R)(c.gamma.x / 90.0), gi = (R)(c.gamma.y / 90.0);
-    for (int e = threadIdx.x; e < nq * nq; e += blockDim.x) {
-      const int gx = e % nq, gy = e / nq;
+    const SmallOp<R> o = op(l);
+    small_sweep<R, CV, L>(x, b, n, o, true);
+    // residual over the colour slots (the convection table's order)
+    const int pp = o.per * o.per;
+    for (int i = threadIdx.x; i < 9 * pp; i += blockDim.x) {
+      const int col = i / pp, e = i - col * pp;
+      const int gx = col % 3 + 3 * (e % o.per), gy = col / 3 + 3 * (e / o.per);
+      if (gx >= nq || gy >= nq) continue;
       cpx<R> r = cmk<cpx<R>>(0, 0);
       if (gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2) {
-        cpx<R> ax, dg;
-        small_apply<R>(x, nq, gx, gy, ar, ai, gr, gi, ax, dg);
-        r.x = b[e].x - ax.x;
-        r.y = b[e].y - ax.y;
+        R tv[25], axr, axi, cdg;
+        if (CV) small_tab<R, 1>(o, col, e, 0, tv);
+        small_apply<R, CV, 1>(x, nq, gx, gy, 0, o, tv, axr, axi, cdg);
+        const cpx<R> bv = b[gy * nq + gx];
+        r.x = bv.x - axr;
+        r.y = bv.y - axi;
       }
-      rs[e] = r;
+      rs[gy * nq + gx] = r;
     }
     __syncthreads();
     cpx<R>* bc = bsc + (off[l + 1] - off[1]);
@@ -576,15 +703,63 @@ __global__ __launch_bounds__(256) void k_q2_small_vcycle(cpx<R>* xg, const cpx<R
       x[e].y += pi;
     }
     __syncthreads();
-    small_sweep<R>(x, blev(l), n, c, false);
+    small_sweep<R, CV, L>(x, blev(l), n, op(l), false);
   }
   for (int e = threadIdx.x; e < nq0 * nq0; e += blockDim.x) xg[g0 + e] = xs[e];
 }
 
+// lanes per colour slot of the small Q2 V-cycle: four (512 threads) with
+// convection, where a node's stencil is the longest chain of a colour step
+template <typename R>
+static int small_lanes(bool cv) { return cv ? 4 : 1; }
+
 template <typename R>
 void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
-                            int fpc, const double2* inv, int nb, Mask mk) {
-  hipLaunchKernelGGL(k_q2_small_vcycle<R>, dim3((unsigned)nb), dim3(256), 0, s, x, x0, b, n0, coef, fpc, inv, nb, mk);
+                            int fpc, const double2* inv, const R* tconv, int nb, Mask mk) {
+  const dim3 g((unsigned)nb);
+  const bool cv = tconv != nullptr;
+  const int L = small_lanes<R>(cv);
+#define PINTOC_SMALL(CV, LL)                                                                                       \
+  if (cv == CV && L == LL) {                                                                                      \
+    hipLaunchKernelGGL((k_q2_small_vcycle<R, CV, LL>), g, dim3(64 * kSmallWaves<LL>), 0, s, x, x0, b, n0, coef, fpc, \
+                       inv, tconv, nb, mk);                                                                       \
+    return;                                                                                                       \
+  }
+  PINTOC_SMALL(true, 4)
+  PINTOC_SMALL(false, 1)
+  PINTOC_SMALL(true, 1)
+  PINTOC_SMALL(false, 4)
+#undef PINTOC_SMALL
+}
+
+// Convection table of the small levels n0, n0 / 2, .., 4 for one operator
+// half (0: N, 1: N^T), the levels back to back, in the order the small
+// V-cycle's threads read it.  On a level (nq = 2n + 1, per = (nq + 2) / 3
+// nodes per colour and direction) node (gx, gy) = (cx + 3 i, cy + 3 j) of
+// colour col = 3 cy + cx is slot e = per j + i, and its coefficient of offset
+// (dx, dy) in -2..2 sits at [(25 col + 5 (dy + 2) + dx + 2) per^2 + e]; slots
+// off the interior hold zeros.  tabs[l] is level l's table of 50 values per
+// padded node (N, then N^T).
+size_t q2_small_conv_entries(int n0) {
+  size_t e = 0;
+  for (int n = n0; n >= 4; n >>= 1) e += (size_t)225 * ((2 * n + 3) / 3) * ((2 * n + 3) / 3);
+  return e;
+}
+
+void q2_small_conv_table(int n0, const std::vector<const double*>& tabs, int half, double* out) {
+  size_t base = 0;
+  int l = 0;
+  for (int n = n0; n >= 4; n >>= 1, ++l) {
+    const int nq = 2 * n + 1, per = (nq + 2) / 3, pp = per * per;
+    for (int col = 0; col < 9; ++col)
+      for (int e = 0; e < pp; ++e) {
+        const int gx = col % 3 + 3 * (e % per), gy = col / 3 + 3 * (e / per);
+        const bool in = gx >= 1 && gx <= nq - 2 && gy >= 1 && gy <= nq - 2;
+        for (int k = 0; k < 25; ++k)
+          out[base + (size_t)(col * 25 + k) * pp + e] = in ? tabs[l][((size_t)gy * nq + gx) * 50 + half * 25 + k] : 0.0;
+      }
+    base += (size_t)225 * pp;
+  }
 }
 
 // The Q1 counterpart for the pressure hierarchies (no convection): levels
@@ -921,7 +1096,7 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
   template void launch_schur_combine_pin<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, \
                                             int, int, int, Mask);                                                   \
   template void launch_q2_small_vcycle<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, const OpCoef*,  \
-                                          int, const double2*, int, Mask);                                           \
+                                          int, const double2*, const R*, int, Mask);                                 \
   template void launch_q1_small_vcycle<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, const OpCoef*,  \
                                           int, const double2*, int, Mask);
 

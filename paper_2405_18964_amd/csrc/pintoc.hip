@@ -46,8 +46,8 @@ struct Probe {
     return PINTOC_OK;
   }
   ~Probe() {
-    for (auto e : e0) hipEventDestroy(e);
-    for (auto e : e1) hipEventDestroy(e);
+    for (auto e : e0) (void)hipEventDestroy(e);
+    for (auto e : e1) (void)hipEventDestroy(e);
   }
 };
 
@@ -65,6 +65,8 @@ struct MGPlan {
   OpCoef* coef = nullptr;              // device
   double2* inv = nullptr;              // device
   std::vector<const void*> conv;       // per level (device; Q2: tile layout in the grids' precision) or null
+  const void* sconv = nullptr;         // Q2 small levels n <= sconv_n: per-node table (grids' precision) or null
+  int sconv_n = 0;
   // per-level device buffers (complex, precision-typed): b, x (level >= 1),
   // t (second iterate buffer of the out-of-place smoother), r (residual)
   std::vector<void*> b, x, r, t;
@@ -116,6 +118,9 @@ struct pintoc_problem {
   std::vector<double> conv1_h;                // finest Q1 grid, 18 per node
   std::vector<std::vector<double>> tconv_h[2];  // per level below the coarsest: N, N^T in tile layout
   std::vector<void*> tconv[2];                 // device, in the inner precision (double or float entries)
+  std::vector<double> sconv_h[2];              // levels n <= kQ2SmallN (above the coarsest): per-node layout
+  void* sconv[2] = {nullptr, nullptr};         // device, in the inner precision
+  int sconv_n = 0;                             // finest level of the small tables
   double* conv50 = nullptr;                   // finest level, 50 per node (block and all-at-once matrices)
   double* conv1 = nullptr;
   MGPlan mgQ, mgQH;
@@ -309,6 +314,7 @@ static void carve(pintoc_problem* p, char* base) {
       p->tconv[hf].assign(p->tconv_h[hf].size(), nullptr);
       for (size_t l = 0; l < p->tconv_h[hf].size(); ++l)
         p->tconv[hf][l] = cv.take<char>(p->csize / 2 * p->tconv_h[hf][l].size());
+      p->sconv[hf] = p->sconv_h[hf].empty() ? nullptr : cv.take<char>(p->csize / 2 * p->sconv_h[hf].size());
     }
     p->conv1 = cv.take<double>(sizeof(double) * p->conv1_h.size());
     p->cpsi = cv.take<OpCoef>(sizeof(OpCoef) * nf);
@@ -321,6 +327,9 @@ static void carve(pintoc_problem* p, char* base) {
     p->Pt = cv.take<char>(pbytes);
     p->Ub = cv.take<char>(pbytes);
     for (size_t l = 0; l < p->tconv[0].size(); ++l) { p->mgQ.conv[l] = p->tconv[0][l]; p->mgQH.conv[l] = p->tconv[1][l]; }
+    p->mgQ.sconv = p->sconv[0];
+    p->mgQH.sconv = p->sconv[1];
+    p->mgQ.sconv_n = p->mgQH.sconv_n = p->sconv_n;
     plan_mg_buffers(p->mgQ, cv, p->csize);
     plan_mg_buffers(p->mgQH, cv, p->csize);
   } else {
@@ -542,6 +551,17 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
           q2_tile_conv_table(n, p->conv2_h[l].data(), hf, p->tconv_h[hf].back().data());
         }
     }
+    int l0 = 0;                                   // the levels of the one-launch small V-cycle
+    while ((N >> l0) > kQ2SmallN) ++l0;
+    if (l0 + 1 < nl) {
+      p->sconv_n = N >> l0;
+      std::vector<const double*> tabs;
+      for (int l = l0; l + 1 < nl; ++l) tabs.push_back(p->conv2_h[l].data());
+      for (int hf = 0; hf < 2; ++hf) {
+        p->sconv_h[hf].assign(q2_small_conv_entries(p->sconv_n), 0.0);
+        q2_small_conv_table(p->sconv_n, tabs, hf, p->sconv_h[hf].data());
+      }
+    }
   }
   MGPlan& W = p->mgW;
   W.q2 = true; W.N = N; W.nb = 4 * p->nf; W.fpc = 4; W.ncoef = p->nf; W.fpj = 4;
@@ -632,17 +652,26 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
   if (p->d.flow == PINTOC_OSEEN) {
     HIPCHK(hipMemcpyAsync(p->conv50, p->conv2_h[0].data(), sizeof(double) * p->conv2_h[0].size(),
                           hipMemcpyHostToDevice, s));
-    for (int hf = 0; hf < 2; ++hf)
-      for (size_t l = 0; l < p->tconv[hf].size(); ++l) {
-        const std::vector<double>& t = p->tconv_h[hf][l];
-        if (p->csize == 16) {
-          HIPCHK(hipMemcpyAsync(p->tconv[hf][l], t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, s));
-        } else {                          // FP32 inner solves read FP32 tables
-          const std::vector<float> f(t.begin(), t.end());
-          HIPCHK(hipMemcpyAsync(p->tconv[hf][l], f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, s));
-          HIPCHK(hipStreamSynchronize(s));   // f is a temporary
-        }
+    auto upload = [&](void* dst, const std::vector<double>& t) -> int {
+      if (p->csize == 16) {
+        HIPCHK(hipMemcpyAsync(dst, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, s));
+      } else {                            // FP32 inner solves read FP32 tables
+        const std::vector<float> f(t.begin(), t.end());
+        HIPCHK(hipMemcpyAsync(dst, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));   // f is a temporary
       }
+      return PINTOC_OK;
+    };
+    for (int hf = 0; hf < 2; ++hf) {
+      for (size_t l = 0; l < p->tconv[hf].size(); ++l) {
+        const int rc = upload(p->tconv[hf][l], p->tconv_h[hf][l]);
+        if (rc != PINTOC_OK) return rc;
+      }
+      if (p->sconv[hf]) {
+        const int rc = upload(p->sconv[hf], p->sconv_h[hf]);
+        if (rc != PINTOC_OK) return rc;
+      }
+    }
     HIPCHK(hipMemcpyAsync(p->conv1, p->conv1_h.data(), sizeof(double) * p->conv1_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsi, p->cpsi_h.data(), sizeof(OpCoef) * p->cpsi_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsih, p->cpsih_h.data(), sizeof(OpCoef) * p->cpsih_h.size(), hipMemcpyHostToDevice, s));
@@ -675,8 +704,13 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
     launch_coarse<R>(s, m.q2, x, b, m.inv, m.fpc, m.nb, m.mk());
     return;
   }
-  if (!m.conv[l] && n <= (m.q2 ? kQ2SmallN : kQ1SmallN)) {   // every remaining level in one work-group per grid
-    if (m.q2) launch_q2_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv, m.nb, m.mk());
+  // every remaining level in one work-group per grid (Q2 convection from the
+  // small-level table, which starts at level sconv_n)
+  const bool small = m.q2 ? n <= kQ2SmallN && (!m.conv[l] || (m.sconv && n == m.sconv_n)) : !m.conv[l] && n <= kQ1SmallN;
+  if (small) {
+    if (m.q2)
+      launch_q2_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv,
+                                m.conv[l] ? (const R*)m.sconv : nullptr, m.nb, m.mk());
     else launch_q1_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv, m.nb, m.mk());
     return;
   }
