@@ -709,9 +709,11 @@ __global__ __launch_bounds__(64 * kSmallWaves<L>) void k_q2_small_vcycle(cpx<R>*
 }
 
 // lanes per colour slot of the small Q2 V-cycle: four (512 threads) with
-// convection, where a node's stencil is the longest chain of a colour step
+// convection, where a node's stencil is the longest chain of a colour step,
+// and in FP32, where four 512-thread work-groups still fit a CU; one for FP64
+// without convection (its registers would leave two work-groups per CU)
 template <typename R>
-static int small_lanes(bool cv) { return cv ? 4 : 1; }
+static int small_lanes(bool cv) { return (cv || sizeof(R) == 4) ? 4 : 1; }
 
 template <typename R>
 void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
