@@ -93,7 +93,8 @@ def precond_model_bytes(N: int, nt: int, n_vcycles: int, n_cheb: int, csize: int
     one fused residual/restriction pass (reads x, b, writes the coarse rhs:
     2 + 1/4), the Q1 levels a residual (3) and a restriction (1 + 1/4): 8.5
     (Q2) and 10.5 (Q1) passes per level.  A Chebyshev step reads x_k, x_{k-1},
-    b, writes x_{k+1}.  The FFT pair reads and writes the canonical vector and
+    b, writes x_{k+1}; the first reads b and writes x_1, the second has no
+    x_0 to read (4 n - 3 passes for n steps).  The FFT pair reads and writes the canonical vector and
     the frequency vector once each."""
     nf = nt // 2 + 1
     nq2, np2 = (2 * N + 1) ** 2, (N + 1) ** 2

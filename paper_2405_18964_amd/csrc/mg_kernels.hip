@@ -928,7 +928,8 @@ void launch_q1_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cp
 // mass matrix (Q2 interior or Q1 unconstrained):
 //   first:  xn = g D^{-1} b
 //   else:   xn = w (x - xp + g D^{-1}(b - M x)) + xp
-// xn may alias xp (each thread reads its own xp entry before writing).
+// xn may alias xp (each thread reads its own xp entry before writing);
+// xp == nullptr stands for x_{k-1} = 0 (the second step).
 template <typename R>
 __global__ __launch_bounds__(256) void k_q2_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
                           const cpx<R>* __restrict__ b, int n, double h, double g, double w, int first, Mask mk) {
@@ -956,7 +957,7 @@ __global__ __launch_bounds__(256) void k_q2_cheb(cpx<R>* xn, const cpx<R>* __res
   }
   cpx<R> ax, dg;
   q2_apply_node<R>(x + (size_t)f * nq * nq, nq, ix, iy, h, c, nullptr, ax, dg);
-  const cpx<R> bi = b[i], xi = x[i], pi = xp[i];
+  const cpx<R> bi = b[i], xi = x[i], pi = xp ? xp[i] : cmk<cpx<R>>(0, 0);
   const R d = dg.x;
   cpx<R> v;
   v.x = wr * (xi.x - pi.x + gr * (bi.x - ax.x) / d) + pi.x;
@@ -990,7 +991,7 @@ __global__ __launch_bounds__(256) void k_q1_cheb(cpx<R>* xn, const cpx<R>* __res
     return;
   }
   q1_apply_node<R>(x + (size_t)f * np * np, n, ix, iy, h, c, nullptr, ax, dg);
-  const cpx<R> bi = b[i], xi = x[i], pi = xp[i];
+  const cpx<R> bi = b[i], xi = x[i], pi = xp ? xp[i] : cmk<cpx<R>>(0, 0);
   const R d = dg.x;
   cpx<R> v;
   v.x = wr * (xi.x - pi.x + gr * (bi.x - ax.x) / d) + pi.x;

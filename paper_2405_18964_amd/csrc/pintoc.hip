@@ -752,14 +752,13 @@ static cpx<R>* chebyshev(hipStream_t s, bool q2, int n, int nb, cpx<R>* A, cpx<R
                          double lo, double hi, Mask mk) {
   const double g = 2.0 / (lo + hi), sg = (hi - lo) / (hi + lo);
   const double h = 1.0 / n;
-  const size_t bytes = (q2 ? (size_t)(2 * n + 1) * (2 * n + 1) : (size_t)(n + 1) * (n + 1)) * nb * sizeof(cpx<R>);
   launch_cheb<R>(s, q2, A, A, A, b, n, h, g, 1.0, 1, nb, mk);         // x_1 = g D^{-1} b
-  launch_fill_zero(s, B, bytes);                                       // x_0 = 0
   cpx<R>*cur = A, *prev = B;
   double w = 1.0;
   for (int k = 1; k < steps; ++k) {
     w = k == 1 ? 1.0 / (1.0 - 0.5 * sg * sg) : 1.0 / (1.0 - 0.25 * sg * sg * w);
-    launch_cheb<R>(s, q2, prev, cur, prev, b, n, h, g, w, 0, nb, mk); // x_{k+1} overwrites x_{k-1}
+    // x_{k+1} overwrites x_{k-1}; the step from x_0 = 0 reads no x_{k-1}
+    launch_cheb<R>(s, q2, prev, cur, k == 1 ? nullptr : prev, b, n, h, g, w, 0, nb, mk);
     std::swap(cur, prev);
   }
   return cur;

@@ -668,7 +668,7 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
 // One Chebyshev step for the Q2 mass matrix (not the first):
 //   xn = w (x - xp + g D^{-1} (b - M x)) + xp      (D = diag(M), zero boundary)
 // with M x formed on the LDS tile.  xn may alias xp (each node's xp is read
-// by the thread that writes it).
+// by the thread that writes it); xp == nullptr stands for x_{k-1} = 0.
 template <typename R>
 __global__ __launch_bounds__(256) void k_q2_tile_cheb(cpx<R>* xn, const cpx<R>* __restrict__ x, const cpx<R>* xp,
                                                       const cpx<R>* __restrict__ b, int n, double h, double g,
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(256) void k_q2_tile_cheb(cpx<R>* xn, const cpx<R>* 
       continue;
     }
     const R d = (R)(cm0(gx & 1) * cm0(gy & 1)) * t.ar;
-    const cpx<R> mx = sx[ly * kSP + lx], xi = x[i], pi = xp[i], bi = b[i];
+    const cpx<R> mx = sx[ly * kSP + lx], xi = x[i], pi = xp ? xp[i] : cmk<cpx<R>>(0, 0), bi = b[i];
     cpx<R> v;
     v.x = wr * (xi.x - pi.x + gr * (bi.x - mx.x) / d) + pi.x;
     v.y = wr * (xi.y - pi.y + gr * (bi.y - mx.y) / d) + pi.y;
