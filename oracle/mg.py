@@ -96,6 +96,8 @@ class Levels:
             n //= 2
         self.ops = []
         w = None if wind is None else np.asarray(wind)
+        # largest nodal wind speed of the finest grid (0 without wind)
+        self.wind_max = 0.0 if w is None else float(np.sqrt((w.reshape(2, -1) ** 2).sum(axis=0)).max())
         for l, n in enumerate(self.sizes):
             self.ops.append(Operators(n, 1.0, w))
             if l + 1 < len(self.sizes):
@@ -126,15 +128,30 @@ class Levels:
         return self.P2[l] if fam == "q2" else self.P1[l]
 
 
-class ScalarMG:
-    """V(1,1) multigrid for  alpha M + gamma K + eta N + eta_t N^T."""
+def coarse_viscosity(nu: float, wind_max: float, sizes) -> list:
+    """Viscosity of the multigrid level operators of a convection-diffusion
+    operator: the true nu on the finest level; on a coarser level of n x n
+    elements (side h = 1/n) at least wind_max h / 4, so that its mesh Peclet
+    number wind_max h / (2 nu_l) stays at most 2.  Rediscretising at the true
+    nu makes the V-cycle diverge once the coarse levels are convection
+    dominated (the Gauss-Seidel smoother and the coarse correction both
+    amplify there); the finest level, where the residual is formed, keeps the
+    true operator, so the cycle stays a preconditioner for it."""
+    return [nu if l == 0 else max(nu, wind_max / (4.0 * n)) for l, n in enumerate(sizes)]
 
-    def __init__(self, levels: Levels, fam: str, alpha, gamma, eta=0.0, eta_t=0.0):
+
+class ScalarMG:
+    """V(1,1) multigrid for  alpha M + gamma K + eta N + eta_t N^T.
+
+    ``gamma_levels`` (optional, one value per level) replaces gamma on each
+    level's operator (the finest included)."""
+
+    def __init__(self, levels: Levels, fam: str, alpha, gamma, eta=0.0, eta_t=0.0, gamma_levels=None):
         self.lv, self.fam = levels, fam
         self.A, self.sor = [], []
         for l in range(len(levels.sizes)):
             M, K, N, col, tiles = levels.family(fam, l)
-            A = alpha * M + gamma * K
+            A = alpha * M + (gamma if gamma_levels is None else gamma_levels[l]) * K
             if eta != 0:
                 A = A + eta * N
             if eta_t != 0:

@@ -61,7 +61,7 @@ import scipy.sparse as sp
 
 from . import circulant as circ
 from .krylov import gmres
-from .mg import Levels, ScalarMG
+from .mg import Levels, ScalarMG, coarse_viscosity
 from .smoothers import Q1_MASS_BOUNDS, Q2_MASS_BOUNDS, chebyshev
 
 
@@ -259,11 +259,13 @@ class OseenPreconditioner(_Common):
 
     def Q_mgs(self, j):
         """Multigrid for Q_j = (d + tau/sqrt(beta)) M + tau nu K + tau N and
-        Q_j^H = conj(d + tau/sqrt(beta)) M + tau nu K + tau N^T."""
+        Q_j^H = conj(d + tau/sqrt(beta)) M + tau nu K + tau N^T, with the
+        coarse-level viscosity of ``coarse_viscosity``."""
         if j not in self.mg_Q:
             a, tau, nu = self.q_shift(j), self.P.tau, self.P.nu
-            self.mg_Q[j] = ScalarMG(self.lv, "q2", a, tau * nu, eta=tau)
-            self.mg_QH[j] = ScalarMG(self.lv, "q2", np.conj(a), tau * nu, eta_t=tau)
+            g = [tau * v for v in coarse_viscosity(nu, self.lv.wind_max, self.lv.sizes)]
+            self.mg_Q[j] = ScalarMG(self.lv, "q2", a, tau * nu, eta=tau, gamma_levels=g)
+            self.mg_QH[j] = ScalarMG(self.lv, "q2", np.conj(a), tau * nu, eta_t=tau, gamma_levels=g)
         return self.mg_Q[j], self.mg_QH[j]
 
     def _vec(self, f, x):

@@ -40,14 +40,16 @@ void launch_coarse(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, const dou
 // the rest of a Q2 V-cycle from level n0 <= kQ2SmallN down to N = 2 in one
 // launch, one work-group per grid; x0: initial iterate or null (zero); tconv:
 // the convection table of q2_small_conv_table (scaled by coef.eta) in the
-// grids' precision, or null
+// grids' precision, or null; coef[l cstride + set]: coefficients of the l-th
+// level below n0 (l = 0: n0)
 constexpr int kQ2SmallN = 16;
 template <typename R>
 void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
-                            int fpc, const double2* inv, const R* tconv, int nb, Mask mk);
+                            int cstride, int fpc, const double2* inv, const R* tconv, int nb, Mask mk);
 size_t q2_small_conv_entries(int n0);
 void q2_small_conv_table(int n0, const std::vector<const double*>& tabs, int half, double* out);
-// the same for the unconstrained Q1 hierarchies (n0 <= kQ1SmallN)
+// the same for the unconstrained Q1 hierarchies (n0 <= kQ1SmallN), whose
+// operator is the same on every level (coef: the sets of level n0)
 constexpr int kQ1SmallN = 16;
 template <typename R>
 void launch_q1_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,

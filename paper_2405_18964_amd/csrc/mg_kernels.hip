@@ -586,7 +586,7 @@ __device__ __forceinline__ R small_pw(int r, int q) {
 template <typename R, bool CV, int L>
 __global__ __launch_bounds__(64 * kSmallWaves<L>) void k_q2_small_vcycle(cpx<R>* xg, const cpx<R>* x0,
                                                          const cpx<R>* __restrict__ bg, int n0,
-                                                         const OpCoef* __restrict__ coef, int fpc,
+                                                         const OpCoef* __restrict__ coef, int cstride, int fpc,
                                                          const double2* __restrict__ inv,
                                                          const R* __restrict__ tconv, int nb, Mask mk) {
   // x of every level and b of the coarser levels in LDS (the top level's b is
@@ -595,14 +595,16 @@ __global__ __launch_bounds__(64 * kSmallWaves<L>) void k_q2_small_vcycle(cpx<R>*
   __shared__ cpx<R> xs[kSmallEntries], bsc[kB], rs[sq(2 * kSmallN + 1)];
   const int f = blockIdx.x;
   if (f >= nb || mk.off(f)) return;
-  const OpCoef c = coef[f / fpc];
   int lev = 0, off[8], nn[8], toff[8];
   for (int n = n0, o = 0, t = 0; n >= 2; n >>= 1, ++lev) {
     off[lev] = o; nn[lev] = n; toff[lev] = t;
     o += sq(2 * n + 1);
     t += 225 * sq((2 * n + 3) / 3);
   }
-  auto op = [&](int l) { return small_op<R>(c, nn[l], CV ? tconv + toff[l] : nullptr); };
+  // level l's coefficients: coef[l cstride + set]
+  auto op = [&](int l) {
+    return small_op<R>(coef[(size_t)l * cstride + f / fpc], nn[l], CV ? tconv + toff[l] : nullptr);
+  };
   const int nq0 = 2 * n0 + 1;
   const size_t g0 = (size_t)f * nq0 * nq0;
   const cpx<R>* b0 = bg + g0;
@@ -717,14 +719,14 @@ static int small_lanes(bool cv) { return (cv || sizeof(R) == 4) ? 4 : 1; }
 
 template <typename R>
 void launch_q2_small_vcycle(hipStream_t s, cpx<R>* x, const cpx<R>* x0, const cpx<R>* b, int n0, const OpCoef* coef,
-                            int fpc, const double2* inv, const R* tconv, int nb, Mask mk) {
+                            int cstride, int fpc, const double2* inv, const R* tconv, int nb, Mask mk) {
   const dim3 g((unsigned)nb);
   const bool cv = tconv != nullptr;
   const int L = small_lanes<R>(cv);
 #define PINTOC_SMALL(CV, LL)                                                                                       \
   if (cv == CV && L == LL) {                                                                                      \
-    hipLaunchKernelGGL((k_q2_small_vcycle<R, CV, LL>), g, dim3(64 * kSmallWaves<LL>), 0, s, x, x0, b, n0, coef, fpc, \
-                       inv, tconv, nb, mk);                                                                       \
+    hipLaunchKernelGGL((k_q2_small_vcycle<R, CV, LL>), g, dim3(64 * kSmallWaves<LL>), 0, s, x, x0, b, n0, coef,    \
+                       cstride, fpc, inv, tconv, nb, mk);                                                         \
     return;                                                                                                       \
   }
   PINTOC_SMALL(true, 4)
@@ -1099,7 +1101,7 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
   template void launch_schur_combine_pin<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, \
                                             int, int, int, Mask);                                                   \
   template void launch_q2_small_vcycle<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, const OpCoef*,  \
-                                          int, const double2*, const R*, int, Mask);                                 \
+                                          int, int, const double2*, const R*, int, Mask);                            \
   template void launch_q1_small_vcycle<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, const OpCoef*,  \
                                           int, const double2*, int, Mask);
 

@@ -59,10 +59,12 @@ struct MGPlan {
   int nb = 0;           // grids in the batch
   int fpc = 1;          // grids per coefficient set
   int ncoef = 0;
-  std::vector<OpCoef> coef_h;          // eta scales N, etat scales N^T (coarsest inverses)
-  std::vector<OpCoef> coef_dev_h;      // as uploaded: Q2 tile kernels apply eta to the plan's one table
+  std::vector<OpCoef> coef_h;          // finest level; eta scales N, etat scales N^T
+  std::vector<double> visc;            // per level: real diffusion coefficient replacing gamma (empty: gamma;
+                                       // Q1 plans keep one operator on every level)
+  std::vector<OpCoef> coef_dev_h;      // as uploaded, [level][set]: Q2 tile kernels apply eta to the plan's one table
   std::vector<double2> inv_h;          // coarsest inverses, per coefficient set
-  OpCoef* coef = nullptr;              // device
+  OpCoef* coef = nullptr;              // device, [level][set]
   double2* inv = nullptr;              // device
   std::vector<const void*> conv;       // per level (device; Q2: tile layout in the grids' precision) or null
   const void* sconv = nullptr;         // Q2 small levels n <= sconv_n: per-node table (grids' precision) or null
@@ -75,6 +77,13 @@ struct MGPlan {
   const int* mask = nullptr;           // per-frequency activity (inner GMRES), or null
   int active = 0;                      // grids of the batch that the mask leaves active
   Mask mk() const { return Mask{mask, fpj}; }
+  const OpCoef* coefl(int l) const { return coef + (size_t)l * ncoef; }
+  // coefficient set c on level l (host)
+  OpCoef level_coef(const OpCoef& c, int l) const {
+    OpCoef r = c;
+    if (!visc.empty()) r.gamma = make_double2(visc[l], 0.0);
+    return r;
+  }
   int n(int l) const { return N >> l; }
   size_t nodes(int l) const {
     const size_t m = q2 ? (size_t)(2 * n(l) + 1) : (size_t)(n(l) + 1);
@@ -266,7 +275,7 @@ static void plan_mg_buffers(MGPlan& m, Carver& cv, size_t csize) {
       m.t[l] = cv.take<char>(bytes);
     }
   }
-  m.coef = cv.take<OpCoef>(sizeof(OpCoef) * m.ncoef);
+  m.coef = cv.take<OpCoef>(sizeof(OpCoef) * m.ncoef * m.nlev);
   m.inv = cv.take<double2>(sizeof(double2) * m.inv_h.size());
 }
 
@@ -601,6 +610,21 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   for (MGPlan* m : {&p->mgQ, &p->mgQH}) {
     m->q2 = true; m->N = N; m->nb = 2 * p->nf; m->fpc = 2; m->ncoef = p->nf; m->fpj = 2;
   }
+  if (oseen) {
+    // Coarse-level viscosity of the convection-diffusion multigrid: level l of
+    // n x n elements (side h = 1/n) diffuses with tau max(nu, |w|_max h / 4),
+    // so its mesh Peclet number |w|_max h / (2 nu_l) is at most 2; the finest
+    // level keeps tau nu.  With the true nu on convection-dominated coarse
+    // levels the V-cycle diverges.
+    const int nq = 2 * N + 1;
+    double wmax = 0.0;
+    for (size_t i = 0; i < (size_t)nq * nq; ++i)
+      wmax = std::max(wmax, std::hypot(d->wind[i], d->wind[(size_t)nq * nq + i]));
+    std::vector<double> visc;
+    for (int l = 0; l < nl; ++l) visc.push_back(tau * (l == 0 ? nu : std::max(nu, wmax / (4.0 * (N >> l)))));
+    p->mgQ.visc = visc;
+    p->mgQH.visc = visc;
+  }
   std::vector<MGPlan*> plans = {&K};
   if (oseen) { plans.push_back(&p->mgQ); plans.push_back(&p->mgQH); }
   else plans.push_back(&W);
@@ -608,17 +632,22 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     m->nlev = nl;
     m->conv.assign(nl, nullptr);
     m->active = m->nb;
-    for (OpCoef c : m->coef_h) {          // the Q2 tile kernels take the one nonzero half as eta
-      if (m->q2 && (c.etat.x != 0.0 || c.etat.y != 0.0)) {
-        if (c.eta.x != 0.0 || c.eta.y != 0.0) { delete p; return fail(PINTOC_EINVAL, "operator with N and N^T"); }
-        c.eta = c.etat;
-        c.etat = make_double2(0, 0);
+    for (int l = 0; l < nl; ++l)
+      for (const OpCoef& c0 : m->coef_h) {  // the Q2 tile kernels take the one nonzero half as eta
+        OpCoef c = m->level_coef(c0, l);
+        if (m->q2 && (c.etat.x != 0.0 || c.etat.y != 0.0)) {
+          if (c.eta.x != 0.0 || c.eta.y != 0.0) { delete p; return fail(PINTOC_EINVAL, "operator with N and N^T"); }
+          c.eta = c.etat;
+          c.etat = make_double2(0, 0);
+        }
+        m->coef_dev_h.push_back(c);
       }
-      m->coef_dev_h.push_back(c);
-    }
     const std::vector<double>* cc = (oseen && m->q2) ? &p->conv2_h[nl - 1] : nullptr;
     for (const OpCoef& c : m->coef_h)
-      if (!coarse_inverse(m->q2, c, cc, m->inv_h)) { delete p; return fail(PINTOC_EINVAL, "singular coarse operator"); }
+      if (!coarse_inverse(m->q2, m->level_coef(c, nl - 1), cc, m->inv_h)) {
+        delete p;
+        return fail(PINTOC_EINVAL, "singular coarse operator");
+      }
   }
   carve(p, nullptr);
   *out = p;
@@ -709,9 +738,9 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
   const bool small = m.q2 ? n <= kQ2SmallN && (!m.conv[l] || (m.sconv && n == m.sconv_n)) : !m.conv[l] && n <= kQ1SmallN;
   if (small) {
     if (m.q2)
-      launch_q2_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv,
+      launch_q2_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coefl(l), m.ncoef, m.fpc, m.inv,
                                 m.conv[l] ? (const R*)m.sconv : nullptr, m.nb, m.mk());
-    else launch_q1_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coef, m.fpc, m.inv, m.nb, m.mk());
+    else launch_q1_small_vcycle<R>(s, x, x_zero ? nullptr : x, b, n, m.coefl(l), m.fpc, m.inv, m.nb, m.mk());
     return;
   }
   cpx<R>* t = (cpx<R>*)m.t[l];
@@ -721,7 +750,7 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
   Probe* pr = (l == 0 && m.probe && m.probe->on) ? m.probe : nullptr;
   const int slot = pr ? (int)(pr->count % Probe::kCap) : 0;
   if (pr) (void)hipEventRecord(pr->e0[slot], s);
-  launch_tile_sweep<R>(s, m.q2, t, x_zero ? nullptr : x, b, nullptr, n, h, m.coef, m.fpc, m.nb, m.conv[l], true,
+  launch_tile_sweep<R>(s, m.q2, t, x_zero ? nullptr : x, b, nullptr, n, h, m.coefl(l), m.fpc, m.nb, m.conv[l], true,
                        m.mk());
   if (pr) {
     (void)hipEventRecord(pr->e1[slot], s);
@@ -730,13 +759,13 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
   }
   cpx<R>* r = (cpx<R>*)m.r[l];
   if (m.q2) {
-    launch_q2_residual_restrict<R>(s, bc, r, t, b, n, h, m.coef, m.fpc, m.nb, (const R*)m.conv[l], m.mk());
+    launch_q2_residual_restrict<R>(s, bc, r, t, b, n, h, m.coefl(l), m.fpc, m.nb, (const R*)m.conv[l], m.mk());
   } else {
-    launch_q1_residual<R>(s, r, t, b, n, h, m.coef, m.fpc, m.nb, (const double*)m.conv[l], m.mk());
+    launch_q1_residual<R>(s, r, t, b, n, h, m.coefl(l), m.fpc, m.nb, (const double*)m.conv[l], m.mk());
     launch_q1_restrict<R>(s, bc, r, n / 2, m.nb, m.mk());
   }
   vcycle<R>(s, m, l + 1, xc, bc, true);
-  launch_tile_sweep<R>(s, m.q2, x, t, b, xc, n, h, m.coef, m.fpc, m.nb, m.conv[l], false, m.mk());
+  launch_tile_sweep<R>(s, m.q2, x, t, b, xc, n, h, m.coefl(l), m.fpc, m.nb, m.conv[l], false, m.mk());
 }
 
 // x = MG^cycles(b) from x = 0

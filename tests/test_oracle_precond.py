@@ -12,7 +12,7 @@ from oracle import circulant as circ
 from oracle.fem import Operators
 from oracle.kkt import Problem
 from oracle.krylov import fgmres, gmres
-from oracle.mg import Levels, ScalarMG
+from oracle.mg import Levels, ScalarMG, coarse_viscosity
 from oracle.precond import OseenPreconditioner, StokesPreconditioner, stokes_constants
 from oracle.smoothers import (Q1_MASS_BOUNDS, Q2_MASS_BOUNDS, ColouredSOR, TiledSOR, chebyshev,
                               chebyshev_error_bound, colours_q1, colours_q2, tiles_of)
@@ -350,6 +350,62 @@ def test_vcycle_equals_error_propagation_formula(N, fam, conv):
         x = mg.solve(b, cycles)
         ref = xe - Ek @ xe
         assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(xe)
+
+
+def test_vcycle_error_formula_with_level_viscosity():
+    """The same pin with a different diffusion coefficient on every level
+    (the coarse-level viscosity of the convection-diffusion hierarchies)."""
+    N = 8
+    lv = Levels(N, W.wind_nodal(N))
+    mg = ScalarMG(lv, "q2", 0.9 + 0.4j, 0.07, eta=0.3, gamma_levels=[0.07, 0.21, 0.5])
+    assert not np.allclose(mg.A[1].toarray(), ScalarMG(lv, "q2", 0.9 + 0.4j, 0.07, eta=0.3).A[1].toarray())
+    A = mg.A[0].toarray()
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    E = _vcycle_error_operator(mg, 0)
+    xe = np.linalg.solve(A, b)
+    x = mg.solve(b, 2)
+    assert np.linalg.norm(x - (xe - E @ E @ xe)) <= 1e-11 * np.linalg.norm(xe)
+
+
+def test_coarse_viscosity_closed_form():
+    """nu_l = max(nu, |w|_max h_l / 4) below the finest level; the workload
+    wind (2y(1-x^2), -2x(1-y^2)) peaks at |w| = 2 in the corners (0,1), (1,0)."""
+    lv = Levels(8, W.wind_nodal(8))
+    assert lv.wind_max == pytest.approx(2.0, abs=1e-15)
+    got = coarse_viscosity(0.01, 2.0, [128, 64, 32, 16, 8, 4, 2])
+    assert got == pytest.approx([0.01, 0.01, 1 / 64, 1 / 32, 1 / 16, 1 / 8, 1 / 4], rel=1e-15)
+    # diffusion-dominated: every level keeps nu (the plain rediscretised hierarchy)
+    assert coarse_viscosity(1.0, 2.0, [64, 32, 16, 8, 4, 2]) == [1.0] * 6
+    assert Levels(4).wind_max == 0.0
+
+
+def test_coarse_viscosity_makes_convective_vcycle_contract():
+    """A convection-dominated shifted operator (nu = 0.01, tau = 1/64,
+    beta = 4.7e-3, j = 0): V-cycles on the plainly rediscretised hierarchy
+    diverge after two cycles, with the coarse-level viscosity every cycle
+    contracts."""
+    N, tau, nu, beta = 32, 1.0 / 64, 0.01, 4.7e-3
+    lv = Levels(N, W.wind_nodal(N))
+    a = tau / np.sqrt(beta)
+    g = [tau * v for v in coarse_viscosity(nu, lv.wind_max, lv.sizes)]
+    plain = ScalarMG(lv, "q2", a, tau * nu, eta=tau)
+    visc = ScalarMG(lv, "q2", a, tau * nu, eta=tau, gamma_levels=g)
+    A = plain.A[0]
+    assert abs(A - visc.A[0]).max() == 0.0                 # the finest operator is the true one
+    rng = np.random.default_rng(3)
+    b = A @ (rng.standard_normal(A.shape[0]) + 0j)
+
+    def history(mg):
+        x, out = np.zeros_like(b), []
+        for _ in range(8):
+            x = mg.vcycle(0, b, x)
+            out.append(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+        return out
+
+    hp, hv = history(plain), history(visc)
+    assert hp[7] > hp[1] and hp[7] > 1.0
+    assert all(hv[k + 1] < hv[k] for k in range(7)) and hv[7] < 2e-3
 
 
 def test_linear_stokes_preconditioner_symmetric(stokes4):
