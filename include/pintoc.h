@@ -95,7 +95,8 @@ typedef struct {
                              residual estimate is still above half its start
                              after a restart cycle, and the outer solve when
                              its residual estimate is above half the initial
-                             residual after 10 iterations (NOT_CONVERGED).  A
+                             residual after its first restart cycle, and at
+                             least 10 iterations (NOT_CONVERGED).  A
                              safeguard outside the paper's method for blocks
                              whose multigrid diverges; 0 turns it off.       */
 } pintoc_options;

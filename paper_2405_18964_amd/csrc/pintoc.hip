@@ -1315,8 +1315,9 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
         g[k + 1] = -sn[k] * g[k];
         g[k] = cs[k] * g[k];
         ++its;
-        // stagnation guard: ten iterations without halving the initial residual
-        stalled = p->o.stall_guard && its >= 10 && std::fabs(g[k + 1]) > 0.5 * res0;
+        // stagnation guard: a first restart cycle (at least ten iterations)
+        // without halving the initial residual
+        stalled = p->o.stall_guard && its >= std::max(10, m) && std::fabs(g[k + 1]) > 0.5 * res0;
         if (std::fabs(g[k + 1]) <= p->o.tol * bnorm || breakdown || stalled) { ++k; break; }
       }
       // y = H^{-1} g (upper triangular), x += Z y
