@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond-reps", type=int, default=5)
     ap.add_argument("--no-fp32", action="store_true", help="skip the extra FP32-inner solve")
+    ap.add_argument("--no-minres", action="store_true", help="skip the extra MINRES (Algorithm 1) solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of 1 GiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -288,6 +289,24 @@ def main():
                              "note": "multigrid, Chebyshev, Uzawa and inner GMRES in FP32; outer FGMRES, "
                                      "residuals and the coarsest-grid inverses in FP64"}
         del g32
+    if not args.no_minres and args.precision == "fp64" and w.flow == W.STOKES:
+        # paper variant: MINRES with the linear preconditioner (Algorithm 1), FP64
+        gm = P.Problem.from_workload(w, inner=P.INNER_LINEAR, outer=P.OUTER_MINRES, precision=P.PREC_FP64,
+                                     max_outer=800)
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, stm, okm = gm.solve(b, x)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t1
+        rm = float(torch.linalg.norm(b - gm.kkt_apply(x)) / torch.linalg.norm(b))
+        out["minres_linear_fp64"] = {"solves_per_s": 1.0 / tm, "seconds": tm, "converged": bool(okm),
+                                     "final_rel_residual": rm, "iterations": stm["outer_iterations"],
+                                     "note": "MINRES on the symmetric all-at-once matrix with the symmetric "
+                                             "positive definite linear preconditioner (Algorithm 1), FP64"}
+        print(f"[bench] MINRES + Algorithm 1 (FP64): {stm['outer_iterations']} its, {tm:.2f} s",
+              file=sys.stderr, flush=True)
+        del gm
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, outer, inner_mean)
     print(json.dumps(out), flush=True)

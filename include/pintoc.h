@@ -59,6 +59,13 @@ enum { PINTOC_INNER_LINEAR = 0, PINTOC_INNER_GMRES = 1 };
  * residual recomputation, FFTs and the all-at-once matrix stay FP64. */
 enum { PINTOC_PREC_FP64 = 0, PINTOC_PREC_FP32_INNER = 1 };
 
+/* Outer Krylov method.  FGMRES (section 3.4) takes any preconditioner.
+ * MINRES applies to the Stokes problem with the linear preconditioner
+ * (Algorithm 1): the all-at-once matrix of eq. (FinalA) is symmetric and the
+ * preconditioner symmetric positive definite (section 3.3), so a short
+ * recurrence replaces the Arnoldi basis. */
+enum { PINTOC_OUTER_FGMRES = 0, PINTOC_OUTER_MINRES = 1 };
+
 /* Problem of section 2 (eq. OseenOptimization / OseenFlow) on the unit square,
  * Q2-Q1 Taylor-Hood elements on N x N uniform quadrilaterals (section 2.2),
  * backward Euler with nt steps of tau = T / nt, v_0 = 0, f = 0, h = 0. */
@@ -99,6 +106,15 @@ typedef struct {
                              least 10 iterations (NOT_CONVERGED).  A
                              safeguard outside the paper's method for blocks
                              whose multigrid diverges; 0 turns it off.       */
+  int32_t outer;          /* PINTOC_OUTER_FGMRES (default) or
+                             PINTOC_OUTER_MINRES (Stokes with the linear
+                             preconditioner only, restart >= 4: its vectors
+                             reuse the FGMRES basis; EINVAL otherwise).
+                             MINRES stops on the true residual, formed every
+                             5 steps once its preconditioned residual
+                             estimate is below 100 tol times its start;
+                             outer_iterations counts MINRES steps, capped by
+                             max_outer.                                      */
 } pintoc_options;
 
 /* Statistics of one pintoc_solve call (host memory, filled by the library). */

@@ -120,3 +120,87 @@ def fgmres(matvec, precond, b, tol, restart=10, maxit=200, x0=None):
         if brk and hist[-1] > tol:
             break
     return x, its, hist
+
+
+def minres(matvec, precond, b, tol, maxit=500, x0=None, check_every=0):
+    """Preconditioned MINRES (Paige & Saunders) for a symmetric matrix and a
+    symmetric positive definite preconditioner ``precond`` ~ A^{-1}, real data.
+
+    Lanczos in the inner product of the preconditioner: v_j are the Lanczos
+    vectors, z_j = precond(v_j) / gamma_j with gamma_j^2 = <z_j, v_j>; the
+    tridiagonal T_j (diagonal delta_j, off-diagonal gamma_j) is reduced by
+    Givens rotations and the iterate is advanced along the search directions
+    w_j.  |eta_j| equals the residual norm ||r_j||_{precond} of the j-th
+    iterate, which minimises it over the preconditioned Krylov space.
+
+    check_every = 0: stop when |eta_j| <= tol gamma_1.  check_every = c > 0:
+    stop on the true residual ||b - A x_j||_2 <= tol ||b||_2, tested every c
+    steps once |eta_j| <= 100 tol gamma_1 and at every step where
+    |eta_j| <= tol gamma_1.  Returns (x, iterations, history of
+    |eta_j| / gamma_1, converged on the true residual (check_every > 0))."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    v = b - matvec(x) if x0 is not None else b.copy()
+    bnorm = np.linalg.norm(b)
+    z = precond(v)
+    g = np.sqrt(max(float(v @ z), 0.0))
+    if g == 0.0:
+        return x, 0, [0.0], True
+    g1, eta = g, g
+    v_old = np.zeros_like(b)
+    w_old = np.zeros_like(b)
+    w = np.zeros_like(b)
+    g_old = 1.0
+    c_old, c, s_old, s = 1.0, 1.0, 0.0, 0.0
+    hist, its, done = [1.0], 0, False
+    while its < maxit:
+        z = z / g
+        Az = matvec(z)
+        delta = float(Az @ z)
+        v_new = Az - (delta / g) * v - (g / g_old) * v_old
+        z_new = precond(v_new)
+        g2 = float(v_new @ z_new)
+        g_new = np.sqrt(max(g2, 0.0))
+        a0 = c * delta - c_old * s * g
+        a1 = np.hypot(a0, g_new)
+        a2 = s * delta + c_old * c * g
+        a3 = s_old * g
+        if not a1 > 0:
+            break
+        c_old, s_old = c, s
+        c, s = a0 / a1, g_new / a1
+        w_new = (z - a3 * w_old - a2 * w) / a1
+        x = x + (c * eta) * w_new
+        eta = -s * eta
+        its += 1
+        hist.append(abs(eta) / g1)
+        if check_every:
+            if abs(eta) <= tol * g1 or (abs(eta) <= 100 * tol * g1 and its % check_every == 0):
+                if np.linalg.norm(b - matvec(x)) <= tol * bnorm:
+                    done = True
+                    break
+        elif abs(eta) <= tol * g1:
+            break
+        if not g2 > 0:
+            break
+        v_old, v, z, g_old, g = v, v_new, z_new, g, g_new
+        w_old, w = w, w_new
+    return x, its, hist, done
+
+
+def minres_restarted(matvec, precond, b, tol, maxit=500, check_every=5):
+    """MINRES stopping on the true residual ||b - A x||_2 <= tol ||b||_2
+    (``minres`` with check_every), started again from the iterate only if the
+    recurrence breaks down first.  Returns (x, iterations, true relative
+    residual at the end of every run)."""
+    bnorm = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    if bnorm == 0:
+        return x, 0, [0.0]
+    its, hist = 0, []
+    while its < maxit:
+        x, k, _, done = minres(matvec, precond, b, tol, maxit - its, x0=x if its else None, check_every=check_every)
+        its += k
+        hist.append(np.linalg.norm(b - matvec(x)) / bnorm)
+        if done or hist[-1] <= tol or k == 0:
+            break
+    return x, its, hist

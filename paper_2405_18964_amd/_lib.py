@@ -10,6 +10,7 @@ _LIB_PATH = os.path.join(HERE, "libpintoc.so")
 STOKES, OSEEN = 0, 1
 INNER_LINEAR, INNER_GMRES = 0, 1
 PREC_FP64, PREC_FP32_INNER = 0, 1
+OUTER_FGMRES, OUTER_MINRES = 0, 1
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -27,7 +28,7 @@ class Options(C.Structure):
                 ("max_outer", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("inner_restart", C.c_int32), ("inner_maxit", C.c_int32), ("n_vcycles", C.c_int32),
                 ("n_cheb", C.c_int32), ("n_uzawa", C.c_int32), ("mu_uzawa", C.c_double),
-                ("stall_guard", C.c_int32)]
+                ("stall_guard", C.c_int32), ("outer", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -92,6 +92,8 @@ void launch_mdot(hipStream_t s, const double* V, size_t ld, int k, const double*
                  double* out);
 void launch_mgs_update(hipStream_t s, double* w, const double* V, size_t ld, int k, const double* c, size_t n);
 void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b, size_t n);
+void launch_axpbypcz(hipStream_t s, double* y, const double* x, const double* z, double a, double b, double c,
+                     size_t n);
 void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, int k, const double* c, size_t n);
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
 

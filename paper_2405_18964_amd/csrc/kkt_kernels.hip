@@ -277,6 +277,19 @@ void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b,
   hipLaunchKernelGGL(k_axpby, dim3(2048), dim3(256), 0, s, y, x, a, b, n);
 }
 
+// y = a x + b z + c y (the three-term updates of MINRES)
+__global__ __launch_bounds__(256) void k_axpbypcz(double* __restrict__ y, const double* __restrict__ x,
+                                                  const double* __restrict__ z, double a, double b, double c,
+                                                  size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * z[i] + c * y[i];
+}
+
+void launch_axpbypcz(hipStream_t s, double* y, const double* x, const double* z, double a, double b, double c,
+                     size_t n) {
+  hipLaunchKernelGGL(k_axpbypcz, dim3(2048), dim3(256), 0, s, y, x, z, a, b, c, n);
+}
+
 void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, int k, const double* c, size_t n) {
   hipLaunchKernelGGL(k_lincomb_add, dim3(2048), dim3(256), 0, s, y, Z, ld, k, c, n);
 }

@@ -445,6 +445,7 @@ extern "C" int pintoc_default_options(pintoc_options* o) {
   o->n_uzawa = 6;
   o->mu_uzawa = 0.75;
   o->stall_guard = 1;
+  o->outer = PINTOC_OUTER_FGMRES;
   return PINTOC_OK;
 }
 
@@ -515,6 +516,11 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   if (opt.restart < 1 || opt.restart > 60 || opt.max_outer < 1 || !(opt.tol > 0) || opt.n_vcycles < 1 ||
       opt.n_cheb < 1 || (opt.stall_guard != 0 && opt.stall_guard != 1))
     return fail(PINTOC_EINVAL, "invalid solver options");
+  if (opt.outer != PINTOC_OUTER_FGMRES && opt.outer != PINTOC_OUTER_MINRES)
+    return fail(PINTOC_EINVAL, "unknown outer method");
+  if (opt.outer == PINTOC_OUTER_MINRES &&
+      (d->flow != PINTOC_STOKES || opt.inner != PINTOC_INNER_LINEAR || opt.restart < 4))
+    return fail(PINTOC_EINVAL, "MINRES needs the Stokes flow, the linear preconditioner and restart >= 4");
   auto* p = new pintoc_problem();
   p->d = *d;
   p->d.wind = nullptr;
@@ -1243,6 +1249,103 @@ static int dots(pintoc_problem* p, hipStream_t s, const double* V, int k, const 
   return PINTOC_OK;
 }
 
+// Preconditioned MINRES (Paige & Saunders) on the symmetric all-at-once
+// matrix with the symmetric positive definite linear preconditioner of
+// Algorithm 1 (section 3.3), FP64, from the iterate in x.  Lanczos in the
+// preconditioner's inner product: z_j = P^{-1} v_j / gamma_j with
+// gamma_j^2 = <P^{-1} v_j, v_j>, delta_j = <A z_j, z_j>,
+// v_{j+1} = A z_j - (delta_j / gamma_j) v_j - (gamma_j / gamma_{j-1}) v_{j-1};
+// the tridiagonal matrix is reduced by Givens rotations (c, s) and x moves
+// along w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j) / a1.  |eta| is the residual norm
+// in the preconditioner's inner product.  The true residual decides the stop:
+// it is formed every kMinresCheck steps once |eta| <= 100 tol |eta_0| and at
+// every step with |eta| <= tol |eta_0|.  A breakdown of the recurrence starts
+// it again from x.  Vectors: v_{j-1}, v_j, w_{j-1}, w_j, A z in the FGMRES
+// basis V, z_j and P^{-1} v_{j+1} in Z.  Returns PINTOC_OK or an error; its,
+// res (true residual norm) and conv report the outcome.
+constexpr int kMinresCheck = 5;
+
+static int solve_minres(pintoc_problem* p, const double* b, double* x, double bnorm, hipStream_t s, int& its,
+                        double& res, bool& conv) {
+  const size_t n = (size_t)p->n_all;
+  double hb[2];
+  int rc;
+  double* V[2] = {p->Vk, p->Vk + n};                       // v_{j-1} (then v_{j+1}), v_j
+  double* Wv[2] = {p->Vk + 2 * n, p->Vk + 3 * n};          // w_{j-1} (then w_{j+1}), w_j
+  double* AZ = p->Vk + 4 * n;
+  auto true_residual = [&]() -> int {
+    kkt(p, x, p->rvec, s);
+    launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
+    int r = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb);
+    res = std::sqrt(hb[0]);
+    return r;
+  };
+  if ((rc = true_residual())) return rc;
+  while (true) {
+    if (!std::isfinite(res)) return PINTOC_OK;
+    if (res <= p->o.tol * bnorm) { conv = true; return PINTOC_OK; }
+    if (its >= p->o.max_outer) return PINTOC_OK;
+    double* Zc = p->Zk;                                    // z_j
+    double* Zn = p->Zk + n;                                // P^{-1} v_{j+1}
+    // v_1 = r, z = P^{-1} v_1, gamma_1 = sqrt(<z, v_1>)
+    launch_axpby(s, V[1], p->rvec, 1.0, 0.0, n);
+    if ((rc = precond(p, V[1], Zc, s))) return rc;
+    if ((rc = dots(p, s, V[1], 1, Zc, p->dd, hb))) return rc;
+    if (!(hb[0] > 0)) return PINTOC_OK;                    // not positive definite
+    double g = std::sqrt(hb[0]), g_old = 1.0;
+    const double g1 = g;
+    double eta = g, c_old = 1.0, c = 1.0, s_old = 0.0, sn = 0.0;
+    launch_fill_zero(s, V[0], n * sizeof(double));
+    launch_fill_zero(s, Wv[0], n * sizeof(double));
+    launch_fill_zero(s, Wv[1], n * sizeof(double));
+    const int its0 = its;
+    bool checked = false;
+    while (its < p->o.max_outer) {
+      launch_axpby(s, Zc, Zc, 1.0 / g, 0.0, n);             // z_j
+      kkt(p, Zc, AZ, s);
+      if ((rc = dots(p, s, AZ, 1, Zc, p->dd, hb))) return rc;
+      const double delta = hb[0];
+      // v_{j+1} over v_{j-1}
+      launch_axpbypcz(s, V[0], AZ, V[1], 1.0, -delta / g, -g / g_old, n);
+      if ((rc = precond(p, V[0], Zn, s))) return rc;
+      if ((rc = dots(p, s, V[0], 1, Zn, p->dd, hb))) return rc;
+      const double g2 = hb[0];
+      const double g_new = std::sqrt(std::max(g2, 0.0));
+      const double a0 = c * delta - c_old * sn * g;
+      const double a1 = std::hypot(a0, g_new);
+      const double a2 = sn * delta + c_old * c * g;
+      const double a3 = s_old * g;
+      if (!(a1 > 0) || !std::isfinite(a1)) break;
+      c_old = c;
+      s_old = sn;
+      c = a0 / a1;
+      sn = g_new / a1;
+      // w_{j+1} over w_{j-1}, then x += c eta w_{j+1}
+      launch_axpbypcz(s, Wv[0], Zc, Wv[1], 1.0 / a1, -a2 / a1, -a3 / a1, n);
+      launch_axpby(s, x, Wv[0], c * eta, 1.0, n);
+      eta = -sn * eta;
+      ++its;
+      const double e = std::fabs(eta);
+      checked = false;
+      if (e <= p->o.tol * g1 || (e <= 100.0 * p->o.tol * g1 && (its - its0) % kMinresCheck == 0)) {
+        if ((rc = true_residual())) return rc;
+        checked = true;
+        if (res <= p->o.tol * bnorm) { conv = true; return PINTOC_OK; }
+      }
+      if (!(g2 > 0)) break;
+      std::swap(V[0], V[1]);
+      std::swap(Wv[0], Wv[1]);
+      std::swap(Zc, Zn);
+      g_old = g;
+      g = g_new;
+    }
+    // breakdown or the iteration cap: start again from x (the loop head stops at the cap)
+    const double prev = res;
+    if (!checked && (rc = true_residual())) return rc;
+    if (its == its0 || !(res < prev || checked)) return PINTOC_OK;
+  }
+}
+
 extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pintoc_solve_stats* st, void* stream) {
   int rc = check_ready(p);
   if (rc) return rc;
@@ -1264,6 +1367,8 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
   if (bnorm == 0.0) {
     launch_fill_zero(s, x, n * sizeof(double));
     conv = true;
+  } else if (p->o.outer == PINTOC_OUTER_MINRES) {
+    if ((rc = solve_minres(p, b, x, bnorm, s, its, res, conv))) return rc;
   } else {
     // r = b - A x
     kkt(p, x, p->rvec, s);

@@ -178,3 +178,31 @@ def test_solve_config1_gmres(lib):
     xh, bh = _host(x), _host(b)
     xs = op.to_canonical(op.solve_direct(op.to_compact(bh)))
     assert np.linalg.norm(xh - xs) <= 1e-5 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("N,nt,beta", [(8, 16, 1e-2), (8, 32, 1e-4)])
+def test_solve_minres_parity(lib, N, nt, beta):
+    """MINRES with the linear preconditioner (Algorithm 1): the same number of
+    steps as the oracle's restarted MINRES, the same iterate to 1e-8 relative
+    (the two preconditioners agree to 1e-10 per application), a true residual
+    of at most 1e-8 and the sparse direct solution to 1e-6."""
+    from oracle.kkt import Problem as OP
+    from oracle.krylov import minres_restarted
+    from oracle.precond import StokesPreconditioner
+    print(f"solve minres N={N} nt={nt}", flush=True)
+    w = W.small(W.STOKES, N, nt, beta=beta)
+    gp = lib.Problem.from_workload(w, outer=lib.OUTER_MINRES, max_outer=400)
+    b = gp.assemble_rhs(_dev(W.desired_state(w)))
+    x, st, ok = gp.solve(b)
+    assert ok and st["rel_residual"] <= 1e-8
+    op = OP.from_workload(w)
+    bh, xh = _host(b), _host(x)
+    pc = StokesPreconditioner(op)
+    A = op.kkt_matrix()
+    xo, its, hist = minres_restarted(lambda v: A @ v, lambda v: pc.apply(v), op.to_compact(bh), 1e-8)
+    assert st["outer_iterations"] == its
+    xo = op.to_canonical(xo)
+    assert np.linalg.norm(xh - xo) <= 1e-8 * np.linalg.norm(xo)
+    xs = op.to_canonical(op.solve_direct(op.to_compact(bh)))
+    assert np.linalg.norm(xh - xs) <= 1e-6 * np.linalg.norm(xs)
+    assert np.all(xh[~W.canonical_mask(N, nt)] == 0)

@@ -51,6 +51,15 @@ def test_host_validation(lib):
     assert o.stall_guard == 1
     bad_opt = default_options(stall_guard=2)
     assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(bad_opt), ctypes.byref(h)) == -1
+    # MINRES: outer method 1 needs the Stokes flow, the linear preconditioner and restart >= 4
+    assert o.outer == 0
+    for bad_opt in (default_options(outer=2), default_options(outer=1, inner=1), default_options(outer=1, restart=3)):
+        assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(bad_opt), ctypes.byref(h)) == -1
+    wind = (ctypes.c_double * (2 * 17 * 17))()
+    oseen = Desc(8, 16, 1.0, 1.0, 1e-2, 1, ctypes.cast(wind, ctypes.POINTER(ctypes.c_double)))
+    assert lib.pintoc_problem_create(ctypes.byref(oseen), ctypes.byref(default_options(outer=1)), ctypes.byref(h)) == -1
+    assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(default_options(outer=1)), ctypes.byref(h)) == 0
+    lib.pintoc_problem_destroy(h)
     assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(o), ctypes.byref(h)) == 0
     assert lib.pintoc_vector_length(h) == 2 * 16 * (2 * 17 ** 2 + 9 ** 2)
     assert lib.pintoc_workspace_bytes(h) > 0
