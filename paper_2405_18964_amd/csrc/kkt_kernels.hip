@@ -13,44 +13,6 @@
 
 namespace pintoc {
 
-// Weighted Q2 stencil sums at interior node (ix, iy) of one scalar grid:
-// returns M u and K u (and N u, N^T u when a convection table is given).
-// Offsets +-2 have zero weight at midpoint nodes next to the boundary; their
-// indices are clamped so that every load stays inside the grid.
-__device__ inline void q2_mk(const double* __restrict__ u, int nq, int ix, int iy, double h, const double* mx,
-                             const double* kx, const double* my, const double* ky, double& mu, double& ku) {
-  mu = 0; ku = 0;
-  int cx[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) cx[d] = min(max(ix + d - 2, 0), nq - 1);
-#pragma unroll
-  for (int dy = 0; dy < 5; ++dy) {
-    const double* row = u + min(max(iy + dy - 2, 0), nq - 1) * nq;
-    double sm = 0, sk = 0;
-#pragma unroll
-    for (int dx = 0; dx < 5; ++dx) { sm += mx[dx] * row[cx[dx]]; sk += kx[dx] * row[cx[dx]]; }
-    mu += my[dy] * sm;
-    ku += ky[dy] * sm + my[dy] * sk;
-  }
-}
-
-__device__ inline void q2_conv(const double* __restrict__ u, int nq, int ix, int iy, const double* cn,
-                               double& nu_, double& ntu) {
-  nu_ = 0; ntu = 0;
-  int cx[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) cx[d] = min(max(ix + d - 2, 0), nq - 1);
-#pragma unroll
-  for (int dy = 0; dy < 5; ++dy) {
-    const double* row = u + min(max(iy + dy - 2, 0), nq - 1) * nq;
-#pragma unroll
-    for (int dx = 0; dx < 5; ++dx) {
-      nu_ += cn[dy * 5 + dx] * row[cx[dx]];
-      ntu += cn[25 + dy * 5 + dx] * row[cx[dx]];
-    }
-  }
-}
-
 // (B^T q)_comp at Q2 node (jx, jy): -sum mix(ky,jy) gmix(kx,jx) q (comp 0) or
 // -sum gmix(ky,jy) mix(kx,jx) q (comp 1).
 __device__ inline double bt_node(const double* __restrict__ q, int n, double h, int jx, int jy, int comp) {
@@ -94,11 +56,12 @@ __device__ inline double b_node(const double* __restrict__ vx, const double* __r
   return -s;
 }
 
+// One thread per entry g >= g0 of the canonical vector.
 __global__ __launch_bounds__(256) void k_kkt_apply(const double* __restrict__ x, double* __restrict__ y, int n, int nt, double tau,
-                            double beta, double nu, const double* __restrict__ conv) {
+                            double beta, double nu, const double* __restrict__ conv, int g0) {
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int L = 2 * nq2 + np2;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = g0 + blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y, b = blockIdx.z;
   if (g >= L) return;
   const double h = 1.0 / n;
@@ -113,28 +76,45 @@ __global__ __launch_bounds__(256) void k_kkt_apply(const double* __restrict__ x,
       double mx[5], kx[5], my[5], ky[5];
       q2_rows(ix, h, mx, kx);
       q2_rows(iy, h, my, ky);
+      // One pass over the 25 neighbours.  Adjoint rows (b = 0):
+      //   M (tau v_t + l_t - l_{t+1}) + tau nu K l_t + tau N^T l_t + tau B^T mu_t;
+      // state rows (b = 1):
+      //   M (v_t - v_{t-1} - tau/beta l_t) + tau nu K v_t + tau N v_t + tau B^T p_t.
+      // The mass term acts on one combined field, the stiffness and convection
+      // terms on the field u they differentiate (l_t, resp. v_t).
       const double* vt = lev(X0, t) + comp * nq2;
       const double* lt = lev(X1, t) + comp * nq2;
-      double Mv, Kv, Ml, Kl;
-      q2_mk(vt, nq, ix, iy, h, mx, kx, my, ky, Mv, Kv);
-      q2_mk(lt, nq, ix, iy, h, mx, kx, my, ky, Ml, Kl);
-      double Nv = 0, NTv = 0, Nl = 0, NTl = 0;
-      if (conv) {
-        const double* cn = conv + (size_t)node * 50;
-        q2_conv(vt, nq, ix, iy, cn, Nv, NTv);
-        q2_conv(lt, nq, ix, iy, cn, Nl, NTl);
+      const double* un = b == 0 ? (t + 1 < nt ? lev(X1, t + 1) + comp * nq2 : nullptr)
+                                : (t > 0 ? lev(X0, t - 1) + comp * nq2 : nullptr);
+      const double ca = b == 0 ? tau : 1.0, cb = b == 0 ? 1.0 : -tau / beta;   // mass field ca v_t + cb l_t - un
+      const double* cn = conv ? conv + (size_t)node * 50 + (b == 0 ? 25 : 0) : nullptr;
+      int cx[5];
+#pragma unroll
+      for (int d = 0; d < 5; ++d) cx[d] = min(max(ix + d - 2, 0), nq - 1);
+      // per row: x-mass sums of the mass field (sm) and of u (su), x-stiffness
+      // sums of u (sk); M = m'_y (m'_x .), K = m'_y (k'_x .) + k'_y (m'_x .)
+      double mm = 0, kk = 0, cc = 0;
+#pragma unroll 1
+      for (int dy = 0; dy < 5; ++dy) {
+        const size_t ro = (size_t)min(max(iy + dy - 2, 0), nq - 1) * nq;
+        double sm = 0, sk = 0, su = 0;
+#pragma unroll
+        for (int dx = 0; dx < 5; ++dx) {
+          const double vv = vt[ro + cx[dx]], ll = lt[ro + cx[dx]];
+          const double un_v = un ? un[ro + cx[dx]] : 0.0;
+          const double u = b == 0 ? ll : vv;
+          const double f = ca * vv + cb * ll - un_v;
+          sm += mx[dx] * f;
+          sk += kx[dx] * u;
+          su += mx[dx] * u;
+          if (cn) cc += cn[dy * 5 + dx] * u;
+        }
+        mm += my[dy] * sm;
+        kk += my[dy] * sk + ky[dy] * su;
       }
-      if (b == 0) {
-        double Mln = 0, dummy;
-        if (t + 1 < nt) q2_mk(lev(X1, t + 1) + comp * nq2, nq, ix, iy, h, mx, kx, my, ky, Mln, dummy);
-        const double btmu = bt_node(lev(X1, t) + 2 * nq2, n, h, ix, iy, comp);
-        out = tau * Mv + (Ml - Mln) + tau * (nu * Kl + NTl) + tau * btmu;
-      } else {
-        double Mvp = 0, dummy;
-        if (t > 0) q2_mk(lev(X0, t - 1) + comp * nq2, nq, ix, iy, h, mx, kx, my, ky, Mvp, dummy);
-        const double btp = bt_node(lev(X0, t) + 2 * nq2, n, h, ix, iy, comp);
-        out = (Mv - Mvp) + tau * (nu * Kv + Nv) + tau * btp - (tau / beta) * Ml;
-      }
+      const double* pf = b == 0 ? lev(X1, t) + 2 * nq2 : lev(X0, t) + 2 * nq2;
+      const double bt = bt_node(pf, n, h, ix, iy, comp);
+      out = mm + tau * (nu * kk + cc) + tau * bt;
     }
   } else {
     const int k = g - 2 * nq2;
@@ -145,6 +125,130 @@ __global__ __launch_bounds__(256) void k_kkt_apply(const double* __restrict__ x,
     }
   }
   y[((size_t)b * nt + t) * L + g] = out;
+}
+
+// Velocity rows without convection (Stokes), column strips.  Thread (ix, strip)
+// of grid (b, t, comp) walks the rows of its strip downwards.  M and K are
+// tensor products of 1-D rows (M = m'_y (m'_x .), K = m'_y (k'_x .) +
+// k'_y (m'_x .)), so per input row y' it forms the x-sums at column ix once --
+// sm (m'_x on the mass field ca v_t + cb l_t - un), sk (k'_x on u), su
+// (m'_x on u) -- and keeps those of rows y - 2 .. y + 2 in registers: 15 loads
+// per output row instead of 75.  The x-weights depend on the parity of ix
+// only; rows outside the grid contribute zero (their y-weights vanish).
+// Entry (k, j = 2k + off) of the 1-D mixed Q1-Q2 mass (m) and derivative (g)
+// rows, the same values as mixed_rows(k) at index off + 2 (zero outside).
+__device__ __forceinline__ void mixed_at(int k, int off, int n, double h, double& m, double& g) {
+  m = 0.0;
+  g = 0.0;
+  if (k < 0 || k > n || off < -2 || off > 2) return;
+  const bool lo = k > 0, hi = k < n;
+  switch (off) {
+    case -2: g = lo ? -1.0 / 6.0 : 0.0; break;
+    case -1: m = lo ? h / 3.0 : 0.0; g = lo ? -2.0 / 3.0 : 0.0; break;
+    case 0: m = (lo ? h / 6.0 : 0.0) + (hi ? h / 6.0 : 0.0); g = (lo ? 5.0 / 6.0 : 0.0) + (hi ? -5.0 / 6.0 : 0.0); break;
+    case 1: m = hi ? h / 3.0 : 0.0; g = hi ? 2.0 / 3.0 : 0.0; break;
+    default: g = hi ? 1.0 / 6.0 : 0.0; break;
+  }
+}
+
+constexpr int kKStrip = 16;                 // rows per thread
+
+__global__ __launch_bounds__(256) void k_kkt_vel_strips(const double* __restrict__ x, double* __restrict__ y, int n,
+                                                        int nt, double tau, double beta, double nu, int ncb,
+                                                        int nstrip) {
+  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
+  const int L = 2 * nq2 + np2;
+  const int t = blockIdx.y, bc = blockIdx.z, b = bc >> 1, comp = bc & 1;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cb = blockIdx.x % ncb, st = (blockIdx.x / ncb) * 4 + w;
+  const int ix = cb * 64 + lane;
+  if (ix >= nq || st >= nstrip) return;
+  const int y0 = st * kKStrip, y1 = min(y0 + kKStrip, nq);
+  const double* X0 = x;
+  const double* X1 = x + (size_t)nt * L;
+  const double* vt = X0 + (size_t)t * L + comp * nq2;
+  const double* lt = X1 + (size_t)t * L + comp * nq2;
+  const double* un = b == 0 ? (t + 1 < nt ? X1 + (size_t)(t + 1) * L + comp * nq2 : nullptr)
+                            : (t > 0 ? X0 + (size_t)(t - 1) * L + comp * nq2 : nullptr);
+  const double* pf = (b == 0 ? X1 : X0) + (size_t)t * L + 2 * nq2;
+  const double ca = b == 0 ? tau : 1.0, cb2 = b == 0 ? 1.0 : -tau / beta;
+  double* yo = y + ((size_t)b * nt + t) * L + comp * nq2;
+  const bool xin = ix >= 1 && ix <= nq - 2;
+  if (!xin) {                                 // boundary column: zero rows
+    for (int iy = y0; iy < y1; ++iy) yo[(size_t)iy * nq + ix] = 0.0;
+    return;
+  }
+  const double h = 1.0 / n;
+  double mx[5], kx[5], my[5], ky[5];
+  q2_rows(ix, h, mx, kx);
+  int cx[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) cx[d] = min(max(ix + d - 2, 0), nq - 1);
+  // B^T at this column: x-weights of the Q1 nodes kx0 .. kx0 + 2 (fixed per
+  // thread: the derivative row for component 0, the mass row for component 1)
+  const int kx0 = (ix >> 1) - 1;
+  double wbx[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double m, g;
+    mixed_at(kx0 + c, ix - 2 * (kx0 + c), n, h, m, g);
+    wbx[c] = comp == 0 ? g : m;
+  }
+  auto btq = [&](int iy) -> double {          // (B^T q)_comp at (ix, iy), q = p_t or mu_t
+    const int ky0 = (iy >> 1) - 1;
+    double sum = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int ky = ky0 + a;
+      if (ky < 0 || ky > n) continue;
+      double m, g;
+      mixed_at(ky, iy - 2 * ky, n, h, m, g);
+      const double* row = pf + (size_t)ky * np;
+      double rs = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int kx = kx0 + c;
+        if (kx >= 0 && kx <= n) rs += wbx[c] * row[kx];
+      }
+      sum += (comp == 0 ? m : g) * rs;
+    }
+    return -sum;
+  };
+  auto rowsums = [&](int yr, double& sm, double& sk, double& su) {
+    sm = 0; sk = 0; su = 0;
+    if (yr < 0 || yr >= nq) return;
+    const size_t ro = (size_t)yr * nq;
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) {
+      const double vv = vt[ro + cx[dx]], ll = lt[ro + cx[dx]];
+      const double uv = un ? un[ro + cx[dx]] : 0.0;
+      const double u = b == 0 ? ll : vv;
+      sm += mx[dx] * (ca * vv + cb2 * ll - uv);
+      sk += kx[dx] * u;
+      su += mx[dx] * u;
+    }
+  };
+  double SM[5] = {0, 0, 0, 0, 0}, SK[5] = {0, 0, 0, 0, 0}, SU[5] = {0, 0, 0, 0, 0};   // rows iy - 2 .. iy + 2
+  // the first four steps only fill the window (rows y0 - 2 .. y0 + 1)
+#pragma unroll 1
+  for (int iy = y0 - 4; iy < y1; ++iy) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) { SM[d] = SM[d + 1]; SK[d] = SK[d + 1]; SU[d] = SU[d + 1]; }
+    rowsums(iy + 2, SM[4], SK[4], SU[4]);
+    if (iy < y0) continue;
+    double out = 0.0;
+    if (iy >= 1 && iy <= nq - 2) {
+      q2_rows(iy, h, my, ky);
+      double mm = 0, kk = 0;
+#pragma unroll
+      for (int d = 0; d < 5; ++d) {
+        mm += my[d] * SM[d];
+        kk += my[d] * SK[d] + ky[d] * SU[d];
+      }
+      out = mm + tau * nu * kk + tau * btq(iy);
+    }
+    yo[(size_t)iy * nq + ix] = out;
+  }
 }
 
 // b = tau M v_d on the adjoint momentum rows, zero elsewhere.
@@ -185,8 +289,19 @@ __global__ __launch_bounds__(256) void k_assemble_rhs(const double* __restrict__
 
 void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,
                       const double* conv) {
-  const int L = 2 * (2 * n + 1) * (2 * n + 1) + (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_kkt_apply, dim3((L + 255) / 256, nt, 2), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, conv);
+  const int nq = 2 * n + 1, L = 2 * nq * nq + (n + 1) * (n + 1);
+  if (conv) {                               // Oseen: every entry per thread
+    hipLaunchKernelGGL(k_kkt_apply, dim3((L + 255) / 256, nt, 2), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, conv,
+                       0);
+    return;
+  }
+  // Stokes: velocity rows by column strips, pressure rows per entry
+  const int ncb = (nq + 63) / 64, nstrip = (nq + kKStrip - 1) / kKStrip;
+  hipLaunchKernelGGL(k_kkt_vel_strips, dim3(ncb * ((nstrip + 3) / 4), nt, 4), dim3(256), 0, s, x, y, n, nt, tau, beta,
+                     nu, ncb, nstrip);
+  const int g0 = 2 * nq * nq, np2 = (n + 1) * (n + 1);
+  hipLaunchKernelGGL(k_kkt_apply, dim3((np2 + 255) / 256, nt, 2), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, conv,
+                     g0);
 }
 
 void launch_assemble_rhs(hipStream_t s, const double* vd, double* b, int n, int nt, double tau) {
