@@ -126,7 +126,9 @@ typedef struct {
   int32_t inner_iterations_max;
   int32_t precond_applications;
   double seconds;                /* host wall time of the call              */
-  double model_bytes;            /* modelled compulsory HBM traffic         */
+  double model_bytes;            /* reserved, 0 (the HBM byte model of a
+                                    preconditioner application is kept by
+                                    the benchmark driver)                  */
 } pintoc_solve_stats;
 
 /* Fill *o with the defaults above.  Never fails for a non-NULL pointer. */
