@@ -69,8 +69,18 @@ __global__ __launch_bounds__(256) void k_fdot(const cpx<R>* __restrict__ bV, con
 __global__ __launch_bounds__(256) void k_fdot_reduce(const double2* __restrict__ part, int k, int nf, int nch, double2* __restrict__ out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= k * nf) return;
+  // sequential sum in chunk order; the unrolled loads are issued ahead of the adds
   double sr = 0, si = 0;
-  for (int c = 0; c < nch; ++c) { const double2 v = part[(size_t)t * nch + c]; sr += v.x; si += v.y; }
+  const double2* pt = part + (size_t)t * nch;
+  int c = 0;
+  for (; c + 8 <= nch; c += 8) {
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = pt[c + q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) { sr += v[q].x; si += v[q].y; }
+  }
+  for (; c < nch; ++c) { const double2 v = pt[c]; sr += v.x; si += v.y; }
   out[t] = make_double2(sr, si);
 }
 
