@@ -109,3 +109,28 @@ def test_oseen_precond_single_frequency_full_size(lib):
     pc = OseenPreconditioner(op, wind, freqs=[j, w.nt - j])
     ref = op.to_canonical(pc.apply(op.to_compact(r), nonlinear=False))
     assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_oseen_solve_full_size_oracle_residual(lib):
+    """The Oseen workload (N=128, nt=128, nu=1/100, beta=1e-4) with FP32 inner
+    solves and FP64 outer FGMRES: the true residual of the GPU solution,
+    recomputed by the oracle's level-by-level all-at-once product (with the
+    convection operator) against the oracle's right-hand side, is at most 1e-8
+    of ||b||."""
+    from oracle.kkt import Problem as OP
+    w = W.config(3)
+    print(f"oseen full-size solve {w.name}", flush=True)
+    wind = W.wind_nodal(w.N)
+    vd = W.desired_state(w)
+    gp = lib.Problem.from_workload(w, inner=lib.INNER_GMRES, precision=lib.PREC_FP32_INNER, max_outer=60)
+    x, st, ok = gp.solve(gp.assemble_rhs(_dev(vd)))
+    assert ok and st["rel_residual"] <= 1e-8
+    xh = _host(x)
+    del x, gp
+    torch.cuda.empty_cache()
+    op = OP.from_workload(w, wind)
+    bo = op.rhs(vd)
+    rel = np.linalg.norm(bo - op.kkt_apply(op.to_compact(xh))) / np.linalg.norm(bo)
+    print(f"oracle residual {rel:.3e}, library {st['rel_residual']:.3e}", flush=True)
+    assert rel <= 1e-8
+    assert abs(rel - st["rel_residual"]) <= 1e-3 * st["rel_residual"]
