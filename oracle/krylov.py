@@ -1,4 +1,5 @@
-"""Krylov solvers: right-preconditioned GMRES and flexible GMRES.
+"""Krylov solvers: right-preconditioned GMRES, flexible GMRES and
+preconditioned MINRES.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -8,7 +9,8 @@ is the outer iteration, since a preconditioner that contains an inner Krylov
 solve changes from one application to the next (section 3.4).  Both use
 modified Gram-Schmidt Arnoldi with Givens rotations, work for complex data
 with the Hermitian inner product, and start from x_0 = 0 unless told
-otherwise.
+otherwise.  MINRES (Paige & Saunders) applies to the symmetric Stokes system
+with the symmetric positive definite linear preconditioner of section 3.3.
 """
 from __future__ import annotations
 
