@@ -40,12 +40,12 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc passes over one solve of this workload (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch at the finest grid), each scaled by what the
 # same counter reads for a 1 GiB device copy in the same process (FETCH_SIZE
-# 524314.6 KiB, WRITE_SIZE 1048576 KiB).  Valid only for the kernel source they
+# 524330.3 KiB, WRITE_SIZE 1048576 KiB).  Valid only for the kernel source they
 # were taken on: reported as null once that file changes.
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2405_18964_amd", "csrc", "q2_tiles.hip")
-SWEEP_PMC = {"source_sha256": "0504e22a60f03b92e91a4ee2e99e8b5cc5e32c2d6abe5f281bc2857c0ada4810",
-             "fetch_kib": 363449.8, "fetch_scale": 1048576.0 / 524314.6,
-             "write_kib": 419995.5, "write_scale": 1.0}
+SWEEP_PMC = {"source_sha256": "2e972e25d279af992d70cb6a44fbf622b8d1c0048c0d6ad1b8b2b9f983a0b544",
+             "fetch_kib": 363452.0, "fetch_scale": 1048576.0 / 524330.3,
+             "write_kib": 420161.8, "write_scale": 1.0}
 
 
 def sweep_traffic_bytes():

@@ -53,8 +53,14 @@ constexpr int kT = 48;                 // tile side (node indices)
 constexpr int kE = kT + 4;             // tile with halo
 constexpr int kH = kE / 2;             // parity sub-grid side
 constexpr int kSub = kH * kH + 4;      // sub-grid stride (entries; = 8 mod 16 for the row-order phases)
-constexpr int kSP = kT + 1;            // row pitch of the staged results of the operator tiles
-static_assert(kT * kSP <= 4 * kSub, "staged results fit the tile");
+constexpr int kSP = kT;                // row pitch of the staged results of the operator tiles
+// Staged results are row-major with one entry of skew per four rows.  The
+// restriction gives the 16 lanes of a group a 4 x 4 block of coarse nodes, so
+// they read fine entries 4 apart in x and 4 rows apart in y: with the pitch a
+// multiple of 4 and the row skew the 16 entries fall on 16 different 16-byte
+// residues (conflict-free 128-bit LDS reads).
+__device__ __forceinline__ int stage_idx(int lx, int ly) { return ly * kSP + lx + (ly >> 2); }
+static_assert((kT - 1) * kSP + (kT - 1) + (kT - 1) / 4 < 4 * kSub, "staged results fit the tile");
 
 __host__ __device__ constexpr int wlen(int P) { return P ? 3 : 5; }
 __host__ __device__ constexpr int wlo(int P) { return P ? -1 : -2; }
@@ -462,7 +468,7 @@ __device__ __forceinline__ cpx<R> apply_node(const cpx<R>* sx, int col, int la, 
                                              const R* __restrict__ ctile, int& si) {
   int lx, ly;
   node_of(PX, PY, col, la, lb, lx, ly);
-  si = ly * kSP + lx;
+  si = stage_idx(lx, ly);
   const int gx = X0 + lx, gy = Y0 + ly;
   if (gx < 1 || gx > nq - 2 || gy < 1 || gy > nq - 2) return cmk<cpx<R>>(0, 0);
   const cpx<R>* base = sx + ((ly - PY) >> 1) * kH + ((lx - PX) >> 1);
@@ -473,7 +479,7 @@ __device__ __forceinline__ cpx<R> apply_node(const cpx<R>* sx, int col, int la, 
 }
 
 // Load x into the tile and leave A x of every tile node staged row-major
-// (pitch kSP) in the LDS tile (zero on boundary and outside nodes).
+// (stage_idx layout) in the LDS tile (zero on boundary and outside nodes).
 template <typename R, bool CV>
 __device__ __forceinline__ void apply_stage(cpx<R>* sx, const cpx<R>* __restrict__ x, int nq, int X0, int Y0,
                                             const TCoef<R>& t, const R* __restrict__ ctile, int w, int lane,
@@ -538,7 +544,7 @@ __global__ __launch_bounds__(256) void k_q2_tile_apply(cpx<R>* __restrict__ out,
         if (ly >= kT || gy >= nq) break;
         const ptrdiff_t g = g0 + (ptrdiff_t)5 * k * nq;
         const bool in = xin && gy >= 1 && gy <= nq - 2;
-        cpx<R> v = in ? sx[ly * kSP + lx] : cmk<cpx<R>>(0, 0);
+        cpx<R> v = in ? sx[stage_idx(lx, ly)] : cmk<cpx<R>>(0, 0);
         if (b) v = in ? b[g] - v : cmk<cpx<R>>(0, 0);
         out[g] = v;
       }
@@ -571,10 +577,16 @@ template <int PI, int PJ, typename R>
 __device__ __forceinline__ void restrict_class(cpx<R>* __restrict__ bcf, cpx<R>* __restrict__ sd, const cpx<R>* sr,
                                                int I0, int J0, int nqc) {
   constexpr int na = PI ? kCT / 2 : kCT / 2 + 1, nbj = PJ ? kCT / 2 : kCT / 2 + 1;
-  for (int e = threadIdx.x; e < na * nbj; e += blockDim.x) {
-    const int ci = 2 * (e % na) + PI, cj = 2 * (e / na) + PJ;
+  constexpr int nbx = (na + 3) / 4;
+  static_assert(16 * nbx * ((nbj + 3) / 4) <= 256, "one coarse node per thread");
+  // lane group g = threadIdx / 16 takes a 4 x 4 block of the class's coarse nodes
+  {
+    const int e = (int)threadIdx.x, g = e >> 4;
+    const int ia = 4 * (g % nbx) + (e & 3), ib = 4 * (g / nbx) + ((e >> 2) & 3);
+    if (ia >= na || ib >= nbj) return;
+    const int ci = 2 * ia + PI, cj = 2 * ib + PJ;
     const int I = I0 + ci, J = J0 + cj;
-    if (I >= nqc || J >= nqc) continue;
+    if (I >= nqc || J >= nqc) return;
     R vr = 0, vi = 0;
 #pragma unroll
     for (int iy = 0; iy < 5; ++iy) {
@@ -587,7 +599,7 @@ __device__ __forceinline__ void restrict_class(cpx<R>* __restrict__ bcf, cpx<R>*
         if (rw<PI>(ix) == 0.0) continue;
         const int fx = 2 * ci + roff(ix);
         if (fx < 0 || fx >= kT) continue;
-        const cpx<R> v = sr[fy * kSP + fx];
+        const cpx<R> v = sr[stage_idx(fx, fy)];
         rr = fma((R)rw<PI>(ix), v.x, rr);
         ri = fma((R)rw<PI>(ix), v.y, ri);
       }
@@ -648,11 +660,11 @@ __global__ __launch_bounds__(256) void k_q2_residual_restrict(cpx<R>* __restrict
       const int ly = ly0 + 5 * k;
       if (ly >= kT) break;
       if constexpr (!kPre) bv[k] = bload(k);
-      const cpx<R> a = sx[ly * kSP + lx];
+      const cpx<R> a = sx[stage_idx(lx, ly)];
       cpx<R> r;
       r.x = bv[k].x - a.x;
       r.y = bv[k].y - a.y;
-      sx[ly * kSP + lx] = r;
+      sx[stage_idx(lx, ly)] = r;
     }
   }
   __syncthreads();
@@ -697,7 +709,7 @@ __global__ __launch_bounds__(256) void k_q2_tile_cheb(cpx<R>* xn, const cpx<R>* 
       continue;
     }
     const R d = (R)(cm0(gx & 1) * cm0(gy & 1)) * t.ar;
-    const cpx<R> mx = sx[ly * kSP + lx], xi = x[i], pi = xp ? xp[i] : cmk<cpx<R>>(0, 0), bi = b[i];
+    const cpx<R> mx = sx[stage_idx(lx, ly)], xi = x[i], pi = xp ? xp[i] : cmk<cpx<R>>(0, 0), bi = b[i];
     cpx<R> v;
     v.x = wr * (xi.x - pi.x + gr * (bi.x - mx.x) / d) + pi.x;
     v.y = wr * (xi.y - pi.y + gr * (bi.y - mx.y) / d) + pi.y;
@@ -868,15 +880,15 @@ __device__ __forceinline__ void block_phase(const cpx<R>* sx, const cpx<R>* sp, 
   }
 }
 
-// staging index (pitch kSP) of a lane's node at colour step c
+// staging index (stage_idx layout) of a lane's node at colour step c
 __device__ __forceinline__ int stage_at(int w, int c, int rot, int la, int lb) {
   const int cl = class_of(w, c, rot);
   int lx, ly;
   node_of(cl & 1, cl >> 1, c, la, lb, lx, ly);
-  return ly * kSP + lx;
+  return stage_idx(lx, ly);
 }
 
-// store a staged (pitch kSP) result tile to dst; zero on boundary nodes
+// store a staged (stage_idx layout) result tile to dst; zero on boundary nodes
 template <typename R>
 __device__ __forceinline__ void store_staged(cpx<R>* __restrict__ dst, const cpx<R>* st, int nq, int X0, int Y0) {
   if (threadIdx.x >= 5 * kT) return;
@@ -890,7 +902,7 @@ __device__ __forceinline__ void store_staged(cpx<R>* __restrict__ dst, const cpx
     const int ly = ly0 + 5 * k, gy = Y0 + ly;
     if (ly >= kT || gy >= nq) break;
     const bool in = xin && gy >= 1 && gy <= nq - 2;
-    d[(ptrdiff_t)5 * k * nq] = in ? st[ly * kSP + lx] : cmk<cpx<R>>(0, 0);
+    d[(ptrdiff_t)5 * k * nq] = in ? st[stage_idx(lx, ly)] : cmk<cpx<R>>(0, 0);
   }
 }
 }  // namespace
