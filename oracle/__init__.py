@@ -20,8 +20,11 @@ kkt        the all-at-once matrix of eq. (FinalA), its right-hand side, a sparse
            check of the optimality system (section 2.1/2.2).
 circulant  the circulant perturbation P_C, its FFT diagonalisation and the
            per-frequency blocks G_j (section 3.1, eq. SubBlockG).
-smoothers  multicolour symmetric SOR, Chebyshev semi-iteration (section 3.4).
-mg         geometric multigrid V-cycles (section 3.4).
+smoothers  multicolour SOR over whole grids (the reading of section 3.4), the
+           tiled variant a GPU may run (tile sizes passed in by the caller),
+           Chebyshev semi-iteration (section 3.4).
+mg         geometric multigrid V-cycles (section 3.4), and exact solves that
+           stand in for them in the pins of the block compositions.
 precond    the Stokes preconditioners of section 3.2-3.4 (Algorithms 1 and 2)
            and the Oseen preconditioner of section 4 (Algorithm 3).
 krylov     right-preconditioned GMRES and flexible GMRES.
@@ -30,5 +33,8 @@ Parity status: every function is pinned by a ``-m "not gpu"`` test.  The
 multigrid V-cycle is pinned to the textbook two-/three-grid error propagation
 operator assembled from dense smoother, transfer and coarse matrices; its
 contraction rate is a property of that operator (no closed form) and is only
-checked for being a contraction.
+checked for being a contraction.  The block compositions of section 3.2 and
+section 4 (P~_j^{-1}, the Uzawa Schur block, the pressure Schur step and the
+second step of Algorithm 3) are pinned, with exact inner inverses, to dense
+evaluations of the paper's product forms, and planted mistakes each fail.
 """

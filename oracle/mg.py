@@ -6,10 +6,12 @@ Section 3.4 applies "4 V-cycles" of a geometric multigrid method with SOR
 smoothing to W_j and K_p (Stokes) and to Q_j, Q_j^H and K_p (Oseen).  Readings
 used (the paper leaves these unstated):
 
-* V(1,1) cycle: one forward sweep of the tiled multicolour Gauss-Seidel
-  smoother (``smoothers.TiledSOR``) before the coarse correction, one backward
-  sweep after it (so the cycle is symmetric for symmetric operators); coarsest
-  grid N = 2 solved exactly by dense LU.
+* V(1,1) cycle: one forward sweep of multicolour Gauss-Seidel (SOR with
+  relaxation factor 1 over the whole grid, ``smoothers.ColouredSOR``) before
+  the coarse correction, one backward sweep after it (so the cycle is
+  symmetric for symmetric operators); coarsest grid N = 2 solved exactly by
+  dense LU.  ``tiling`` (a ``smoothers.Tiling``) selects instead the tiled
+  block-Jacobi/Gauss-Seidel variant a GPU may run, with the caller's tiles.
 * Coarse operators are rediscretised with the same coefficients on the coarse
   grid; for nested conforming spaces with exact quadrature this equals the
   Galerkin product P^T A P.  The coarse-grid wind is the fine nodal wind
@@ -42,7 +44,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .fem import Operators
-from .smoothers import TILE_Q1, TILE_Q2, TiledSOR, colours_q2, tiles_of
+from .smoothers import ColouredSOR, TiledSOR, colours_q2, tiles_of
 
 
 def prolong_1d_q2(Nc: int) -> np.ndarray:
@@ -112,16 +114,17 @@ class Levels:
             self.P1.append(sp.csr_matrix(np.kron(p, p)))      # unconstrained Q1
 
     def family(self, fam: str, l: int):
+        """(M, K, N, colours, (ix, iy, nodes per side)) of a level's node set."""
         o = self.ops[l]
         g = o.grid
         if fam == "q2":
             iy, ix = np.divmod(g.v_interior, g.nq)
-            return o.Ms, o.Ks, o.Ns, colours_q2(g), tiles_of(ix, iy, g.nq, TILE_Q2)
+            return o.Ms, o.Ks, o.Ns, colours_q2(g), (ix, iy, g.nq)
         if fam == "q1":
             f = o.full
             Nn = f["N1"] if "N1" in f else sp.csr_matrix(f["M1"].shape)
             iy, ix = np.divmod(np.arange(g.np2), g.np1)
-            return f["M1"], f["K1"], Nn, 2 * (iy % 2) + (ix % 2), tiles_of(ix, iy, g.np1, TILE_Q1)
+            return f["M1"], f["K1"], Nn, 2 * (iy % 2) + (ix % 2), (ix, iy, g.np1)
         raise ValueError(fam)
 
     def prolong(self, fam: str, l: int):
@@ -144,13 +147,16 @@ class ScalarMG:
     """V(1,1) multigrid for  alpha M + gamma K + eta N + eta_t N^T.
 
     ``gamma_levels`` (optional, one value per level) replaces gamma on each
-    level's operator (the finest included)."""
+    level's operator (the finest included).  ``tiling`` (optional
+    ``smoothers.Tiling``) replaces the global multicolour sweep by the tiled
+    variant."""
 
-    def __init__(self, levels: Levels, fam: str, alpha, gamma, eta=0.0, eta_t=0.0, gamma_levels=None):
+    def __init__(self, levels: Levels, fam: str, alpha, gamma, eta=0.0, eta_t=0.0, gamma_levels=None,
+                 tiling=None):
         self.lv, self.fam = levels, fam
         self.A, self.sor = [], []
         for l in range(len(levels.sizes)):
-            M, K, N, col, tiles = levels.family(fam, l)
+            M, K, N, col, (ix, iy, side) = levels.family(fam, l)
             A = alpha * M + (gamma if gamma_levels is None else gamma_levels[l]) * K
             if eta != 0:
                 A = A + eta * N
@@ -158,7 +164,11 @@ class ScalarMG:
                 A = A + eta_t * N.T
             A = sp.csr_matrix(A)
             self.A.append(A)
-            self.sor.append(TiledSOR(A, col, tiles))
+            if tiling is None:
+                self.sor.append(ColouredSOR(A, col))
+            else:
+                T = tiling.q2 if fam == "q2" else tiling.q1
+                self.sor.append(TiledSOR(A, col, tiles_of(ix, iy, side, T)))
         Ac = self.A[-1].toarray()
         self.pin_coarse = fam == "q1"
         self.coarse = sla.lu_factor(Ac[1:, 1:] if self.pin_coarse else Ac)
@@ -188,3 +198,35 @@ class ScalarMG:
         for _ in range(cycles):
             x = self.vcycle(0, b, x)
         return x
+
+
+class ExactSolve:
+    """Drop-in for ``ScalarMG`` that solves the level-0 operator exactly
+    (sparse LU), for pins that replace the paper's inner approximations by the
+    inverses they approximate.  Q1 operators act on the unconstrained node set
+    and may be singular (the pressure Laplacian): node 0 is then held at zero,
+    which solves every consistent system."""
+
+    def __init__(self, A, pin_node0: bool = False):
+        import scipy.sparse.linalg as spla
+        A = sp.csc_matrix(A)
+        self.pin = pin_node0
+        self.real = not np.iscomplexobj(A.data)
+        self.lu = spla.splu(A[1:, 1:].tocsc() if pin_node0 else A)
+
+    def _lu(self, b):
+        if self.real and np.iscomplexobj(b):
+            return self.lu.solve(np.ascontiguousarray(b.real)) + 1j * self.lu.solve(np.ascontiguousarray(b.imag))
+        return self.lu.solve(b)
+
+    def _one(self, b):
+        if not self.pin:
+            return self._lu(b)
+        x = np.zeros(b.shape, dtype=np.result_type(b, 1.0))
+        x[1:] = self._lu(np.ascontiguousarray(b[1:]))
+        return x
+
+    def solve(self, b: np.ndarray, cycles: int = 0) -> np.ndarray:
+        if b.ndim == 1:
+            return self._one(b)
+        return np.stack([self._one(np.ascontiguousarray(b[:, k])) for k in range(b.shape[1])], axis=1)

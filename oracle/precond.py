@@ -61,13 +61,22 @@ import scipy.sparse as sp
 
 from . import circulant as circ
 from .krylov import gmres
-from .mg import Levels, ScalarMG, coarse_viscosity
+from .mg import ExactSolve, Levels, ScalarMG, coarse_viscosity
 from .smoothers import Q1_MASS_BOUNDS, Q2_MASS_BOUNDS, chebyshev
 
 
 class Settings:
+    """Solver parameters of section 3.4 / section 5.
+
+    ``tiling``: None for the multicolour SOR smoother over whole grids (the
+    reading of section 3.4), or a ``smoothers.Tiling`` for the tiled variant.
+    ``exact``: replace every inner approximation (multigrid, Chebyshev) by the
+    exact inverse it stands for -- for pins of the block compositions."""
+
     def __init__(self, n_vcycles=4, n_cheb=10, n_uzawa=6, mu_uzawa=0.75,
-                 inner_tol=1e-2, inner_restart=50, inner_maxit=200):
+                 inner_tol=1e-2, inner_restart=50, inner_maxit=200, tiling=None, exact=False):
+        self.tiling = tiling
+        self.exact = exact
         self.n_vcycles = n_vcycles
         self.n_cheb = n_cheb
         self.n_uzawa = n_uzawa
@@ -94,11 +103,29 @@ class _Common:
         self.freqs = range(P.nt) if freqs is None else freqs
         self.inner_its = {}
 
+    def _mg(self, fam, alpha, gamma, eta=0.0, eta_t=0.0, gamma_levels=None):
+        """Multigrid for a scalar operator of the family (or its exact inverse)."""
+        if self.s.exact:
+            M, K, N, _, _ = self.lv.family(fam, 0)
+            A = alpha * M + gamma * K
+            if eta != 0:
+                A = A + eta * N
+            if eta_t != 0:
+                A = A + eta_t * N.T
+            return ExactSolve(A, pin_node0=fam == "q1")
+        return ScalarMG(self.lv, fam, alpha, gamma, eta, eta_t, gamma_levels, tiling=self.s.tiling)
+
+    def _mass_solver(self, M, bounds):
+        if self.s.exact:
+            ex = ExactSolve(M)
+            return lambda x: ex.solve(x)
+        return lambda x: chebyshev(M, x, self.s.n_cheb, bounds)
+
     def _pressure_solvers(self):
         o = self.P.ops
-        self.mg_Kp = ScalarMG(self.lv, "q1", 0.0, 1.0)
+        self.mg_Kp = self._mg("q1", 0.0, 1.0)
         self.MN = o.full["M1"].tocsr()                       # unconstrained Q1 mass
-        self.cheb_MN = lambda x: chebyshev(self.MN, x, self.s.n_cheb, Q1_MASS_BOUNDS)
+        self.cheb_MN = self._mass_solver(self.MN, Q1_MASS_BOUNDS)
 
     @staticmethod
     def unpin_in(r):
@@ -159,7 +186,7 @@ class StokesPreconditioner(_Common):
     def W_mg(self, j):
         if j not in self.mg_W:
             _, _, c1, c2 = self.constants(j)
-            self.mg_W[j] = ScalarMG(self.lv, "q2", 1.0 + c1, c2 * self.P.nu)
+            self.mg_W[j] = self._mg("q2", 1.0 + c1, c2 * self.P.nu)
         return self.mg_W[j]
 
     # --- the transforms of eq. (GJTransformation)
@@ -251,7 +278,7 @@ class OseenPreconditioner(_Common):
         super().__init__(P, wind, settings, freqs)
         self._pressure_solvers()
         o = P.ops
-        self.cheb_M = lambda x: chebyshev(o.Ms, x, self.s.n_cheb, Q2_MASS_BOUNDS)
+        self.cheb_M = self._mass_solver(o.Ms, Q2_MASS_BOUNDS)
         self.mg_Q, self.mg_QH = {}, {}
 
     def q_shift(self, j):
@@ -264,8 +291,8 @@ class OseenPreconditioner(_Common):
         if j not in self.mg_Q:
             a, tau, nu = self.q_shift(j), self.P.tau, self.P.nu
             g = [tau * v for v in coarse_viscosity(nu, self.lv.wind_max, self.lv.sizes)]
-            self.mg_Q[j] = ScalarMG(self.lv, "q2", a, tau * nu, eta=tau, gamma_levels=g)
-            self.mg_QH[j] = ScalarMG(self.lv, "q2", np.conj(a), tau * nu, eta_t=tau, gamma_levels=g)
+            self.mg_Q[j] = self._mg("q2", a, tau * nu, eta=tau, gamma_levels=g)
+            self.mg_QH[j] = self._mg("q2", np.conj(a), tau * nu, eta_t=tau, gamma_levels=g)
         return self.mg_Q[j], self.mg_QH[j]
 
     def _vec(self, f, x):

@@ -13,13 +13,14 @@ Chebyshev spectrum bounds; the readings used here are:
   1 index, so (ix mod 2, iy mod 2) gives 4.  Colour number = 3*(iy%3) + ix%3
   (Q2) or 2*(iy%2) + ix%2 (Q1) with (ix, iy) the padded-grid node indices.
   A forward sweep visits colours 0..C-1, a backward sweep C-1..0.
-* Subdomains: as in a distributed SOR (each process relaxes its own unknowns
-  and sees its neighbours' values from the start of the sweep), the grid is cut
-  into square tiles of TILE_Q2 = 48 (Q2) or TILE_Q1 = 32 (Q1) node indices,
-  tile (ix // T, iy // T); the colour sweep runs inside every tile while
-  couplings to other tiles use the values the sweep started from (block Jacobi
-  between tiles, Gauss-Seidel inside).  Grids of at most T nodes per side form a
-  single tile, i.e. plain multicolour Gauss-Seidel.
+* Tiled variant (not the paper's method).  A GPU may run the sweep inside
+  square tiles held in fast on-chip memory: the grid is cut into tiles of T
+  node indices per side, tile (ix // T, iy // T); the colour sweep runs inside
+  every tile while couplings to other tiles use the values the sweep started
+  from (block Jacobi between tiles, Gauss-Seidel inside).  ``TiledSOR`` states
+  that sweep for a tile size the caller passes in; this module fixes none.
+  Grids of at most T nodes per side form a single tile, where the tiled sweep
+  is plain multicolour Gauss-Seidel.
 * Chebyshev: Jacobi-preconditioned semi-iteration of Golub and Varga with the
   element-wise spectrum bounds of diag(M)^{-1} M: the 1-D P2 element gives
   [1/2, 5/4] and P1 gives [1/2, 3/2]; tensor products give [1/4, 25/16] for
@@ -32,8 +33,6 @@ import scipy.sparse as sp
 
 Q2_MASS_BOUNDS = (0.25, 25.0 / 16.0)
 Q1_MASS_BOUNDS = (0.25, 9.0 / 4.0)
-TILE_Q2 = 48
-TILE_Q1 = 32
 
 
 def colours_q2(grid) -> np.ndarray:
@@ -83,6 +82,16 @@ class ColouredSOR:
         for c in range(self.ncol - 1, -1, -1):
             self._update(c, b, x)
         return x
+
+
+class Tiling:
+    """Tile sizes (node indices per side) of the tiled smoother variant on Q2
+    and Q1 grids.  Passed in by whoever compares against a tiled sweep."""
+
+    def __init__(self, q2: int, q1: int):
+        if q2 < 1 or q1 < 1:
+            raise ValueError("tile sizes must be positive")
+        self.q2, self.q1 = int(q2), int(q1)
 
 
 class TiledSOR:
