@@ -59,6 +59,19 @@ enum { PINTOC_INNER_LINEAR = 0, PINTOC_INNER_GMRES = 1 };
  * residual recomputation, FFTs and the all-at-once matrix stay FP64. */
 enum { PINTOC_PREC_FP64 = 0, PINTOC_PREC_FP32_INNER = 1 };
 
+/* Multigrid smoother (section 3.4 names successive over-relaxation).
+ *  TILED:  multicolour Gauss-Seidel inside square tiles of 48 (Q2 grids) or
+ *          32 (Q1 grids) node indices held in LDS, block Jacobi between tiles
+ *          -- a GPU-side variant of the sweep (one launch per sweep).
+ *  GLOBAL: multicolour Gauss-Seidel (SOR, relaxation factor 1) over whole
+ *          grids, 9 colours (ix mod 3, iy mod 3) on Q2 and 4 on Q1 grids,
+ *          forward colour order before and backward after the coarse
+ *          correction -- the reading of the paper's smoother (one launch per
+ *          colour).
+ * Grids of at most 48 (Q2) / 32 (Q1) nodes per side are one tile, where both
+ * are the same sweep. */
+enum { PINTOC_SMOOTHER_TILED = 0, PINTOC_SMOOTHER_GLOBAL = 1 };
+
 /* Outer Krylov method.  FGMRES (section 3.4) takes any preconditioner.
  * MINRES applies to the Stokes problem with the linear preconditioner
  * (Algorithm 1): the all-at-once matrix of eq. (FinalA) is symmetric and the
@@ -66,9 +79,10 @@ enum { PINTOC_PREC_FP64 = 0, PINTOC_PREC_FP32_INNER = 1 };
  * recurrence replaces the Arnoldi basis. */
 enum { PINTOC_OUTER_FGMRES = 0, PINTOC_OUTER_MINRES = 1 };
 
-/* Problem of section 2 (eq. OseenOptimization / OseenFlow) on the unit square,
- * Q2-Q1 Taylor-Hood elements on N x N uniform quadrilaterals (section 2.2),
- * backward Euler with nt steps of tau = T / nt, v_0 = 0, f = 0, h = 0. */
+/* Problem of section 2 (eq. OseenOptimization / OseenFlow) on a square
+ * domain [x0, x1] x [y0, y1] (all four zero: the unit square), Q2-Q1
+ * Taylor-Hood elements on N x N uniform quadrilaterals (section 2.2),
+ * backward Euler with nt steps of tau = T / nt. */
 typedef struct {
   int32_t N;            /* quads per side, a power of two >= 2               */
   int32_t nt;           /* time steps = FFT length, >= 2, at most 1024       */
@@ -79,6 +93,8 @@ typedef struct {
   const double* wind;   /* host, [2][(2N+1)^2] Q2 nodal values of the
                            divergence-free wind (x component first); NULL
                            for Stokes.  Copied; the caller may free it.      */
+  double x0, y0, x1, y1; /* domain corners; x1 - x0 = y1 - y0 > 0 required
+                           (square elements); all zero = [0, 1]^2            */
 } pintoc_problem_desc;
 
 /* Solver parameters.  Defaults (pintoc_default_options) follow section 5:
@@ -115,9 +131,22 @@ typedef struct {
                              estimate is below 100 tol times its start;
                              outer_iterations counts MINRES steps, capped by
                              max_outer.                                      */
+  int32_t smoother;       /* PINTOC_SMOOTHER_TILED (default) or _GLOBAL      */
 } pintoc_options;
 
-/* Statistics of one pintoc_solve call (host memory, filled by the library). */
+/* Phases of a solve whose device time pintoc_solve_stats reports. */
+enum {
+  PINTOC_PHASE_FFT = 0,      /* forward time FFT (+ T_l^{-1}), section 3.1     */
+  PINTOC_PHASE_BLOCKS = 1,   /* per-frequency block solves (sections 3.2-4)    */
+  PINTOC_PHASE_IFFT = 2,     /* inverse time FFT (+ T_r^{-1})                  */
+  PINTOC_PHASE_MATVEC = 3,   /* all-at-once products A x of eq. (FinalA)       */
+  PINTOC_PHASE_ORTH = 4,     /* outer orthogonalisation, dots, vector updates  */
+  PINTOC_NPHASES = 5
+};
+
+/* Statistics of one pintoc_solve call (host memory).  Fields marked "in" are
+ * read by the library (set them before the call; zero/NULL = unused), the
+ * rest are written. */
 typedef struct {
   int32_t outer_iterations;
   int32_t converged;             /* 1 if the tolerance was met              */
@@ -126,9 +155,31 @@ typedef struct {
   int32_t inner_iterations_max;
   int32_t precond_applications;
   double seconds;                /* host wall time of the call              */
-  double model_bytes;            /* reserved, 0 (the HBM byte model of a
-                                    preconditioner application is kept by
-                                    the benchmark driver)                  */
+  double model_bytes;            /* modelled compulsory HBM bytes of the
+                                    whole solve: every preconditioner
+                                    application (FFT pair, the multigrid,
+                                    Chebyshev and Uzawa passes of each block
+                                    application, the inner GMRES block
+                                    products and orthogonalisation as
+                                    executed), the all-at-once products and
+                                    the outer orthogonalisation             */
+  double precond_model_bytes;    /* the same model for ONE application of the
+                                    linear block preconditioner (Algorithm 1
+                                    / Algorithm 3) to all kept frequencies,
+                                    FFT pair included                       */
+  double phase_seconds[PINTOC_NPHASES]; /* device time per phase (HIP events
+                                    on the solve's stream)                  */
+  double* residual_history;      /* in: host array or NULL; out: relative
+                                    residual after each outer iteration
+                                    (FGMRES: the Arnoldi estimate |g_k+1| /
+                                    ||b||; MINRES: the preconditioned-norm
+                                    estimate over its start)                */
+  int32_t history_capacity;      /* in: entries of residual_history         */
+  int32_t history_length;        /* out: entries written (<= capacity)      */
+  int32_t* inner_counts;         /* in: host array or NULL; out: inner GMRES
+                                    iterations per kept frequency j =
+                                    0..nt/2, summed over the solve          */
+  int32_t inner_counts_capacity; /* in: entries of inner_counts             */
 } pintoc_solve_stats;
 
 /* Fill *o with the defaults above.  Never fails for a non-NULL pointer. */
@@ -138,7 +189,8 @@ int pintoc_default_options(pintoc_options* o);
  * section 4), the multigrid hierarchy and the coarsest-grid inverses, and
  * plan the workspace.  Host only; no device memory is touched.
  * Errors: PINTOC_EINVAL for N not a power of two >= 2, nt < 2 or > 1024,
- * T, nu or beta <= 0, an unknown flow/inner/precision, or Oseen without wind.
+ * T, nu or beta <= 0, an unknown flow/inner/precision/smoother, Oseen
+ * without wind, or a domain that is not a square.
  * On success *out owns the handle; release it with pintoc_problem_destroy. */
 int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_options* o,
                           pintoc_problem** out);

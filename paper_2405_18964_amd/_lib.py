@@ -11,6 +11,7 @@ STOKES, OSEEN = 0, 1
 INNER_LINEAR, INNER_GMRES = 0, 1
 PREC_FP64, PREC_FP32_INNER = 0, 1
 OUTER_FGMRES, OUTER_MINRES = 0, 1
+SMOOTHER_TILED, SMOOTHER_GLOBAL = 0, 1
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -20,7 +21,8 @@ class LibraryMissing(RuntimeError):
 
 class Desc(C.Structure):
     _fields_ = [("N", C.c_int32), ("nt", C.c_int32), ("T", C.c_double), ("nu", C.c_double),
-                ("beta", C.c_double), ("flow", C.c_int32), ("wind", C.POINTER(C.c_double))]
+                ("beta", C.c_double), ("flow", C.c_int32), ("wind", C.POINTER(C.c_double)),
+                ("x0", C.c_double), ("y0", C.c_double), ("x1", C.c_double), ("y1", C.c_double)]
 
 
 class Options(C.Structure):
@@ -28,16 +30,30 @@ class Options(C.Structure):
                 ("max_outer", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("inner_restart", C.c_int32), ("inner_maxit", C.c_int32), ("n_vcycles", C.c_int32),
                 ("n_cheb", C.c_int32), ("n_uzawa", C.c_int32), ("mu_uzawa", C.c_double),
-                ("stall_guard", C.c_int32), ("outer", C.c_int32)]
+                ("stall_guard", C.c_int32), ("outer", C.c_int32), ("smoother", C.c_int32)]
+
+
+NPHASES = 5
+PHASES = ("fft", "blocks", "ifft", "matvec", "orth")
 
 
 class SolveStats(C.Structure):
     _fields_ = [("outer_iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double),
                 ("inner_iterations_mean", C.c_double), ("inner_iterations_max", C.c_int32),
-                ("precond_applications", C.c_int32), ("seconds", C.c_double), ("model_bytes", C.c_double)]
+                ("precond_applications", C.c_int32), ("seconds", C.c_double), ("model_bytes", C.c_double),
+                ("precond_model_bytes", C.c_double), ("phase_seconds", C.c_double * NPHASES),
+                ("residual_history", C.POINTER(C.c_double)), ("history_capacity", C.c_int32),
+                ("history_length", C.c_int32), ("inner_counts", C.POINTER(C.c_int32)),
+                ("inner_counts_capacity", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            if k in ("residual_history", "inner_counts", "history_capacity", "inner_counts_capacity"):
+                continue
+            v = getattr(self, k)
+            out[k] = dict(zip(PHASES, list(v))) if k == "phase_seconds" else v
+        return out
 
 
 class KernelTiming(C.Structure):
@@ -109,7 +125,7 @@ class Problem:
     Vectors are torch float64 CUDA tensors in the canonical layout of
     include/pintoc.h (length :attr:`n_all`)."""
 
-    def __init__(self, N, nt, T, nu, beta, flow=STOKES, wind=None, device="cuda", **options):
+    def __init__(self, N, nt, T, nu, beta, flow=STOKES, wind=None, device="cuda", domain=None, **options):
         import numpy as np
         import torch
         lib = library()
@@ -120,7 +136,8 @@ class Problem:
         if wind is not None:
             self._wind = np.ascontiguousarray(np.asarray(wind, dtype=np.float64).reshape(-1))
             wptr = self._wind.ctypes.data_as(C.POINTER(C.c_double))
-        d = Desc(N, nt, T, nu, beta, flow, wptr)
+        x0, y0, x1, y1 = (0.0, 0.0, 0.0, 0.0) if domain is None else tuple(float(v) for v in domain)
+        d = Desc(N, nt, T, nu, beta, flow, wptr, x0, y0, x1, y1)
         self.options = default_options(**options)
         h = C.c_void_p()
         _check(lib.pintoc_problem_create(C.byref(d), C.byref(self.options), C.byref(h)), "pintoc_problem_create")
@@ -175,13 +192,26 @@ class Problem:
                                               self._stream()), "pintoc_precond_apply")
         return out
 
-    def solve(self, b, x=None):
-        """Returns (x, stats dict, converged flag)."""
+    def solve(self, b, x=None, history=0):
+        """Returns (x, stats dict, converged flag).  The stats carry the
+        per-frequency inner GMRES counts of the solve and, with ``history``
+        > 0, up to that many per-iteration residual estimates."""
         x = self.empty() if x is None else x
         st = SolveStats()
+        nf = self.nt // 2 + 1
+        counts = (C.c_int32 * nf)()
+        st.inner_counts = C.cast(counts, C.POINTER(C.c_int32))
+        st.inner_counts_capacity = nf
+        hist = (C.c_double * max(int(history), 1))()
+        if history > 0:
+            st.residual_history = C.cast(hist, C.POINTER(C.c_double))
+            st.history_capacity = int(history)
         rc = _check(library().pintoc_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), C.byref(st),
                                            self._stream()), "pintoc_solve")
-        return x, st.as_dict(), rc == OK
+        out = st.as_dict()
+        out["inner_counts"] = [int(counts[j]) for j in range(nf)]
+        out["residual_history"] = [float(hist[k]) for k in range(st.history_length)]
+        return x, out, rc == OK
 
     def last_inner_iterations(self):
         """Inner GMRES counts per kept frequency of the last application."""

@@ -27,6 +27,16 @@ template <typename R>
 void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, const cpx<R>* b, const cpx<R>* ec,
                        int n, double h, const OpCoef* coef, int fpc, int nb, const void* conv, bool forward,
                        Mask mk);
+// Multicolour Gauss-Seidel over whole grids (one launch per colour, in place;
+// forward: colours 0..C-1, backward C-1..0).  conv: Q2 per-node table of the
+// level (50 values per node: N then N^T, scaled by coef.eta / coef.etat) or null.
+template <typename R>
+void launch_colour_sweep(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef,
+                         int fpc, int nb, const double* conv, bool forward, Mask mk);
+// x = t + P ec (prolongation from the level with n / 2 elements per side)
+template <typename R>
+void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* t, const cpx<R>* ec, int n, int nb,
+                        Mask mk);
 template <typename R>
 void launch_q1_residual(hipStream_t s, cpx<R>* r, const cpx<R>* x, const cpx<R>* b, int n, double h,
                         const OpCoef* coef, int fpc, int nb, const double* conv, Mask mk);

@@ -1019,6 +1019,108 @@ __global__ __launch_bounds__(256) void k_schur_combine_pin(cpx<R>* __restrict__ 
                            a * ((double)k.y - (double)k0.y) + g * ((double)m.y - (double)m0.y));
 }
 
+// ---------------------------------------------- global multicolour sweeps
+// Gauss-Seidel (SOR with relaxation factor 1) over whole grids in the
+// multicolour order, the smoother of section 3.4 as read for this method:
+// one launch per colour, in place (nodes of one colour do not couple).  Q2
+// colour (ix mod 3, iy mod 3) over the interior padded indices 1..2n-1, Q1
+// colour (ix mod 2, iy mod 2) over all nodes 0..n.  ``conv``: per-node
+// stencil table of the level (25 values of N, 25 of N^T per Q2 node), with
+// coef.eta scaling N and coef.etat scaling N^T, or null.
+template <typename R>
+__global__ __launch_bounds__(256) void k_q2_colour(cpx<R>* x, const cpx<R>* __restrict__ b, int n, double h,
+                                                   const OpCoef* __restrict__ coef, int fpc,
+                                                   const double* __restrict__ conv, int cx, int cy, int mx, int my,
+                                                   Mask mk) {
+  const int f = blockIdx.y;
+  if (mk.off(f)) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= mx * my) return;
+  const int nq = 2 * n + 1;
+  const int ix = (cx == 0 ? 3 : cx) + 3 * (t % mx), iy = (cy == 0 ? 3 : cy) + 3 * (t / mx);
+  cpx<R>* xf = x + (size_t)f * nq * nq;
+  cpx<R> ax, dg;
+  q2_apply_node<R>(xf, nq, ix, iy, h, coef[f / fpc], conv, ax, dg);
+  const size_t i = (size_t)iy * nq + ix;
+  const cpx<R> r = b[(size_t)f * nq * nq + i] - ax;
+  const cpx<R> d = cdiv(r, dg);
+  xf[i] = xf[i] + d;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_q1_colour(cpx<R>* x, const cpx<R>* __restrict__ b, int n, double h,
+                                                   const OpCoef* __restrict__ coef, int fpc, int cx, int cy, int mx,
+                                                   int my, Mask mk) {
+  const int f = blockIdx.y;
+  if (mk.off(f)) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= mx * my) return;
+  const int np = n + 1;
+  const int ix = cx + 2 * (t % mx), iy = cy + 2 * (t / mx);
+  cpx<R>* xf = x + (size_t)f * np * np;
+  cpx<R> ax, dg;
+  q1_apply_node<R>(xf, n, ix, iy, h, coef[f / fpc], nullptr, ax, dg);
+  const size_t i = (size_t)iy * np + ix;
+  const cpx<R> r = b[(size_t)f * np * np + i] - ax;
+  const cpx<R> d = cdiv(r, dg);
+  xf[i] = xf[i] + d;
+}
+
+// 1-D Q2 interpolation from the coarse grid (coarse padded index c, fine i =
+// 0..2 nf): a coarse vertex or midpoint coincides with fine nodes 4e and
+// 4e + 2; the quarter points 4e + 1, 4e + 3 take the quadratic through the
+// coarse element's three nodes at 1/4 and 3/4 of it.
+__device__ __forceinline__ int q2_interp_1d(int i, int c[3], double w[3]) {
+  const int e = i >> 2, r = i & 3;
+  if (r == 0) { c[0] = 2 * e; w[0] = 1.0; return 1; }
+  if (r == 2) { c[0] = 2 * e + 1; w[0] = 1.0; return 1; }
+  c[0] = 2 * e; c[1] = 2 * e + 1; c[2] = 2 * e + 2;
+  if (r == 1) { w[0] = 0.375; w[1] = 0.75; w[2] = -0.125; }
+  else { w[0] = -0.125; w[1] = 0.75; w[2] = 0.375; }
+  return 3;
+}
+
+// x = t + P ec on a Q2 level of n elements per side (coarse n / 2)
+template <typename R>
+__global__ __launch_bounds__(256) void k_q2_prolong_add(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ t,
+                                                        const cpx<R>* __restrict__ ec, int n, Mask mk) {
+  const int f = blockIdx.y;
+  if (mk.off(f)) return;
+  const int nq = 2 * n + 1, nqc = n + 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nq * nq) return;
+  const int ix = k % nq, iy = k / nq;
+  const size_t i = (size_t)f * nq * nq + k;
+  if (ix == 0 || iy == 0 || ix == nq - 1 || iy == nq - 1) { x[i] = cmk<cpx<R>>(0, 0); return; }
+  int cxs[3], cys[3];
+  double wx[3], wy[3];
+  const int nx = q2_interp_1d(ix, cxs, wx), ny = q2_interp_1d(iy, cys, wy);
+  const cpx<R>* e = ec + (size_t)f * nqc * nqc;
+  double sr = 0, si = 0;
+  for (int a = 0; a < ny; ++a)
+    for (int q = 0; q < nx; ++q) {
+      const cpx<R> v = e[(size_t)cys[a] * nqc + cxs[q]];
+      sr += wx[q] * wy[a] * (double)v.x;
+      si += wx[q] * wy[a] * (double)v.y;
+    }
+  const cpx<R> tv = t[i];
+  x[i] = cmk<cpx<R>>((double)tv.x + sr, (double)tv.y + si);
+}
+
+// x = t + P ec on a Q1 level (all nodes)
+template <typename R>
+__global__ __launch_bounds__(256) void k_q1_prolong_add(cpx<R>* __restrict__ x, const cpx<R>* __restrict__ t,
+                                                        const cpx<R>* __restrict__ ec, int n, Mask mk) {
+  const int f = blockIdx.y;
+  if (mk.off(f)) return;
+  const int np = n + 1, npc = n / 2 + 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np * np) return;
+  const size_t i = (size_t)f * np * np + k;
+  const cpx<R> p = q1_prolong_at<R>(ec + (size_t)f * npc * npc, npc, k % np, k / np);
+  x[i] = t[i] + p;
+}
+
 // ------------------------------------------------------------ launchers
 static inline dim3 grid2(long work, int nb, int bs = 256) { return dim3((unsigned)((work + bs - 1) / bs), nb); }
 
@@ -1033,6 +1135,36 @@ void launch_tile_sweep(hipStream_t s, bool q2, cpx<R>* xo, const cpx<R>* xi, con
     hipLaunchKernelGGL(k_q1_tile_sweep<R>, dim3(ntx * ntx, nb), dim3(256), 0, s, xo, xi, b, ec, n, h, coef, fpc,
                        (const double*)conv, forward ? 1 : 0, ntx, mk);
   }
+}
+
+template <typename R>
+void launch_colour_sweep(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* b, int n, double h, const OpCoef* coef,
+                         int fpc, int nb, const double* conv, bool forward, Mask mk) {
+  const int nc = q2 ? 9 : 4, m = q2 ? 3 : 2;
+  for (int k = 0; k < nc; ++k) {
+    const int c = forward ? k : nc - 1 - k;
+    const int cx = c % m, cy = c / m;
+    if (q2) {
+      // interior padded indices 1..2n-1 with index mod 3 = c: first 3 (c = 0) or c
+      auto cnt = [&](int c0) { const int f0 = c0 == 0 ? 3 : c0; return f0 > 2 * n - 1 ? 0 : (2 * n - 1 - f0) / 3 + 1; };
+      const int mx = cnt(cx), my = cnt(cy);
+      if (mx * my == 0) continue;
+      hipLaunchKernelGGL(k_q2_colour<R>, grid2((long)mx * my, nb), dim3(256), 0, s, x, b, n, h, coef, fpc, conv, cx, cy,
+                         mx, my, mk);
+    } else {
+      const int mx = (n - cx) / 2 + 1, my = (n - cy) / 2 + 1;
+      hipLaunchKernelGGL(k_q1_colour<R>, grid2((long)mx * my, nb), dim3(256), 0, s, x, b, n, h, coef, fpc, cx, cy, mx,
+                         my, mk);
+    }
+  }
+}
+
+template <typename R>
+void launch_prolong_add(hipStream_t s, bool q2, cpx<R>* x, const cpx<R>* t, const cpx<R>* ec, int n, int nb,
+                        Mask mk) {
+  const long nn = q2 ? (long)(2 * n + 1) * (2 * n + 1) : (long)(n + 1) * (n + 1);
+  if (q2) hipLaunchKernelGGL(k_q2_prolong_add<R>, grid2(nn, nb), dim3(256), 0, s, x, t, ec, n, mk);
+  else hipLaunchKernelGGL(k_q1_prolong_add<R>, grid2(nn, nb), dim3(256), 0, s, x, t, ec, n, mk);
 }
 
 template <typename R>
@@ -1088,6 +1220,9 @@ void launch_schur_combine_pin(hipStream_t s, cpx<R>* out, const cpx<R>* yK, cons
 }
 
 #define PINTOC_INST(R)                                                                                        \
+  template void launch_colour_sweep<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, int, double, const OpCoef*, int,  \
+                                       int, const double*, bool, Mask);                                              \
+  template void launch_prolong_add<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int, Mask);    \
   template void launch_tile_sweep<R>(hipStream_t, bool, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, \
                                      double, const OpCoef*, int, int, const void*, bool, Mask);                    \
   template void launch_q1_residual<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, int, double,          \

@@ -72,6 +72,14 @@ struct MGPlan {
   // per-level device buffers (complex, precision-typed): b, x (level >= 1),
   // t (second iterate buffer of the out-of-place smoother), r (residual)
   std::vector<void*> b, x, r, t;
+  // global multicolour smoother (PINTOC_SMOOTHER_GLOBAL): coefficient sets
+  // as defined ([level][set], eta on N and etat on N^T) and per-level 50-entry
+  // Q2 convection tables (null without convection)
+  bool global = false;
+  std::vector<OpCoef> coefg_h;
+  OpCoef* coefg = nullptr;
+  std::vector<const double*> conv50;
+  const OpCoef* coefgl(int l) const { return coefg + (size_t)l * ncoef; }
   Probe* probe = nullptr;              // times the finest-level sweeps when on
   int fpj = 1;                         // grids per frequency in the batch
   const int* mask = nullptr;           // per-frequency activity (inner GMRES), or null
@@ -131,6 +139,7 @@ struct pintoc_problem {
   void* sconv[2] = {nullptr, nullptr};         // device, in the inner precision
   int sconv_n = 0;                             // finest level of the small tables
   double* conv50 = nullptr;                   // finest level, 50 per node (block and all-at-once matrices)
+  std::vector<double*> conv50l;               // every level, 50 per node (global smoother only; [0] = conv50)
   double* conv1 = nullptr;
   MGPlan mgQ, mgQH;
   int* maskd = nullptr;                 // device mask of the batched inner GMRES
@@ -146,6 +155,22 @@ struct pintoc_problem {
   void *B1 = nullptr, *B2 = nullptr, *X1 = nullptr, *X2 = nullptr, *T1 = nullptr, *T2 = nullptr, *Rb = nullptr;
   void *C1 = nullptr, *C2 = nullptr, *Pt = nullptr, *Ub = nullptr;
   Probe probe;
+  // device time per phase of a solve: pairs of HIP events on the solve's
+  // stream, summed when the solve ends
+  struct PhaseTimer {
+    std::vector<hipEvent_t> e0, e1;
+    std::vector<int> phase;
+    size_t used = 0;
+    bool on = false;
+    ~PhaseTimer() {
+      for (auto e : e0) (void)hipEventDestroy(e);
+      for (auto e : e1) (void)hipEventDestroy(e);
+    }
+  } pt;
+  // modelled bytes: the whole solve so far, and the parts of one application
+  double bytes_acc = 0.0;
+  double model_fft = 0.0, model_block = 0.0, model_bmat = 0.0, model_fvec = 0.0, model_canon = 0.0;
+  std::vector<long> its_acc;           // inner GMRES iterations per frequency, summed over a solve
   // inner statistics
   long inner_its_sum = 0, inner_blocks = 0;
   int inner_its_max = 0;
@@ -277,6 +302,7 @@ static void plan_mg_buffers(MGPlan& m, Carver& cv, size_t csize) {
   }
   m.coef = cv.take<OpCoef>(sizeof(OpCoef) * m.ncoef * m.nlev);
   m.inv = cv.take<double2>(sizeof(double2) * m.inv_h.size());
+  m.coefg = m.global ? cv.take<OpCoef>(sizeof(OpCoef) * m.coefg_h.size()) : nullptr;
 }
 
 static void carve(pintoc_problem* p, char* base) {
@@ -336,6 +362,14 @@ static void carve(pintoc_problem* p, char* base) {
     p->Pt = cv.take<char>(pbytes);
     p->Ub = cv.take<char>(pbytes);
     for (size_t l = 0; l < p->tconv[0].size(); ++l) { p->mgQ.conv[l] = p->tconv[0][l]; p->mgQH.conv[l] = p->tconv[1][l]; }
+    if (p->o.smoother == PINTOC_SMOOTHER_GLOBAL) {
+      // per-node tables of every level the global sweep visits (the finest is conv50)
+      p->conv50l.assign(p->conv2_h.size(), nullptr);
+      p->conv50l[0] = p->conv50;
+      for (size_t l = 1; l < p->conv2_h.size(); ++l) p->conv50l[l] = cv.take<double>(sizeof(double) * p->conv2_h[l].size());
+      p->mgQ.conv50.assign(p->conv50l.begin(), p->conv50l.end());
+      p->mgQH.conv50.assign(p->conv50l.begin(), p->conv50l.end());
+    }
     p->mgQ.sconv = p->sconv[0];
     p->mgQH.sconv = p->sconv[1];
     p->mgQ.sconv_n = p->mgQH.sconv_n = p->sconv_n;
@@ -446,6 +480,7 @@ extern "C" int pintoc_default_options(pintoc_options* o) {
   o->mu_uzawa = 0.75;
   o->stall_guard = 1;
   o->outer = PINTOC_OUTER_FGMRES;
+  o->smoother = PINTOC_SMOOTHER_TILED;
   return PINTOC_OK;
 }
 
@@ -497,6 +532,8 @@ extern "C" int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* co
   return k;
 }
 
+static void byte_model(pintoc_problem* p);
+
 extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_options* o, pintoc_problem** out) {
   if (!d || !out) return fail(PINTOC_EINVAL, "NULL descriptor or output pointer");
   pintoc_options opt;
@@ -506,6 +543,10 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   if (d->nt < 2 || !pow2(d->nt) || d->nt > 1024) return fail(PINTOC_EINVAL, "nt must be a power of two in [2, 1024]");
   if (!(d->T > 0) || !(d->nu > 0) || !(d->beta > 0)) return fail(PINTOC_EINVAL, "T, nu and beta must be > 0");
   if (d->flow != PINTOC_STOKES && d->flow != PINTOC_OSEEN) return fail(PINTOC_EINVAL, "unknown flow");
+  const bool unit = d->x0 == 0.0 && d->y0 == 0.0 && d->x1 == 0.0 && d->y1 == 0.0;
+  const double side = unit ? 1.0 : d->x1 - d->x0;
+  if (!unit && (!(side > 0) || !std::isfinite(side) || std::fabs((d->y1 - d->y0) - side) > 1e-12 * side))
+    return fail(PINTOC_EINVAL, "the domain must be a square [x0, x1] x [y0, y1] with x1 - x0 = y1 - y0 > 0");
   if (d->flow == PINTOC_OSEEN && !d->wind) return fail(PINTOC_EINVAL, "Oseen flow needs a wind");
   if (opt.inner != PINTOC_INNER_LINEAR && opt.inner != PINTOC_INNER_GMRES) return fail(PINTOC_EINVAL, "unknown inner mode");
   if (opt.inner == PINTOC_INNER_GMRES &&
@@ -518,6 +559,8 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     return fail(PINTOC_EINVAL, "invalid solver options");
   if (opt.outer != PINTOC_OUTER_FGMRES && opt.outer != PINTOC_OUTER_MINRES)
     return fail(PINTOC_EINVAL, "unknown outer method");
+  if (opt.smoother != PINTOC_SMOOTHER_TILED && opt.smoother != PINTOC_SMOOTHER_GLOBAL)
+    return fail(PINTOC_EINVAL, "unknown smoother");
   if (opt.outer == PINTOC_OUTER_MINRES &&
       (d->flow != PINTOC_STOKES || opt.inner != PINTOC_INNER_LINEAR || opt.restart < 4))
     return fail(PINTOC_EINVAL, "MINRES needs the Stokes flow, the linear preconditioner and restart >= 4");
@@ -648,6 +691,11 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
         }
         m->coef_dev_h.push_back(c);
       }
+    if (opt.smoother == PINTOC_SMOOTHER_GLOBAL) {
+      m->global = true;
+      for (int l = 0; l < nl; ++l)
+        for (const OpCoef& c0 : m->coef_h) m->coefg_h.push_back(m->level_coef(c0, l));
+    }
     const std::vector<double>* cc = (oseen && m->q2) ? &p->conv2_h[nl - 1] : nullptr;
     for (const OpCoef& c : m->coef_h)
       if (!coarse_inverse(m->q2, m->level_coef(c, nl - 1), cc, m->inv_h)) {
@@ -656,6 +704,7 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
       }
   }
   carve(p, nullptr);
+  byte_model(p);
   *out = p;
   return PINTOC_OK;
 }
@@ -683,6 +732,8 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
     if (m->nlev == 0 || !m->coef) continue;
     HIPCHK(hipMemcpyAsync(m->coef, m->coef_dev_h.data(), sizeof(OpCoef) * m->coef_dev_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(m->inv, m->inv_h.data(), sizeof(double2) * m->inv_h.size(), hipMemcpyHostToDevice, s));
+    if (m->coefg)
+      HIPCHK(hipMemcpyAsync(m->coefg, m->coefg_h.data(), sizeof(OpCoef) * m->coefg_h.size(), hipMemcpyHostToDevice, s));
   }
   if (p->d.flow == PINTOC_OSEEN) {
     HIPCHK(hipMemcpyAsync(p->conv50, p->conv2_h[0].data(), sizeof(double) * p->conv2_h[0].size(),
@@ -708,6 +759,9 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
       }
     }
     HIPCHK(hipMemcpyAsync(p->conv1, p->conv1_h.data(), sizeof(double) * p->conv1_h.size(), hipMemcpyHostToDevice, s));
+    for (size_t l = 1; l < p->conv50l.size(); ++l)
+      HIPCHK(hipMemcpyAsync(p->conv50l[l], p->conv2_h[l].data(), sizeof(double) * p->conv2_h[l].size(),
+                            hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsi, p->cpsi_h.data(), sizeof(OpCoef) * p->cpsi_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsih, p->cpsih_h.data(), sizeof(OpCoef) * p->cpsih_h.size(), hipMemcpyHostToDevice, s));
     const double tau = p->tau;
@@ -723,6 +777,72 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
   HIPCHK(hipStreamSynchronize(s));
   p->bound = true;
   return PINTOC_OK;
+}
+
+// ------------------------------------------------------------ solve statistics
+// Phase timing: an event pair around each phase of a solve (only while a
+// solve runs).  Returns the slot to close, or -1.
+static int phase_open(pintoc_problem* p, hipStream_t s, int phase) {
+  auto& t = p->pt;
+  if (!t.on) return -1;
+  if (t.used == t.e0.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return -1; }
+    t.e0.push_back(a); t.e1.push_back(b); t.phase.push_back(0);
+  }
+  const int k = (int)t.used++;
+  t.phase[k] = phase;
+  (void)hipEventRecord(t.e0[k], s);
+  return k;
+}
+static void phase_close(pintoc_problem* p, hipStream_t s, int k) {
+  if (k >= 0) (void)hipEventRecord(p->pt.e1[k], s);
+}
+// sums the recorded phases (waits for their events)
+static void phase_sum(pintoc_problem* p, double out[PINTOC_NPHASES]) {
+  for (int i = 0; i < PINTOC_NPHASES; ++i) out[i] = 0.0;
+  auto& t = p->pt;
+  for (size_t k = 0; k < t.used; ++k) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(t.e1[k]) == hipSuccess && hipEventElapsedTime(&ms, t.e0[k], t.e1[k]) == hipSuccess)
+      out[t.phase[k]] += 1e-3 * ms;
+  }
+}
+
+// Byte model: compulsory HBM traffic of the passes as implemented (each
+// field a kernel touches is read or written once; stencil tables, coefficient
+// sets and the coarsest grids are left out).  Sizes: V = the four velocity
+// grids of all kept frequencies, P = the two pressure grids, in the inner
+// precision; C = one canonical FP64 vector.  A multigrid solve of c cycles
+// costs (8.5 c - 1) passes per level on Q2 levels (pre-smoothing 3, 2 in the
+// first cycle; fused residual/restriction 2.25; post-smoothing with the
+// coarse correction 3.25) and (10.5 c - 1) on Q1 levels (residual 3 and
+// restriction 1.25 instead), times 4/3 for the hierarchy; c Chebyshev steps
+// 4 c - 3 passes.
+static void byte_model(pintoc_problem* p) {
+  const double cs = (double)p->csize, nf = p->nf;
+  const double V = 4.0 * nf * p->nq2 * cs, P = 2.0 * nf * p->np2 * cs, H = V / 2.0;
+  const double C = 8.0 * (double)p->n_all;
+  const int c = p->o.n_vcycles, k = p->o.n_cheb;
+  const double mg2 = (8.5 * c - 1.0) * 4.0 / 3.0, mg1 = (10.5 * c - 1.0) * 4.0 / 3.0, ch = 4.0 * k - 3.0;
+  double block;
+  if (p->d.flow == PINTOC_STOKES) {
+    // W_j on 4 velocity grids, K_N and M_N on 2 pressure grids, unpin copy and combine
+    block = mg2 * V + mg1 * P + ch * P + 2 * P + 3 * P;
+  } else {
+    // one Uzawa step on the half-blocks H: four operator products (2 each),
+    // three combinations (4, 3, 4) and a final one (3), Chebyshev on M, two
+    // multigrid solves (Q_j, Q_j^H) and the mass product between them (2)
+    const double step = 4 * 2 * H + (4 + 3 + 4 + 3) * H + ch * H + 2 * mg2 * H + 2 * H;
+    block = p->o.n_uzawa * step + 4 * H + 2 * H + 4 * H     // copies in, zero fill, copies out
+            + (2 * P + 2 * H) + 2 * P + ch * P + 2 * P + 2 * P + mg1 * P + 2 * P;   // Schur step
+  }
+  p->model_fft = 2.0 * (C + V + P);
+  p->model_block = block;                // all kept frequencies
+  p->model_bmat = 2.0 * (V + P);         // block product Z_j / G_j, all frequencies
+  p->model_fvec = V + P;                 // one frequency vector
+  p->model_canon = C;
 }
 
 // ------------------------------------------------------------ multigrid
@@ -752,6 +872,26 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
   cpx<R>* t = (cpx<R>*)m.t[l];
   cpx<R>* bc = (cpx<R>*)m.b[l + 1];
   cpx<R>* xc = (cpx<R>*)m.x[l + 1];
+  if (m.global) {
+    // multicolour Gauss-Seidel over whole grids: t = x (or 0), forward colour
+    // sweep in place; after the coarse correction x = t + P e_c, backward sweep
+    const size_t bytes = m.nodes(l) * m.nb * sizeof(cpx<R>);
+    if (x_zero) launch_fill_zero(s, t, bytes);
+    else (void)hipMemcpyAsync(t, x, bytes, hipMemcpyDeviceToDevice, s);
+    const double* cv = m.conv50.empty() ? nullptr : m.conv50[l];
+    launch_colour_sweep<R>(s, m.q2, t, b, n, h, m.coefgl(l), m.fpc, m.nb, cv, true, m.mk());
+    cpx<R>* r = (cpx<R>*)m.r[l];
+    if (m.q2) {
+      launch_q2_residual_restrict<R>(s, bc, r, t, b, n, h, m.coefl(l), m.fpc, m.nb, (const R*)m.conv[l], m.mk());
+    } else {
+      launch_q1_residual<R>(s, r, t, b, n, h, m.coefl(l), m.fpc, m.nb, (const double*)m.conv[l], m.mk());
+      launch_q1_restrict<R>(s, bc, r, n / 2, m.nb, m.mk());
+    }
+    vcycle<R>(s, m, l + 1, xc, bc, true);
+    launch_prolong_add<R>(s, m.q2, x, t, xc, n, m.nb, m.mk());
+    launch_colour_sweep<R>(s, m.q2, x, b, n, h, m.coefgl(l), m.fpc, m.nb, cv, false, m.mk());
+    return;
+  }
   // the probe times the finest pre-smoothing sweeps (reads b and, unless x = 0, x; writes t)
   Probe* pr = (l == 0 && m.probe && m.probe->on) ? m.probe : nullptr;
   const int slot = pr ? (int)(pr->count % Probe::kCap) : 0;
@@ -1168,7 +1308,20 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
   }
   clear_mask();
   p->last_its = its;
+  if ((int)p->its_acc.size() != nf) p->its_acc.assign(nf, 0);
+  {
+    // model: per frequency, each iteration k applies the block preconditioner
+    // and the block product and reads the basis twice (2 k + 6 vector passes);
+    // each restart cycle ends with one more preconditioner application
+    const double per_j_block = p->model_block / nf, per_j_bmat = p->model_bmat / nf, fv = p->model_fvec / nf;
+    for (int j = 0; j < nf; ++j) {
+      const double kk = its[j];
+      const double cycles = its[j] > 0 ? std::ceil(kk / m) : 0.0;
+      p->bytes_acc += (kk + cycles) * per_j_block + kk * per_j_bmat + (kk * (kk - 1.0) + 6.0 * kk) * fv;
+    }
+  }
   for (int j = 0; j < nf; ++j) {
+    p->its_acc[j] += its[j];
     p->inner_its_sum += its[j];
     p->inner_blocks += 1;
     p->inner_its_max = std::max(p->inner_its_max, its[j]);
@@ -1184,14 +1337,22 @@ template <typename R>
 static int precond_apply_t(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
   cpx<R>*Vb = (cpx<R>*)p->Vb, *Vx = (cpx<R>*)p->Vx, *Pb = (cpx<R>*)p->Pb, *Px = (cpx<R>*)p->Px;
   const int mode = p->d.flow == PINTOC_STOKES ? 1 : 0;
+  int ph = phase_open(p, s, PINTOC_PHASE_FFT);
   launch_time_fft_fwd<R>(s, r, Vb, Pb, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, mode);
+  phase_close(p, s, ph);
+  ph = phase_open(p, s, PINTOC_PHASE_BLOCKS);
   if (p->o.inner == PINTOC_INNER_LINEAR) {
     block_precond<R>(p, s, Vb, Pb, Vx, Px);
+    p->bytes_acc += p->model_block;
   } else {
     int rc = gmres_blocks<R>(p, s);
     if (rc) return rc;
   }
+  phase_close(p, s, ph);
+  ph = phase_open(p, s, PINTOC_PHASE_IFFT);
   launch_time_fft_inv<R>(s, Vx, Px, z, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, mode);
+  phase_close(p, s, ph);
+  p->bytes_acc += p->model_fft;
   return PINTOC_OK;
 }
 
@@ -1222,6 +1383,14 @@ extern "C" int pintoc_assemble_rhs(pintoc_problem* p, const double* vd, double* 
 static void kkt(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
   launch_kkt_apply(s, x, y, p->d.N, p->d.nt, p->tau, p->d.beta, p->d.nu,
                    p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr);
+}
+
+// the all-at-once product inside a solve: timed as its phase, counted in the byte model
+static void kkt_t(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
+  const int ph = phase_open(p, s, PINTOC_PHASE_MATVEC);
+  kkt(p, x, y, s);
+  phase_close(p, s, ph);
+  p->bytes_acc += 2.0 * p->model_canon;
 }
 
 extern "C" int pintoc_kkt_apply(pintoc_problem* p, const double* x, double* y, void* stream) {
@@ -1266,7 +1435,7 @@ static int dots(pintoc_problem* p, hipStream_t s, const double* V, int k, const 
 constexpr int kMinresCheck = 5;
 
 static int solve_minres(pintoc_problem* p, const double* b, double* x, double bnorm, hipStream_t s, int& its,
-                        double& res, bool& conv) {
+                        double& res, bool& conv, std::vector<double>& hist) {
   const size_t n = (size_t)p->n_all;
   double hb[2];
   int rc;
@@ -1274,7 +1443,7 @@ static int solve_minres(pintoc_problem* p, const double* b, double* x, double bn
   double* Wv[2] = {p->Vk + 2 * n, p->Vk + 3 * n};          // w_{j-1} (then w_{j+1}), w_j
   double* AZ = p->Vk + 4 * n;
   auto true_residual = [&]() -> int {
-    kkt(p, x, p->rvec, s);
+    kkt_t(p, x, p->rvec, s);
     launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
     int r = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb);
     res = std::sqrt(hb[0]);
@@ -1302,7 +1471,8 @@ static int solve_minres(pintoc_problem* p, const double* b, double* x, double bn
     bool checked = false;
     while (its < p->o.max_outer) {
       launch_axpby(s, Zc, Zc, 1.0 / g, 0.0, n);             // z_j
-      kkt(p, Zc, AZ, s);
+      kkt_t(p, Zc, AZ, s);
+      p->bytes_acc += 14.0 * p->model_canon;                // vector updates and dots of one step
       if ((rc = dots(p, s, AZ, 1, Zc, p->dd, hb))) return rc;
       const double delta = hb[0];
       // v_{j+1} over v_{j-1}
@@ -1326,6 +1496,7 @@ static int solve_minres(pintoc_problem* p, const double* b, double* x, double bn
       eta = -sn * eta;
       ++its;
       const double e = std::fabs(eta);
+      hist.push_back(e / g1);
       checked = false;
       if (e <= p->o.tol * g1 || (e <= 100.0 * p->o.tol * g1 && (its - its0) % kMinresCheck == 0)) {
         if ((rc = true_residual())) return rc;
@@ -1358,6 +1529,15 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
   p->inner_its_sum = 0;
   p->inner_blocks = 0;
   p->inner_its_max = 0;
+  p->bytes_acc = 0.0;
+  p->its_acc.assign(p->nf, 0);
+  p->pt.used = 0;
+  p->pt.on = true;
+  struct TimerOff {
+    pintoc_problem* q;
+    ~TimerOff() { q->pt.on = false; }
+  } timer_off{p};
+  std::vector<double> hist;
   double hb[64], hb2[64];
   if ((rc = dots(p, s, b, 1, b, p->dd, hb))) return rc;
   const double bnorm = std::sqrt(hb[0]);
@@ -1368,10 +1548,10 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
     launch_fill_zero(s, x, n * sizeof(double));
     conv = true;
   } else if (p->o.outer == PINTOC_OUTER_MINRES) {
-    if ((rc = solve_minres(p, b, x, bnorm, s, its, res, conv))) return rc;
+    if ((rc = solve_minres(p, b, x, bnorm, s, its, res, conv, hist))) return rc;
   } else {
     // r = b - A x
-    kkt(p, x, p->rvec, s);
+    kkt_t(p, x, p->rvec, s);
     launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
     if ((rc = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb))) return rc;
     res = std::sqrt(hb[0]);
@@ -1393,8 +1573,10 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
         double* zk = p->Zk + (size_t)k * n;
         double* w = p->Vk + (size_t)(k + 1) * n;
         if ((rc = precond(p, vk, zk, s))) return rc;
-        kkt(p, zk, w, s);
+        kkt_t(p, zk, w, s);
         // classical Gram-Schmidt, twice
+        const int ph = phase_open(p, s, PINTOC_PHASE_ORTH);
+        p->bytes_acc += (4.0 * k + 13.0) * p->model_canon;
         if ((rc = dots(p, s, p->Vk, k + 1, w, p->dd, hb))) return rc;
         launch_mgs_update(s, w, p->Vk, n, k + 1, p->dd, n);
         if ((rc = dots(p, s, p->Vk, k + 1, w, p->dd2, hb2))) return rc;
@@ -1406,6 +1588,7 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
         H[(size_t)(k + 1) * m + k] = hk1;
         if (hk1 > 0) launch_axpby(s, w, w, 1.0 / hk1, 0.0, n);
         else breakdown = true;
+        phase_close(p, s, ph);
         for (int i = 0; i < k; ++i) {
           const double a = H[(size_t)i * m + k], c = H[(size_t)(i + 1) * m + k];
           H[(size_t)i * m + k] = cs[i] * a + sn[i] * c;
@@ -1420,6 +1603,7 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
         g[k + 1] = -sn[k] * g[k];
         g[k] = cs[k] * g[k];
         ++its;
+        hist.push_back(std::fabs(g[k + 1]) / bnorm);
         // stagnation guard: a first restart cycle (at least ten iterations)
         // without halving the initial residual
         stalled = p->o.stall_guard && its >= std::max(10, m) && std::fabs(g[k + 1]) > 0.5 * res0;
@@ -1431,10 +1615,13 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
         for (int j = i + 1; j < k; ++j) v -= H[(size_t)i * m + j] * y[j];
         y[i] = v / H[(size_t)i * m + i];
       }
+      const int ph = phase_open(p, s, PINTOC_PHASE_ORTH);
       HIPCHK(hipMemcpyAsync(p->dd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
       launch_lincomb_add(s, x, p->Zk, n, k, p->dd, n);
+      phase_close(p, s, ph);
+      p->bytes_acc += (k + 2.0 + 4.0) * p->model_canon;
       // true residual
-      kkt(p, x, p->rvec, s);
+      kkt_t(p, x, p->rvec, s);
       launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
       if ((rc = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb))) return rc;
       res = std::sqrt(hb[0]);
@@ -1444,7 +1631,24 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   if (st) {
+    double* hist_out = st->residual_history;
+    const int hcap = st->history_capacity;
+    int32_t* cnt_out = st->inner_counts;
+    const int ccap = st->inner_counts_capacity;
     std::memset(st, 0, sizeof(*st));
+    st->residual_history = hist_out;
+    st->history_capacity = hcap;
+    st->inner_counts = cnt_out;
+    st->inner_counts_capacity = ccap;
+    if (hist_out && hcap > 0) {
+      st->history_length = (int32_t)std::min<size_t>((size_t)hcap, hist.size());
+      std::copy(hist.begin(), hist.begin() + st->history_length, hist_out);
+    }
+    if (cnt_out && ccap > 0)
+      for (int j = 0; j < std::min(ccap, p->nf); ++j) cnt_out[j] = (int32_t)p->its_acc[j];
+    phase_sum(p, st->phase_seconds);
+    st->model_bytes = p->bytes_acc;
+    st->precond_model_bytes = p->model_fft + p->model_block;
     st->outer_iterations = its;
     st->converged = conv ? 1 : 0;
     st->rel_residual = bnorm > 0 ? res / bnorm : 0.0;

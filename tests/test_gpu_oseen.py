@@ -96,7 +96,8 @@ def test_oseen_precond_single_frequency_full_size(lib):
     """Full size of the Oseen workload (N=128, nt=128, nu=1/100, beta=1e-4):
     a residual with one temporal Fourier mode is checked against the oracle's
     block j and nt-j alone."""
-    from oracle.precond import OseenPreconditioner
+    from oracle.precond import OseenPreconditioner, Settings
+    from oracle.smoothers import Tiling   # the library's tiled smoother (include/pintoc.h)
     w = W.config(3)
     j = 21
     print(f"oseen precond full size mode j={j}", flush=True)
@@ -106,7 +107,7 @@ def test_oseen_precond_single_frequency_full_size(lib):
     z = _host(gp.precond_apply(_dev(r)))
     from oracle.kkt import Problem as OP
     op = OP.from_workload(w, wind)
-    pc = OseenPreconditioner(op, wind, freqs=[j, w.nt - j])
+    pc = OseenPreconditioner(op, wind, Settings(tiling=Tiling(48, 32)), freqs=[j, w.nt - j])
     ref = op.to_canonical(pc.apply(op.to_compact(r), nonlinear=False))
     assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
 

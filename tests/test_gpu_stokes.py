@@ -99,7 +99,8 @@ def test_precond_single_frequency_full_size(lib):
     one Fourier mode j in time excites only blocks j and nt-j, so the oracle
     computes its image from one frequency block."""
     from oracle.kkt import Problem as OP
-    from oracle.precond import StokesPreconditioner
+    from oracle.precond import StokesPreconditioner, Settings
+    from oracle.smoothers import Tiling   # the library's tiled smoother (include/pintoc.h)
     w = W.config(2)
     j = 37
     print(f"precond full size N={w.N} nt={w.nt} mode j={j}", flush=True)
@@ -107,7 +108,7 @@ def test_precond_single_frequency_full_size(lib):
     r = W.single_frequency_canonical(w.N, w.nt, j, seed=3)
     z = _host(gp.precond_apply(_dev(r)))
     op = OP.from_workload(w)
-    pc = StokesPreconditioner(op, freqs=[j, w.nt - j])
+    pc = StokesPreconditioner(op, Settings(tiling=Tiling(48, 32)), freqs=[j, w.nt - j])
     ref = op.to_canonical(pc.apply(op.to_compact(r), nonlinear=False))
     assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
 
@@ -231,3 +232,29 @@ def test_solve_full_size_oracle_residual(lib):
     assert rel <= 1e-8
     assert abs(rel - st["rel_residual"]) <= 1e-3 * st["rel_residual"]
     assert np.all(xh[~W.canonical_mask(w.N, w.nt)] == 0)
+
+
+def test_solve_stats(lib):
+    """The statistics of a solve: device time per phase (all phases present,
+    together within the wall time), the byte model (one linear application as
+    the benchmark's formula; the whole solve at least that many times the
+    applications), the residual history and the per-frequency inner counts."""
+    import bench
+    w = W.config(1)
+    gp = lib.Problem.from_workload(w, inner=lib.INNER_GMRES)
+    b = gp.assemble_rhs(_dev(W.desired_state(w)))
+    x, st, ok = gp.solve(b, history=64)
+    assert ok
+    ph = st["phase_seconds"]
+    print(f"phases {ph}, wall {st['seconds']:.4f}", flush=True)
+    assert all(v > 0 for v in ph.values())
+    assert sum(ph.values()) <= 1.05 * st["seconds"] + 1e-3
+    ref = bench.precond_model_bytes(w.N, w.nt, 4, 10, 16)["total"]
+    assert abs(st["precond_model_bytes"] - ref) <= 1e-12 * ref
+    assert st["model_bytes"] >= st["precond_applications"] * st["precond_model_bytes"]
+    h = st["residual_history"]
+    assert len(h) == st["outer_iterations"] and h[-1] <= 1e-8 and min(h) > 0
+    nf = w.nt // 2 + 1
+    counts = st["inner_counts"]
+    assert len(counts) == nf and min(counts) > 0
+    assert sum(counts) == round(st["inner_iterations_mean"] * nf * st["precond_applications"])

@@ -55,6 +55,18 @@ def test_host_validation(lib):
     assert o.outer == 0
     for bad_opt in (default_options(outer=2), default_options(outer=1, inner=1), default_options(outer=1, restart=3)):
         assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(bad_opt), ctypes.byref(h)) == -1
+    # smoother option and domain validation
+    assert o.smoother == 0
+    assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(default_options(smoother=2)),
+                                     ctypes.byref(h)) == -1
+    assert b"smoother" in lib.pintoc_last_error()
+    assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(default_options(smoother=1)),
+                                     ctypes.byref(h)) == 0
+    lib.pintoc_problem_destroy(h)
+    for dom in [(0.0, 0.0, 1.0, 2.0), (1.0, 0.0, 1.0, 0.0), (0.0, 0.0, -1.0, -1.0)]:
+        bad = Desc(8, 16, 1.0, 1.0, 1e-2, 0, None, *dom)
+        assert lib.pintoc_problem_create(ctypes.byref(bad), ctypes.byref(o), ctypes.byref(h)) == -1
+        assert b"square" in lib.pintoc_last_error()
     wind = (ctypes.c_double * (2 * 17 * 17))()
     oseen = Desc(8, 16, 1.0, 1.0, 1e-2, 1, ctypes.cast(wind, ctypes.POINTER(ctypes.c_double)))
     assert lib.pintoc_problem_create(ctypes.byref(oseen), ctypes.byref(default_options(outer=1)), ctypes.byref(h)) == -1
@@ -113,3 +125,28 @@ def test_serve_stream_draw():
     assert np.all(np.diff(arr) > 0) and 0.8 < arr[-1] / 256 < 1.2
     assert {w.N for w, _ in s} <= {32, 64, 128, 256} and 256 in {w.N for w, _ in s}
     assert max(w.N for w, _ in W.serve_stream(64, max_N=128)) <= 128
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's field
+    offsets and sizes (the header compiled by gcc on the host)."""
+    import subprocess
+    from paper_2405_18964_amd._lib import Desc, KernelTiming, Options, SolveStats
+    structs = {"pintoc_problem_desc": Desc, "pintoc_options": Options, "pintoc_solve_stats": SolveStats,
+               "pintoc_kernel_timing": KernelTiming}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pintoc.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
