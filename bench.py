@@ -36,20 +36,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the dominant kernel (finest-grid pre-smoothing sweep) from two
-# rocprofv3 --pmc passes over one solve of this workload (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch at the finest grid), each scaled by what the
-# same counter reads for a 1 GiB device copy in the same process (FETCH_SIZE
-# 524330.3 KiB, WRITE_SIZE 1048576 KiB).  Valid only for the kernel source they
-# were taken on: reported as null once that file changes.
+# The roofline kernel: the finest-grid post-smoothing sweep of the velocity
+# multigrid (the largest share of device time in the solve).
+SWEEP_KERNEL = "k_q2_sweep<double,false,false,true>"
+
+# HBM traffic of that kernel from two rocprofv3 --pmc passes over one solve of
+# this workload (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch at the finest
+# grid), each scaled by what the same counter reads for a 1 GiB device copy in
+# the same process.  Valid only for the kernel source they were taken on:
+# reported as null once that file changes (or before they are taken).
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2405_18964_amd", "csrc", "q2_tiles.hip")
-SWEEP_PMC = {"source_sha256": "2e972e25d279af992d70cb6a44fbf622b8d1c0048c0d6ad1b8b2b9f983a0b544",
-             "fetch_kib": 363452.0, "fetch_scale": 1048576.0 / 524330.3,
-             "write_kib": 420161.8, "write_scale": 1.0}
+SWEEP_PMC = None
 
 
 def sweep_traffic_bytes():
     import hashlib
+    if SWEEP_PMC is None:
+        return None
     with open(SWEEP_SOURCE, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != SWEEP_PMC["source_sha256"]:
             return None
@@ -62,7 +65,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3; 1 for --config 4 and 5)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2,
-                    help="workload: 1, 2 (single Stokes problem) or 4 (batched 64-problem mix)")
+                    help="workload: 1, 2 (single Stokes problem), 3 (single Oseen problem), "
+                         "4 (batched 64-problem mix) or 5 (served request stream)")
     ap.add_argument("--batch-count", type=int, default=64, help="problems of the batched mix (--config 4)")
     ap.add_argument("--workers", type=int, default=4, help="concurrent problems on the device (--config 4)")
     ap.add_argument("--requests", type=int, default=32, help="requests of the served stream (--config 5)")
@@ -70,88 +74,159 @@ def parse():
     ap.add_argument("--serve-max-n", type=int, default=128, help="largest grid of the served stream (--config 5)")
     ap.add_argument("--compare", action="store_true",
                     help="--config 4: also solve the mix one problem at a time (FP32-inner and FP64)")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
+                    help="inner arithmetic of the timed solves (default: fp64 for Stokes, fp32 for Oseen)")
     ap.add_argument("--inner", choices=["gmres", "linear"], default="gmres")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond-reps", type=int, default=5)
-    ap.add_argument("--no-fp32", action="store_true", help="skip the extra FP32-inner solve")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the solve in the other precision mode")
     ap.add_argument("--no-minres", action="store_true", help="skip the extra MINRES (Algorithm 1) solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of 1 GiB first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def precond_model_bytes(N: int, nt: int, n_vcycles: int, n_cheb: int, csize: int) -> dict:
-    """Compulsory HBM bytes of one linear preconditioner application
-    (Algorithm 1): every kernel pass reads/writes each field it touches once.
-
-    Field sizes per kept frequency (nf = nt/2 + 1): 4 complex Q2 grids (velocity
-    of both blocks) and 2 complex Q1 grids (pressure).  Per multigrid level
-    (sizes shrink by 4, so a cycle costs 4/3 of its finest level): the
-    pre-smoothing sweep reads x, b and writes x (3 passes; 2 in the first cycle,
-    which starts from x = 0), the post-smoothing sweep reads x, the coarse
-    correction and b and writes x (3 + 1/4).  Between them the Q2 levels run
-    one fused residual/restriction pass (reads x, b, writes the coarse rhs:
-    2 + 1/4), the Q1 levels a residual (3) and a restriction (1 + 1/4): 8.5
-    (Q2) and 10.5 (Q1) passes per level.  A Chebyshev step reads x_k, x_{k-1},
-    b, writes x_{k+1}; the first reads b and writes x_1, the second has no
-    x_0 to read (4 n - 3 passes for n steps).  The FFT pair reads and writes the canonical vector and
-    the frequency vector once each."""
-    nf = nt // 2 + 1
-    nq2, np2 = (2 * N + 1) ** 2, (N + 1) ** 2
-    FV = 4 * nf * nq2 * csize          # velocity frequency fields
-    FP = 2 * nf * np2 * csize          # pressure frequency fields
-    L = 2 * nq2 + np2
-    canon = 2 * nt * L * 8
-    freq = FV + FP
-    mg_w = (8.5 * n_vcycles - 1.0) * 4.0 / 3.0 * FV
-    mg_k = (10.5 * n_vcycles - 1.0) * 4.0 / 3.0 * FP
-    cheb = (1 + 4 * (n_cheb - 1)) * FP
-    schur = 2 * FP + 3 * FP            # unpin copy, combine
-    fft = 2 * (canon + freq)
-    total = mg_w + mg_k + cheb + schur + fft
-    return {"total": total, "mg_velocity": mg_w, "mg_pressure": mg_k, "chebyshev": cheb, "fft": fft,
-            "velocity_field_bytes": FV}
+def _host_cores() -> int:
+    """Cores this process may use on the host (the CPU share of one GPU is at
+    most 16 cores on the GPU hosts), whatever the machine's total."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
-def cpu_baseline(w, outer_its: int, inner_mean: float, budget_s: float = 15.0) -> dict:
-    """Time the oracle's per-frequency block solve P~_j^{-1} at the full grid
-    size on the host and extrapolate to one KKT solve with the iteration
-    counts the GPU solve used (each outer iteration applies P~_j^{-1} to
-    (inner_mean + 1) vectors per frequency for all nt frequencies)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_block_worker(args):
+    """One pool worker: the oracle's nonlinear block solve of frequency j
+    (Algorithm 2 / its Oseen analogue: T transforms, inner GMRES with the
+    block preconditioner, the block matvec and Gram-Schmidt) capped at one
+    inner iteration, on one BLAS thread.  Returns (seconds, applications of
+    the block preconditioner and block matrix it made)."""
+    w, j = args
     import numpy as np
     from threadpoolctl import threadpool_limits
 
+    import workloads as W
     from oracle.kkt import Problem as OP
-    from oracle.precond import StokesPreconditioner
+    from oracle.precond import OseenPreconditioner, Settings, StokesPreconditioner
 
     with threadpool_limits(limits=1):
-        op = OP.from_workload(w)
-        freqs = [1, w.nt // 4, w.nt // 2]
-        pc = StokesPreconditioner(op, freqs=freqs)
-        rng = np.random.default_rng(0)
-        n = op.nv
-        for j in freqs:
-            pc.W_mg(j)                                   # set-up outside the timing
-        samples = 0
-        t_used = 0.0
-        while t_used < budget_s:                         # bounded sample: ~budget_s of CPU work
-            j = freqs[samples % len(freqs)]
-            s1 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
-            s2 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
-            s3 = rng.standard_normal(op.nP) + 1j * rng.standard_normal(op.nP)
-            s4 = rng.standard_normal(op.nP) + 1j * rng.standard_normal(op.nP)
-            t0 = time.perf_counter()
-            pc.ptilde_inv(j, s1, s2, s3, s4)
-            t_used += time.perf_counter() - t0
-            samples += 1
-    t_block = t_used / samples
-    t_solve = outer_its * (inner_mean + 1.0) * w.nt * t_block
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{samples} per-frequency P~_j applications of the FP64 oracle at N={w.N} "
-                       f"({t_block:.2f} s each, BLAS threads 1), extrapolated to {outer_its} outer x "
-                       f"({inner_mean:.1f} inner + 1) x {w.nt} frequencies; FFTs and matvecs omitted"),
-            "seconds_measured": t_used}
+        wind = W.wind_nodal(w.N) if w.flow == W.OSEEN else None
+        op = OP.from_workload(w, wind)
+        st = Settings(inner_maxit=1, inner_restart=1)
+        if w.flow == W.STOKES:
+            pc = StokesPreconditioner(op, st, freqs=[j])
+            pc.W_mg(j)                                  # multigrid set-up outside the timing
+        else:
+            pc = OseenPreconditioner(op, wind, st, freqs=[j])
+            pc.Q_mgs(j)
+        rng = np.random.default_rng(j)
+        r = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in (op.nv, op.nv, op.nP, op.nP)]
+        t0 = time.perf_counter()
+        pc.block_apply(j, *r, nonlinear=True)
+        # GMRES capped at one iteration: one Arnoldi step (preconditioner,
+        # block matrix, Gram-Schmidt), the update through the preconditioner
+        # and the residual through the block matrix
+        return time.perf_counter() - t0, 2
+
+
+def cpu_sample(w) -> dict:
+    """Time the FP64 oracle on the host, before the GPU is touched.
+
+    The per-frequency block solves are the oracle's parallel part (the paper
+    distributes frequency blocks over processes, section 5.3): one pool worker
+    per host core, each timing one frequency's nonlinear block solve capped at
+    one inner iteration, all workers at once so they share memory bandwidth as
+    a full run would.  The serial parts -- the time FFT pair over the whole
+    vector, one all-at-once matvec and one step of the outer modified
+    Gram-Schmidt -- are timed after the pool on one core."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import circulant as circ
+    from oracle.kkt import Problem as OP
+
+    cores = _host_cores()
+    nf = w.nt // 2 + 1
+    js = sorted({int(round(i * (nf - 1) / max(cores - 1, 1))) for i in range(cores)})
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(len(js)) as pool:
+        res = pool.map(_oracle_block_worker, [(w, j) for j in js], chunksize=1)
+    t_pool = time.perf_counter() - t0
+    t_app = float(np.mean([t / k for t, k in res]))     # one block preconditioner + block matvec, under load
+    with threadpool_limits(limits=1):
+        op = OP.from_workload(w, W.wind_nodal(w.N) if w.flow == W.OSEEN else None)
+        x = np.random.default_rng(0).standard_normal(2 * op.nt * op.n)
+        t1 = time.perf_counter()
+        circ.time_ifft(op, circ.time_fft(op, x))
+        t_fft = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        y = op.kkt_apply(x)
+        t_mv = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        hdot = np.vdot(x, y)
+        y -= hdot * x
+        t_mgs = time.perf_counter() - t1
+    return {"cores": cores, "cpu_model": _cpu_model(), "t_block_app": t_app, "t_fft_pair": t_fft,
+            "t_matvec": t_mv, "t_mgs_step": t_mgs, "frequencies_sampled": js, "pool_seconds": t_pool,
+            "seconds_measured": t_pool + t_fft + t_mv + t_mgs}
+
+
+def cpu_baseline(w, smp: dict, outer_its: int, inner_mean: float, restart: int = 10) -> dict:
+    """Oracle solves/s extrapolated from the sample: per outer iteration the
+    oracle's preconditioner transforms the vector, solves all nt frequency
+    blocks (it does not use the conjugate symmetry of real data) with
+    inner_mean + 1 block preconditioner and block matrix applications each,
+    spread over the pool, and makes one all-at-once matvec and a Gram-Schmidt
+    step against half a restart cycle's basis on average; plus the final
+    residual."""
+    cores = smp["cores"]
+    waves = math.ceil(w.nt / cores)
+    per_outer = (smp["t_fft_pair"] + waves * (inner_mean + 1.0) * smp["t_block_app"] + smp["t_matvec"]
+                 + (restart + 1) / 2.0 * smp["t_mgs_step"])
+    t_solve = outer_its * per_outer + smp["t_matvec"]
+    kind = "Stokes (Algorithm 2)" if w.flow == 0 else "Oseen (Algorithm 3 inside GMRES)"
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "cpu_model": smp["cpu_model"], "extrapolated": True,
+            "sample": (f"FP64 oracle on {cores} host cores ({smp['cpu_model']}): {len(smp['frequencies_sampled'])} "
+                       f"per-frequency {kind} block solves of the N={w.N}, nt={w.nt} workload in a process pool "
+                       f"(one inner iteration each: {smp['t_block_app']:.2f} s per block preconditioner + block "
+                       f"matrix application under full load), one time-FFT pair ({smp['t_fft_pair']:.2f} s), "
+                       f"all-at-once matvec ({smp['t_matvec']:.2f} s) and Gram-Schmidt step "
+                       f"({smp['t_mgs_step']:.2f} s) on one core; extrapolated to {outer_its} outer iterations x "
+                       f"{w.nt} frequency blocks x ({inner_mean:.1f} inner + 1) applications over {cores} cores"),
+            "seconds_measured": smp["seconds_measured"], "seconds_per_solve": t_solve}
+
+
+def _pct(lat, q):
+    s = sorted(lat)
+    return s[min(len(s) - 1, max(0, int(math.ceil(q * len(s))) - 1))]
+
+
+def _timed_solve(gp, b, x):
+    """One solve from x = 0 timed with host clocks around a synchronised
+    call; returns (seconds, stats, converged)."""
+    import torch
+    x.zero_()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, st, ok = gp.solve(b, x)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t1, st, ok
 
 
 def main():
@@ -161,21 +236,28 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
+    import workloads as W
+
+    if args.config not in (4, 5):
+        w = W.config(args.config)
+        # the oracle sample runs first, in forked workers, before the GPU is touched
+        smp = None if args.no_cpu_baseline else cpu_sample(w)
     import numpy as np
     import torch
 
     import paper_2405_18964_amd as P
-    import workloads as W
 
     if args.config == 4:
         return bench_batch(args)
     if args.config == 5:
         return bench_serve(args)
-    w = W.config(args.config)
-    prec = P.PREC_FP64 if args.precision == "fp64" else P.PREC_FP32_INNER
+    precision = args.precision or ("fp32" if w.flow == W.OSEEN else "fp64")
+    prec = P.PREC_FP64 if precision == "fp64" else P.PREC_FP32_INNER
     inner = P.INNER_GMRES if args.inner == "gmres" else P.INNER_LINEAR
-    gp = P.Problem.from_workload(w, inner=inner, precision=prec, max_outer=60 if args.inner == "gmres" else 400,
-                                 restart=10 if args.inner == "gmres" else 30)
+    flow = "Stokes" if w.flow == W.STOKES else "Oseen"
+    solver_opts = dict(inner=inner, max_outer=60 if args.inner == "gmres" else 400,
+                       restart=10 if args.inner == "gmres" else 30)
+    gp = P.Problem.from_workload(w, precision=prec, **solver_opts)
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -195,7 +277,7 @@ def main():
         print(f"[bench] warmup {i}: {st['outer_iterations']} its, {st['seconds']:.2f} s", file=sys.stderr,
               flush=True)
     lat, stats = [], []
-    gp.profile_enable(True)          # HIP events around the dominant kernel's launches
+    gp.profile_enable(True)          # HIP events around the finest-grid smoother launches
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -216,28 +298,27 @@ def main():
     kt = gp.profile_read()
     gp.profile_enable(False)
     # independent check of the last solution: true residual through the KKT matvec
-    r = b - gp.kkt_apply(x)
-    rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
-    # linear preconditioner application: model bytes / time
+    rel = float(torch.linalg.norm(b - gp.kkt_apply(x)) / torch.linalg.norm(b))
+    x_main = x.clone()
+    # linear preconditioner application (Algorithm 1 / Algorithm 3): model bytes / time
     lp = P.Problem.from_workload(w, inner=P.INNER_LINEAR, precision=prec)
     z = lp.empty()
     lp.precond_apply(b, z)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
+    pc_lat = []
     for _ in range(args.precond_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         lp.precond_apply(b, z)
-    e1.record(stream)
-    e1.synchronize()
-    t_pc = e0.elapsed_time(e1) / 1e3 / args.precond_reps
-    csize = 16 if args.precision == "fp64" else 8
-    model = precond_model_bytes(w.N, w.nt, 4, 10, csize)
-    del lp
-    lat_sorted = sorted(lat)
-    p50 = lat_sorted[len(lat) // 2]
-    p99 = lat_sorted[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]
+        e1.record(stream)
+        e1.synchronize()
+        pc_lat.append(e0.elapsed_time(e1) / 1e3)
+    t_pc = sum(pc_lat) / len(pc_lat)
+    pc_bytes = stats[-1]["precond_model_bytes"]
+    del lp, z
     outer = int(np.mean([s["outer_iterations"] for s in stats]))
     inner_mean = float(np.mean([s["inner_iterations_mean"] for s in stats]))
+    phases = {k: float(np.mean([s["phase_seconds"][k] for s in stats])) for k in P.PHASES}
     out = {
         "metric": "KKT solves/sec to 1e-8 residual and preconditioner-apply HBM GB/s; p50/p99",
         "value": args.steps / wall,
@@ -249,56 +330,68 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32-inner/f64-outer",
+        "dtype": "f64" if precision == "fp64" else "f32-inner/f64-outer",
         "data": "synthetic",
-        "config": {"workload": f"Stokes control, Q2-Q1 on {w.N}x{w.N} quads, nt={w.nt}, T={w.T}, nu={w.nu}, "
-                               f"beta={w.beta}, {gp.n_all} unknowns (canonical)",
-                   "solver": f"FGMRES(10) + block-circulant preconditioner, inner={args.inner}",
-                   "precision": args.precision},
-        "latency_s": {"p50": p50, "p99": p99, "all": lat},
+        "config": {"workload": f"{flow} control, Q2-Q1 on {w.N}x{w.N} quads of the unit square, nt={w.nt}, "
+                               f"T={w.T}, nu={w.nu:g}, beta={w.beta:g}"
+                               + (", wind w=(2y(1-x^2), -2x(1-y^2))" if w.flow == W.OSEEN else "")
+                               + f", {gp.n_all} unknowns (canonical)",
+                   "solver": f"FGMRES({solver_opts['restart']}) + block-circulant preconditioner, "
+                             f"inner={args.inner}" + (", coarse-level viscosity on the Q_j multigrid"
+                                                       if w.flow == W.OSEEN else ""),
+                   "precision": precision},
+        "latency_s": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99), "all": lat},
         "iterations": {"outer": outer, "inner_mean": inner_mean,
                        "inner_max": int(max(s["inner_iterations_max"] for s in stats))},
         "final_rel_residual": rel,
-        "precond_apply": {"ms": 1e3 * t_pc, "model_bytes": model["total"],
-                          "model_GBs": model["total"] / t_pc / 1e9,
-                          "frac_of_hbm_peak": model["total"] / t_pc / 1e9 / HBM_PEAK_GBS},
+        "phase_seconds": phases,
+        "solve_model_bytes": float(np.mean([s["model_bytes"] for s in stats])),
+        "precond_apply": {"ms": 1e3 * t_pc, "p50_ms": 1e3 * _pct(pc_lat, 0.5), "p99_ms": 1e3 * _pct(pc_lat, 0.99),
+                          "model_bytes": pc_bytes, "model_GBs": pc_bytes / t_pc / 1e9,
+                          "frac_of_hbm_peak": pc_bytes / t_pc / 1e9 / HBM_PEAK_GBS},
     }
-    achieved = kt["algorithmic_bytes"] / (kt["avg_ms"] * 1e-3) / 1e9
+    post = kt["post"]
+    achieved = post["algorithmic_bytes"] / (post["avg_ms"] * 1e-3) / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic_bytes(),
-                       "kernel": "k_q2_sweep<double,false,true,false> (finest-grid pre-smoothing sweep of the "
-                                 "velocity multigrid, all kept frequencies)",
-                       "avg_launch_ms": kt["avg_ms"], "launches_timed": kt["launches"],
-                       "algorithmic_bytes_per_launch": kt["algorithmic_bytes"]}
-    if not args.no_fp32 and args.precision == "fp64":
+                       "kernel": SWEEP_KERNEL + " (finest-grid post-smoothing sweep of the velocity multigrid "
+                                 "with the prolonged coarse correction, all kept frequencies; the kernel with "
+                                 "the largest share of device time)",
+                       "avg_launch_ms": post["avg_ms"], "launches_timed": post["launches"],
+                       "algorithmic_bytes_per_launch": post["algorithmic_bytes"]}
+    pre_gbs = kt["algorithmic_bytes"] / (kt["avg_ms"] * 1e-3) / 1e9
+    out["pre_smoothing_sweep"] = {"avg_launch_ms": kt["avg_ms"], "launches_timed": kt["launches"],
+                                  "algorithmic_bytes_per_launch": kt["algorithmic_bytes"], "achieved_GBs": pre_gbs,
+                                  "frac": pre_gbs / HBM_PEAK_GBS}
+    if not args.no_fp32:
+        # the other precision mode on the same right-hand side, and the
+        # difference of the two solutions (the FP32-inner result's error
+        # against the FP64 form, both at the 1e-8 true residual)
         del gp
         torch.cuda.empty_cache()
-        g32 = P.Problem.from_workload(w, inner=inner, precision=P.PREC_FP32_INNER, max_outer=60, restart=10)
-        x.zero_()
-        g32.solve(b, x)                                  # warm-up
-        x.zero_()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, st32, ok32 = g32.solve(b, x)
-        torch.cuda.synchronize()
-        t32 = time.perf_counter() - t1
-        r32 = float(torch.linalg.norm(b - g32.kkt_apply(x)) / torch.linalg.norm(b))
-        out["fp32_inner"] = {"solves_per_s": 1.0 / t32, "seconds": t32, "converged": bool(ok32),
-                             "final_rel_residual": r32, "outer": st32["outer_iterations"],
-                             "inner_mean": st32["inner_iterations_mean"],
-                             "note": "multigrid, Chebyshev, Uzawa and inner GMRES in FP32; outer FGMRES, "
-                                     "residuals and the coarsest-grid inverses in FP64"}
-        del g32
-    if not args.no_minres and args.precision == "fp64" and w.flow == W.STOKES:
+        other = "fp32" if precision == "fp64" else "fp64"
+        go = P.Problem.from_workload(w, precision=P.PREC_FP32_INNER if other == "fp32" else P.PREC_FP64,
+                                     **solver_opts)
+        _timed_solve(go, b, x)                       # warm-up
+        t_o, st_o, ok_o = _timed_solve(go, b, x)
+        r_o = float(torch.linalg.norm(b - go.kkt_apply(x)) / torch.linalg.norm(b))
+        x32, x64 = (x, x_main) if other == "fp32" else (x_main, x)
+        err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+        out["fp32_inner" if other == "fp32" else "fp64_reference"] = {
+            "solves_per_s": 1.0 / t_o, "seconds": t_o, "converged": bool(ok_o), "final_rel_residual": r_o,
+            "outer": st_o["outer_iterations"], "inner_mean": st_o["inner_iterations_mean"]}
+        out["fp32_inner_vs_fp64"] = {
+            "rel_error_2norm": err,
+            "note": "||x_fp32inner - x_fp64|| / ||x_fp64|| for this right-hand side; multigrid, Chebyshev, "
+                    "Uzawa and inner GMRES in FP32, outer FGMRES, residuals and coarsest-grid inverses in FP64"}
+        print(f"[bench] {other} solve: {st_o['outer_iterations']} its, {t_o:.2f} s, rel. difference {err:.2e}",
+              file=sys.stderr, flush=True)
+        del go
+    if not args.no_minres and precision == "fp64" and w.flow == W.STOKES:
         # paper variant: MINRES with the linear preconditioner (Algorithm 1), FP64
         gm = P.Problem.from_workload(w, inner=P.INNER_LINEAR, outer=P.OUTER_MINRES, precision=P.PREC_FP64,
                                      max_outer=800)
-        x.zero_()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, stm, okm = gm.solve(b, x)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t1
+        tm, stm, okm = _timed_solve(gm, b, x)
         rm = float(torch.linalg.norm(b - gm.kkt_apply(x)) / torch.linalg.norm(b))
         out["minres_linear_fp64"] = {"solves_per_s": 1.0 / tm, "seconds": tm, "converged": bool(okm),
                                      "final_rel_residual": rm, "iterations": stm["outer_iterations"],
@@ -307,8 +400,8 @@ def main():
         print(f"[bench] MINRES + Algorithm 1 (FP64): {stm['outer_iterations']} its, {tm:.2f} s",
               file=sys.stderr, flush=True)
         del gm
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, outer, inner_mean)
+    if smp is not None:
+        out["cpu_baseline"] = cpu_baseline(w, smp, outer, inner_mean, solver_opts["restart"])
     print(json.dumps(out), flush=True)
 
 

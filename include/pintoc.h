@@ -270,21 +270,27 @@ int64_t pintoc_vector_length(const pintoc_problem* p);
  * application).  Entries are zero in LINEAR mode. */
 int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* counts, int32_t n);
 
-/* Live timing of the dominant kernel, for roofline reports: the fine-grid
- * pre-smoothing sweep of the velocity multigrid (the tiled Gauss-Seidel sweep
- * of section 3.4 applied to W_j (Stokes) or Q_j (Oseen) on all kept
- * frequencies at once).  While enabled, each such launch is bracketed by HIP
- * events recorded on the stream it runs on; the most recent 4096 launches are
- * kept.  Enabling allocates the events (host-side HIP objects, no device
- * memory from the workspace). */
+/* Live timing of the multigrid smoother at the finest grid, for roofline
+ * reports: the tiled Gauss-Seidel sweeps of section 3.4 applied to W_j
+ * (Stokes) or Q_j (Oseen) on all kept frequencies at once, before (pre-) and
+ * after (post-smoothing, with the prolonged coarse correction added while the
+ * tile loads) the coarse-grid correction.  While enabled, each such launch is
+ * bracketed by HIP events recorded on the stream it runs on; the most recent
+ * 4096 launches of each kind are kept.  Enabling allocates the events
+ * (host-side HIP objects, no device memory from the workspace).  The global
+ * multicolour smoother (PINTOC_SMOOTHER_GLOBAL) is not timed. */
 typedef struct {
-  double avg_ms;             /* mean duration of the timed launches           */
+  double avg_ms;             /* pre-smoothing: mean duration of the timed launches */
   int64_t launches;          /* number of launches averaged (<= 4096)         */
   double algorithmic_bytes;  /* mean compulsory bytes of one launch over the
                                 grids it updates (frequencies skipped by the
                                 inner GMRES excluded): read b, read x (not on
                                 the first V-cycle, which starts from x = 0),
-                                write x                                       */
+                                write the new iterate                         */
+  double post_avg_ms;        /* post-smoothing: the same three figures; the   */
+  int64_t post_launches;     /* bytes read the pre-smoothed iterate, b and    */
+  double post_algorithmic_bytes; /* the coarse correction (a quarter field)
+                                and write x                                   */
 } pintoc_kernel_timing;
 
 /* enable != 0 starts a new recording (clears previous samples); 0 stops.

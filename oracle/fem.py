@@ -1,4 +1,4 @@
-"""Q2-Q1 Taylor-Hood matrices on N x N uniform quadrilaterals of [0,1]^2.
+"""Q2-Q1 Taylor-Hood matrices on N x N uniform quadrilaterals of a square.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -9,6 +9,9 @@ Section 2.2 of the paper discretises velocity with Q2 and pressure with Q1
 * ``L``  the weak form of  -nu Laplace + w . grad  (per velocity component),
 * ``B``  the discretised *negative* divergence,
 * ``M_p, K_p, L_p`` their pressure-space counterparts (section 2.3 and 4).
+
+The square is [x0, x0 + side] x [y0, y0 + side] (default: the unit square;
+the paper's own experiments use [-1, 1]^2, section 5).
 
 Node numbering (both here and at the library boundary): a Q2 grid has
 ``nq = 2N+1`` nodes per side with spacing h/2, numbered ``iy*nq + ix`` (x
@@ -51,11 +54,15 @@ def p1_basis(s):
 class Grid:
     """Index bookkeeping for the Q2 velocity and Q1 pressure grids."""
 
-    def __init__(self, N: int):
+    def __init__(self, N: int, side: float = 1.0, origin=(0.0, 0.0)):
         if N < 1:
             raise ValueError("N must be >= 1")
+        if side <= 0:
+            raise ValueError("side must be positive")
         self.N = N
-        self.h = 1.0 / N
+        self.side = float(side)
+        self.x0, self.y0 = float(origin[0]), float(origin[1])
+        self.h = self.side / N
         self.nq = 2 * N + 1          # Q2 nodes per side
         self.np1 = N + 1             # Q1 nodes per side
         self.nq2 = self.nq * self.nq
@@ -71,11 +78,16 @@ class Grid:
     # node coordinates
     def q2_xy(self):
         iy, ix = np.divmod(np.arange(self.nq2), self.nq)
-        return ix * (self.h / 2), iy * (self.h / 2)
+        return self.x0 + ix * (self.h / 2), self.y0 + iy * (self.h / 2)
 
     def q1_xy(self):
         iy, ix = np.divmod(np.arange(self.np2), self.np1)
-        return ix * self.h, iy * self.h
+        return self.x0 + ix * self.h, self.y0 + iy * self.h
+
+    def q2_boundary(self):
+        """Mask of the Q2 nodes on the boundary (Dirichlet velocity nodes)."""
+        iy, ix = np.divmod(np.arange(self.nq2), self.nq)
+        return (ix == 0) | (iy == 0) | (ix == self.nq - 1) | (iy == self.nq - 1)
 
     # restriction operators (rows select kept nodes)
     def Rv(self):
@@ -123,7 +135,7 @@ def _assemble(rows_map, cols_map, elem_mats, shape):
     return sp.coo_matrix((em.ravel(), (R.ravel(), C.ravel())), shape=shape).tocsr()
 
 
-def assemble_full(N: int, wind=None):
+def assemble_full(N: int, wind=None, side: float = 1.0):
     """Element-by-element assembly on the full (unconstrained) node sets.
 
     Returns a dict with Q2 scalar matrices ``M2, K2`` (and ``N2`` if a wind is
@@ -132,8 +144,9 @@ def assemble_full(N: int, wind=None):
         Bx[i, j] = - int psi_i d/dx phi_j ,   By[i, j] = - int psi_i d/dy phi_j.
     ``wind`` is a pair of Q2 nodal arrays (wx, wy) of length (2N+1)^2.
     Convection: N2[i, j] = int (w . grad phi_j) phi_i, N1 likewise with psi.
+    ``side``: side length of the square (elements of side side / N).
     """
-    g = Grid(N)
+    g = Grid(N, side)
     wq, PHI, DX, DY, PSI, PDX, PDY = _tabulate(g.h)
     e2 = g.q2_elem_nodes()
     e1 = g.q1_elem_nodes()
@@ -174,10 +187,10 @@ class Operators:
     * ``Mp, Kp, Np``, ``Lp = nu Kp + Np`` (pressure space, natural BCs, pinned)
     """
 
-    def __init__(self, N: int, nu: float, wind=None):
-        self.grid = g = Grid(N)
+    def __init__(self, N: int, nu: float, wind=None, side: float = 1.0, origin=(0.0, 0.0)):
+        self.grid = g = Grid(N, side, origin)
         self.nu = float(nu)
-        full = assemble_full(N, wind)
+        full = assemble_full(N, wind, side)
         Rv, Rp = g.Rv(), g.Rp()
         r = lambda A, R1, R2: (R1 @ A @ R2.T).tocsr()
         self.Ms = r(full["M2"], Rv, Rv)

@@ -16,7 +16,9 @@ per backward-Euler step), the unknowns of block 0 are (v, p) at t_k = k tau,
 k = 1..nt, those of block 1 are (lambda, mu) at the same times, the rows of
 block 0 are the adjoint equations and those of block 1 the state equations.
 With v_0 = 0, f = 0, h = 0 and lambda_{nt+1} = 0 the right-hand side is
-tau M v_d(t_k) on the adjoint momentum rows and zero elsewhere (section 2.2).
+tau M v_d(t_k) on the adjoint momentum rows and zero elsewhere (section 2.2);
+``rhs_data`` forms it for a forcing f, Dirichlet data h and an initial
+velocity v_0 as well (the vectors g and h of section 2.2).
 
 Two vector layouts are used: *compact* (only free unknowns:
 [b][t][v (2 n_V), p (n_P)]) and *canonical* (the library's padded layout,
@@ -34,12 +36,18 @@ from .fem import Operators
 class Problem:
     """Spatial operators plus the time discretisation of one control problem."""
 
-    def __init__(self, N: int, nt: int, T: float, nu: float, beta: float, wind=None):
+    def __init__(self, N: int, nt: int, T: float, nu: float, beta: float, wind=None, domain=None):
+        """``domain``: (x0, y0, x1, y1) of a square, default the unit square."""
         if nt < 2:
             raise ValueError("nt must be >= 2")
         self.N, self.nt, self.T, self.nu, self.beta = N, nt, float(T), float(nu), float(beta)
         self.tau = self.T / nt
-        self.ops = Operators(N, nu, wind)
+        x0, y0, x1, y1 = (0.0, 0.0, 1.0, 1.0) if domain is None else (float(v) for v in domain)
+        if not (x1 > x0 and abs((y1 - y0) - (x1 - x0)) <= 1e-14 * (x1 - x0)):
+            raise ValueError("domain must be a square")
+        self.side = x1 - x0
+        self.origin = (x0, y0)
+        self.ops = Operators(N, nu, wind, self.side, self.origin)
         g = self.ops.grid
         self.nV, self.nv, self.nP = g.nV, g.nv, g.nP
         self.n = self.nv + self.nP             # unknowns per time level and block
@@ -126,6 +134,66 @@ class Problem:
         b = np.zeros((2, self.nt, self.n))
         b[0, :, :self.nv] = self.tau * (self.ops.M @ vdi.T).T
         return b.reshape(-1)
+
+    def rhs_data(self, vd=None, f=None, h=None, v0=None) -> np.ndarray:
+        """b of section 2.2 for general data (compact layout).
+
+        Nodal values on the full Q2 grid, None meaning zero: ``vd`` and ``f``
+        of shape (nt, 2, (2N+1)^2) at t_k = k tau, k = 1..nt; ``h`` of shape
+        (nt + 1, 2, (2N+1)^2) at t_k, k = 0..nt (only its boundary entries are
+        used); ``v0`` of shape (2, (2N+1)^2) (only its interior entries are
+        used; its boundary values are h at t_0).
+
+        The velocity at t_k is v_k = v_k^I + h_k^B, the unknown interior part
+        plus the known boundary values.  Moving every known term of the
+        discrete equations of section 2.2 to the right, with full-grid
+        matrices restricted to interior rows (R):
+          adjoint momentum  tau R M (v_d,k - h_k^B)
+          adjoint div.      0
+          state momentum    R [tau M f_k - (M + tau L) h_k^B + M w_{k-1}],
+                            w_0 = v_0^I + h_0^B, w_{k-1} = h_{k-1}^B (k >= 2)
+          state div.        -tau R_p B h_k^B
+        """
+        g, o, nt, tau = self.ops.grid, self.ops, self.nt, self.tau
+        full = o.full
+        nq2 = g.nq2
+        bd = g.q2_boundary()
+        M2 = full["M2"]
+        L2 = (self.nu * full["K2"] + full["N2"]).tocsr() if "N2" in full else (self.nu * full["K2"]).tocsr()
+        z = np.zeros((nt, 2, nq2))
+        vd = z if vd is None else np.asarray(vd, float)
+        f = z if f is None else np.asarray(f, float)
+        H = np.zeros((nt + 1, 2, nq2)) if h is None else np.asarray(h, float) * bd
+        v0i = np.zeros((2, nq2)) if v0 is None else np.asarray(v0, float) * ~bd
+        Rv, Rp = g.Rv(), g.Rp()
+        Bf = [full["Bx"], full["By"]]
+        b = np.zeros((2, nt, self.n))
+        for k in range(nt):
+            hk = H[k + 1]
+            wprev = (v0i + H[0]) if k == 0 else H[k]
+            adj = [tau * (Rv @ (M2 @ (vd[k, c] - hk[c]))) for c in range(2)]
+            st = [Rv @ (tau * (M2 @ f[k, c]) - (M2 @ hk[c] + tau * (L2 @ hk[c])) + M2 @ wprev[c]) for c in range(2)]
+            div = -tau * (Rp @ (Bf[0] @ hk[0] + Bf[1] @ hk[1]))
+            b[0, k, :self.nv] = np.concatenate(adj)
+            b[1, k, :self.nv] = np.concatenate(st)
+            b[1, k, self.nv:] = div
+        return b.reshape(-1)
+
+    def full_velocity(self, x: np.ndarray, h=None, v0=None) -> np.ndarray:
+        """State velocity on the full Q2 grid at t_0..t_nt: (nt + 1, 2, (2N+1)^2),
+        interior values from the compact solution x, boundary values from the
+        Dirichlet data h (as in ``rhs_data``), t_0 from v0 and h_0."""
+        g = self.ops.grid
+        nq2 = g.nq2
+        bd = g.q2_boundary()
+        H = np.zeros((self.nt + 1, 2, nq2)) if h is None else np.asarray(h, float) * bd
+        V = H.copy()
+        if v0 is not None:
+            V[0] += np.asarray(v0, float) * ~bd
+        v, _, _, _ = self.split(x)
+        for k in range(self.nt):
+            V[k + 1][:, g.v_interior] = v[k].reshape(2, g.nV)
+        return V
 
     # ----------------------------------------------------------- direct solve
     def solve_direct(self, b: np.ndarray) -> np.ndarray:

@@ -88,10 +88,11 @@ def inject_wind(wind, Nf: int):
 class Levels:
     """Level matrices and transfer operators of one hierarchy (one wind)."""
 
-    def __init__(self, N: int, wind=None):
+    def __init__(self, N: int, wind=None, side: float = 1.0):
         if N < 2 or (N & (N - 1)):
             raise ValueError("N must be a power of two >= 2")
         self.sizes = []
+        self.side = float(side)
         n = N
         while n >= 2:
             self.sizes.append(n)
@@ -101,7 +102,7 @@ class Levels:
         # largest nodal wind speed of the finest grid (0 without wind)
         self.wind_max = 0.0 if w is None else float(np.sqrt((w.reshape(2, -1) ** 2).sum(axis=0)).max())
         for l, n in enumerate(self.sizes):
-            self.ops.append(Operators(n, 1.0, w))
+            self.ops.append(Operators(n, 1.0, w, side))
             if l + 1 < len(self.sizes):
                 w = inject_wind(w, n)
         self.P2, self.P1 = [], []
@@ -131,16 +132,16 @@ class Levels:
         return self.P2[l] if fam == "q2" else self.P1[l]
 
 
-def coarse_viscosity(nu: float, wind_max: float, sizes) -> list:
+def coarse_viscosity(nu: float, wind_max: float, sizes, side: float = 1.0) -> list:
     """Viscosity of the multigrid level operators of a convection-diffusion
     operator: the true nu on the finest level; on a coarser level of n x n
-    elements (side h = 1/n) at least wind_max h / 4, so that its mesh Peclet
+    elements (side h = side/n) at least wind_max h / 4, so that its mesh Peclet
     number wind_max h / (2 nu_l) stays at most 2.  Rediscretising at the true
     nu makes the V-cycle diverge once the coarse levels are convection
     dominated (the Gauss-Seidel smoother and the coarse correction both
     amplify there); the finest level, where the residual is formed, keeps the
     true operator, so the cycle stays a preconditioner for it."""
-    return [nu if l == 0 else max(nu, wind_max / (4.0 * n)) for l, n in enumerate(sizes)]
+    return [nu if l == 0 else max(nu, wind_max * side / (4.0 * n)) for l, n in enumerate(sizes)]
 
 
 class ScalarMG:

@@ -98,7 +98,7 @@ class _Common:
     def __init__(self, P, wind=None, settings: Settings | None = None, freqs=None):
         self.P = P
         self.s = settings or Settings()
-        self.lv = Levels(P.N, wind)
+        self.lv = Levels(P.N, wind, P.side)
         self.d = circ.d_closed_form(P.nt)
         self.freqs = range(P.nt) if freqs is None else freqs
         self.inner_its = {}
@@ -290,7 +290,7 @@ class OseenPreconditioner(_Common):
         coarse-level viscosity of ``coarse_viscosity``."""
         if j not in self.mg_Q:
             a, tau, nu = self.q_shift(j), self.P.tau, self.P.nu
-            g = [tau * v for v in coarse_viscosity(nu, self.lv.wind_max, self.lv.sizes)]
+            g = [tau * v for v in coarse_viscosity(nu, self.lv.wind_max, self.lv.sizes, self.P.side)]
             self.mg_Q[j] = self._mg("q2", a, tau * nu, eta=tau, gamma_levels=g)
             self.mg_QH[j] = self._mg("q2", np.conj(a), tau * nu, eta_t=tau, gamma_levels=g)
         return self.mg_Q[j], self.mg_QH[j]

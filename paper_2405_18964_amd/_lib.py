@@ -13,6 +13,7 @@ PREC_FP64, PREC_FP32_INNER = 0, 1
 OUTER_FGMRES, OUTER_MINRES = 0, 1
 SMOOTHER_TILED, SMOOTHER_GLOBAL = 0, 1
 OK, NOT_CONVERGED = 0, 1
+EINVAL, ENOMEM, EHIP, ESTATE = -1, -2, -3, -4
 
 
 class LibraryMissing(RuntimeError):
@@ -57,7 +58,8 @@ class SolveStats(C.Structure):
 
 
 class KernelTiming(C.Structure):
-    _fields_ = [("avg_ms", C.c_double), ("launches", C.c_int64), ("algorithmic_bytes", C.c_double)]
+    _fields_ = [("avg_ms", C.c_double), ("launches", C.c_int64), ("algorithmic_bytes", C.c_double),
+                ("post_avg_ms", C.c_double), ("post_launches", C.c_int64), ("post_algorithmic_bytes", C.c_double)]
 
 
 _lib = None
@@ -221,13 +223,16 @@ class Problem:
         return [int(arr[i]) for i in range(k)]
 
     def profile_enable(self, on=True):
-        """Start (or stop) timing the finest-level velocity smoother launches."""
+        """Start (or stop) timing the finest-level velocity smoother launches
+        (pre- and post-smoothing sweeps)."""
         _check(library().pintoc_profile_enable(self._h, 1 if on else 0), "pintoc_profile_enable")
 
     def profile_read(self):
         kt = KernelTiming()
         _check(library().pintoc_profile_read(self._h, C.byref(kt)), "pintoc_profile_read")
-        return {"avg_ms": kt.avg_ms, "launches": kt.launches, "algorithmic_bytes": kt.algorithmic_bytes}
+        return {"avg_ms": kt.avg_ms, "launches": kt.launches, "algorithmic_bytes": kt.algorithmic_bytes,
+                "post": {"avg_ms": kt.post_avg_ms, "launches": kt.post_launches,
+                         "algorithmic_bytes": kt.post_algorithmic_bytes}}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -80,7 +80,8 @@ struct MGPlan {
   OpCoef* coefg = nullptr;
   std::vector<const double*> conv50;
   const OpCoef* coefgl(int l) const { return coefg + (size_t)l * ncoef; }
-  Probe* probe = nullptr;              // times the finest-level sweeps when on
+  Probe* probe = nullptr;              // times the finest-level pre-smoothing sweeps when on
+  Probe* probe_post = nullptr;         // times the finest-level post-smoothing sweeps when on
   int fpj = 1;                         // grids per frequency in the batch
   const int* mask = nullptr;           // per-frequency activity (inner GMRES), or null
   int active = 0;                      // grids of the batch that the mask leaves active
@@ -154,7 +155,7 @@ struct pintoc_problem {
   double2 abO_h;
   void *B1 = nullptr, *B2 = nullptr, *X1 = nullptr, *X2 = nullptr, *T1 = nullptr, *T2 = nullptr, *Rb = nullptr;
   void *C1 = nullptr, *C2 = nullptr, *Pt = nullptr, *Ub = nullptr;
-  Probe probe;
+  Probe probe, probe_post;
   // device time per phase of a solve: pairs of HIP events on the solve's
   // stream, summed when the solve ends
   struct PhaseTimer {
@@ -490,33 +491,45 @@ extern "C" int64_t pintoc_vector_length(const pintoc_problem* p) { return p ? p-
 
 extern "C" int pintoc_profile_enable(pintoc_problem* p, int32_t enable) {
   if (!p) return fail(PINTOC_EINVAL, "NULL handle");
+  MGPlan& m = p->d.flow == PINTOC_OSEEN ? p->mgQ : p->mgW;
   if (enable) {
-    if (p->probe.create() != PINTOC_OK) return fail(PINTOC_EHIP, "hipEventCreate failed");
-    p->probe.count = 0;
-    p->probe.on = true;
-    (p->d.flow == PINTOC_OSEEN ? p->mgQ : p->mgW).probe = &p->probe;
+    if (p->probe.create() != PINTOC_OK || p->probe_post.create() != PINTOC_OK)
+      return fail(PINTOC_EHIP, "hipEventCreate failed");
+    p->probe.count = p->probe_post.count = 0;
+    p->probe.on = p->probe_post.on = true;
+    m.probe = &p->probe;
+    m.probe_post = &p->probe_post;
   } else {
-    p->probe.on = false;
+    p->probe.on = p->probe_post.on = false;
   }
+  return PINTOC_OK;
+}
+
+// mean duration and algorithmic bytes of the recorded launches of one probe
+static int probe_mean(Probe& pr, double& ms_avg, int64_t& n_out, double& bytes_avg) {
+  const long n = std::min<long>(pr.count, Probe::kCap);
+  ms_avg = bytes_avg = 0.0;
+  n_out = n;
+  if (n == 0) return PINTOC_OK;
+  double sum = 0, bytes = 0;
+  for (long i = 0; i < n; ++i) {
+    HIPCHK(hipEventSynchronize(pr.e1[i]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, pr.e0[i], pr.e1[i]));
+    sum += ms;
+    bytes += pr.bytes[i];
+  }
+  ms_avg = sum / n;
+  bytes_avg = bytes / n;
   return PINTOC_OK;
 }
 
 extern "C" int pintoc_profile_read(pintoc_problem* p, pintoc_kernel_timing* out) {
   if (!p || !out) return fail(PINTOC_EINVAL, "NULL handle or output");
-  const long n = std::min<long>(p->probe.count, Probe::kCap);
-  if (n == 0) return fail(PINTOC_ESTATE, "no timed launches recorded");
-  double sum = 0, bytes = 0;
-  for (long i = 0; i < n; ++i) {
-    HIPCHK(hipEventSynchronize(p->probe.e1[i]));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, p->probe.e0[i], p->probe.e1[i]));
-    sum += ms;
-    bytes += p->probe.bytes[i];
-  }
-  out->avg_ms = sum / n;
-  out->launches = n;
-  out->algorithmic_bytes = bytes / n;
-  return PINTOC_OK;
+  if (std::min<long>(p->probe.count, Probe::kCap) == 0) return fail(PINTOC_ESTATE, "no timed launches recorded");
+  int rc = probe_mean(p->probe, out->avg_ms, out->launches, out->algorithmic_bytes);
+  if (rc != PINTOC_OK) return rc;
+  return probe_mean(p->probe_post, out->post_avg_ms, out->post_launches, out->post_algorithmic_bytes);
 }
 
 extern "C" int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* counts, int32_t n) {
@@ -713,11 +726,18 @@ extern "C" size_t pintoc_workspace_bytes(const pintoc_problem* p) { return p ? p
 
 extern "C" void pintoc_problem_destroy(pintoc_problem* p) { delete p; }
 
+static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s);
+
 extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes, void* stream) {
   if (!p || !dev) return fail(PINTOC_EINVAL, "NULL handle or workspace");
   if (((uintptr_t)dev) & 255) return fail(PINTOC_EINVAL, "workspace must be 256-byte aligned");
   if (bytes < p->need) return fail(PINTOC_ENOMEM, "workspace too small: need " + std::to_string(p->need) + " bytes");
-  hipStream_t s = (hipStream_t)stream;
+  return bind_impl(p, dev, bytes, (hipStream_t)stream);
+}
+
+// carve the workspace, clear it and upload the tables on stream s
+static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s) {
+  p->bound = false;
   p->ws = dev;
   p->ws_bytes = bytes;
   carve(p, (char*)dev);
@@ -911,7 +931,17 @@ static void vcycle(hipStream_t s, MGPlan& m, int l, cpx<R>* x, const cpx<R>* b, 
     launch_q1_restrict<R>(s, bc, r, n / 2, m.nb, m.mk());
   }
   vcycle<R>(s, m, l + 1, xc, bc, true);
+  // the second probe times the finest post-smoothing sweeps (reads t, b and the
+  // coarse correction, a quarter of a field; writes x)
+  Probe* pp = (l == 0 && m.probe_post && m.probe_post->on) ? m.probe_post : nullptr;
+  const int pslot = pp ? (int)(pp->count % Probe::kCap) : 0;
+  if (pp) (void)hipEventRecord(pp->e0[pslot], s);
   launch_tile_sweep<R>(s, m.q2, x, t, b, xc, n, h, m.coefl(l), m.fpc, m.nb, m.conv[l], false, m.mk());
+  if (pp) {
+    (void)hipEventRecord(pp->e1[pslot], s);
+    pp->bytes[pslot] = (3.0 * (double)m.nodes(0) + (double)m.nodes(1)) * m.active * sizeof(cpx<R>);
+    pp->count++;
+  }
 }
 
 // x = MG^cycles(b) from x = 0
