@@ -37,8 +37,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # The roofline kernel: the finest-grid post-smoothing sweep of the velocity
-# multigrid (the largest share of device time in the solve).
-SWEEP_KERNEL = "k_q2_sweep<double,false,false,true>"
+# multigrid (the largest share of device time in the Stokes solve);
+# template arguments <arithmetic, convection table, forward sweep, prolongation>.
+
+
+def sweep_kernel(fp64: bool, oseen: bool) -> str:
+    return f"k_q2_sweep<{'double' if fp64 else 'float'},{'true' if oseen else 'false'},false,true>"
+
 
 # HBM traffic of that kernel from two rocprofv3 --pmc passes over one solve of
 # this workload (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch at the finest
@@ -49,9 +54,9 @@ SWEEP_SOURCE = os.path.join(ROOT, "paper_2405_18964_amd", "csrc", "q2_tiles.hip"
 SWEEP_PMC = None
 
 
-def sweep_traffic_bytes():
+def sweep_traffic_bytes(kernel=None):
     import hashlib
-    if SWEEP_PMC is None:
+    if SWEEP_PMC is None or (kernel is not None and kernel != SWEEP_PMC["kernel"]):
         return None
     with open(SWEEP_SOURCE, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != SWEEP_PMC["source_sha256"]:
@@ -69,9 +74,14 @@ def parse():
                          "4 (batched 64-problem mix) or 5 (served request stream)")
     ap.add_argument("--batch-count", type=int, default=64, help="problems of the batched mix (--config 4)")
     ap.add_argument("--workers", type=int, default=4, help="concurrent problems on the device (--config 4)")
-    ap.add_argument("--requests", type=int, default=32, help="requests of the served stream (--config 5)")
-    ap.add_argument("--rho", type=float, default=0.8, help="arrival rate / measured capacity (--config 5)")
-    ap.add_argument("--serve-max-n", type=int, default=128, help="largest grid of the served stream (--config 5)")
+    ap.add_argument("--requests", type=int, default=256, help="requests of the served stream (--config 5)")
+    ap.add_argument("--rho", type=str, default="0.8",
+                    help="comma-separated arrival rates / capacity, one open-loop pass each (--config 5)")
+    ap.add_argument("--capacity", type=float, default=None,
+                    help="--config 5: capacity in solves/s measured earlier (skips the closed-loop pass)")
+    ap.add_argument("--slice-cycles", type=int, default=1,
+                    help="--config 5: FGMRES restart cycles per turn before a slot is recycled (0: whole solves)")
+    ap.add_argument("--serve-max-n", type=int, default=256, help="largest grid of the served stream (--config 5)")
     ap.add_argument("--compare", action="store_true",
                     help="--config 4: also solve the mix one problem at a time (FP32-inner and FP64)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
@@ -353,8 +363,9 @@ def main():
     post = kt["post"]
     achieved = post["algorithmic_bytes"] / (post["avg_ms"] * 1e-3) / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic_bytes(),
-                       "kernel": SWEEP_KERNEL + " (finest-grid post-smoothing sweep of the velocity multigrid "
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": sweep_traffic_bytes(sweep_kernel(precision == "fp64", w.flow == W.OSEEN)),
+                       "kernel": sweep_kernel(precision == "fp64", w.flow == W.OSEEN) + " (finest-grid post-smoothing sweep of the velocity multigrid "
                                  "with the prolonged coarse correction, all kept frequencies; the kernel with "
                                  "the largest share of device time)",
                        "avg_launch_ms": post["avg_ms"], "launches_timed": post["launches"],
@@ -478,7 +489,8 @@ def bench_batch(args):
 
 
 def bench_serve(args):
-    """Served form: Poisson arrivals at rho times the measured capacity."""
+    """Served form: Poisson arrivals at rho times the measured capacity,
+    slots recycled at FGMRES restart boundaries (``--slice-cycles``)."""
     import torch
 
     import paper_2405_18964_amd as P
@@ -492,47 +504,66 @@ def bench_serve(args):
                  "wind": W.wind_nodal(w.N) if w.flow == W.OSEEN else None, "vd": W.desired_state(w),
                  "arrival": (a / rate if rate else 0.0)} for w, a in stream]
     opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+
     def progress(tag):
         def cb(k, r):
             w = stream[k][0]
-            print(f"[bench] {tag}: request {k} ({w.name}, nt={w.nt}) {r['end'] - r['start']:.2f} s",
-                  file=sys.stderr, flush=True)
+            print(f"[bench] {tag}: request {k} ({w.name}, nt={w.nt}) {r['end'] - r['arrival']:.2f} s after arrival, "
+                  f"{r['slices']} turns", file=sys.stderr, flush=True)
         return cb
 
-    closed = run(jobs_at(None), workers=args.workers, checksum=True, on_done=progress("closed loop"), **opts)
-    cap = len(stream) / (time.perf_counter() - t0)
-    rate = args.rho * cap
-    print(f"[bench] closed loop: capacity {cap:.3f} solves/s; open loop at {rate:.3f} requests/s",
-          file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    out = run(jobs_at(rate), workers=args.workers, checksum=True, on_done=progress("open loop"), **opts)
-    wall = time.perf_counter() - t0
-    lat = sorted(r["end"] - r["arrival"] for r in out)
-    same = int(sum(a["digest"] == b["digest"] for a, b in zip(closed, out)))
+    closed = None
+    if args.capacity:
+        cap = args.capacity
+    else:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        closed = run(jobs_at(None), workers=args.workers, checksum=True, slice_cycles=args.slice_cycles,
+                     on_done=progress("closed loop"), **opts)
+        cap = len(stream) / (time.perf_counter() - t0)
+        print(f"[bench] closed loop: capacity {cap:.3f} solves/s", file=sys.stderr, flush=True)
+    rates = {}
+    for rho in [float(r) for r in args.rho.split(",")] if args.rho else []:
+        rate = rho * cap
+        print(f"[bench] open loop at rho={rho}: {rate:.3f} requests/s", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        out = run(jobs_at(rate), workers=args.workers, checksum=True, slice_cycles=args.slice_cycles,
+                  on_done=progress(f"rho={rho}"), **opts)
+        wall = time.perf_counter() - t0
+        lat = [r["end"] - r["arrival"] for r in out]
+        rates[str(rho)] = {"arrival_rate_per_s": rate, "solves_per_s": len(stream) / wall, "seconds": wall,
+                           "latency_s": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99)},
+                           "queue_s": {"p50": _pct([r["start"] - r["arrival"] for r in out], 0.5),
+                                       "p99": _pct([r["start"] - r["arrival"] for r in out], 0.99)},
+                           "converged": int(sum(r["converged"] for r in out)),
+                           "turns_mean": sum(r["slices"] for r in out) / len(out)}
+        if closed is not None:
+            rates[str(rho)]["identical_to_closed_loop"] = int(sum(a["digest"] == b["digest"]
+                                                                  for a, b in zip(closed, out)))
+    first = next(iter(rates.values())) if rates else None
     res = {
         "metric": "served KKT solves/sec to 1e-8 residual; p50/p99 arrival-to-completion latency",
-        "value": len(stream) / wall,
+        "value": first["solves_per_s"] if first else cap,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 0,
-        "ms_per_step": 1e3 * wall,
+        "ms_per_step": 1e3 * (first["seconds"] if first else len(stream) / cap),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32-inner/f64-outer",
         "data": "synthetic",
         "config": {"workload": f"{len(stream)} Poisson-arrival Stokes/Oseen control requests (N in 32..."
-                               f"{args.serve_max_n}, nt in 32...256), rate {args.rho} x measured capacity, "
-                               f"{args.workers} concurrent on one GPU"},
+                               f"{args.serve_max_n}, nt in 32...256, log-uniform beta, nu in {{1,1/50,1/100}}), "
+                               f"{args.workers} worker streams, slots recycled every {args.slice_cycles} FGMRES "
+                               "restart cycle(s)"},
         "capacity_solves_per_s": cap,
-        "arrival_rate_per_s": rate,
-        "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]},
-        "converged": int(sum(r["converged"] for r in out)),
-        "identical_to_closed_loop": same,
+        "capacity_measured": closed is not None,
+        "rates": rates,
     }
+    if closed is not None:
+        res["closed_loop_converged"] = int(sum(r["converged"] for r in closed))
     print(json.dumps(res), flush=True)
 
 

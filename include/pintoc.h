@@ -37,6 +37,8 @@ extern "C" {
 enum {
   PINTOC_OK = 0,
   PINTOC_NOT_CONVERGED = 1, /* pintoc_solve: tolerance not reached, x = last iterate */
+  PINTOC_PAUSED = 2,        /* pintoc_solve: stopped at a restart boundary after the
+                               caller's cycle budget; resume it (stats.resume)   */
   PINTOC_EINVAL = -1,       /* invalid argument (sizes, parameters, NULL pointers)   */
   PINTOC_ENOMEM = -2,       /* workspace too small                                   */
   PINTOC_EHIP = -3,         /* a HIP runtime call failed (message has its string)    */
@@ -80,9 +82,15 @@ enum { PINTOC_SMOOTHER_TILED = 0, PINTOC_SMOOTHER_GLOBAL = 1 };
 enum { PINTOC_OUTER_FGMRES = 0, PINTOC_OUTER_MINRES = 1 };
 
 /* Problem of section 2 (eq. OseenOptimization / OseenFlow) on a square
- * domain [x0, x1] x [y0, y1] (all four zero: the unit square), Q2-Q1
- * Taylor-Hood elements on N x N uniform quadrilaterals (section 2.2),
- * backward Euler with nt steps of tau = T / nt. */
+ * domain [x0, x1] x [y0, y1] (all four zero: the unit square; section 5 uses
+ * [-1, 1]^2), Q2-Q1 Taylor-Hood elements on N x N uniform quadrilaterals
+ * (section 2.2), backward Euler with nt steps of tau = T / nt.  A square of
+ * side l is solved as the unit square's problem with viscosity nu / l^2 and
+ * wind w / l (its matrices M, K, B, N scale as l^2, 1, l, l), with momentum
+ * rows scaled by l^2, divergence rows by l and the pressure by l at the
+ * boundary, so every entry point takes and returns the physical vectors.
+ * The inner GMRES of the nonlinear preconditioner then measures the
+ * residual of the unit-square blocks. */
 typedef struct {
   int32_t N;            /* quads per side, a power of two >= 2               */
   int32_t nt;           /* time steps = FFT length, >= 2, at most 1024       */
@@ -94,7 +102,9 @@ typedef struct {
                            divergence-free wind (x component first); NULL
                            for Stokes.  Copied; the caller may free it.      */
   double x0, y0, x1, y1; /* domain corners; x1 - x0 = y1 - y0 > 0 required
-                           (square elements); all zero = [0, 1]^2            */
+                           (square elements); all zero = [0, 1]^2.  The wind
+                           is sampled at the physical Q2 nodes
+                           (x0 + ix (x1 - x0) / (2N), y0 + iy (...) / (2N)). */
 } pintoc_problem_desc;
 
 /* Solver parameters.  Defaults (pintoc_default_options) follow section 5:
@@ -180,6 +190,19 @@ typedef struct {
                                     iterations per kept frequency j =
                                     0..nt/2, summed over the solve          */
   int32_t inner_counts_capacity; /* in: entries of inner_counts             */
+  int32_t cycle_budget;          /* in: > 0: FGMRES only -- return
+                                    PINTOC_PAUSED after this many restart
+                                    cycles of this call if not converged
+                                    (x = the iterate at the restart boundary,
+                                    the state of the solve kept in the
+                                    handle); 0: run to the end              */
+  int32_t resume;                /* in: 1 = continue the handle's paused
+                                    solve (same b and x pointers, x
+                                    untouched since); the iteration count,
+                                    initial residual, history, statistics
+                                    and the cap max_outer carry over, so the
+                                    iterates equal those of one uninterrupted
+                                    call bit for bit                        */
 } pintoc_solve_stats;
 
 /* Fill *o with the defaults above.  Never fails for a non-NULL pointer. */
@@ -212,6 +235,27 @@ int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes, void* stre
  * Asynchronous on ``stream``. */
 int pintoc_assemble_rhs(pintoc_problem* p, const double* vd, double* b, void* stream);
 
+/* Right-hand side for general data (section 2.2: the vectors g and h that
+ * carry forcing, boundary and initial conditions).  With v_k = v_k^I + h_k^B
+ * (unknown interior part, known Dirichlet values), the known terms of the
+ * discrete state and adjoint equations move to the right:
+ *   adjoint momentum rows  tau M (v_d(t_k) - h_k^B)
+ *   state momentum rows    tau M f(t_k) - (M + tau L) h_k^B + M w_{k-1},
+ *                          w_0 = v_0 (interior values) + h_0^B, w_{k-1} = h_{k-1}^B
+ *   state divergence rows  -tau B h_k^B
+ *   adjoint divergence rows 0
+ * with the full-grid matrices (boundary columns included) on interior rows.
+ * All inputs are device arrays of Q2 nodal values on the full grid, NULL
+ * meaning zero:
+ *   vd, f: [nt][2][(2N+1)^2] at t_k = k tau, k = 1..nt (x component first);
+ *   h:     [nt+1][2][(2N+1)^2] at t_k, k = 0..nt (only boundary entries read);
+ *   v0:    [2][(2N+1)^2] (only interior entries read).
+ * b: device, canonical layout.  With every input but vd NULL this equals
+ * pintoc_assemble_rhs except that boundary values of vd enter through the
+ * mass matrix.  Asynchronous on ``stream``. */
+int pintoc_assemble_rhs_data(pintoc_problem* p, const double* vd, const double* f, const double* h,
+                             const double* v0, double* b, void* stream);
+
 /* y = A x with A the all-at-once matrix of eq. (FinalA) (FP64).  x, y: device,
  * canonical layout, must not alias.  Asynchronous on ``stream``. */
 int pintoc_kkt_apply(pintoc_problem* p, const double* x, double* y, void* stream);
@@ -225,13 +269,19 @@ int pintoc_kkt_apply(pintoc_problem* p, const double* x, double* y, void* stream
 int pintoc_precond_apply(pintoc_problem* p, const double* r, double* z, void* stream);
 
 /* Solve A x = b with restarted flexible GMRES (section 3.4) preconditioned by
- * pintoc_precond_apply.  x: device, canonical; on entry the initial guess,
+ * pintoc_precond_apply.  A solve can run in slices of whole restart cycles
+ * (stats.cycle_budget / stats.resume): every restart recomputes the true
+ * residual from x, so a solve paused and resumed makes exactly the
+ * computation of an uninterrupted one, and a scheduler can interleave several
+ * problems on one stream at restart boundaries while their vectors stay in
+ * device memory.  x: device, canonical; on entry the initial guess,
  * on exit the solution (or the last iterate).  Stops when the true residual
  * satisfies ||b - A x||_2 <= options.tol ||b||_2.  st may be NULL.
  * Synchronises ``stream`` before returning.
  * Returns PINTOC_OK, or PINTOC_NOT_CONVERGED after options.max_outer
  * iterations or a Krylov breakdown without convergence (x then holds the
- * last iterate, st the residual reached). */
+ * last iterate, st the residual reached), or PINTOC_PAUSED (see above);
+ * PINTOC_ESTATE for a resume without a paused solve. */
 int pintoc_solve(pintoc_problem* p, const double* b, double* x, pintoc_solve_stats* st,
                  void* stream);
 

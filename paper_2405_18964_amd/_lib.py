@@ -12,7 +12,7 @@ INNER_LINEAR, INNER_GMRES = 0, 1
 PREC_FP64, PREC_FP32_INNER = 0, 1
 OUTER_FGMRES, OUTER_MINRES = 0, 1
 SMOOTHER_TILED, SMOOTHER_GLOBAL = 0, 1
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, PAUSED = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ESTATE = -1, -2, -3, -4
 
 
@@ -45,12 +45,13 @@ class SolveStats(C.Structure):
                 ("precond_model_bytes", C.c_double), ("phase_seconds", C.c_double * NPHASES),
                 ("residual_history", C.POINTER(C.c_double)), ("history_capacity", C.c_int32),
                 ("history_length", C.c_int32), ("inner_counts", C.POINTER(C.c_int32)),
-                ("inner_counts_capacity", C.c_int32)]
+                ("inner_counts_capacity", C.c_int32), ("cycle_budget", C.c_int32), ("resume", C.c_int32)]
 
     def as_dict(self):
         out = {}
         for k, _ in self._fields_:
-            if k in ("residual_history", "inner_counts", "history_capacity", "inner_counts_capacity"):
+            if k in ("residual_history", "inner_counts", "history_capacity", "inner_counts_capacity",
+                     "cycle_budget", "resume"):
                 continue
             v = getattr(self, k)
             out[k] = dict(zip(PHASES, list(v))) if k == "phase_seconds" else v
@@ -71,6 +72,7 @@ SIGNATURES = {
     "pintoc_workspace_bytes": (C.c_size_t, [C.c_void_p]),
     "pintoc_bind_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "pintoc_assemble_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pintoc_assemble_rhs_data": (C.c_int, [C.c_void_p] * 7),
     "pintoc_kkt_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pintoc_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pintoc_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
@@ -182,6 +184,27 @@ class Problem:
                                              self._stream()), "pintoc_assemble_rhs")
         return out
 
+    def assemble_rhs_data(self, vd=None, f=None, h=None, v0=None, out=None):
+        """Right-hand side for a desired state, forcing, Dirichlet data and an
+        initial velocity (float64 CUDA tensors of Q2 nodal values, None = 0):
+        vd, f [nt, 2, (2N+1)^2], h [nt + 1, 2, (2N+1)^2], v0 [2, (2N+1)^2]."""
+        t = self._torch
+        nq2 = (2 * self.N + 1) ** 2
+        ptrs = []
+        for name, a, n in (("vd", vd, self.nt * 2 * nq2), ("f", f, self.nt * 2 * nq2),
+                           ("h", h, (self.nt + 1) * 2 * nq2), ("v0", v0, 2 * nq2)):
+            if a is None:
+                ptrs.append(None)
+                continue
+            if not (isinstance(a, t.Tensor) and a.is_cuda and a.dtype == t.float64 and a.is_contiguous()
+                    and a.numel() == n):
+                raise TypeError(f"{name} must be a contiguous float64 CUDA tensor with {n} entries")
+            ptrs.append(C.c_void_p(a.data_ptr()))
+        out = self.empty() if out is None else out
+        _check(library().pintoc_assemble_rhs_data(self._h, *ptrs, self._vec(out, "out"), self._stream()),
+               "pintoc_assemble_rhs_data")
+        return out
+
     def kkt_apply(self, x, out=None):
         out = self.empty() if out is None else out
         _check(library().pintoc_kkt_apply(self._h, self._vec(x, "x"), self._vec(out, "out"), self._stream()),
@@ -194,12 +217,17 @@ class Problem:
                                               self._stream()), "pintoc_precond_apply")
         return out
 
-    def solve(self, b, x=None, history=0):
+    def solve(self, b, x=None, history=0, cycle_budget=0, resume=False):
         """Returns (x, stats dict, converged flag).  The stats carry the
         per-frequency inner GMRES counts of the solve and, with ``history``
-        > 0, up to that many per-iteration residual estimates."""
+        > 0, up to that many per-iteration residual estimates.  With
+        ``cycle_budget`` > 0 the call returns after that many FGMRES restart
+        cycles (stats "paused" true if not converged); ``resume`` continues
+        the paused solve (same b and x)."""
         x = self.empty() if x is None else x
         st = SolveStats()
+        st.cycle_budget = int(cycle_budget)
+        st.resume = 1 if resume else 0
         nf = self.nt // 2 + 1
         counts = (C.c_int32 * nf)()
         st.inner_counts = C.cast(counts, C.POINTER(C.c_int32))
@@ -213,6 +241,7 @@ class Problem:
         out = st.as_dict()
         out["inner_counts"] = [int(counts[j]) for j in range(nf)]
         out["residual_history"] = [float(hist[k]) for k in range(st.history_length)]
+        out["paused"] = rc == PAUSED
         return x, out, rc == OK
 
     def last_inner_iterations(self):

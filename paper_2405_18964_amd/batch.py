@@ -1,14 +1,16 @@
-"""Many control problems on one GPU: concurrent solves under a memory budget.
+"""Many control problems on one GPU: concurrent solves under a memory budget,
+and a served request stream with slots recycled at restart boundaries.
 
-``run(jobs, workers, budget_bytes)`` keeps up to ``workers`` problems on the
-device at once.  Each worker is a host thread with its own HIP stream; it takes
-the next job in arrival order once the job has arrived and its device memory
-(workspace, right-hand side, solution, desired state) fits the budget left,
-then creates and binds the problem, assembles the right-hand side, solves and
-releases the memory.  Kernels of different problems overlap on the device;
-every kernel and reduction of a solve depends only on its own problem, so each
-result equals that of a lone solve.  The compute runs in the HIP library
-(``pintoc_solve`` per job); this module only schedules.
+``run(jobs, workers, budget_bytes, slice_cycles)`` admits jobs in arrival
+order while their device memory (workspace, right-hand side, solution,
+desired state) fits the budget, and ``workers`` host threads, each with its
+own HIP stream, solve them: whole (``slice_cycles`` = 0) or a few FGMRES
+restart cycles per turn, round robin over the admitted jobs, whose Krylov
+state stays in device memory between turns.  Kernels of different problems
+overlap on the device; every kernel and reduction of a solve depends only on
+its own problem and a sliced solve makes the same iterates as an
+uninterrupted one, so each result equals that of a lone solve.  The compute
+runs in the HIP library (``pintoc_solve``); this module only schedules.
 
 A job is a dict with the problem data of :class:`Problem` (``N, nt, T, nu,
 beta, flow, wind``), the desired state ``vd`` (array of shape
@@ -48,14 +50,34 @@ def job_bytes(job, **options) -> int:
 
 
 def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions: bool = False,
-        checksum: bool = False, on_done=None, device="cuda", **options):
+        checksum: bool = False, on_done=None, device="cuda", slice_cycles: int = 0, **options):
     """Solve every job; returns one record per job (in job order) with the
     stats of its solve, its arrival, start and end times (seconds after the
-    start of the run), the device bytes it held, with ``keep_solutions`` its
-    solution copied to host memory (numpy) and with ``checksum`` a BLAKE2b
-    digest of the solution's bytes (to compare runs without keeping them).
-    ``on_done(k, record)`` is called (from the worker thread) as job k ends."""
+    start of the run), the device bytes it held, the number of slices it ran
+    in, with ``keep_solutions`` its solution copied to host memory (numpy) and
+    with ``checksum`` a BLAKE2b digest of the solution's bytes (to compare
+    runs without keeping them).  ``on_done(k, record)`` is called (from a
+    worker thread) as job k ends.
+
+    Scheduling.  A job is admitted in arrival order once it has arrived and
+    its device memory fits the budget left; the worker that admits it creates
+    and binds the problem and assembles the right-hand side, and the job joins
+    the ready queue.  Each of the ``workers`` host threads owns a HIP stream
+    and repeatedly takes the job at the head of the ready queue.  With
+    ``slice_cycles`` = 0 it solves the job to the end; with ``slice_cycles`` =
+    c > 0 it runs c FGMRES restart cycles (``pintoc_solve`` with a cycle
+    budget, resumed on the next turn) and, if the job is not finished, puts it
+    back at the tail of the queue: the worker's slot is recycled at a restart
+    boundary, so requests that arrive while long solves run start at once and
+    every admitted request progresses.  A paused job keeps its problem,
+    workspace and vectors (its Krylov state) in device memory between turns;
+    each turn completes before the next starts (the library synchronises the
+    stream), so a job may move between worker streams.  The iterates of a
+    sliced solve equal those of an uninterrupted one, so each result is the
+    same alone, in a batch and served."""
+    import collections
     import hashlib
+
     import numpy as np
     import torch
 
@@ -73,42 +95,79 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
     order = sorted(range(n), key=lambda k: (jobs[k].get("arrival", 0.0), k))
     out = [None] * n
     lock = threading.Condition()
-    state = {"next": 0, "free": budget_bytes, "error": None}
+    ready = collections.deque()                          # admitted jobs: [k, problem, b, x, turns, start]
+    state = {"next": 0, "free": budget_bytes, "error": None, "done": 0}
     t0 = time.perf_counter()
+
+    def admit_one():
+        """Under the lock: index of the next job if it has arrived and fits, else None."""
+        if state["next"] >= n:
+            return None
+        k = order[state["next"]]
+        if jobs[k].get("arrival", 0.0) > time.perf_counter() - t0 or need[k] > state["free"]:
+            return None
+        state["next"] += 1
+        state["free"] -= need[k]
+        return k
+
+    def next_wait():
+        if state["next"] >= n:
+            return 0.05
+        k = order[state["next"]]
+        return min(max(jobs[k].get("arrival", 0.0) - (time.perf_counter() - t0), 0.0), 0.05) or 0.05
+
+    def setup(k, stream):
+        job = jobs[k]
+        start = time.perf_counter() - t0
+        with torch.cuda.stream(stream):
+            p = Problem(job["N"], job["nt"], job.get("T", 1.0), job["nu"], job["beta"],
+                        job.get("flow", 0), job.get("wind"), device=device, **options)
+            vd = torch.as_tensor(np.ascontiguousarray(job["vd"], dtype=np.float64)).to(device)
+            b = p.assemble_rhs(vd)
+            x = p.empty()
+            stream.synchronize()
+        return [k, p, b, x, 0, start]
+
+    def finish(item, st, ok, stream):
+        k, p, b, x, turns, start = item
+        with torch.cuda.stream(stream):
+            sol = x.cpu().numpy() if (keep_solutions or checksum) else None
+        digest = hashlib.blake2b(sol.tobytes(), digest_size=16).hexdigest() if checksum else None
+        p.close()
+        end = time.perf_counter() - t0
+        out[k] = {"stats": st, "converged": ok, "arrival": jobs[k].get("arrival", 0.0), "start": start,
+                  "end": end, "bytes": need[k], "slices": turns, "digest": digest,
+                  "solution": sol if keep_solutions else None}
 
     def worker():
         stream = torch.cuda.Stream(device=device)          # default priority
         while True:
+            item, k_new = None, None
             with lock:
                 while True:
-                    if state["error"] is not None or state["next"] >= n:
+                    if state["error"] is not None or state["done"] >= n:
                         return
-                    k = order[state["next"]]
-                    wait = jobs[k].get("arrival", 0.0) - (time.perf_counter() - t0)
-                    if wait <= 0 and need[k] <= state["free"]:
-                        state["next"] += 1
-                        state["free"] -= need[k]
+                    k_new = admit_one()
+                    if k_new is not None:
                         break
-                    lock.wait(timeout=max(wait, 0.0) if wait > 0 else 0.05)
-            start = time.perf_counter() - t0
+                    if ready:
+                        item = ready.popleft()
+                        break
+                    lock.wait(timeout=next_wait())
             try:
-                job = jobs[k]
+                if k_new is not None:
+                    item = setup(k_new, stream)
+                k, p, b, x = item[0], item[1], item[2], item[3]
                 with torch.cuda.stream(stream):
-                    p = Problem(job["N"], job["nt"], job.get("T", 1.0), job["nu"], job["beta"],
-                                job.get("flow", 0), job.get("wind"), device=device, **options)
-                    vd = torch.as_tensor(np.ascontiguousarray(job["vd"], dtype=np.float64)).to(device)
-                    b = p.assemble_rhs(vd)
-                    x, st, ok = p.solve(b)
-                    stream.synchronize()
-                    sol = x.cpu().numpy() if (keep_solutions or checksum) else None
-                    digest = hashlib.blake2b(sol.tobytes(), digest_size=16).hexdigest() if checksum else None
-                    if not keep_solutions:
-                        sol = None
-                    p.close()
-                    del p, vd, b, x
-                end = time.perf_counter() - t0
-                out[k] = {"stats": st, "converged": ok, "arrival": job.get("arrival", 0.0), "start": start,
-                          "end": end, "bytes": need[k], "solution": sol, "digest": digest}
+                    _, st, ok = p.solve(b, x, cycle_budget=slice_cycles, resume=item[4] > 0)
+                item[4] += 1
+                if st["paused"]:
+                    with lock:
+                        ready.append(item)
+                        lock.notify_all()
+                    continue
+                finish(item, st, ok, stream)
+                del item, p, b, x
             except BaseException as e:                      # noqa: BLE001 - reported to the caller
                 with lock:
                     state["error"] = e
@@ -116,6 +175,7 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
                 return
             with lock:
                 state["free"] += need[k]
+                state["done"] += 1
                 lock.notify_all()
             if on_done is not None:
                 on_done(k, out[k])
@@ -126,6 +186,7 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
     for t in threads:
         t.join()
     torch.cuda.synchronize(device)
+    ready.clear()
     torch.cuda.empty_cache()
     if state["error"] is not None:
         raise state["error"]

@@ -98,6 +98,9 @@ void q2_tile_conv_table(int n, const double* t50, int half, double* out);
 void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,
                       const double* conv);
 void launch_assemble_rhs(hipStream_t s, const double* vd, double* b, int n, int nt, double tau);
+void launch_rhs_data(hipStream_t s, const double* vd, const double* f, const double* hb, const double* v0, double* b,
+                     int n, int nt, double tau, double nu, const double* conv);
+void launch_scale_canon(hipStream_t s, double* y, const double* x, int n, int nt, double sv, double sp);
 void launch_mdot(hipStream_t s, const double* V, size_t ld, int k, const double* w, size_t n, double* part,
                  double* out);
 void launch_mgs_update(hipStream_t s, double* w, const double* V, size_t ld, int k, const double* c, size_t n);

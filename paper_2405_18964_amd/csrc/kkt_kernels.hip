@@ -287,6 +287,118 @@ __global__ __launch_bounds__(256) void k_assemble_rhs(const double* __restrict__
   out[((size_t)b * nt + t) * L + g] = v;
 }
 
+// Right-hand side for general data (section 2.2: the vectors g and h that
+// collect forcing, boundary and initial values).  With the velocity at t_k
+// split into the unknown interior part and the known boundary values h_k^B,
+// the known terms of the discrete equations move to the right:
+//   adjoint momentum (b=0): tau M (v_d,k - h_k^B)
+//   adjoint divergence     : 0
+//   state momentum   (b=1): tau M f_k - (M + tau L) h_k^B + M w_{k-1},
+//                           w_0 = v_0 (interior) + h_0^B, w_{k-1} = h_{k-1}^B
+//   state divergence       : -tau B h_k^B
+// evaluated with the full-grid matrices (boundary columns included) on the
+// interior rows.  Inputs are full Q2 nodal grids (NULL = zero): vd, f
+// [nt][2][nq2] at t_1..t_nt, hb [nt+1][2][nq2] at t_0..t_nt (boundary entries
+// read), v0 [2][nq2] (interior entries read).  Level t of the output is t_{t+1}.
+__global__ __launch_bounds__(256) void k_rhs_data(const double* __restrict__ vd, const double* __restrict__ f,
+                                                  const double* __restrict__ hb, const double* __restrict__ v0,
+                                                  double* __restrict__ out, int n, int nt, double tau, double nu,
+                                                  const double* __restrict__ conv) {
+  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
+  const int L = 2 * nq2 + np2;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y, b = blockIdx.z;
+  if (g >= L) return;
+  const double h = 1.0 / n;
+  auto on_bd = [&](int jx, int jy) { return jx == 0 || jy == 0 || jx == nq - 1 || jy == nq - 1; };
+  // boundary value of the Dirichlet data at time level k (0..nt), component c
+  auto hval = [&](int k, int c, int jx, int jy) {
+    return (hb && on_bd(jx, jy)) ? hb[((size_t)k * 2 + c) * nq2 + (size_t)jy * nq + jx] : 0.0;
+  };
+  auto grid = [&](const double* a, int k, int c, int jx, int jy) {
+    return a ? a[((size_t)k * 2 + c) * nq2 + (size_t)jy * nq + jx] : 0.0;
+  };
+  double v = 0;
+  if (g < 2 * nq2) {
+    const int comp = g >= nq2, node = g - comp * nq2;
+    const int ix = node % nq, iy = node / nq;
+    if (!on_bd(ix, iy)) {
+      double mx[5], kx[5], my[5], ky[5];
+      q2_rows(ix, h, mx, kx);
+      q2_rows(iy, h, my, ky);
+      const double* cn = (conv && b == 1) ? conv + (size_t)node * 50 : nullptr;     // N (not N^T)
+      double mm = 0, kk = 0, cc = 0;
+      for (int dy = 0; dy < 5; ++dy) {
+        const int jy = iy + dy - 2;
+        if (jy < 0 || jy >= nq) continue;
+        double sm = 0, sk = 0, su = 0;
+        for (int dx = 0; dx < 5; ++dx) {
+          const int jx = ix + dx - 2;
+          if (jx < 0 || jx >= nq) continue;
+          const double hk = hval(t + 1, comp, jx, jy);
+          double fm;
+          if (b == 0) {
+            fm = grid(vd, t, comp, jx, jy) - hk;
+          } else {
+            double wp;
+            if (t == 0) wp = on_bd(jx, jy) ? hval(0, comp, jx, jy) : (v0 ? v0[(size_t)comp * nq2 + (size_t)jy * nq + jx] : 0.0);
+            else wp = hval(t, comp, jx, jy);
+            fm = tau * grid(f, t, comp, jx, jy) - hk + wp;
+          }
+          sm += mx[dx] * fm;
+          sk += kx[dx] * hk;
+          su += mx[dx] * hk;
+          if (cn) cc += cn[dy * 5 + dx] * hk;
+        }
+        mm += my[dy] * sm;
+        kk += my[dy] * sk + ky[dy] * su;
+      }
+      v = b == 0 ? tau * mm : mm - tau * (nu * kk + cc);
+    }
+  } else if (b == 1) {
+    const int k = g - 2 * nq2, kx = k % np, ky = k / np;
+    if (k != 0 && hb) {
+      // -tau (B h^B)_k, B = negative divergence: B v = -(int psi_k d/dx v_x + int psi_k d/dy v_y)
+      double mxx[5], gxx[5], mxy[5], gxy[5];
+      mixed_rows(kx, n, h, mxx, gxx);
+      mixed_rows(ky, n, h, mxy, gxy);
+      double sdiv = 0;
+      for (int dy = 0; dy < 5; ++dy) {
+        const int jy = 2 * ky + dy - 2;
+        if (jy < 0 || jy >= nq) continue;
+        for (int dx = 0; dx < 5; ++dx) {
+          const int jx = 2 * kx + dx - 2;
+          if (jx < 0 || jx >= nq) continue;
+          sdiv += mxy[dy] * gxx[dx] * hval(t + 1, 0, jx, jy) + gxy[dy] * mxx[dx] * hval(t + 1, 1, jx, jy);
+        }
+      }
+      v = tau * sdiv;                       // -tau * (-sdiv)
+    }
+  }
+  out[((size_t)b * nt + t) * L + g] = v;
+}
+
+// y = diag(sv on velocity entries, sp on pressure entries) x over both blocks
+// and every time level; y may equal x.
+__global__ __launch_bounds__(256) void k_scale_canon(double* y, const double* x, int n, int nt, double sv, double sp) {
+  const int nq = 2 * n + 1, nq2 = nq * nq, L = 2 * nq2 + (n + 1) * (n + 1);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= L) return;
+  const size_t i = (size_t)blockIdx.y * L + g;
+  y[i] = x[i] * (g < 2 * nq2 ? sv : sp);
+}
+
+void launch_rhs_data(hipStream_t s, const double* vd, const double* f, const double* hb, const double* v0, double* b,
+                     int n, int nt, double tau, double nu, const double* conv) {
+  const int L = 2 * (2 * n + 1) * (2 * n + 1) + (n + 1) * (n + 1);
+  hipLaunchKernelGGL(k_rhs_data, dim3((L + 255) / 256, nt, 2), dim3(256), 0, s, vd, f, hb, v0, b, n, nt, tau, nu, conv);
+}
+
+void launch_scale_canon(hipStream_t s, double* y, const double* x, int n, int nt, double sv, double sp) {
+  const int L = 2 * (2 * n + 1) * (2 * n + 1) + (n + 1) * (n + 1);
+  hipLaunchKernelGGL(k_scale_canon, dim3((L + 255) / 256, 2 * nt), dim3(256), 0, s, y, x, n, nt, sv, sp);
+}
+
 void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,
                       const double* conv) {
   const int nq = 2 * n + 1, L = 2 * nq * nq + (n + 1) * (n + 1);

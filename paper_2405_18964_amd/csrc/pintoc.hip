@@ -180,8 +180,23 @@ struct pintoc_problem {
   double *Vk = nullptr, *Zk = nullptr, *rvec = nullptr, *xtmp = nullptr;
   double *dd = nullptr, *dd2 = nullptr, *part = nullptr;
   bool bound = false;
+  double side = 1.0;                    // side of the square domain (section 5: [-1, 1]^2 has 2)
+  double* dscale = nullptr;             // one canonical vector for the domain scaling (side != 1 only)
   // statistics
   int precond_apps = 0;
+  // a solve paused at a restart boundary (pintoc_solve_stats.cycle_budget):
+  // its vectors stay in device memory (x and b are the caller's, the rest is
+  // rebuilt from them), the scalars that carry over are kept here
+  struct Paused {
+    bool on = false;
+    const double* b = nullptr;
+    double* x = nullptr;
+    int its = 0;
+    double bnorm = 0, res0 = 0;
+    std::vector<double> hist;
+    std::chrono::steady_clock::duration elapsed{};
+    double phase[PINTOC_NPHASES] = {};
+  } paused;
 };
 
 // -------------------------------------------------------- small host helpers
@@ -386,6 +401,7 @@ static void carve(pintoc_problem* p, char* base) {
   p->Zk = cv.take<double>(vb * m);
   p->rvec = cv.take<double>(vb);
   p->xtmp = cv.take<double>(vb);
+  p->dscale = p->side != 1.0 ? cv.take<double>(vb) : nullptr;
   p->dd = cv.take<double>(sizeof(double) * 64);
   p->dd2 = cv.take<double>(sizeof(double) * 64);
   p->part = cv.take<double>(sizeof(double) * 8 * 1024);
@@ -581,6 +597,20 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   p->d = *d;
   p->d.wind = nullptr;
   p->o = opt;
+  // A square of side l is the unit square's problem with viscosity nu / l^2
+  // and wind w / l: M, K, B, N(w) scale as l^2, 1, l and l, so the physical
+  // matrix is D_r A' D_c with A' the unit-square matrix of (nu / l^2, w / l),
+  // D_r = l^2 on momentum rows and l on divergence rows, D_c = 1/l on
+  // pressure columns.  Everything below is set up for A'; the entry points
+  // apply D_r, D_c (kkt_scaled, precond_scaled).
+  p->side = side;
+  p->d.nu = d->nu / (side * side);
+  std::vector<double> wsc;
+  if (d->flow == PINTOC_OSEEN) {
+    const size_t nw = 2 * (size_t)(2 * d->N + 1) * (2 * d->N + 1);
+    wsc.assign(d->wind, d->wind + nw);
+    for (double& v : wsc) v /= side;
+  }
   const int N = d->N, nt = d->nt;
   p->tau = d->T / nt;
   p->nf = nt / 2 + 1;
@@ -598,14 +628,14 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   }
   // per-frequency constants (section 3.1-3.2): d_j = 1 - exp(-2 pi i j/nt),
   // c2 = (1/beta + d_c^2/tau^2)^{-1/2},  c1 = d_r / sqrt(tau^2/beta + d_c^2)
-  const double tau = p->tau, beta = d->beta, nu = d->nu;
+  const double tau = p->tau, beta = d->beta, nu = p->d.nu;
   const bool oseen = d->flow == PINTOC_OSEEN;
   int nl = 0;
   for (int n = N; n >= 2; n >>= 1) ++nl;
   if (oseen) {
     // wind on every level by injection of the finest nodal values
     const int nq = 2 * N + 1;
-    std::vector<double> wx(d->wind, d->wind + (size_t)nq * nq), wy(d->wind + (size_t)nq * nq, d->wind + 2 * (size_t)nq * nq);
+    std::vector<double> wx(wsc.begin(), wsc.begin() + (size_t)nq * nq), wy(wsc.begin() + (size_t)nq * nq, wsc.end());
     p->conv2_h.resize(nl);
     for (int l = 0; l < nl; ++l) {
       const int n = N >> l, nql = 2 * n + 1, st = 1 << l;
@@ -681,7 +711,7 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     const int nq = 2 * N + 1;
     double wmax = 0.0;
     for (size_t i = 0; i < (size_t)nq * nq; ++i)
-      wmax = std::max(wmax, std::hypot(d->wind[i], d->wind[(size_t)nq * nq + i]));
+      wmax = std::max(wmax, std::hypot(wsc[i], wsc[(size_t)nq * nq + i]));
     std::vector<double> visc;
     for (int l = 0; l < nl; ++l) visc.push_back(tau * (l == 0 ? nu : std::max(nu, wmax / (4.0 * (N >> l)))));
     p->mgQ.visc = visc;
@@ -1387,8 +1417,15 @@ static int precond_apply_t(pintoc_problem* p, const double* r, double* z, hipStr
 }
 
 static int precond(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
+  // on a square of side l: P^{-1} = D_c^{-1} P'^{-1} D_r^{-1} (see pintoc_problem_create)
+  const double l = p->side;
+  if (l != 1.0) {
+    launch_scale_canon(s, p->dscale, r, p->d.N, p->d.nt, 1.0 / (l * l), 1.0 / l);
+    r = p->dscale;
+  }
   int rc = p->o.precision == PINTOC_PREC_FP64 ? precond_apply_t<double>(p, r, z, s) : precond_apply_t<float>(p, r, z, s);
   if (rc) return rc;
+  if (l != 1.0) launch_scale_canon(s, z, z, p->d.N, p->d.nt, 1.0, l);
   p->precond_apps++;
   HIPCHK(hipGetLastError());
   return PINTOC_OK;
@@ -1406,13 +1443,35 @@ extern "C" int pintoc_assemble_rhs(pintoc_problem* p, const double* vd, double* 
   if (rc) return rc;
   if (!vd || !b) return fail(PINTOC_EINVAL, "NULL vector");
   launch_assemble_rhs((hipStream_t)stream, vd, b, p->d.N, p->d.nt, p->tau);
+  if (p->side != 1.0) launch_scale_canon((hipStream_t)stream, b, b, p->d.N, p->d.nt, p->side * p->side, p->side);
+  HIPCHK(hipGetLastError());
+  return PINTOC_OK;
+}
+
+extern "C" int pintoc_assemble_rhs_data(pintoc_problem* p, const double* vd, const double* f, const double* h,
+                                        const double* v0, double* b, void* stream) {
+  int rc = check_ready(p);
+  if (rc) return rc;
+  if (!b) return fail(PINTOC_EINVAL, "NULL right-hand side");
+  hipStream_t s = (hipStream_t)stream;
+  // the unit-square equivalent's right-hand side, then D_r (see pintoc_problem_create)
+  launch_rhs_data(s, vd, f, h, v0, b, p->d.N, p->d.nt, p->tau, p->d.nu,
+                  p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr);
+  if (p->side != 1.0) launch_scale_canon(s, b, b, p->d.N, p->d.nt, p->side * p->side, p->side);
   HIPCHK(hipGetLastError());
   return PINTOC_OK;
 }
 
 static void kkt(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
+  // on a square of side l: A = D_r A' D_c (see pintoc_problem_create)
+  const double l = p->side;
+  if (l != 1.0) {
+    launch_scale_canon(s, p->dscale, x, p->d.N, p->d.nt, 1.0, 1.0 / l);
+    x = p->dscale;
+  }
   launch_kkt_apply(s, x, y, p->d.N, p->d.nt, p->tau, p->d.beta, p->d.nu,
                    p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr);
+  if (l != 1.0) launch_scale_canon(s, y, y, p->d.N, p->d.nt, l * l, l);
 }
 
 // the all-at-once product inside a solve: timed as its phase, counted in the byte model
@@ -1555,25 +1614,47 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
   const auto t0 = std::chrono::steady_clock::now();
   const size_t n = (size_t)p->n_all;
   const int m = p->o.restart;
-  p->precond_apps = 0;
-  p->inner_its_sum = 0;
-  p->inner_blocks = 0;
-  p->inner_its_max = 0;
-  p->bytes_acc = 0.0;
-  p->its_acc.assign(p->nf, 0);
+  const int budget = st ? st->cycle_budget : 0;
+  const bool resume = st && st->resume;
+  auto& pz = p->paused;
+  std::chrono::steady_clock::duration prev_elapsed{};
+  double prev_phase[PINTOC_NPHASES] = {};
+  if (resume) {
+    if (!pz.on) return fail(PINTOC_ESTATE, "no paused solve to resume");
+    prev_elapsed = pz.elapsed;
+    std::copy(pz.phase, pz.phase + PINTOC_NPHASES, prev_phase);
+    if (pz.b != b || pz.x != x) return fail(PINTOC_EINVAL, "a resumed solve must pass the paused call's b and x");
+    if (p->o.outer != PINTOC_OUTER_FGMRES) return fail(PINTOC_EINVAL, "only FGMRES solves can be paused");
+  } else {
+    if (budget < 0 || (budget > 0 && p->o.outer != PINTOC_OUTER_FGMRES))
+      return fail(PINTOC_EINVAL, "cycle_budget needs FGMRES and must be >= 0");
+    pz = pintoc_problem::Paused{};
+    p->precond_apps = 0;
+    p->inner_its_sum = 0;
+    p->inner_blocks = 0;
+    p->inner_its_max = 0;
+    p->bytes_acc = 0.0;
+    p->its_acc.assign(p->nf, 0);
+  }
   p->pt.used = 0;
   p->pt.on = true;
   struct TimerOff {
     pintoc_problem* q;
     ~TimerOff() { q->pt.on = false; }
   } timer_off{p};
-  std::vector<double> hist;
+  std::vector<double> hist = resume ? pz.hist : std::vector<double>();
   double hb[64], hb2[64];
-  if ((rc = dots(p, s, b, 1, b, p->dd, hb))) return rc;
-  const double bnorm = std::sqrt(hb[0]);
-  int its = 0;
+  double bnorm;
+  if (resume) {
+    bnorm = pz.bnorm;
+  } else {
+    if ((rc = dots(p, s, b, 1, b, p->dd, hb))) return rc;
+    bnorm = std::sqrt(hb[0]);
+  }
+  int its = resume ? pz.its : 0;
   double res = 0;
-  bool conv = false;
+  bool conv = false, paused = false;
+  pz.on = false;
   if (bnorm == 0.0) {
     launch_fill_zero(s, x, n * sizeof(double));
     conv = true;
@@ -1585,13 +1666,26 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
     launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
     if ((rc = dots(p, s, p->rvec, 1, p->rvec, p->dd, hb))) return rc;
     res = std::sqrt(hb[0]);
-    const double res0 = res;
+    const double res0 = resume ? pz.res0 : res;
     bool stalled = false;
+    int cycles = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     while (true) {
       if (!std::isfinite(res)) break;                  // NaN or overflow: give up
       if (res <= p->o.tol * bnorm) { conv = true; break; }
       if (its >= p->o.max_outer) break;
+      if (budget > 0 && cycles >= budget) {            // pause at a restart boundary
+        paused = true;
+        pz.on = true;
+        pz.b = b;
+        pz.x = x;
+        pz.its = its;
+        pz.bnorm = bnorm;
+        pz.res0 = res0;
+        pz.hist = hist;
+        break;
+      }
+      ++cycles;
       // V_0 = r / ||r||
       launch_axpby(s, p->Vk, p->rvec, 1.0 / res, 0.0, n);
       std::fill(g.begin(), g.end(), 0.0);
@@ -1677,6 +1771,12 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
     if (cnt_out && ccap > 0)
       for (int j = 0; j < std::min(ccap, p->nf); ++j) cnt_out[j] = (int32_t)p->its_acc[j];
     phase_sum(p, st->phase_seconds);
+    const auto el = std::chrono::steady_clock::now() - t0 + prev_elapsed;
+    for (int i = 0; i < PINTOC_NPHASES; ++i) st->phase_seconds[i] += prev_phase[i];
+    if (paused) {
+      pz.elapsed = el;
+      for (int i = 0; i < PINTOC_NPHASES; ++i) pz.phase[i] = st->phase_seconds[i];
+    }
     st->model_bytes = p->bytes_acc;
     st->precond_model_bytes = p->model_fft + p->model_block;
     st->outer_iterations = its;
@@ -1685,8 +1785,11 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
     st->precond_applications = p->precond_apps;
     st->inner_iterations_mean = p->inner_blocks ? (double)p->inner_its_sum / p->inner_blocks : 0.0;
     st->inner_iterations_max = p->inner_its_max;
-    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st->seconds = std::chrono::duration<double>(el).count();
+    st->cycle_budget = budget;
+    st->resume = resume ? 1 : 0;
   }
+  if (paused) return PINTOC_PAUSED;
   return conv ? PINTOC_OK : PINTOC_NOT_CONVERGED;
 }
 
