@@ -228,6 +228,25 @@ size_t pintoc_workspace_bytes(const pintoc_problem* p);
  * misaligned pointer, PINTOC_EHIP if an upload fails. */
 int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): bind the
+ * problem to a device array of the library itself instead of caller memory,
+ * as pintoc_bind_workspace would bind a caller workspace (carve, clear, upload
+ * the tables on ``stream``).  Allocates nothing: the array is a static device
+ * array of 128 MiB that each device the library runs on holds until the
+ * process ends; it is taken on the current device, which must be the
+ * stream's.  After the call every entry point of the problem runs on it.
+ * At most one problem per device is bound to the array at a time: binding
+ * another problem takes it over, and the earlier one then fails with
+ * PINTOC_ESTATE until it is bound again (its results are lost).  Calls on two
+ * handles that overlap in time on one device race on the array.
+ * pintoc_bind_workspace or pintoc_problem_destroy release the array.
+ * Errors: PINTOC_ENOMEM if pintoc_workspace_bytes(p) exceeds 128 MiB (for
+ * example a Stokes problem with N = 16, nt = 16 in GMRES mode needs 53 MiB,
+ * N = 32, nt = 32 needs 393 MiB), PINTOC_EINVAL for NULL, PINTOC_EHIP if the
+ * array's address or an upload fails. */
+int pintoc_bind_scratch(pintoc_problem* p, void* stream);
+
 /* Right-hand side for v_0 = f = h = 0 (section 2.2): b = tau M v_d(t_k) on the
  * adjoint momentum rows (b = 0 velocity entries), zero elsewhere.
  * vd: device, [nt][2][(2N+1)^2] Q2 nodal desired state at t_k = k tau,

@@ -71,6 +71,7 @@ SIGNATURES = {
     "pintoc_problem_create": (C.c_int, [C.POINTER(Desc), C.POINTER(Options), C.POINTER(C.c_void_p)]),
     "pintoc_workspace_bytes": (C.c_size_t, [C.c_void_p]),
     "pintoc_bind_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pintoc_bind_scratch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pintoc_assemble_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pintoc_assemble_rhs_data": (C.c_int, [C.c_void_p] * 7),
     "pintoc_kkt_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -182,6 +183,7 @@ struct pintoc_problem {
   bool bound = false;
   double side = 1.0;                    // side of the square domain (section 5: [-1, 1]^2 has 2)
   double* dscale = nullptr;             // one canonical vector for the domain scaling (side != 1 only)
+  int scratch_dev = -1;                 // device whose static scratch is bound (pintoc_bind_scratch), or -1
   // statistics
   int precond_apps = 0;
   // a solve paused at a restart boundary (pintoc_solve_stats.cycle_budget):
@@ -754,7 +756,33 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
 
 extern "C" size_t pintoc_workspace_bytes(const pintoc_problem* p) { return p ? p->need : 0; }
 
-extern "C" void pintoc_problem_destroy(pintoc_problem* p) { delete p; }
+// ------------------------------------------------------------ static scratch
+// Device memory of the library itself, for callers that cannot allocate
+// (pintoc_bind_scratch).  Each device the library runs on holds one copy of
+// the array until the process ends.  In host code the array's name is no
+// device address: its address on the current device comes from
+// hipGetSymbolAddress, taken once per device and kept in g_scratch_ptr.  At
+// most one problem per device is bound to it (g_scratch_owner); binding
+// another problem takes the array over and unbinds the earlier one.
+static constexpr size_t kScratchBytes = (size_t)128 << 20;
+static constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices] = {};
+static pintoc_problem* g_scratch_owner[kScratchDevices] = {};
+
+// gives up p's hold on its device's scratch array (no-op if it has none)
+static void scratch_release(pintoc_problem* p) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (p->scratch_dev >= 0 && g_scratch_owner[p->scratch_dev] == p) g_scratch_owner[p->scratch_dev] = nullptr;
+  p->scratch_dev = -1;
+}
+
+extern "C" void pintoc_problem_destroy(pintoc_problem* p) {
+  if (!p) return;
+  scratch_release(p);
+  delete p;
+}
 
 static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s);
 
@@ -762,7 +790,41 @@ extern "C" int pintoc_bind_workspace(pintoc_problem* p, void* dev, size_t bytes,
   if (!p || !dev) return fail(PINTOC_EINVAL, "NULL handle or workspace");
   if (((uintptr_t)dev) & 255) return fail(PINTOC_EINVAL, "workspace must be 256-byte aligned");
   if (bytes < p->need) return fail(PINTOC_ENOMEM, "workspace too small: need " + std::to_string(p->need) + " bytes");
+  scratch_release(p);
   return bind_impl(p, dev, bytes, (hipStream_t)stream);
+}
+
+extern "C" int pintoc_bind_scratch(pintoc_problem* p, void* stream) {
+  if (!p) return fail(PINTOC_EINVAL, "NULL handle");
+  if (p->need > kScratchBytes)
+    return fail(PINTOC_ENOMEM, "problem needs " + std::to_string(p->need) + " bytes of workspace, more than the " +
+                                   std::to_string(kScratchBytes) + " bytes of the static scratch");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(PINTOC_EINVAL, "device index out of range");
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* a = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !a)
+        return fail(PINTOC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      g_scratch_ptr[dev] = a;
+    }
+    ptr = g_scratch_ptr[dev];
+    pintoc_problem* prev = g_scratch_owner[dev];
+    if (prev && prev != p) {              // the earlier problem loses its device memory
+      prev->bound = false;
+      prev->ws = nullptr;
+      prev->scratch_dev = -1;
+    }
+    if (p->scratch_dev >= 0 && p->scratch_dev != dev && g_scratch_owner[p->scratch_dev] == p)
+      g_scratch_owner[p->scratch_dev] = nullptr;
+    g_scratch_owner[dev] = p;
+    p->scratch_dev = dev;
+  }
+  return bind_impl(p, ptr, kScratchBytes, (hipStream_t)stream);
 }
 
 // carve the workspace, clear it and upload the tables on stream s
@@ -1434,7 +1496,7 @@ static int precond(pintoc_problem* p, const double* r, double* z, hipStream_t s)
 // ------------------------------------------------------------ public entries
 static int check_ready(pintoc_problem* p) {
   if (!p) return fail(PINTOC_EINVAL, "NULL handle");
-  if (!p->bound) return fail(PINTOC_ESTATE, "no workspace bound");
+  if (!p->bound) return fail(PINTOC_ESTATE, "no workspace bound (or its scratch binding was taken over)");
   return PINTOC_OK;
 }
 

@@ -151,3 +151,17 @@ def test_struct_layout_matches_header(tmp_path):
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
+
+def test_bind_scratch_rejects_before_gpu_work():
+    """pintoc_bind_scratch refuses a NULL handle and a problem whose workspace
+    exceeds the static array before touching the device."""
+    from paper_2405_18964_amd._lib import ENOMEM, EINVAL, Desc, default_options, library
+    lib = library()
+    assert lib.pintoc_bind_scratch(None, None) == EINVAL
+    d = Desc(32, 32, 1.0, 1.0, 1e-2, 0, None, 0.0, 0.0, 0.0, 0.0)
+    h = ctypes.c_void_p()
+    assert lib.pintoc_problem_create(ctypes.byref(d), ctypes.byref(default_options(inner=1)), ctypes.byref(h)) == 0
+    assert lib.pintoc_workspace_bytes(h) > (128 << 20)
+    assert lib.pintoc_bind_scratch(h, None) == ENOMEM
+    assert b"static scratch" in lib.pintoc_last_error()
+    lib.pintoc_problem_destroy(h)
