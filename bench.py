@@ -51,7 +51,9 @@ def sweep_kernel(fp64: bool, oseen: bool) -> str:
 # the same process.  Valid only for the kernel source they were taken on:
 # reported as null once that file changes (or before they are taken).
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2405_18964_amd", "csrc", "q2_tiles.hip")
-SWEEP_PMC = None
+SWEEP_PMC = {"kernel": "k_q2_sweep<double,false,false,true>",
+             "source_sha256": "2e972e25d279af992d70cb6a44fbf622b8d1c0048c0d6ad1b8b2b9f983a0b544",
+             "fetch_kib": 468560.3, "fetch_scale": 2.0, "write_kib": 422822.4, "write_scale": 1.0}
 
 
 def sweep_traffic_bytes(kernel=None):
