@@ -75,7 +75,8 @@ def parse():
                     help="workload: 1, 2 (single Stokes problem), 3 (single Oseen problem), "
                          "4 (batched 64-problem mix) or 5 (served request stream)")
     ap.add_argument("--batch-count", type=int, default=64, help="problems of the batched mix (--config 4)")
-    ap.add_argument("--workers", type=int, default=4, help="concurrent problems on the device (--config 4)")
+    ap.add_argument("--workers", type=int, default=4, help="concurrent problems on the device (--config 4, 5)")
+    ap.add_argument("--fused-workers", type=int, default=2, help="concurrent fused groups (--config 4)")
     ap.add_argument("--requests", type=int, default=256, help="requests of the served stream (--config 5)")
     ap.add_argument("--rho", type=str, default="0.8",
                     help="comma-separated arrival rates / capacity, one open-loop pass each (--config 5)")
@@ -419,12 +420,15 @@ def main():
 
 
 def bench_batch(args):
-    """Batched form: the 64-problem mix through the concurrent runner."""
+    """Batched form: the 64-problem mix, fused (groups of the same grid and
+    flow in one handle, group size and smoother per class from the
+    autotuner), with --compare also the concurrent form (one problem per
+    stream) and one problem at a time (FP32-inner and the plain FP64 form)."""
     import torch
 
     import paper_2405_18964_amd as P
     import workloads as W
-    from paper_2405_18964_amd.batch import job_bytes, run
+    from paper_2405_18964_amd.batch import autotune, job_bytes, run, run_fused
 
     mix = W.batch_mix(args.batch_count)
     jobs = [{"N": w.N, "nt": w.nt, "T": w.T, "nu": w.nu, "beta": w.beta, "flow": w.flow,
@@ -435,9 +439,16 @@ def bench_batch(args):
     small = sorted(range(len(jobs)), key=lambda k: job_bytes(jobs[k], **opts))[:args.workers]
     for i in range(args.warmup):                           # module loading, allocator warm-up
         run([jobs[k] for k in small], workers=args.workers, **opts)
+    t0 = time.perf_counter()
+    plan = autotune(jobs, **opts)
+    t_tune = time.perf_counter() - t0
+    for key, v in sorted(plan.items()):
+        print(f"[bench] autotune N={key[0]} {'Oseen' if key[1] else 'Stokes'}: group size {v['size']}, "
+              f"smoother {'global' if v['smoother'] else 'tiled'}", file=sys.stderr, flush=True)
+
     def progress(tag):
         def cb(k, r):
-            print(f"[bench] {tag}: job {k} ({mix[k].name}, nt={mix[k].nt}) {r['end'] - r['start']:.2f} s"
+            print(f"[bench] {tag}: job {k} ({mix[k].name}, nt={mix[k].nt}) done at {r['end']:.2f} s"
                   f"{'' if r['converged'] else ' NOT CONVERGED'}", file=sys.stderr, flush=True)
         return cb
 
@@ -445,15 +456,15 @@ def bench_batch(args):
     for i in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = run(jobs, workers=args.workers, checksum=True, on_done=progress(f"step {i}"), **opts)
+        out = run_fused(jobs, plan, workers=args.fused_workers, checksum=True, on_done=progress(f"fused {i}"), **opts)
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t0)
         outs.append(out)
-        print(f"[bench] step {i}: {walls[-1]:.2f} s, converged {sum(r['converged'] for r in out)}/{len(out)}",
+        print(f"[bench] fused step {i}: {walls[-1]:.2f} s, converged {sum(r['converged'] for r in out)}/{len(out)}",
               file=sys.stderr, flush=True)
     out = outs[-1]
     wall = sum(walls)
-    lat = sorted(r["end"] - r["start"] for r in out)
+    lat = [r["end"] - r["start"] for r in out]
     res = {
         "metric": "KKT solves/sec to 1e-8 residual (batched mix, aggregate); p50/p99 per-solve latency",
         "value": len(jobs) * args.steps / wall,
@@ -468,24 +479,35 @@ def bench_batch(args):
         "dtype": "f32-inner/f64-outer",
         "data": "synthetic",
         "config": {"workload": f"{len(jobs)} independent Stokes/Oseen control problems (N in {{32,64,128}}, "
-                               "nt in {32,...,256}, log-uniform beta in [1e-6,1e-2], nu in {1,1/50,1/100}), "
-                               f"{args.workers} concurrent on one GPU",
-                   "solver": "FGMRES(10) + block-circulant preconditioner with inner GMRES per frequency"},
+                               "nt in {32,...,256}, log-uniform beta in [1e-6,1e-2], nu in {1,1/50,1/100})",
+                   "solver": "FGMRES(10) + block-circulant preconditioner with inner GMRES per frequency; "
+                             "fused groups of the same grid and flow (one batch of every per-frequency kernel, "
+                             f"lockstep FGMRES), {args.fused_workers} groups concurrent"},
         "converged": int(sum(r["converged"] for r in out)),
-        "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]},
+        "latency_s": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99)},
+        "autotune": {"seconds": t_tune,
+                     "plan": {f"N{k[0]}_{'oseen' if k[1] else 'stokes'}": {"size": v["size"], "smoother":
+                              "global" if v["smoother"] else "tiled"} for k, v in sorted(plan.items())},
+                     "trials": {f"N{k[0]}_{'oseen' if k[1] else 'stokes'}": v["trials"] for k, v in sorted(plan.items())}},
+        "groups": len({r["group"] for r in out}),
     }
     if args.compare:
-        for name, prec in (("sequential_fp32_inner", P.PREC_FP32_INNER), ("sequential_fp64", P.PREC_FP64)):
+        for name, prec, workers in (("concurrent_fp32_inner", P.PREC_FP32_INNER, args.workers),
+                                    ("sequential_fp32_inner", P.PREC_FP32_INNER, 1),
+                                    ("sequential_fp64", P.PREC_FP64, 1)):
             o = dict(opts, precision=prec)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            seq = run(jobs, workers=1, checksum=True, on_done=progress(name), **o)
+            seq = run(jobs, workers=workers, checksum=True, on_done=progress(name), **o)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
-            res[name] = {"solves_per_s": len(jobs) / t, "seconds": t,
+            res[name] = {"solves_per_s": len(jobs) / t, "seconds": t, "workers": workers,
                          "converged": int(sum(r["converged"] for r in seq))}
-            if prec == P.PREC_FP32_INNER:
-                res["identical_to_sequential"] = int(sum(a["digest"] == b["digest"] for a, b in zip(seq, out)))
+            if name == "concurrent_fp32_inner":
+                tiled = [k for k in range(len(jobs)) if plan[(jobs[k]["N"], jobs[k]["flow"])]["smoother"] == 0]
+                res["fused_identical_to_concurrent"] = {
+                    "tiled_classes": len(tiled),
+                    "identical": int(sum(out[k]["digest"] == seq[k]["digest"] for k in tiled))}
             print(f"[bench] {name}: {t:.2f} s", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 

@@ -322,6 +322,49 @@ int pintoc_solve(pintoc_problem* p, const double* b, double* x, pintoc_solve_sta
 int pintoc_solve_batch(pintoc_problem* const* p, const double* const* b, double* const* x,
                        pintoc_solve_stats* st, void* const* streams, int32_t n);
 
+/* ---------------------------------------------------------------- groups
+ * Fused batched form: the all-at-once systems of n problems solved by one
+ * handle (the per-problem solve of section 5 for a set of problems at once).
+ * The members share N, the flow, the domain (the unit square), the wind
+ * (Oseen: the same nodal values) and the options; nt, T, nu and beta may
+ * differ.  The kept frequencies of all members form one batch: every
+ * per-frequency kernel of the block preconditioner (multigrid, Chebyshev,
+ * Uzawa, inner GMRES; sections 3.2-4) runs once for all members, each
+ * frequency with its own member's constants.  Each member runs its own FGMRES
+ * (section 3.4) in lockstep with the others; members that have converged sit
+ * out (their frequencies are masked).  Every kernel and reduction acts on one
+ * member's data in a fixed order, so each member's result equals that of a
+ * lone pintoc_solve bit for bit.
+ *
+ * pintoc_group_create: d is a host array of n descriptors (1 <= n <= 4096);
+ * errors as pintoc_problem_create, plus PINTOC_EINVAL for members that differ
+ * in N, flow, domain or wind, a domain other than the unit square, or MINRES.
+ * The handle takes pintoc_workspace_bytes / pintoc_bind_workspace /
+ * pintoc_problem_destroy like a lone problem; the lone vector entry points
+ * (pintoc_assemble_rhs, _kkt_apply, _precond_apply, _solve) refuse it with
+ * PINTOC_EINVAL.  Vectors of member k have pintoc_group_vector_length(p, k)
+ * entries in the canonical layout of that member. */
+int pintoc_group_create(const pintoc_problem_desc* d, int32_t n, const pintoc_options* o,
+                        pintoc_problem** out);
+int32_t pintoc_group_size(const pintoc_problem* p);               /* n, or 0 for NULL    */
+int64_t pintoc_group_vector_length(const pintoc_problem* p, int32_t k); /* 0 if k is out of range */
+/* b = right-hand side of member k for its desired state (as pintoc_assemble_rhs). */
+int pintoc_group_assemble_rhs(pintoc_problem* p, int32_t k, const double* vd, double* b, void* stream);
+/* y = A_k x for member k (as pintoc_kkt_apply). */
+int pintoc_group_kkt_apply(pintoc_problem* p, int32_t k, const double* x, double* y, void* stream);
+/* z[k] = P_k^{-1} r[k] for every member k with r[k] != NULL, in one fused
+ * application (r, z: host arrays of n device pointers; z[k] must not alias
+ * r[k]).  Members with r[k] == NULL are skipped (z[k] untouched). */
+int pintoc_group_precond_apply(pintoc_problem* p, const double* const* r, double* const* z, void* stream);
+/* Solve every member: x[k] (in: initial guess, out: solution) for b[k];
+ * st: host array of n stats records or NULL (history and inner counts per
+ * member as for pintoc_solve; model_bytes and the phase times are the
+ * group's; cycle_budget / resume are not supported and ignored).  Returns
+ * PINTOC_OK when every member converged, else PINTOC_NOT_CONVERGED (see st).
+ * Synchronises ``stream`` before returning. */
+int pintoc_group_solve(pintoc_problem* p, const double* const* b, double* const* x, pintoc_solve_stats* st,
+                       void* stream);
+
 /* Release the handle (does not free the bound workspace, which the caller owns). */
 void pintoc_problem_destroy(pintoc_problem* p);
 

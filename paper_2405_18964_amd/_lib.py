@@ -80,6 +80,14 @@ SIGNATURES = {
     "pintoc_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                       C.POINTER(SolveStats), C.POINTER(C.c_void_p), C.c_int32]),
     "pintoc_problem_destroy": (None, [C.c_void_p]),
+    "pintoc_group_create": (C.c_int, [C.POINTER(Desc), C.c_int32, C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "pintoc_group_size": (C.c_int32, [C.c_void_p]),
+    "pintoc_group_vector_length": (C.c_int64, [C.c_void_p, C.c_int32]),
+    "pintoc_group_assemble_rhs": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pintoc_group_kkt_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pintoc_group_precond_apply": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+    "pintoc_group_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                      C.POINTER(SolveStats), C.c_void_p]),
     "pintoc_last_error": (C.c_char_p, []),
     "pintoc_vector_length": (C.c_int64, [C.c_void_p]),
     "pintoc_last_inner_iterations": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
@@ -275,6 +283,141 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+class Group:
+    """Several problems of the same N and flow (and wind, for Oseen) as one
+    handle (``pintoc_group_create``): their kept frequencies run as one batch
+    in every per-frequency kernel, their FGMRES iterations in lockstep.
+    ``members`` is a list of dicts with N, nt, T, nu, beta, flow and wind (the
+    keys of :class:`Problem`).  Vectors of member k are float64 CUDA tensors
+    of ``n_all[k]`` entries."""
+
+    def __init__(self, members, device="cuda", **options):
+        import numpy as np
+        import torch
+        lib = library()
+        self._torch = torch
+        self.members = [dict(m) for m in members]
+        n = len(members)
+        descs = (Desc * n)()
+        self._winds = []
+        for k, m in enumerate(members):
+            wptr = None
+            if m.get("wind") is not None:
+                w = np.ascontiguousarray(np.asarray(m["wind"], dtype=np.float64).reshape(-1))
+                self._winds.append(w)
+                wptr = w.ctypes.data_as(C.POINTER(C.c_double))
+            descs[k] = Desc(m["N"], m["nt"], m.get("T", 1.0), m["nu"], m["beta"], m.get("flow", STOKES), wptr,
+                            0.0, 0.0, 0.0, 0.0)
+        self.options = default_options(**options)
+        h = C.c_void_p()
+        _check(lib.pintoc_group_create(descs, n, C.byref(self.options), C.byref(h)), "pintoc_group_create")
+        self._h = h
+        self.size = int(lib.pintoc_group_size(h))
+        self.n_all = [int(lib.pintoc_group_vector_length(h, k)) for k in range(n)]
+        self.workspace_bytes = int(lib.pintoc_workspace_bytes(h))
+        self.device = torch.device(device)
+        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        _check(lib.pintoc_bind_workspace(h, C.c_void_p(self._ws.data_ptr()), self.workspace_bytes,
+                                         self._stream()), "pintoc_bind_workspace")
+
+    def _stream(self):
+        return C.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _vec(self, v, k, name):
+        t = self._torch
+        if not (isinstance(v, t.Tensor) and v.is_cuda and v.dtype == t.float64 and v.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+        if v.numel() != self.n_all[k]:
+            raise ValueError(f"{name} of member {k} has {v.numel()} entries, expected {self.n_all[k]}")
+        return v.data_ptr()
+
+    def empty(self, k):
+        return self._torch.zeros(self.n_all[k], dtype=self._torch.float64, device=self.device)
+
+    def assemble_rhs(self, k, vd, out=None):
+        out = self.empty(k) if out is None else out
+        _check(library().pintoc_group_assemble_rhs(self._h, k, C.c_void_p(vd.data_ptr()),
+                                                   C.c_void_p(self._vec(out, k, "out")), self._stream()),
+               "pintoc_group_assemble_rhs")
+        return out
+
+    def kkt_apply(self, k, x, out=None):
+        out = self.empty(k) if out is None else out
+        _check(library().pintoc_group_kkt_apply(self._h, k, C.c_void_p(self._vec(x, k, "x")),
+                                                C.c_void_p(self._vec(out, k, "out")), self._stream()),
+               "pintoc_group_kkt_apply")
+        return out
+
+    def precond_apply(self, rs, outs=None):
+        """z[k] = P_k^{-1} r[k] for the members with r[k] not None (one fused application)."""
+        n = self.size
+        outs = [None if r is None else self.empty(k) for k, r in enumerate(rs)] if outs is None else list(outs)
+        R = (C.c_void_p * n)(*[None if r is None else self._vec(r, k, "r") for k, r in enumerate(rs)])
+        Z = (C.c_void_p * n)(*[None if z is None else self._vec(z, k, "z") for k, z in enumerate(outs)])
+        _check(library().pintoc_group_precond_apply(self._h, R, Z, self._stream()), "pintoc_group_precond_apply")
+        return outs
+
+    def solve(self, bs, xs=None, history=0):
+        """Returns (list of x, list of stats dicts, list of converged flags)."""
+        n = self.size
+        xs = [self.empty(k) for k in range(n)] if xs is None else list(xs)
+        st = (SolveStats * n)()
+        counts = [(C.c_int32 * (m["nt"] // 2 + 1))() for m in self.members]
+        hists = [(C.c_double * max(int(history), 1))() for _ in range(n)]
+        for k in range(n):
+            st[k].inner_counts = C.cast(counts[k], C.POINTER(C.c_int32))
+            st[k].inner_counts_capacity = self.members[k]["nt"] // 2 + 1
+            if history > 0:
+                st[k].residual_history = C.cast(hists[k], C.POINTER(C.c_double))
+                st[k].history_capacity = int(history)
+        B = (C.c_void_p * n)(*[self._vec(b, k, "b") for k, b in enumerate(bs)])
+        X = (C.c_void_p * n)(*[self._vec(x, k, "x") for k, x in enumerate(xs)])
+        _check(library().pintoc_group_solve(self._h, B, X, st, self._stream()), "pintoc_group_solve")
+        out = []
+        for k in range(n):
+            d = st[k].as_dict()
+            d["inner_counts"] = [int(counts[k][j]) for j in range(self.members[k]["nt"] // 2 + 1)]
+            d["residual_history"] = [float(hists[k][i]) for i in range(st[k].history_length)]
+            out.append(d)
+        return xs, out, [bool(d["converged"]) for d in out]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().pintoc_problem_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def group_bytes(members, **options) -> int:
+    """Device bytes of a group's workspace (host-side set-up only)."""
+    import numpy as np
+    lib = library()
+    n = len(members)
+    descs = (Desc * n)()
+    keep = []
+    for k, m in enumerate(members):
+        wptr = None
+        if m.get("wind") is not None:
+            w = np.ascontiguousarray(np.asarray(m["wind"], dtype=np.float64).reshape(-1))
+            keep.append(w)
+            wptr = w.ctypes.data_as(C.POINTER(C.c_double))
+        descs[k] = Desc(m["N"], m["nt"], m.get("T", 1.0), m["nu"], m["beta"], m.get("flow", STOKES), wptr,
+                        0.0, 0.0, 0.0, 0.0)
+    o = default_options(**options)
+    h = C.c_void_p()
+    _check(lib.pintoc_group_create(descs, n, C.byref(o), C.byref(h)), "pintoc_group_create")
+    try:
+        return int(lib.pintoc_workspace_bytes(h))
+    finally:
+        lib.pintoc_problem_destroy(h)
 
 
 def solve_batch(problems, bs, xs=None):

@@ -191,3 +191,172 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
     if state["error"] is not None:
         raise state["error"]
     return out
+
+
+def _member_of(job):
+    return {"N": job["N"], "nt": job["nt"], "T": job.get("T", 1.0), "nu": job["nu"], "beta": job["beta"],
+            "flow": job.get("flow", 0), "wind": job.get("wind")}
+
+
+def autotune(jobs, sizes=(1, 2, 4, 8, 16), smoothers=None, budget_bytes=None, device="cuda", reps=2,
+             **options) -> dict:
+    """Pick, per class of jobs with the same (N, flow), the group size and the
+    smoother of the fused form by measurement: for every candidate that fits
+    the memory budget, one group of that many of the class's jobs (linear
+    preconditioner, the options' precision) applies its fused preconditioner
+    ``reps`` times; the candidate with the most member applications per
+    second wins, the smaller group on ties within 5 % (a smaller group wastes
+    less when its members converge at different iterations).  Returns
+    {(N, flow): {"size", "smoother", "trials": [...]}}."""
+    import numpy as np
+    import torch
+
+    from ._lib import INNER_LINEAR, SMOOTHER_GLOBAL, SMOOTHER_TILED, Group, group_bytes
+
+    smoothers = (SMOOTHER_TILED, SMOOTHER_GLOBAL) if smoothers is None else smoothers
+    if budget_bytes is None:
+        torch.cuda.synchronize(device)
+        torch.cuda.empty_cache()
+        free, _ = torch.cuda.mem_get_info(device)
+        budget_bytes = int(0.5 * free)
+    tune_opts = {k: v for k, v in options.items() if k in ("precision", "n_vcycles", "n_cheb", "n_uzawa", "mu_uzawa")}
+    classes = {}
+    for j in jobs:
+        classes.setdefault((j["N"], j.get("flow", 0)), []).append(j)
+    out = {}
+    for key, cj in classes.items():
+        trials = []
+        for sm in smoothers:
+            for g in sizes:
+                if g > len(cj):
+                    break
+                members = [_member_of(j) for j in cj[:g]]
+                opts = dict(tune_opts, inner=INNER_LINEAR, smoother=sm)
+                need = group_bytes(members, **opts) + sum(8 * 2 * (2 * m["nt"] * (2 * (2 * m["N"] + 1) ** 2
+                                                                                  + (m["N"] + 1) ** 2))
+                                                          for m in members)
+                if need > budget_bytes:
+                    break
+                grp = Group(members, device=device, **opts)
+                rs = [torch.randn(grp.n_all[k], dtype=torch.float64, device=device) for k in range(g)]
+                grp.precond_apply(rs)                                   # warm-up
+                torch.cuda.synchronize(device)
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    grp.precond_apply(rs)
+                torch.cuda.synchronize(device)
+                dt = (time.perf_counter() - t0) / reps
+                trials.append({"size": g, "smoother": int(sm), "seconds": dt, "member_apps_per_s": g / dt})
+                grp.close()
+                del grp, rs
+                torch.cuda.empty_cache()
+        best = max(t["member_apps_per_s"] for t in trials)
+        pick = min((t for t in trials if t["member_apps_per_s"] >= 0.95 * best),
+                   key=lambda t: (t["size"], t["smoother"]))
+        out[key] = {"size": pick["size"], "smoother": pick["smoother"], "trials": trials}
+    return out
+
+
+def run_fused(jobs, plan=None, workers: int = 2, budget_bytes: int | None = None, checksum: bool = False,
+              keep_solutions: bool = False, on_done=None, device="cuda", **options):
+    """The fused batched form: jobs with the same (N, flow) are solved in
+    groups (``pintoc_group_*``: one batch of every per-frequency kernel, FGMRES
+    in lockstep), the group size and smoother per class from ``plan`` (see
+    ``autotune``; default: groups of 4, tiled smoother).  ``workers`` host
+    threads, each with its own stream, run groups concurrently while their
+    device memory fits the budget.  Returns one record per job, as ``run``
+    (with the group it ran in)."""
+    import hashlib
+
+    import numpy as np
+    import torch
+
+    from ._lib import Group, group_bytes
+
+    n = len(jobs)
+    classes = {}
+    for k, j in enumerate(jobs):
+        classes.setdefault((j["N"], j.get("flow", 0)), []).append(k)
+    groups = []
+    for key, ks in classes.items():
+        size = plan[key]["size"] if plan and key in plan else 4
+        sm = plan[key]["smoother"] if plan and key in plan else 0
+        for i in range(0, len(ks), size):
+            groups.append((ks[i:i + size], sm))
+    torch.cuda.synchronize(device)
+    torch.cuda.empty_cache()
+    if budget_bytes is None:
+        free, _ = torch.cuda.mem_get_info(device)
+        budget_bytes = int(0.85 * free)
+
+    def vec_bytes(j):
+        return 8 * (2 * 2 * j["nt"] * (2 * (2 * j["N"] + 1) ** 2 + (j["N"] + 1) ** 2) + j["nt"] * 2 * (2 * j["N"] + 1) ** 2)
+
+    need = []
+    for ks, sm in groups:
+        members = [_member_of(jobs[k]) for k in ks]
+        need.append(group_bytes(members, smoother=sm, **options) + sum(vec_bytes(jobs[k]) for k in ks))
+    if groups and max(need) > budget_bytes:
+        raise ValueError(f"a group needs {max(need)} bytes, more than the budget {budget_bytes}")
+    # largest groups first: they bound the makespan
+    order = sorted(range(len(groups)), key=lambda g: -need[g])
+    out = [None] * n
+    lock = threading.Condition()
+    state = {"next": 0, "free": budget_bytes, "error": None}
+    t0 = time.perf_counter()
+
+    def worker():
+        stream = torch.cuda.Stream(device=device)          # default priority
+        while True:
+            with lock:
+                while True:
+                    if state["error"] is not None or state["next"] >= len(order):
+                        return
+                    gi = order[state["next"]]
+                    if need[gi] <= state["free"]:
+                        state["next"] += 1
+                        state["free"] -= need[gi]
+                        break
+                    lock.wait(timeout=0.05)
+            ks, sm = groups[gi]
+            start = time.perf_counter() - t0
+            try:
+                with torch.cuda.stream(stream):
+                    g = Group([_member_of(jobs[k]) for k in ks], device=device, smoother=sm, **options)
+                    bs = []
+                    for i, k in enumerate(ks):
+                        vd = torch.as_tensor(np.ascontiguousarray(jobs[k]["vd"], dtype=np.float64)).to(device)
+                        bs.append(g.assemble_rhs(i, vd))
+                    xs, sts, oks = g.solve(bs)
+                    stream.synchronize()
+                    end = time.perf_counter() - t0
+                    for i, k in enumerate(ks):
+                        sol = xs[i].cpu().numpy() if (keep_solutions or checksum) else None
+                        digest = hashlib.blake2b(sol.tobytes(), digest_size=16).hexdigest() if checksum else None
+                        out[k] = {"stats": sts[i], "converged": oks[i], "arrival": 0.0, "start": start, "end": end,
+                                  "bytes": need[gi], "group": gi, "group_size": len(ks), "digest": digest,
+                                  "solution": sol if keep_solutions else None}
+                    g.close()
+                    del g, bs, xs
+            except BaseException as e:                      # noqa: BLE001 - reported to the caller
+                with lock:
+                    state["error"] = e
+                    lock.notify_all()
+                return
+            with lock:
+                state["free"] += need[gi]
+                lock.notify_all()
+            if on_done is not None:
+                for k in ks:
+                    on_done(k, out[k])
+
+    threads = [threading.Thread(target=worker, daemon=True) for _ in range(max(1, workers))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize(device)
+    torch.cuda.empty_cache()
+    if state["error"] is not None:
+        raise state["error"]
+    return out

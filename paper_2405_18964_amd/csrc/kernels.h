@@ -138,17 +138,18 @@ void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n);
 // frequency blocks and the Oseen preconditioner pieces (oseen_kernels.hip)
 template <typename R>
 void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                      const BlockCoef* bc, const R* tcN, const R* tcNT, double sp, Mask mk);
+                      const BlockCoef* bc, const R* tcN, const R* tcNT, Mask mk);
+// per-frequency parameters ftau, fbeta, fnu: one entry per kept frequency
 template <typename R>
 void launch_schur_rhs(hipStream_t s, cpx<R>* out, const cpx<R>* in, const cpx<R>* y1, const cpx<R>* y2, int n,
-                      int nf, double tau, Mask mk);
+                      int nf, const double* ftau, Mask mk);
 template <typename R>
-void launch_oseen_hp(hipStream_t s, cpx<R>* U, const cpx<R>* zz, int n, int nf, const double2* dj, double tau,
-                     double beta, double nu, const double* conv, Mask mk);
+void launch_oseen_hp(hipStream_t s, cpx<R>* U, const cpx<R>* zz, int n, int nf, const double2* dj, const double* ftau,
+                     const double* fbeta, const double* fnu, const double* conv, Mask mk);
 template <typename R>
 void launch_block_copy(hipStream_t s, cpx<R>* V, cpx<R>* X, int n, int nf, int b, int dir, Mask mk);
 template <typename R>
 void launch_combine3(hipStream_t s, cpx<R>* out, const cpx<R>* A, const cpx<R>* B, const cpx<R>* C, double c0,
-                     double c1, double c2, size_t n, int seg, Mask mk);
+                     double c1, double c2, const double* c1f, size_t n, int seg, Mask mk);
 
 }  // namespace pintoc

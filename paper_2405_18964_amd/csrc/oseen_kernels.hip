@@ -43,10 +43,11 @@ __device__ inline void b_apply_node(const cpx<R>* __restrict__ ux, const cpx<R>*
   }
 }
 
-// rows 3 and 4: yP[j][0] = s B lambda, yP[j][1] = s B v  (node 0 pinned: 0)
+// rows 3 and 4: yP[j][0] = s_j B lambda, yP[j][1] = s_j B v  (node 0 pinned: 0),
+// s_j = bc[j].s
 template <typename R>
 __global__ __launch_bounds__(256) void k_block_pres(cpx<R>* __restrict__ yP, const cpx<R>* __restrict__ xV, int n,
-                                                    double s, Mask mk) {
+                                                    const BlockCoef* __restrict__ bc, Mask mk) {
   const int nq2 = (2 * n + 1) * (2 * n + 1), np2 = (n + 1) * (n + 1);
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int jb = blockIdx.y;
@@ -57,16 +58,17 @@ __global__ __launch_bounds__(256) void k_block_pres(cpx<R>* __restrict__ yP, con
   const cpx<R>* ux = xV + ((size_t)(j * 2 + (b == 0 ? 1 : 0)) * 2 + 0) * nq2;
   double sr, si;
   b_apply_node<R>(ux, ux + nq2, n, k, sr, si);
+  const double s = bc[j].s;
   yP[o] = cmk<cpx<R>>(s * sr, s * si);
 }
 
 // Pressure inputs of the Schur step of Algorithm 3:
-//   out[j][0] = in[j][0] - tau B y2_j,   out[j][1] = in[j][1] - tau B y1_j
+//   out[j][0] = in[j][0] - tau_j B y2_j,   out[j][1] = in[j][1] - tau_j B y1_j
 // with y1, y2 given as 2-component velocity batches [j][comp] (node 0 -> 0).
 template <typename R>
 __global__ __launch_bounds__(256) void k_schur_rhs(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ in,
                                                    const cpx<R>* __restrict__ y1, const cpx<R>* __restrict__ y2,
-                                                   int n, double tau, Mask mk) {
+                                                   int n, const double* __restrict__ ftau, Mask mk) {
   const int nq2 = (2 * n + 1) * (2 * n + 1), np2 = (n + 1) * (n + 1);
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int jb = blockIdx.y;
@@ -77,6 +79,7 @@ __global__ __launch_bounds__(256) void k_schur_rhs(cpx<R>* __restrict__ out, con
   const cpx<R>* u = (b == 0 ? y2 : y1) + (size_t)j * 2 * nq2;
   double sr, si;
   b_apply_node<R>(u, u + nq2, n, k, sr, si);
+  const double tau = ftau[j];
   const cpx<R> v = in[o];
   out[o] = cmk<cpx<R>>((double)v.x - tau * sr, (double)v.y - tau * si);
 }
@@ -84,11 +87,13 @@ __global__ __launch_bounds__(256) void k_schur_rhs(cpx<R>* __restrict__ out, con
 // u-step of the Oseen Schur inverse on the unconstrained Q1 grid:
 //   with z1 = zz[j][1], z2 = zz[j][0] (already multiplied by (tau M_N)^{-1}),
 //   U[j][0] = u2 = (d M + tau L) z1 - tau/beta M z2
-//   U[j][1] = u1 = tau M z1 + (conj(d) M + tau L^T) z2,   L = nu K + N.
+//   U[j][1] = u1 = tau M z1 + (conj(d) M + tau L^T) z2,   L = nu K + N,
+// with the frequency's own tau, beta, nu (ftau, fbeta, fnu).
 template <typename R>
 __global__ __launch_bounds__(256) void k_oseen_hp(cpx<R>* __restrict__ U, const cpx<R>* __restrict__ zz, int n,
-                                                  const double2* __restrict__ dj, double tau, double beta,
-                                                  double nu, const double* __restrict__ conv, Mask mk) {
+                                                  const double2* __restrict__ dj, const double* __restrict__ ftau,
+                                                  const double* __restrict__ fbeta, const double* __restrict__ fnu,
+                                                  const double* __restrict__ conv, Mask mk) {
   const int np = n + 1, np2 = np * np;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
@@ -122,6 +127,7 @@ __global__ __launch_bounds__(256) void k_oseen_hp(cpx<R>* __restrict__ U, const 
     }
   }
   const double2 d = dj[j];
+  const double tau = ftau[j], beta = fbeta[j], nu = fnu[j];
   const double u2r = d.x * M1[0] - d.y * M1[1] + tau * (nu * K1[0] + N1[0]) - (tau / beta) * M2[0];
   const double u2i = d.x * M1[1] + d.y * M1[0] + tau * (nu * K1[1] + N1[1]) - (tau / beta) * M2[1];
   const double u1r = tau * M1[0] + d.x * M2[0] + d.y * M2[1] + tau * (nu * K2[0] + T2[0]);
@@ -145,15 +151,23 @@ __global__ __launch_bounds__(256) void k_block_copy(cpx<R>* __restrict__ V, cpx<
   else V[ov] = X[ox];
 }
 
-// out = c0 A + c1 B + c2 C (real coefficients; B or C may be null); out may alias A.
+// out = c0 A + c1 f_j B + c2 C (real coefficients; B or C may be null; f_j =
+// c1f[frequency of the grid], 1 when c1f is null); out may alias A.
 template <typename R>
 __global__ __launch_bounds__(256) void k_combine3(cpx<R>* out, const cpx<R>* A, const cpx<R>* B, const cpx<R>* C,
-                                                  double c0, double c1, double c2, size_t n, int seg, Mask mk) {
+                                                  double c0, double c1, double c2, const double* __restrict__ c1f,
+                                                  size_t n, int seg, Mask mk) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    if (mk.off((int)(e / seg))) continue;
+    const int grid = (int)(e / seg);
+    if (mk.off(grid)) continue;
     const cpx<R> a = A[e];
     double r = c0 * (double)a.x, i = c0 * (double)a.y;
-    if (B) { const cpx<R> v = B[e]; r += c1 * (double)v.x; i += c1 * (double)v.y; }
+    if (B) {
+      const double cb = c1f ? c1 * c1f[grid / mk.fpj] : c1;
+      const cpx<R> v = B[e];
+      r += cb * (double)v.x;
+      i += cb * (double)v.y;
+    }
     if (C) { const cpx<R> v = C[e]; r += c2 * (double)v.x; i += c2 * (double)v.y; }
     out[e] = cmk<cpx<R>>(r, i);
   }
@@ -161,24 +175,25 @@ __global__ __launch_bounds__(256) void k_combine3(cpx<R>* out, const cpx<R>* A, 
 
 template <typename R>
 void launch_block_mat(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, const cpx<R>* xP, int n, int nf,
-                      const BlockCoef* bc, const R* tcN, const R* tcNT, double sp, Mask mk) {
+                      const BlockCoef* bc, const R* tcN, const R* tcNT, Mask mk) {
   const int np2 = (n + 1) * (n + 1);
   launch_q2_block_vel<R>(s, yV, xV, xP, n, nf, bc, tcN, tcNT, mk);
-  hipLaunchKernelGGL(k_block_pres<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, yP, xV, n, sp, mk);
+  hipLaunchKernelGGL(k_block_pres<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, yP, xV, n, bc, mk);
 }
 
 template <typename R>
 void launch_schur_rhs(hipStream_t s, cpx<R>* out, const cpx<R>* in, const cpx<R>* y1, const cpx<R>* y2, int n,
-                      int nf, double tau, Mask mk) {
+                      int nf, const double* ftau, Mask mk) {
   const int np2 = (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_schur_rhs<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, out, in, y1, y2, n, tau, mk);
+  hipLaunchKernelGGL(k_schur_rhs<R>, dim3((np2 + 255) / 256, 2 * nf), dim3(256), 0, s, out, in, y1, y2, n, ftau, mk);
 }
 
 template <typename R>
-void launch_oseen_hp(hipStream_t s, cpx<R>* U, const cpx<R>* zz, int n, int nf, const double2* dj, double tau,
-                     double beta, double nu, const double* conv, Mask mk) {
+void launch_oseen_hp(hipStream_t s, cpx<R>* U, const cpx<R>* zz, int n, int nf, const double2* dj, const double* ftau,
+                     const double* fbeta, const double* fnu, const double* conv, Mask mk) {
   const int np2 = (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_oseen_hp<R>, dim3((np2 + 255) / 256, nf), dim3(256), 0, s, U, zz, n, dj, tau, beta, nu, conv, mk);
+  hipLaunchKernelGGL(k_oseen_hp<R>, dim3((np2 + 255) / 256, nf), dim3(256), 0, s, U, zz, n, dj, ftau, fbeta, fnu,
+                     conv, mk);
 }
 
 template <typename R>
@@ -189,20 +204,20 @@ void launch_block_copy(hipStream_t s, cpx<R>* V, cpx<R>* X, int n, int nf, int b
 
 template <typename R>
 void launch_combine3(hipStream_t s, cpx<R>* out, const cpx<R>* A, const cpx<R>* B, const cpx<R>* C, double c0,
-                     double c1, double c2, size_t n, int seg, Mask mk) {
-  hipLaunchKernelGGL(k_combine3<R>, dim3(2048), dim3(256), 0, s, out, A, B, C, c0, c1, c2, n, seg, mk);
+                     double c1, double c2, const double* c1f, size_t n, int seg, Mask mk) {
+  hipLaunchKernelGGL(k_combine3<R>, dim3(2048), dim3(256), 0, s, out, A, B, C, c0, c1, c2, c1f, n, seg, mk);
 }
 
 #define PINTOC_OSEEN_INST(R)                                                                                       \
   template void launch_block_mat<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,         \
-                                    const BlockCoef*, const R*, const R*, double, Mask);                       \
+                                    const BlockCoef*, const R*, const R*, Mask);                               \
   template void launch_schur_rhs<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, int, int,   \
-                                    double, Mask);                                                                       \
-  template void launch_oseen_hp<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, const double2*, double, double,  \
-                                   double, const double*, Mask);                                                         \
+                                    const double*, Mask);                                                                \
+  template void launch_oseen_hp<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, const double2*, const double*,   \
+                                   const double*, const double*, const double*, Mask);                                   \
   template void launch_block_copy<R>(hipStream_t, cpx<R>*, cpx<R>*, int, int, int, int, Mask);                           \
   template void launch_combine3<R>(hipStream_t, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*, double,      \
-                                   double, double, size_t, int, Mask);
+                                   double, double, const double*, size_t, int, Mask);
 
 PINTOC_OSEEN_INST(double)
 PINTOC_OSEEN_INST(float)

@@ -61,7 +61,7 @@ struct MGPlan {
   int fpc = 1;          // grids per coefficient set
   int ncoef = 0;
   std::vector<OpCoef> coef_h;          // finest level; eta scales N, etat scales N^T
-  std::vector<double> visc;            // per level: real diffusion coefficient replacing gamma (empty: gamma;
+  std::vector<double> visc;            // [level][set]: real diffusion coefficient replacing gamma (empty: gamma;
                                        // Q1 plans keep one operator on every level)
   std::vector<OpCoef> coef_dev_h;      // as uploaded, [level][set]: Q2 tile kernels apply eta to the plan's one table
   std::vector<double2> inv_h;          // coarsest inverses, per coefficient set
@@ -89,9 +89,9 @@ struct MGPlan {
   Mask mk() const { return Mask{mask, fpj}; }
   const OpCoef* coefl(int l) const { return coef + (size_t)l * ncoef; }
   // coefficient set c on level l (host)
-  OpCoef level_coef(const OpCoef& c, int l) const {
-    OpCoef r = c;
-    if (!visc.empty()) r.gamma = make_double2(visc[l], 0.0);
+  OpCoef level_coef(int set, int l) const {
+    OpCoef r = coef_h[set];
+    if (!visc.empty()) r.gamma = make_double2(visc[(size_t)l * ncoef + set], 0.0);
     return r;
   }
   int n(int l) const { return N >> l; }
@@ -101,8 +101,22 @@ struct MGPlan {
   }
 };
 
+// One problem of a group (a lone problem is a group of one).  Its kept
+// frequencies are f0 .. f0 + nf - 1 of the group's batch, its twiddles start
+// at tw0; nu is the viscosity of the unit-square equivalent.  The outer Krylov
+// vectors are the member's own.
+struct Member {
+  int nt = 0, nf = 0, f0 = 0, tw0 = 0;
+  double T = 0, tau = 0, nu = 0, beta = 0;
+  int64_t n_all = 0;
+  double *Vk = nullptr, *Zk = nullptr, *rvec = nullptr, *xtmp = nullptr;
+};
+
 struct pintoc_problem {
   pintoc_problem_desc d{};
+  std::vector<Member> mem;              // one entry for a lone problem
+  bool group = false;                   // created by pintoc_group_create
+  std::vector<int> mem_on, freq_on;     // members (and their frequencies) taking part in the current application
   pintoc_options o{};
   std::vector<double> wind;
   double tau = 0;
@@ -130,7 +144,6 @@ struct pintoc_problem {
   // block coefficients of Z_j (Stokes) or G_j (Oseen), per kept frequency
   std::vector<BlockCoef> bc_h;
   BlockCoef* bc = nullptr;
-  double block_scale = 1.0;            // s of the pressure rows (1 Stokes, tau Oseen)
   // Oseen: convection tables (host copies and device), Q_j / Q_j^H multigrid,
   // operator tables of the Uzawa steps and the Schur step
   std::vector<std::vector<double>> conv2_h;   // per level, 50 per Q2 node
@@ -149,11 +162,14 @@ struct pintoc_problem {
   const int* cur_mask = nullptr;       // mask in force for the current block operations
   Mask mk(int fpj) const { return Mask{cur_mask, fpj}; }
   std::vector<OpCoef> cpsi_h, cpsih_h;
-  OpCoef *cpsi = nullptr, *cpsih = nullptr, *cscal = nullptr;   // cscal: [tau M, tau/beta M, M]
+  OpCoef *cpsi = nullptr, *cpsih = nullptr, *cscal = nullptr;   // cscal: [tau M, tau/beta M, M][j]
   std::vector<double2> dj_h;
-  double2 *dj = nullptr, *abO = nullptr;
-  OpCoef cscal_h[3];
-  double2 abO_h;
+  double2 *dj = nullptr, *abO = nullptr;                          // abO[j] = -1/tau^2
+  std::vector<OpCoef> cscal_h[3];
+  std::vector<double2> abO_h;
+  // per kept frequency: its member's tau, 1/tau, beta, nu
+  std::vector<double> ftau_h, finvtau_h, fbeta_h, fnu_h;
+  double *ftau = nullptr, *finvtau = nullptr, *fbeta = nullptr, *fnu = nullptr;
   void *B1 = nullptr, *B2 = nullptr, *X1 = nullptr, *X2 = nullptr, *T1 = nullptr, *T2 = nullptr, *Rb = nullptr;
   void *C1 = nullptr, *C2 = nullptr, *Pt = nullptr, *Ub = nullptr;
   Probe probe, probe_post;
@@ -326,7 +342,11 @@ static void plan_mg_buffers(MGPlan& m, Carver& cv, size_t csize) {
 static void carve(pintoc_problem* p, char* base) {
   Carver cv{base};
   const int nf = p->nf;
-  p->tw = cv.take<double2>(sizeof(double2) * (p->d.nt / 2));
+  p->tw = cv.take<double2>(sizeof(double2) * p->tw_h.size());
+  p->ftau = cv.take<double>(sizeof(double) * nf);
+  p->finvtau = cv.take<double>(sizeof(double) * nf);
+  p->fbeta = cv.take<double>(sizeof(double) * nf);
+  p->fnu = cv.take<double>(sizeof(double) * nf);
   p->tj = cv.take<double2>(sizeof(double2) * nf);
   p->ab = cv.take<double2>(sizeof(double2) * nf);
   const size_t vbytes = (size_t)4 * nf * p->nq2 * p->csize;
@@ -372,9 +392,9 @@ static void carve(pintoc_problem* p, char* base) {
     p->conv1 = cv.take<double>(sizeof(double) * p->conv1_h.size());
     p->cpsi = cv.take<OpCoef>(sizeof(OpCoef) * nf);
     p->cpsih = cv.take<OpCoef>(sizeof(OpCoef) * nf);
-    p->cscal = cv.take<OpCoef>(sizeof(OpCoef) * 3);
+    p->cscal = cv.take<OpCoef>(sizeof(OpCoef) * 3 * nf);
     p->dj = cv.take<double2>(sizeof(double2) * nf);
-    p->abO = cv.take<double2>(sizeof(double2));
+    p->abO = cv.take<double2>(sizeof(double2) * nf);
     const size_t hb = (size_t)2 * nf * p->nq2 * p->csize;    // one velocity block: [j][comp]
     for (void** q : {&p->B1, &p->B2, &p->X1, &p->X2, &p->T1, &p->T2, &p->Rb, &p->C1, &p->C2}) *q = cv.take<char>(hb);
     p->Pt = cv.take<char>(pbytes);
@@ -398,12 +418,18 @@ static void carve(pintoc_problem* p, char* base) {
   }
   plan_mg_buffers(p->mgK, cv, p->csize);
   const int m = p->o.restart;
-  const size_t vb = sizeof(double) * (size_t)p->n_all;
-  p->Vk = cv.take<double>(vb * (m + 1));
-  p->Zk = cv.take<double>(vb * m);
-  p->rvec = cv.take<double>(vb);
-  p->xtmp = cv.take<double>(vb);
-  p->dscale = p->side != 1.0 ? cv.take<double>(vb) : nullptr;
+  for (Member& mb : p->mem) {
+    const size_t vb = sizeof(double) * (size_t)mb.n_all;
+    mb.Vk = cv.take<double>(vb * (m + 1));
+    mb.Zk = cv.take<double>(vb * m);
+    mb.rvec = cv.take<double>(vb);
+    mb.xtmp = cv.take<double>(vb);
+  }
+  p->Vk = p->mem[0].Vk;
+  p->Zk = p->mem[0].Zk;
+  p->rvec = p->mem[0].rvec;
+  p->xtmp = p->mem[0].xtmp;
+  p->dscale = p->side != 1.0 ? cv.take<double>(sizeof(double) * (size_t)p->n_all) : nullptr;
   p->dd = cv.take<double>(sizeof(double) * 64);
   p->dd2 = cv.take<double>(sizeof(double) * 64);
   p->part = cv.take<double>(sizeof(double) * 8 * 1024);
@@ -565,20 +591,42 @@ extern "C" int pintoc_last_inner_iterations(const pintoc_problem* p, int32_t* co
 
 static void byte_model(pintoc_problem* p);
 
-extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_options* o, pintoc_problem** out) {
-  if (!d || !out) return fail(PINTOC_EINVAL, "NULL descriptor or output pointer");
+// Validation and set-up of one problem or of a group of problems (members)
+// that share N, the flow, the domain, the wind and the options; the kept
+// frequencies of all members form one batch (member k owns the frequencies
+// f0 .. f0 + nt_k/2 of it), every per-frequency table carries its member's
+// tau, beta and nu.
+static int create_impl(const pintoc_problem_desc* ds, int nm, const pintoc_options* o, pintoc_problem** out) {
+  if (!ds || !out) return fail(PINTOC_EINVAL, "NULL descriptor or output pointer");
+  if (nm < 1 || nm > 4096) return fail(PINTOC_EINVAL, "a group needs 1 to 4096 members");
   pintoc_options opt;
   pintoc_default_options(&opt);
   if (o) opt = *o;
-  if (d->N < 2 || !pow2(d->N) || d->N > 4096) return fail(PINTOC_EINVAL, "N must be a power of two in [2, 4096]");
-  if (d->nt < 2 || !pow2(d->nt) || d->nt > 1024) return fail(PINTOC_EINVAL, "nt must be a power of two in [2, 1024]");
-  if (!(d->T > 0) || !(d->nu > 0) || !(d->beta > 0)) return fail(PINTOC_EINVAL, "T, nu and beta must be > 0");
-  if (d->flow != PINTOC_STOKES && d->flow != PINTOC_OSEEN) return fail(PINTOC_EINVAL, "unknown flow");
+  const pintoc_problem_desc* d = &ds[0];
+  for (int k = 0; k < nm; ++k) {
+    const pintoc_problem_desc* e = &ds[k];
+    const std::string who = nm > 1 ? "member " + std::to_string(k) + ": " : std::string();
+    if (e->N < 2 || !pow2(e->N) || e->N > 4096) return fail(PINTOC_EINVAL, who + "N must be a power of two in [2, 4096]");
+    if (e->nt < 2 || !pow2(e->nt) || e->nt > 1024) return fail(PINTOC_EINVAL, who + "nt must be a power of two in [2, 1024]");
+    if (!(e->T > 0) || !(e->nu > 0) || !(e->beta > 0)) return fail(PINTOC_EINVAL, who + "T, nu and beta must be > 0");
+    if (e->flow != PINTOC_STOKES && e->flow != PINTOC_OSEEN) return fail(PINTOC_EINVAL, who + "unknown flow");
+    if (e->flow == PINTOC_OSEEN && !e->wind) return fail(PINTOC_EINVAL, who + "Oseen flow needs a wind");
+    if (k > 0) {
+      if (e->N != d->N || e->flow != d->flow) return fail(PINTOC_EINVAL, who + "group members need the same N and flow");
+      if (e->x0 != d->x0 || e->y0 != d->y0 || e->x1 != d->x1 || e->y1 != d->y1)
+        return fail(PINTOC_EINVAL, who + "group members need the same domain");
+      if (e->flow == PINTOC_OSEEN) {
+        const size_t nw = 2 * (size_t)(2 * d->N + 1) * (2 * d->N + 1);
+        if (std::memcmp(e->wind, d->wind, nw * sizeof(double)) != 0)
+          return fail(PINTOC_EINVAL, who + "group members need the same wind");
+      }
+    }
+  }
   const bool unit = d->x0 == 0.0 && d->y0 == 0.0 && d->x1 == 0.0 && d->y1 == 0.0;
   const double side = unit ? 1.0 : d->x1 - d->x0;
   if (!unit && (!(side > 0) || !std::isfinite(side) || std::fabs((d->y1 - d->y0) - side) > 1e-12 * side))
     return fail(PINTOC_EINVAL, "the domain must be a square [x0, x1] x [y0, y1] with x1 - x0 = y1 - y0 > 0");
-  if (d->flow == PINTOC_OSEEN && !d->wind) return fail(PINTOC_EINVAL, "Oseen flow needs a wind");
+  if (nm > 1 && side != 1.0) return fail(PINTOC_EINVAL, "groups are set up on the unit square only");
   if (opt.inner != PINTOC_INNER_LINEAR && opt.inner != PINTOC_INNER_GMRES) return fail(PINTOC_EINVAL, "unknown inner mode");
   if (opt.inner == PINTOC_INNER_GMRES &&
       (opt.inner_restart < 1 || opt.inner_restart > 100 || opt.inner_maxit < 1 || !(opt.inner_tol > 0)))
@@ -593,18 +641,19 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   if (opt.smoother != PINTOC_SMOOTHER_TILED && opt.smoother != PINTOC_SMOOTHER_GLOBAL)
     return fail(PINTOC_EINVAL, "unknown smoother");
   if (opt.outer == PINTOC_OUTER_MINRES &&
-      (d->flow != PINTOC_STOKES || opt.inner != PINTOC_INNER_LINEAR || opt.restart < 4))
-    return fail(PINTOC_EINVAL, "MINRES needs the Stokes flow, the linear preconditioner and restart >= 4");
+      (nm > 1 || d->flow != PINTOC_STOKES || opt.inner != PINTOC_INNER_LINEAR || opt.restart < 4))
+    return fail(PINTOC_EINVAL, "MINRES needs a single Stokes problem, the linear preconditioner and restart >= 4");
   auto* p = new pintoc_problem();
   p->d = *d;
   p->d.wind = nullptr;
   p->o = opt;
+  p->group = nm > 1;
   // A square of side l is the unit square's problem with viscosity nu / l^2
   // and wind w / l: M, K, B, N(w) scale as l^2, 1, l and l, so the physical
   // matrix is D_r A' D_c with A' the unit-square matrix of (nu / l^2, w / l),
   // D_r = l^2 on momentum rows and l on divergence rows, D_c = 1/l on
   // pressure columns.  Everything below is set up for A'; the entry points
-  // apply D_r, D_c (kkt_scaled, precond_scaled).
+  // apply D_r, D_c (see kkt and precond).
   p->side = side;
   p->d.nu = d->nu / (side * side);
   std::vector<double> wsc;
@@ -613,24 +662,37 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     wsc.assign(d->wind, d->wind + nw);
     for (double& v : wsc) v /= side;
   }
-  const int N = d->N, nt = d->nt;
-  p->tau = d->T / nt;
-  p->nf = nt / 2 + 1;
+  const int N = d->N;
   p->nq2 = (2 * N + 1) * (2 * N + 1);
   p->np2 = (N + 1) * (N + 1);
   p->L = 2 * p->nq2 + p->np2;
-  p->n_all = (int64_t)2 * nt * p->L;
   p->csize = opt.precision == PINTOC_PREC_FP64 ? 16 : 8;
   p->segV = 4 * p->nq2;
   p->segP = 2 * p->np2;
-  // twiddles exp(-2 pi i k / nt)
-  for (int k = 0; k < nt / 2; ++k) {
-    const double a = -2.0 * M_PI * k / nt;
-    p->tw_h.push_back(make_double2(std::cos(a), std::sin(a)));
+  int f0 = 0, tw0 = 0;
+  for (int k = 0; k < nm; ++k) {
+    Member m;
+    m.nt = ds[k].nt;
+    m.nf = m.nt / 2 + 1;
+    m.f0 = f0;
+    m.tw0 = tw0;
+    m.T = ds[k].T;
+    m.tau = ds[k].T / m.nt;
+    m.nu = ds[k].nu / (side * side);
+    m.beta = ds[k].beta;
+    m.n_all = (int64_t)2 * m.nt * p->L;
+    f0 += m.nf;
+    tw0 += m.nt / 2;
+    // twiddles exp(-2 pi i k / nt) of this member's FFT length
+    for (int q = 0; q < m.nt / 2; ++q) {
+      const double a = -2.0 * M_PI * q / m.nt;
+      p->tw_h.push_back(make_double2(std::cos(a), std::sin(a)));
+    }
+    p->mem.push_back(m);
   }
-  // per-frequency constants (section 3.1-3.2): d_j = 1 - exp(-2 pi i j/nt),
-  // c2 = (1/beta + d_c^2/tau^2)^{-1/2},  c1 = d_r / sqrt(tau^2/beta + d_c^2)
-  const double tau = p->tau, beta = d->beta, nu = p->d.nu;
+  p->nf = f0;
+  p->tau = p->mem[0].tau;
+  p->n_all = p->mem[0].n_all;
   const bool oseen = d->flow == PINTOC_OSEEN;
   int nl = 0;
   for (int n = N; n >= 2; n >>= 1) ++nl;
@@ -668,36 +730,60 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
   }
   MGPlan& W = p->mgW;
   W.q2 = true; W.N = N; W.nb = 4 * p->nf; W.fpc = 4; W.ncoef = p->nf; W.fpj = 4;
-  const double sb = std::sqrt(beta);
-  for (int j = 0; j < p->nf; ++j) {
-    const double th = 2.0 * M_PI * j / nt;
-    const double dr = 1.0 - std::cos(th), dc = std::sin(th);
-    const cd dj(dr, dc), djc(dr, -dc);
-    const double c2 = 1.0 / std::sqrt(1.0 / beta + dc * dc / (tau * tau));
-    const double c1 = dr / std::sqrt(tau * tau / beta + dc * dc);
-    p->tj_h.push_back(make_double2(dc, c2));
-    p->ab_h.push_back(make_double2(1.0 + c1, nu * c2));
-    p->cj_h.push_back(make_double2(c1, c2 * nu));          // X = c1 M + c2 L, L = nu K
-    W.coef_h.push_back(mkcoef(1.0 + c1, nu * c2));        // W_j = (1 + c1) M + c2 nu K
-    BlockCoef bc{};
-    auto c2d = [](cd v) { return make_double2(v.real(), v.imag()); };
-    if (!oseen) {          // Z_j = [[M, X, 0, B^T], [X, -M, B^T, 0], [0, B, 0, 0], [B, 0, 0, 0]]
-      bc.a11 = c2d(1.0); bc.a12 = c2d(c1); bc.b12 = c2d(c2 * nu); bc.e12 = c2d(0.0);
-      bc.a21 = c2d(c1); bc.b21 = c2d(c2 * nu); bc.e21 = c2d(0.0); bc.a22 = c2d(-1.0); bc.s = 1.0;
-    } else {               // G_j of eq. (SubBlockG)
-      bc.a11 = c2d(tau); bc.a12 = c2d(djc); bc.b12 = c2d(tau * nu); bc.e12 = c2d(tau);
-      bc.a21 = c2d(dj); bc.b21 = c2d(tau * nu); bc.e21 = c2d(tau); bc.a22 = c2d(-tau / beta); bc.s = tau;
-      // Psi = d M + tau L, Psi^H = conj(d) M + tau L^T (L = nu K + N);
-      // Q_j = Psi + tau/sqrt(beta) M, Q_j^H = Psi^H + tau/sqrt(beta) M
-      p->cpsi_h.push_back(mkcoef(dj, tau * nu, tau, 0.0));
-      p->cpsih_h.push_back(mkcoef(djc, tau * nu, tau, 0.0));     // eta: applied to the N^T table
-      p->mgQ.coef_h.push_back(mkcoef(dj + tau / sb, tau * nu, tau, 0.0));
-      p->mgQH.coef_h.push_back(mkcoef(djc + tau / sb, tau * nu, 0.0, tau));
-      p->dj_h.push_back(make_double2(dr, dc));
+  double wmax = 0.0;                             // largest nodal wind speed (coarse-level viscosity)
+  if (oseen)
+    for (size_t i = 0; i < (size_t)p->nq2; ++i) wmax = std::max(wmax, std::hypot(wsc[i], wsc[(size_t)p->nq2 + i]));
+  std::vector<double> visc((size_t)nl * p->nf);
+  for (const Member& mb : p->mem) {
+    // per-frequency constants (section 3.1-3.2): d_j = 1 - exp(-2 pi i j/nt),
+    // c2 = (1/beta + d_c^2/tau^2)^{-1/2},  c1 = d_r / sqrt(tau^2/beta + d_c^2)
+    const double tau = mb.tau, beta = mb.beta, nu = mb.nu, sb = std::sqrt(beta);
+    for (int j = 0; j < mb.nf; ++j) {
+      const int jg = mb.f0 + j;
+      const double th = 2.0 * M_PI * j / mb.nt;
+      const double dr = 1.0 - std::cos(th), dc = std::sin(th);
+      const cd dj(dr, dc), djc(dr, -dc);
+      const double c2 = 1.0 / std::sqrt(1.0 / beta + dc * dc / (tau * tau));
+      const double c1 = dr / std::sqrt(tau * tau / beta + dc * dc);
+      p->tj_h.push_back(make_double2(dc, c2));
+      p->ab_h.push_back(make_double2(1.0 + c1, nu * c2));
+      p->cj_h.push_back(make_double2(c1, c2 * nu));          // X = c1 M + c2 L, L = nu K
+      W.coef_h.push_back(mkcoef(1.0 + c1, nu * c2));        // W_j = (1 + c1) M + c2 nu K
+      p->ftau_h.push_back(tau);
+      p->finvtau_h.push_back(1.0 / tau);
+      p->fbeta_h.push_back(beta);
+      p->fnu_h.push_back(nu);
+      BlockCoef bc{};
+      auto c2d = [](cd v) { return make_double2(v.real(), v.imag()); };
+      if (!oseen) {          // Z_j = [[M, X, 0, B^T], [X, -M, B^T, 0], [0, B, 0, 0], [B, 0, 0, 0]]
+        bc.a11 = c2d(1.0); bc.a12 = c2d(c1); bc.b12 = c2d(c2 * nu); bc.e12 = c2d(0.0);
+        bc.a21 = c2d(c1); bc.b21 = c2d(c2 * nu); bc.e21 = c2d(0.0); bc.a22 = c2d(-1.0); bc.s = 1.0;
+      } else {               // G_j of eq. (SubBlockG)
+        bc.a11 = c2d(tau); bc.a12 = c2d(djc); bc.b12 = c2d(tau * nu); bc.e12 = c2d(tau);
+        bc.a21 = c2d(dj); bc.b21 = c2d(tau * nu); bc.e21 = c2d(tau); bc.a22 = c2d(-tau / beta); bc.s = tau;
+        // Psi = d M + tau L, Psi^H = conj(d) M + tau L^T (L = nu K + N);
+        // Q_j = Psi + tau/sqrt(beta) M, Q_j^H = Psi^H + tau/sqrt(beta) M
+        p->cpsi_h.push_back(mkcoef(dj, tau * nu, tau, 0.0));
+        p->cpsih_h.push_back(mkcoef(djc, tau * nu, tau, 0.0));     // eta: applied to the N^T table
+        p->mgQ.coef_h.push_back(mkcoef(dj + tau / sb, tau * nu, tau, 0.0));
+        p->mgQH.coef_h.push_back(mkcoef(djc + tau / sb, tau * nu, 0.0, tau));
+        p->dj_h.push_back(make_double2(dr, dc));
+        // the mass operators of the Uzawa steps: tau M, tau/beta M, M
+        p->cscal_h[0].push_back(mkcoef(tau, 0.0));
+        p->cscal_h[1].push_back(mkcoef(tau / beta, 0.0));
+        p->cscal_h[2].push_back(mkcoef(1.0, 0.0));
+        p->abO_h.push_back(make_double2(-1.0 / (tau * tau), 0.0));
+        // Coarse-level viscosity of the convection-diffusion multigrid: level
+        // l of n x n elements (side h = 1/n) diffuses with tau max(nu,
+        // |w|_max h / 4), so its mesh Peclet number |w|_max h / (2 nu_l) is at
+        // most 2; the finest level keeps tau nu.  With the true nu on
+        // convection-dominated coarse levels the V-cycle diverges.
+        for (int l = 0; l < nl; ++l)
+          visc[(size_t)l * p->nf + jg] = tau * (l == 0 ? nu : std::max(nu, wmax / (4.0 * (N >> l))));
+      }
+      p->bc_h.push_back(bc);
     }
-    p->bc_h.push_back(bc);
   }
-  p->block_scale = oseen ? tau : 1.0;
   MGPlan& K = p->mgK;
   K.q2 = false; K.N = N; K.nb = 2 * p->nf; K.fpc = 2 * p->nf; K.ncoef = 1; K.fpj = 2;
   K.coef_h.push_back(mkcoef(0.0, 1.0));                   // unconstrained pressure Laplacian
@@ -705,17 +791,6 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     m->q2 = true; m->N = N; m->nb = 2 * p->nf; m->fpc = 2; m->ncoef = p->nf; m->fpj = 2;
   }
   if (oseen) {
-    // Coarse-level viscosity of the convection-diffusion multigrid: level l of
-    // n x n elements (side h = 1/n) diffuses with tau max(nu, |w|_max h / 4),
-    // so its mesh Peclet number |w|_max h / (2 nu_l) is at most 2; the finest
-    // level keeps tau nu.  With the true nu on convection-dominated coarse
-    // levels the V-cycle diverges.
-    const int nq = 2 * N + 1;
-    double wmax = 0.0;
-    for (size_t i = 0; i < (size_t)nq * nq; ++i)
-      wmax = std::max(wmax, std::hypot(wsc[i], wsc[(size_t)nq * nq + i]));
-    std::vector<double> visc;
-    for (int l = 0; l < nl; ++l) visc.push_back(tau * (l == 0 ? nu : std::max(nu, wmax / (4.0 * (N >> l)))));
     p->mgQ.visc = visc;
     p->mgQH.visc = visc;
   }
@@ -727,8 +802,8 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     m->conv.assign(nl, nullptr);
     m->active = m->nb;
     for (int l = 0; l < nl; ++l)
-      for (const OpCoef& c0 : m->coef_h) {  // the Q2 tile kernels take the one nonzero half as eta
-        OpCoef c = m->level_coef(c0, l);
+      for (int set = 0; set < m->ncoef; ++set) {  // the Q2 tile kernels take the one nonzero half as eta
+        OpCoef c = m->level_coef(set, l);
         if (m->q2 && (c.etat.x != 0.0 || c.etat.y != 0.0)) {
           if (c.eta.x != 0.0 || c.eta.y != 0.0) { delete p; return fail(PINTOC_EINVAL, "operator with N and N^T"); }
           c.eta = c.etat;
@@ -739,19 +814,31 @@ extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_
     if (opt.smoother == PINTOC_SMOOTHER_GLOBAL) {
       m->global = true;
       for (int l = 0; l < nl; ++l)
-        for (const OpCoef& c0 : m->coef_h) m->coefg_h.push_back(m->level_coef(c0, l));
+        for (int set = 0; set < m->ncoef; ++set) m->coefg_h.push_back(m->level_coef(set, l));
     }
     const std::vector<double>* cc = (oseen && m->q2) ? &p->conv2_h[nl - 1] : nullptr;
-    for (const OpCoef& c : m->coef_h)
-      if (!coarse_inverse(m->q2, m->level_coef(c, nl - 1), cc, m->inv_h)) {
+    for (int set = 0; set < m->ncoef; ++set)
+      if (!coarse_inverse(m->q2, m->level_coef(set, nl - 1), cc, m->inv_h)) {
         delete p;
         return fail(PINTOC_EINVAL, "singular coarse operator");
       }
   }
+  p->mem_on.assign(nm, 1);
+  p->freq_on.assign(p->nf, 1);
   carve(p, nullptr);
   byte_model(p);
   *out = p;
   return PINTOC_OK;
+}
+
+extern "C" int pintoc_problem_create(const pintoc_problem_desc* d, const pintoc_options* o, pintoc_problem** out) {
+  return create_impl(d, 1, o, out);
+}
+
+extern "C" int pintoc_group_create(const pintoc_problem_desc* d, int32_t n, const pintoc_options* o,
+                                   pintoc_problem** out) {
+  if (n < 1) return fail(PINTOC_EINVAL, "a group needs at least one member");
+  return create_impl(d, n, o, out);
 }
 
 extern "C" size_t pintoc_workspace_bytes(const pintoc_problem* p) { return p ? p->need : 0; }
@@ -836,6 +923,10 @@ static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s) 
   // zero every buffer once: padded boundaries of all grids stay zero afterwards
   launch_fill_zero(s, (char*)dev, (p->need + 15) & ~(size_t)15);
   HIPCHK(hipMemcpyAsync(p->tw, p->tw_h.data(), sizeof(double2) * p->tw_h.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->ftau, p->ftau_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->finvtau, p->finvtau_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->fbeta, p->fbeta_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->fnu, p->fnu_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->tj, p->tj_h.data(), sizeof(double2) * p->tj_h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->ab, p->ab_h.data(), sizeof(double2) * p->ab_h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->cj, p->cj_h.data(), sizeof(double2) * p->cj_h.size(), hipMemcpyHostToDevice, s));
@@ -876,14 +967,11 @@ static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s) 
                             hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsi, p->cpsi_h.data(), sizeof(OpCoef) * p->cpsi_h.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->cpsih, p->cpsih_h.data(), sizeof(OpCoef) * p->cpsih_h.size(), hipMemcpyHostToDevice, s));
-    const double tau = p->tau;
-    p->cscal_h[0] = mkcoef(tau, 0.0);
-    p->cscal_h[1] = mkcoef(tau / p->d.beta, 0.0);
-    p->cscal_h[2] = mkcoef(1.0, 0.0);
-    HIPCHK(hipMemcpyAsync(p->cscal, p->cscal_h, sizeof(p->cscal_h), hipMemcpyHostToDevice, s));
+    for (int q = 0; q < 3; ++q)
+      HIPCHK(hipMemcpyAsync(p->cscal + (size_t)q * p->nf, p->cscal_h[q].data(), sizeof(OpCoef) * p->nf,
+                            hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->dj, p->dj_h.data(), sizeof(double2) * p->dj_h.size(), hipMemcpyHostToDevice, s));
-    p->abO_h = make_double2(-1.0 / (tau * tau), 0.0);
-    HIPCHK(hipMemcpyAsync(p->abO, &p->abO_h, sizeof(double2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->abO, p->abO_h.data(), sizeof(double2) * p->nf, hipMemcpyHostToDevice, s));
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -935,7 +1023,8 @@ static void phase_sum(pintoc_problem* p, double out[PINTOC_NPHASES]) {
 static void byte_model(pintoc_problem* p) {
   const double cs = (double)p->csize, nf = p->nf;
   const double V = 4.0 * nf * p->nq2 * cs, P = 2.0 * nf * p->np2 * cs, H = V / 2.0;
-  const double C = 8.0 * (double)p->n_all;
+  double C = 0.0;                        // the canonical vectors of all members
+  for (const Member& mb : p->mem) C += 8.0 * (double)mb.n_all;
   const int c = p->o.n_vcycles, k = p->o.n_cheb;
   const double mg2 = (8.5 * c - 1.0) * 4.0 / 3.0, mg1 = (10.5 * c - 1.0) * 4.0 / 3.0, ch = 4.0 * k - 3.0;
   double block;
@@ -1087,7 +1176,7 @@ template <typename R>
 static void puz(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP, cpx<R>* outV,
                 cpx<R>* outP) {
   const int nf = p->nf, N = p->d.N, cyc = p->o.n_vcycles;
-  const double tau = p->tau, h = 1.0 / N;
+  const double h = 1.0 / N;
   const size_t nh = (size_t)2 * nf * p->nq2;                  // complex entries of one velocity block
   cpx<R>*B1 = (cpx<R>*)p->B1, *B2 = (cpx<R>*)p->B2, *X1 = (cpx<R>*)p->X1, *X2 = (cpx<R>*)p->X2;
   cpx<R>*T1 = (cpx<R>*)p->T1, *T2 = (cpx<R>*)p->T2, *Rb = (cpx<R>*)p->Rb;
@@ -1100,32 +1189,32 @@ static void puz(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R
   const R *cvN = (const R*)p->tconv[0][0], *cvNT = (const R*)p->tconv[1][0];
   for (int k = 0; k < p->o.n_uzawa; ++k) {
     // x1 += tau^{-1} M^^{-1} (b1 - tau M x1 - Psi^H x2)
-    launch_apply<R>(s, true, T1, X1, N, h, p->cscal + 0, 2 * nf, 2 * nf, nullptr, m2);
+    launch_apply<R>(s, true, T1, X1, N, h, p->cscal + 0 * (size_t)nf, 2, 2 * nf, nullptr, m2);
     launch_apply<R>(s, true, T2, X2, N, h, p->cpsih, 2, 2 * nf, cvNT, m2);
-    launch_combine3<R>(s, Rb, B1, T1, T2, 1.0, -1.0, -1.0, nh, nq2, m2);
+    launch_combine3<R>(s, Rb, B1, T1, T2, 1.0, -1.0, -1.0, nullptr, nh, nq2, m2);
     cpx<R>* c = chebyshev<R>(s, true, N, 2 * nf, (cpx<R>*)p->C1, (cpx<R>*)p->C2, Rb, p->o.n_cheb, 0.25, 25.0 / 16.0,
                              m2);
-    launch_combine3<R>(s, X1, X1, c, nullptr, 1.0, 1.0 / tau, 0.0, nh, nq2, m2);
+    launch_combine3<R>(s, X1, X1, c, nullptr, 1.0, 1.0, 0.0, p->finvtau, nh, nq2, m2);   // 1/tau_j
     // x2 -= mu^{-1} S^^{-1} (b2 - Psi x1 + tau/beta M x2)
     launch_apply<R>(s, true, T1, X1, N, h, p->cpsi, 2, 2 * nf, cvN, m2);
-    launch_apply<R>(s, true, T2, X2, N, h, p->cscal + 1, 2 * nf, 2 * nf, nullptr, m2);
-    launch_combine3<R>(s, Rb, B2, T1, T2, 1.0, -1.0, 1.0, nh, nq2, m2);
+    launch_apply<R>(s, true, T2, X2, N, h, p->cscal + 1 * (size_t)nf, 2, 2 * nf, nullptr, m2);
+    launch_combine3<R>(s, Rb, B2, T1, T2, 1.0, -1.0, 1.0, nullptr, nh, nq2, m2);
     mg_solve<R>(s, p->mgQ, T1, Rb, cyc);                                   // Q_j^{-1}
-    launch_apply<R>(s, true, T2, T1, N, h, p->cscal + 2, 2 * nf, 2 * nf, nullptr, m2);   // M
+    launch_apply<R>(s, true, T2, T1, N, h, p->cscal + 2 * (size_t)nf, 2, 2 * nf, nullptr, m2);   // M
     mg_solve<R>(s, p->mgQH, T1, T2, cyc);                                  // Q_j^{-H}
-    launch_combine3<R>(s, X2, X2, T1, nullptr, 1.0, -tau / p->o.mu_uzawa, 0.0, nh, nq2, m2);
+    launch_combine3<R>(s, X2, X2, T1, nullptr, 1.0, -1.0 / p->o.mu_uzawa, 0.0, p->ftau, nh, nq2, m2);
   }
   launch_block_copy<R>(s, outV, X1, N, nf, 0, 1, m2);
   launch_block_copy<R>(s, outV, X2, N, nf, 1, 1, m2);
   // Schur step on the pressure fields
   cpx<R>*Pt = (cpx<R>*)p->Pt, *Ub = (cpx<R>*)p->Ub, *z = (cpx<R>*)p->Ptmp;
-  launch_schur_rhs<R>(s, Pt, inP, X1, X2, N, nf, tau, m2);       // (r3 - tau B y2, r4 - tau B y1)
+  launch_schur_rhs<R>(s, Pt, inP, X1, X2, N, nf, p->ftau, m2);   // (r3 - tau B y2, r4 - tau B y1)
   launch_unpin_copy<R>(s, z, Pt, p->np2, 2 * nf, m2);
   cpx<R>* zz = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25, m2);
-  launch_oseen_hp<R>(s, Ub, zz, N, nf, p->dj, tau, p->d.beta, p->d.nu, p->conv1, p->mk(1));
+  launch_oseen_hp<R>(s, Ub, zz, N, nf, p->dj, p->ftau, p->fbeta, p->fnu, p->conv1, p->mk(1));
   launch_unpin_copy<R>(s, z, Ub, p->np2, 2 * nf, m2);
   mg_solve<R>(s, p->mgK, (cpx<R>*)p->PxK, z, cyc);
-  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, (cpx<R>*)p->PxK, p->abO, 2 * nf, p->np2, 2 * nf, m2);
+  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, (cpx<R>*)p->PxK, p->abO, 2, p->np2, 2 * nf, m2);
 }
 
 // block preconditioner of the flow: P~_j (Stokes) or P~_j^(UZ) (Oseen)
@@ -1142,7 +1231,35 @@ static void block_matvec(pintoc_problem* p, hipStream_t s, cpx<R>* yV, cpx<R>* y
                          const cpx<R>* xP) {
   const bool oseen = p->d.flow == PINTOC_OSEEN;
   launch_block_mat<R>(s, yV, yP, xV, xP, p->d.N, p->nf, p->bc, oseen ? (const R*)p->tconv[0][0] : nullptr,
-                      oseen ? (const R*)p->tconv[1][0] : nullptr, p->block_scale, p->mk(2));
+                      oseen ? (const R*)p->tconv[1][0] : nullptr, p->mk(2));
+}
+
+// Group members sitting out an application (converged ones): their
+// frequencies are masked in every block kernel of the linear preconditioner.
+static int member_mask(pintoc_problem* p, hipStream_t s) {
+  bool all = true;
+  for (int v : p->freq_on) all &= v != 0;
+  if (all) return PINTOC_OK;
+  p->mask_h = p->freq_on;
+  HIPCHK(hipMemcpyAsync(p->maskd, p->mask_h.data(), sizeof(int) * p->nf, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  p->cur_mask = p->maskd;
+  int on_count = 0;
+  for (int v : p->freq_on) on_count += v != 0;
+  for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) { m->mask = p->maskd; m->active = on_count * m->fpj; }
+  return PINTOC_OK;
+}
+
+static void clear_member_mask(pintoc_problem* p) {
+  p->cur_mask = nullptr;
+  for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) { m->mask = nullptr; m->active = m->nb; }
+}
+
+// share of the batch's frequencies taking part (byte model)
+static double active_fraction(const pintoc_problem* p) {
+  int on = 0;
+  for (int v : p->freq_on) on += v != 0;
+  return p->nf ? (double)on / p->nf : 0.0;
 }
 
 // complex Givens rotation (c real) with [c, s; -conj(s), c] [a; b] = [r; 0]
@@ -1221,7 +1338,7 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
   for (int j = 0; j < nf; ++j) {
     bnorm[j] = std::sqrt(std::max(hb[j].x, 0.0));
     rnorm[j] = bnorm[j];
-    if (!(bnorm[j] > 0)) done[j] = 1;
+    if (!(bnorm[j] > 0) || !p->freq_on[j]) done[j] = 1;     // nothing to solve, or a member sitting out
   }
   launch_fill_zero(s, XV, (size_t)segV * nf * sizeof(cpx<R>));
   launch_fill_zero(s, XP, (size_t)segP * nf * sizeof(cpx<R>));
@@ -1443,6 +1560,7 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
     }
   }
   for (int j = 0; j < nf; ++j) {
+    if (!p->freq_on[j]) continue;
     p->its_acc[j] += its[j];
     p->inner_its_sum += its[j];
     p->inner_blocks += 1;
@@ -1456,47 +1574,81 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
 // to the inner tolerance), (T_r^{-1} +) inverse FFT.  Stokes: Algorithms 1
 // and 2; Oseen: Algorithm 3 and its GMRES wrapper (section 4).
 template <typename R>
-static int precond_apply_t(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
+static int precond_apply_t(pintoc_problem* p, const double* const* r, double* const* z, hipStream_t s) {
   cpx<R>*Vb = (cpx<R>*)p->Vb, *Vx = (cpx<R>*)p->Vx, *Pb = (cpx<R>*)p->Pb, *Px = (cpx<R>*)p->Px;
   const int mode = p->d.flow == PINTOC_STOKES ? 1 : 0;
   int ph = phase_open(p, s, PINTOC_PHASE_FFT);
-  launch_time_fft_fwd<R>(s, r, Vb, Pb, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, mode);
+  for (size_t k = 0; k < p->mem.size(); ++k) {
+    if (!p->mem_on[k]) continue;
+    const Member& mb = p->mem[k];
+    launch_time_fft_fwd<R>(s, r[k], Vb + (size_t)mb.f0 * p->segV, Pb + (size_t)mb.f0 * p->segP, mb.nt, p->L, p->nq2,
+                           p->np2, p->tw + mb.tw0, p->tj + mb.f0, mb.tau, mode);
+  }
   phase_close(p, s, ph);
   ph = phase_open(p, s, PINTOC_PHASE_BLOCKS);
   if (p->o.inner == PINTOC_INNER_LINEAR) {
+    int rc = member_mask(p, s);                // group members that sit out skip every block kernel
+    if (rc) return rc;
     block_precond<R>(p, s, Vb, Pb, Vx, Px);
-    p->bytes_acc += p->model_block;
+    clear_member_mask(p);
+    p->bytes_acc += p->model_block * active_fraction(p);
   } else {
     int rc = gmres_blocks<R>(p, s);
     if (rc) return rc;
   }
   phase_close(p, s, ph);
   ph = phase_open(p, s, PINTOC_PHASE_IFFT);
-  launch_time_fft_inv<R>(s, Vx, Px, z, p->d.nt, p->L, p->nq2, p->np2, p->tw, p->tj, p->tau, mode);
+  for (size_t k = 0; k < p->mem.size(); ++k) {
+    if (!p->mem_on[k]) continue;
+    const Member& mb = p->mem[k];
+    launch_time_fft_inv<R>(s, Vx + (size_t)mb.f0 * p->segV, Px + (size_t)mb.f0 * p->segP, z[k], mb.nt, p->L, p->nq2,
+                           p->np2, p->tw + mb.tw0, p->tj + mb.f0, mb.tau, mode);
+  }
   phase_close(p, s, ph);
-  p->bytes_acc += p->model_fft;
+  p->bytes_acc += p->model_fft * active_fraction(p);
   return PINTOC_OK;
 }
 
-static int precond(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
-  // on a square of side l: P^{-1} = D_c^{-1} P'^{-1} D_r^{-1} (see pintoc_problem_create)
+// z_k = P^{-1} r_k for the members k with r[k] != NULL, in one fused
+// application (a lone problem: its one vector)
+static int precond_members(pintoc_problem* p, const double* const* r, double* const* z, hipStream_t s) {
+  const size_t nm = p->mem.size();
+  std::vector<const double*> rr(r, r + nm);
+  for (size_t k = 0; k < nm; ++k) p->mem_on[k] = r[k] != nullptr;
+  for (size_t k = 0; k < nm; ++k)
+    for (int j = 0; j < p->mem[k].nf; ++j) p->freq_on[p->mem[k].f0 + j] = p->mem_on[k];
+  // on a square of side l: P^{-1} = D_c^{-1} P'^{-1} D_r^{-1} (see create_impl; lone problems only)
   const double l = p->side;
   if (l != 1.0) {
-    launch_scale_canon(s, p->dscale, r, p->d.N, p->d.nt, 1.0 / (l * l), 1.0 / l);
-    r = p->dscale;
+    launch_scale_canon(s, p->dscale, rr[0], p->d.N, p->d.nt, 1.0 / (l * l), 1.0 / l);
+    rr[0] = p->dscale;
   }
-  int rc = p->o.precision == PINTOC_PREC_FP64 ? precond_apply_t<double>(p, r, z, s) : precond_apply_t<float>(p, r, z, s);
+  int rc = p->o.precision == PINTOC_PREC_FP64 ? precond_apply_t<double>(p, rr.data(), z, s)
+                                              : precond_apply_t<float>(p, rr.data(), z, s);
+  std::fill(p->mem_on.begin(), p->mem_on.end(), 1);
+  std::fill(p->freq_on.begin(), p->freq_on.end(), 1);
   if (rc) return rc;
-  if (l != 1.0) launch_scale_canon(s, z, z, p->d.N, p->d.nt, 1.0, l);
+  if (l != 1.0) launch_scale_canon(s, z[0], z[0], p->d.N, p->d.nt, 1.0, l);
   p->precond_apps++;
   HIPCHK(hipGetLastError());
   return PINTOC_OK;
 }
 
+static int precond(pintoc_problem* p, const double* r, double* z, hipStream_t s) {
+  return precond_members(p, &r, &z, s);
+}
+
 // ------------------------------------------------------------ public entries
-static int check_ready(pintoc_problem* p) {
+static int check_bound(pintoc_problem* p) {
   if (!p) return fail(PINTOC_EINVAL, "NULL handle");
   if (!p->bound) return fail(PINTOC_ESTATE, "no workspace bound (or its scratch binding was taken over)");
+  return PINTOC_OK;
+}
+
+static int check_ready(pintoc_problem* p) {
+  const int rc = check_bound(p);
+  if (rc) return rc;
+  if (p->group) return fail(PINTOC_EINVAL, "a group handle takes the pintoc_group_* entry points");
   return PINTOC_OK;
 }
 
@@ -1524,24 +1676,27 @@ extern "C" int pintoc_assemble_rhs_data(pintoc_problem* p, const double* vd, con
   return PINTOC_OK;
 }
 
-static void kkt(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
-  // on a square of side l: A = D_r A' D_c (see pintoc_problem_create)
+// y = A x of member k
+static void kkt_member(pintoc_problem* p, int k, const double* x, double* y, hipStream_t s) {
+  const Member& mb = p->mem[k];
+  // on a square of side l: A = D_r A' D_c (see create_impl)
   const double l = p->side;
   if (l != 1.0) {
-    launch_scale_canon(s, p->dscale, x, p->d.N, p->d.nt, 1.0, 1.0 / l);
+    launch_scale_canon(s, p->dscale, x, p->d.N, mb.nt, 1.0, 1.0 / l);
     x = p->dscale;
   }
-  launch_kkt_apply(s, x, y, p->d.N, p->d.nt, p->tau, p->d.beta, p->d.nu,
-                   p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr);
-  if (l != 1.0) launch_scale_canon(s, y, y, p->d.N, p->d.nt, l * l, l);
+  launch_kkt_apply(s, x, y, p->d.N, mb.nt, mb.tau, mb.beta, mb.nu, p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr);
+  if (l != 1.0) launch_scale_canon(s, y, y, p->d.N, mb.nt, l * l, l);
 }
 
+static void kkt(pintoc_problem* p, const double* x, double* y, hipStream_t s) { kkt_member(p, 0, x, y, s); }
+
 // the all-at-once product inside a solve: timed as its phase, counted in the byte model
-static void kkt_t(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
+static void kkt_t(pintoc_problem* p, const double* x, double* y, hipStream_t s, int k = 0) {
   const int ph = phase_open(p, s, PINTOC_PHASE_MATVEC);
-  kkt(p, x, y, s);
+  kkt_member(p, k, x, y, s);
   phase_close(p, s, ph);
-  p->bytes_acc += 2.0 * p->model_canon;
+  p->bytes_acc += 2.0 * 8.0 * (double)p->mem[k].n_all;
 }
 
 extern "C" int pintoc_kkt_apply(pintoc_problem* p, const double* x, double* y, void* stream) {
@@ -1562,8 +1717,9 @@ extern "C" int pintoc_precond_apply(pintoc_problem* p, const double* r, double* 
 
 // dots of the first k vectors of V (stride n) with w, returned on the host
 static int dots(pintoc_problem* p, hipStream_t s, const double* V, int k, const double* w, double* dev_out,
-                double* host_out) {
-  launch_mdot(s, V, (size_t)p->n_all, k, w, (size_t)p->n_all, p->part, dev_out);
+                double* host_out, size_t n = 0) {
+  if (n == 0) n = (size_t)p->n_all;
+  launch_mdot(s, V, n, k, w, n, p->part, dev_out);
   HIPCHK(hipMemcpyAsync(host_out, dev_out, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   return PINTOC_OK;
@@ -1857,6 +2013,250 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
 
 // Several problems at once: one host thread per problem, each driving its
 // problem's solve on that problem's stream.
+// ------------------------------------------------------------ groups
+// A group solves the all-at-once systems of several problems that share N,
+// the flow, the wind and the options.  Every member runs its own restarted
+// FGMRES with the operations of pintoc_solve in the same order; the members
+// advance in lockstep, and the preconditioner applications of all members
+// still iterating are one fused application (their kept frequencies form one
+// batch of every per-frequency kernel).  Each kernel and reduction acts on
+// one member's data in a fixed order, so every member's iterates equal those
+// of a lone solve bit for bit.
+struct MemberSolve {
+  double bnorm = 0, res = 0, res0 = 0;
+  int its = 0, k = 0, apps = 0, inner_max = 0;
+  bool done = false, conv = false, in_cycle = false, stalled = false, breakdown = false;
+  std::vector<double> H, cs, sn, g, y, hist;
+};
+
+static int check_member(pintoc_problem* p, int32_t k) {
+  const int rc = check_bound(p);
+  if (rc) return rc;
+  if (k < 0 || k >= (int32_t)p->mem.size()) return fail(PINTOC_EINVAL, "member index out of range");
+  return PINTOC_OK;
+}
+
+extern "C" int32_t pintoc_group_size(const pintoc_problem* p) { return p ? (int32_t)p->mem.size() : 0; }
+
+extern "C" int64_t pintoc_group_vector_length(const pintoc_problem* p, int32_t k) {
+  return (p && k >= 0 && k < (int32_t)p->mem.size()) ? p->mem[k].n_all : 0;
+}
+
+extern "C" int pintoc_group_assemble_rhs(pintoc_problem* p, int32_t k, const double* vd, double* b, void* stream) {
+  int rc = check_member(p, k);
+  if (rc) return rc;
+  if (!vd || !b) return fail(PINTOC_EINVAL, "NULL vector");
+  launch_assemble_rhs((hipStream_t)stream, vd, b, p->d.N, p->mem[k].nt, p->mem[k].tau);
+  HIPCHK(hipGetLastError());
+  return PINTOC_OK;
+}
+
+extern "C" int pintoc_group_kkt_apply(pintoc_problem* p, int32_t k, const double* x, double* y, void* stream) {
+  int rc = check_member(p, k);
+  if (rc) return rc;
+  if (!x || !y || x == y) return fail(PINTOC_EINVAL, "NULL or aliased vectors");
+  kkt_member(p, k, x, y, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return PINTOC_OK;
+}
+
+extern "C" int pintoc_group_precond_apply(pintoc_problem* p, const double* const* r, double* const* z, void* stream) {
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!r || !z) return fail(PINTOC_EINVAL, "NULL vector arrays");
+  for (size_t k = 0; k < p->mem.size(); ++k)
+    if (r[k] && (!z[k] || r[k] == z[k])) return fail(PINTOC_EINVAL, "member " + std::to_string(k) + ": NULL or aliased output");
+  return precond_members(p, r, z, (hipStream_t)stream);
+}
+
+extern "C" int pintoc_group_solve(pintoc_problem* p, const double* const* b, double* const* x, pintoc_solve_stats* st,
+                                  void* stream) {
+  int rc = check_bound(p);
+  if (rc) return rc;
+  if (!b || !x) return fail(PINTOC_EINVAL, "NULL vector arrays");
+  if (p->o.outer != PINTOC_OUTER_FGMRES) return fail(PINTOC_EINVAL, "a group solves with FGMRES");
+  const int nm = (int)p->mem.size();
+  for (int k = 0; k < nm; ++k)
+    if (!b[k] || !x[k] || b[k] == x[k]) return fail(PINTOC_EINVAL, "member " + std::to_string(k) + ": NULL or aliased vectors");
+  hipStream_t s = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int m = p->o.restart;
+  p->paused = pintoc_problem::Paused{};
+  p->precond_apps = 0;
+  p->inner_its_sum = 0;
+  p->inner_blocks = 0;
+  p->inner_its_max = 0;
+  p->bytes_acc = 0.0;
+  p->its_acc.assign(p->nf, 0);
+  p->pt.used = 0;
+  p->pt.on = true;
+  struct TimerOff {
+    pintoc_problem* q;
+    ~TimerOff() { q->pt.on = false; }
+  } timer_off{p};
+  std::vector<MemberSolve> ms(nm);
+  double hb[64], hb2[64];
+  for (int k = 0; k < nm; ++k) {
+    Member& mb = p->mem[k];
+    MemberSolve& q = ms[k];
+    const size_t n = (size_t)mb.n_all;
+    if ((rc = dots(p, s, b[k], 1, b[k], p->dd, hb, n))) return rc;
+    q.bnorm = std::sqrt(hb[0]);
+    q.H.assign((size_t)(m + 1) * m, 0.0);
+    q.cs.assign(m, 0.0); q.sn.assign(m, 0.0); q.g.assign(m + 1, 0.0); q.y.assign(m, 0.0);
+    if (q.bnorm == 0.0) {
+      launch_fill_zero(s, x[k], n * sizeof(double));
+      q.conv = q.done = true;
+      continue;
+    }
+    kkt_t(p, x[k], mb.rvec, s, k);                       // r = b - A x
+    launch_axpby(s, mb.rvec, b[k], 1.0, -1.0, n);
+    if ((rc = dots(p, s, mb.rvec, 1, mb.rvec, p->dd, hb, n))) return rc;
+    q.res = q.res0 = std::sqrt(hb[0]);
+  }
+  const double tol = p->o.tol;
+  std::vector<const double*> rr(nm);
+  std::vector<double*> zz(nm);
+  while (true) {
+    // start a restart cycle for every member between cycles
+    for (int k = 0; k < nm; ++k) {
+      MemberSolve& q = ms[k];
+      if (q.done || q.in_cycle) continue;
+      if (!std::isfinite(q.res)) { q.done = true; continue; }
+      if (q.res <= tol * q.bnorm) { q.conv = q.done = true; continue; }
+      if (q.its >= p->o.max_outer) { q.done = true; continue; }
+      const Member& mb = p->mem[k];
+      launch_axpby(s, mb.Vk, mb.rvec, 1.0 / q.res, 0.0, (size_t)mb.n_all);
+      std::fill(q.g.begin(), q.g.end(), 0.0);
+      q.g[0] = q.res;
+      q.k = 0;
+      q.breakdown = false;
+      q.in_cycle = true;
+    }
+    bool any = false;
+    for (int k = 0; k < nm; ++k) {
+      const MemberSolve& q = ms[k];
+      const Member& mb = p->mem[k];
+      const size_t n = (size_t)mb.n_all;
+      rr[k] = q.in_cycle ? mb.Vk + (size_t)q.k * n : nullptr;
+      zz[k] = q.in_cycle ? mb.Zk + (size_t)q.k * n : nullptr;
+      any |= q.in_cycle;
+    }
+    if (!any) break;
+    // one fused preconditioner application for every member in a cycle
+    if ((rc = precond_members(p, rr.data(), zz.data(), s))) return rc;
+    for (int k = 0; k < nm; ++k) {
+      MemberSolve& q = ms[k];
+      if (!q.in_cycle) continue;
+      q.apps++;
+      const Member& mb = p->mem[k];
+      for (int j = 0; j < mb.nf; ++j)
+        if ((size_t)(mb.f0 + j) < p->last_its.size()) q.inner_max = std::max(q.inner_max, p->last_its[mb.f0 + j]);
+      const size_t n = (size_t)mb.n_all;
+      const int kk = q.k;
+      double* zk = mb.Zk + (size_t)kk * n;
+      double* w = mb.Vk + (size_t)(kk + 1) * n;
+      kkt_t(p, zk, w, s, k);
+      // classical Gram-Schmidt, twice
+      const int ph = phase_open(p, s, PINTOC_PHASE_ORTH);
+      p->bytes_acc += (4.0 * kk + 13.0) * 8.0 * (double)n;
+      if ((rc = dots(p, s, mb.Vk, kk + 1, w, p->dd, hb, n))) return rc;
+      launch_mgs_update(s, w, mb.Vk, n, kk + 1, p->dd, n);
+      if ((rc = dots(p, s, mb.Vk, kk + 1, w, p->dd2, hb2, n))) return rc;
+      launch_mgs_update(s, w, mb.Vk, n, kk + 1, p->dd2, n);
+      double nrm2;
+      if ((rc = dots(p, s, w, 1, w, p->dd, &nrm2, n))) return rc;
+      const double hk1 = std::sqrt(nrm2);
+      std::vector<double>& H = q.H;
+      for (int i = 0; i <= kk; ++i) H[(size_t)i * m + kk] = hb[i] + hb2[i];
+      H[(size_t)(kk + 1) * m + kk] = hk1;
+      if (hk1 > 0) launch_axpby(s, w, w, 1.0 / hk1, 0.0, n);
+      else q.breakdown = true;
+      phase_close(p, s, ph);
+      for (int i = 0; i < kk; ++i) {
+        const double a = H[(size_t)i * m + kk], c = H[(size_t)(i + 1) * m + kk];
+        H[(size_t)i * m + kk] = q.cs[i] * a + q.sn[i] * c;
+        H[(size_t)(i + 1) * m + kk] = -q.sn[i] * a + q.cs[i] * c;
+      }
+      const double a = H[(size_t)kk * m + kk], c = H[(size_t)(kk + 1) * m + kk];
+      const double t = std::hypot(a, c);
+      q.cs[kk] = t > 0 ? a / t : 1.0;
+      q.sn[kk] = t > 0 ? c / t : 0.0;
+      H[(size_t)kk * m + kk] = t;
+      H[(size_t)(kk + 1) * m + kk] = 0.0;
+      q.g[kk + 1] = -q.sn[kk] * q.g[kk];
+      q.g[kk] = q.cs[kk] * q.g[kk];
+      ++q.its;
+      q.hist.push_back(std::fabs(q.g[kk + 1]) / q.bnorm);
+      q.stalled = p->o.stall_guard && q.its >= std::max(10, m) && std::fabs(q.g[kk + 1]) > 0.5 * q.res0;
+      const bool stop = std::fabs(q.g[kk + 1]) <= tol * q.bnorm || q.breakdown || q.stalled;
+      q.k = kk + 1;
+      if (!(stop || q.k >= m || q.its >= p->o.max_outer)) continue;
+      // end of the cycle: y = H^{-1} g, x += Z y, true residual
+      const int nk = q.k;
+      for (int i = nk - 1; i >= 0; --i) {
+        double v = q.g[i];
+        for (int j = i + 1; j < nk; ++j) v -= H[(size_t)i * m + j] * q.y[j];
+        q.y[i] = v / H[(size_t)i * m + i];
+      }
+      const int ph2 = phase_open(p, s, PINTOC_PHASE_ORTH);
+      HIPCHK(hipMemcpyAsync(p->dd, q.y.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
+      launch_lincomb_add(s, x[k], mb.Zk, n, nk, p->dd, n);
+      phase_close(p, s, ph2);
+      p->bytes_acc += (nk + 2.0 + 4.0) * 8.0 * (double)n;
+      kkt_t(p, x[k], mb.rvec, s, k);
+      launch_axpby(s, mb.rvec, b[k], 1.0, -1.0, n);
+      if ((rc = dots(p, s, mb.rvec, 1, mb.rvec, p->dd, hb, n))) return rc;
+      q.res = std::sqrt(hb[0]);
+      q.in_cycle = false;
+      if ((q.breakdown || q.stalled) && !(q.res <= tol * q.bnorm)) q.done = true;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  bool all = true;
+  for (const MemberSolve& q : ms) all &= q.conv;
+  if (st) {
+    double ph[PINTOC_NPHASES];
+    phase_sum(p, ph);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < nm; ++k) {
+      pintoc_solve_stats* o = &st[k];
+      const MemberSolve& q = ms[k];
+      const Member& mb = p->mem[k];
+      double* hist_out = o->residual_history;
+      const int hcap = o->history_capacity;
+      int32_t* cnt_out = o->inner_counts;
+      const int ccap = o->inner_counts_capacity;
+      std::memset(o, 0, sizeof(*o));
+      o->residual_history = hist_out;
+      o->history_capacity = hcap;
+      o->inner_counts = cnt_out;
+      o->inner_counts_capacity = ccap;
+      if (hist_out && hcap > 0) {
+        o->history_length = (int32_t)std::min<size_t>((size_t)hcap, q.hist.size());
+        std::copy(q.hist.begin(), q.hist.begin() + o->history_length, hist_out);
+      }
+      long isum = 0;
+      for (int j = 0; j < mb.nf; ++j) {
+        isum += p->its_acc[mb.f0 + j];
+        if (cnt_out && j < ccap) cnt_out[j] = (int32_t)p->its_acc[mb.f0 + j];
+      }
+      for (int i = 0; i < PINTOC_NPHASES; ++i) o->phase_seconds[i] = ph[i];
+      o->model_bytes = p->bytes_acc;                    // the whole group's
+      o->precond_model_bytes = (p->model_fft + p->model_block) * mb.nf / p->nf;
+      o->outer_iterations = q.its;
+      o->converged = q.conv ? 1 : 0;
+      o->rel_residual = q.bnorm > 0 ? q.res / q.bnorm : 0.0;
+      o->precond_applications = q.apps;
+      o->inner_iterations_mean = (p->o.inner == PINTOC_INNER_GMRES && q.apps > 0) ? (double)isum / ((double)q.apps * mb.nf) : 0.0;
+      o->inner_iterations_max = q.inner_max;
+      o->seconds = secs;
+    }
+  }
+  return all ? PINTOC_OK : PINTOC_NOT_CONVERGED;
+}
+
 extern "C" int pintoc_solve_batch(pintoc_problem* const* p, const double* const* b, double* const* x,
                                   pintoc_solve_stats* st, void* const* streams, int32_t n) {
   if (n < 0) return fail(PINTOC_EINVAL, "negative problem count");

@@ -165,3 +165,47 @@ def test_bind_scratch_rejects_before_gpu_work():
     assert lib.pintoc_bind_scratch(h, None) == ENOMEM
     assert b"static scratch" in lib.pintoc_last_error()
     lib.pintoc_problem_destroy(h)
+
+
+def test_group_create_validation():
+    """pintoc_group_create accepts members that differ in nt, T, nu and beta
+    and refuses members of other grids, flows, domains or winds (host only)."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2405_18964_amd._lib import EINVAL, Desc, default_options, library
+    lib = library()
+    o = default_options(inner=1)
+
+    def grp(descs, opts=o):
+        arr = (Desc * len(descs))(*descs)
+        h = ctypes.c_void_p()
+        rc = lib.pintoc_group_create(arr, len(descs), ctypes.byref(opts), ctypes.byref(h))
+        return rc, h
+
+    a = Desc(8, 16, 1.0, 1.0, 1e-2, 0, None, 0.0, 0.0, 0.0, 0.0)
+    b = Desc(8, 32, 2.0, 0.5, 1e-4, 0, None, 0.0, 0.0, 0.0, 0.0)
+    rc, h = grp([a, b])
+    assert rc == 0
+    assert lib.pintoc_group_size(h) == 2
+    assert lib.pintoc_group_vector_length(h, 1) == 2 * 32 * (2 * 17 ** 2 + 81)
+    assert lib.pintoc_group_vector_length(h, 2) == 0
+    assert lib.pintoc_kkt_apply(h, None, None, None) < 0     # unbound, and a group takes the group calls
+    lib.pintoc_problem_destroy(h)
+    assert grp([a, Desc(16, 16, 1.0, 1.0, 1e-2, 0, None, 0.0, 0.0, 0.0, 0.0)])[0] == EINVAL
+    w1 = np.ascontiguousarray(W.wind_nodal(8).reshape(-1))
+    w2 = 0.5 * w1
+    o1 = Desc(8, 16, 1.0, 0.01, 1e-2, 1, w1.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0.0)
+    o2 = Desc(8, 8, 1.0, 0.02, 1e-3, 1, w2.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0.0)
+    assert grp([a, o1])[0] == EINVAL                          # flows differ
+    assert grp([o1, o2])[0] == EINVAL                         # winds differ
+    assert b"wind" in lib.pintoc_last_error()
+    o3 = Desc(8, 8, 1.0, 0.02, 1e-3, 1, w1.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0.0)
+    rc, h = grp([o1, o3])
+    assert rc == 0
+    lib.pintoc_problem_destroy(h)
+    sq = Desc(8, 16, 1.0, 1.0, 1e-2, 0, None, -1.0, -1.0, 1.0, 1.0)
+    assert grp([sq, sq])[0] == EINVAL                         # groups on the unit square only
+    assert grp([a, b], default_options(outer=1, restart=10))[0] == EINVAL
+    h = ctypes.c_void_p()
+    assert lib.pintoc_group_create((Desc * 1)(a), 0, ctypes.byref(o), ctypes.byref(h)) == EINVAL
