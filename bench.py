@@ -76,7 +76,7 @@ def parse():
                          "4 (batched 64-problem mix) or 5 (served request stream)")
     ap.add_argument("--batch-count", type=int, default=64, help="problems of the batched mix (--config 4)")
     ap.add_argument("--workers", type=int, default=4, help="concurrent problems on the device (--config 4, 5)")
-    ap.add_argument("--fused-workers", type=int, default=2, help="concurrent fused groups (--config 4)")
+    ap.add_argument("--fused-workers", type=int, default=4, help="concurrent fused groups (--config 4)")
     ap.add_argument("--requests", type=int, default=256, help="requests of the served stream (--config 5)")
     ap.add_argument("--rho", type=str, default="0.8",
                     help="comma-separated arrival rates / capacity, one open-loop pass each (--config 5)")

@@ -78,8 +78,17 @@ enum { PINTOC_SMOOTHER_TILED = 0, PINTOC_SMOOTHER_GLOBAL = 1 };
  * MINRES applies to the Stokes problem with the linear preconditioner
  * (Algorithm 1): the all-at-once matrix of eq. (FinalA) is symmetric and the
  * preconditioner symmetric positive definite (section 3.3), so a short
- * recurrence replaces the Arnoldi basis. */
-enum { PINTOC_OUTER_FGMRES = 0, PINTOC_OUTER_MINRES = 1 };
+ * recurrence replaces the Arnoldi basis.
+ * FGMRES_FREQ runs FGMRES in the frequency domain (section 3.1, Theorem 1):
+ * with A = P_C + U (U the rank-2 n_v corner term coupling the first and last
+ * time steps), the Fourier-transformed matrix is diag(G_j) plus that corner
+ * term, which needs two time samples of the velocity spread over all
+ * frequencies; the Krylov vectors are the kept spectra scaled by
+ * sqrt(w_j / nt) (w = 1 at j = 0 and nt/2, 2 otherwise), so their Euclidean
+ * inner product is the time-domain one.  b is transformed once and x back
+ * once: the iterations run no FFT.  Single problems on the unit square only,
+ * FP64 inner solves for Oseen (EINVAL otherwise). */
+enum { PINTOC_OUTER_FGMRES = 0, PINTOC_OUTER_MINRES = 1, PINTOC_OUTER_FGMRES_FREQ = 2 };
 
 /* Problem of section 2 (eq. OseenOptimization / OseenFlow) on a square
  * domain [x0, x1] x [y0, y1] (all four zero: the unit square; section 5 uses

@@ -97,3 +97,31 @@ def pc_apply_direct(P, r: np.ndarray) -> np.ndarray:
     """P_C^{-1} r by a sparse LU of the assembled P_C (E replaced by C)."""
     A = P.kkt_matrix(time_matrix=circulant_C(P.nt)).tocsc()
     return spla.splu(A).solve(np.asarray(r, float))
+
+
+def freq_domain_apply(P, Xh: np.ndarray) -> np.ndarray:
+    """A^ X^ = (F A F^{-1}) X^ for a transformed vector X^ of shape (2, nt, n)
+    (all nt frequencies), written as Theorem 1's split A = P_C + U (section
+    3.1): the diagonal blocks G_j of P_C act frequency by frequency, and the
+    corner term U, which is all that E and C differ by (E - C has its one entry
+    1 at row 0, column nt - 1), adds M v_{nt-1} to the state momentum rows of
+    time step 0 and M lambda_0 to the adjoint momentum rows of step nt - 1
+    (E^T - C^T).  In the Fourier basis those rows become all frequencies: the
+    state rows of frequency j get M v_{nt-1} (the DFT of e_0 is all ones), the
+    adjoint rows exp(2 pi i j / nt) M lambda_0 (the DFT of e_{nt-1}), where
+    v_{nt-1} and lambda_0 are time samples of the inverse transform."""
+    nt, nv = P.nt, P.nv
+    d = d_closed_form(nt)
+    Yh = np.empty_like(Xh, dtype=complex)
+    for j in range(nt):
+        x1, x2, x3, x4 = split_freq(P, Xh[:, j, :])
+        y = G_block(P, d[j]) @ np.concatenate([x1, x2, x3, x4])
+        Yh[:, j, :] = join_freq(P, y[:nv], y[nv:2 * nv], y[2 * nv:2 * nv + P.nP], y[2 * nv + P.nP:])
+    x_t = np.fft.ifft(Xh, axis=1)                   # time samples
+    v_last = x_t[0, nt - 1, :nv]                    # v at the last step
+    lam_first = x_t[1, 0, :nv]                      # lambda at the first step
+    Mv, Ml = P.ops.M @ v_last, P.ops.M @ lam_first
+    ph = np.exp(2j * np.pi * np.arange(nt) / nt)
+    Yh[1, :, :nv] += Mv[None, :]
+    Yh[0, :, :nv] += ph[:, None] * Ml[None, :]
+    return Yh

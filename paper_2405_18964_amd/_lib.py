@@ -10,7 +10,7 @@ _LIB_PATH = os.path.join(HERE, "libpintoc.so")
 STOKES, OSEEN = 0, 1
 INNER_LINEAR, INNER_GMRES = 0, 1
 PREC_FP64, PREC_FP32_INNER = 0, 1
-OUTER_FGMRES, OUTER_MINRES = 0, 1
+OUTER_FGMRES, OUTER_MINRES, OUTER_FGMRES_FREQ = 0, 1, 2
 SMOOTHER_TILED, SMOOTHER_GLOBAL = 0, 1
 OK, NOT_CONVERGED, PAUSED = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ESTATE = -1, -2, -3, -4

@@ -199,14 +199,17 @@ def _member_of(job):
 
 
 def autotune(jobs, sizes=(1, 2, 4, 8, 16), smoothers=None, budget_bytes=None, device="cuda", reps=2,
-             **options) -> dict:
+             keep: float = 0.85, **options) -> dict:
     """Pick, per class of jobs with the same (N, flow), the group size and the
     smoother of the fused form by measurement: for every candidate that fits
     the memory budget, one group of that many of the class's jobs (linear
     preconditioner, the options' precision) applies its fused preconditioner
-    ``reps`` times; the candidate with the most member applications per
-    second wins, the smaller group on ties within 5 % (a smaller group wastes
-    less when its members converge at different iterations).  Returns
+    ``reps`` times.  The pick is the smallest group whose member applications
+    per second reach ``keep`` times the best candidate's: the fused
+    application runs beside other groups on other streams, and a group's
+    members converge at different outer iterations (those that finish sit
+    out while the rest iterate), so beyond the knee a larger group gains
+    little throughput and loses concurrency.  Returns
     {(N, flow): {"size", "smoother", "trials": [...]}}."""
     import numpy as np
     import torch
@@ -251,7 +254,7 @@ def autotune(jobs, sizes=(1, 2, 4, 8, 16), smoothers=None, budget_bytes=None, de
                 del grp, rs
                 torch.cuda.empty_cache()
         best = max(t["member_apps_per_s"] for t in trials)
-        pick = min((t for t in trials if t["member_apps_per_s"] >= 0.95 * best),
+        pick = min((t for t in trials if t["member_apps_per_s"] >= keep * best),
                    key=lambda t: (t["size"], t["smoother"]))
         out[key] = {"size": pick["size"], "smoother": pick["smoother"], "trials": trials}
     return out

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpintoc.so")
 SOURCES = ["pintoc.hip", "fft_kernels.hip", "mg_kernels.hip", "kkt_kernels.hip", "inner_kernels.hip", "oseen_kernels.hip",
-           "q2_tiles.hip"]
+           "q2_tiles.hip", "freq_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

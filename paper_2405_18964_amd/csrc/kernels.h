@@ -110,6 +110,15 @@ void launch_axpbypcz(hipStream_t s, double* y, const double* x, const double* z,
 void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, int k, const double* c, size_t n);
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
 
+// outer Krylov method in the frequency domain (freq_kernels.hip)
+void launch_freq_scale(hipStream_t s, double2* y, const double2* x, const double* f, int nf, int segV, int segP);
+template <typename R>
+void launch_freq_convert(hipStream_t s, const double2* xo, cpx<R>* V, cpx<R>* P, double2* yo, int nf, int nq2,
+                         int np2, const double2* tj, double tau, int mode, int dir);
+// y += the corner term of A^ applied to x (tmp: 8 (2N+1)^2 doubles)
+void launch_freq_corner(hipStream_t s, double2* yV, const double2* xV, double* tmp, const double* sj, int n, int nf,
+                        int nt);
+
 // per-frequency GMRES vector operations (inner_kernels.hip)
 template <typename R>
 void launch_fdot(hipStream_t s, const cpx<R>* bV, const cpx<R>* bP, size_t ldV, size_t ldP, int k, const cpx<R>* wV,

@@ -198,8 +198,19 @@ struct pintoc_problem {
   double *dd = nullptr, *dd2 = nullptr, *part = nullptr;
   bool bound = false;
   double side = 1.0;                    // side of the square domain (section 5: [-1, 1]^2 has 2)
+  // frequency-domain FGMRES: outer vector length (reals), b~, scalings s_j and
+  // 1/s_j, scratch of the corner term, the G_j coefficients (Stokes)
+  int64_t nF = 0;
+  double *fb = nullptr, *fsc = nullptr, *fisc = nullptr, *ftmp = nullptr;
+  std::vector<double> fsc_h, fisc_h;
+  std::vector<BlockCoef> gc_h;
+  BlockCoef* gcoef = nullptr;
   double* dscale = nullptr;             // one canonical vector for the domain scaling (side != 1 only)
   int scratch_dev = -1;                 // device whose static scratch is bound (pintoc_bind_scratch), or -1
+  // side stream of the Stokes preconditioner (pressure part beside the
+  // velocity multigrid) and its fork/join events; default priority
+  hipStream_t pstream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // statistics
   int precond_apps = 0;
   // a solve paused at a restart boundary (pintoc_solve_stats.cycle_budget):
@@ -418,8 +429,9 @@ static void carve(pintoc_problem* p, char* base) {
   }
   plan_mg_buffers(p->mgK, cv, p->csize);
   const int m = p->o.restart;
+  const bool freq = p->o.outer == PINTOC_OUTER_FGMRES_FREQ;
   for (Member& mb : p->mem) {
-    const size_t vb = sizeof(double) * (size_t)mb.n_all;
+    const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(mb.n_all, freq ? p->nF : 0);
     mb.Vk = cv.take<double>(vb * (m + 1));
     mb.Zk = cv.take<double>(vb * m);
     mb.rvec = cv.take<double>(vb);
@@ -430,6 +442,13 @@ static void carve(pintoc_problem* p, char* base) {
   p->rvec = p->mem[0].rvec;
   p->xtmp = p->mem[0].xtmp;
   p->dscale = p->side != 1.0 ? cv.take<double>(sizeof(double) * (size_t)p->n_all) : nullptr;
+  if (freq) {
+    p->fb = cv.take<double>(sizeof(double) * (size_t)p->nF);
+    p->fsc = cv.take<double>(sizeof(double) * nf);
+    p->fisc = cv.take<double>(sizeof(double) * nf);
+    p->ftmp = cv.take<double>(sizeof(double) * 8 * (size_t)p->nq2);
+    p->gcoef = cv.take<BlockCoef>(sizeof(BlockCoef) * nf);
+  }
   p->dd = cv.take<double>(sizeof(double) * 64);
   p->dd2 = cv.take<double>(sizeof(double) * 64);
   p->part = cv.take<double>(sizeof(double) * 8 * 1024);
@@ -636,8 +655,12 @@ static int create_impl(const pintoc_problem_desc* ds, int nm, const pintoc_optio
   if (opt.restart < 1 || opt.restart > 60 || opt.max_outer < 1 || !(opt.tol > 0) || opt.n_vcycles < 1 ||
       opt.n_cheb < 1 || (opt.stall_guard != 0 && opt.stall_guard != 1))
     return fail(PINTOC_EINVAL, "invalid solver options");
-  if (opt.outer != PINTOC_OUTER_FGMRES && opt.outer != PINTOC_OUTER_MINRES)
+  if (opt.outer != PINTOC_OUTER_FGMRES && opt.outer != PINTOC_OUTER_MINRES && opt.outer != PINTOC_OUTER_FGMRES_FREQ)
     return fail(PINTOC_EINVAL, "unknown outer method");
+  if (opt.outer == PINTOC_OUTER_FGMRES_FREQ &&
+      (nm > 1 || side != 1.0 || (d->flow == PINTOC_OSEEN && opt.precision != PINTOC_PREC_FP64)))
+    return fail(PINTOC_EINVAL, "the frequency-domain FGMRES needs a single problem on the unit square "
+                               "(and FP64 for Oseen)");
   if (opt.smoother != PINTOC_SMOOTHER_TILED && opt.smoother != PINTOC_SMOOTHER_GLOBAL)
     return fail(PINTOC_EINVAL, "unknown smoother");
   if (opt.outer == PINTOC_OUTER_MINRES &&
@@ -825,6 +848,27 @@ static int create_impl(const pintoc_problem_desc* ds, int nm, const pintoc_optio
   }
   p->mem_on.assign(nm, 1);
   p->freq_on.assign(p->nf, 1);
+  if (opt.outer == PINTOC_OUTER_FGMRES_FREQ) {
+    const Member& mb = p->mem[0];
+    p->nF = (int64_t)2 * p->nf * (p->segV + p->segP);
+    for (int j = 0; j < p->nf; ++j) {
+      const double w = (j == 0 || 2 * j == mb.nt) ? 1.0 : 2.0;
+      p->fsc_h.push_back(std::sqrt(w / mb.nt));
+      p->fisc_h.push_back(1.0 / std::sqrt(w / mb.nt));
+      // G_j of eq. (SubBlockG) for Stokes (no convection): the pattern of
+      // oseen_kernels.hip with a11 = tau, a12 = conj(d), b = tau nu, a22 = -tau/beta, s = tau
+      const double th = 2.0 * M_PI * j / mb.nt;
+      BlockCoef g{};
+      g.a11 = make_double2(mb.tau, 0.0);
+      g.a12 = make_double2(1.0 - std::cos(th), -std::sin(th));
+      g.b12 = make_double2(mb.tau * mb.nu, 0.0);
+      g.a21 = make_double2(1.0 - std::cos(th), std::sin(th));
+      g.b21 = make_double2(mb.tau * mb.nu, 0.0);
+      g.a22 = make_double2(-mb.tau / mb.beta, 0.0);
+      g.s = mb.tau;
+      p->gc_h.push_back(g);
+    }
+  }
   carve(p, nullptr);
   byte_model(p);
   *out = p;
@@ -868,6 +912,12 @@ static void scratch_release(pintoc_problem* p) {
 extern "C" void pintoc_problem_destroy(pintoc_problem* p) {
   if (!p) return;
   scratch_release(p);
+  if (p->pstream) {
+    (void)hipStreamSynchronize(p->pstream);
+    (void)hipStreamDestroy(p->pstream);
+  }
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   delete p;
 }
 
@@ -917,6 +967,11 @@ extern "C" int pintoc_bind_scratch(pintoc_problem* p, void* stream) {
 // carve the workspace, clear it and upload the tables on stream s
 static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s) {
   p->bound = false;
+  if (p->d.flow == PINTOC_STOKES && !p->pstream) {
+    HIPCHK(hipStreamCreateWithFlags(&p->pstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  }
   p->ws = dev;
   p->ws_bytes = bytes;
   carve(p, (char*)dev);
@@ -927,6 +982,11 @@ static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s) 
   HIPCHK(hipMemcpyAsync(p->finvtau, p->finvtau_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->fbeta, p->fbeta_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->fnu, p->fnu_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
+  if (p->fsc) {
+    HIPCHK(hipMemcpyAsync(p->fsc, p->fsc_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->fisc, p->fisc_h.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->gcoef, p->gc_h.data(), sizeof(BlockCoef) * p->nf, hipMemcpyHostToDevice, s));
+  }
   HIPCHK(hipMemcpyAsync(p->tj, p->tj_h.data(), sizeof(double2) * p->tj_h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->ab, p->ab_h.data(), sizeof(double2) * p->ab_h.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->cj, p->cj_h.data(), sizeof(double2) * p->cj_h.size(), hipMemcpyHostToDevice, s));
@@ -1155,16 +1215,31 @@ static cpx<R>* chebyshev(hipStream_t s, bool q2, int n, int nb, cpx<R>* A, cpx<R
 // velocity fields, S^_j^{-1} = R L [(1+c1) K_N^+ + nu c2 M_N^{-1}] L^T R^T on
 // the pressure fields.  in and out must not alias.
 template <typename R>
+// The pressure part (K_N multigrid, M_N Chebyshev) and the velocity part
+// (W_j multigrid) touch disjoint buffers: the pressure part runs on the
+// problem's side stream, forked from s after the inputs and joined before
+// the outputs are used, so its small latency-bound Q1 launches overlap the
+// velocity V-cycles (the results do not depend on the overlap).
 static void ptilde(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP, cpx<R>* outV,
                    cpx<R>* outP) {
   const int nf = p->nf, cyc = p->o.n_vcycles, N = p->d.N;
-  mg_solve<R>(s, p->mgW, outV, inV, cyc);
+  hipStream_t ps = s;
+  if (p->pstream) {
+    (void)hipEventRecord(p->ev_fork, s);
+    (void)hipStreamWaitEvent(p->pstream, p->ev_fork, 0);
+    ps = p->pstream;
+  }
   cpx<R>* z = (cpx<R>*)p->Ptmp;
-  launch_unpin_copy<R>(s, z, inP, p->np2, 2 * nf, p->mk(2));
-  mg_solve<R>(s, p->mgK, (cpx<R>*)p->PxK, z, cyc);
-  cpx<R>* ym = chebyshev<R>(s, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25,
+  launch_unpin_copy<R>(ps, z, inP, p->np2, 2 * nf, p->mk(2));
+  mg_solve<R>(ps, p->mgK, (cpx<R>*)p->PxK, z, cyc);
+  cpx<R>* ym = chebyshev<R>(ps, false, N, 2 * nf, (cpx<R>*)p->PxM, (cpx<R>*)p->PxM2, z, p->o.n_cheb, 0.25, 2.25,
                             p->mk(2));
-  launch_schur_combine_pin<R>(s, outP, (cpx<R>*)p->PxK, ym, p->ab, 2, p->np2, 2 * nf, p->mk(2));
+  launch_schur_combine_pin<R>(ps, outP, (cpx<R>*)p->PxK, ym, p->ab, 2, p->np2, 2 * nf, p->mk(2));
+  mg_solve<R>(s, p->mgW, outV, inV, cyc);
+  if (p->pstream) {
+    (void)hipEventRecord(p->ev_join, p->pstream);
+    (void)hipStreamWaitEvent(s, p->ev_join, 0);
+  }
 }
 
 // P~_j^(UZ)^{-1} of Algorithm 3 (Oseen) on a frequency vector, all kept
@@ -1824,6 +1899,159 @@ static int solve_minres(pintoc_problem* p, const double* b, double* x, double bn
   }
 }
 
+// FGMRES in the frequency domain (section 3.1, Theorem 1): the Krylov vectors
+// are the scaled kept-frequency spectra (freq_kernels.hip); the operator is
+// A^ = diag(G_j) + corner term, the preconditioner the block solves alone, so
+// neither needs an FFT: b is transformed once at the start and x once at the
+// end.  The operations and stopping rule are those of pintoc_solve's FGMRES;
+// the reported residual is the time-domain one of the transformed-back x.
+static void matvec_freq(pintoc_problem* p, const double* x, double* y, hipStream_t s) {
+  const int ph = phase_open(p, s, PINTOC_PHASE_MATVEC);
+  const int nf = p->nf;
+  const double2 *xV = (const double2*)x, *xP = xV + (size_t)nf * p->segV;
+  double2 *yV = (double2*)y, *yP = yV + (size_t)nf * p->segV;
+  const bool oseen = p->d.flow == PINTOC_OSEEN;
+  launch_block_mat<double>(s, yV, yP, xV, xP, p->d.N, nf, oseen ? p->bc : p->gcoef,
+                           oseen ? (const double*)p->tconv[0][0] : nullptr,
+                           oseen ? (const double*)p->tconv[1][0] : nullptr, kAll);
+  launch_freq_corner(s, yV, xV, p->ftmp, p->fsc, p->d.N, nf, p->d.nt);
+  phase_close(p, s, ph);
+  p->bytes_acc += 2.0 * 8.0 * (double)p->nF + 3.0 * 0.5 * 8.0 * (double)p->nF;
+}
+
+template <typename R>
+static int precond_freq_t(pintoc_problem* p, const double* v, double* z, hipStream_t s) {
+  cpx<R>*Vb = (cpx<R>*)p->Vb, *Vx = (cpx<R>*)p->Vx, *Pb = (cpx<R>*)p->Pb, *Px = (cpx<R>*)p->Px;
+  const int mode = p->d.flow == PINTOC_STOKES ? 1 : 0;
+  int ph = phase_open(p, s, PINTOC_PHASE_FFT);           // the T_l^{-1} transform in place of the FFT
+  launch_freq_convert<R>(s, (const double2*)v, Vb, Pb, nullptr, p->nf, p->nq2, p->np2, p->tj, p->tau, mode, 0);
+  phase_close(p, s, ph);
+  ph = phase_open(p, s, PINTOC_PHASE_BLOCKS);
+  if (p->o.inner == PINTOC_INNER_LINEAR) {
+    block_precond<R>(p, s, Vb, Pb, Vx, Px);
+    p->bytes_acc += p->model_block;
+  } else {
+    int rc = gmres_blocks<R>(p, s);
+    if (rc) return rc;
+  }
+  phase_close(p, s, ph);
+  ph = phase_open(p, s, PINTOC_PHASE_IFFT);
+  launch_freq_convert<R>(s, nullptr, Vx, Px, (double2*)z, p->nf, p->nq2, p->np2, p->tj, p->tau, mode, 1);
+  phase_close(p, s, ph);
+  p->bytes_acc += 2.0 * (p->model_fvec + 8.0 * (double)p->nF);
+  p->precond_apps++;
+  HIPCHK(hipGetLastError());
+  return PINTOC_OK;
+}
+
+static int precond_freq(pintoc_problem* p, const double* v, double* z, hipStream_t s) {
+  return p->o.precision == PINTOC_PREC_FP64 ? precond_freq_t<double>(p, v, z, s) : precond_freq_t<float>(p, v, z, s);
+}
+
+static int solve_freq(pintoc_problem* p, const double* b, double* x, double bnorm, hipStream_t s, int& its,
+                      double& res, bool& conv, std::vector<double>& hist) {
+  const size_t n = (size_t)p->nF;
+  const int m = p->o.restart, nf = p->nf;
+  const Member& mb = p->mem[0];
+  double hb[64], hb2[64];
+  int rc;
+  // b~ = s F b and x~ = s F x (forward FFT without the T transforms)
+  double2 *fb = (double2*)p->fb, *fx = (double2*)mb.xtmp;
+  int ph = phase_open(p, s, PINTOC_PHASE_FFT);
+  launch_time_fft_fwd<double>(s, b, fb, fb + (size_t)nf * p->segV, mb.nt, p->L, p->nq2, p->np2, p->tw, p->tj, mb.tau, 0);
+  launch_freq_scale(s, fb, fb, p->fsc, nf, p->segV, p->segP);
+  launch_time_fft_fwd<double>(s, x, fx, fx + (size_t)nf * p->segV, mb.nt, p->L, p->nq2, p->np2, p->tw, p->tj, mb.tau, 0);
+  launch_freq_scale(s, fx, fx, p->fsc, nf, p->segV, p->segP);
+  phase_close(p, s, ph);
+  double* rv = mb.rvec;
+  double* xf = mb.xtmp;
+  auto residual = [&]() -> int {                         // r~ = b~ - A^ x~, res = ||r~||
+    matvec_freq(p, xf, rv, s);
+    launch_axpby(s, rv, p->fb, 1.0, -1.0, n);
+    int r = dots(p, s, rv, 1, rv, p->dd, hb, n);
+    if (r) return r;
+    res = std::sqrt(hb[0]);
+    return PINTOC_OK;
+  };
+  if ((rc = residual())) return rc;
+  const double res0 = res;
+  bool stalled = false;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (true) {
+    if (!std::isfinite(res)) break;
+    if (res <= p->o.tol * bnorm) { conv = true; break; }
+    if (its >= p->o.max_outer) break;
+    launch_axpby(s, mb.Vk, rv, 1.0 / res, 0.0, n);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = res;
+    int k = 0;
+    bool breakdown = false;
+    for (; k < m && its < p->o.max_outer; ++k) {
+      double* vk = mb.Vk + (size_t)k * n;
+      double* zk = mb.Zk + (size_t)k * n;
+      double* w = mb.Vk + (size_t)(k + 1) * n;
+      if ((rc = precond_freq(p, vk, zk, s))) return rc;
+      matvec_freq(p, zk, w, s);
+      const int ph2 = phase_open(p, s, PINTOC_PHASE_ORTH);
+      p->bytes_acc += (4.0 * k + 13.0) * 8.0 * (double)n;
+      if ((rc = dots(p, s, mb.Vk, k + 1, w, p->dd, hb, n))) return rc;
+      launch_mgs_update(s, w, mb.Vk, n, k + 1, p->dd, n);
+      if ((rc = dots(p, s, mb.Vk, k + 1, w, p->dd2, hb2, n))) return rc;
+      launch_mgs_update(s, w, mb.Vk, n, k + 1, p->dd2, n);
+      double nrm2;
+      if ((rc = dots(p, s, w, 1, w, p->dd, &nrm2, n))) return rc;
+      const double hk1 = std::sqrt(nrm2);
+      for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hb[i] + hb2[i];
+      H[(size_t)(k + 1) * m + k] = hk1;
+      if (hk1 > 0) launch_axpby(s, w, w, 1.0 / hk1, 0.0, n);
+      else breakdown = true;
+      phase_close(p, s, ph2);
+      for (int i = 0; i < k; ++i) {
+        const double a = H[(size_t)i * m + k], c = H[(size_t)(i + 1) * m + k];
+        H[(size_t)i * m + k] = cs[i] * a + sn[i] * c;
+        H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * c;
+      }
+      const double a = H[(size_t)k * m + k], c = H[(size_t)(k + 1) * m + k];
+      const double t = std::hypot(a, c);
+      cs[k] = t > 0 ? a / t : 1.0;
+      sn[k] = t > 0 ? c / t : 0.0;
+      H[(size_t)k * m + k] = t;
+      H[(size_t)(k + 1) * m + k] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      ++its;
+      hist.push_back(std::fabs(g[k + 1]) / bnorm);
+      stalled = p->o.stall_guard && its >= std::max(10, m) && std::fabs(g[k + 1]) > 0.5 * res0;
+      if (std::fabs(g[k + 1]) <= p->o.tol * bnorm || breakdown || stalled) { ++k; break; }
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double v = g[i];
+      for (int j = i + 1; j < k; ++j) v -= H[(size_t)i * m + j] * y[j];
+      y[i] = v / H[(size_t)i * m + i];
+    }
+    const int ph3 = phase_open(p, s, PINTOC_PHASE_ORTH);
+    HIPCHK(hipMemcpyAsync(p->dd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    launch_lincomb_add(s, xf, mb.Zk, n, k, p->dd, n);
+    phase_close(p, s, ph3);
+    p->bytes_acc += (k + 2.0 + 4.0) * 8.0 * (double)n;
+    if ((rc = residual())) return rc;
+    if ((breakdown || stalled) && !(res <= p->o.tol * bnorm)) break;
+  }
+  // x = F^{-1} (x~ / s), then the time-domain true residual
+  ph = phase_open(p, s, PINTOC_PHASE_IFFT);
+  launch_freq_scale(s, (double2*)rv, (const double2*)xf, p->fisc, nf, p->segV, p->segP);
+  launch_time_fft_inv<double>(s, (const double2*)rv, (const double2*)rv + (size_t)nf * p->segV, x, mb.nt, p->L,
+                              p->nq2, p->np2, p->tw, p->tj, mb.tau, 0);
+  phase_close(p, s, ph);
+  double* rt = mb.Zk;                                      // a time-domain vector's worth of scratch
+  kkt_t(p, x, rt, s);
+  launch_axpby(s, rt, b, 1.0, -1.0, (size_t)p->n_all);
+  if ((rc = dots(p, s, rt, 1, rt, p->dd, hb))) return rc;
+  res = std::sqrt(hb[0]);
+  conv = res <= p->o.tol * bnorm;
+  return PINTOC_OK;
+}
+
 extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pintoc_solve_stats* st, void* stream) {
   int rc = check_ready(p);
   if (rc) return rc;
@@ -1878,6 +2106,8 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
     conv = true;
   } else if (p->o.outer == PINTOC_OUTER_MINRES) {
     if ((rc = solve_minres(p, b, x, bnorm, s, its, res, conv, hist))) return rc;
+  } else if (p->o.outer == PINTOC_OUTER_FGMRES_FREQ) {
+    if ((rc = solve_freq(p, b, x, bnorm, s, its, res, conv, hist))) return rc;
   } else {
     // r = b - A x
     kkt_t(p, x, p->rvec, s);

@@ -53,7 +53,7 @@ def test_host_validation(lib):
     assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(bad_opt), ctypes.byref(h)) == -1
     # MINRES: outer method 1 needs the Stokes flow, the linear preconditioner and restart >= 4
     assert o.outer == 0
-    for bad_opt in (default_options(outer=2), default_options(outer=1, inner=1), default_options(outer=1, restart=3)):
+    for bad_opt in (default_options(outer=3), default_options(outer=1, inner=1), default_options(outer=1, restart=3)):
         assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(bad_opt), ctypes.byref(h)) == -1
     # smoother option and domain validation
     assert o.smoother == 0
@@ -209,3 +209,28 @@ def test_group_create_validation():
     assert grp([a, b], default_options(outer=1, restart=10))[0] == EINVAL
     h = ctypes.c_void_p()
     assert lib.pintoc_group_create((Desc * 1)(a), 0, ctypes.byref(o), ctypes.byref(h)) == EINVAL
+
+
+def test_frequency_domain_outer_validation():
+    """The frequency-domain FGMRES takes single problems on the unit square
+    (Oseen in FP64 only)."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2405_18964_amd._lib import EINVAL, Desc, default_options, library
+    lib = library()
+    h = ctypes.c_void_p()
+    st = Desc(8, 16, 1.0, 1.0, 1e-2, 0, None, 0.0, 0.0, 0.0, 0.0)
+    for prec in (0, 1):
+        assert lib.pintoc_problem_create(ctypes.byref(st), ctypes.byref(default_options(outer=2, precision=prec)),
+                                         ctypes.byref(h)) == 0
+        lib.pintoc_problem_destroy(h)
+    w = np.ascontiguousarray(W.wind_nodal(8).reshape(-1))
+    os_ = Desc(8, 16, 1.0, 0.1, 1e-2, 1, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0.0)
+    assert lib.pintoc_problem_create(ctypes.byref(os_), ctypes.byref(default_options(outer=2)), ctypes.byref(h)) == 0
+    lib.pintoc_problem_destroy(h)
+    assert lib.pintoc_problem_create(ctypes.byref(os_), ctypes.byref(default_options(outer=2, precision=1)),
+                                     ctypes.byref(h)) == EINVAL
+    sq = Desc(8, 16, 1.0, 1.0, 1e-2, 0, None, -1.0, -1.0, 1.0, 1.0)
+    assert lib.pintoc_problem_create(ctypes.byref(sq), ctypes.byref(default_options(outer=2)), ctypes.byref(h)) == EINVAL
+    assert lib.pintoc_problem_create(ctypes.byref(st), ctypes.byref(default_options(outer=3)), ctypes.byref(h)) == EINVAL

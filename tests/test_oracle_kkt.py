@@ -142,3 +142,38 @@ def test_theorem1_low_rank_and_unit_eigenvalues(small_stokes):
     ev = np.linalg.eigvals(np.linalg.solve(PC, A))
     n_unit = int(np.sum(np.abs(ev - 1.0) < 1e-8))
     assert n_unit >= 2 * P.nt * (P.nv + P.nP) - 2 * P.nv
+
+
+@pytest.mark.parametrize("flow", [0, 1])
+def test_frequency_domain_operator_is_blocks_plus_corner(flow):
+    """Theorem 1 in the Fourier basis: F A F^{-1} equals the block-diagonal
+    G_j plus the corner term (two time samples spread over all frequencies),
+    checked against the assembled all-at-once matrix on random complex
+    spectra (not only Hermitian-symmetric ones), with planted mistakes (no
+    corner term, the corner phase conjugated) failing."""
+    import workloads as W
+    from oracle import circulant as circ
+    from oracle.kkt import Problem
+    N, nt = 4, 8
+    wind = W.wind_nodal(N) if flow else None
+    P = Problem(N, nt, 1.0, 0.1, 1e-2, wind)
+    A = P.kkt_matrix()
+    rng = np.random.default_rng(3)
+    Xh = rng.standard_normal((2, nt, P.n)) + 1j * rng.standard_normal((2, nt, P.n))
+    x = np.fft.ifft(Xh, axis=1).reshape(-1)
+    ref = np.fft.fft((A @ x).reshape(2, nt, P.n), axis=1)
+    got = circ.freq_domain_apply(P, Xh)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    # planted mistakes: the corner term left out / its phase conjugated
+    no_corner = np.empty_like(ref)
+    d = circ.d_closed_form(nt)
+    for j in range(nt):
+        v = circ.G_block(P, d[j]) @ np.concatenate(circ.split_freq(P, Xh[:, j, :]))
+        no_corner[:, j, :] = circ.join_freq(P, v[:P.nv], v[P.nv:2 * P.nv], v[2 * P.nv:2 * P.nv + P.nP],
+                                            v[2 * P.nv + P.nP:])
+    assert np.abs(no_corner - ref).max() > 1e-3 * np.abs(ref).max()
+    x_t = np.fft.ifft(Xh, axis=1)
+    bad = no_corner.copy()
+    bad[1, :, :P.nv] += (P.ops.M @ x_t[0, nt - 1, :P.nv])[None, :]
+    bad[0, :, :P.nv] += np.exp(-2j * np.pi * np.arange(nt) / nt)[:, None] * (P.ops.M @ x_t[1, 0, :P.nv])[None, :]
+    assert np.abs(bad - ref).max() > 1e-3 * np.abs(ref).max()
