@@ -414,6 +414,18 @@ def main():
         print(f"[bench] MINRES + Algorithm 1 (FP64): {stm['outer_iterations']} its, {tm:.2f} s",
               file=sys.stderr, flush=True)
         del gm
+    if not args.no_minres and w.flow == W.STOKES:
+        # the same solve with the pressure part of P~_j on a second stream
+        go = P.Problem.from_workload(w, precision=prec, pressure_stream=1, **solver_opts)
+        _timed_solve(go, b, x)                       # warm-up
+        to, sto, oko = _timed_solve(go, b, x)
+        same = bool(torch.equal(x, x_main))
+        out["pressure_stream"] = {"solves_per_s": 1.0 / to, "seconds": to, "converged": bool(oko),
+                                  "identical_to_value_solve": same,
+                                  "note": "options.pressure_stream = 1: K_p multigrid and M_p Chebyshev on a second "
+                                          "stream beside the velocity multigrid (same results)"}
+        print(f"[bench] pressure part on a second stream: {to:.2f} s, identical {same}", file=sys.stderr, flush=True)
+        del go
     if smp is not None:
         out["cpu_baseline"] = cpu_baseline(w, smp, outer, inner_mean, solver_opts["restart"])
     print(json.dumps(out), flush=True)
@@ -487,8 +499,11 @@ def bench_batch(args):
         "latency_s": {"p50": _pct(lat, 0.5), "p99": _pct(lat, 0.99)},
         "autotune": {"seconds": t_tune,
                      "plan": {f"N{k[0]}_{'oseen' if k[1] else 'stokes'}": {"size": v["size"], "smoother":
-                              "global" if v["smoother"] else "tiled"} for k, v in sorted(plan.items())},
-                     "trials": {f"N{k[0]}_{'oseen' if k[1] else 'stokes'}": v["trials"] for k, v in sorted(plan.items())}},
+                              "global" if v["smoother"] else "tiled", "fused_beats_side_by_side": v["fused_wins"]}
+                              for k, v in sorted(plan.items())},
+                     "trials": {f"N{k[0]}_{'oseen' if k[1] else 'stokes'}": {"fused": v["trials"],
+                                                                            "side_by_side": v["concurrent"]}
+                                for k, v in sorted(plan.items())}},
         "groups": len({r["group"] for r in out}),
     }
     if args.compare:

@@ -151,6 +151,22 @@ typedef struct {
                              outer_iterations counts MINRES steps, capped by
                              max_outer.                                      */
   int32_t smoother;       /* PINTOC_SMOOTHER_TILED (default) or _GLOBAL      */
+  int32_t pressure_stream; /* Stokes: 1 = run the pressure part of P~_j (the
+                             K_p multigrid and the M_p Chebyshev steps) on a
+                             second stream of the handle beside the velocity
+                             multigrid (they touch disjoint buffers; fork and
+                             join by events; same results); 0 (default) = one
+                             stream.  The overlap shortens an application but
+                             the velocity kernels then share HBM with the
+                             pressure kernels.                               */
+  int32_t graphs;          /* 1 = capture the launch sequence of a block
+                             preconditioner application (V-cycles, Chebyshev
+                             and Uzawa steps of all frequencies, section 3.4)
+                             once per set of buffers into a HIP graph and
+                             replay it (same kernels and arguments: same
+                             results); eager launches while the timing probe
+                             records, for the global smoother and on the
+                             legacy null stream.  0 (default) = eager.       */
 } pintoc_options;
 
 /* Phases of a solve whose device time pintoc_solve_stats reports. */

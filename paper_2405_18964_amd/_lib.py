@@ -31,7 +31,8 @@ class Options(C.Structure):
                 ("max_outer", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("inner_restart", C.c_int32), ("inner_maxit", C.c_int32), ("n_vcycles", C.c_int32),
                 ("n_cheb", C.c_int32), ("n_uzawa", C.c_int32), ("mu_uzawa", C.c_double),
-                ("stall_guard", C.c_int32), ("outer", C.c_int32), ("smoother", C.c_int32)]
+                ("stall_guard", C.c_int32), ("outer", C.c_int32), ("smoother", C.c_int32),
+                ("pressure_stream", C.c_int32), ("graphs", C.c_int32)]
 
 
 NPHASES = 5
@@ -138,7 +139,10 @@ class Problem:
     Vectors are torch float64 CUDA tensors in the canonical layout of
     include/pintoc.h (length :attr:`n_all`)."""
 
-    def __init__(self, N, nt, T, nu, beta, flow=STOKES, wind=None, device="cuda", domain=None, **options):
+    def __init__(self, N, nt, T, nu, beta, flow=STOKES, wind=None, device="cuda", domain=None, workspace=None,
+                 **options):
+        """``workspace``: optional caller-provided uint8 CUDA tensor (at least
+        ``workspace_bytes``, 256-byte aligned) to bind instead of a new one."""
         import numpy as np
         import torch
         lib = library()
@@ -158,7 +162,13 @@ class Problem:
         self.n_all = int(lib.pintoc_vector_length(h))
         self.workspace_bytes = int(lib.pintoc_workspace_bytes(h))
         self.device = torch.device(device)
-        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        else:
+            if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda and workspace.dtype == torch.uint8
+                    and workspace.numel() >= self.workspace_bytes):
+                raise ValueError(f"workspace must be a uint8 CUDA tensor of at least {self.workspace_bytes} bytes")
+            self._ws = workspace
         _check(lib.pintoc_bind_workspace(h, C.c_void_p(self._ws.data_ptr()), self.workspace_bytes,
                                          self._stream()), "pintoc_bind_workspace")
 

@@ -26,8 +26,8 @@ from ._lib import Problem
 _PROBLEM_KEYS = ("N", "nt", "T", "nu", "beta", "flow", "wind")
 
 
-def job_bytes(job, **options) -> int:
-    """Device bytes a job holds while it runs (workspace + four vectors)."""
+def job_layout(job, **options):
+    """(workspace bytes, canonical vector length) of a job (host-side set-up only)."""
     import ctypes as C
 
     from ._lib import Desc, _check, default_options, library
@@ -45,8 +45,63 @@ def job_bytes(job, **options) -> int:
         n_all = int(lib.pintoc_vector_length(h))
     finally:
         lib.pintoc_problem_destroy(h)
+    return ws, n_all
+
+
+_ALIGN = 4096
+
+
+def _up(v):
+    return (v + _ALIGN - 1) // _ALIGN * _ALIGN
+
+
+def _pieces(job, ws, n_all):
+    """Byte sizes of a job's workspace, b, x and desired state in its arena chunk."""
     nq2 = (2 * job["N"] + 1) ** 2
-    return ws + 8 * (2 * n_all + job["nt"] * 2 * nq2)
+    return [_up(ws), _up(8 * n_all), _up(8 * n_all), _up(8 * job["nt"] * 2 * nq2)]
+
+
+def job_bytes(job, **options) -> int:
+    """Device bytes a job holds while it runs (workspace + three vectors)."""
+    ws, n_all = job_layout(job, **options)
+    return sum(_pieces(job, ws, n_all))
+
+
+class _Arena:
+    """First-fit allocator over one device allocation made at the start of a
+    run: jobs of very different sizes (up to ~120 GB) come and go, and
+    carving them from one arena keeps the caching allocator of the framework
+    out of it (its per-stream pools and split blocks left large requests
+    without room although the budget had it).  Freed ranges coalesce."""
+
+    def __init__(self, nbytes, device):
+        import torch
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.free = [(0, nbytes)]                         # sorted (offset, size)
+
+    def largest(self):
+        return max((s for _, s in self.free), default=0)
+
+    def alloc(self, n):
+        for i, (o, s) in enumerate(self.free):
+            if s >= n:
+                if s == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (o + n, s - n)
+                return o
+        return None
+
+    def release(self, o, n):
+        self.free.append((o, n))
+        self.free.sort()
+        merged = []
+        for a, s in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == a:
+                merged[-1] = (merged[-1][0], merged[-1][1] + s)
+            else:
+                merged.append((a, s))
+        self.free = merged
 
 
 def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions: bool = False,
@@ -59,8 +114,11 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
     runs without keeping them).  ``on_done(k, record)`` is called (from a
     worker thread) as job k ends.
 
-    Scheduling.  A job is admitted in arrival order once it has arrived and
-    its device memory fits the budget left; the worker that admits it creates
+    Scheduling.  The run makes one device allocation of the budget (capped
+    at what all jobs together need) and carves each job's memory (workspace,
+    right-hand side, iterate, desired state) from it first-fit.  A job is
+    admitted in arrival order once it has arrived and a free range of that
+    arena holds it; the worker that admits it creates
     and binds the problem and assembles the right-hand side, and the job joins
     the ready queue.  Each of the ``workers`` host threads owns a HIP stream
     and repeatedly takes the job at the head of the ready queue.  With
@@ -82,32 +140,40 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
     import torch
 
     n = len(jobs)
-    need = [job_bytes(j, **options) for j in jobs]
+    lay = [job_layout(j, **options) for j in jobs]
+    pieces = [_pieces(j, ws, n_all) for j, (ws, n_all) in zip(jobs, lay)]
+    need = [sum(pc) for pc in pieces]
     # blocks the caching allocator keeps for streams of earlier runs are of no
-    # use to this run's streams: return them before measuring the free memory
+    # use to this run: return them before measuring the free memory
     torch.cuda.synchronize(device)
     torch.cuda.empty_cache()
     if budget_bytes is None:
         free, _ = torch.cuda.mem_get_info(device)
-        budget_bytes = int(0.85 * free)
+        budget_bytes = int(0.85 * free) // _ALIGN * _ALIGN
     if n and max(need) > budget_bytes:
         raise ValueError(f"a job needs {max(need)} bytes, more than the budget {budget_bytes}")
+    arena = _Arena(min(budget_bytes, sum(need)) if n else _ALIGN, device)
     order = sorted(range(n), key=lambda k: (jobs[k].get("arrival", 0.0), k))
     out = [None] * n
     lock = threading.Condition()
-    ready = collections.deque()                          # admitted jobs: [k, problem, b, x, turns, start]
-    state = {"next": 0, "free": budget_bytes, "error": None, "done": 0}
+    ready = collections.deque()                          # admitted jobs: [k, problem, b, x, turns, start, offset]
+    state = {"next": 0, "error": None, "done": 0}
+    offset = [None] * n
     t0 = time.perf_counter()
 
     def admit_one():
-        """Under the lock: index of the next job if it has arrived and fits, else None."""
+        """Under the lock: index of the next job if it has arrived and a free
+        range of the arena holds it, else None (arrival order is kept)."""
         if state["next"] >= n:
             return None
         k = order[state["next"]]
-        if jobs[k].get("arrival", 0.0) > time.perf_counter() - t0 or need[k] > state["free"]:
+        if jobs[k].get("arrival", 0.0) > time.perf_counter() - t0:
             return None
+        o = arena.alloc(need[k])
+        if o is None:
+            return None
+        offset[k] = o
         state["next"] += 1
-        state["free"] -= need[k]
         return k
 
     def next_wait():
@@ -117,14 +183,26 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
         return min(max(jobs[k].get("arrival", 0.0) - (time.perf_counter() - t0), 0.0), 0.05) or 0.05
 
     def setup(k, stream):
+        """Problem, right-hand side and initial guess of job k in its arena range
+        [workspace | b | x | desired state]."""
         job = jobs[k]
         start = time.perf_counter() - t0
+        ws, n_all = lay[k]
+        o = offset[k]
+        views = []
+        for sz in pieces[k]:
+            views.append(arena.buf[o:o + sz])
+            o += sz
+        b = views[1][:8 * n_all].view(torch.float64)
+        x = views[2][:8 * n_all].view(torch.float64)
+        nq2 = (2 * job["N"] + 1) ** 2
+        vd = views[3][:8 * job["nt"] * 2 * nq2].view(torch.float64)
         with torch.cuda.stream(stream):
-            p = Problem(job["N"], job["nt"], job.get("T", 1.0), job["nu"], job["beta"],
-                        job.get("flow", 0), job.get("wind"), device=device, **options)
-            vd = torch.as_tensor(np.ascontiguousarray(job["vd"], dtype=np.float64)).to(device)
-            b = p.assemble_rhs(vd)
-            x = p.empty()
+            p = Problem(job["N"], job["nt"], job.get("T", 1.0), job["nu"], job["beta"], job.get("flow", 0),
+                        job.get("wind"), device=device, workspace=views[0], **options)
+            vd.copy_(torch.as_tensor(np.ascontiguousarray(job["vd"], dtype=np.float64)).reshape(-1))
+            x.zero_()
+            p.assemble_rhs(vd, b)
             stream.synchronize()
         return [k, p, b, x, 0, start]
 
@@ -132,6 +210,7 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
         k, p, b, x, turns, start = item
         with torch.cuda.stream(stream):
             sol = x.cpu().numpy() if (keep_solutions or checksum) else None
+            stream.synchronize()
         digest = hashlib.blake2b(sol.tobytes(), digest_size=16).hexdigest() if checksum else None
         p.close()
         end = time.perf_counter() - t0
@@ -174,7 +253,7 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
                     lock.notify_all()
                 return
             with lock:
-                state["free"] += need[k]
+                arena.release(offset[k], need[k])
                 state["done"] += 1
                 lock.notify_all()
             if on_done is not None:
@@ -187,6 +266,7 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
         t.join()
     torch.cuda.synchronize(device)
     ready.clear()
+    del arena
     torch.cuda.empty_cache()
     if state["error"] is not None:
         raise state["error"]
@@ -204,17 +284,20 @@ def autotune(jobs, sizes=(1, 2, 4, 8, 16), smoothers=None, budget_bytes=None, de
     smoother of the fused form by measurement: for every candidate that fits
     the memory budget, one group of that many of the class's jobs (linear
     preconditioner, the options' precision) applies its fused preconditioner
-    ``reps`` times.  The pick is the smallest group whose member applications
-    per second reach ``keep`` times the best candidate's: the fused
+    ``reps`` times, and the same members as lone problems apply theirs on
+    streams of their own, side by side.  The pick is the smallest group whose
+    member applications per second reach ``keep`` times the best candidate's
+    (size 1 -- no fusion -- where the lone problems side by side are faster
+    than that group): the fused
     application runs beside other groups on other streams, and a group's
     members converge at different outer iterations (those that finish sit
     out while the rest iterate), so beyond the knee a larger group gains
     little throughput and loses concurrency.  Returns
-    {(N, flow): {"size", "smoother", "trials": [...]}}."""
+    {(N, flow): {"size", "smoother", "trials", "concurrent", "fused_wins"}}."""
     import numpy as np
     import torch
 
-    from ._lib import INNER_LINEAR, SMOOTHER_GLOBAL, SMOOTHER_TILED, Group, group_bytes
+    from ._lib import INNER_LINEAR, SMOOTHER_GLOBAL, SMOOTHER_TILED, Group, Problem, group_bytes
 
     smoothers = (SMOOTHER_TILED, SMOOTHER_GLOBAL) if smoothers is None else smoothers
     if budget_bytes is None:
@@ -228,7 +311,7 @@ def autotune(jobs, sizes=(1, 2, 4, 8, 16), smoothers=None, budget_bytes=None, de
         classes.setdefault((j["N"], j.get("flow", 0)), []).append(j)
     out = {}
     for key, cj in classes.items():
-        trials = []
+        trials, concurrent = [], []
         for sm in smoothers:
             for g in sizes:
                 if g > len(cj):
@@ -251,12 +334,38 @@ def autotune(jobs, sizes=(1, 2, 4, 8, 16), smoothers=None, budget_bytes=None, de
                 dt = (time.perf_counter() - t0) / reps
                 trials.append({"size": g, "smoother": int(sm), "seconds": dt, "member_apps_per_s": g / dt})
                 grp.close()
-                del grp, rs
+                del grp
+                if sm == smoothers[0] and g > 1:
+                    # the same members as lone problems on streams of their own
+                    lone = [Problem(device=device, **m, **opts) for m in members]
+                    streams = [torch.cuda.Stream(device=device) for _ in members]
+                    zs = [q.empty() for q in lone]
+
+                    def issue():
+                        for q, st, r, z in zip(lone, streams, rs, zs):
+                            with torch.cuda.stream(st):
+                                q.precond_apply(r, z)
+                    issue()
+                    torch.cuda.synchronize(device)
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        issue()
+                    torch.cuda.synchronize(device)
+                    dt = (time.perf_counter() - t0) / reps
+                    concurrent.append({"size": g, "seconds": dt, "member_apps_per_s": g / dt})
+                    for q in lone:
+                        q.close()
+                    del lone, zs
+                del rs
                 torch.cuda.empty_cache()
         best = max(t["member_apps_per_s"] for t in trials)
         pick = min((t for t in trials if t["member_apps_per_s"] >= keep * best),
                    key=lambda t: (t["size"], t["smoother"]))
-        out[key] = {"size": pick["size"], "smoother": pick["smoother"], "trials": trials}
+        # fusion pays only where it beats the same members running side by side
+        conc = [c for c in concurrent if c["size"] == pick["size"]]
+        fused_wins = not conc or pick["member_apps_per_s"] > conc[0]["member_apps_per_s"]
+        out[key] = {"size": pick["size"] if fused_wins else 1, "smoother": pick["smoother"], "trials": trials,
+                    "concurrent": concurrent, "fused_wins": fused_wins}
     return out
 
 
@@ -301,8 +410,8 @@ def run_fused(jobs, plan=None, workers: int = 2, budget_bytes: int | None = None
         need.append(group_bytes(members, smoother=sm, **options) + sum(vec_bytes(jobs[k]) for k in ks))
     if groups and max(need) > budget_bytes:
         raise ValueError(f"a group needs {max(need)} bytes, more than the budget {budget_bytes}")
-    # largest groups first: they bound the makespan
-    order = sorted(range(len(groups)), key=lambda g: -need[g])
+    # groups in the order of their first job (as ``run`` admits jobs)
+    order = sorted(range(len(groups)), key=lambda g: min(groups[g][0]))
     out = [None] * n
     lock = threading.Condition()
     state = {"next": 0, "free": budget_bytes, "error": None}

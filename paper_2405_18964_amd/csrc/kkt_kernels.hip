@@ -127,14 +127,6 @@ __global__ __launch_bounds__(256) void k_kkt_apply(const double* __restrict__ x,
   y[((size_t)b * nt + t) * L + g] = out;
 }
 
-// Velocity rows without convection (Stokes), column strips.  Thread (ix, strip)
-// of grid (b, t, comp) walks the rows of its strip downwards.  M and K are
-// tensor products of 1-D rows (M = m'_y (m'_x .), K = m'_y (k'_x .) +
-// k'_y (m'_x .)), so per input row y' it forms the x-sums at column ix once --
-// sm (m'_x on the mass field ca v_t + cb l_t - un), sk (k'_x on u), su
-// (m'_x on u) -- and keeps those of rows y - 2 .. y + 2 in registers: 15 loads
-// per output row instead of 75.  The x-weights depend on the parity of ix
-// only; rows outside the grid contribute zero (their y-weights vanish).
 // Entry (k, j = 2k + off) of the 1-D mixed Q1-Q2 mass (m) and derivative (g)
 // rows, the same values as mixed_rows(k) at index off + 2 (zero outside).
 __device__ __forceinline__ void mixed_at(int k, int off, int n, double h, double& m, double& g) {
@@ -151,41 +143,55 @@ __device__ __forceinline__ void mixed_at(int k, int off, int n, double h, double
   }
 }
 
-constexpr int kKStrip = 16;                 // rows per thread
+// Velocity rows without convection (Stokes) on LDS tiles.  A work-group owns
+// 64 x 32 interior output nodes of one grid (b, t, comp) and stages the two
+// fields its rows act on -- the mass field f = ca v_t + cb l_t - un and the
+// differentiated field u (l_t for the adjoint rows, v_t for the state rows) --
+// over the tile and a two-node halo, read once from HBM with coalesced rows.
+// Thread (column, strip of 8 rows) then walks its strip keeping the x-sums
+// (m' on f, k' and m' on u) of the five rows around the output row in
+// registers: 10 LDS reads per output.  B^T q comes from the 3 x 3 pressure
+// nodes around the output (Q1 field p_t or mu_t, read from L2).  The
+// Dirichlet ring is written by k_kkt_ring.
+constexpr int kVTX = 64, kVTY = 32, kVTS = 8;
+constexpr int kVLX = kVTX + 4, kVLY = kVTY + 4;
 
-__global__ __launch_bounds__(256) void k_kkt_vel_strips(const double* __restrict__ x, double* __restrict__ y, int n,
-                                                        int nt, double tau, double beta, double nu, int ncb,
-                                                        int nstrip) {
+__global__ __launch_bounds__(256) void k_kkt_vel_tile(const double* __restrict__ x, double* __restrict__ y, int n,
+                                                      int nt, double tau, double beta, double nu, int ntx) {
+  __shared__ double F[kVLY * kVLX], U[kVLY * kVLX];
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int L = 2 * nq2 + np2;
   const int t = blockIdx.y, bc = blockIdx.z, b = bc >> 1, comp = bc & 1;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cb = blockIdx.x % ncb, st = (blockIdx.x / ncb) * 4 + w;
-  const int ix = cb * 64 + lane;
-  if (ix >= nq || st >= nstrip) return;
-  const int y0 = st * kKStrip, y1 = min(y0 + kKStrip, nq);
+  const int bx = blockIdx.x % ntx, by = blockIdx.x / ntx;
+  const int x0 = 1 + bx * kVTX, y0 = 1 + by * kVTY;      // first interior output node of the tile
   const double* X0 = x;
   const double* X1 = x + (size_t)nt * L;
   const double* vt = X0 + (size_t)t * L + comp * nq2;
   const double* lt = X1 + (size_t)t * L + comp * nq2;
   const double* un = b == 0 ? (t + 1 < nt ? X1 + (size_t)(t + 1) * L + comp * nq2 : nullptr)
                             : (t > 0 ? X0 + (size_t)(t - 1) * L + comp * nq2 : nullptr);
-  const double* pf = (b == 0 ? X1 : X0) + (size_t)t * L + 2 * nq2;
   const double ca = b == 0 ? tau : 1.0, cb2 = b == 0 ? 1.0 : -tau / beta;
-  double* yo = y + ((size_t)b * nt + t) * L + comp * nq2;
-  const bool xin = ix >= 1 && ix <= nq - 2;
-  if (!xin) {                                 // boundary column: zero rows
-    for (int iy = y0; iy < y1; ++iy) yo[(size_t)iy * nq + ix] = 0.0;
-    return;
+  for (int e = threadIdx.x; e < kVLY * kVLX; e += blockDim.x) {
+    const int ly = e / kVLX, lx = e - ly * kVLX;
+    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+    double f = 0.0, u = 0.0;
+    if (gx >= 0 && gx < nq && gy >= 0 && gy < nq) {
+      const size_t o = (size_t)gy * nq + gx;
+      const double vv = vt[o], ll = lt[o];
+      f = ca * vv + cb2 * ll - (un ? un[o] : 0.0);
+      u = b == 0 ? ll : vv;
+    }
+    F[e] = f;
+    U[e] = u;
   }
+  __syncthreads();
+  const int lx = threadIdx.x & (kVTX - 1), strip = threadIdx.x / kVTX;
+  const int ix = x0 + lx;
+  if (ix > nq - 2) return;
   const double h = 1.0 / n;
   double mx[5], kx[5], my[5], ky[5];
   q2_rows(ix, h, mx, kx);
-  int cx[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) cx[d] = min(max(ix + d - 2, 0), nq - 1);
-  // B^T at this column: x-weights of the Q1 nodes kx0 .. kx0 + 2 (fixed per
-  // thread: the derivative row for component 0, the mass row for component 1)
+  const double* pf = (b == 0 ? X1 : X0) + (size_t)t * L + 2 * nq2;
   const int kx0 = (ix >> 1) - 1;
   double wbx[3];
 #pragma unroll
@@ -194,50 +200,27 @@ __global__ __launch_bounds__(256) void k_kkt_vel_strips(const double* __restrict
     mixed_at(kx0 + c, ix - 2 * (kx0 + c), n, h, m, g);
     wbx[c] = comp == 0 ? g : m;
   }
-  auto btq = [&](int iy) -> double {          // (B^T q)_comp at (ix, iy), q = p_t or mu_t
-    const int ky0 = (iy >> 1) - 1;
-    double sum = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int ky = ky0 + a;
-      if (ky < 0 || ky > n) continue;
-      double m, g;
-      mixed_at(ky, iy - 2 * ky, n, h, m, g);
-      const double* row = pf + (size_t)ky * np;
-      double rs = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int kx = kx0 + c;
-        if (kx >= 0 && kx <= n) rs += wbx[c] * row[kx];
-      }
-      sum += (comp == 0 ? m : g) * rs;
-    }
-    return -sum;
-  };
-  auto rowsums = [&](int yr, double& sm, double& sk, double& su) {
+  double* yo = y + ((size_t)b * nt + t) * L + comp * nq2;
+  const int r0 = strip * kVTS;                           // first output row of the strip (tile-local)
+  double SM[5], SK[5], SU[5];
+  auto sums = [&](int lr, double& sm, double& sk, double& su) {   // lr: staged row (0 = y0 - 2)
+    const double* fr = F + lr * kVLX + lx;
+    const double* ur = U + lr * kVLX + lx;
     sm = 0; sk = 0; su = 0;
-    if (yr < 0 || yr >= nq) return;
-    const size_t ro = (size_t)yr * nq;
 #pragma unroll
     for (int dx = 0; dx < 5; ++dx) {
-      const double vv = vt[ro + cx[dx]], ll = lt[ro + cx[dx]];
-      const double uv = un ? un[ro + cx[dx]] : 0.0;
-      const double u = b == 0 ? ll : vv;
-      sm += mx[dx] * (ca * vv + cb2 * ll - uv);
-      sk += kx[dx] * u;
-      su += mx[dx] * u;
+      sm += mx[dx] * fr[dx];
+      sk += kx[dx] * ur[dx];
+      su += mx[dx] * ur[dx];
     }
   };
-  double SM[5] = {0, 0, 0, 0, 0}, SK[5] = {0, 0, 0, 0, 0}, SU[5] = {0, 0, 0, 0, 0};   // rows iy - 2 .. iy + 2
-  // the first four steps only fill the window (rows y0 - 2 .. y0 + 1)
-#pragma unroll 1
-  for (int iy = y0 - 4; iy < y1; ++iy) {
 #pragma unroll
-    for (int d = 0; d < 4; ++d) { SM[d] = SM[d + 1]; SK[d] = SK[d + 1]; SU[d] = SU[d + 1]; }
-    rowsums(iy + 2, SM[4], SK[4], SU[4]);
-    if (iy < y0) continue;
-    double out = 0.0;
-    if (iy >= 1 && iy <= nq - 2) {
+  for (int d = 0; d < 4; ++d) sums(r0 + d, SM[d], SK[d], SU[d]);
+#pragma unroll 1
+  for (int i = 0; i < kVTS; ++i) {
+    const int iy = y0 + r0 + i;
+    sums(r0 + i + 4, SM[4], SK[4], SU[4]);
+    if (iy <= nq - 2) {
       q2_rows(iy, h, my, ky);
       double mm = 0, kk = 0;
 #pragma unroll
@@ -245,10 +228,45 @@ __global__ __launch_bounds__(256) void k_kkt_vel_strips(const double* __restrict
         mm += my[d] * SM[d];
         kk += my[d] * SK[d] + ky[d] * SU[d];
       }
-      out = mm + tau * nu * kk + tau * btq(iy);
+      const int ky0 = (iy >> 1) - 1;
+      double bt = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int kyy = ky0 + a;
+        if (kyy < 0 || kyy > n) continue;
+        double m, g;
+        mixed_at(kyy, iy - 2 * kyy, n, h, m, g);
+        const double* row = pf + (size_t)kyy * np;
+        double rs = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int kxx = kx0 + c;
+          if (kxx >= 0 && kxx <= n) rs += wbx[c] * row[kxx];
+        }
+        bt += (comp == 0 ? m : g) * rs;
+      }
+      yo[(size_t)iy * nq + ix] = mm + tau * nu * kk - tau * bt;
     }
-    yo[(size_t)iy * nq + ix] = out;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) { SM[d] = SM[d + 1]; SK[d] = SK[d + 1]; SU[d] = SU[d + 1]; }
   }
+}
+
+// zero velocity rows on the Dirichlet ring of every grid (b, t, comp)
+__global__ __launch_bounds__(256) void k_kkt_ring(double* __restrict__ y, int n, int nt) {
+  const int nq = 2 * n + 1, nq2 = nq * nq, L = 2 * nq2 + (n + 1) * (n + 1);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 4 * (nq - 1)) return;
+  const int t = blockIdx.y, bc = blockIdx.z, b = bc >> 1, comp = bc & 1;
+  const int side = e / (nq - 1), k = e - side * (nq - 1);
+  int ix, iy;
+  switch (side) {
+    case 0: ix = k; iy = 0; break;
+    case 1: ix = nq - 1; iy = k; break;
+    case 2: ix = nq - 1 - k; iy = nq - 1; break;
+    default: ix = 0; iy = nq - 1 - k; break;
+  }
+  y[((size_t)b * nt + t) * L + comp * nq2 + (size_t)iy * nq + ix] = 0.0;
 }
 
 // b = tau M v_d on the adjoint momentum rows, zero elsewhere.
@@ -407,10 +425,10 @@ void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, 
                        0);
     return;
   }
-  // Stokes: velocity rows by column strips, pressure rows per entry
-  const int ncb = (nq + 63) / 64, nstrip = (nq + kKStrip - 1) / kKStrip;
-  hipLaunchKernelGGL(k_kkt_vel_strips, dim3(ncb * ((nstrip + 3) / 4), nt, 4), dim3(256), 0, s, x, y, n, nt, tau, beta,
-                     nu, ncb, nstrip);
+  // Stokes: velocity rows on LDS tiles (and the Dirichlet ring), pressure rows per entry
+  const int ntx = (nq - 2 + kVTX - 1) / kVTX, nty = (nq - 2 + kVTY - 1) / kVTY;
+  hipLaunchKernelGGL(k_kkt_vel_tile, dim3(ntx * nty, nt, 4), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, ntx);
+  hipLaunchKernelGGL(k_kkt_ring, dim3((4 * (nq - 1) + 255) / 256, nt, 4), dim3(256), 0, s, y, n, nt);
   const int g0 = 2 * nq * nq, np2 = (n + 1) * (n + 1);
   hipLaunchKernelGGL(k_kkt_apply, dim3((np2 + 255) / 256, nt, 2), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, conv,
                      g0);

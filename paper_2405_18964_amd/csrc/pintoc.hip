@@ -101,6 +101,21 @@ struct MGPlan {
   }
 };
 
+// Captured block-preconditioner applications (options.graphs), keyed by the
+// buffers and the mask they were captured with.
+struct GraphKey {
+  const void *inV, *inP, *outV, *outP;
+  const int* mask;
+  int rsize;
+  bool operator==(const GraphKey& o) const {
+    return inV == o.inV && inP == o.inP && outV == o.outV && outP == o.outP && mask == o.mask && rsize == o.rsize;
+  }
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+};
+
 // One problem of a group (a lone problem is a group of one).  Its kept
 // frequencies are f0 .. f0 + nf - 1 of the group's batch, its twiddles start
 // at tw0; nu is the viscosity of the unit-square equivalent.  The outer Krylov
@@ -211,6 +226,7 @@ struct pintoc_problem {
   // velocity multigrid) and its fork/join events; default priority
   hipStream_t pstream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<GraphEntry> graphs;       // captured block-preconditioner applications (options.graphs)
   // statistics
   int precond_apps = 0;
   // a solve paused at a restart boundary (pintoc_solve_stats.cycle_budget):
@@ -545,6 +561,8 @@ extern "C" int pintoc_default_options(pintoc_options* o) {
   o->stall_guard = 1;
   o->outer = PINTOC_OUTER_FGMRES;
   o->smoother = PINTOC_SMOOTHER_TILED;
+  o->pressure_stream = 0;
+  o->graphs = 0;
   return PINTOC_OK;
 }
 
@@ -663,6 +681,8 @@ static int create_impl(const pintoc_problem_desc* ds, int nm, const pintoc_optio
                                "(and FP64 for Oseen)");
   if (opt.smoother != PINTOC_SMOOTHER_TILED && opt.smoother != PINTOC_SMOOTHER_GLOBAL)
     return fail(PINTOC_EINVAL, "unknown smoother");
+  if (opt.pressure_stream != 0 && opt.pressure_stream != 1) return fail(PINTOC_EINVAL, "pressure_stream must be 0 or 1");
+  if (opt.graphs != 0 && opt.graphs != 1) return fail(PINTOC_EINVAL, "graphs must be 0 or 1");
   if (opt.outer == PINTOC_OUTER_MINRES &&
       (nm > 1 || d->flow != PINTOC_STOKES || opt.inner != PINTOC_INNER_LINEAR || opt.restart < 4))
     return fail(PINTOC_EINVAL, "MINRES needs a single Stokes problem, the linear preconditioner and restart >= 4");
@@ -918,6 +938,7 @@ extern "C" void pintoc_problem_destroy(pintoc_problem* p) {
   }
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  for (GraphEntry& e : p->graphs) (void)hipGraphExecDestroy(e.exec);
   delete p;
 }
 
@@ -967,7 +988,9 @@ extern "C" int pintoc_bind_scratch(pintoc_problem* p, void* stream) {
 // carve the workspace, clear it and upload the tables on stream s
 static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s) {
   p->bound = false;
-  if (p->d.flow == PINTOC_STOKES && !p->pstream) {
+  for (GraphEntry& e : p->graphs) (void)hipGraphExecDestroy(e.exec);   // captured with the old buffers
+  p->graphs.clear();
+  if (p->d.flow == PINTOC_STOKES && p->o.pressure_stream && !p->pstream) {
     HIPCHK(hipStreamCreateWithFlags(&p->pstream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
@@ -1216,10 +1239,11 @@ static cpx<R>* chebyshev(hipStream_t s, bool q2, int n, int nb, cpx<R>* A, cpx<R
 // the pressure fields.  in and out must not alias.
 template <typename R>
 // The pressure part (K_N multigrid, M_N Chebyshev) and the velocity part
-// (W_j multigrid) touch disjoint buffers: the pressure part runs on the
-// problem's side stream, forked from s after the inputs and joined before
-// the outputs are used, so its small latency-bound Q1 launches overlap the
-// velocity V-cycles (the results do not depend on the overlap).
+// (W_j multigrid) touch disjoint buffers: with options.pressure_stream the
+// pressure part runs on the problem's side stream, forked from s after the
+// inputs and joined before the outputs are used, so its small latency-bound
+// Q1 launches overlap the velocity V-cycles (the results do not depend on the
+// overlap).
 static void ptilde(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP, cpx<R>* outV,
                    cpx<R>* outP) {
   const int nf = p->nf, cyc = p->o.n_vcycles, N = p->d.N;
@@ -1294,10 +1318,55 @@ static void puz(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R
 
 // block preconditioner of the flow: P~_j (Stokes) or P~_j^(UZ) (Oseen)
 template <typename R>
-static void block_precond(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP, cpx<R>* outV,
-                          cpx<R>* outP) {
+static void block_precond_eager(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP,
+                                cpx<R>* outV, cpx<R>* outP) {
   if (p->d.flow == PINTOC_OSEEN) puz<R>(p, s, inV, inP, outV, outP);
   else ptilde<R>(p, s, inV, inP, outV, outP);
+}
+
+// With options.graphs the launch sequence of one block preconditioner
+// application (the V-cycles, Chebyshev and Uzawa steps of every frequency,
+// 100-300 launches) is captured once per set of buffers and mask into a HIP
+// graph and replayed: the kernels, their order and their arguments are the
+// same, so the results equal the eager sequence bit for bit.  Eager instead
+// while the kernel-timing probe records (its events are host bookkeeping), for
+// the global smoother (its copies), or when s cannot capture (the legacy null
+// stream); a capture that fails falls back to eager launches.
+template <typename R>
+static void block_precond(pintoc_problem* p, hipStream_t s, const cpx<R>* inV, const cpx<R>* inP, cpx<R>* outV,
+                          cpx<R>* outP) {
+  const bool probing = p->probe.on || p->probe_post.on;
+  if (!p->o.graphs || probing || p->o.smoother == PINTOC_SMOOTHER_GLOBAL || s == nullptr) {
+    block_precond_eager<R>(p, s, inV, inP, outV, outP);
+    return;
+  }
+  const GraphKey key{inV, inP, outV, outP, p->cur_mask, (int)sizeof(R)};
+  for (const GraphEntry& e : p->graphs)
+    if (e.key == key) {
+      if (hipGraphLaunch(e.exec, s) == hipSuccess) return;
+      block_precond_eager<R>(p, s, inV, inP, outV, outP);
+      return;
+    }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone ||
+      hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    block_precond_eager<R>(p, s, inV, inP, outV, outP);
+    return;
+  }
+  block_precond_eager<R>(p, s, inV, inP, outV, outP);
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  const bool ok = hipStreamEndCapture(s, &g) == hipSuccess && g &&
+                  hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!ok) {                                   // nothing ran: launch the sequence eagerly
+    (void)hipGetLastError();
+    block_precond_eager<R>(p, s, inV, inP, outV, outP);
+    return;
+  }
+  p->graphs.push_back(GraphEntry{key, ex});
+  if (hipGraphLaunch(ex, s) != hipSuccess) block_precond_eager<R>(p, s, inV, inP, outV, outP);
 }
 
 // block matrix of the flow: Z_j (Stokes) or G_j (Oseen)

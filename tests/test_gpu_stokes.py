@@ -56,6 +56,25 @@ def test_kkt_apply_parity(lib, N, nt, beta):
     assert np.all(y[~W.canonical_mask(N, nt)] == 0)
 
 
+@pytest.mark.parametrize("N,nt", [(64, 4), (128, 2)])
+def test_kkt_apply_parity_tiles(lib, N, nt):
+    """Stokes velocity rows run on 64 x 32 LDS tiles of interior nodes: 127
+    and 255 interior nodes per side give 2 x 4 and 4 x 8 tiles, the last
+    column and row of tiles ragged."""
+    from oracle.kkt import Problem as OP
+    print(f"kkt_apply N={N} nt={nt}", flush=True)
+    w = W.small(W.STOKES, N, nt, beta=1e-3)
+    op = OP.from_workload(w)
+    gp = lib.Problem.from_workload(w)
+    xc = W.random_canonical(N, nt, seed=12)
+    y = _host(gp.kkt_apply(_dev(xc)))
+    ref = op.to_canonical(op.kkt_apply(op.to_compact(xc)))
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"  max rel error {err:.2e}", flush=True)
+    assert err <= 1e-13
+    assert np.all(y[~W.canonical_mask(N, nt)] == 0)
+
+
 @pytest.mark.parametrize("N,nt,beta", CASES[:3])
 def test_assemble_rhs_parity(lib, N, nt, beta):
     from oracle.kkt import Problem as OP

@@ -114,6 +114,40 @@ def test_batch_job_bytes_and_mix():
     assert job_bytes(small, precision=1) < job_bytes(small, precision=0)
 
 
+def test_batch_arena_first_fit():
+    """The batch runner's arena: first fit, exhaustion, and freed ranges that
+    coalesce so a job as large as the whole arena fits again (host logic on a
+    CPU buffer)."""
+    import random
+    from paper_2405_18964_amd.batch import _Arena
+    a = _Arena(1000, "cpu")
+    assert a.alloc(400) == 0 and a.alloc(300) == 400 and a.alloc(400) is None
+    assert a.alloc(300) == 700 and a.largest() == 0
+    a.release(400, 300)
+    assert a.alloc(301) is None and a.alloc(200) == 400 and a.largest() == 100
+    a.release(0, 400)
+    a.release(700, 300)
+    assert a.free == [(0, 400), (600, 400)]
+    a.release(400, 200)
+    assert a.free == [(0, 1000)] and a.alloc(1000) == 0
+    a.release(0, 1000)
+    rng = random.Random(3)
+    held = []
+    for _ in range(2000):                       # random traffic never overlaps ranges
+        if held and rng.random() < 0.5:
+            held.remove(r := rng.choice(held))
+            a.release(*r)
+        else:
+            n = rng.randint(1, 300)
+            o = a.alloc(n)
+            if o is not None:
+                assert all(o + n <= q or q + m <= o for q, m in held)
+                held.append((o, n))
+    for r in held:
+        a.release(*r)
+    assert a.free == [(0, 1000)]
+
+
 def test_serve_stream_draw():
     """Served workload: seeded Poisson arrivals (increasing, mean gap 1 at unit
     rate) and request parameters drawn like the batched mix."""
