@@ -95,8 +95,10 @@ size_t q2_tile_conv_entries(int n);
 void q2_tile_conv_table(int n, const double* t50, int half, double* out);
 
 // all-at-once matrix, rhs, FP64 vector kernels (kkt_kernels.hip)
+// convT: Oseen convection entries of the finest grid, entry-major ([50][nq^2]:
+// N at entries 0..24, N^T at 25..49); nullptr for Stokes
 void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,
-                      const double* conv);
+                      const double* convT);
 void launch_assemble_rhs(hipStream_t s, const double* vd, double* b, int n, int nt, double tau);
 void launch_rhs_data(hipStream_t s, const double* vd, const double* f, const double* hb, const double* v0, double* b,
                      int n, int nt, double tau, double nu, const double* conv);

@@ -9,123 +9,11 @@
 //   state divergence  (b=1): tau B v_t
 // with v_{-1} = 0, l_{nt} = 0, L = nu K + N(w), the pinned pressure row and
 // the Dirichlet velocity rows zero.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace pintoc {
-
-// (B^T q)_comp at Q2 node (jx, jy): -sum mix(ky,jy) gmix(kx,jx) q (comp 0) or
-// -sum gmix(ky,jy) mix(kx,jx) q (comp 1).
-__device__ inline double bt_node(const double* __restrict__ q, int n, double h, int jx, int jy, int comp) {
-  double mxx[3], gxx[3], mxy[3], gxy[3];
-  mixed_cols(jx, n, h, mxx, gxx);
-  mixed_cols(jy, n, h, mxy, gxy);
-  const int kx0 = (jx >> 1) - 1, ky0 = (jy >> 1) - 1, np = n + 1;
-  double s = 0;
-  for (int a = 0; a < 3; ++a) {
-    const int ky = ky0 + a;
-    if (ky < 0 || ky > n) continue;
-    const double wy = comp == 0 ? mxy[a] : gxy[a];
-    for (int c = 0; c < 3; ++c) {
-      const int kx = kx0 + c;
-      if (kx < 0 || kx > n) continue;
-      const double wx = comp == 0 ? gxx[c] : mxx[c];
-      s += wy * wx * q[ky * np + kx];
-    }
-  }
-  return -s;
-}
-
-// (B v)_k at Q1 node (kx, ky), v = (vx, vy) padded Q2 grids.
-__device__ inline double b_node(const double* __restrict__ vx, const double* __restrict__ vy, int n, double h,
-                                int kx, int ky) {
-  double mxx[5], gxx[5], mxy[5], gxy[5];
-  mixed_rows(kx, n, h, mxx, gxx);
-  mixed_rows(ky, n, h, mxy, gxy);
-  const int nq = 2 * n + 1;
-  double s = 0;
-  for (int dy = 0; dy < 5; ++dy) {
-    const int jy = 2 * ky + dy - 2;
-    if (jy < 0 || jy >= nq) continue;
-    for (int dx = 0; dx < 5; ++dx) {
-      const int jx = 2 * kx + dx - 2;
-      if (jx < 0 || jx >= nq) continue;
-      const int j = jy * nq + jx;
-      s += mxy[dy] * gxx[dx] * vx[j] + gxy[dy] * mxx[dx] * vy[j];
-    }
-  }
-  return -s;
-}
-
-// One thread per entry g >= g0 of the canonical vector.
-__global__ __launch_bounds__(256) void k_kkt_apply(const double* __restrict__ x, double* __restrict__ y, int n, int nt, double tau,
-                            double beta, double nu, const double* __restrict__ conv, int g0) {
-  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
-  const int L = 2 * nq2 + np2;
-  const int g = g0 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = blockIdx.y, b = blockIdx.z;
-  if (g >= L) return;
-  const double h = 1.0 / n;
-  const double* X0 = x;                           // block 0: v, p
-  const double* X1 = x + (size_t)nt * L;          // block 1: l, mu
-  auto lev = [&](const double* B0, int tt) { return B0 + (size_t)tt * L; };
-  double out = 0;
-  if (g < 2 * nq2) {
-    const int comp = g >= nq2, node = g - comp * nq2;
-    const int ix = node % nq, iy = node / nq;
-    if (ix > 0 && iy > 0 && ix < nq - 1 && iy < nq - 1) {
-      double mx[5], kx[5], my[5], ky[5];
-      q2_rows(ix, h, mx, kx);
-      q2_rows(iy, h, my, ky);
-      // One pass over the 25 neighbours.  Adjoint rows (b = 0):
-      //   M (tau v_t + l_t - l_{t+1}) + tau nu K l_t + tau N^T l_t + tau B^T mu_t;
-      // state rows (b = 1):
-      //   M (v_t - v_{t-1} - tau/beta l_t) + tau nu K v_t + tau N v_t + tau B^T p_t.
-      // The mass term acts on one combined field, the stiffness and convection
-      // terms on the field u they differentiate (l_t, resp. v_t).
-      const double* vt = lev(X0, t) + comp * nq2;
-      const double* lt = lev(X1, t) + comp * nq2;
-      const double* un = b == 0 ? (t + 1 < nt ? lev(X1, t + 1) + comp * nq2 : nullptr)
-                                : (t > 0 ? lev(X0, t - 1) + comp * nq2 : nullptr);
-      const double ca = b == 0 ? tau : 1.0, cb = b == 0 ? 1.0 : -tau / beta;   // mass field ca v_t + cb l_t - un
-      const double* cn = conv ? conv + (size_t)node * 50 + (b == 0 ? 25 : 0) : nullptr;
-      int cx[5];
-#pragma unroll
-      for (int d = 0; d < 5; ++d) cx[d] = min(max(ix + d - 2, 0), nq - 1);
-      // per row: x-mass sums of the mass field (sm) and of u (su), x-stiffness
-      // sums of u (sk); M = m'_y (m'_x .), K = m'_y (k'_x .) + k'_y (m'_x .)
-      double mm = 0, kk = 0, cc = 0;
-#pragma unroll 1
-      for (int dy = 0; dy < 5; ++dy) {
-        const size_t ro = (size_t)min(max(iy + dy - 2, 0), nq - 1) * nq;
-        double sm = 0, sk = 0, su = 0;
-#pragma unroll
-        for (int dx = 0; dx < 5; ++dx) {
-          const double vv = vt[ro + cx[dx]], ll = lt[ro + cx[dx]];
-          const double un_v = un ? un[ro + cx[dx]] : 0.0;
-          const double u = b == 0 ? ll : vv;
-          const double f = ca * vv + cb * ll - un_v;
-          sm += mx[dx] * f;
-          sk += kx[dx] * u;
-          su += mx[dx] * u;
-          if (cn) cc += cn[dy * 5 + dx] * u;
-        }
-        mm += my[dy] * sm;
-        kk += my[dy] * sk + ky[dy] * su;
-      }
-      const double* pf = b == 0 ? lev(X1, t) + 2 * nq2 : lev(X0, t) + 2 * nq2;
-      const double bt = bt_node(pf, n, h, ix, iy, comp);
-      out = mm + tau * (nu * kk + cc) + tau * bt;
-    }
-  } else {
-    const int k = g - 2 * nq2;
-    if (k != 0) {
-      const int kx = k % np, ky = k / np;
-      const double* src = b == 0 ? lev(X1, t) : lev(X0, t);
-      out = tau * b_node(src, src + nq2, n, h, kx, ky);
-    }
-  }
-  y[((size_t)b * nt + t) * L + g] = out;
-}
 
 // Entry (k, j = 2k + off) of the 1-D mixed Q1-Q2 mass (m) and derivative (g)
 // rows, the same values as mixed_rows(k) at index off + 2 (zero outside).
@@ -143,112 +31,501 @@ __device__ __forceinline__ void mixed_at(int k, int off, int n, double h, double
   }
 }
 
-// Velocity rows without convection (Stokes) on LDS tiles.  A work-group owns
-// 64 x 32 interior output nodes of one grid (b, t, comp) and stages the two
-// fields its rows act on -- the mass field f = ca v_t + cb l_t - un and the
-// differentiated field u (l_t for the adjoint rows, v_t for the state rows) --
-// over the tile and a two-node halo, read once from HBM with coalesced rows.
-// Thread (column, strip of 8 rows) then walks its strip keeping the x-sums
-// (m' on f, k' and m' on u) of the five rows around the output row in
-// registers: 10 LDS reads per output.  B^T q comes from the 3 x 3 pressure
-// nodes around the output (Q1 field p_t or mu_t, read from L2).  The
-// Dirichlet ring is written by k_kkt_ring.
+// Oseen: momentum and divergence rows of one block row b at one time step t
+// on LDS tiles.  A work-group owns 64 x 32 interior Q2 nodes and the Q1 nodes whose
+// mixed stencils (Q2 nodes 2k - 2 .. 2k + 2 per direction) fall inside its
+// staged window: Q1 columns [32 bx + 1, 32 bx + 33) (from 0 in the first tile
+// column, up to n in the last), rows likewise with 16.  Per velocity
+// component it stages, over the tile and a two-node halo,
+//   F = ca v_t + cb l_t - un   (the field the mass matrix acts on)
+//   U = l_t (b = 0) or v_t (b = 1)   (the field K, N and B act on)
+// with all 30 global loads of a thread issued before the first is used, and
+// once per work-group the 35 x 19 Q1 window of the pressure field of B^T
+// (mu_t for b = 0, p_t for b = 1).  Thread (column, strip of 8 rows) walks
+// its strip keeping the x-sums (m' on F, k' and m' on U) of the five rows
+// around the output row in registers; B^T reads the Q1 window; the Oseen
+// convection stencil reads its 25 entries per node from an entry-major table
+// (coalesced) and U.  The divergence rows accumulate both components' B
+// terms over U in registers and are written after the second component.
+// The Dirichlet ring of the velocity rows is written by k_kkt_ring.
 constexpr int kVTX = 64, kVTY = 32, kVTS = 8;
-constexpr int kVLX = kVTX + 4, kVLY = kVTY + 4;
+constexpr int kVLX = kVTX + 4, kVLY = kVTY + 4, kVLN = kVLX * kVLY;
+constexpr int kPLX = kVTX / 2 + 3, kPLY = kVTY / 2 + 3, kPLN = kPLX * kPLY;
+constexpr int kVIt = (kVLN + 255) / 256, kPIt = (kPLN + 255) / 256;
+constexpr int kDivPer = 3;                                   // owned Q1 nodes per thread (33 x 17 <= 3 x 256)
+static_assert((kVTX / 2 + 1) * (kVTY / 2 + 1) <= kDivPer * 256, "divergence rows per thread");
+static_assert(kVTY == 4 * kVTS, "four strips of rows per tile");
 
-__global__ __launch_bounds__(256) void k_kkt_vel_tile(const double* __restrict__ x, double* __restrict__ y, int n,
-                                                      int nt, double tau, double beta, double nu, int ntx) {
-  __shared__ double F[kVLY * kVLX], U[kVLY * kVLX];
+template <bool CV>
+__global__ __launch_bounds__(256, 3) void k_kkt_tile(const double* __restrict__ x, double* __restrict__ y, int n, int nt,
+                                                  double tau, double beta, double nu,
+                                                  const double* __restrict__ convT, int ntx) {
+  __shared__ double F[kVLN], U[kVLN], Q[kPLN], D[kDivPer * 256];
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int L = 2 * nq2 + np2;
-  const int t = blockIdx.y, bc = blockIdx.z, b = bc >> 1, comp = bc & 1;
+  const int b = blockIdx.y, t = blockIdx.z;
   const int bx = blockIdx.x % ntx, by = blockIdx.x / ntx;
-  const int x0 = 1 + bx * kVTX, y0 = 1 + by * kVTY;      // first interior output node of the tile
-  const double* X0 = x;
-  const double* X1 = x + (size_t)nt * L;
-  const double* vt = X0 + (size_t)t * L + comp * nq2;
-  const double* lt = X1 + (size_t)t * L + comp * nq2;
-  const double* un = b == 0 ? (t + 1 < nt ? X1 + (size_t)(t + 1) * L + comp * nq2 : nullptr)
-                            : (t > 0 ? X0 + (size_t)(t - 1) * L + comp * nq2 : nullptr);
-  const double ca = b == 0 ? tau : 1.0, cb2 = b == 0 ? 1.0 : -tau / beta;
-  for (int e = threadIdx.x; e < kVLY * kVLX; e += blockDim.x) {
-    const int ly = e / kVLX, lx = e - ly * kVLX;
-    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-    double f = 0.0, u = 0.0;
-    if (gx >= 0 && gx < nq && gy >= 0 && gy < nq) {
-      const size_t o = (size_t)gy * nq + gx;
-      const double vv = vt[o], ll = lt[o];
-      f = ca * vv + cb2 * ll - (un ? un[o] : 0.0);
-      u = b == 0 ? ll : vv;
+  const int x0 = 1 + bx * kVTX, y0 = 1 + by * kVTY;          // first interior output node of the tile
+  const int qx0 = (x0 >> 1) - 1, qy0 = (y0 >> 1) - 1;        // first staged Q1 node
+  const double h = 1.0 / n;
+  const double* X0 = x + (size_t)t * L;                      // v_t, p_t
+  const double* X1 = x + (size_t)(nt + t) * L;               // l_t, mu_t
+  const bool has_un = b == 0 ? t + 1 < nt : t > 0;
+  const double* UN = b == 0 ? X1 + (has_un ? L : 0) : X0 - (has_un ? L : 0);   // l_{t+1} or v_{t-1}
+  const double ca = b == 0 ? tau : 1.0, cb = b == 0 ? 1.0 : -tau / beta;
+  // pressure field of B^T into Q (zero outside [0, n]^2)
+  {
+    const double* pf = (b == 0 ? X1 : X0) + 2 * nq2;
+    double qv[kPIt];
+#pragma unroll
+    for (int k = 0; k < kPIt; ++k) {
+      const int e = threadIdx.x + 256 * k, ly = e / kPLX, lx = e - ly * kPLX;
+      const int gx = qx0 + lx, gy = qy0 + ly;
+      const bool in = e < kPLN && gx >= 0 && gx <= n && gy >= 0 && gy <= n;
+      const double v = pf[(size_t)min(max(gy, 0), n) * np + min(max(gx, 0), n)];
+      qv[k] = in ? v : 0.0;
     }
-    F[e] = f;
-    U[e] = u;
+#pragma unroll
+    for (int k = 0; k < kPIt; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < kPLN) Q[e] = qv[k];
+    }
   }
-  __syncthreads();
   const int lx = threadIdx.x & (kVTX - 1), strip = threadIdx.x / kVTX;
   const int ix = x0 + lx;
-  if (ix > nq - 2) return;
-  const double h = 1.0 / n;
   double mx[5], kx[5], my[5], ky[5];
   q2_rows(ix, h, mx, kx);
-  const double* pf = (b == 0 ? X1 : X0) + (size_t)t * L + 2 * nq2;
   const int kx0 = (ix >> 1) - 1;
-  double wbx[3];
+  double wbm[3], wbg[3];                                     // mixed mass / derivative weights along x
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double m, g;
-    mixed_at(kx0 + c, ix - 2 * (kx0 + c), n, h, m, g);
-    wbx[c] = comp == 0 ? g : m;
-  }
-  double* yo = y + ((size_t)b * nt + t) * L + comp * nq2;
-  const int r0 = strip * kVTS;                           // first output row of the strip (tile-local)
-  double SM[5], SK[5], SU[5];
-  auto sums = [&](int lr, double& sm, double& sk, double& su) {   // lr: staged row (0 = y0 - 2)
-    const double* fr = F + lr * kVLX + lx;
-    const double* ur = U + lr * kVLX + lx;
-    sm = 0; sk = 0; su = 0;
+  for (int c = 0; c < 3; ++c) mixed_at(kx0 + c, ix - 2 * (kx0 + c), n, h, wbm[c], wbg[c]);
+  const int r0 = strip * kVTS;                               // first output row of the strip (tile-local)
+  // owned Q1 nodes
+  const int kxb = bx == 0 ? 0 : qx0 + 2, kxe = min(qx0 + 2 + kVTX / 2, n + 1);
+  const int kyb = by == 0 ? 0 : qy0 + 2, kye = min(qy0 + 2 + kVTY / 2, n + 1);
+  const int nkx = kxe - kxb, nk = nkx * (kye - kyb);
 #pragma unroll
-    for (int dx = 0; dx < 5; ++dx) {
-      sm += mx[dx] * fr[dx];
-      sk += kx[dx] * ur[dx];
-      su += mx[dx] * ur[dx];
-    }
-  };
-#pragma unroll
-  for (int d = 0; d < 4; ++d) sums(r0 + d, SM[d], SK[d], SU[d]);
+  for (int i = 0; i < kDivPer; ++i) D[threadIdx.x + 256 * i] = 0.0;   // divergence sums, one slot per owned node
+  double* Y = y + ((size_t)b * nt + t) * L;
 #pragma unroll 1
-  for (int i = 0; i < kVTS; ++i) {
-    const int iy = y0 + r0 + i;
-    sums(r0 + i + 4, SM[4], SK[4], SU[4]);
-    if (iy <= nq - 2) {
-      q2_rows(iy, h, my, ky);
-      double mm = 0, kk = 0;
+  for (int comp = 0; comp < 2; ++comp) {
+    const double* vt = X0 + comp * nq2;
+    const double* lt = X1 + comp * nq2;
+    const double* un = UN + comp * nq2;
+    double fv[kVIt], uv[kVIt];
 #pragma unroll
-      for (int d = 0; d < 5; ++d) {
-        mm += my[d] * SM[d];
-        kk += my[d] * SK[d] + ky[d] * SU[d];
+    for (int k = 0; k < kVIt; ++k) {
+      const int e = threadIdx.x + 256 * k, ly = e / kVLX, lxs = e - ly * kVLX;
+      const int gx = x0 - 2 + lxs, gy = y0 - 2 + ly;
+      const bool in = e < kVLN && gx >= 0 && gx < nq && gy >= 0 && gy < nq;
+      const size_t o = (size_t)min(max(gy, 0), nq - 1) * nq + min(max(gx, 0), nq - 1);
+      const double vv = vt[o], ll = lt[o], uu = un[o];
+      fv[k] = in ? ca * vv + cb * ll - (has_un ? uu : 0.0) : 0.0;
+      uv[k] = in ? (b == 0 ? ll : vv) : 0.0;
+    }
+    if (comp) __syncthreads();                               // the previous component's reads are done
+#pragma unroll
+    for (int k = 0; k < kVIt; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < kVLN) {
+        F[e] = fv[k];
+        U[e] = uv[k];
       }
-      const int ky0 = (iy >> 1) - 1;
-      double bt = 0.0;
+    }
+    __syncthreads();
+    // momentum rows of this component
+    if (ix <= nq - 2) {
+      double SM[5], SK[5], SU[5];
+      auto sums = [&](int lr, double& sm, double& sk, double& su) {   // lr: staged row (0 = y0 - 2)
+        const double* fr = F + lr * kVLX + lx;
+        const double* ur = U + lr * kVLX + lx;
+        sm = 0;
+        sk = 0;
+        su = 0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int kyy = ky0 + a;
-        if (kyy < 0 || kyy > n) continue;
-        double m, g;
-        mixed_at(kyy, iy - 2 * kyy, n, h, m, g);
-        const double* row = pf + (size_t)kyy * np;
+        for (int dx = 0; dx < 5; ++dx) {
+          sm += mx[dx] * fr[dx];
+          sk += kx[dx] * ur[dx];
+          su += mx[dx] * ur[dx];
+        }
+      };
+#pragma unroll
+      for (int d = 0; d < 4; ++d) sums(r0 + d, SM[d], SK[d], SU[d]);
+      double* yo = Y + comp * nq2;
+#pragma unroll 1
+      for (int i = 0; i < kVTS; ++i) {
+        const int iy = y0 + r0 + i;
+        sums(r0 + i + 4, SM[4], SK[4], SU[4]);
+        if (iy <= nq - 2) {
+          q2_rows(iy, h, my, ky);
+          double mm = 0, kk = 0;
+#pragma unroll
+          for (int d = 0; d < 5; ++d) {
+            mm += my[d] * SM[d];
+            kk += my[d] * SK[d] + ky[d] * SU[d];
+          }
+          const int ky0 = (iy >> 1) - 1;
+          double bt = 0.0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            double m, g;
+            mixed_at(ky0 + a, iy - 2 * (ky0 + a), n, h, m, g);
+            const double* row = Q + (ky0 + a - qy0) * kPLX + (kx0 - qx0);
+            const double rs = comp == 0 ? wbg[0] * row[0] + wbg[1] * row[1] + wbg[2] * row[2]
+                                        : wbm[0] * row[0] + wbm[1] * row[1] + wbm[2] * row[2];
+            bt += (comp == 0 ? m : g) * rs;
+          }
+          double out = mm + tau * nu * kk;
+          if (CV) {
+            // entries of N (b = 1) or N^T (b = 0) at this node, entry-major
+            const double* ct = convT + (size_t)(b == 0 ? 25 : 0) * nq2 + (size_t)iy * nq + ix;
+            double cc = 0.0;
+#pragma unroll
+            for (int dy = 0; dy < 5; ++dy) {
+              const double* ur = U + (r0 + i + dy) * kVLX + lx;
+#pragma unroll
+              for (int dx = 0; dx < 5; ++dx) cc += ct[(size_t)(dy * 5 + dx) * nq2] * ur[dx];
+            }
+            out += tau * cc;
+          }
+          yo[(size_t)iy * nq + ix] = out - tau * bt;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          SM[d] = SM[d + 1];
+          SK[d] = SK[d + 1];
+          SU[d] = SU[d + 1];
+        }
+      }
+    }
+    // divergence rows: this component's B term on U
+#pragma unroll 1
+    for (int e = threadIdx.x; e < nk; e += 256) {
+      const int kyy = kyb + e / nkx, kxx = kxb + e % nkx;
+      double wx[5], wy[5], w2[5];
+      if (comp == 0) {
+        mixed_rows(kxx, n, h, w2, wx);             // derivative along x
+        mixed_rows(kyy, n, h, wy, w2);             // mass along y
+      } else {
+        mixed_rows(kxx, n, h, wx, w2);             // mass along x
+        mixed_rows(kyy, n, h, w2, wy);             // derivative along y
+      }
+      // staged indices of Q2 nodes 2k - 2 .. 2k + 2 (those outside the window
+      // only ever meet zero weights: clamp them)
+      const int sx = 2 * kxx - x0, sy = 2 * kyy - y0;
+      double s = 0.0;
+#pragma unroll
+      for (int dy = 0; dy < 5; ++dy) {
+        const double* ur = U + min(max(sy + dy, 0), kVLY - 1) * kVLX;
         double rs = 0.0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int kxx = kx0 + c;
-          if (kxx >= 0 && kxx <= n) rs += wbx[c] * row[kxx];
-        }
-        bt += (comp == 0 ? m : g) * rs;
+        for (int dx = 0; dx < 5; ++dx) rs += wx[dx] * ur[min(max(sx + dx, 0), kVLX - 1)];
+        s += wy[dy] * rs;
       }
-      yo[(size_t)iy * nq + ix] = mm + tau * nu * kk - tau * bt;
+      D[e] += s;
     }
+  }
+#pragma unroll 1
+  for (int e = threadIdx.x; e < nk; e += 256) {
+    const int kyy = kyb + e / nkx, kxx = kxb + e % nkx, k = kyy * np + kxx;
+    Y[2 * nq2 + k] = k == 0 ? 0.0 : -tau * D[e];              // the pinned pressure row is zero
+  }
+}
+
+// Stokes: the same rows with time stepping.  A work-group owns one tile of
+// 64 x 16 interior Q2 nodes (with its Q1 nodes, chosen as above) for a span
+// of tc consecutive time steps and walks them in order, staging each field
+// once (v_t and l_t per component, p_t and mu_t) instead of once per block
+// row and again as the neighbouring step's field.  By linearity the mass
+// terms split into M v_t, M l_t of the current step, so a thread keeps per
+// output node and component
+//   MVp = M v_{t-1}                                  (state row at t)
+//   AP  = tau M v_{t-1} + M l_{t-1} + tau nu K l_{t-1} + tau B^T mu_{t-1}
+//                                                    (adjoint row at t-1, less M l_t)
+// in registers: the state row at t is written in step t, the adjoint row at
+// t - 1 in step t once M l_t is known.  A span starts one step early (M v
+// only) and ends one step late (M l only) unless it touches t = 0 or nt.
+// Row and column parities fix the 1-D weights, so M and K use the integer
+// weights m', k' with the scales applied once.  The global loads of the next
+// (step, component) phase are issued before the current phase computes, so
+// HBM latency overlaps the stencil work.
+constexpr int kSTX = 64, kSTY = 16, kSTS = 4;                // tile (interior Q2 nodes) and rows per thread
+constexpr int kSLX = kSTX + 4, kSLY = kSTY + 4, kSLN = kSLX * kSLY;
+constexpr int kSPX = kSTX / 2 + 3, kSPY = kSTY / 2 + 3, kSPN = kSPX * kSPY;
+constexpr int kSVIt = (kSLN + 255) / 256, kSPIt = (kSPN + 255) / 256;
+constexpr int kSDiv = 2;                                     // owned Q1 nodes per thread (33 x 9 <= 2 x 256)
+static_assert((kSTX / 2 + 1) * (kSTY / 2 + 1) <= kSDiv * 256, "divergence rows per thread");
+static_assert(kSTY == 4 * kSTS, "four strips of rows per tile");
+
+struct SpanStage {
+  double v[kSVIt], l[kSVIt], p[kSPIt], m[kSPIt];
+};
+
+// Issue the loads of step s, component c (v and/or l, and the two pressure
+// fields when wq) into registers; out-of-grid nodes read as zero.
+__device__ __forceinline__ void span_load(SpanStage& st, const double* __restrict__ x, int nq, int n, int L, int nt,
+                                          int s, int c, bool wv, bool wl, bool wq, int x0, int y0, int qx0, int qy0) {
+  const int nq2 = nq * nq, np = n + 1;
+  const double* vs = x + (size_t)s * L + c * nq2;
+  const double* ls = x + (size_t)(nt + s) * L + c * nq2;
 #pragma unroll
-    for (int d = 0; d < 4; ++d) { SM[d] = SM[d + 1]; SK[d] = SK[d + 1]; SU[d] = SU[d + 1]; }
+  for (int k = 0; k < kSVIt; ++k) {
+    const int e = threadIdx.x + 256 * k, ly = e / kSLX, lxs = e - ly * kSLX;
+    const int gx = x0 - 2 + lxs, gy = y0 - 2 + ly;
+    const bool in = e < kSLN && gx >= 0 && gx < nq && gy >= 0 && gy < nq;
+    const size_t o = (size_t)min(max(gy, 0), nq - 1) * nq + min(max(gx, 0), nq - 1);
+    if (wv) st.v[k] = in ? vs[o] : 0.0;
+    if (wl) st.l[k] = in ? ls[o] : 0.0;
+  }
+  if (wq) {
+    const double* ps = x + (size_t)s * L + 2 * nq2;
+    const double* ms = x + (size_t)(nt + s) * L + 2 * nq2;
+#pragma unroll
+    for (int k = 0; k < kSPIt; ++k) {
+      const int e = threadIdx.x + 256 * k, ly = e / kSPX, lx = e - ly * kSPX;
+      const int gx = qx0 + lx, gy = qy0 + ly;
+      const bool in = e < kSPN && gx >= 0 && gx <= n && gy >= 0 && gy <= n;
+      const size_t o = (size_t)min(max(gy, 0), n) * np + min(max(gx, 0), n);
+      st.p[k] = in ? ps[o] : 0.0;
+      st.m[k] = in ? ms[o] : 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void span_store(const SpanStage& st, double* V, double* Lm, double* QP, double* QM, bool wv,
+                                           bool wl, bool wq) {
+#pragma unroll
+  for (int k = 0; k < kSVIt; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < kSLN) {
+      if (wv) V[e] = st.v[k];
+      if (wl) Lm[e] = st.l[k];
+    }
+  }
+  if (wq) {
+#pragma unroll
+    for (int k = 0; k < kSPIt; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < kSPN) {
+        QP[e] = st.p[k];
+        QM[e] = st.m[k];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ x, double* __restrict__ y, int n,
+                                                     int nt, double tau, double beta, double nu, int ntx, int tc) {
+  __shared__ double V[kSLN], Lm[kSLN], QP[kSPN], QM[kSPN], DV[kSDiv * 256], DL[kSDiv * 256];
+  const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
+  const int L = 2 * nq2 + np2;
+  const int bx = blockIdx.x % ntx, by = blockIdx.x / ntx;
+  const int x0 = 1 + bx * kSTX, y0 = 1 + by * kSTY;
+  const int qx0 = (x0 >> 1) - 1, qy0 = (y0 >> 1) - 1;
+  const int t0 = blockIdx.y * tc, t1 = min(t0 + tc, nt);
+  const int sb = t0 > 0 ? t0 - 1 : t0, se = t1 < nt ? t1 : t1 - 1;
+  const double h = 1.0 / n, tb = tau / beta, tn = tau * nu;
+  const int kxb = bx == 0 ? 0 : qx0 + 2, kxe = min(qx0 + 2 + kSTX / 2, n + 1);
+  const int kyb = by == 0 ? 0 : qy0 + 2, kye = min(qy0 + 2 + kSTY / 2, n + 1);
+  const int nkx = kxe - kxb, nk = nkx * (kye - kyb);
+#pragma unroll
+  for (int i = 0; i < kSDiv; ++i) {
+    DV[threadIdx.x + 256 * i] = 0.0;
+    DL[threadIdx.x + 256 * i] = 0.0;
+  }
+  double MVp[2][kSTS], AP[2][kSTS];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < kSTS; ++i) {
+      MVp[c][i] = 0.0;
+      AP[c][i] = 0.0;
+    }
+
+  // one (step, component) phase over the staged fields
+  auto phase = [&](int s, auto cc) {
+    constexpr int c = decltype(cc)::value;
+    const bool pro = s < t0, epi = s >= t1;
+    // Per-lane geometry, recomputed in every phase from a thread index the
+    // compiler may not treat as loop-invariant: hoisting these values (and the
+    // addresses derived from them) out of the step loop would hold far more
+    // registers than recomputing them costs.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lx = tid & (kSTX - 1);
+    const int r0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kSTX) * kSTS;   // wave-uniform strip
+    const int ix = x0 + lx;
+    const bool colin = ix <= nq - 2;
+    // integer x-weights of the column (vertex: m' = (-1, 2, 8, 2, -1), k' = (1, -8, 14, -8, 1);
+    // midpoint: m' = (0, 2, 16, 2, 0), k' = (0, -8, 16, -8, 0)); the scales h/30 and
+    // 1/(3h) are applied with the y-weights
+    const bool xvert = (ix & 1) == 0;
+    const double m04 = xvert ? -1.0 : 0.0, m2 = xvert ? 8.0 : 16.0, k04 = xvert ? 1.0 : 0.0, k2 = xvert ? 14.0 : 16.0;
+    const int kx0 = (ix >> 1) - 1;
+    if (colin) {
+      double S[5][4];                          // x-sums per staged row: m' v, k' v, m' l, k' l
+      auto sums = [&](int lr, double* o) {
+        const double* vr = V + lr * kSLX + lx;
+        const double* lr_ = Lm + lr * kSLX + lx;
+        const double v04 = vr[0] + vr[4], v13 = vr[1] + vr[3], l04 = lr_[0] + lr_[4], l13 = lr_[1] + lr_[3];
+        o[0] = fma(m04, v04, fma(2.0, v13, m2 * vr[2]));
+        o[1] = fma(k04, v04, fma(-8.0, v13, k2 * vr[2]));
+        o[2] = fma(m04, l04, fma(2.0, l13, m2 * lr_[2]));
+        o[3] = fma(k04, l04, fma(-8.0, l13, k2 * lr_[2]));
+      };
+#pragma unroll
+      for (int d = 0; d < 4; ++d) sums(r0 + d, S[d]);
+      double* Ys = y + ((size_t)(nt + s)) * L + c * nq2;       // state rows at s
+      double* Ya = y + (size_t)max(s - 1, 0) * L + c * nq2;    // adjoint rows at s - 1 (s > 0 when written)
+      double* Yl = y + (size_t)s * L + c * nq2;                // adjoint rows at s (s = nt - 1)
+      // Output row iy = y0 + r0 + i has the parity of i + 1 (y0 odd, r0 even),
+      // so its 1-D Q2 weights (h/30 m', 1/(3h) k') and, for an interior row,
+      // its mixed weights over the Q1 rows around it are fixed per i.
+      const double smm = (h / 30.0) * (h / 30.0), smk = (h / 30.0) / (3.0 * h), h3 = h / 3.0;
+#pragma unroll
+      for (int i = 0; i < kSTS; ++i) {
+        const int iy = y0 + r0 + i;
+        sums(r0 + i + 4, S[4]);
+        if (iy <= nq - 2) {
+          const bool vert = (i & 1) == 1;            // iy even: a vertex row
+          double MV, KV, ML, KL;
+          {
+            double a0, a1, a2, a3, b0, b2;           // m'-combinations of the four sums, k'-combinations of m-sums
+            if (vert) {
+              a0 = 8 * S[2][0] + 2 * (S[1][0] + S[3][0]) - (S[0][0] + S[4][0]);
+              a1 = 8 * S[2][1] + 2 * (S[1][1] + S[3][1]) - (S[0][1] + S[4][1]);
+              a2 = 8 * S[2][2] + 2 * (S[1][2] + S[3][2]) - (S[0][2] + S[4][2]);
+              a3 = 8 * S[2][3] + 2 * (S[1][3] + S[3][3]) - (S[0][3] + S[4][3]);
+              b0 = 14 * S[2][0] - 8 * (S[1][0] + S[3][0]) + (S[0][0] + S[4][0]);
+              b2 = 14 * S[2][2] - 8 * (S[1][2] + S[3][2]) + (S[0][2] + S[4][2]);
+            } else {
+              a0 = 16 * S[2][0] + 2 * (S[1][0] + S[3][0]);
+              a1 = 16 * S[2][1] + 2 * (S[1][1] + S[3][1]);
+              a2 = 16 * S[2][2] + 2 * (S[1][2] + S[3][2]);
+              a3 = 16 * S[2][3] + 2 * (S[1][3] + S[3][3]);
+              b0 = 16 * S[2][0] - 8 * (S[1][0] + S[3][0]);
+              b2 = 16 * S[2][2] - 8 * (S[1][2] + S[3][2]);
+            }
+            MV = smm * a0;
+            KV = smk * (a1 + b0);
+            ML = smm * a2;
+            KL = smk * (a3 + b2);
+          }
+          const size_t o = (size_t)iy * nq + ix;
+          if (pro) {
+            MVp[c][i] = MV;
+          } else if (epi) {
+            Ya[o] = AP[c][i] - ML;
+          } else {
+            // B^T: Q1 rows around iy with their mixed mass (m) / derivative (g) weights
+            const int kr = (iy >> 1) - 1 - qy0;          // window row of Q1 row (iy >> 1) - 1
+            const int qo = kr * kSPX + (kx0 - qx0);
+            double w[3];                                 // x-weights of B^T: derivative (c = 0) or mass (c = 1)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              double m, g;
+              mixed_at(kx0 + q, ix - 2 * (kx0 + q), n, h, m, g);
+              w[q] = c == 0 ? g : m;
+            }
+            auto rowp = [&](const double* Q, int r) {
+              return w[0] * Q[qo + r * kSPX] + w[1] * Q[qo + r * kSPX + 1] + w[2] * Q[qo + r * kSPX + 2];
+            };
+            double btp, btm;
+            if (vert) {                                  // rows k-1, k, k+1: m = (0, h/3, 0), g = (1/6, 0, -1/6)
+              if (c == 0) {
+                btp = h3 * rowp(QP, 1);
+                btm = h3 * rowp(QM, 1);
+              } else {
+                btp = (1.0 / 6.0) * (rowp(QP, 0) - rowp(QP, 2));
+                btm = (1.0 / 6.0) * (rowp(QM, 0) - rowp(QM, 2));
+              }
+            } else {                                     // rows k, k+1: m = (h/3, h/3), g = (2/3, -2/3)
+              if (c == 0) {
+                btp = h3 * (rowp(QP, 1) + rowp(QP, 2));
+                btm = h3 * (rowp(QM, 1) + rowp(QM, 2));
+              } else {
+                btp = (2.0 / 3.0) * (rowp(QP, 1) - rowp(QP, 2));
+                btm = (2.0 / 3.0) * (rowp(QM, 1) - rowp(QM, 2));
+              }
+            }
+            Ys[o] = MV - MVp[c][i] - tb * ML + tn * KV - tau * btp;
+            MVp[c][i] = MV;
+            const double ap = tau * MV + ML + tn * KL - tau * btm;
+            if (s > t0) Ya[o] = AP[c][i] - ML;
+            if (s == nt - 1) Yl[o] = ap;
+            AP[c][i] = ap;
+          }
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) S[d][q] = S[d + 1][q];
+      }
+    }
+    if (pro || epi) return;
+    // divergence rows: this component's B terms on v_s and l_s
+    const int kxb = bx == 0 ? 0 : qx0 + 2, kxe = min(qx0 + 2 + kSTX / 2, n + 1);
+    const int kyb = by == 0 ? 0 : qy0 + 2, kye = min(qy0 + 2 + kSTY / 2, n + 1);
+    const int nkx = kxe - kxb, nk = nkx * (kye - kyb);
+#pragma unroll 1
+    for (int e = tid; e < nk; e += 256) {
+      const int kyy = kyb + e / nkx, kxx = kxb + e % nkx;
+      double wx[5], wy[5], w2[5];
+      if (c == 0) {
+        mixed_rows(kxx, n, h, w2, wx);
+        mixed_rows(kyy, n, h, wy, w2);
+      } else {
+        mixed_rows(kxx, n, h, wx, w2);
+        mixed_rows(kyy, n, h, w2, wy);
+      }
+      const int sx = 2 * kxx - x0, sy = 2 * kyy - y0;
+      double sv = 0.0, sl = 0.0;
+#pragma unroll
+      for (int dy = 0; dy < 5; ++dy) {
+        const int ro = min(max(sy + dy, 0), kSLY - 1) * kSLX;
+        double rv = 0.0, rl = 0.0;
+#pragma unroll
+        for (int dx = 0; dx < 5; ++dx) {
+          const int q = ro + min(max(sx + dx, 0), kSLX - 1);
+          rv += wx[dx] * V[q];
+          rl += wx[dx] * Lm[q];
+        }
+        sv += wy[dy] * rv;
+        sl += wy[dy] * rl;
+      }
+      if (c == 0) {
+        DV[e] += sv;
+        DL[e] += sl;
+      } else {
+        const int k = kyy * np + kxx;
+        const double dv = DV[e] + sv, dl = DL[e] + sl;
+        y[(size_t)(nt + s) * L + 2 * nq2 + k] = k == 0 ? 0.0 : -tau * dv;     // state divergence
+        y[(size_t)s * L + 2 * nq2 + k] = k == 0 ? 0.0 : -tau * dl;            // adjoint divergence
+        DV[e] = 0.0;
+        DL[e] = 0.0;
+      }
+    }
+  };
+
+  SpanStage st;
+  span_load(st, x, nq, n, L, nt, sb, 0, true, sb >= t0, sb >= t0, x0, y0, qx0, qy0);
+#pragma unroll 1
+  for (int s = sb; s <= se; ++s) {
+    const bool pro = s < t0, epi = s >= t1, wq = !pro && !epi;
+    const bool wv = !epi, wl = !pro;
+    span_store(st, V, Lm, QP, QM, wv, wl, wq);
+    __syncthreads();
+    span_load(st, x, nq, n, L, nt, s, 1, wv, wl, false, x0, y0, qx0, qy0);
+    phase(s, std::integral_constant<int, 0>{});
+    __syncthreads();
+    span_store(st, V, Lm, QP, QM, wv, wl, false);
+    __syncthreads();
+    if (s < se) {
+      const bool npro = s + 1 < t0, nepi = s + 1 >= t1;
+      span_load(st, x, nq, n, L, nt, s + 1, 0, !nepi, !npro, !npro && !nepi, x0, y0, qx0, qy0);
+    }
+    phase(s, std::integral_constant<int, 1>{});
+    __syncthreads();
   }
 }
 
@@ -417,21 +694,33 @@ void launch_scale_canon(hipStream_t s, double* y, const double* x, int n, int nt
   hipLaunchKernelGGL(k_scale_canon, dim3((L + 255) / 256, 2 * nt), dim3(256), 0, s, y, x, n, nt, sv, sp);
 }
 
+// Time steps per span of k_kkt_span: long spans save the extra first and
+// last step of each span, short ones give more work-groups; aim at about 512
+// work-groups (two resident per CU), spans of 4 to 32 steps.  (At N = 128,
+// nt = 256 spans of 8, 16 and 32 steps took 0.53, 0.52 and 0.50 ms.)
+static int kkt_span_steps(int tiles, int nt) {
+  int tc = 4;
+  while (tc < 32 && (long)tiles * ((nt + 2 * tc - 1) / (2 * tc)) >= 512) tc *= 2;
+  return tc;
+}
+
 void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, double tau, double beta, double nu,
-                      const double* conv) {
+                      const double* convT) {
   const int nq = 2 * n + 1, L = 2 * nq * nq + (n + 1) * (n + 1);
-  if (conv) {                               // Oseen: every entry per thread
-    hipLaunchKernelGGL(k_kkt_apply, dim3((L + 255) / 256, nt, 2), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, conv,
-                       0);
-    return;
+  (void)L;
+  // momentum and divergence rows on LDS tiles, then the Dirichlet ring of the
+  // momentum rows
+  if (convT) {                // Oseen: one work-group per (tile, block row, step)
+    const int ntx = (nq - 2 + kVTX - 1) / kVTX, nty = (nq - 2 + kVTY - 1) / kVTY;
+    hipLaunchKernelGGL(k_kkt_tile<true>, dim3(ntx * nty, 2, nt), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, convT,
+                       ntx);
+  } else {                    // Stokes: one work-group per (tile, span of tc steps)
+    const int ntx = (nq - 2 + kSTX - 1) / kSTX, nty = (nq - 2 + kSTY - 1) / kSTY;
+    const int tc = kkt_span_steps(ntx * nty, nt);
+    hipLaunchKernelGGL(k_kkt_span, dim3(ntx * nty, (nt + tc - 1) / tc), dim3(256), 0, s, x, y, n, nt, tau, beta,
+                       nu, ntx, tc);
   }
-  // Stokes: velocity rows on LDS tiles (and the Dirichlet ring), pressure rows per entry
-  const int ntx = (nq - 2 + kVTX - 1) / kVTX, nty = (nq - 2 + kVTY - 1) / kVTY;
-  hipLaunchKernelGGL(k_kkt_vel_tile, dim3(ntx * nty, nt, 4), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, ntx);
   hipLaunchKernelGGL(k_kkt_ring, dim3((4 * (nq - 1) + 255) / 256, nt, 4), dim3(256), 0, s, y, n, nt);
-  const int g0 = 2 * nq * nq, np2 = (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_kkt_apply, dim3((np2 + 255) / 256, nt, 2), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, conv,
-                     g0);
 }
 
 void launch_assemble_rhs(hipStream_t s, const double* vd, double* b, int n, int nt, double tau) {

@@ -168,7 +168,9 @@ struct pintoc_problem {
   std::vector<double> sconv_h[2];              // levels n <= kQ2SmallN (above the coarsest): per-node layout
   void* sconv[2] = {nullptr, nullptr};         // device, in the inner precision
   int sconv_n = 0;                             // finest level of the small tables
-  double* conv50 = nullptr;                   // finest level, 50 per node (block and all-at-once matrices)
+  double* conv50 = nullptr;                   // finest level, 50 per node (block matrices)
+  std::vector<double> conv50t_h;              // finest level entry-major: entry e of node g at e nq^2 + g
+  double* conv50t = nullptr;                  // device copy (all-at-once matrix)
   std::vector<double*> conv50l;               // every level, 50 per node (global smoother only; [0] = conv50)
   double* conv1 = nullptr;
   MGPlan mgQ, mgQH;
@@ -410,6 +412,7 @@ static void carve(pintoc_problem* p, char* base) {
   p->maskd = cv.take<int>(sizeof(int) * nf);
   if (p->d.flow == PINTOC_OSEEN) {
     p->conv50 = cv.take<double>(sizeof(double) * p->conv2_h[0].size());
+    p->conv50t = cv.take<double>(sizeof(double) * p->conv50t_h.size());
     for (int hf = 0; hf < 2; ++hf) {
       p->tconv[hf].assign(p->tconv_h[hf].size(), nullptr);
       for (size_t l = 0; l < p->tconv_h[hf].size(); ++l)
@@ -753,6 +756,12 @@ static int create_impl(const pintoc_problem_desc* ds, int nm, const pintoc_optio
           ly[(size_t)iy * nql + ix] = wy[(size_t)(iy * st) * nq + ix * st];
         }
       conv_tables(n, lx.data(), ly.data(), p->conv2_h[l], l == 0 ? &p->conv1_h : nullptr);
+      if (l == 0) {
+        const size_t nn = (size_t)nql * nql;
+        p->conv50t_h.resize(50 * nn);
+        for (size_t g = 0; g < nn; ++g)
+          for (int e = 0; e < 50; ++e) p->conv50t_h[(size_t)e * nn + g] = p->conv2_h[0][g * 50 + e];
+      }
       if (l + 1 < nl)
         for (int hf = 0; hf < 2; ++hf) {
           p->tconv_h[hf].emplace_back(q2_tile_conv_entries(n));
@@ -1023,6 +1032,8 @@ static int bind_impl(pintoc_problem* p, void* dev, size_t bytes, hipStream_t s) 
   }
   if (p->d.flow == PINTOC_OSEEN) {
     HIPCHK(hipMemcpyAsync(p->conv50, p->conv2_h[0].data(), sizeof(double) * p->conv2_h[0].size(),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->conv50t, p->conv50t_h.data(), sizeof(double) * p->conv50t_h.size(),
                           hipMemcpyHostToDevice, s));
     auto upload = [&](void* dst, const std::vector<double>& t) -> int {
       if (p->csize == 16) {
@@ -1829,7 +1840,7 @@ static void kkt_member(pintoc_problem* p, int k, const double* x, double* y, hip
     launch_scale_canon(s, p->dscale, x, p->d.N, mb.nt, 1.0, 1.0 / l);
     x = p->dscale;
   }
-  launch_kkt_apply(s, x, y, p->d.N, mb.nt, mb.tau, mb.beta, mb.nu, p->d.flow == PINTOC_OSEEN ? p->conv50 : nullptr);
+  launch_kkt_apply(s, x, y, p->d.N, mb.nt, mb.tau, mb.beta, mb.nu, p->d.flow == PINTOC_OSEEN ? p->conv50t : nullptr);
   if (l != 1.0) launch_scale_canon(s, y, y, p->d.N, mb.nt, l * l, l);
 }
 
