@@ -268,9 +268,11 @@ __device__ __forceinline__ void span_load(SpanStage& st, const double* __restric
   const int nq2 = nq * nq, np = n + 1;
   const double* vs = x + (size_t)s * L + c * nq2;
   const double* ls = x + (size_t)(nt + s) * L + c * nq2;
+  int tid = threadIdx.x;                 // recomputed offsets, not held across the step loop
+  asm volatile("" : "+v"(tid));
 #pragma unroll
   for (int k = 0; k < kSVIt; ++k) {
-    const int e = threadIdx.x + 256 * k, ly = e / kSLX, lxs = e - ly * kSLX;
+    const int e = tid + 256 * k, ly = e / kSLX, lxs = e - ly * kSLX;
     const int gx = x0 - 2 + lxs, gy = y0 - 2 + ly;
     const bool in = e < kSLN && gx >= 0 && gx < nq && gy >= 0 && gy < nq;
     const size_t o = (size_t)min(max(gy, 0), nq - 1) * nq + min(max(gx, 0), nq - 1);
@@ -282,7 +284,7 @@ __device__ __forceinline__ void span_load(SpanStage& st, const double* __restric
     const double* ms = x + (size_t)(nt + s) * L + 2 * nq2;
 #pragma unroll
     for (int k = 0; k < kSPIt; ++k) {
-      const int e = threadIdx.x + 256 * k, ly = e / kSPX, lx = e - ly * kSPX;
+      const int e = tid + 256 * k, ly = e / kSPX, lx = e - ly * kSPX;
       const int gx = qx0 + lx, gy = qy0 + ly;
       const bool in = e < kSPN && gx >= 0 && gx <= n && gy >= 0 && gy <= n;
       const size_t o = (size_t)min(max(gy, 0), n) * np + min(max(gx, 0), n);
@@ -314,8 +316,14 @@ __device__ __forceinline__ void span_store(const SpanStage& st, double* V, doubl
   }
 }
 
+// Uniform scalars of k_kkt_span, computed on the host (kernel arguments stay
+// in scalar registers instead of occupying vector registers).
+struct SpanScal {
+  double tau, tb, tn, h, smm, smk, h3, c16, c23;   // tau, tau/beta, tau nu, h, (h/30)^2, (h/30)/(3h), h/3, 1/6, 2/3
+};
+
 __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ x, double* __restrict__ y, int n,
-                                                     int nt, double tau, double beta, double nu, int ntx, int tc) {
+                                                     int nt, SpanScal sc, int ntx, int tc) {
   __shared__ double V[kSLN], Lm[kSLN], QP[kSPN], QM[kSPN], DV[kSDiv * 256], DL[kSDiv * 256];
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int L = 2 * nq2 + np2;
@@ -324,7 +332,7 @@ __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ 
   const int qx0 = (x0 >> 1) - 1, qy0 = (y0 >> 1) - 1;
   const int t0 = blockIdx.y * tc, t1 = min(t0 + tc, nt);
   const int sb = t0 > 0 ? t0 - 1 : t0, se = t1 < nt ? t1 : t1 - 1;
-  const double h = 1.0 / n, tb = tau / beta, tn = tau * nu;
+  const double tau = sc.tau, tb = sc.tb, tn = sc.tn, h = sc.h;
   const int kxb = bx == 0 ? 0 : qx0 + 2, kxe = min(qx0 + 2 + kSTX / 2, n + 1);
   const int kyb = by == 0 ? 0 : qy0 + 2, kye = min(qy0 + 2 + kSTY / 2, n + 1);
   const int nkx = kxe - kxb, nk = nkx * (kye - kyb);
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ 
       // Output row iy = y0 + r0 + i has the parity of i + 1 (y0 odd, r0 even),
       // so its 1-D Q2 weights (h/30 m', 1/(3h) k') and, for an interior row,
       // its mixed weights over the Q1 rows around it are fixed per i.
-      const double smm = (h / 30.0) * (h / 30.0), smk = (h / 30.0) / (3.0 * h), h3 = h / 3.0;
+      const double smm = sc.smm, smk = sc.smk, h3 = sc.h3;
 #pragma unroll
       for (int i = 0; i < kSTS; ++i) {
         const int iy = y0 + r0 + i;
@@ -392,19 +400,20 @@ __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ 
           {
             double a0, a1, a2, a3, b0, b2;           // m'-combinations of the four sums, k'-combinations of m-sums
             if (vert) {
-              a0 = 8 * S[2][0] + 2 * (S[1][0] + S[3][0]) - (S[0][0] + S[4][0]);
-              a1 = 8 * S[2][1] + 2 * (S[1][1] + S[3][1]) - (S[0][1] + S[4][1]);
-              a2 = 8 * S[2][2] + 2 * (S[1][2] + S[3][2]) - (S[0][2] + S[4][2]);
-              a3 = 8 * S[2][3] + 2 * (S[1][3] + S[3][3]) - (S[0][3] + S[4][3]);
-              b0 = 14 * S[2][0] - 8 * (S[1][0] + S[3][0]) + (S[0][0] + S[4][0]);
-              b2 = 14 * S[2][2] - 8 * (S[1][2] + S[3][2]) + (S[0][2] + S[4][2]);
+              // integer weights by exponent shifts (exact) and inline constants
+              a0 = ldexp(S[2][0], 3) + 2 * (S[1][0] + S[3][0]) - (S[0][0] + S[4][0]);
+              a1 = ldexp(S[2][1], 3) + 2 * (S[1][1] + S[3][1]) - (S[0][1] + S[4][1]);
+              a2 = ldexp(S[2][2], 3) + 2 * (S[1][2] + S[3][2]) - (S[0][2] + S[4][2]);
+              a3 = ldexp(S[2][3], 3) + 2 * (S[1][3] + S[3][3]) - (S[0][3] + S[4][3]);
+              b0 = fma(-2.0, S[2][0], ldexp(S[2][0], 4)) - ldexp(S[1][0] + S[3][0], 3) + (S[0][0] + S[4][0]);
+              b2 = fma(-2.0, S[2][2], ldexp(S[2][2], 4)) - ldexp(S[1][2] + S[3][2], 3) + (S[0][2] + S[4][2]);
             } else {
-              a0 = 16 * S[2][0] + 2 * (S[1][0] + S[3][0]);
-              a1 = 16 * S[2][1] + 2 * (S[1][1] + S[3][1]);
-              a2 = 16 * S[2][2] + 2 * (S[1][2] + S[3][2]);
-              a3 = 16 * S[2][3] + 2 * (S[1][3] + S[3][3]);
-              b0 = 16 * S[2][0] - 8 * (S[1][0] + S[3][0]);
-              b2 = 16 * S[2][2] - 8 * (S[1][2] + S[3][2]);
+              a0 = ldexp(S[2][0], 4) + 2 * (S[1][0] + S[3][0]);
+              a1 = ldexp(S[2][1], 4) + 2 * (S[1][1] + S[3][1]);
+              a2 = ldexp(S[2][2], 4) + 2 * (S[1][2] + S[3][2]);
+              a3 = ldexp(S[2][3], 4) + 2 * (S[1][3] + S[3][3]);
+              b0 = ldexp(S[2][0], 4) - ldexp(S[1][0] + S[3][0], 3);
+              b2 = ldexp(S[2][2], 4) - ldexp(S[1][2] + S[3][2], 3);
             }
             MV = smm * a0;
             KV = smk * (a1 + b0);
@@ -420,12 +429,17 @@ __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ 
             // B^T: Q1 rows around iy with their mixed mass (m) / derivative (g) weights
             const int kr = (iy >> 1) - 1 - qy0;          // window row of Q1 row (iy >> 1) - 1
             const int qo = kr * kSPX + (kx0 - qx0);
-            double w[3];                                 // x-weights of B^T: derivative (c = 0) or mass (c = 1)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              double m, g;
-              mixed_at(kx0 + q, ix - 2 * (kx0 + q), n, h, m, g);
-              w[q] = c == 0 ? g : m;
+            // x-weights of B^T over Q1 columns kx0 .. kx0 + 2 (derivative for c = 0,
+            // mass for c = 1), fixed by the parity of the interior column ix
+            double w[3];
+            if (c == 0) {
+              w[0] = xvert ? sc.c16 : 0.0;
+              w[1] = xvert ? 0.0 : sc.c23;
+              w[2] = xvert ? -sc.c16 : -sc.c23;
+            } else {
+              w[0] = 0.0;
+              w[1] = sc.h3;
+              w[2] = xvert ? 0.0 : sc.h3;
             }
             auto rowp = [&](const double* Q, int r) {
               return w[0] * Q[qo + r * kSPX] + w[1] * Q[qo + r * kSPX + 1] + w[2] * Q[qo + r * kSPX + 2];
@@ -436,16 +450,16 @@ __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ 
                 btp = h3 * rowp(QP, 1);
                 btm = h3 * rowp(QM, 1);
               } else {
-                btp = (1.0 / 6.0) * (rowp(QP, 0) - rowp(QP, 2));
-                btm = (1.0 / 6.0) * (rowp(QM, 0) - rowp(QM, 2));
+                btp = sc.c16 * (rowp(QP, 0) - rowp(QP, 2));
+                btm = sc.c16 * (rowp(QM, 0) - rowp(QM, 2));
               }
             } else {                                     // rows k, k+1: m = (h/3, h/3), g = (2/3, -2/3)
               if (c == 0) {
                 btp = h3 * (rowp(QP, 1) + rowp(QP, 2));
                 btm = h3 * (rowp(QM, 1) + rowp(QM, 2));
               } else {
-                btp = (2.0 / 3.0) * (rowp(QP, 1) - rowp(QP, 2));
-                btm = (2.0 / 3.0) * (rowp(QM, 1) - rowp(QM, 2));
+                btp = sc.c23 * (rowp(QP, 1) - rowp(QP, 2));
+                btm = sc.c23 * (rowp(QM, 1) - rowp(QM, 2));
               }
             }
             Ys[o] = MV - MVp[c][i] - tb * ML + tn * KV - tau * btp;
@@ -717,8 +731,10 @@ void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, 
   } else {                    // Stokes: one work-group per (tile, span of tc steps)
     const int ntx = (nq - 2 + kSTX - 1) / kSTX, nty = (nq - 2 + kSTY - 1) / kSTY;
     const int tc = kkt_span_steps(ntx * nty, nt);
-    hipLaunchKernelGGL(k_kkt_span, dim3(ntx * nty, (nt + tc - 1) / tc), dim3(256), 0, s, x, y, n, nt, tau, beta,
-                       nu, ntx, tc);
+    const double h = 1.0 / n;
+    const SpanScal sc{tau, tau / beta, tau * nu, h, (h / 30.0) * (h / 30.0), (h / 30.0) / (3.0 * h), h / 3.0,
+                      1.0 / 6.0, 2.0 / 3.0};
+    hipLaunchKernelGGL(k_kkt_span, dim3(ntx * nty, (nt + tc - 1) / tc), dim3(256), 0, s, x, y, n, nt, sc, ntx, tc);
   }
   hipLaunchKernelGGL(k_kkt_ring, dim3((4 * (nq - 1) + 255) / 256, nt, 4), dim3(256), 0, s, y, n, nt);
 }
