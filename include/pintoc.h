@@ -167,6 +167,19 @@ typedef struct {
                              results); eager launches while the timing probe
                              records, for the global smoother and on the
                              legacy null stream.  0 (default) = eager.       */
+  int32_t z_fp32;          /* 1 = keep the outer FGMRES basis Z of
+                             preconditioned vectors (section 3.4) in FP32.
+                             They come from the FP32 inner solves, so FP32
+                             storage drops nothing they carry; the solution
+                             update x += Z y reads them and the true residual
+                             taken at every restart corrects the rest (the
+                             outer loop acts as iterative refinement).  The
+                             outer method's vectors shrink from 2 restart + 3
+                             to 1.5 restart + 3 canonical FP64 vectors (at
+                             restart 10 and N = 128, nt = 256: 3.0 GB less).
+                             Needs PINTOC_PREC_FP32_INNER and
+                             PINTOC_OUTER_FGMRES (EINVAL otherwise).
+                             0 (default) = FP64.                             */
 } pintoc_options;
 
 /* Phases of a solve whose device time pintoc_solve_stats reports. */

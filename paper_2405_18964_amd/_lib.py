@@ -32,7 +32,7 @@ class Options(C.Structure):
                 ("inner_restart", C.c_int32), ("inner_maxit", C.c_int32), ("n_vcycles", C.c_int32),
                 ("n_cheb", C.c_int32), ("n_uzawa", C.c_int32), ("mu_uzawa", C.c_double),
                 ("stall_guard", C.c_int32), ("outer", C.c_int32), ("smoother", C.c_int32),
-                ("pressure_stream", C.c_int32), ("graphs", C.c_int32)]
+                ("pressure_stream", C.c_int32), ("graphs", C.c_int32), ("z_fp32", C.c_int32)]
 
 
 NPHASES = 5

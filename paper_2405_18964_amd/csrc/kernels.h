@@ -110,6 +110,8 @@ void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b,
 void launch_axpbypcz(hipStream_t s, double* y, const double* x, const double* z, double a, double b, double c,
                      size_t n);
 void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, int k, const double* c, size_t n);
+void launch_to_f32(hipStream_t s, float* y, const double* x, size_t n);
+void launch_lincomb_add_f32(hipStream_t s, double* y, const float* Z, size_t ld, int k, const double* c, size_t n);
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
 
 // outer Krylov method in the frequency domain (freq_kernels.hip)

@@ -56,7 +56,6 @@ constexpr int kDivPer = 3;                                   // owned Q1 nodes p
 static_assert((kVTX / 2 + 1) * (kVTY / 2 + 1) <= kDivPer * 256, "divergence rows per thread");
 static_assert(kVTY == 4 * kVTS, "four strips of rows per tile");
 
-template <bool CV>
 __global__ __launch_bounds__(256, 3) void k_kkt_tile(const double* __restrict__ x, double* __restrict__ y, int n, int nt,
                                                   double tau, double beta, double nu,
                                                   const double* __restrict__ convT, int ntx) {
@@ -175,20 +174,16 @@ __global__ __launch_bounds__(256, 3) void k_kkt_tile(const double* __restrict__ 
                                         : wbm[0] * row[0] + wbm[1] * row[1] + wbm[2] * row[2];
             bt += (comp == 0 ? m : g) * rs;
           }
-          double out = mm + tau * nu * kk;
-          if (CV) {
-            // entries of N (b = 1) or N^T (b = 0) at this node, entry-major
-            const double* ct = convT + (size_t)(b == 0 ? 25 : 0) * nq2 + (size_t)iy * nq + ix;
-            double cc = 0.0;
+          // convection: entries of N (b = 1) or N^T (b = 0) at this node, entry-major
+          const double* ct = convT + (size_t)(b == 0 ? 25 : 0) * nq2 + (size_t)iy * nq + ix;
+          double cc = 0.0;
 #pragma unroll
-            for (int dy = 0; dy < 5; ++dy) {
-              const double* ur = U + (r0 + i + dy) * kVLX + lx;
+          for (int dy = 0; dy < 5; ++dy) {
+            const double* ur = U + (r0 + i + dy) * kVLX + lx;
 #pragma unroll
-              for (int dx = 0; dx < 5; ++dx) cc += ct[(size_t)(dy * 5 + dx) * nq2] * ur[dx];
-            }
-            out += tau * cc;
+            for (int dx = 0; dx < 5; ++dx) cc += ct[(size_t)(dy * 5 + dx) * nq2] * ur[dx];
           }
-          yo[(size_t)iy * nq + ix] = out - tau * bt;
+          yo[(size_t)iy * nq + ix] = mm + tau * nu * kk + tau * cc - tau * bt;
         }
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
@@ -726,8 +721,7 @@ void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, 
   // momentum rows
   if (convT) {                // Oseen: one work-group per (tile, block row, step)
     const int ntx = (nq - 2 + kVTX - 1) / kVTX, nty = (nq - 2 + kVTY - 1) / kVTY;
-    hipLaunchKernelGGL(k_kkt_tile<true>, dim3(ntx * nty, 2, nt), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, convT,
-                       ntx);
+    hipLaunchKernelGGL(k_kkt_tile, dim3(ntx * nty, 2, nt), dim3(256), 0, s, x, y, n, nt, tau, beta, nu, convT, ntx);
   } else {                    // Stokes: one work-group per (tile, span of tc steps)
     const int ntx = (nq - 2 + kSTX - 1) / kSTX, nty = (nq - 2 + kSTY - 1) / kSTY;
     const int tc = kkt_span_steps(ntx * nty, nt);
@@ -842,6 +836,30 @@ void launch_axpbypcz(hipStream_t s, double* y, const double* x, const double* z,
 
 void launch_lincomb_add(hipStream_t s, double* y, const double* Z, size_t ld, int k, const double* c, size_t n) {
   hipLaunchKernelGGL(k_lincomb_add, dim3(2048), dim3(256), 0, s, y, Z, ld, k, c, n);
+}
+
+// FP32 copy of a vector (the FP32 outer basis: z is stored after its matvec)
+__global__ __launch_bounds__(256) void k_to_f32(float* __restrict__ y, const double* __restrict__ x, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = (float)x[e];
+}
+
+// y += sum_i c[i] Z_i with FP32 Z, accumulated in FP64 (c on device)
+__global__ __launch_bounds__(256) void k_lincomb_add_f32(double* __restrict__ y, const float* __restrict__ Z,
+                                                         size_t ld, int k, const double* __restrict__ c, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double s = y[e];
+    for (int i = 0; i < k; ++i) s += c[i] * (double)Z[i * ld + e];
+    y[e] = s;
+  }
+}
+
+void launch_to_f32(hipStream_t s, float* y, const double* x, size_t n) {
+  hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(256), 0, s, y, x, n);
+}
+
+void launch_lincomb_add_f32(hipStream_t s, double* y, const float* Z, size_t ld, int k, const double* c, size_t n) {
+  hipLaunchKernelGGL(k_lincomb_add_f32, dim3(2048), dim3(256), 0, s, y, Z, ld, k, c, n);
 }
 
 // zero-fill (a kernel rather than hipMemsetAsync so the sequence stays capturable)

@@ -125,6 +125,7 @@ struct Member {
   double T = 0, tau = 0, nu = 0, beta = 0;
   int64_t n_all = 0;
   double *Vk = nullptr, *Zk = nullptr, *rvec = nullptr, *xtmp = nullptr;
+  float* Zk32 = nullptr;                // FP32 basis (options.z_fp32; then Zk is null and xtmp holds z)
 };
 
 struct pintoc_problem {
@@ -452,7 +453,10 @@ static void carve(pintoc_problem* p, char* base) {
   for (Member& mb : p->mem) {
     const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(mb.n_all, freq ? p->nF : 0);
     mb.Vk = cv.take<double>(vb * (m + 1));
-    mb.Zk = cv.take<double>(vb * m);
+    if (p->o.z_fp32)
+      mb.Zk32 = cv.take<float>(vb / 2 * m);
+    else
+      mb.Zk = cv.take<double>(vb * m);
     mb.rvec = cv.take<double>(vb);
     mb.xtmp = cv.take<double>(vb);
   }
@@ -566,6 +570,7 @@ extern "C" int pintoc_default_options(pintoc_options* o) {
   o->smoother = PINTOC_SMOOTHER_TILED;
   o->pressure_stream = 0;
   o->graphs = 0;
+  o->z_fp32 = 0;
   return PINTOC_OK;
 }
 
@@ -686,6 +691,9 @@ static int create_impl(const pintoc_problem_desc* ds, int nm, const pintoc_optio
     return fail(PINTOC_EINVAL, "unknown smoother");
   if (opt.pressure_stream != 0 && opt.pressure_stream != 1) return fail(PINTOC_EINVAL, "pressure_stream must be 0 or 1");
   if (opt.graphs != 0 && opt.graphs != 1) return fail(PINTOC_EINVAL, "graphs must be 0 or 1");
+  if (opt.z_fp32 != 0 &&
+      (opt.z_fp32 != 1 || opt.precision != PINTOC_PREC_FP32_INNER || opt.outer != PINTOC_OUTER_FGMRES))
+    return fail(PINTOC_EINVAL, "z_fp32 needs FP32 inner solves and the time-domain FGMRES");
   if (opt.outer == PINTOC_OUTER_MINRES &&
       (nm > 1 || d->flow != PINTOC_STOKES || opt.inner != PINTOC_INNER_LINEAR || opt.restart < 4))
     return fail(PINTOC_EINVAL, "MINRES needs a single Stokes problem, the linear preconditioner and restart >= 4");
@@ -2221,11 +2229,16 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
       int k = 0;
       bool breakdown = false;
       for (; k < m && its < p->o.max_outer; ++k) {
+        const Member& m0 = p->mem[0];
         double* vk = p->Vk + (size_t)k * n;
-        double* zk = p->Zk + (size_t)k * n;
+        double* zk = m0.Zk32 ? m0.xtmp : p->Zk + (size_t)k * n;
         double* w = p->Vk + (size_t)(k + 1) * n;
         if ((rc = precond(p, vk, zk, s))) return rc;
         kkt_t(p, zk, w, s);
+        if (m0.Zk32) {
+          launch_to_f32(s, m0.Zk32 + (size_t)k * n, zk, n);
+          p->bytes_acc += 1.5 * p->model_canon;
+        }
         // classical Gram-Schmidt, twice
         const int ph = phase_open(p, s, PINTOC_PHASE_ORTH);
         p->bytes_acc += (4.0 * k + 13.0) * p->model_canon;
@@ -2269,9 +2282,12 @@ extern "C" int pintoc_solve(pintoc_problem* p, const double* b, double* x, pinto
       }
       const int ph = phase_open(p, s, PINTOC_PHASE_ORTH);
       HIPCHK(hipMemcpyAsync(p->dd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-      launch_lincomb_add(s, x, p->Zk, n, k, p->dd, n);
+      if (p->mem[0].Zk32)
+        launch_lincomb_add_f32(s, x, p->mem[0].Zk32, n, k, p->dd, n);
+      else
+        launch_lincomb_add(s, x, p->Zk, n, k, p->dd, n);
       phase_close(p, s, ph);
-      p->bytes_acc += (k + 2.0 + 4.0) * p->model_canon;
+      p->bytes_acc += ((p->mem[0].Zk32 ? 0.5 : 1.0) * k + 2.0 + 4.0) * p->model_canon;
       // true residual
       kkt_t(p, x, p->rvec, s);
       launch_axpby(s, p->rvec, b, 1.0, -1.0, n);
@@ -2449,7 +2465,7 @@ extern "C" int pintoc_group_solve(pintoc_problem* p, const double* const* b, dou
       const Member& mb = p->mem[k];
       const size_t n = (size_t)mb.n_all;
       rr[k] = q.in_cycle ? mb.Vk + (size_t)q.k * n : nullptr;
-      zz[k] = q.in_cycle ? mb.Zk + (size_t)q.k * n : nullptr;
+      zz[k] = q.in_cycle ? (mb.Zk32 ? mb.xtmp : mb.Zk + (size_t)q.k * n) : nullptr;
       any |= q.in_cycle;
     }
     if (!any) break;
@@ -2464,9 +2480,13 @@ extern "C" int pintoc_group_solve(pintoc_problem* p, const double* const* b, dou
         if ((size_t)(mb.f0 + j) < p->last_its.size()) q.inner_max = std::max(q.inner_max, p->last_its[mb.f0 + j]);
       const size_t n = (size_t)mb.n_all;
       const int kk = q.k;
-      double* zk = mb.Zk + (size_t)kk * n;
+      double* zk = mb.Zk32 ? mb.xtmp : mb.Zk + (size_t)kk * n;
       double* w = mb.Vk + (size_t)(kk + 1) * n;
       kkt_t(p, zk, w, s, k);
+      if (mb.Zk32) {
+        launch_to_f32(s, mb.Zk32 + (size_t)kk * n, zk, n);
+        p->bytes_acc += 1.5 * 8.0 * (double)n;
+      }
       // classical Gram-Schmidt, twice
       const int ph = phase_open(p, s, PINTOC_PHASE_ORTH);
       p->bytes_acc += (4.0 * kk + 13.0) * 8.0 * (double)n;
@@ -2511,9 +2531,12 @@ extern "C" int pintoc_group_solve(pintoc_problem* p, const double* const* b, dou
       }
       const int ph2 = phase_open(p, s, PINTOC_PHASE_ORTH);
       HIPCHK(hipMemcpyAsync(p->dd, q.y.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
-      launch_lincomb_add(s, x[k], mb.Zk, n, nk, p->dd, n);
+      if (mb.Zk32)
+        launch_lincomb_add_f32(s, x[k], mb.Zk32, n, nk, p->dd, n);
+      else
+        launch_lincomb_add(s, x[k], mb.Zk, n, nk, p->dd, n);
       phase_close(p, s, ph2);
-      p->bytes_acc += (nk + 2.0 + 4.0) * 8.0 * (double)n;
+      p->bytes_acc += ((mb.Zk32 ? 0.5 : 1.0) * nk + 2.0 + 4.0) * 8.0 * (double)n;
       kkt_t(p, x[k], mb.rvec, s, k);
       launch_axpby(s, mb.rvec, b[k], 1.0, -1.0, n);
       if ((rc = dots(p, s, mb.rvec, 1, mb.rvec, p->dd, hb, n))) return rc;

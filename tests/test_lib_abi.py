@@ -55,6 +55,21 @@ def test_host_validation(lib):
     assert o.outer == 0
     for bad_opt in (default_options(outer=3), default_options(outer=1, inner=1), default_options(outer=1, restart=3)):
         assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(bad_opt), ctypes.byref(h)) == -1
+    # FP32 outer basis: FP32 inner solves and the time-domain FGMRES only; it
+    # shrinks the workspace by half the restart length of canonical vectors
+    assert o.z_fp32 == 0
+    for bad_opt in (default_options(z_fp32=1), default_options(z_fp32=1, precision=1, outer=2),
+                    default_options(z_fp32=2, precision=1)):
+        assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(bad_opt), ctypes.byref(h)) == -1
+        assert b"z_fp32" in lib.pintoc_last_error()
+    sizes = []
+    for z in (0, 1):
+        assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(default_options(precision=1, z_fp32=z)),
+                                         ctypes.byref(h)) == 0
+        sizes.append((lib.pintoc_workspace_bytes(h), lib.pintoc_vector_length(h)))
+        lib.pintoc_problem_destroy(h)
+    (w0, n_all), (w1, _) = sizes
+    assert w0 - w1 == pytest.approx(o.restart * 4 * n_all, abs=4096 * (o.restart + 2))
     # smoother option and domain validation
     assert o.smoother == 0
     assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(default_options(smoother=2)),
