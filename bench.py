@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--serve-max-n", type=int, default=256, help="largest grid of the served stream (--config 5)")
     ap.add_argument("--z-fp32", action="store_true",
                     help="--config 4, 5: keep the outer FGMRES basis in FP32 (options.z_fp32)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="--config 4, 5: replay block preconditioner applications from HIP graphs (options.graphs)")
     ap.add_argument("--compare", action="store_true",
                     help="--config 4: also solve the mix one problem at a time (FP32-inner and FP64)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
@@ -447,7 +449,8 @@ def bench_batch(args):
     mix = W.batch_mix(args.batch_count)
     jobs = [{"N": w.N, "nt": w.nt, "T": w.T, "nu": w.nu, "beta": w.beta, "flow": w.flow,
              "wind": W.wind_nodal(w.N) if w.flow == W.OSEEN else None, "vd": W.desired_state(w)} for w in mix]
-    opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60, z_fp32=int(args.z_fp32))
+    opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60, z_fp32=int(args.z_fp32),
+                graphs=int(args.graphs))
     job_mem = sum(job_bytes(j, **opts) for j in jobs)
     print(f"[bench] batched mix of {len(jobs)} problems, {sum(w.n_all for w in mix) / 1e9:.2f}e9 unknowns, "
           f"{job_mem / 1e9:.0f} GB of job memory", file=sys.stderr, flush=True)
@@ -510,6 +513,7 @@ def bench_batch(args):
         "groups": len({r["group"] for r in out}),
         "job_memory_GB": job_mem / 1e9,
         "z_fp32": bool(args.z_fp32),
+        "graphs": bool(args.graphs),
     }
     if args.compare:
         for name, prec, workers in (("concurrent_fp32_inner", P.PREC_FP32_INNER, args.workers),
@@ -547,7 +551,8 @@ def bench_serve(args):
         return [{"N": w.N, "nt": w.nt, "T": w.T, "nu": w.nu, "beta": w.beta, "flow": w.flow,
                  "wind": W.wind_nodal(w.N) if w.flow == W.OSEEN else None, "vd": W.desired_state(w),
                  "arrival": (a / rate if rate else 0.0)} for w, a in stream]
-    opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60, z_fp32=int(args.z_fp32))
+    opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60, z_fp32=int(args.z_fp32),
+                graphs=int(args.graphs))
 
     def progress(tag):
         def cb(k, r):

@@ -305,7 +305,8 @@ def autotune(jobs, sizes=(1, 2, 4, 8, 16), smoothers=None, budget_bytes=None, de
         torch.cuda.empty_cache()
         free, _ = torch.cuda.mem_get_info(device)
         budget_bytes = int(0.5 * free)
-    tune_opts = {k: v for k, v in options.items() if k in ("precision", "n_vcycles", "n_cheb", "n_uzawa", "mu_uzawa")}
+    tune_opts = {k: v for k, v in options.items()
+                 if k in ("precision", "n_vcycles", "n_cheb", "n_uzawa", "mu_uzawa", "graphs")}
     classes = {}
     for j in jobs:
         classes.setdefault((j["N"], j.get("flow", 0)), []).append(j)
