@@ -10,7 +10,9 @@ solve changes from one application to the next (section 3.4).  Both use
 modified Gram-Schmidt Arnoldi with Givens rotations, work for complex data
 with the Hermitian inner product, and start from x_0 = 0 unless told
 otherwise.  MINRES (Paige & Saunders) applies to the symmetric Stokes system
-with the symmetric positive definite linear preconditioner of section 3.3.
+with the symmetric positive definite linear preconditioner of section 3.3,
+and to the real symmetric Stokes blocks Z_j with P~_j (section 3.2) as an
+inner solver.
 """
 from __future__ import annotations
 
@@ -125,8 +127,11 @@ def fgmres(matvec, precond, b, tol, restart=10, maxit=200, x0=None):
 
 
 def minres(matvec, precond, b, tol, maxit=500, x0=None, check_every=0):
-    """Preconditioned MINRES (Paige & Saunders) for a symmetric matrix and a
-    symmetric positive definite preconditioner ``precond`` ~ A^{-1}, real data.
+    """Preconditioned MINRES (Paige & Saunders) for a Hermitian matrix and a
+    Hermitian positive definite preconditioner ``precond`` ~ A^{-1} (real
+    symmetric data, or complex vectors with a real symmetric matrix such as
+    the Stokes blocks Z_j of section 3.2): the Lanczos coefficients are real,
+    inner products take the conjugate of their first argument.
 
     Lanczos in the inner product of the preconditioner: v_j are the Lanczos
     vectors, z_j = precond(v_j) / gamma_j with gamma_j^2 = <z_j, v_j>; the
@@ -144,7 +149,7 @@ def minres(matvec, precond, b, tol, maxit=500, x0=None, check_every=0):
     v = b - matvec(x) if x0 is not None else b.copy()
     bnorm = np.linalg.norm(b)
     z = precond(v)
-    g = np.sqrt(max(float(v @ z), 0.0))
+    g = np.sqrt(max(float(np.vdot(v, z).real), 0.0))
     if g == 0.0:
         return x, 0, [0.0], True
     g1, eta = g, g
@@ -157,10 +162,10 @@ def minres(matvec, precond, b, tol, maxit=500, x0=None, check_every=0):
     while its < maxit:
         z = z / g
         Az = matvec(z)
-        delta = float(Az @ z)
+        delta = float(np.vdot(z, Az).real)
         v_new = Az - (delta / g) * v - (g / g_old) * v_old
         z_new = precond(v_new)
-        g2 = float(v_new @ z_new)
+        g2 = float(np.vdot(v_new, z_new).real)
         g_new = np.sqrt(max(g2, 0.0))
         a0 = c * delta - c_old * s * g
         a1 = np.hypot(a0, g_new)

@@ -39,6 +39,10 @@ drives the inner GMRES counts up without bound as h -> 0.
 * Algorithm 1 (linear):   FFT -> T_l^{-1} -> P~_j^{-1} -> T_r^{-1} -> inverse FFT.
 * Algorithm 2 (nonlinear): the middle step is GMRES(Z_j, P~_j, tol eps).
   Reading: the inner preconditioner is P~_j (the practical one), not P^_j.
+  Variant (Settings.inner_solver = "minres"): preconditioned MINRES on the
+  real symmetric Z_j with the Hermitian positive definite P~_j, stopped when
+  the P~_j-norm of the residual is below eps times that of the right-hand
+  side.
 
 Oseen (section 4, Algorithm 3).  No T transforms; each frequency block G_j is
 preconditioned by P~_j^(UZ):
@@ -60,7 +64,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import circulant as circ
-from .krylov import gmres
+from .krylov import gmres, minres
 from .mg import ExactSolve, Levels, ScalarMG, coarse_viscosity
 from .smoothers import Q1_MASS_BOUNDS, Q2_MASS_BOUNDS, chebyshev
 
@@ -74,7 +78,9 @@ class Settings:
     exact inverse it stands for -- for pins of the block compositions."""
 
     def __init__(self, n_vcycles=4, n_cheb=10, n_uzawa=6, mu_uzawa=0.75,
-                 inner_tol=1e-2, inner_restart=50, inner_maxit=200, tiling=None, exact=False):
+                 inner_tol=1e-2, inner_restart=50, inner_maxit=200, tiling=None, exact=False,
+                 inner_solver="gmres"):
+        self.inner_solver = inner_solver
         self.tiling = tiling
         self.exact = exact
         self.n_vcycles = n_vcycles
@@ -264,8 +270,14 @@ class StokesPreconditioner(_Common):
             def prec(v):
                 return np.concatenate(self.ptilde_inv(j, *np.split(v, cut)))
             sv = np.concatenate(s)
-            xv, its, _ = gmres(lambda v: Zj @ v, prec, sv, self.s.inner_tol,
-                               self.s.inner_restart, self.s.inner_maxit)
+            if self.s.inner_solver == "minres":
+                # Z_j is real symmetric and P~_j Hermitian positive definite:
+                # MINRES, stopping when the P~_j-norm of the residual falls
+                # below inner_tol times that of s_j
+                xv, its, _, _ = minres(lambda v: Zj @ v, prec, sv, self.s.inner_tol, self.s.inner_maxit)
+            else:
+                xv, its, _ = gmres(lambda v: Zj @ v, prec, sv, self.s.inner_tol,
+                                   self.s.inner_restart, self.s.inner_maxit)
             self.inner_its[j] = its
             x = np.split(xv, cut)
         return self.t_right_inv(j, *x)

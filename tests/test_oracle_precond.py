@@ -556,6 +556,70 @@ def test_minres_iterate_is_the_krylov_minimiser():
         assert hist[-1] == pytest.approx(np.sqrt(r @ P @ r) / np.sqrt(b @ P @ b), rel=1e-9)
 
 
+def test_minres_complex_iterate_is_the_krylov_minimiser():
+    """With complex vectors, a real symmetric indefinite matrix and a Hermitian
+    positive definite preconditioner P (the setting of the Stokes blocks Z_j
+    with P~_j), the k-th MINRES iterate minimises ||b - A x|| in the P-norm
+    over span{P b, (P A) P b, ...}: checked by a dense least-squares solve.
+    Dropping the conjugate in either inner product breaks it."""
+    from oracle.krylov import minres
+    rng = np.random.default_rng(8)
+    n = 24
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    A = Q @ np.diag(np.concatenate([rng.uniform(1, 3, 14), -rng.uniform(0.5, 2, 10)])) @ Q.T
+    B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    P = np.linalg.inv(B @ B.conj().T + n * np.eye(n)) * n
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    Lc = np.linalg.cholesky(P)                     # P = Lc Lc^H
+    for k in range(1, 7):
+        x, its, hist, _ = minres(lambda v: A @ v, lambda v: P @ v, b, 0.0, maxit=k)
+        assert its == k
+        K = np.zeros((n, k), complex)
+        K[:, 0] = P @ b
+        for j in range(1, k):
+            K[:, j] = P @ (A @ K[:, j - 1])
+        K = np.linalg.qr(K)[0]
+        y = np.linalg.lstsq(Lc.conj().T @ (A @ K), Lc.conj().T @ b, rcond=None)[0]
+        xr = K @ y
+        assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
+        r = b - A @ xr
+        assert hist[-1] == pytest.approx(np.sqrt(np.vdot(r, P @ r).real / np.vdot(b, P @ b).real), rel=1e-9)
+
+
+def test_minres_inner_solver_on_stokes_blocks(stokes4):
+    """The inner MINRES variant of Algorithm 2 rests on Z_j being real
+    symmetric and P~_j (with exact inner inverses here) Hermitian positive
+    definite on complex frequency vectors; MINRES then stops with the
+    P~_j-norm of the residual below the tolerance times that of s_j, and at a
+    tight tolerance it reaches the direct solution.  The nonlinear
+    preconditioner with the variant records its inner counts."""
+    from oracle.krylov import minres
+    from oracle.precond import Settings, StokesPreconditioner
+    w, P, _ = stokes4
+    pc = StokesPreconditioner(P, Settings(exact=True, inner_solver="minres"))
+    cut = np.cumsum([P.nv, P.nv, P.nP])
+    rng = np.random.default_rng(9)
+    for j in (0, 1, P.nt // 2):
+        Z = pc.Z_matrix(j)
+        Zd = Z.toarray() if hasattr(Z, "toarray") else np.asarray(Z)
+        assert np.isrealobj(Zd)
+        assert np.abs(Zd - Zd.T).max() <= 1e-12 * np.abs(Zd).max()
+        n = Zd.shape[0]
+        Pm = np.column_stack([np.concatenate(pc.ptilde_inv(j, *np.split(e.astype(complex), cut)))
+                              for e in np.eye(n)])
+        assert np.abs(Pm - Pm.conj().T).max() <= 1e-10 * np.abs(Pm).max()
+        assert np.linalg.eigvalsh((Pm + Pm.conj().T) / 2).min() > 0
+        s_ = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        for tol in (1e-2, 1e-11):
+            x, its, hist, _ = minres(lambda v: Zd @ v, lambda v: Pm @ v, s_, tol, 400)
+            r = s_ - Zd @ x
+            assert np.sqrt(np.vdot(r, Pm @ r).real) <= tol * np.sqrt(np.vdot(s_, Pm @ s_).real) * (1 + 1e-6)
+        xd = np.linalg.solve(Zd, s_)
+        assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+        pc.block_apply(j, *np.split(s_, cut), nonlinear=True)
+        assert pc.inner_its[j] > 0
+
+
 def test_minres_stokes_linear_preconditioner(stokes4):
     """Algorithm 1 is symmetric positive definite on the Stokes problem, so
     MINRES applies; restarted on the true residual it reaches 1e-8 and agrees
