@@ -93,7 +93,9 @@ def parse():
                     help="--config 4: also solve the mix one problem at a time (FP32-inner and FP64)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
                     help="inner arithmetic of the timed solves (default: fp64 for Stokes, fp32 for Oseen)")
-    ap.add_argument("--inner", choices=["gmres", "linear"], default="gmres")
+    ap.add_argument("--inner", choices=["gmres", "linear", "minres"], default="gmres",
+                    help="inner treatment of the frequency blocks: GMRES (Algorithm 2), one application of the "
+                         "linear preconditioner (Algorithm 1, outer GMRES(30)), or MINRES on the Stokes blocks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond-reps", type=int, default=5)
     ap.add_argument("--no-fp32", action="store_true", help="skip the solve in the other precision mode")
@@ -270,10 +272,10 @@ def main():
         return bench_serve(args)
     precision = args.precision or ("fp32" if w.flow == W.OSEEN else "fp64")
     prec = P.PREC_FP64 if precision == "fp64" else P.PREC_FP32_INNER
-    inner = P.INNER_GMRES if args.inner == "gmres" else P.INNER_LINEAR
+    inner = {"gmres": P.INNER_GMRES, "linear": P.INNER_LINEAR, "minres": P.INNER_MINRES}[args.inner]
     flow = "Stokes" if w.flow == W.STOKES else "Oseen"
-    solver_opts = dict(inner=inner, max_outer=60 if args.inner == "gmres" else 400,
-                       restart=10 if args.inner == "gmres" else 30)
+    solver_opts = dict(inner=inner, max_outer=400 if args.inner == "linear" else 60,
+                       restart=30 if args.inner == "linear" else 10)
     gp = P.Problem.from_workload(w, precision=prec, **solver_opts)
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")

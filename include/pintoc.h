@@ -54,8 +54,15 @@ enum { PINTOC_STOKES = 0, PINTOC_OSEEN = 1 };
  *  LINEAR: one application of the block preconditioner per frequency
  *          (Algorithm 1 for Stokes; P~_j^(UZ) of Algorithm 3 for Oseen).
  *  GMRES:  the blocks are solved by right-preconditioned GMRES to a relative
- *          tolerance (Algorithm 2 for Stokes; its Oseen analogue, section 4). */
-enum { PINTOC_INNER_LINEAR = 0, PINTOC_INNER_GMRES = 1 };
+ *          tolerance (Algorithm 2 for Stokes; its Oseen analogue, section 4).
+ *  MINRES: Stokes only (EINVAL for Oseen): the real symmetric blocks Z_j of
+ *          section 3.2 are solved by preconditioned MINRES with the Hermitian
+ *          positive definite P~_j, stopping when the P~_j-norm of the
+ *          residual is below inner_tol times that of the right-hand side (at
+ *          most inner_maxit steps; inner_restart is not used).  A short
+ *          recurrence replaces the Arnoldi basis: seven block vectors instead
+ *          of inner_restart + 1. */
+enum { PINTOC_INNER_LINEAR = 0, PINTOC_INNER_GMRES = 1, PINTOC_INNER_MINRES = 2 };
 
 /* Arithmetic of the per-frequency block solves.  The outer Krylov method,
  * residual recomputation, FFTs and the all-at-once matrix stay FP64. */
@@ -120,7 +127,7 @@ typedef struct {
  * 4 V-cycles per multigrid solve, 10 Chebyshev steps, 6 Uzawa steps with
  * mu = 3/4 (section 4), inner tolerance 1e-2, outer FGMRES restart 10. */
 typedef struct {
-  int32_t inner;          /* PINTOC_INNER_LINEAR or PINTOC_INNER_GMRES        */
+  int32_t inner;          /* PINTOC_INNER_LINEAR, _GMRES or _MINRES            */
   int32_t precision;      /* PINTOC_PREC_*                                   */
   int32_t restart;        /* outer FGMRES restart length                     */
   int32_t max_outer;      /* outer iteration cap                             */

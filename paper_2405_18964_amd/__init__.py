@@ -10,7 +10,7 @@ and raises if it is missing (there is no fallback path).
 PyTorch supplies device memory (``torch.empty``) and the stream
 (``torch.cuda.current_stream()``).
 """
-from ._lib import (INNER_GMRES, INNER_LINEAR, OSEEN, OUTER_FGMRES, OUTER_FGMRES_FREQ, OUTER_MINRES, PREC_FP32_INNER, PREC_FP64,
+from ._lib import (INNER_GMRES, INNER_LINEAR, INNER_MINRES, OSEEN, OUTER_FGMRES, OUTER_FGMRES_FREQ, OUTER_MINRES, PREC_FP32_INNER, PREC_FP64,
                    SMOOTHER_GLOBAL, SMOOTHER_TILED, STOKES, LibraryMissing, PHASES,
                    Group, Problem, SolveStats, group_bytes, library, library_path, solve_batch)
 

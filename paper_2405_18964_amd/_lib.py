@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libpintoc.so")
 
 STOKES, OSEEN = 0, 1
-INNER_LINEAR, INNER_GMRES = 0, 1
+INNER_LINEAR, INNER_GMRES, INNER_MINRES = 0, 1, 2
 PREC_FP64, PREC_FP32_INNER = 0, 1
 OUTER_FGMRES, OUTER_MINRES, OUTER_FGMRES_FREQ = 0, 1, 2
 SMOOTHER_TILED, SMOOTHER_GLOBAL = 0, 1

@@ -306,6 +306,36 @@ __global__ __launch_bounds__(256) void k_fscale(cpx<R>* yV, cpx<R>* yP, const cp
   if (inV) yV[off] = y; else yP[off] = y;
 }
 
+// y = a_j y + b_j x1 + c_j x2 per frequency j with real coefficients
+// coef[j], coef[nf + j], coef[2 nf + j] (the three-term updates of the inner
+// MINRES); x2 may be null (c_j ignored)
+template <typename R>
+__global__ __launch_bounds__(256) void k_fcomb3(cpx<R>* __restrict__ yV, cpx<R>* __restrict__ yP,
+                                                const cpx<R>* __restrict__ x1V, const cpx<R>* __restrict__ x1P,
+                                                const cpx<R>* __restrict__ x2V, const cpx<R>* __restrict__ x2P,
+                                                const double* __restrict__ coef, int segV, int segP, int nf,
+                                                Mask mk) {
+  const int j = blockIdx.y;
+  if (mk.off(j)) return;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool inV = e < (size_t)segV;
+  if (!inV && e >= (size_t)segV + segP) return;
+  const size_t off = inV ? (size_t)j * segV + e : (size_t)j * segP + (e - segV);
+  cpx<R>* Y = inV ? yV : yP;
+  const cpx<R>* X1 = inV ? x1V : x1P;
+  const cpx<R>* X2 = inV ? x2V : x2P;
+  const double a = coef[j], b = coef[nf + j];
+  const cpx<R> y = Y[off], u = X1[off];
+  double re = a * (double)y.x + b * (double)u.x, im = a * (double)y.y + b * (double)u.y;
+  if (X2) {
+    const double c = coef[2 * nf + j];
+    const cpx<R> v = X2[off];
+    re += c * (double)v.x;
+    im += c * (double)v.y;
+  }
+  Y[off] = cmk<cpx<R>>(re, im);
+}
+
 // unpinned copy of the pressure fields: dst = src with dst[f][0] = -sum_{i>=1} src[f][i]
 template <typename R>
 __global__ __launch_bounds__(256) void k_unpin_copy(cpx<R>* __restrict__ dst, const cpx<R>* __restrict__ src, int nn, Mask mk) {
@@ -403,6 +433,14 @@ void launch_fscale(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, cons
 }
 
 template <typename R>
+void launch_fcomb3(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* x1V, const cpx<R>* x1P, const cpx<R>* x2V,
+                   const cpx<R>* x2P, const double* coef, int segV, int segP, int nf, Mask mk) {
+  const size_t tot = (size_t)segV + segP;
+  hipLaunchKernelGGL(k_fcomb3<R>, dim3((unsigned)((tot + 255) / 256), nf), dim3(256), 0, s, yV, yP, x1V, x1P, x2V,
+                     x2P, coef, segV, segP, nf, mk);
+}
+
+template <typename R>
 void launch_unpin_copy(hipStream_t s, cpx<R>* dst, const cpx<R>* src, int nn, int nb, Mask mk) {
   hipLaunchKernelGGL(k_unpin_copy<R>, dim3(nb), dim3(256), 0, s, dst, src, nn, mk);
 }
@@ -420,6 +458,8 @@ void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n) {
   template void launch_fscale<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, const double2*, int, \
                                  int, int, Mask);                                                                        \
   template void launch_unpin_copy<R>(hipStream_t, cpx<R>*, const cpx<R>*, int, int, Mask);                         \
+  template void launch_fcomb3<R>(hipStream_t, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, const cpx<R>*,       \
+                                 const cpx<R>*, const double*, int, int, int, Mask);                               \
   template void launch_fdot_lag<R>(hipStream_t, const cpx<R>*, const cpx<R>*, size_t, size_t, int, const cpx<R>*,  \
                                    const cpx<R>*, const cpx<R>*, const cpx<R>*, int, int, int, double2*, double2*, Mask); \
   template void launch_fupdate_lag<R>(hipStream_t, cpx<R>*, cpx<R>*, size_t, size_t, int, const double2*,           \

@@ -145,6 +145,10 @@ void launch_fscale(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* xV, cons
                    int segV, int segP, int nf, Mask mk);
 template <typename R>
 void launch_unpin_copy(hipStream_t s, cpx<R>* dst, const cpx<R>* src, int nn, int nb, Mask mk);
+// y = a_j y + b_j x1 + c_j x2 per frequency (coef: a[nf], b[nf], c[nf]; x2 may be null)
+template <typename R>
+void launch_fcomb3(hipStream_t s, cpx<R>* yV, cpx<R>* yP, const cpx<R>* x1V, const cpx<R>* x1P, const cpx<R>* x2V,
+                   const cpx<R>* x2P, const double* coef, int segV, int segP, int nf, Mask mk);
 template <typename Rd, typename Rs>
 void launch_convert(hipStream_t s, cpx<Rd>* d, const cpx<Rs>* src, size_t n);
 

@@ -390,8 +390,9 @@ static void carve(pintoc_problem* p, char* base) {
   p->PxK = cv.take<char>(pbytes);
   p->PxM = cv.take<char>(pbytes);
   p->PxM2 = cv.take<char>(pbytes);
-  if (p->o.inner == PINTOC_INNER_GMRES) {
-    const int mi = p->o.inner_restart;
+  if (p->o.inner != PINTOC_INNER_LINEAR) {
+    // inner GMRES: the Arnoldi basis; inner MINRES: its seven block vectors
+    const int mi = p->o.inner == PINTOC_INNER_MINRES ? 6 : p->o.inner_restart;
     p->ZtV = cv.take<char>(vbytes);
     p->ZtP = cv.take<char>(pbytes);
     p->UV = cv.take<char>(vbytes);
@@ -672,10 +673,13 @@ static int create_impl(const pintoc_problem_desc* ds, int nm, const pintoc_optio
   if (!unit && (!(side > 0) || !std::isfinite(side) || std::fabs((d->y1 - d->y0) - side) > 1e-12 * side))
     return fail(PINTOC_EINVAL, "the domain must be a square [x0, x1] x [y0, y1] with x1 - x0 = y1 - y0 > 0");
   if (nm > 1 && side != 1.0) return fail(PINTOC_EINVAL, "groups are set up on the unit square only");
-  if (opt.inner != PINTOC_INNER_LINEAR && opt.inner != PINTOC_INNER_GMRES) return fail(PINTOC_EINVAL, "unknown inner mode");
+  if (opt.inner != PINTOC_INNER_LINEAR && opt.inner != PINTOC_INNER_GMRES && opt.inner != PINTOC_INNER_MINRES)
+    return fail(PINTOC_EINVAL, "unknown inner mode");
   if (opt.inner == PINTOC_INNER_GMRES &&
       (opt.inner_restart < 1 || opt.inner_restart > 100 || opt.inner_maxit < 1 || !(opt.inner_tol > 0)))
     return fail(PINTOC_EINVAL, "invalid inner GMRES options");
+  if (opt.inner == PINTOC_INNER_MINRES && (d->flow != PINTOC_STOKES || opt.inner_maxit < 1 || !(opt.inner_tol > 0)))
+    return fail(PINTOC_EINVAL, "inner MINRES needs the Stokes flow, inner_maxit >= 1 and inner_tol > 0");
   if (opt.precision != PINTOC_PREC_FP64 && opt.precision != PINTOC_PREC_FP32_INNER)
     return fail(PINTOC_EINVAL, "unknown precision");
   if (opt.restart < 1 || opt.restart > 60 || opt.max_outer < 1 || !(opt.tol > 0) || opt.n_vcycles < 1 ||
@@ -1732,6 +1736,180 @@ static int gmres_blocks(pintoc_problem* p, hipStream_t s) {
   return PINTOC_OK;
 }
 
+// Batched preconditioned MINRES, one system Z_j x_j = s_j per kept frequency
+// (the inner-solver variant of Algorithm 2 for Stokes: Z_j real symmetric,
+// P~_j Hermitian positive definite on the complex frequency vectors).  All
+// frequencies advance in lockstep under a per-frequency mask; the Lanczos
+// and Givens scalars are real and kept on the host, one short recurrence per
+// frequency (Paige and Saunders):
+//   z = z^ / g,  delta = <z, Z z>,  v+ = Z z - (delta/g) v - (g/g-) v-,
+//   z^+ = P~^{-1} v+,  g+ = sqrt(<v+, z^+>),
+//   a0 = c delta - c- s g,  a1 = hypot(a0, g+),  a2 = s delta + c- c g,
+//   a3 = s- g,  (c, s) <- (a0, g+) / a1,
+//   w+ = (z - a3 w- - a2 w) / a1,  x += c eta w+,  eta <- -s eta,
+// stopping when |eta| <= eps g_1 (eta is the P~_j-norm of the residual, g_1
+// that of s_j).  The scaling by 1/g is folded into the update coefficients,
+// so z^ is never rescaled in memory.  Block vectors: three Lanczos vectors,
+// two preconditioned ones, two search directions (seven in all).
+template <typename R>
+static int minres_blocks(pintoc_problem* p, hipStream_t s) {
+  const int nf = p->nf, segV = p->segV, segP = p->segP;
+  const size_t ldV = (size_t)segV * nf, ldP = (size_t)segP * nf;
+  cpx<R>*SV = (cpx<R>*)p->Vb, *SP = (cpx<R>*)p->Pb, *XV = (cpx<R>*)p->Vx, *XP = (cpx<R>*)p->Px;
+  cpx<R>*BV = (cpx<R>*)p->BV, *BP = (cpx<R>*)p->BP;
+  auto BVk = [&](int k) { return BV + (size_t)k * ldV; };
+  auto BPk = [&](int k) { return BP + (size_t)k * ldP; };
+  double* cf = (double*)p->ydev;                          // 3 nf update coefficients
+  std::vector<double2> hb(nf), unit(nf, make_double2(1.0, 0.0));
+  std::vector<double> cfh((size_t)3 * nf, 0.0);
+  int rc;
+  auto fetch = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(hb.data(), p->hdev, sizeof(double2) * nf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PINTOC_OK;
+  };
+  auto set_mask = [&](const std::vector<int>& on) -> int {
+    p->mask_h = on;
+    HIPCHK(hipMemcpyAsync(p->maskd, p->mask_h.data(), sizeof(int) * nf, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    p->cur_mask = p->maskd;
+    int on_count = 0;
+    for (int v : on) on_count += v != 0;
+    for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) { m->mask = p->maskd; m->active = on_count * m->fpj; }
+    return PINTOC_OK;
+  };
+  auto comb = [&](int y, const cpx<R>* x1V, const cpx<R>* x1P, const cpx<R>* x2V, const cpx<R>* x2P) -> int {
+    HIPCHK(hipMemcpyAsync(cf, cfh.data(), sizeof(double) * 3 * nf, hipMemcpyHostToDevice, s));
+    cpx<R>* yV = y < 0 ? XV : BVk(y);
+    cpx<R>* yP = y < 0 ? XP : BPk(y);
+    launch_fcomb3<R>(s, yV, yP, x1V, x1P, x2V, x2P, cf, segV, segP, nf, p->mk(1));
+    HIPCHK(hipStreamSynchronize(s));                       // cfh is rewritten by the next call
+    return PINTOC_OK;
+  };
+  std::vector<int> done(nf, 0), its(nf, 0);
+  for (int j = 0; j < nf; ++j) done[j] = !p->freq_on[j];
+  // slots: Lanczos vectors v-, v, v+ and z^, z^+, search directions w-, w
+  int iv0 = 0, iv = 1, iv1 = 2, iz = 3, iz1 = 4, iw0 = 5, iw = 6;
+  for (int k : {iv0, iw0, iw}) {
+    launch_fill_zero(s, BVk(k), ldV * sizeof(cpx<R>));
+    launch_fill_zero(s, BPk(k), ldP * sizeof(cpx<R>));
+  }
+  launch_fill_zero(s, XV, ldV * sizeof(cpx<R>));
+  launch_fill_zero(s, XP, ldP * sizeof(cpx<R>));
+  std::vector<int> active(nf);
+  for (int j = 0; j < nf; ++j) active[j] = !done[j];
+  if ((rc = set_mask(active))) return rc;
+  HIPCHK(hipMemcpyAsync(p->h2dev, unit.data(), sizeof(double2) * nf, hipMemcpyHostToDevice, s));
+  launch_fscale<R>(s, BVk(iv), BPk(iv), SV, SP, p->h2dev, segV, segP, nf, p->mk(1));    // v = s_j
+  block_precond<R>(p, s, BVk(iv), BPk(iv), BVk(iz), BPk(iz));
+  launch_fdot<R>(s, BVk(iv), BPk(iv), 0, 0, 1, BVk(iz), BPk(iz), segV, segP, nf, p->fpart, p->hdev, p->mk(1));
+  if ((rc = fetch())) return rc;
+  std::vector<double> g(nf), g0(nf, 1.0), g1(nf), eta(nf), c(nf, 1.0), c0(nf, 1.0), sn(nf, 0.0), sn0(nf, 0.0),
+      delta(nf), gn(nf), g2(nf);
+  for (int j = 0; j < nf; ++j) {
+    if (done[j]) continue;
+    g[j] = std::sqrt(std::max(hb[j].x, 0.0));
+    g1[j] = eta[j] = g[j];
+    if (!(g[j] > 0)) done[j] = 1;
+  }
+  int total = 0;
+  while (total < p->o.inner_maxit) {
+    bool any = false;
+    for (int j = 0; j < nf; ++j) any |= (active[j] = !done[j]) != 0;
+    if (!any) break;
+    if (active != p->mask_h && (rc = set_mask(active))) return rc;
+    // Z z^ and <z^, Z z^>
+    block_matvec<R>(p, s, BVk(iv1), BPk(iv1), BVk(iz), BPk(iz));
+    launch_fdot<R>(s, BVk(iz), BPk(iz), 0, 0, 1, BVk(iv1), BPk(iv1), segV, segP, nf, p->fpart, p->hdev, p->mk(1));
+    if ((rc = fetch())) return rc;
+    for (int j = 0; j < nf; ++j) {
+      if (!active[j]) continue;
+      delta[j] = hb[j].x / (g[j] * g[j]);
+      cfh[j] = 1.0 / g[j];                                  // v+ = (Z z^)/g - (delta/g) v - (g/g-) v-
+      cfh[nf + j] = -delta[j] / g[j];
+      cfh[2 * nf + j] = -g[j] / g0[j];
+    }
+    if ((rc = comb(iv1, BVk(iv), BPk(iv), BVk(iv0), BPk(iv0)))) return rc;
+    block_precond<R>(p, s, BVk(iv1), BPk(iv1), BVk(iz1), BPk(iz1));
+    launch_fdot<R>(s, BVk(iv1), BPk(iv1), 0, 0, 1, BVk(iz1), BPk(iz1), segV, segP, nf, p->fpart, p->hdev, p->mk(1));
+    if ((rc = fetch())) return rc;
+    std::vector<int> upd = active;
+    std::vector<double> step(nf, 0.0);
+    for (int j = 0; j < nf; ++j) {
+      if (!active[j]) continue;
+      g2[j] = hb[j].x;
+      gn[j] = std::sqrt(std::max(g2[j], 0.0));
+      const double a0 = c[j] * delta[j] - c0[j] * sn[j] * g[j];
+      const double a1 = std::hypot(a0, gn[j]);
+      const double a2 = sn[j] * delta[j] + c0[j] * c[j] * g[j];
+      const double a3 = sn0[j] * g[j];
+      if (!(a1 > 0)) {                                      // breakdown: keep the iterate
+        done[j] = 1;
+        upd[j] = 0;
+        continue;
+      }
+      c0[j] = c[j];
+      sn0[j] = sn[j];
+      c[j] = a0 / a1;
+      sn[j] = gn[j] / a1;
+      cfh[j] = -a3 / a1;                                    // w+ (in the w- slot) = z^/(g a1) - (a3/a1) w- - (a2/a1) w
+      cfh[nf + j] = 1.0 / (g[j] * a1);
+      cfh[2 * nf + j] = -a2 / a1;
+      step[j] = c[j] * eta[j];
+    }
+    bool anyu = false;
+    for (int v : upd) anyu |= v != 0;
+    if (anyu) {
+      if (upd != p->mask_h && (rc = set_mask(upd))) return rc;
+      if ((rc = comb(iw0, BVk(iz), BPk(iz), BVk(iw), BPk(iw)))) return rc;
+      for (int j = 0; j < nf; ++j) {
+        cfh[j] = 1.0;                                       // x += c eta w+
+        cfh[nf + j] = step[j];
+        cfh[2 * nf + j] = 0.0;
+      }
+      if ((rc = comb(-1, BVk(iw0), BPk(iw0), nullptr, nullptr))) return rc;
+    }
+    ++total;
+    for (int j = 0; j < nf; ++j) {
+      if (!upd[j]) continue;
+      eta[j] = -sn[j] * eta[j];
+      its[j]++;
+      if (std::fabs(eta[j]) <= p->o.inner_tol * g1[j] || !(g2[j] > 0)) done[j] = 1;
+      g0[j] = g[j];
+      g[j] = gn[j];
+    }
+    // rotate: v- <- v <- v+, z^ <- z^+, w- <-> w (w+ was written over w-)
+    const int t = iv0;
+    iv0 = iv;
+    iv = iv1;
+    iv1 = t;
+    std::swap(iz, iz1);
+    std::swap(iw0, iw);
+  }
+  p->cur_mask = nullptr;
+  for (MGPlan* m : {&p->mgW, &p->mgK, &p->mgQ, &p->mgQH}) { m->mask = nullptr; m->active = m->nb; }
+  p->last_its = its;
+  if ((int)p->its_acc.size() != nf) p->its_acc.assign(nf, 0);
+  {
+    // model: per frequency, each step applies the block preconditioner and
+    // the block product and makes 15 vector passes (two dots, three updates)
+    const double per_j_block = p->model_block / nf, per_j_bmat = p->model_bmat / nf, fv = p->model_fvec / nf;
+    for (int j = 0; j < nf; ++j) {
+      if (!p->freq_on[j]) continue;
+      const double kk = its[j];
+      p->bytes_acc += (kk + 1.0) * per_j_block + kk * per_j_bmat + (15.0 * kk + 4.0) * fv;
+    }
+  }
+  for (int j = 0; j < nf; ++j) {
+    if (!p->freq_on[j]) continue;
+    p->its_acc[j] += its[j];
+    p->inner_its_sum += its[j];
+    p->inner_blocks += 1;
+    p->inner_its_max = std::max(p->inner_its_max, its[j]);
+  }
+  return PINTOC_OK;
+}
+
 // The block-circulant preconditioner: FFT in time (+ T_l^{-1} for Stokes),
 // per-frequency block solves (one application of P~_j / P~_j^(UZ), or GMRES
 // to the inner tolerance), (T_r^{-1} +) inverse FFT.  Stokes: Algorithms 1
@@ -1756,7 +1934,7 @@ static int precond_apply_t(pintoc_problem* p, const double* const* r, double* co
     clear_member_mask(p);
     p->bytes_acc += p->model_block * active_fraction(p);
   } else {
-    int rc = gmres_blocks<R>(p, s);
+    int rc = p->o.inner == PINTOC_INNER_MINRES ? minres_blocks<R>(p, s) : gmres_blocks<R>(p, s);
     if (rc) return rc;
   }
   phase_close(p, s, ph);
@@ -2019,7 +2197,7 @@ static int precond_freq_t(pintoc_problem* p, const double* v, double* z, hipStre
     block_precond<R>(p, s, Vb, Pb, Vx, Px);
     p->bytes_acc += p->model_block;
   } else {
-    int rc = gmres_blocks<R>(p, s);
+    int rc = p->o.inner == PINTOC_INNER_MINRES ? minres_blocks<R>(p, s) : gmres_blocks<R>(p, s);
     if (rc) return rc;
   }
   phase_close(p, s, ph);
@@ -2582,7 +2760,7 @@ extern "C" int pintoc_group_solve(pintoc_problem* p, const double* const* b, dou
       o->converged = q.conv ? 1 : 0;
       o->rel_residual = q.bnorm > 0 ? q.res / q.bnorm : 0.0;
       o->precond_applications = q.apps;
-      o->inner_iterations_mean = (p->o.inner == PINTOC_INNER_GMRES && q.apps > 0) ? (double)isum / ((double)q.apps * mb.nf) : 0.0;
+      o->inner_iterations_mean = (p->o.inner != PINTOC_INNER_LINEAR && q.apps > 0) ? (double)isum / ((double)q.apps * mb.nf) : 0.0;
       o->inner_iterations_max = q.inner_max;
       o->seconds = secs;
     }

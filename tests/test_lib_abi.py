@@ -85,6 +85,8 @@ def test_host_validation(lib):
     wind = (ctypes.c_double * (2 * 17 * 17))()
     oseen = Desc(8, 16, 1.0, 1.0, 1e-2, 1, ctypes.cast(wind, ctypes.POINTER(ctypes.c_double)))
     assert lib.pintoc_problem_create(ctypes.byref(oseen), ctypes.byref(default_options(outer=1)), ctypes.byref(h)) == -1
+    assert lib.pintoc_problem_create(ctypes.byref(oseen), ctypes.byref(default_options(inner=2)), ctypes.byref(h)) == -1
+    assert b"MINRES" in lib.pintoc_last_error()
     assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(default_options(outer=1)), ctypes.byref(h)) == 0
     lib.pintoc_problem_destroy(h)
     assert lib.pintoc_problem_create(ctypes.byref(good), ctypes.byref(o), ctypes.byref(h)) == 0
