@@ -420,6 +420,23 @@ def main():
         print(f"[bench] MINRES + Algorithm 1 (FP64): {stm['outer_iterations']} its, {tm:.2f} s",
               file=sys.stderr, flush=True)
         del gm
+    if not args.no_minres and precision == "fp64" and w.flow == W.STOKES and args.inner == "gmres":
+        # paper variant: Algorithm 2 with MINRES in place of the inner GMRES, FP64
+        gi = P.Problem.from_workload(w, inner=P.INNER_MINRES, precision=P.PREC_FP64, max_outer=60)
+        _timed_solve(gi, b, x)                       # warm-up
+        ti, sti, oki = _timed_solve(gi, b, x)
+        ri = float(torch.linalg.norm(b - gi.kkt_apply(x)) / torch.linalg.norm(b))
+        out["inner_minres_fp64"] = {"solves_per_s": 1.0 / ti, "seconds": ti, "converged": bool(oki),
+                                    "final_rel_residual": ri, "outer": sti["outer_iterations"],
+                                    "inner_mean": sti["inner_iterations_mean"],
+                                    "workspace_GB": gi.workspace_bytes / 1e9,
+                                    "workspace_GB_inner_gmres": gp.workspace_bytes / 1e9,
+                                    "note": "FGMRES(10) with MINRES on the Stokes blocks Z_j (preconditioned by "
+                                            "P~_j) in place of the inner GMRES of Algorithm 2, FP64"}
+        print(f"[bench] inner MINRES (FP64): {sti['outer_iterations']} its, inner mean "
+              f"{sti['inner_iterations_mean']:.1f}, {ti:.2f} s, workspace {gi.workspace_bytes / 1e9:.1f} GB",
+              file=sys.stderr, flush=True)
+        del gi
     if not args.no_minres and w.flow == W.STOKES:
         # the same solve with the pressure part of P~_j on a second stream
         go = P.Problem.from_workload(w, precision=prec, pressure_stream=1, **solver_opts)
