@@ -84,3 +84,22 @@ def test_solve_inner_minres(lib, precision):
           f"(GMRES {gm.workspace_bytes / 2**20:.0f} MiB)", flush=True)
     assert res <= 1e-8
     assert diff <= 1e-6
+
+
+def test_group_inner_minres_equals_lone(lib):
+    """Fused group (two Stokes members of one grid): the per-frequency MINRES
+    runs over the members' frequencies in one batch; every member's result
+    equals its lone solve bit for bit."""
+    print("group inner minres", flush=True)
+    ws = [W.small(W.STOKES, 16, 16, beta=1e-3), W.small(W.STOKES, 16, 32, beta=1e-4)]
+    opts = dict(inner=lib.INNER_MINRES)
+    members = [{"N": w.N, "nt": w.nt, "T": w.T, "nu": w.nu, "beta": w.beta, "flow": w.flow} for w in ws]
+    g = lib.Group(members, **opts)
+    bs = [g.assemble_rhs(i, _dev(W.desired_state(w))) for i, w in enumerate(ws)]
+    xs, sts, oks = g.solve(bs)
+    for i, w in enumerate(ws):
+        gp = lib.Problem.from_workload(w, **opts)
+        x, st, ok = gp.solve(gp.assemble_rhs(_dev(W.desired_state(w))))
+        assert oks[i] and ok
+        assert sts[i]["outer_iterations"] == st["outer_iterations"]
+        assert np.array_equal(_host(xs[i]), _host(x))
