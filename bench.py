@@ -288,6 +288,7 @@ def main():
     x = gp.empty()
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+    ws_main = gp.workspace_bytes
     print(f"[bench] {w.name} n_all={gp.n_all} workspace={gp.workspace_bytes / 1e9:.1f} GB", file=sys.stderr,
           flush=True)
     for i in range(args.warmup):
@@ -430,7 +431,7 @@ def main():
                                     "final_rel_residual": ri, "outer": sti["outer_iterations"],
                                     "inner_mean": sti["inner_iterations_mean"],
                                     "workspace_GB": gi.workspace_bytes / 1e9,
-                                    "workspace_GB_inner_gmres": gp.workspace_bytes / 1e9,
+                                    "workspace_GB_inner_gmres": ws_main / 1e9,
                                     "note": "FGMRES(10) with MINRES on the Stokes blocks Z_j (preconditioned by "
                                             "P~_j) in place of the inner GMRES of Algorithm 2, FP64"}
         print(f"[bench] inner MINRES (FP64): {sti['outer_iterations']} its, inner mean "
