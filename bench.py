@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--serve-max-n", type=int, default=256, help="largest grid of the served stream (--config 5)")
     ap.add_argument("--z-fp32", action="store_true",
                     help="--config 4, 5: keep the outer FGMRES basis in FP32 (options.z_fp32)")
+    ap.add_argument("--stokes-inner", choices=["gmres", "minres"], default="gmres",
+                    help="--config 4, 5: inner solver of the Stokes jobs (the Oseen jobs keep GMRES)")
     ap.add_argument("--graphs", action="store_true",
                     help="--config 4, 5: replay block preconditioner applications from HIP graphs (options.graphs)")
     ap.add_argument("--compare", action="store_true",
@@ -455,6 +457,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _stokes_inner(args, w, P):
+    """Per-job option overrides: the inner MINRES for Stokes jobs when asked."""
+    return {"inner": P.INNER_MINRES} if args.stokes_inner == "minres" and w.flow == 0 else {}
+
+
 def bench_batch(args):
     """Batched form: the 64-problem mix, fused (groups of the same grid and
     flow in one handle, group size and smoother per class from the
@@ -468,7 +475,8 @@ def bench_batch(args):
 
     mix = W.batch_mix(args.batch_count)
     jobs = [{"N": w.N, "nt": w.nt, "T": w.T, "nu": w.nu, "beta": w.beta, "flow": w.flow,
-             "wind": W.wind_nodal(w.N) if w.flow == W.OSEEN else None, "vd": W.desired_state(w)} for w in mix]
+             "wind": W.wind_nodal(w.N) if w.flow == W.OSEEN else None, "vd": W.desired_state(w),
+             "options": _stokes_inner(args, w, P)} for w in mix]
     opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60, z_fp32=int(args.z_fp32),
                 graphs=int(args.graphs))
     job_mem = sum(job_bytes(j, **opts) for j in jobs)
@@ -534,6 +542,7 @@ def bench_batch(args):
         "job_memory_GB": job_mem / 1e9,
         "z_fp32": bool(args.z_fp32),
         "graphs": bool(args.graphs),
+        "stokes_inner": args.stokes_inner,
     }
     if args.compare:
         for name, prec, workers in (("concurrent_fp32_inner", P.PREC_FP32_INNER, args.workers),
@@ -570,7 +579,7 @@ def bench_serve(args):
     def jobs_at(rate):
         return [{"N": w.N, "nt": w.nt, "T": w.T, "nu": w.nu, "beta": w.beta, "flow": w.flow,
                  "wind": W.wind_nodal(w.N) if w.flow == W.OSEEN else None, "vd": W.desired_state(w),
-                 "arrival": (a / rate if rate else 0.0)} for w, a in stream]
+                 "arrival": (a / rate if rate else 0.0), "options": _stokes_inner(args, w, P)} for w, a in stream]
     opts = dict(inner=P.INNER_GMRES, precision=P.PREC_FP32_INNER, max_outer=60, z_fp32=int(args.z_fp32),
                 graphs=int(args.graphs))
 

@@ -26,6 +26,12 @@ from ._lib import Problem
 _PROBLEM_KEYS = ("N", "nt", "T", "nu", "beta", "flow", "wind")
 
 
+def job_options(job, options):
+    """The run's options with the job's own ``job["options"]`` (if any) on top:
+    e.g. ``{"inner": INNER_MINRES}`` for the Stokes jobs of a mixed list."""
+    return dict(options, **job.get("options", {}))
+
+
 def job_layout(job, **options):
     """(workspace bytes, canonical vector length) of a job (host-side set-up only)."""
     import ctypes as C
@@ -36,7 +42,7 @@ def job_layout(job, **options):
     w = None if wind is None else np.ascontiguousarray(np.asarray(wind, dtype=np.float64).reshape(-1))
     d = Desc(job["N"], job["nt"], job.get("T", 1.0), job["nu"], job["beta"], job.get("flow", 0),
              None if w is None else w.ctypes.data_as(C.POINTER(C.c_double)))
-    o = default_options(**options)
+    o = default_options(**job_options(job, options))
     h = C.c_void_p()
     lib = library()
     _check(lib.pintoc_problem_create(C.byref(d), C.byref(o), C.byref(h)), "pintoc_problem_create")
@@ -132,7 +138,8 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
     each turn completes before the next starts (the library synchronises the
     stream), so a job may move between worker streams.  The iterates of a
     sliced solve equal those of an uninterrupted one, so each result is the
-    same alone, in a batch and served."""
+    same alone, in a batch and served.  A job's ``options`` entry (a dict)
+    overrides the run's options for that job."""
     import collections
     import hashlib
 
@@ -199,7 +206,7 @@ def run(jobs, workers: int = 4, budget_bytes: int | None = None, keep_solutions:
         vd = views[3][:8 * job["nt"] * 2 * nq2].view(torch.float64)
         with torch.cuda.stream(stream):
             p = Problem(job["N"], job["nt"], job.get("T", 1.0), job["nu"], job["beta"], job.get("flow", 0),
-                        job.get("wind"), device=device, workspace=views[0], **options)
+                        job.get("wind"), device=device, workspace=views[0], **job_options(job, options))
             vd.copy_(torch.as_tensor(np.ascontiguousarray(job["vd"], dtype=np.float64)).reshape(-1))
             x.zero_()
             p.assemble_rhs(vd, b)
@@ -377,8 +384,9 @@ def run_fused(jobs, plan=None, workers: int = 2, budget_bytes: int | None = None
     in lockstep), the group size and smoother per class from ``plan`` (see
     ``autotune``; default: groups of 4, tiled smoother).  ``workers`` host
     threads, each with its own stream, run groups concurrently while their
-    device memory fits the budget.  Returns one record per job, as ``run``
-    (with the group it ran in)."""
+    device memory fits the budget.  Per-job ``options`` overrides must agree
+    within an (N, flow) class (the group takes its first job's).  Returns one
+    record per job, as ``run`` (with the group it ran in)."""
     import hashlib
 
     import numpy as np
@@ -408,7 +416,8 @@ def run_fused(jobs, plan=None, workers: int = 2, budget_bytes: int | None = None
     need = []
     for ks, sm in groups:
         members = [_member_of(jobs[k]) for k in ks]
-        need.append(group_bytes(members, smoother=sm, **options) + sum(vec_bytes(jobs[k]) for k in ks))
+        need.append(group_bytes(members, smoother=sm, **job_options(jobs[ks[0]], options))
+                    + sum(vec_bytes(jobs[k]) for k in ks))
     if groups and max(need) > budget_bytes:
         raise ValueError(f"a group needs {max(need)} bytes, more than the budget {budget_bytes}")
     # groups in the order of their first job (as ``run`` admits jobs)
@@ -435,7 +444,8 @@ def run_fused(jobs, plan=None, workers: int = 2, budget_bytes: int | None = None
             start = time.perf_counter() - t0
             try:
                 with torch.cuda.stream(stream):
-                    g = Group([_member_of(jobs[k]) for k in ks], device=device, smoother=sm, **options)
+                    g = Group([_member_of(jobs[k]) for k in ks], device=device, smoother=sm,
+                              **job_options(jobs[ks[0]], options))
                     bs = []
                     for i, k in enumerate(ks):
                         vd = torch.as_tensor(np.ascontiguousarray(jobs[k]["vd"], dtype=np.float64)).to(device)

@@ -129,6 +129,9 @@ def test_batch_job_bytes_and_mix():
     big = dict(small, nt=32)
     assert 0 < job_bytes(small) < job_bytes(big)
     assert job_bytes(small, precision=1) < job_bytes(small, precision=0)
+    # a job's own options override the run's (here: the inner MINRES of a Stokes job)
+    assert job_bytes(dict(small, options={"inner": 2}), inner=1) < job_bytes(small, inner=1)
+    assert job_bytes(dict(small, options={"inner": 1}), inner=2) == job_bytes(small, inner=1)
 
 
 def test_batch_arena_first_fit():
