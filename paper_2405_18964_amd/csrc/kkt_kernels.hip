@@ -318,19 +318,29 @@ struct SpanScal {
 };
 
 __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ x, double* __restrict__ y, int n,
-                                                     int nt, SpanScal sc, int ntx, int tc) {
+                                                     int nt, SpanScal sc, int ntx, int ntiles, int tc) {
+  // DV, DL: divergence sums of the Q1 nodes on the grid's boundary (indexed
+  // like the owned nodes); IV, IL: those of interior Q1 nodes, per thread and
+  // vertex row of its strip
   __shared__ double V[kSLN], Lm[kSLN], QP[kSPN], QM[kSPN], DV[kSDiv * 256], DL[kSDiv * 256];
+  __shared__ double IV[(kSTS / 2) * 256], IL[(kSTS / 2) * 256];
   const int nq = 2 * n + 1, nq2 = nq * nq, np = n + 1, np2 = np * np;
   const int L = 2 * nq2 + np2;
-  const int bx = blockIdx.x % ntx, by = blockIdx.x / ntx;
+  // Work-group ids are dealt round-robin to the 8 XCDs; id g takes item
+  // v = (g % 8) (G / 8) + g / 8, so each XCD holds a contiguous range of v,
+  // i.e. a compact block of tiles (row-major, spans fastest): neighbouring
+  // tiles of one span share their halo lines in that XCD's L2.
+  const int nspan = (nt + tc - 1) / tc;
+  const unsigned v = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if (v >= (unsigned)(ntiles * nspan)) return;                 // whole work-group: no barrier is skipped
+  const int tile = (int)(v / nspan), span = (int)(v % nspan);
+  const int bx = tile % ntx, by = tile / ntx;
   const int x0 = 1 + bx * kSTX, y0 = 1 + by * kSTY;
   const int qx0 = (x0 >> 1) - 1, qy0 = (y0 >> 1) - 1;
-  const int t0 = blockIdx.y * tc, t1 = min(t0 + tc, nt);
+  const int t0 = span * tc, t1 = min(t0 + tc, nt);
   const int sb = t0 > 0 ? t0 - 1 : t0, se = t1 < nt ? t1 : t1 - 1;
   const double tau = sc.tau, tb = sc.tb, tn = sc.tn, h = sc.h;
-  const int kxb = bx == 0 ? 0 : qx0 + 2, kxe = min(qx0 + 2 + kSTX / 2, n + 1);
-  const int kyb = by == 0 ? 0 : qy0 + 2, kye = min(qy0 + 2 + kSTY / 2, n + 1);
-  const int nkx = kxe - kxb, nk = nkx * (kye - kyb);
+  const bool ring = bx == 0 || bx == ntx - 1 || by == 0 || (by + 1) * kSTY >= 2 * n - 1;   // tile on the grid edge
 #pragma unroll
   for (int i = 0; i < kSDiv; ++i) {
     DV[threadIdx.x + 256 * i] = 0.0;
@@ -366,7 +376,11 @@ __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ 
     const double m04 = xvert ? -1.0 : 0.0, m2 = xvert ? 8.0 : 16.0, k04 = xvert ? 1.0 : 0.0, k2 = xvert ? 14.0 : 16.0;
     const int kx0 = (ix >> 1) - 1;
     if (colin) {
-      double S[5][4];                          // x-sums per staged row: m' v, k' v, m' l, k' l
+      // x-sums per staged row: m' v, k' v, m' l, k' l, and the mixed x-sums of
+      // the divergence rows (derivative weights for c = 0, mass for c = 1) that
+      // a Q1 node kx takes from the five Q2 nodes around 2 kx = ix (used by the
+      // lanes of even ix)
+      double S[5][6];
       auto sums = [&](int lr, double* o) {
         const double* vr = V + lr * kSLX + lx;
         const double* lr_ = Lm + lr * kSLX + lx;
@@ -375,6 +389,13 @@ __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ 
         o[1] = fma(k04, v04, fma(-8.0, v13, k2 * vr[2]));
         o[2] = fma(m04, l04, fma(2.0, l13, m2 * lr_[2]));
         o[3] = fma(k04, l04, fma(-8.0, l13, k2 * lr_[2]));
+        if (c == 0) {
+          o[4] = fma(sc.c16, vr[4] - vr[0], sc.c23 * (vr[3] - vr[1]));
+          o[5] = fma(sc.c16, lr_[4] - lr_[0], sc.c23 * (lr_[3] - lr_[1]));
+        } else {
+          o[4] = sc.h3 * (vr[1] + vr[2] + vr[3]);
+          o[5] = sc.h3 * (lr_[1] + lr_[2] + lr_[3]);
+        }
       };
 #pragma unroll
       for (int d = 0; d < 4; ++d) sums(r0 + d, S[d]);
@@ -463,22 +484,39 @@ __global__ __launch_bounds__(256, 2) void k_kkt_span(const double* __restrict__ 
             if (s > t0) Ya[o] = AP[c][i] - ML;
             if (s == nt - 1) Yl[o] = ap;
             AP[c][i] = ap;
+            if (vert) {
+              // divergence rows of the interior Q1 node (ix / 2, iy / 2): the y-weights
+              // of the rows iy - 2 .. iy + 2 are mass for c = 0 and derivative for c = 1
+              const int slot = (i >> 1) * 256 + tid;
+              if (c == 0) {
+                IV[slot] = h3 * (S[1][4] + S[2][4] + S[3][4]);
+                IL[slot] = h3 * (S[1][5] + S[2][5] + S[3][5]);
+              } else if (xvert) {
+                const double dv = IV[slot] + fma(sc.c16, S[4][4] - S[0][4], sc.c23 * (S[3][4] - S[1][4]));
+                const double dl = IL[slot] + fma(sc.c16, S[4][5] - S[0][5], sc.c23 * (S[3][5] - S[1][5]));
+                const size_t k = (size_t)(iy >> 1) * np + (ix >> 1);
+                y[(size_t)(nt + s) * L + 2 * nq2 + k] = -tau * dv;       // state divergence
+                y[(size_t)s * L + 2 * nq2 + k] = -tau * dl;              // adjoint divergence
+              }
+            }
           }
         }
 #pragma unroll
         for (int d = 0; d < 4; ++d)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) S[d][q] = S[d + 1][q];
+          for (int q = 0; q < 6; ++q) S[d][q] = S[d + 1][q];
       }
     }
-    if (pro || epi) return;
-    // divergence rows: this component's B terms on v_s and l_s
+    if (pro || epi || !ring) return;
+    // divergence rows of the Q1 nodes on the grid's boundary (their Q2 centre
+    // is no momentum output): this component's B terms on v_s and l_s
     const int kxb = bx == 0 ? 0 : qx0 + 2, kxe = min(qx0 + 2 + kSTX / 2, n + 1);
     const int kyb = by == 0 ? 0 : qy0 + 2, kye = min(qy0 + 2 + kSTY / 2, n + 1);
     const int nkx = kxe - kxb, nk = nkx * (kye - kyb);
 #pragma unroll 1
     for (int e = tid; e < nk; e += 256) {
       const int kyy = kyb + e / nkx, kxx = kxb + e % nkx;
+      if (kxx > 0 && kxx < n && kyy > 0 && kyy < n) continue;
       double wx[5], wy[5], w2[5];
       if (c == 0) {
         mixed_rows(kxx, n, h, w2, wx);
@@ -728,7 +766,8 @@ void launch_kkt_apply(hipStream_t s, const double* x, double* y, int n, int nt, 
     const double h = 1.0 / n;
     const SpanScal sc{tau, tau / beta, tau * nu, h, (h / 30.0) * (h / 30.0), (h / 30.0) / (3.0 * h), h / 3.0,
                       1.0 / 6.0, 2.0 / 3.0};
-    hipLaunchKernelGGL(k_kkt_span, dim3(ntx * nty, (nt + tc - 1) / tc), dim3(256), 0, s, x, y, n, nt, sc, ntx, tc);
+    const int items = ntx * nty * ((nt + tc - 1) / tc);
+    hipLaunchKernelGGL(k_kkt_span, dim3((items + 7) / 8 * 8), dim3(256), 0, s, x, y, n, nt, sc, ntx, ntx * nty, tc);
   }
   hipLaunchKernelGGL(k_kkt_ring, dim3((4 * (nq - 1) + 255) / 256, nt, 4), dim3(256), 0, s, y, n, nt);
 }
