@@ -250,6 +250,28 @@ def _timed_solve(gp, b, x):
     return time.perf_counter() - t1, st, ok
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of `nbytes` (read + write = 2 x nbytes of HBM
+    traffic), timed with events after one untimed copy: the attainable
+    streaming rate that the roofline kernel's fraction is also read against."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_per_copy": 2 * nbytes, "avg_ms": ms, "reps": reps,
+            "frac_of_peak": 2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     args = parse()
     if args.steps is None:
@@ -382,6 +404,8 @@ def main():
                                  "the largest share of device time)",
                        "avg_launch_ms": post["avg_ms"], "launches_timed": post["launches"],
                        "algorithmic_bytes_per_launch": post["algorithmic_bytes"]}
+    cp = copy_bandwidth(torch)
+    out["hbm_copy"] = dict(cp, roofline_kernel_frac_of_copy=achieved / cp["GBs"])
     pre_gbs = kt["algorithmic_bytes"] / (kt["avg_ms"] * 1e-3) / 1e9
     out["pre_smoothing_sweep"] = {"avg_launch_ms": kt["avg_ms"], "launches_timed": kt["launches"],
                                   "algorithmic_bytes_per_launch": kt["algorithmic_bytes"], "achieved_GBs": pre_gbs,
