@@ -21,6 +21,17 @@ namespace pintoc {
 
 __device__ inline int bitrev(int v, int logn) { return (int)(__brev((unsigned)v) >> (32 - logn)); }
 
+// Tile of a work-group (or ~0u past the last of ntile tiles).  Work-group ids
+// are dealt round-robin to the 8 XCDs, so id g takes tile (g % 8) (G / 8) +
+// g / 8 (G, the grid, a multiple of 8): each XCD runs a contiguous range of
+// level indices, and the cache lines that two neighbouring tiles share (rows
+// of L or (2N+1)^2 entries start at any offset) meet in one L2.
+__device__ __forceinline__ unsigned xcd_tile(int ntile) {
+  const unsigned v = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  return v < (unsigned)ntile ? v : ~0u;
+}
+__host__ inline unsigned xcd_grid(int ntile) { return (unsigned)((ntile + 7) / 8 * 8); }
+
 // Radix-2 decimation-in-time stages over TN sequences of length nt held in
 // LDS in bit-reversed order.  sgn = -1 forward, +1 inverse (twiddle conj).
 __device__ inline void lds_fft(double2* buf, int TN, int nt, int logn, const double2* __restrict__ tw, bool inverse) {
@@ -49,7 +60,9 @@ __global__ __launch_bounds__(256) void k_time_fft_fwd(const double* __restrict__
                                int nt, int logn, int L, int nq2, int np2, int nf, int TN,
                                const double2* __restrict__ tw, const double2* __restrict__ tj, double tau, int mode) {
   extern __shared__ double2 buf[];
-  const int n0 = blockIdx.x * TN;
+  const unsigned tile = xcd_tile((L + TN - 1) / TN);
+  if (tile == ~0u) return;
+  const int n0 = (int)tile * TN;
   for (int e = threadIdx.x; e < TN * nt; e += blockDim.x) {
     const int n = e % TN, t = e / TN;
     double a = 0, b = 0;
@@ -106,7 +119,9 @@ __global__ __launch_bounds__(256) void k_time_fft_inv(const cpx<R>* __restrict__
                                int nt, int logn, int L, int nq2, int np2, int nf, int TN,
                                const double2* __restrict__ tw, const double2* __restrict__ tj, double tau, int mode) {
   extern __shared__ double2 buf[];
-  const int n0 = blockIdx.x * TN;
+  const unsigned tile = xcd_tile((L + TN - 1) / TN);
+  if (tile == ~0u) return;
+  const int n0 = (int)tile * TN;
   const double st = sqrt(tau);
   for (int e = threadIdx.x; e < TN * nt; e += blockDim.x) {
     const int n = e % TN, j = e / TN;
@@ -233,7 +248,9 @@ __global__ __launch_bounds__(kFN * N1) void k_fft4_fwd(const double* __restrict_
   constexpr int NT = N1 * N2, NF = NT / 2 + 1;
   __shared__ double2 buf[NT * kFN];
   const int n = threadIdx.x & (kFN - 1), c = threadIdx.x / kFN;
-  const int n0 = blockIdx.x * kFN, g = n0 + n;
+  const unsigned tile = xcd_tile((L + kFN - 1) / kFN);
+  if (tile == ~0u) return;
+  const int n0 = (int)tile * kFN, g = n0 + n;
   const bool live = g < L;
   if (c < N2) {                                   // pass 1: column t2 = c
     double2 x[N1];
@@ -299,7 +316,9 @@ __global__ __launch_bounds__(kFN * N1) void k_fft4_inv(const cpx<R>* __restrict_
   constexpr int NT = N1 * N2, NF = NT / 2 + 1;
   __shared__ double2 buf[NT * kFN];
   const int n = threadIdx.x & (kFN - 1), c = threadIdx.x / kFN;
-  const int g = blockIdx.x * kFN + n;
+  const unsigned tile = xcd_tile((L + kFN - 1) / kFN);
+  if (tile == ~0u) return;
+  const int g = (int)tile * kFN + n;
   const bool live = g < L;
   const double st = sqrt(tau);
   // Spectrum of z = y0 + i y1 at j and nt - j from the kept j = 0..nt/2.
@@ -367,14 +386,14 @@ __global__ __launch_bounds__(kFN * N1) void k_fft4_inv(const cpx<R>* __restrict_
 template <typename R, int N1, int N2>
 static void fft4_fwd(hipStream_t s, const double* r, cpx<R>* V, cpx<R>* P, int L, int nq2, int np2,
                      const double2* tw, const double2* tj, double tau, int mode) {
-  hipLaunchKernelGGL((k_fft4_fwd<R, N1, N2>), dim3((unsigned)((L + kFN - 1) / kFN)), dim3(kFN * N1), 0, s, r, V, P, L,
+  hipLaunchKernelGGL((k_fft4_fwd<R, N1, N2>), dim3(xcd_grid((L + kFN - 1) / kFN)), dim3(kFN * N1), 0, s, r, V, P, L,
                      nq2, np2, tw, tj, tau, mode);
 }
 
 template <typename R, int N1, int N2>
 static void fft4_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double* z, int L, int nq2, int np2,
                      const double2* tw, const double2* tj, double tau, int mode) {
-  hipLaunchKernelGGL((k_fft4_inv<R, N1, N2>), dim3((unsigned)((L + kFN - 1) / kFN)), dim3(kFN * N1), 0, s, V, P, z, L,
+  hipLaunchKernelGGL((k_fft4_inv<R, N1, N2>), dim3(xcd_grid((L + kFN - 1) / kFN)), dim3(kFN * N1), 0, s, V, P, z, L,
                      nq2, np2, tw, tj, tau, mode);
 }
 
@@ -400,7 +419,7 @@ void launch_time_fft_fwd(hipStream_t s, const double* r, cpx<R>* V, cpx<R>* P, i
   int logn = 0;
   while ((1 << logn) < nt) ++logn;
   const int TN = fft_tile(nt), nf = nt / 2 + 1;
-  const unsigned blocks = (unsigned)((L + TN - 1) / TN);
+  const unsigned blocks = xcd_grid((L + TN - 1) / TN);
   hipLaunchKernelGGL(k_time_fft_fwd<R>, dim3(blocks), dim3(256), (size_t)TN * nt * sizeof(double2), s, r, V, P, nt,
                      logn, L, nq2, np2, nf, TN, tw, tj, tau, mode);
 }
@@ -422,7 +441,7 @@ void launch_time_fft_inv(hipStream_t s, const cpx<R>* V, const cpx<R>* P, double
   int logn = 0;
   while ((1 << logn) < nt) ++logn;
   const int TN = fft_tile(nt), nf = nt / 2 + 1;
-  const unsigned blocks = (unsigned)((L + TN - 1) / TN);
+  const unsigned blocks = xcd_grid((L + TN - 1) / TN);
   hipLaunchKernelGGL(k_time_fft_inv<R>, dim3(blocks), dim3(256), (size_t)TN * nt * sizeof(double2), s, V, P, z, nt,
                      logn, L, nq2, np2, nf, TN, tw, tj, tau, mode);
 }
